@@ -1,0 +1,223 @@
+"""FP64 CPU oracle for the Born-rule probability path (ExtraFerm, arXiv 2511.12416).
+
+TEST INFRASTRUCTURE ONLY: this package may be imported by the test-suite, by
+the smoke check and by the benchmark's CPU-baseline leg, nothing else.  It
+shares no code with the HIP library.  The heavy part (``xfo.c``) is plain C:
+explicit mode-matrix products, a textbook partial-pivot LU, the exact sum over
+all 2^k trajectories (Sec. III-B, Eq. 8) or the Raw Estimate average over
+sampled trajectories (Sec. III-A, Eq. 10-12).  The small closed forms (extent,
+Eq. 5; trajectory bound, Eq. 6) and the matrix exponential of rotation
+generators with its adjoint are written here in NumPy/SciPy.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "xfo.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle.  No FMA contraction, baseline x86-64 ISA, so the
+    FP64 sampler thresholds are computed operation by operation as written."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-std=c11",
+                               "-Wall", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        L.xfo_philox4x32_10.argtypes = [P, P, P]
+        L.xfo_sampler_table.argtypes = [ctypes.c_int, P, P]
+        L.xfo_sample_trajectories.argtypes = [ctypes.c_int, P, ctypes.c_uint64, ctypes.c_uint64,
+                                              ctypes.c_int64, P]
+        L.xfo_det.argtypes = [ctypes.c_int, P, P]
+        L.xfo_extent.argtypes = [ctypes.c_int, P]
+        L.xfo_extent.restype = ctypes.c_double
+        sig = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P,
+               ctypes.c_int, ctypes.c_int64, ctypes.c_uint64]
+        L.xfo_probabilities.argtypes = sig + [P, P]
+        L.xfo_probabilities.restype = ctypes.c_int
+        L.xfo_log_prob_grad.argtypes = sig + [P, P, P]
+        L.xfo_log_prob_grad.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ----------------------------------------------------------------------------
+# closed forms
+# ----------------------------------------------------------------------------
+
+def extent(theta) -> float:
+    """Eq. 5: xi* = prod_j (cos(|theta_j|/4) + sin(|theta_j|/4))^2."""
+    th = np.abs(np.asarray(theta, dtype=np.float64))
+    return float(np.prod((np.cos(th / 4) + np.sin(th / 4)) ** 2))
+
+
+def trajectory_bound(eps: float, delta: float, p_max: float, xi: float) -> int:
+    """Eq. 6 (natural logarithm):
+    t = ceil( 2 (sqrt(xi) + sqrt(p_max))^2 / (sqrt(p_max + eps) - sqrt(p_max))^2
+              * log(2 e^2 / delta) )."""
+    num = (math.sqrt(xi) + math.sqrt(p_max)) ** 2
+    den = (math.sqrt(p_max + eps) - math.sqrt(p_max)) ** 2
+    return int(math.ceil(2.0 * num / den * math.log(2.0 * math.e ** 2 / delta)))
+
+
+def sampling_probability(theta) -> np.ndarray:
+    """Eq. 11: p(x_j = 1) = sin(|theta|/4) / (sin(|theta|/4) + cos(|theta|/4))."""
+    th = np.abs(np.asarray(theta, dtype=np.float64))
+    s, c = np.sin(th / 4), np.cos(th / 4)
+    return s / (s + c)
+
+
+def expm(K: np.ndarray) -> np.ndarray:
+    import scipy.linalg
+    return scipy.linalg.expm(np.asarray(K, dtype=np.complex128))
+
+
+def expm_adjoint(K: np.ndarray, G_U: np.ndarray) -> np.ndarray:
+    """Gradient with respect to K (dL/dRe K + i dL/dIm K) of a real loss whose
+    gradient with respect to U = exp(K) is G_U, via the adjoint of the
+    Frechet derivative: L(K, .)^* = L(K^H, .)."""
+    import scipy.linalg
+    K = np.asarray(K, dtype=np.complex128)
+    _, L = scipy.linalg.expm_frechet(K.conj().T, np.asarray(G_U, dtype=np.complex128))
+    return L
+
+
+def rotations_from_generators(gens: np.ndarray) -> np.ndarray:
+    """Spin-restricted layers exp(K_l) (+) exp(K_l)."""
+    out = []
+    for K in gens:
+        U = expm(K)
+        d = U.shape[0]
+        R = np.zeros((2 * d, 2 * d), dtype=np.complex128)
+        R[:d, :d] = U
+        R[d:, d:] = U
+        out.append(R)
+    return np.stack(out)
+
+
+# ----------------------------------------------------------------------------
+# wrappers of the C oracle
+# ----------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().xfo_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def sampler_table(theta) -> np.ndarray:
+    th = _c(theta, np.float64)
+    k = th.shape[0]
+    T = np.zeros((max(k, 1), max(k, 1)), np.uint32)
+    lib().xfo_sampler_table(k, _ptr(th), _ptr(T))
+    return T[:k, :k]
+
+
+def sample_trajectories(theta, seed: int, bidx: int, t: int) -> np.ndarray:
+    """[t, 2] uint64 trajectory bitmasks (bit j <=> x_j = 1)."""
+    th = _c(theta, np.float64)
+    out = np.zeros((t, 2), np.uint64)
+    lib().xfo_sample_trajectories(th.shape[0], _ptr(th), seed, bidx, t, _ptr(out))
+    return out
+
+
+def det(a: np.ndarray) -> complex:
+    a = _c(a, np.complex128)
+    m = a.shape[0]
+    out = np.zeros(2)
+    lib().xfo_det(m, _ptr(a), _ptr(out))
+    return complex(out[0], out[1])
+
+
+def _circuit_args(rot, pairs, layer, theta, input_bits):
+    rot = _c(rot, np.complex128)
+    n_rot, n, _ = rot.shape
+    pairs = _c(pairs, np.int32).reshape(-1, 2)
+    layer = _c(layer, np.int32)
+    theta = _c(theta, np.float64)
+    inp = _c(input_bits, np.uint64)
+    return rot, n, n_rot, pairs, layer, theta, inp
+
+
+def _theta_sample(theta_sample):
+    if theta_sample is None:
+        return None, None
+    ts = _c(theta_sample, np.float64)
+    return ts, _ptr(ts)
+
+
+def probabilities(rot, pairs, layer, theta, input_bits, bits, mode="exact", t=0, seed=0,
+                  return_amp=False, theta_sample=None):
+    """Born-rule probabilities p_b (exact, Eq. 8) or Raw Estimate p_hat_b.
+    ``theta_sample`` freezes the sampling table at other angles."""
+    rot, n, n_rot, pairs, layer, theta, inp = _circuit_args(rot, pairs, layer, theta, input_bits)
+    ts_keep, ts_ptr = _theta_sample(theta_sample)
+    bits = _c(bits, np.uint64).reshape(-1, 2)
+    B = bits.shape[0]
+    prob = np.zeros(B)
+    amp = np.zeros((B, 2))
+    md = 0 if mode == "exact" else 1
+    rc = lib().xfo_probabilities(n, n_rot, _ptr(rot), theta.shape[0], _ptr(pairs), _ptr(layer),
+                                 _ptr(theta), ts_ptr, _ptr(inp), B, _ptr(bits), md, int(t), int(seed),
+                                 _ptr(prob), _ptr(amp))
+    if rc != 0:
+        raise ValueError("oracle: unsupported sizes")
+    if return_amp:
+        return prob, amp[:, 0] + 1j * amp[:, 1]
+    return prob
+
+
+def log_prob_grad(rot, pairs, layer, theta, input_bits, bits, g, mode="exact", t=0, seed=0,
+                  theta_sample=None):
+    """(dL/drot, dL/dtheta) for L = sum_b g_b log p_b; rotation gradients in
+    the dL/dRe + i dL/dIm convention.  Raw Estimate samples are held fixed."""
+    rot, n, n_rot, pairs, layer, theta, inp = _circuit_args(rot, pairs, layer, theta, input_bits)
+    ts_keep, ts_ptr = _theta_sample(theta_sample)
+    bits = _c(bits, np.uint64).reshape(-1, 2)
+    g = _c(g, np.float64)
+    B = bits.shape[0]
+    grot = np.zeros((n_rot, n, n, 2))
+    gth = np.zeros(max(theta.shape[0], 1))
+    md = 0 if mode == "exact" else 1
+    rc = lib().xfo_log_prob_grad(n, n_rot, _ptr(rot), theta.shape[0], _ptr(pairs), _ptr(layer),
+                                 _ptr(theta), ts_ptr, _ptr(inp), B, _ptr(bits), md, int(t), int(seed),
+                                 _ptr(g), _ptr(grot), _ptr(gth))
+    if rc != 0:
+        raise ValueError("oracle: unsupported sizes")
+    return grot[..., 0] + 1j * grot[..., 1], gth[:theta.shape[0]]
+
+
+def run_workload(w, B=None, mode=None, return_amp=False):
+    """Oracle probabilities for a ``workloads.Workload`` (first ``B`` bitstrings)."""
+    rot = w.rot if w.rot is not None else rotations_from_generators(w.gens)
+    bits = w.bits if B is None else w.bits[:B]
+    return probabilities(rot, w.pairs, w.layer, w.theta, w.input_bits, bits,
+                         mode or w.mode, w.t, w.seed, return_amp=return_amp)
