@@ -1,0 +1,175 @@
+/*
+ * xf.h -- C ABI of the MI355X (gfx950) Born-rule probability library for
+ * circuits made of passive (particle-number-conserving) matchgates and
+ * controlled-phase gates, after "ExtraFerm: An Extended Matchgate Simulator"
+ * (arXiv 2511.12416).
+ *
+ * What is computed (column convention, Sec. II-B Eq. 2-3 read together with the
+ * composition of Sec. IV-B Eq. 14):
+ *   A rotation layer U maps a_c^dag to sum_r U[r][c] a_r^dag.  The circuit is
+ *   rotation 0, then the CPhase gates of layer 0, rotation 1, ..., rotation
+ *   n_rot-1.  Replacing every CPhase(theta_j) by d_{x_j}(theta_j) (Sec. III-B,
+ *   Eq. 7) gives the trajectory mode matrix
+ *       V(x) = R_{L} D_{L-1}(x) R_{L-1} ... D_0(x) R_0,   L = n_rot - 1,
+ *   with D_l(x) diagonal: mode q gets prod over the layer's gates j touching q
+ *   of e^{i theta_j/2} (x_j = 0) or -e^{i theta_j/2} (x_j = 1).  For an output
+ *   bitstring b with occupied modes R (ascending) and input occupation C:
+ *       Exact (Sec. III-B Eq. 8-9, exponent of cos read as 1 - x_j):
+ *           A_b = sum_x w(x) det V(x)[R, C],
+ *           w(x) = prod_j cos(theta_j/4)^{1-x_j} (i sin(theta_j/4))^{x_j}
+ *       Raw Estimate (Sec. III-A, trajectories drawn from Eq. 10-11):
+ *           A_b = sqrt(xi*)/t * sum_{s<t} phase(x_s) det V(x_s)[R, C],
+ *           phase(x) = prod_{j: x_j = 1} (i if theta_j >= 0 else -i)
+ *       p_b = |A_b|^2.
+ *   The global phase e^{-i theta_j/4} of every gate is dropped from A_b.
+ *   Trajectories differing only where the same modes flip (same pattern N of
+ *   Sec. IV-B Eq. 16-19) share one determinant, which is evaluated once.
+ *
+ * Trajectory sampler (both this library and any checker implement it from this
+ * definition; it draws from the product distribution of Eq. 10-11):
+ *   p_j = s_j / (s_j + c_j), s_j = sin(|theta_j|/4), c_j = cos(|theta_j|/4).
+ *   Table T[a][j] (0 <= a <= j < k) = min(floor(2^32 * (1 - S)), 2^32 - 1) with
+ *   S = prod_{i=a..j} (1 - p_i) accumulated left to right in IEEE FP64 without
+ *   fused multiply-add.  Sample s of the bitstring with batch index i starts at
+ *   a = 0; the d-th draw u_d (d = 0, 1, ...) is word (d mod 4) of
+ *   Philox4x32-10 (Salmon et al., SC'11) with counter
+ *   (s, d div 4, lo32(i), hi32(i)) and key (lo32(seed), hi32(seed)).  While
+ *   a < k: draw u; the next gate with x_j = 1 is the smallest j >= a with
+ *   u < T[a][j]; if there is none the sample ends, otherwise set x_j = 1 and
+ *   continue at a = j + 1.
+ *
+ * Conventions for every call:
+ *   - Complex numbers are interleaved (re, im) doubles; matrices row-major.
+ *   - Pointers named d_* are device memory on the plan's device, h_* and
+ *     unprefixed pointers are host memory.  The caller owns every buffer.
+ *   - Asynchronous calls are ordered on the given hip_stream (a hipStream_t,
+ *     NULL = default stream) and return before the kernels finish.
+ *   - On any error the call returns a non-zero xf_status, writes nothing to
+ *     its outputs, and xf_last_error() describes the problem.
+ *   - A plan may be used from one host thread at a time; distinct plans are
+ *     independent.
+ */
+#ifndef XF_H
+#define XF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XF_OK = 0,
+    XF_EINVAL = 1,        /* invalid argument (null pointer, bad size, NaN, non-unitary layer, ...) */
+    XF_EUNSUPPORTED = 2,  /* valid but outside what this library implements (sizes below)          */
+    XF_ENOMEM = 3,        /* device or host allocation failed                                       */
+    XF_EDEVICE = 4        /* a HIP runtime call failed                                              */
+} xf_status;
+
+typedef enum { XF_EXACT = 0, XF_RAW_ESTIMATE = 1 } xf_mode;
+
+/* XF_FP64: every step in FP64.
+ * XF_MIXED: the low-rank correction of each trajectory's submatrix is formed
+ * in FP32; the base submatrix, the elimination, the pivot product and the
+ * cross-term accumulation stay FP64. */
+typedef enum { XF_FP64 = 0, XF_MIXED = 1 } xf_precision;
+
+/* 128-bit occupation / bitstring: bit p of (w[0] | w[1] << 64) <=> mode p occupied
+ * (Jordan-Wigner: qubit p in |1> <=> fermion in mode p, Sec. II-B; bit-packed
+ * 128-bit states as in Sec. IV-A). */
+typedef struct { uint64_t w[2]; } xf_bits128;
+
+typedef struct {
+    int32_t n;              /* modes = qubits, 1 <= n <= 128                                   */
+    int32_t n_rot;          /* rotation layers in time order, 1 <= n_rot <= 3                  */
+    const double *rot;      /* host [n_rot][n][n][2]: unitary mode matrices (column convention) */
+    int32_t k;              /* CPhase gates (k = 0 requires nothing else)                      */
+    const int32_t *pairs;   /* host [k][2]: the two modes of gate j, distinct, in [0, n)        */
+    const int32_t *layer;   /* host [k]: gate j acts after rotation layer[j], 0 <= layer[j] < n_rot-1 */
+    const double *theta;    /* host [k]: angles, finite, |theta| < 2*pi                        */
+} xf_circuit;
+
+typedef struct xf_plan xf_plan;
+
+/* Creates a plan on HIP device `device` for circuit `c` and input occupation
+ * `input` (eta = popcount <= 64, all bits below n).  Copies what it needs
+ * from the host arrays; they may be freed afterwards.  Validates unitarity of
+ * every layer (max |U^H U - I| <= 1e-10).  The trajectory-sampling table is
+ * frozen at the angles given here (see xf_plan_refreeze).
+ * Errors: XF_EINVAL, XF_EUNSUPPORTED (n > 128, eta > 64, n_rot > 3),
+ * XF_ENOMEM, XF_EDEVICE. */
+xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision precision,
+                         int device, xf_plan **plan);
+
+/* Replaces rotation entries and angles (same shapes as at creation; either
+ * pointer may be NULL to keep the current values).  The sampling table stays
+ * frozen, so Raw Estimate draws the same trajectories: this is the estimator
+ * whose derivative xf_log_prob_backward returns.  Synchronous. */
+xf_status xf_plan_set_params(xf_plan *plan, const double *rot, const double *theta);
+
+/* Rebuilds the sampling table from the current angles.  Synchronous. */
+xf_status xf_plan_refreeze(xf_plan *plan);
+
+/* Frees the plan and its device memory (synchronises the plan's device). */
+xf_status xf_plan_destroy(xf_plan *plan);
+
+/* Extent of the current angles, Sec. III-A Eq. 5:
+ * xi* = prod_j (cos(|theta_j|/4) + sin(|theta_j|/4))^2. */
+xf_status xf_extent(const xf_plan *plan, double *xi);
+
+/* Trajectory count of Sec. III-A Eq. 6 (natural logarithm):
+ * t = ceil(2 (sqrt(xi) + sqrt(p_max))^2 / (sqrt(p_max + eps) - sqrt(p_max))^2
+ *          * log(2 e^2 / delta)).
+ * Requires eps > 0, 0 < delta < 1, 0 <= p_max <= 1, xi >= 1; XF_EUNSUPPORTED
+ * if t exceeds 2^62. */
+xf_status xf_trajectory_bound(double eps, double delta, double p_max, double xi, int64_t *t);
+
+/* Born-rule probabilities of B output bitstrings (Sec. III-A/B).
+ *   d_bits  device [B] xf_bits128 (batch index i of d_bits[i] keys the sampler)
+ *   mode    XF_EXACT (all 2^k trajectories; k <= 24) or XF_RAW_ESTIMATE (t >= 1,
+ *           t < 2^32 samples per bitstring; k <= 128; the bit-compressed
+ *           flip pattern, sum over CPhase layers of the modes their gates touch,
+ *           must fit in 128 bits)
+ *   seed    sampler key (ignored in exact mode)
+ *   d_prob  device [B] doubles: p_b
+ *   d_amp   device [B][2] doubles: A_b, or NULL
+ * A bitstring whose weight differs from eta, or with bits at or above n, gets
+ * p = 0 and A = 0 (passive circuits conserve the weight, Sec. II-B).  B = 0 is
+ * a no-op.  Uses plan-owned device scratch; results are bitwise reproducible
+ * for fixed inputs. */
+xf_status xf_probabilities(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, xf_mode mode,
+                           int64_t t, uint64_t seed, double *d_prob, double *d_amp,
+                           void *hip_stream);
+
+/* Gradient of L = sum_b g_b log p_b, g = d_grad_logp (device [B] doubles),
+ * with respect to every rotation entry (h_grad_rot, host [n_rot][n][n][2],
+ * as dL/dRe + i dL/dIm) and every angle (h_grad_theta, host [k]).  Same
+ * bitstrings, mode, t and seed as the forward call it differentiates; Raw
+ * Estimate samples are held fixed (frozen table), the weights depend on the
+ * angles through sqrt(xi*).  Uses Jacobi's formula d det M = det M tr(M^-1 dM)
+ * and recomputes every trajectory's submatrix instead of storing it.
+ * Bitstrings with p_b = 0 contribute nothing.  Synchronises hip_stream. */
+xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, xf_mode mode,
+                               int64_t t, uint64_t seed, const double *d_grad_logp,
+                               double *h_grad_rot, double *h_grad_theta, void *hip_stream);
+
+/* Number of distinct (bitstring, flip-pattern) determinants the last
+ * xf_probabilities call on this plan evaluated (synchronises its stream). */
+xf_status xf_plan_last_term_count(xf_plan *plan, int64_t *count);
+
+/* Host FP64 helpers for rotations parametrised by anti-Hermitian generators
+ * (U = exp(K)), n <= 128:
+ *   xf_expm_antihermitian: U = exp(K), K and U host [n][n][2].
+ *   xf_expm_adjoint: G_K = L(K^H, G_U), the adjoint of the Frechet derivative
+ *     of exp at K applied to G_U; with G_U = dL/dRe U + i dL/dIm U it returns
+ *     dL/dRe K + i dL/dIm K. */
+xf_status xf_expm_antihermitian(int32_t n, const double *K, double *U);
+xf_status xf_expm_adjoint(int32_t n, const double *K, const double *G_U, double *G_K);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char *xf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XF_H */

@@ -49,7 +49,7 @@ def lib():
         L.xfo_det.argtypes = [ctypes.c_int, P, P]
         L.xfo_extent.argtypes = [ctypes.c_int, P]
         L.xfo_extent.restype = ctypes.c_double
-        sig = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P,
+        sig = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P, P,
                ctypes.c_int, ctypes.c_int64, ctypes.c_uint64]
         L.xfo_probabilities.argtypes = sig + [P, P]
         L.xfo_probabilities.restype = ctypes.c_int
@@ -174,19 +174,29 @@ def _theta_sample(theta_sample):
     return ts, _ptr(ts)
 
 
+def _batch_index(batch_index, B):
+    if batch_index is None:
+        return None, None
+    bi = np.ascontiguousarray(np.asarray(batch_index, dtype=np.uint64).reshape(-1))
+    assert bi.shape[0] == B
+    return bi, _ptr(bi)
+
+
 def probabilities(rot, pairs, layer, theta, input_bits, bits, mode="exact", t=0, seed=0,
-                  return_amp=False, theta_sample=None):
+                  return_amp=False, theta_sample=None, batch_index=None):
     """Born-rule probabilities p_b (exact, Eq. 8) or Raw Estimate p_hat_b.
-    ``theta_sample`` freezes the sampling table at other angles."""
+    ``theta_sample`` freezes the sampling table at other angles;
+    ``batch_index[b]`` is the index keying bitstring b's samples (default b)."""
     rot, n, n_rot, pairs, layer, theta, inp = _circuit_args(rot, pairs, layer, theta, input_bits)
     ts_keep, ts_ptr = _theta_sample(theta_sample)
     bits = _c(bits, np.uint64).reshape(-1, 2)
     B = bits.shape[0]
+    bi_keep, bi_ptr = _batch_index(batch_index, B)
     prob = np.zeros(B)
     amp = np.zeros((B, 2))
     md = 0 if mode == "exact" else 1
     rc = lib().xfo_probabilities(n, n_rot, _ptr(rot), theta.shape[0], _ptr(pairs), _ptr(layer),
-                                 _ptr(theta), ts_ptr, _ptr(inp), B, _ptr(bits), md, int(t), int(seed),
+                                 _ptr(theta), ts_ptr, _ptr(inp), B, _ptr(bits), bi_ptr, md, int(t), int(seed),
                                  _ptr(prob), _ptr(amp))
     if rc != 0:
         raise ValueError("oracle: unsupported sizes")
@@ -196,7 +206,7 @@ def probabilities(rot, pairs, layer, theta, input_bits, bits, mode="exact", t=0,
 
 
 def log_prob_grad(rot, pairs, layer, theta, input_bits, bits, g, mode="exact", t=0, seed=0,
-                  theta_sample=None):
+                  theta_sample=None, batch_index=None):
     """(dL/drot, dL/dtheta) for L = sum_b g_b log p_b; rotation gradients in
     the dL/dRe + i dL/dIm convention.  Raw Estimate samples are held fixed."""
     rot, n, n_rot, pairs, layer, theta, inp = _circuit_args(rot, pairs, layer, theta, input_bits)
@@ -204,20 +214,23 @@ def log_prob_grad(rot, pairs, layer, theta, input_bits, bits, g, mode="exact", t
     bits = _c(bits, np.uint64).reshape(-1, 2)
     g = _c(g, np.float64)
     B = bits.shape[0]
+    bi_keep, bi_ptr = _batch_index(batch_index, B)
     grot = np.zeros((n_rot, n, n, 2))
     gth = np.zeros(max(theta.shape[0], 1))
     md = 0 if mode == "exact" else 1
     rc = lib().xfo_log_prob_grad(n, n_rot, _ptr(rot), theta.shape[0], _ptr(pairs), _ptr(layer),
-                                 _ptr(theta), ts_ptr, _ptr(inp), B, _ptr(bits), md, int(t), int(seed),
+                                 _ptr(theta), ts_ptr, _ptr(inp), B, _ptr(bits), bi_ptr, md, int(t), int(seed),
                                  _ptr(g), _ptr(grot), _ptr(gth))
     if rc != 0:
         raise ValueError("oracle: unsupported sizes")
     return grot[..., 0] + 1j * grot[..., 1], gth[:theta.shape[0]]
 
 
-def run_workload(w, B=None, mode=None, return_amp=False):
-    """Oracle probabilities for a ``workloads.Workload`` (first ``B`` bitstrings)."""
+def run_workload(w, index=None, mode=None, return_amp=False):
+    """Oracle probabilities for a ``workloads.Workload``, optionally for the
+    batch positions ``index`` only (their samples keyed by those positions)."""
     rot = w.rot if w.rot is not None else rotations_from_generators(w.gens)
-    bits = w.bits if B is None else w.bits[:B]
+    bits = w.bits if index is None else w.bits[np.asarray(index)]
     return probabilities(rot, w.pairs, w.layer, w.theta, w.input_bits, bits,
-                         mode or w.mode, w.t, w.seed, return_amp=return_amp)
+                         mode or w.mode, w.t, w.seed, return_amp=return_amp,
+                         batch_index=None if index is None else np.asarray(index))

@@ -374,12 +374,15 @@ static int build_terms(const circuit *c, int mode, int64_t t, uint64_t seed, uin
  * the weights sqrt(xi*) phase(x) and the circuit itself always use theta.
  * Holding theta_sample fixed while theta moves freezes the samples, which is
  * what a derivative of the estimator with respect to theta differentiates.
+ * batch_index (nullable) gives the index that keys bitstring b's samples
+ * (default b), so a subset of a larger batch can be recomputed.
  * prob[B], amp[B][2] (nullable).  Returns 0, or -1 on unsupported sizes.
  */
 int xfo_probabilities(int n, int n_rot, const double *rot, int k, const int *pairs,
                       const int *layer, const double *theta, const double *theta_sample,
-                      const uint64_t *input_bits, int64_t B, const uint64_t *bits, int mode,
-                      int64_t t, uint64_t seed, double *prob, double *amp)
+                      const uint64_t *input_bits, int64_t B, const uint64_t *bits,
+                      const uint64_t *batch_index, int mode, int64_t t, uint64_t seed,
+                      double *prob, double *amp)
 {
     if (n < 1 || n > 128 || n_rot < 1 || k < 0 || (mode == 0 && k > 24) || (mode == 1 && (k > 128 || t < 1)))
         return -1;
@@ -410,7 +413,7 @@ int xfo_probabilities(int n, int n_rot, const double *rot, int k, const int *pai
         cplx A = 0.0;
         if (mb == m) {
             term *ts;
-            int nt = build_terms(&c, mode, t, seed, (uint64_t)b, T, sqrt_xi, &ts);
+            int nt = build_terms(&c, mode, t, seed, batch_index ? batch_index[b] : (uint64_t)b, T, sqrt_xi, &ts);
             cplx *Y = (cplx *)malloc(sizeof(cplx) * (size_t)n * (m > 0 ? m : 1));
             cplx *M = (cplx *)malloc(sizeof(cplx) * (size_t)(m > 0 ? m * m : 1));
             int *perm = (int *)malloc(sizeof(int) * (size_t)(m > 0 ? m : 1));
@@ -449,9 +452,9 @@ int xfo_probabilities(int n, int n_rot, const double *rot, int k, const int *pai
  */
 int xfo_log_prob_grad(int n, int n_rot, const double *rot, int k, const int *pairs,
                       const int *layer, const double *theta, const double *theta_sample,
-                      const uint64_t *input_bits, int64_t B, const uint64_t *bits, int mode,
-                      int64_t t, uint64_t seed, const double *g, double *grad_rot,
-                      double *grad_theta)
+                      const uint64_t *input_bits, int64_t B, const uint64_t *bits,
+                      const uint64_t *batch_index, int mode, int64_t t, uint64_t seed,
+                      const double *g, double *grad_rot, double *grad_theta)
 {
     if (n < 1 || n > 128 || n_rot < 1 || k < 0 || (mode == 0 && k > 24) || (mode == 1 && (k > 128 || t < 1)))
         return -1;
@@ -499,7 +502,7 @@ int xfo_log_prob_grad(int n, int n_rot, const double *rot, int k, const int *pai
             int mb = occupied(bits + 2 * b, n, R);
             if (mb != m || g[b] == 0.0) continue;
             term *ts;
-            int nt = build_terms(&c, mode, t, seed, (uint64_t)b, T, sqrt_xi, &ts);
+            int nt = build_terms(&c, mode, t, seed, batch_index ? batch_index[b] : (uint64_t)b, T, sqrt_xi, &ts);
             cplx A = 0.0;
             memset(dA_rot, 0, sizeof(cplx) * nrot_el);
             for (int j = 0; j < k; ++j) dA_th[j] = 0.0;

@@ -1,0 +1,6 @@
+"""MI355X (gfx950) Born-rule probabilities for passive matchgate + controlled-phase
+circuits (ExtraFerm, arXiv 2511.12416): HIP kernels behind the C ABI in
+include/xf.h, with a thin Python binding."""
+from ._abi import XfError, lib  # noqa: F401
+from .api import (Plan, bits_tensor, expm_adjoint, expm_antihermitian,  # noqa: F401
+                  spin_rotations, trajectory_bound)

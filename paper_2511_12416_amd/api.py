@@ -1,0 +1,181 @@
+"""Python view of the C ABI: plans, probabilities and gradients.
+
+Only argument marshalling happens here: host arrays are packed into the
+interleaved (re, im) layout the ABI expects, device tensors are passed by
+pointer together with torch's current HIP stream.  Every step of the
+computation runs in libxf.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import check, lib
+
+_MODES = {"exact": _abi.XF_EXACT, "approx": _abi.XF_RAW_ESTIMATE, "raw_estimate": _abi.XF_RAW_ESTIMATE}
+_PREC = {"fp64": _abi.XF_FP64, "mixed": _abi.XF_MIXED}
+
+
+def _f64(a) -> np.ndarray:
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a)
+
+
+def _complex_host(a) -> np.ndarray:
+    """complex array -> contiguous float64 [..., 2]."""
+    a = _f64(a)
+    if np.iscomplexobj(a):
+        a = np.ascontiguousarray(a.astype(np.complex128)).view(np.float64).reshape(*a.shape, 2)
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def bits_tensor(bits, device="cuda") -> torch.Tensor:
+    """[B, 2] uint64 bit patterns as an int64 tensor on ``device``."""
+    b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint64).reshape(-1, 2))
+    return torch.from_numpy(b.view(np.int64)).to(device)
+
+
+def _stream_handle(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """A circuit (rotation layers, CPhase pairs / layers / angles) bound to an
+    input occupation, a precision and a HIP device."""
+
+    def __init__(self, rot, pairs, layer, theta, input_bits, precision: str = "fp64", device: int = 0):
+        L = lib()
+        self._rot = _complex_host(rot)
+        n_rot, n = self._rot.shape[0], self._rot.shape[1]
+        self._pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        self._layer = np.ascontiguousarray(np.asarray(layer, dtype=np.int32).reshape(-1))
+        self._theta = np.ascontiguousarray(_f64(theta), dtype=np.float64).reshape(-1)
+        k = self._theta.shape[0]
+        circ = _abi.Circuit(n, n_rot, self._rot.ctypes.data, k, self._pairs.ctypes.data,
+                            self._layer.ctypes.data, self._theta.ctypes.data)
+        ib = np.asarray(input_bits, dtype=np.uint64).reshape(2)
+        bits = _abi.Bits128()
+        bits.w[0], bits.w[1] = int(ib[0]), int(ib[1])
+        h = ctypes.c_void_p()
+        check(L.xf_plan_create(ctypes.byref(circ), bits, _PREC[precision], int(device), ctypes.byref(h)))
+        self._h = h
+        self.n, self.n_rot, self.k = n, n_rot, k
+        self.eta = int(bin(int(ib[0])).count("1") + bin(int(ib[1])).count("1"))
+        self.device = torch.device("cuda", int(device))
+        self.precision = precision
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(lib().xf_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- parameters ---------------------------------------------------------
+    def set_params(self, rot=None, theta=None) -> None:
+        r = _complex_host(rot) if rot is not None else None
+        th = np.ascontiguousarray(_f64(theta), dtype=np.float64).reshape(-1) if theta is not None else None
+        check(lib().xf_plan_set_params(self._h, _ptr(r) if r is not None else None,
+                                       _ptr(th) if th is not None else None))
+
+    def refreeze(self) -> None:
+        check(lib().xf_plan_refreeze(self._h))
+
+    def extent(self) -> float:
+        xi = ctypes.c_double()
+        check(lib().xf_extent(self._h, ctypes.byref(xi)))
+        return xi.value
+
+    def last_term_count(self) -> int:
+        c = ctypes.c_int64()
+        check(lib().xf_plan_last_term_count(self._h, ctypes.byref(c)))
+        return c.value
+
+    # -- the hot path ---------------------------------------------------------
+    def probabilities(self, bits: torch.Tensor, mode: str = "exact", t: int = 0, seed: int = 0,
+                      out: Optional[torch.Tensor] = None, amp: Optional[torch.Tensor] = None,
+                      return_amp: bool = False):
+        """p_b for a [B, 2] int64 device tensor of bit patterns."""
+        bits = bits.contiguous()
+        if bits.device != self.device or bits.dtype != torch.int64:
+            raise ValueError("bits must be an int64 tensor on the plan's device")
+        B = bits.shape[0]
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=self.device)
+        if return_amp and amp is None:
+            amp = torch.empty(B, 2, dtype=torch.float64, device=self.device)
+        check(lib().xf_probabilities(self._h, bits.data_ptr(), B, _MODES[mode], int(t),
+                                     int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(),
+                                     amp.data_ptr() if amp is not None else None,
+                                     _stream_handle(self.device)))
+        if return_amp:
+            return out, torch.view_as_complex(amp)
+        return out
+
+    def log_prob_backward(self, bits: torch.Tensor, grad_logp: torch.Tensor, mode: str = "exact",
+                          t: int = 0, seed: int = 0):
+        """(dL/drot as complex [n_rot, n, n], dL/dtheta [k]) for L = sum_b g_b log p_b."""
+        bits = bits.contiguous()
+        g = grad_logp.to(device=self.device, dtype=torch.float64).contiguous()
+        grot = np.zeros((self.n_rot, self.n, self.n, 2))
+        gth = np.zeros(max(self.k, 1))
+        check(lib().xf_log_prob_backward(self._h, bits.data_ptr(), bits.shape[0], _MODES[mode], int(t),
+                                         int(seed) & 0xFFFFFFFFFFFFFFFF, g.data_ptr(), _ptr(grot),
+                                         _ptr(gth), _stream_handle(self.device)))
+        return grot[..., 0] + 1j * grot[..., 1], gth[: self.k]
+
+
+def trajectory_bound(eps: float, delta: float, p_max: float, xi: float) -> int:
+    t = ctypes.c_int64()
+    check(lib().xf_trajectory_bound(eps, delta, p_max, xi, ctypes.byref(t)))
+    return t.value
+
+
+def expm_antihermitian(K) -> np.ndarray:
+    Kh = _complex_host(K)
+    n = Kh.shape[0]
+    U = np.zeros((n, n, 2))
+    check(lib().xf_expm_antihermitian(n, _ptr(Kh), _ptr(U)))
+    return U[..., 0] + 1j * U[..., 1]
+
+
+def expm_adjoint(K, G_U) -> np.ndarray:
+    Kh = _complex_host(K)
+    Gh = _complex_host(G_U)
+    n = Kh.shape[0]
+    GK = np.zeros((n, n, 2))
+    check(lib().xf_expm_adjoint(n, _ptr(Kh), _ptr(Gh), _ptr(GK)))
+    return GK[..., 0] + 1j * GK[..., 1]
+
+
+def spin_rotations(gens) -> np.ndarray:
+    """Layers exp(K_l) (+) exp(K_l) for anti-Hermitian generators K_l."""
+    out = []
+    for K in gens:
+        U = expm_antihermitian(K)
+        d = U.shape[0]
+        R = np.zeros((2 * d, 2 * d), np.complex128)
+        R[:d, :d] = U
+        R[d:, d:] = U
+        out.append(R)
+    return np.stack(out)

@@ -1,0 +1,45 @@
+"""Builds libxf.so (HIP kernels for gfx950 + host plan code) in-tree."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libxf.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.path.join(ROCM, "bin", "hipcc")
+
+# Packed FP32 instructions are disabled for all device code.
+DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# The host plan (sampling table, FP64 precompute) is compiled without FMA
+# contraction on the baseline x86-64 ISA.
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
+              "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("build failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
+    return r
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    host_o = os.path.join(BUILD, "xf_host.o")
+    kern_o = os.path.join(BUILD, "xf_kernels.o")
+    _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "xf_host.cpp"), "-o", host_o])
+    _run([HIPCC, *DEVICE_FLAGS, "-c", os.path.join(CSRC, "xf_kernels.hip"), "-o", kern_o])
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", host_o, kern_o, "-o", tmp])
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

@@ -1,0 +1,653 @@
+// Host side of the C ABI declared in include/xf.h: argument validation, the
+// FP64 plan precompute (absorbed d_0 phases, low-rank factors, sampling
+// table, bit-compressed flip keys, exact-mode term list), the matrix
+// exponential helpers, and the kernel launches.
+//
+// Built with -ffp-contract=off on the baseline x86-64 ISA so that the sampling
+// table is computed operation by operation as its definition states.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/xf.h"
+#include "xf_internal.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+xf_status fail(xf_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+xf_status ok() {
+    g_err.clear();
+    return XF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// small dense complex helpers (row-major)
+// ---------------------------------------------------------------------------
+
+void matmul(const cd *A, const cd *B, cd *C, int p, int q, int r) {
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < r; ++j) {
+            cd acc = 0.0;
+            for (int l = 0; l < q; ++l) acc += A[(size_t)i * q + l] * B[(size_t)l * r + j];
+            C[(size_t)i * r + j] = acc;
+        }
+}
+
+double norm1(const std::vector<cd> &A, int n) {
+    double best = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += std::abs(A[(size_t)i * n + j]);
+        best = std::max(best, s);
+    }
+    return best;
+}
+
+// exp(A) by scaling and squaring with a degree-24 Taylor polynomial on
+// A / 2^s, ||A / 2^s||_1 <= 1/2 (truncation below 1e-30 relative).
+std::vector<cd> expm(const std::vector<cd> &A, int n) {
+    const double nrm = norm1(A, n);
+    int s = 0;
+    if (nrm > 0.5) s = (int)std::ceil(std::log2(nrm / 0.5));
+    const double sc = std::ldexp(1.0, -s);
+    std::vector<cd> X(A.size()), E((size_t)n * n, 0.0), term((size_t)n * n, 0.0), tmp((size_t)n * n);
+    for (size_t i = 0; i < A.size(); ++i) X[i] = A[i] * sc;
+    for (int i = 0; i < n; ++i) E[(size_t)i * n + i] = 1.0, term[(size_t)i * n + i] = 1.0;
+    for (int d = 1; d <= 24; ++d) {
+        matmul(term.data(), X.data(), tmp.data(), n, n, n);
+        for (size_t i = 0; i < tmp.size(); ++i) term[i] = tmp[i] / (double)d;
+        for (size_t i = 0; i < E.size(); ++i) E[i] += term[i];
+    }
+    for (int i = 0; i < s; ++i) {
+        matmul(E.data(), E.data(), tmp.data(), n, n, n);
+        E.swap(tmp);
+    }
+    return E;
+}
+
+bool finite_all(const double *p, size_t cnt) {
+    for (size_t i = 0; i < cnt; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+xf_status dev_upload(DevBuf &b, const void *src, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.bytes < bytes) {
+        if (b.p) hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        if (hipMalloc(&b.p, bytes) != hipSuccess) return fail(XF_ENOMEM, "hipMalloc(%zu) failed", bytes);
+        b.bytes = bytes;
+    }
+    if (src && hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(XF_EDEVICE, "hipMemcpy to device failed");
+    return XF_OK;
+}
+
+void dev_free(DevBuf &b) {
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool okay = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        okay = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct xf_plan {
+    int device = 0;
+    int n = 0, n_rot = 0, k = 0, m = 0, L = 0, G = 4;
+    xf_precision precision = XF_FP64;
+    std::vector<double> rot;      // [n_rot][n][n][2]
+    std::vector<int32_t> pairs;   // [k][2]
+    std::vector<int32_t> layer;   // [k]
+    std::vector<double> theta;    // [k]
+    std::vector<int> C;           // occupied input modes
+    // flip-pattern keys
+    int keykind = 0, keybits = 0, off1 = 0;
+    std::vector<uint8_t> keymode;     // [64]
+    std::vector<uint64_t> gkey;       // [k]
+    std::vector<uint64_t> gmode;      // [k][2]
+    std::vector<uint8_t> gneg;        // [k]
+    // device state
+    DevBuf dP, dPhi0, dA1, dA2, dQ, dR1, fPhi0, fA1, fA2, fQ, fR1;
+    DevBuf dkeymode, dT, dgkey, dgmode, dglayer, dgneg, dnterm;
+    DevBuf dxkeys, dxw;               // exact-mode term list
+    int64_t nxterms = -1;             // -1: not built for the current parameters
+};
+
+namespace {
+
+bool plan_valid(const xf_plan *p) { return p != nullptr && p->n > 0; }
+
+// Validates a circuit description (shared by create / set_params).
+xf_status check_params(int n, int n_rot, const double *rot, int k, const double *theta) {
+    if (!finite_all(rot, (size_t)n_rot * n * n * 2)) return fail(XF_EINVAL, "rotation contains NaN/Inf");
+    for (int l = 0; l < n_rot; ++l) {
+        const double *U = rot + (size_t)l * n * n * 2;
+        double worst = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                cd acc = 0.0;
+                for (int r = 0; r < n; ++r) {
+                    const cd a(U[2 * ((size_t)r * n + i)], U[2 * ((size_t)r * n + i) + 1]);
+                    const cd b(U[2 * ((size_t)r * n + j)], U[2 * ((size_t)r * n + j) + 1]);
+                    acc += std::conj(a) * b;
+                }
+                worst = std::max(worst, std::abs(acc - (i == j ? 1.0 : 0.0)));
+            }
+        if (worst > 1e-10) return fail(XF_EINVAL, "rotation layer %d is not unitary (max |U^H U - I| = %.3g)", l, worst);
+    }
+    if (k > 0 && !finite_all(theta, (size_t)k)) return fail(XF_EINVAL, "theta contains NaN/Inf");
+    for (int j = 0; j < k; ++j)
+        if (!(std::fabs(theta[j]) < 2.0 * M_PI)) return fail(XF_EINVAL, "|theta[%d]| must be < 2 pi", j);
+    return XF_OK;
+}
+
+// Sampling table (definition in xf.h): T[a][j] = min(floor(2^32 (1 - S)), 2^32 - 1),
+// S = prod_{i=a..j} (1 - p_i), p_i = sin(|theta_i|/4) / (sin(|theta_i|/4) + cos(|theta_i|/4)).
+std::vector<uint32_t> sampling_table(const std::vector<double> &theta) {
+    const int k = (int)theta.size();
+    std::vector<double> p(k);
+    for (int j = 0; j < k; ++j) {
+        const double s = std::sin(std::fabs(theta[j]) / 4.0);
+        const double c = std::cos(std::fabs(theta[j]) / 4.0);
+        p[j] = s / (s + c);
+    }
+    std::vector<uint32_t> T((size_t)k * k, 0u);
+    for (int a = 0; a < k; ++a) {
+        double S = 1.0;
+        for (int j = a; j < k; ++j) {
+            S = S * (1.0 - p[j]);
+            const double f = 1.0 - S;
+            const double v = std::floor(f * 4294967296.0);
+            T[(size_t)a * k + j] = v >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)v;
+        }
+    }
+    return T;
+}
+
+double extent_of(const std::vector<double> &theta) {
+    double xi = 1.0;
+    for (double th : theta) {
+        const double f = std::cos(std::fabs(th) / 4.0) + std::sin(std::fabs(th) / 4.0);
+        xi *= f * f;
+    }
+    return xi;
+}
+
+// Host FP64 precompute of the low-rank factors, uploaded to the device.
+xf_status refresh_matrices(xf_plan *P) {
+    const int n = P->n, m = P->m, G = P->G, L = P->L;
+    std::vector<std::vector<cd>> R(P->n_rot, std::vector<cd>((size_t)n * n));
+    for (int l = 0; l < P->n_rot; ++l)
+        for (size_t i = 0; i < (size_t)n * n; ++i)
+            R[l][i] = cd(P->rot[2 * ((size_t)l * n * n + i)], P->rot[2 * ((size_t)l * n * n + i) + 1]);
+    // R'_l = R_l D0_{l-1}: column q of R_l times prod of e^{i theta_j / 2} over
+    // the gates j of CPhase layer l-1 that touch mode q.
+    for (int l = 1; l < P->n_rot; ++l) {
+        std::vector<cd> d(n, 1.0);
+        for (int j = 0; j < P->k; ++j) {
+            if (P->layer[j] != l - 1) continue;
+            const cd f = std::polar(1.0, P->theta[j] / 2.0);
+            d[P->pairs[2 * j]] *= f;
+            d[P->pairs[2 * j + 1]] *= f;
+        }
+        for (int r = 0; r < n; ++r)
+            for (int q = 0; q < n; ++q) R[l][(size_t)r * n + q] *= d[q];
+    }
+    std::vector<cd> Phi0((size_t)n * m), Pm, Qm, Tm;
+    for (int r = 0; r < n; ++r)
+        for (int a = 0; a < m; ++a) Phi0[(size_t)r * m + a] = R[0][(size_t)r * n + P->C[a]];
+    Pm = Phi0;
+    if (L >= 1) {
+        Qm.assign((size_t)n * m, 0.0);
+        matmul(R[1].data(), Phi0.data(), Qm.data(), n, n, m);
+        Pm = Qm;
+    }
+    if (L == 2) {
+        Pm.assign((size_t)n * m, 0.0);
+        matmul(R[2].data(), Qm.data(), Pm.data(), n, n, m);
+        Tm.assign((size_t)n * n, 0.0);
+        matmul(R[2].data(), R[1].data(), Tm.data(), n, n, n);
+    }
+    auto padded = [&](const std::vector<cd> &X) {
+        std::vector<double> out((size_t)n * G * 2, 0.0);
+        for (int r = 0; r < n; ++r)
+            for (int a = 0; a < m; ++a) {
+                out[2 * ((size_t)r * G + a)] = X[(size_t)r * m + a].real();
+                out[2 * ((size_t)r * G + a) + 1] = X[(size_t)r * m + a].imag();
+            }
+        return out;
+    };
+    auto flat = [&](const std::vector<cd> &X) {
+        std::vector<double> out(X.size() * 2);
+        for (size_t i = 0; i < X.size(); ++i) out[2 * i] = X[i].real(), out[2 * i + 1] = X[i].imag();
+        return out;
+    };
+    auto tofloat = [](const std::vector<double> &x) {
+        std::vector<float> f(x.size());
+        for (size_t i = 0; i < x.size(); ++i) f[i] = (float)x[i];
+        return f;
+    };
+    xf_status st;
+    auto up = [&](DevBuf &b, const std::vector<double> &h) { return dev_upload(b, h.data(), h.size() * 8); };
+    auto upf = [&](DevBuf &b, const std::vector<double> &h) {
+        const std::vector<float> f = tofloat(h);
+        return dev_upload(b, f.data(), f.size() * 4);
+    };
+    const std::vector<double> hP = padded(Pm), hPhi = padded(Phi0);
+    if ((st = up(P->dP, hP)) || (st = up(P->dPhi0, hPhi)) || (st = upf(P->fPhi0, hPhi))) return st;
+    if (L == 1) {
+        const std::vector<double> a1 = flat(R[1]);
+        if ((st = up(P->dA1, a1)) || (st = upf(P->fA1, a1))) return st;
+    } else if (L == 2) {
+        const std::vector<double> a1 = flat(Tm), a2 = flat(R[2]), r1 = flat(R[1]), q = padded(Qm);
+        if ((st = up(P->dA1, a1)) || (st = upf(P->fA1, a1)) || (st = up(P->dA2, a2)) ||
+            (st = upf(P->fA2, a2)) || (st = up(P->dR1, r1)) || (st = upf(P->fR1, r1)) ||
+            (st = up(P->dQ, q)) || (st = upf(P->fQ, q)))
+            return st;
+    }
+    P->nxterms = -1;
+    return XF_OK;
+}
+
+xf_status refresh_table(xf_plan *P) {
+    const std::vector<uint32_t> T = sampling_table(P->theta);
+    return dev_upload(P->dT, T.data(), T.size() * 4);
+}
+
+// Exact mode: all 2^k trajectories grouped by key, weights summed in
+// ascending x (Sec. III-B Eq. 8-9); zero weights dropped.
+xf_status build_exact_terms(xf_plan *P) {
+    const int k = P->k;
+    const uint64_t nx = 1ull << k;
+    std::vector<cd> f0(k), f1(k);
+    for (int j = 0; j < k; ++j) {
+        f0[j] = cd(std::cos(P->theta[j] / 4.0), 0.0);
+        f1[j] = cd(0.0, std::sin(P->theta[j] / 4.0));
+    }
+    std::vector<std::pair<uint64_t, uint64_t>> kx;
+    kx.reserve(nx);
+    for (uint64_t x = 0; x < nx; ++x) {
+        uint64_t key = 0;
+        for (int j = 0; j < k; ++j)
+            if ((x >> j) & 1) key ^= P->gkey[j];
+        kx.emplace_back(key, x);
+    }
+    std::sort(kx.begin(), kx.end());
+    std::vector<uint64_t> keys;
+    std::vector<double> w;
+    for (size_t i = 0; i < kx.size();) {
+        size_t e = i;
+        cd acc = 0.0;
+        while (e < kx.size() && kx[e].first == kx[i].first) {
+            cd wx = 1.0;
+            for (int j = 0; j < k; ++j) wx *= ((kx[e].second >> j) & 1) ? f1[j] : f0[j];
+            acc += wx;
+            ++e;
+        }
+        if (acc != 0.0) {
+            keys.push_back(kx[i].first);
+            w.push_back(acc.real());
+            w.push_back(acc.imag());
+        }
+        i = e;
+    }
+    xf_status st;
+    if ((st = dev_upload(P->dxkeys, keys.data(), keys.size() * 8)) ||
+        (st = dev_upload(P->dxw, w.data(), w.size() * 8)))
+        return st;
+    P->nxterms = (int64_t)keys.size();
+    return XF_OK;
+}
+
+xf::DevPlan snapshot(const xf_plan *P) {
+    xf::DevPlan d{};
+    d.n = P->n, d.m = P->m, d.L = P->L, d.k = P->k, d.G = P->G;
+    d.keykind = P->keykind, d.keybits = P->keybits, d.off1 = P->off1;
+    d.P = (const double2 *)P->dP.p;
+    d.Phi0 = (const double2 *)P->dPhi0.p;
+    d.A1 = (const double2 *)P->dA1.p;
+    d.A2 = (const double2 *)P->dA2.p;
+    d.Q = (const double2 *)P->dQ.p;
+    d.R1 = (const double2 *)P->dR1.p;
+    d.fPhi0 = (const float2 *)P->fPhi0.p;
+    d.fA1 = (const float2 *)P->fA1.p;
+    d.fA2 = (const float2 *)P->fA2.p;
+    d.fQ = (const float2 *)P->fQ.p;
+    d.fR1 = (const float2 *)P->fR1.p;
+    d.keymode = (const uint8_t *)P->dkeymode.p;
+    d.T = (const uint32_t *)P->dT.p;
+    d.gkey = (const uint64_t *)P->dgkey.p;
+    d.gmode = (const uint64_t *)P->dgmode.p;
+    d.glayer = (const int32_t *)P->dglayer.p;
+    d.gneg = (const uint8_t *)P->dgneg.p;
+    d.scale = 1.0;
+    return d;
+}
+
+void plan_free(xf_plan *P) {
+    for (DevBuf *b : {&P->dP, &P->dPhi0, &P->dA1, &P->dA2, &P->dQ, &P->dR1, &P->fPhi0, &P->fA1,
+                      &P->fA2, &P->fQ, &P->fR1, &P->dkeymode, &P->dT, &P->dgkey, &P->dgmode,
+                      &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw})
+        dev_free(*b);
+}
+
+xf_status set_gate_tables(xf_plan *P) {
+    // signs of the angles (phase i or -i of a d_1 choice)
+    P->gneg.assign(std::max(P->k, 1), 0);
+    for (int j = 0; j < P->k; ++j) P->gneg[j] = P->theta[j] < 0.0 ? 1 : 0;
+    return dev_upload(P->dgneg, P->gneg.data(), P->gneg.size());
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *xf_last_error(void) { return g_err.c_str(); }
+
+xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision precision, int device,
+                         xf_plan **plan) {
+    if (!plan) return fail(XF_EINVAL, "plan output pointer is NULL");
+    *plan = nullptr;
+    if (!c) return fail(XF_EINVAL, "circuit is NULL");
+    if (c->n < 1) return fail(XF_EINVAL, "n must be >= 1");
+    if (c->n > 128) return fail(XF_EUNSUPPORTED, "n = %d > 128", c->n);
+    if (c->n_rot < 1) return fail(XF_EINVAL, "n_rot must be >= 1");
+    if (c->n_rot > 3) return fail(XF_EUNSUPPORTED, "n_rot = %d > 3", c->n_rot);
+    if (!c->rot) return fail(XF_EINVAL, "rot is NULL");
+    if (c->k < 0) return fail(XF_EINVAL, "k must be >= 0");
+    if (c->k > 0 && (!c->pairs || !c->layer || !c->theta)) return fail(XF_EINVAL, "pairs/layer/theta is NULL");
+    if (precision != XF_FP64 && precision != XF_MIXED) return fail(XF_EINVAL, "unknown precision");
+    const int n = c->n, k = c->k, n_rot = c->n_rot;
+    for (int j = 0; j < k; ++j) {
+        const int a = c->pairs[2 * j], b = c->pairs[2 * j + 1];
+        if (a < 0 || a >= n || b < 0 || b >= n || a == b) return fail(XF_EINVAL, "gate %d has invalid pair (%d, %d)", j, a, b);
+        if (c->layer[j] < 0 || c->layer[j] > n_rot - 2) return fail(XF_EINVAL, "gate %d has invalid layer %d", j, c->layer[j]);
+    }
+    if (n < 128) {
+        const uint64_t hi0 = n >= 64 ? 0ull : (~0ull << n);
+        const uint64_t hi1 = n <= 64 ? ~0ull : (~0ull << (n - 64));
+        if ((input.w[0] & hi0) || (input.w[1] & hi1)) return fail(XF_EINVAL, "input has bits at or above n");
+    }
+    const int m = __builtin_popcountll(input.w[0]) + __builtin_popcountll(input.w[1]);
+    if (m > 64) return fail(XF_EUNSUPPORTED, "eta = %d > 64", m);
+    xf_status st = check_params(n, n_rot, c->rot, k, c->theta);
+    if (st) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(XF_EDEVICE, "device %d not available", device);
+
+    xf_plan *P = new (std::nothrow) xf_plan();
+    if (!P) return fail(XF_ENOMEM, "host allocation failed");
+    P->device = device;
+    P->n = n, P->n_rot = n_rot, P->k = k, P->m = m, P->L = n_rot - 1;
+    P->precision = precision;
+    P->G = 4;
+    while (P->G < m) P->G *= 2;
+    P->rot.assign(c->rot, c->rot + (size_t)n_rot * n * n * 2);
+    P->pairs.assign(c->pairs ? c->pairs : nullptr, c->pairs ? c->pairs + 2 * k : nullptr);
+    P->layer.assign(c->layer ? c->layer : nullptr, c->layer ? c->layer + k : nullptr);
+    P->theta.assign(c->theta ? c->theta : nullptr, c->theta ? c->theta + k : nullptr);
+    for (int q = 0; q < n; ++q)
+        if ((input.w[q >> 6] >> (q & 63)) & 1) P->C.push_back(q);
+
+    // Flip-pattern keys: the modes touched by each CPhase layer, packed.
+    std::vector<std::vector<int>> act(2);
+    for (int j = 0; j < k; ++j)
+        for (int side = 0; side < 2; ++side) act[P->layer[j]].push_back(P->pairs[2 * j + side]);
+    for (auto &v : act) {
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+    P->off1 = (int)act[0].size();
+    P->keybits = (int)(act[0].size() + act[1].size());
+    P->keymode.assign(64, 0);
+    P->gkey.assign(std::max(k, 1), 0);
+    P->gmode.assign(2 * std::max(k, 1), 0);
+    std::vector<int32_t> glayer(std::max(k, 1), 0);
+    if (P->keybits <= 63) P->keykind = 0;
+    else if (k <= 63) P->keykind = 1;
+    else P->keykind = -1;
+    for (size_t i = 0; i < act[0].size() && P->keybits <= 63; ++i) P->keymode[i] = (uint8_t)act[0][i];
+    for (size_t i = 0; i < act[1].size() && P->keybits <= 63; ++i) P->keymode[P->off1 + i] = (uint8_t)act[1][i];
+    for (int j = 0; j < k; ++j) {
+        const int l = P->layer[j];
+        glayer[j] = l;
+        for (int side = 0; side < 2; ++side) {
+            const int q = P->pairs[2 * j + side];
+            P->gmode[2 * j + (q >> 6)] ^= 1ull << (q & 63);
+            if (P->keykind == 0) {
+                const int pos = (l == 0 ? 0 : P->off1) +
+                                (int)(std::lower_bound(act[l].begin(), act[l].end(), q) - act[l].begin());
+                P->gkey[j] ^= 1ull << pos;
+            }
+        }
+        if (P->keykind == 1) P->gkey[j] = 1ull << j;
+    }
+
+    DeviceGuard guard(device);
+    if (!guard.okay) {
+        delete P;
+        return fail(XF_EDEVICE, "hipSetDevice(%d) failed", device);
+    }
+    if (xf::prepare_kernels(P->G) != hipSuccess) {
+        delete P;
+        return fail(XF_EDEVICE, "could not configure kernels");
+    }
+    if ((st = dev_upload(P->dkeymode, P->keymode.data(), 64)) ||
+        (st = dev_upload(P->dgkey, P->gkey.data(), P->gkey.size() * 8)) ||
+        (st = dev_upload(P->dgmode, P->gmode.data(), P->gmode.size() * 8)) ||
+        (st = dev_upload(P->dglayer, glayer.data(), glayer.size() * 4)) ||
+        (st = set_gate_tables(P)) || (st = dev_upload(P->dnterm, nullptr, 8)) ||
+        (st = refresh_matrices(P)) || (st = refresh_table(P))) {
+        plan_free(P);
+        delete P;
+        return st;
+    }
+    if (hipMemset(P->dnterm.p, 0, 8) != hipSuccess) {
+        plan_free(P);
+        delete P;
+        return fail(XF_EDEVICE, "hipMemset failed");
+    }
+    *plan = P;
+    return ok();
+}
+
+xf_status xf_plan_set_params(xf_plan *P, const double *rot, const double *theta) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    const double *r = rot ? rot : P->rot.data();
+    const double *th = theta ? theta : P->theta.data();
+    xf_status st = check_params(P->n, P->n_rot, r, P->k, th);
+    if (st) return st;
+    if (rot) P->rot.assign(rot, rot + P->rot.size());
+    if (theta) P->theta.assign(theta, theta + P->k);
+    DeviceGuard guard(P->device);
+    if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
+    if (hipDeviceSynchronize() != hipSuccess) return fail(XF_EDEVICE, "device synchronisation failed");
+    if ((st = refresh_matrices(P)) || (st = set_gate_tables(P))) return st;
+    return ok();
+}
+
+xf_status xf_plan_refreeze(xf_plan *P) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    DeviceGuard guard(P->device);
+    if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
+    if (hipDeviceSynchronize() != hipSuccess) return fail(XF_EDEVICE, "device synchronisation failed");
+    xf_status st;
+    if ((st = refresh_table(P)) || (st = set_gate_tables(P))) return st;
+    return ok();
+}
+
+xf_status xf_plan_destroy(xf_plan *P) {
+    if (!P) return ok();
+    {
+        DeviceGuard guard(P->device);
+        hipDeviceSynchronize();
+        plan_free(P);
+    }
+    delete P;
+    return ok();
+}
+
+xf_status xf_extent(const xf_plan *P, double *xi) {
+    if (!plan_valid(P) || !xi) return fail(XF_EINVAL, "invalid plan or NULL output");
+    *xi = extent_of(P->theta);
+    return ok();
+}
+
+xf_status xf_trajectory_bound(double eps, double delta, double p_max, double xi, int64_t *t) {
+    if (!t) return fail(XF_EINVAL, "NULL output");
+    if (!(eps > 0.0) || !(delta > 0.0 && delta < 1.0) || !(p_max >= 0.0 && p_max <= 1.0) || !(xi >= 1.0) ||
+        !std::isfinite(eps) || !std::isfinite(xi))
+        return fail(XF_EINVAL, "need eps > 0, 0 < delta < 1, 0 <= p_max <= 1, xi >= 1");
+    const double num = (std::sqrt(xi) + std::sqrt(p_max)) * (std::sqrt(xi) + std::sqrt(p_max));
+    const double gap = std::sqrt(p_max + eps) - std::sqrt(p_max);
+    const double v = std::ceil(2.0 * num / (gap * gap) * std::log(2.0 * std::exp(2.0) / delta));
+    if (!(v < 4.611686018427388e18)) return fail(XF_EUNSUPPORTED, "trajectory count exceeds 2^62");
+    *t = (int64_t)v;
+    return ok();
+}
+
+xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_mode mode, int64_t t,
+                           uint64_t seed, double *d_prob, double *d_amp, void *hip_stream) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    if (B < 0) return fail(XF_EINVAL, "B < 0");
+    if (mode != XF_EXACT && mode != XF_RAW_ESTIMATE) return fail(XF_EINVAL, "unknown mode");
+    if (mode == XF_RAW_ESTIMATE) {
+        if (t < 1) return fail(XF_EINVAL, "t must be >= 1");
+        if (t >= (int64_t)1 << 31) return fail(XF_EUNSUPPORTED, "t must be < 2^31");
+        if (P->k > 128) return fail(XF_EUNSUPPORTED, "k = %d > 128 in Raw Estimate mode", P->k);
+        if (P->keykind < 0) return fail(XF_EUNSUPPORTED, "flip patterns need %d > 63 key bits and k > 63", P->keybits);
+    } else if (P->k > 24) {
+        return fail(XF_EUNSUPPORTED, "exact mode needs k <= 24 (k = %d)", P->k);
+    }
+    if (B == 0) return ok();
+    if (!d_bits || !d_prob) return fail(XF_EINVAL, "d_bits or d_prob is NULL");
+    DeviceGuard guard(P->device);
+    if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)hip_stream;
+    xf_status st;
+    if (mode == XF_EXACT && P->nxterms < 0) {
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
+        if ((st = build_exact_terms(P))) return st;
+    }
+    xf::DevPlan d = snapshot(P);
+    if (xf::launch_zero_u64((unsigned long long *)P->dnterm.p, s) != hipSuccess)
+        return fail(XF_EDEVICE, "launch failed: %s", hipGetErrorString(hipGetLastError()));
+    hipError_t e;
+    if (mode == XF_RAW_ESTIMATE) {
+        d.scale = std::sqrt(extent_of(P->theta)) / (double)t;
+        e = xf::launch_raw_estimate(d, P->precision == XF_MIXED, (const uint64_t *)d_bits, B, t, seed, d_prob,
+                                    d_amp, (unsigned long long *)P->dnterm.p, s);
+    } else {
+        e = xf::launch_exact(d, P->precision == XF_MIXED, (const uint64_t *)P->dxkeys.p,
+                             (const double2 *)P->dxw.p, P->nxterms, (const uint64_t *)d_bits, B, d_prob,
+                             d_amp, (unsigned long long *)P->dnterm.p, s);
+    }
+    if (e != hipSuccess) return fail(XF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+xf_status xf_plan_last_term_count(xf_plan *P, int64_t *count) {
+    if (!plan_valid(P) || !count) return fail(XF_EINVAL, "invalid plan or NULL output");
+    DeviceGuard guard(P->device);
+    unsigned long long v = 0;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&v, P->dnterm.p, 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(XF_EDEVICE, "could not read the term counter");
+    *count = (int64_t)v;
+    return ok();
+}
+
+xf_status xf_log_prob_backward(xf_plan *P, const xf_bits128 *, int64_t, xf_mode, int64_t, uint64_t,
+                               const double *, double *, double *, void *) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    return fail(XF_EUNSUPPORTED, "backward pass not available in this build");
+}
+
+xf_status xf_expm_antihermitian(int32_t n, const double *K, double *U) {
+    if (n < 1 || n > 128) return fail(XF_EINVAL, "n must be in [1, 128]");
+    if (!K || !U) return fail(XF_EINVAL, "NULL pointer");
+    if (!finite_all(K, (size_t)n * n * 2)) return fail(XF_EINVAL, "K contains NaN/Inf");
+    std::vector<cd> A((size_t)n * n);
+    for (size_t i = 0; i < A.size(); ++i) A[i] = cd(K[2 * i], K[2 * i + 1]);
+    double scale = 1.0;
+    for (const cd &z : A) scale = std::max(scale, std::abs(z));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            if (std::abs(A[(size_t)i * n + j] + std::conj(A[(size_t)j * n + i])) > 1e-12 * scale)
+                return fail(XF_EINVAL, "K is not anti-Hermitian at (%d, %d)", i, j);
+    const std::vector<cd> E = expm(A, n);
+    for (size_t i = 0; i < E.size(); ++i) U[2 * i] = E[i].real(), U[2 * i + 1] = E[i].imag();
+    return ok();
+}
+
+xf_status xf_expm_adjoint(int32_t n, const double *K, const double *G_U, double *G_K) {
+    if (n < 1 || n > 128) return fail(XF_EINVAL, "n must be in [1, 128]");
+    if (!K || !G_U || !G_K) return fail(XF_EINVAL, "NULL pointer");
+    if (!finite_all(K, (size_t)n * n * 2) || !finite_all(G_U, (size_t)n * n * 2))
+        return fail(XF_EINVAL, "input contains NaN/Inf");
+    // L(K^H, G) is the top-right block of exp([[K^H, G], [0, K^H]]).
+    const int N2 = 2 * n;
+    std::vector<cd> X((size_t)N2 * N2, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const cd kh = std::conj(cd(K[2 * ((size_t)j * n + i)], K[2 * ((size_t)j * n + i) + 1]));
+            X[(size_t)i * N2 + j] = kh;
+            X[(size_t)(n + i) * N2 + (n + j)] = kh;
+            X[(size_t)i * N2 + (n + j)] = cd(G_U[2 * ((size_t)i * n + j)], G_U[2 * ((size_t)i * n + j) + 1]);
+        }
+    const std::vector<cd> E = expm(X, N2);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const cd v = E[(size_t)i * N2 + (n + j)];
+            G_K[2 * ((size_t)i * n + j)] = v.real();
+            G_K[2 * ((size_t)i * n + j) + 1] = v.imag();
+        }
+    return ok();
+}
+
+}  // extern "C"

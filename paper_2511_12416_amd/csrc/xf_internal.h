@@ -1,0 +1,68 @@
+// Internal definitions shared by the host plan code (xf_host.cpp) and the
+// gfx950 kernels (xf_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+#include <hip/hip_vector_types.h>
+
+namespace xf {
+
+// Threads per workgroup of the per-bitstring kernels (four wave64s).
+constexpr int kThreads = 256;
+// Slots of the per-bitstring LDS hash of flip patterns.  The table is
+// evaluated and cleared whenever one more batch of kThreads samples could push
+// it past three quarters full, so insertion always terminates.
+constexpr int kHashSlots = 2048;
+// Chunk of the shared exact-mode term list evaluated per LDS pass.
+constexpr int kExactChunk = 2048;
+// Empty-slot marker; valid keys use at most 63 bits.
+constexpr uint64_t kEmptyKey = ~0ull;
+
+// Snapshot of a plan's device state, passed by value to the kernels.
+//
+// Mode matrices (complex, (re, im) interleaved, row-major):
+//   Phi0 = R_0[:, C]                                  n x m (row stride G)
+//   P    = R'_L ... R'_1 Phi0                         n x m (row stride G)
+//   L = 1: A1 = R'_1                                   n x n
+//   L = 2: A1 = R'_2 R'_1, A2 = R'_2, R1 = R'_1        n x n,  Q = R'_1 Phi0 (n x m, stride G)
+// where R'_l = R_l D0_{l-1} absorbs the d_0 phases of the CPhase layer that
+// precedes rotation l.  The submatrix of trajectory x for a bitstring with
+// occupied rows R is then (Sec. IV-B Eq. 16-19, extended to two layers)
+//   L = 1: M = P[R,:] - 2 A1[R,N0] Phi0[N0,:]
+//   L = 2: M = P[R,:] - 2 sum_{c in N0} alpha_c Phi0[c,:] - 2 A2[R,N1] Q[N1,:],
+//          alpha_c = A1[R,c] - 2 A2[R,N1] R1[N1,c]
+// with N_l the modes flipped an odd number of times by the d_1 choices of
+// CPhase layer l.
+struct DevPlan {
+    int n, m, L, k, G;
+    // Key of a trajectory: kind 0 = bit-compressed flip pattern (bits
+    // [0, off1) are layer-0 active modes, [off1, keybits) layer-1 active
+    // modes); kind 1 = the trajectory x itself (bit j <=> x_j = 1).
+    int keykind, keybits, off1;
+    const double2 *P, *Phi0, *A1, *A2, *Q, *R1;
+    const float2 *fPhi0, *fA1, *fA2, *fQ, *fR1;
+    const uint8_t *keymode;   // [64] compressed key bit -> mode
+    const uint32_t *T;        // [k][k] sampling table
+    const uint64_t *gkey;     // [k] key contribution of gate j
+    const uint64_t *gmode;    // [k][2] mode mask of gate j's pair
+    const int32_t *glayer;    // [k]
+    const uint8_t *gneg;      // [k] theta_j < 0
+    double scale;             // Raw Estimate: sqrt(xi*) / t
+};
+
+// Launchers (xf_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
+hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
+                               int64_t t, uint64_t seed, double *prob, double *amp,
+                               unsigned long long *nterm, hipStream_t s);
+hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
+                        int64_t nkeys, const uint64_t *bits, int64_t B, double *prob, double *amp,
+                        unsigned long long *nterm, hipStream_t s);
+hipError_t prepare_kernels(int G);
+size_t raw_estimate_lds_bytes(const DevPlan &p);
+size_t exact_lds_bytes(const DevPlan &p);
+
+}  // namespace xf

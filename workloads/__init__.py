@@ -254,10 +254,12 @@ def workload(cfg: int, B: Optional[int] = None) -> Workload:
 
 def random_circuit(seed: int, n: int, eta: int, k: int, n_rot: int = 2,
                    theta_scale: float = 1.0, spin: bool = False,
-                   input_modes=None) -> Workload:
+                   input_modes=None, max_bits: int = 4096) -> Workload:
     """Small random circuit for tests: Haar rotation layers, ``k`` CPhase gates
     on random distinct pairs spread over the ``n_rot - 1`` CPhase layers,
-    angles uniform in [-theta_scale, theta_scale]; all weight-``eta`` outputs."""
+    angles uniform in [-theta_scale, theta_scale]; all weight-``eta`` outputs
+    when there are at most ``max_bits`` of them, else ``max_bits`` uniform
+    draws of weight-``eta`` outputs."""
     rng = np.random.Generator(np.random.PCG64(seed))
     if spin:
         norb = n // 2
@@ -270,6 +272,11 @@ def random_circuit(seed: int, n: int, eta: int, k: int, n_rot: int = 2,
     theta = rng.uniform(-theta_scale, theta_scale, size=k)
     if input_modes is None:
         input_modes = list(range(eta))
+    from math import comb
+    if comb(n, eta) <= max_bits:
+        bits = all_fixed_weight(n, eta)
+    else:
+        sel = random_fixed_weight(rng, np.arange(n), eta, max_bits)
+        bits = np.array([bits_from_modes(x) for x in sel], dtype=np.uint64).reshape(-1, 2)
     return Workload(f"random n={n} eta={eta} k={k}", n, bits_from_modes(input_modes),
-                    rot, pairs, layer, theta, all_fixed_weight(n, eta), "exact",
-                    n_rot=n_rot)
+                    rot, pairs, layer, theta, bits, "exact", n_rot=n_rot)
