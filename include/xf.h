@@ -126,10 +126,11 @@ xf_status xf_trajectory_bound(double eps, double delta, double p_max, double xi,
 
 /* Born-rule probabilities of B output bitstrings (Sec. III-A/B).
  *   d_bits  device [B] xf_bits128 (batch index i of d_bits[i] keys the sampler)
- *   mode    XF_EXACT (all 2^k trajectories; k <= 24) or XF_RAW_ESTIMATE (t >= 1,
- *           t < 2^32 samples per bitstring; k <= 128; the bit-compressed
- *           flip pattern, sum over CPhase layers of the modes their gates touch,
- *           must fit in 128 bits)
+ *   mode    XF_EXACT (all 2^k trajectories; k <= 24) or XF_RAW_ESTIMATE
+ *           (1 <= t < 2^31 samples per bitstring, k <= 128, and either the
+ *           modes touched by the gates of each CPhase layer, summed over
+ *           layers, number at most 63, or k <= 63: a trajectory's key must fit
+ *           in 63 bits; XF_EUNSUPPORTED otherwise)
  *   seed    sampler key (ignored in exact mode)
  *   d_prob  device [B] doubles: p_b
  *   d_amp   device [B][2] doubles: A_b, or NULL
@@ -153,9 +154,11 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
                                int64_t t, uint64_t seed, const double *d_grad_logp,
                                double *h_grad_rot, double *h_grad_theta, void *hip_stream);
 
-/* Number of distinct (bitstring, flip-pattern) determinants the last
- * xf_probabilities call on this plan evaluated (synchronises its stream). */
-xf_status xf_plan_last_term_count(xf_plan *plan, int64_t *count);
+/* Work done by the last xf_probabilities call on this plan (synchronises the
+ * device): *count = distinct (bitstring, flip-pattern) determinants
+ * evaluated; *rank_sum (nullable) = the sum over them of the number of
+ * flipped modes, i.e. of the ranks of the low-rank corrections composed. */
+xf_status xf_plan_last_term_count(xf_plan *plan, int64_t *count, int64_t *rank_sum);
 
 /* Host FP64 helpers for rotations parametrised by anti-Hermitian generators
  * (U = exp(K)), n <= 128:

@@ -106,10 +106,12 @@ class Plan:
         check(lib().xf_extent(self._h, ctypes.byref(xi)))
         return xi.value
 
-    def last_term_count(self) -> int:
-        c = ctypes.c_int64()
-        check(lib().xf_plan_last_term_count(self._h, ctypes.byref(c)))
-        return c.value
+    def last_term_count(self, with_rank: bool = False):
+        """Determinants evaluated by the last probabilities() call (and, with
+        ``with_rank``, the summed rank of their low-rank corrections)."""
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().xf_plan_last_term_count(self._h, ctypes.byref(c), ctypes.byref(r)))
+        return (c.value, r.value) if with_rank else c.value
 
     # -- the hot path ---------------------------------------------------------
     def probabilities(self, bits: torch.Tensor, mode: str = "exact", t: int = 0, seed: int = 0,

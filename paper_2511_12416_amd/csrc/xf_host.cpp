@@ -481,13 +481,13 @@ xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision pre
         (st = dev_upload(P->dgkey, P->gkey.data(), P->gkey.size() * 8)) ||
         (st = dev_upload(P->dgmode, P->gmode.data(), P->gmode.size() * 8)) ||
         (st = dev_upload(P->dglayer, glayer.data(), glayer.size() * 4)) ||
-        (st = set_gate_tables(P)) || (st = dev_upload(P->dnterm, nullptr, 8)) ||
+        (st = set_gate_tables(P)) || (st = dev_upload(P->dnterm, nullptr, 16)) ||
         (st = refresh_matrices(P)) || (st = refresh_table(P))) {
         plan_free(P);
         delete P;
         return st;
     }
-    if (hipMemset(P->dnterm.p, 0, 8) != hipSuccess) {
+    if (hipMemset(P->dnterm.p, 0, 16) != hipSuccess) {
         plan_free(P);
         delete P;
         return fail(XF_EDEVICE, "hipMemset failed");
@@ -591,14 +591,15 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
     return ok();
 }
 
-xf_status xf_plan_last_term_count(xf_plan *P, int64_t *count) {
+xf_status xf_plan_last_term_count(xf_plan *P, int64_t *count, int64_t *rank_sum) {
     if (!plan_valid(P) || !count) return fail(XF_EINVAL, "invalid plan or NULL output");
     DeviceGuard guard(P->device);
-    unsigned long long v = 0;
+    unsigned long long v[2] = {0, 0};
     if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(&v, P->dnterm.p, 8, hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(v, P->dnterm.p, 16, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(XF_EDEVICE, "could not read the term counter");
-    *count = (int64_t)v;
+    *count = (int64_t)v[0];
+    if (rank_sum) *rank_sum = (int64_t)v[1];
     return ok();
 }
 

@@ -223,12 +223,14 @@ __device__ __forceinline__ double2 lu_det(double2 (&a)[G], int m, int lane, doub
 }
 
 // det of the trajectory submatrix for `key`, evaluated by a group of G lanes.
+// *rank receives the number of flipped modes (the rank of the correction).
 template <int G, bool MIXED>
 __device__ __forceinline__ double2 term_det(const DevPlan &p, uint64_t key, const uint8_t *Rb,
-                                            int lane, double2 *piv) {
+                                            int lane, double2 *piv, int *rank) {
     double2 a[G];
+    const Flips f = decode_key(p, key);
+    *rank = __popcll(f.n0[0]) + __popcll(f.n0[1]) + __popcll(f.n1[0]) + __popcll(f.n1[1]);
     if (lane < p.m) {
-        const Flips f = decode_key(p, key);
         compose_row<G, MIXED>(p, Rb[lane], f, a);
     } else {
 #pragma unroll
@@ -354,18 +356,24 @@ __device__ double2 flush_table(const DevPlan &p, const RawSmem &s, int *s_n, int
     }
     const int lane = tid % G, grp = tid / G;
     constexpr int NG = kThreads / G;
+    unsigned rank_sum = 0;
     for (int e = grp; e < nl; e += NG) {
         const uint16_t slot = s.list[e];
-        const double2 d = term_det<G, MIXED>(p, s.hkey[slot], s.Rb, lane, s.piv + grp * G);
+        int rank;
+        const double2 d = term_det<G, MIXED>(p, s.hkey[slot], s.Rb, lane, s.piv + grp * G, &rank);
         if (lane == 0) {
             const int2 c = s.hcnt[slot];
             s.out[e] = make_double2((double)c.x * d.x - (double)c.y * d.y,
                                     (double)c.x * d.y + (double)c.y * d.x);
+            rank_sum += (unsigned)rank;
         }
     }
     __syncthreads();
     const double2 sum = ordered_sum(s.out, nl, s.red);
-    if (tid == 0 && nterm) atomicAdd(nterm, (unsigned long long)nl);
+    if (nterm) {
+        if (tid == 0) atomicAdd(nterm, (unsigned long long)nl);
+        if (lane == 0 && rank_sum) atomicAdd(nterm + 1, (unsigned long long)rank_sum);
+    }
     for (int i = tid; i < kHashSlots; i += kThreads) {
         s.hkey[i] = kEmptyKey;
         s.hcnt[i] = make_int2(0, 0);
@@ -515,11 +523,16 @@ k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict_
             continue;
         }
         double2 total = make_double2(0.0, 0.0);
+        unsigned rank_sum = 0;
         for (int64_t c0 = 0; c0 < nkeys; c0 += kExactChunk) {
             const int ncur = (int)min((int64_t)kExactChunk, nkeys - c0);
             for (int e = grp; e < ncur; e += NG) {
-                const double2 d = term_det<G, MIXED>(p, keys[c0 + e], Rb, lane, piv + grp * G);
-                if (lane == 0) out[e] = c_mul(w[c0 + e], d);
+                int rank;
+                const double2 d = term_det<G, MIXED>(p, keys[c0 + e], Rb, lane, piv + grp * G, &rank);
+                if (lane == 0) {
+                    out[e] = c_mul(w[c0 + e], d);
+                    rank_sum += (unsigned)rank;
+                }
             }
             __syncthreads();
             const double2 part = ordered_sum(out, ncur, red);
@@ -531,11 +544,15 @@ k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict_
             if (amp) { amp[2 * b] = total.x; amp[2 * b + 1] = total.y; }
             if (nterm) atomicAdd(nterm, (unsigned long long)nkeys);
         }
+        if (nterm && lane == 0 && rank_sum) atomicAdd(nterm + 1, (unsigned long long)rank_sum);
         __syncthreads();
     }
 }
 
-__global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+__global__ void k_zero_u64(unsigned long long *p) {
+    p[0] = 0ull;
+    p[1] = 0ull;
+}
 
 constexpr int kMaxGrid = 1 << 20;
 
