@@ -134,13 +134,14 @@ xf_status xf_trajectory_bound(double eps, double delta, double p_max, double xi,
  *   seed    sampler key (ignored in exact mode)
  *   d_prob  device [B] doubles: p_b
  *   d_amp   device [B][2] doubles: A_b, or NULL
+ *   d_logp  device [B] doubles: log p_b in FP64 (-inf where p_b = 0), or NULL
  * A bitstring whose weight differs from eta, or with bits at or above n, gets
  * p = 0 and A = 0 (passive circuits conserve the weight, Sec. II-B).  B = 0 is
  * a no-op.  Uses plan-owned device scratch; results are bitwise reproducible
  * for fixed inputs. */
 xf_status xf_probabilities(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, xf_mode mode,
                            int64_t t, uint64_t seed, double *d_prob, double *d_amp,
-                           void *hip_stream);
+                           double *d_logp, void *hip_stream);
 
 /* Gradient of L = sum_b g_b log p_b, g = d_grad_logp (device [B] doubles),
  * with respect to every rotation entry (h_grad_rot, host [n_rot][n][n][2],

@@ -4,3 +4,4 @@ include/xf.h, with a thin Python binding."""
 from ._abi import XfError, lib  # noqa: F401
 from .api import (Plan, bits_tensor, expm_adjoint, expm_antihermitian,  # noqa: F401
                   spin_rotations, trajectory_bound)
+from . import autograd  # noqa: F401

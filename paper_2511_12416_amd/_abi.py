@@ -60,7 +60,7 @@ def lib() -> ctypes.CDLL:
     L.xf_plan_destroy.argtypes = [P]
     L.xf_extent.argtypes = [P, ctypes.POINTER(D)]
     L.xf_trajectory_bound.argtypes = [D, D, D, D, ctypes.POINTER(I64)]
-    L.xf_probabilities.argtypes = [P, P, I64, S, I64, U64, P, P, P]
+    L.xf_probabilities.argtypes = [P, P, I64, S, I64, U64, P, P, P, P]
     L.xf_log_prob_backward.argtypes = [P, P, I64, S, I64, U64, P, P, P, P]
     L.xf_plan_last_term_count.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.xf_expm_antihermitian.argtypes = [I32, P, P]

@@ -116,8 +116,9 @@ class Plan:
     # -- the hot path ---------------------------------------------------------
     def probabilities(self, bits: torch.Tensor, mode: str = "exact", t: int = 0, seed: int = 0,
                       out: Optional[torch.Tensor] = None, amp: Optional[torch.Tensor] = None,
-                      return_amp: bool = False):
-        """p_b for a [B, 2] int64 device tensor of bit patterns."""
+                      return_amp: bool = False, logp: Optional[torch.Tensor] = None):
+        """p_b for a [B, 2] int64 device tensor of bit patterns (optionally the
+        amplitudes A_b and, into ``logp``, log p_b)."""
         bits = bits.contiguous()
         if bits.device != self.device or bits.dtype != torch.int64:
             raise ValueError("bits must be an int64 tensor on the plan's device")
@@ -129,6 +130,7 @@ class Plan:
         check(lib().xf_probabilities(self._h, bits.data_ptr(), B, _MODES[mode], int(t),
                                      int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(),
                                      amp.data_ptr() if amp is not None else None,
+                                     logp.data_ptr() if logp is not None else None,
                                      _stream_handle(self.device)))
         if return_amp:
             return out, torch.view_as_complex(amp)

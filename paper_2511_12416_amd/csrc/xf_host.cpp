@@ -153,8 +153,14 @@ struct xf_plan {
     // device state
     DevBuf dP, dPhi0, dA1, dA2, dQ, dR1, fPhi0, fA1, fA2, fQ, fR1;
     DevBuf dkeymode, dT, dgkey, dgmode, dglayer, dgneg, dnterm;
-    DevBuf dxkeys, dxw;               // exact-mode term list
+    DevBuf dxkeys, dxw, dxdw;         // exact-mode term list (+ angle derivatives of the weights)
     int64_t nxterms = -1;             // -1: not built for the current parameters
+    bool xterms_have_dw = false;
+    // host copies of the factors, for the backward chain rule
+    std::vector<std::vector<cd>> Rp;  // R'_l = R_l D0_{l-1} (R'_0 = R_0), n x n each
+    std::vector<std::vector<cd>> d0;  // diagonal of D0_{l-1} for l >= 1 (index l)
+    std::vector<cd> hPhi0;            // n x m
+    DevBuf dpart, dgsum;              // backward scratch: per-workgroup partials, reduced sums
 };
 
 namespace {
@@ -226,6 +232,7 @@ xf_status refresh_matrices(xf_plan *P) {
             R[l][i] = cd(P->rot[2 * ((size_t)l * n * n + i)], P->rot[2 * ((size_t)l * n * n + i) + 1]);
     // R'_l = R_l D0_{l-1}: column q of R_l times prod of e^{i theta_j / 2} over
     // the gates j of CPhase layer l-1 that touch mode q.
+    P->d0.assign(P->n_rot, std::vector<cd>());
     for (int l = 1; l < P->n_rot; ++l) {
         std::vector<cd> d(n, 1.0);
         for (int j = 0; j < P->k; ++j) {
@@ -236,10 +243,13 @@ xf_status refresh_matrices(xf_plan *P) {
         }
         for (int r = 0; r < n; ++r)
             for (int q = 0; q < n; ++q) R[l][(size_t)r * n + q] *= d[q];
+        P->d0[l] = d;
     }
+    P->Rp = R;
     std::vector<cd> Phi0((size_t)n * m), Pm, Qm, Tm;
     for (int r = 0; r < n; ++r)
         for (int a = 0; a < m; ++a) Phi0[(size_t)r * m + a] = R[0][(size_t)r * n + P->C[a]];
+    P->hPhi0 = Phi0;
     Pm = Phi0;
     if (L >= 1) {
         Qm.assign((size_t)n * m, 0.0);
@@ -299,8 +309,11 @@ xf_status refresh_table(xf_plan *P) {
 }
 
 // Exact mode: all 2^k trajectories grouped by key, weights summed in
-// ascending x (Sec. III-B Eq. 8-9); zero weights dropped.
-xf_status build_exact_terms(xf_plan *P) {
+// ascending x (Sec. III-B Eq. 8-9).  Without derivatives, keys whose weight
+// sums to exactly zero are dropped.  With derivatives (for the backward
+// pass), dw[key][j] = sum over its x of dw(x)/dtheta_j is stored as well and
+// keys are kept while any of weight or derivatives is non-zero.
+xf_status build_exact_terms(xf_plan *P, bool with_dw) {
     const int k = P->k;
     const uint64_t nx = 1ull << k;
     std::vector<cd> f0(k), f1(k);
@@ -317,21 +330,45 @@ xf_status build_exact_terms(xf_plan *P) {
         kx.emplace_back(key, x);
     }
     std::sort(kx.begin(), kx.end());
+    // d/dtheta of cos(theta/4) and of i sin(theta/4)
+    std::vector<cd> g0(k), g1(k);
+    for (int j = 0; j < k; ++j) {
+        g0[j] = cd(-std::sin(P->theta[j] / 4.0) / 4.0, 0.0);
+        g1[j] = cd(0.0, std::cos(P->theta[j] / 4.0) / 4.0);
+    }
     std::vector<uint64_t> keys;
-    std::vector<double> w;
+    std::vector<double> w, dw;
+    std::vector<cd> dacc(k), fac(k);
     for (size_t i = 0; i < kx.size();) {
         size_t e = i;
         cd acc = 0.0;
+        std::fill(dacc.begin(), dacc.end(), cd(0.0));
         while (e < kx.size() && kx[e].first == kx[i].first) {
+            const uint64_t x = kx[e].second;
             cd wx = 1.0;
-            for (int j = 0; j < k; ++j) wx *= ((kx[e].second >> j) & 1) ? f1[j] : f0[j];
+            for (int j = 0; j < k; ++j) {
+                fac[j] = ((x >> j) & 1) ? f1[j] : f0[j];
+                wx *= fac[j];
+            }
             acc += wx;
+            if (with_dw) {
+                for (int j = 0; j < k; ++j) {
+                    cd d = ((x >> j) & 1) ? g1[j] : g0[j];
+                    for (int i2 = 0; i2 < k; ++i2)
+                        if (i2 != j) d *= fac[i2];
+                    dacc[j] += d;
+                }
+            }
             ++e;
         }
-        if (acc != 0.0) {
+        bool keep = acc != 0.0;
+        for (int j = 0; j < k && with_dw && !keep; ++j) keep = dacc[j] != 0.0;
+        if (keep) {
             keys.push_back(kx[i].first);
             w.push_back(acc.real());
             w.push_back(acc.imag());
+            if (with_dw)
+                for (int j = 0; j < k; ++j) dw.push_back(dacc[j].real()), dw.push_back(dacc[j].imag());
         }
         i = e;
     }
@@ -339,7 +376,9 @@ xf_status build_exact_terms(xf_plan *P) {
     if ((st = dev_upload(P->dxkeys, keys.data(), keys.size() * 8)) ||
         (st = dev_upload(P->dxw, w.data(), w.size() * 8)))
         return st;
+    if (with_dw && (st = dev_upload(P->dxdw, dw.data(), dw.size() * 8))) return st;
     P->nxterms = (int64_t)keys.size();
+    P->xterms_have_dw = with_dw;
     return XF_OK;
 }
 
@@ -371,7 +410,8 @@ xf::DevPlan snapshot(const xf_plan *P) {
 void plan_free(xf_plan *P) {
     for (DevBuf *b : {&P->dP, &P->dPhi0, &P->dA1, &P->dA2, &P->dQ, &P->dR1, &P->fPhi0, &P->fA1,
                       &P->fA2, &P->fQ, &P->fR1, &P->dkeymode, &P->dT, &P->dgkey, &P->dgmode,
-                      &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw})
+                      &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
+                      &P->dgsum})
         dev_free(*b);
 }
 
@@ -552,7 +592,7 @@ xf_status xf_trajectory_bound(double eps, double delta, double p_max, double xi,
 }
 
 xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_mode mode, int64_t t,
-                           uint64_t seed, double *d_prob, double *d_amp, void *hip_stream) {
+                           uint64_t seed, double *d_prob, double *d_amp, double *d_logp, void *hip_stream) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
     if (B < 0) return fail(XF_EINVAL, "B < 0");
     if (mode != XF_EXACT && mode != XF_RAW_ESTIMATE) return fail(XF_EINVAL, "unknown mode");
@@ -572,7 +612,7 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
     xf_status st;
     if (mode == XF_EXACT && P->nxterms < 0) {
         if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
-        if ((st = build_exact_terms(P))) return st;
+        if ((st = build_exact_terms(P, false))) return st;
     }
     xf::DevPlan d = snapshot(P);
     if (xf::launch_zero_u64((unsigned long long *)P->dnterm.p, s) != hipSuccess)
@@ -581,11 +621,11 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
     if (mode == XF_RAW_ESTIMATE) {
         d.scale = std::sqrt(extent_of(P->theta)) / (double)t;
         e = xf::launch_raw_estimate(d, P->precision == XF_MIXED, (const uint64_t *)d_bits, B, t, seed, d_prob,
-                                    d_amp, (unsigned long long *)P->dnterm.p, s);
+                                    d_amp, d_logp, (unsigned long long *)P->dnterm.p, s);
     } else {
         e = xf::launch_exact(d, P->precision == XF_MIXED, (const uint64_t *)P->dxkeys.p,
                              (const double2 *)P->dxw.p, P->nxterms, (const uint64_t *)d_bits, B, d_prob,
-                             d_amp, (unsigned long long *)P->dnterm.p, s);
+                             d_amp, d_logp, (unsigned long long *)P->dnterm.p, s);
     }
     if (e != hipSuccess) return fail(XF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ok();
@@ -603,10 +643,132 @@ xf_status xf_plan_last_term_count(xf_plan *P, int64_t *count, int64_t *rank_sum)
     return ok();
 }
 
-xf_status xf_log_prob_backward(xf_plan *P, const xf_bits128 *, int64_t, xf_mode, int64_t, uint64_t,
-                               const double *, double *, double *, void *) {
+xf_status xf_log_prob_backward(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_mode mode, int64_t t,
+                               uint64_t seed, const double *d_grad_logp, double *h_grad_rot,
+                               double *h_grad_theta, void *hip_stream) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
-    return fail(XF_EUNSUPPORTED, "backward pass not available in this build");
+    if (B < 0) return fail(XF_EINVAL, "B < 0");
+    if (mode != XF_EXACT && mode != XF_RAW_ESTIMATE) return fail(XF_EINVAL, "unknown mode");
+    if (!h_grad_rot || (P->k > 0 && !h_grad_theta)) return fail(XF_EINVAL, "NULL gradient output");
+    if (B > 0 && (!d_bits || !d_grad_logp)) return fail(XF_EINVAL, "d_bits or d_grad_logp is NULL");
+    if (P->L > 1) return fail(XF_EUNSUPPORTED, "the backward pass supports at most one CPhase layer");
+    if (P->G > 16) return fail(XF_EUNSUPPORTED, "the backward pass supports eta <= 16 (eta = %d)", P->m);
+    if (mode == XF_RAW_ESTIMATE) {
+        if (t < 1) return fail(XF_EINVAL, "t must be >= 1");
+        if (t >= (int64_t)1 << 31) return fail(XF_EUNSUPPORTED, "t must be < 2^31");
+        if (P->keykind < 0) return fail(XF_EUNSUPPORTED, "trajectory keys do not fit in 63 bits");
+    } else if (P->k > 16) {
+        return fail(XF_EUNSUPPORTED, "exact-mode backward needs k <= 16 (k = %d)", P->k);
+    }
+    const int n = P->n, m = P->m, G = P->G, k = P->k;
+    xf::GradLayout lay;
+    lay.oP = 0;
+    lay.oPhi = n * G;
+    lay.oA1 = 2 * n * G;
+    lay.oW = lay.oA1 + n * n;
+    lay.oG = lay.oW + k;
+    lay.stride = lay.oG + 1;
+    std::vector<cd> red((size_t)lay.stride, 0.0);
+    xf::DevPlan d = snapshot(P);
+    const size_t lds = mode == XF_RAW_ESTIMATE ? xf::raw_estimate_bwd_lds_bytes(d) : xf::exact_bwd_lds_bytes(d);
+    if (lds > 159 * 1024) return fail(XF_EUNSUPPORTED, "backward needs %zu bytes of LDS (k too large)", lds);
+    DeviceGuard guard(P->device);
+    if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)hip_stream;
+    xf_status st;
+    if (B > 0) {
+        if (mode == XF_EXACT && (P->nxterms < 0 || !P->xterms_have_dw)) {
+            if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
+            if ((st = build_exact_terms(P, true))) return st;
+        }
+        const int nparts = (int)std::min<int64_t>(B, 1024);
+        const size_t part_bytes = (size_t)nparts * lay.stride * 16;
+        if ((st = dev_upload(P->dpart, nullptr, part_bytes)) || (st = dev_upload(P->dgsum, nullptr, (size_t)lay.stride * 16)))
+            return st;
+        hipError_t e = xf::launch_fill_zero((double *)P->dpart.p, part_bytes / 8, s);
+        if (e == hipSuccess) {
+            if (mode == XF_RAW_ESTIMATE) {
+                d.scale = std::sqrt(extent_of(P->theta)) / (double)t;
+                e = xf::launch_raw_estimate_bwd(d, P->precision == XF_MIXED, (const uint64_t *)d_bits, B, t, seed,
+                                                d_grad_logp, (double2 *)P->dpart.p, nparts, lay, s);
+            } else {
+                e = xf::launch_exact_bwd(d, P->precision == XF_MIXED, (const uint64_t *)P->dxkeys.p,
+                                         (const double2 *)P->dxw.p, (const double2 *)P->dxdw.p, P->nxterms,
+                                         (const uint64_t *)d_bits, B, d_grad_logp, (double2 *)P->dpart.p, nparts,
+                                         lay, s);
+            }
+        }
+        if (e == hipSuccess)
+            e = xf::launch_reduce_parts((const double2 *)P->dpart.p, nparts, lay.stride, (double2 *)P->dgsum.p, s);
+        if (e != hipSuccess) return fail(XF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+        if (hipMemcpyAsync(red.data(), P->dgsum.p, (size_t)lay.stride * 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(XF_EDEVICE, "could not read back the gradient sums");
+    }
+    // Host FP64 chain rule from the factors back to rotations and angles.
+    // All Gbar below are holomorphic adjoints: dL = 2 Re sum Gbar .* dZ.
+    std::vector<cd> GP((size_t)n * m), GPhi((size_t)n * m, 0.0), GA1((size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r)
+        for (int a = 0; a < m; ++a) {
+            GP[(size_t)r * m + a] = red[lay.oP + (size_t)r * G + a];
+            GPhi[(size_t)r * m + a] = red[lay.oPhi + (size_t)r * G + a];
+        }
+    for (size_t i = 0; i < (size_t)n * n; ++i) GA1[i] = red[lay.oA1 + i];
+    std::vector<std::vector<cd>> GR(P->n_rot, std::vector<cd>((size_t)n * n, 0.0));
+    std::vector<double> gth(k, 0.0);
+    if (P->L == 1) {
+        // P = R'_1 Phi0, A1 = R'_1
+        std::vector<cd> GRp = GA1;
+        const std::vector<cd> &Rp1 = P->Rp[1];
+        for (int r = 0; r < n; ++r)
+            for (int q = 0; q < n; ++q) {
+                cd acc = 0.0;
+                for (int a = 0; a < m; ++a) acc += GP[(size_t)r * m + a] * P->hPhi0[(size_t)q * m + a];
+                GRp[(size_t)r * n + q] += acc;
+            }
+        for (int q = 0; q < n; ++q)
+            for (int a = 0; a < m; ++a) {
+                cd acc = 0.0;
+                for (int r = 0; r < n; ++r) acc += Rp1[(size_t)r * n + q] * GP[(size_t)r * m + a];
+                GPhi[(size_t)q * m + a] += acc;
+            }
+        // R'_1 = R_1 D0: Gbar_R1[r][q] = Gbar_R'1[r][q] d_q; angles through d_q
+        std::vector<cd> colsum(n, 0.0);
+        for (int r = 0; r < n; ++r)
+            for (int q = 0; q < n; ++q) {
+                GR[1][(size_t)r * n + q] = GRp[(size_t)r * n + q] * P->d0[1][q];
+                colsum[q] += GRp[(size_t)r * n + q] * Rp1[(size_t)r * n + q];
+            }
+        for (int j = 0; j < k; ++j) {
+            const cd tr = colsum[P->pairs[2 * j]] + colsum[P->pairs[2 * j + 1]];
+            gth[j] += 2.0 * (cd(0.0, 0.5) * tr).real();
+        }
+    } else {
+        // P = Phi0
+        for (size_t i = 0; i < GPhi.size(); ++i) GPhi[i] += GP[i];
+    }
+    for (int r = 0; r < n; ++r)
+        for (int a = 0; a < m; ++a) GR[0][(size_t)r * n + P->C[a]] += GPhi[(size_t)r * m + a];
+    // weights
+    if (mode == XF_EXACT) {
+        for (int j = 0; j < k; ++j) gth[j] += 2.0 * red[lay.oW + j].real();
+    } else {
+        const double gsum = red[lay.oG].real();
+        for (int j = 0; j < k; ++j) {
+            const double th = P->theta[j];
+            const double sg = th > 0.0 ? 1.0 : (th < 0.0 ? -1.0 : 0.0);
+            const double sn = std::sin(std::fabs(th) / 4.0), cs = std::cos(std::fabs(th) / 4.0);
+            gth[j] += 2.0 * gsum * sg * (cs - sn) / (4.0 * (sn + cs));
+        }
+    }
+    // PyTorch convention: dL/dRe + i dL/dIm = 2 conj(Gbar)
+    for (int l = 0; l < P->n_rot; ++l)
+        for (size_t i = 0; i < (size_t)n * n; ++i) {
+            h_grad_rot[2 * ((size_t)l * n * n + i)] = 2.0 * GR[l][i].real();
+            h_grad_rot[2 * ((size_t)l * n * n + i) + 1] = -2.0 * GR[l][i].imag();
+        }
+    for (int j = 0; j < k; ++j) h_grad_theta[j] = gth[j];
+    return ok();
 }
 
 xf_status xf_expm_antihermitian(int32_t n, const double *K, double *U) {

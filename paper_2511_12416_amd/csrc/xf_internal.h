@@ -53,16 +53,37 @@ struct DevPlan {
     double scale;             // Raw Estimate: sqrt(xi*) / t
 };
 
+// One workgroup's partial gradient (complex entries, offsets in double2):
+//   oP   Gbar_P    n x G (row stride G)
+//   oPhi Gbar_Phi0 n x G (row stride G)
+//   oA1  Gbar_A1   n x n
+//   oW   exact-mode angle-weight sums, k entries
+//   oG   .x = sum of g_b over the bitstrings that contributed
+struct GradLayout {
+    int stride, oP, oPhi, oA1, oW, oG;
+};
+
 // Launchers (xf_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
 hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
-                               int64_t t, uint64_t seed, double *prob, double *amp,
+                               int64_t t, uint64_t seed, double *prob, double *amp, double *logp,
                                unsigned long long *nterm, hipStream_t s);
 hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
                         int64_t nkeys, const uint64_t *bits, int64_t B, double *prob, double *amp,
-                        unsigned long long *nterm, hipStream_t s);
+                        double *logp, unsigned long long *nterm, hipStream_t s);
+hipError_t launch_raw_estimate_bwd(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
+                                   int64_t t, uint64_t seed, const double *g, double2 *part, int nparts,
+                                   const GradLayout &lay, hipStream_t s);
+hipError_t launch_exact_bwd(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
+                            const double2 *dw, int64_t nkeys, const uint64_t *bits, int64_t B,
+                            const double *g, double2 *part, int nparts, const GradLayout &lay,
+                            hipStream_t s);
+hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
+hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, double2 *out, hipStream_t s);
 hipError_t prepare_kernels(int G);
 size_t raw_estimate_lds_bytes(const DevPlan &p);
 size_t exact_lds_bytes(const DevPlan &p);
+size_t raw_estimate_bwd_lds_bytes(const DevPlan &p);
+size_t exact_bwd_lds_bytes(const DevPlan &p);
 
 }  // namespace xf

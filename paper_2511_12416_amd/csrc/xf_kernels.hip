@@ -17,6 +17,8 @@
 //      reproducible, and p_b = |A_b|^2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "xf_internal.h"
 
 namespace xf {
@@ -241,7 +243,7 @@ __device__ __forceinline__ double2 term_det(const DevPlan &p, uint64_t key, cons
 
 // Loads bitstring b; returns false (and writes p = 0) if its weight is not
 // eta or it has bits at or above n.  Fills Rb with the occupied modes.
-__device__ bool load_bitstring(const DevPlan &p, const uint64_t *bits, int64_t b, uint8_t *Rb,
+__device__ __forceinline__ bool load_bitstring(const DevPlan &p, const uint64_t *bits, int64_t b, uint8_t *Rb,
                                int *s_ok) {
     if (threadIdx.x == 0) {
         const uint64_t w0 = bits[2 * b], w1 = bits[2 * b + 1];
@@ -264,7 +266,7 @@ __device__ bool load_bitstring(const DevPlan &p, const uint64_t *bits, int64_t b
 
 // Fixed-order sum of out[0..cnt): each thread adds a contiguous chunk, then a
 // fixed tree over the workgroup.  Result valid in thread 0.
-__device__ double2 ordered_sum(const double2 *out, int cnt, double2 *red) {
+__device__ __forceinline__ double2 ordered_sum(const double2 *out, int cnt, double2 *red) {
     const int tid = threadIdx.x;
     const int chunk = (cnt + kThreads - 1) / kThreads;
     double2 s = make_double2(0.0, 0.0);
@@ -286,6 +288,14 @@ __device__ double2 ordered_sum(const double2 *out, int cnt, double2 *red) {
     const double2 r = red[0];
     __syncthreads();
     return r;
+}
+
+// Bytes of dynamic LDS the per-bitstring sampler carves (see carve_raw).
+__host__ __device__ __forceinline__ size_t raw_lds_bytes(int kk) {
+    const size_t k = (size_t)kk;
+    const size_t raw = (size_t)kHashSlots * (16 + 8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + k * 8 +
+                       ((k + 7) & ~(size_t)7) + k * k * 4;
+    return (raw + 15) & ~(size_t)15;
 }
 
 struct RawSmem {
@@ -317,28 +327,28 @@ __device__ __forceinline__ RawSmem carve_raw(unsigned char *smem, int k) {
 }
 
 __device__ __forceinline__ uint64_t list_key(const RawSmem &s, uint16_t idx) {
-    return idx == 0xFFFFu ? kEmptyKey : s.hkey[idx];
+    return idx >= kHashSlots ? kEmptyKey : s.hkey[idx];
 }
 
-// Sorts, evaluates and sums the current hash content; clears the table and
-// re-reserves the empty pattern.  Called by the whole workgroup.
-template <int G, bool MIXED>
-__device__ double2 flush_table(const DevPlan &p, const RawSmem &s, int *s_n, int *s_claimed,
-                               int slot0, unsigned long long *nterm) {
+// Gathers the occupied slots of the hash (non-zero count) into s.list and
+// sorts them by key (keys are distinct), so every later pass over the entries
+// runs in a fixed order.  Returns the number of entries.
+__device__ __forceinline__ int prepare_list(const RawSmem &s, int *s_n) {
     const int tid = threadIdx.x;
     if (tid == 0) *s_n = 0;
     __syncthreads();
     for (int i = tid; i < kHashSlots; i += kThreads) {
-        if (s.hkey[i] != kEmptyKey && (s.hcnt[i].x != 0 || s.hcnt[i].y != 0))
-            s.list[atomicAdd(s_n, 1)] = (uint16_t)i;
+        if (s.hkey[i] != kEmptyKey && (s.hcnt[i].x != 0 || s.hcnt[i].y != 0)) {
+            const int at = atomicAdd(s_n, 1);
+            if (at < kHashSlots) s.list[at] = (uint16_t)i;
+        }
     }
     __syncthreads();
-    const int nl = *s_n;
+    const int nl = min(*s_n, kHashSlots);
     int np = 1;
     while (np < nl) np <<= 1;
     for (int i = nl + tid; i < np; i += kThreads) s.list[i] = 0xFFFFu;
     __syncthreads();
-    // bitonic sort of slot indices by key (keys are distinct)
     for (int size = 2; size <= np; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = tid; i < (np >> 1); i += kThreads) {
@@ -354,11 +364,110 @@ __device__ double2 flush_table(const DevPlan &p, const RawSmem &s, int *s_n, int
             __syncthreads();
         }
     }
+    return nl;
+}
+
+// Empties the table and re-reserves the slot of the empty flip pattern.
+__device__ __forceinline__ void clear_table(const RawSmem &s, int *s_claimed, uint32_t slot0) {
+    const int tid = threadIdx.x;
+    __syncthreads();
+    for (int i = tid; i < kHashSlots; i += kThreads) {
+        s.hkey[i] = kEmptyKey;
+        s.hcnt[i] = make_int2(0, 0);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s.hkey[slot0] = 0;
+        *s_claimed = 1;
+    }
+    __syncthreads();
+}
+
+// Draws trajectories of bitstring b (batch index b) from sample `*base`
+// onwards, reducing each to its flip-pattern key in the LDS hash, until either
+// all t samples are in (returns true) or one more batch of kThreads samples
+// could fill the table past three quarters (returns false).  The stopping
+// points depend only on the distinct keys seen, so every pass over the same
+// bitstring empties the table at the same samples.  After each return the
+// caller evaluates the sorted entries (prepare_list) and, if not done, clears
+// the table (clear_table) and calls again.  Whole workgroup; s.T / s.gkey /
+// s.gneg loaded; the table cleared before the first call.
+__device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSmem &s, int *s_claimed,
+                                                   uint32_t slot0, int64_t b, uint32_t t, uint32_t k0,
+                                                   uint32_t k1, uint32_t *base) {
+    const int tid = threadIdx.x;
+    const int k = p.k;
+    const uint32_t blo = (uint32_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
+    for (; *base < t; *base += kThreads) {
+        if (*s_claimed > 1 && *s_claimed + kThreads > (3 * kHashSlots) / 4) return false;
+        const uint32_t smp = *base + tid;
+        const bool valid = smp < t;
+        uint64_t key = 0;
+        uint32_t e = 0;
+        bool empty = true;
+        if (valid && k > 0) {
+            uint32_t blk = 0;
+            uint4 r = philox10(make_uint4(smp, 0u, blo, bhi), k0, k1);
+            uint32_t d = 0;
+            int a = 0;
+            while (a < k) {
+                if ((d >> 2) != blk) {
+                    blk = d >> 2;
+                    r = philox10(make_uint4(smp, blk, blo, bhi), k0, k1);
+                }
+                const uint32_t w = d & 3;
+                const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
+                ++d;
+                const uint32_t *Ta = s.T + a * k;
+                if (!(u < Ta[k - 1])) break;
+                int lo = a, hi = k - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (u < Ta[mid]) hi = mid;
+                    else lo = mid + 1;
+                }
+                key ^= s.gkey[lo];
+                e += 1u + 2u * s.gneg[lo];
+                empty = false;
+                a = lo + 1;
+            }
+        }
+        const unsigned long long ball = __ballot(valid && empty);
+        if ((tid & 63) == 0 && ball) atomicAdd(&s.hcnt[slot0].x, (int)__popcll(ball));
+        if (valid && !empty) {
+            uint32_t slot = hash_slot(key);
+            while (true) {
+                const unsigned long long prev =
+                    atomicCAS((unsigned long long *)&s.hkey[slot], (unsigned long long)kEmptyKey,
+                              (unsigned long long)key);
+                if (prev == kEmptyKey) {
+                    atomicAdd(s_claimed, 1);
+                    break;
+                }
+                if (prev == key) break;
+                slot = (slot + 1) & (kHashSlots - 1);
+            }
+            e &= 3;
+            if (e == 0) atomicAdd(&s.hcnt[slot].x, 1);
+            else if (e == 1) atomicAdd(&s.hcnt[slot].y, 1);
+            else if (e == 2) atomicAdd(&s.hcnt[slot].x, -1);
+            else atomicAdd(&s.hcnt[slot].y, -1);
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// Forward visitor: sum over the sorted entries of count * det, in a fixed order.
+template <int G, bool MIXED>
+__device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &s, int nl, unsigned long long *nterm) {
+    const int tid = threadIdx.x;
     const int lane = tid % G, grp = tid / G;
     constexpr int NG = kThreads / G;
     unsigned rank_sum = 0;
     for (int e = grp; e < nl; e += NG) {
         const uint16_t slot = s.list[e];
+        if (slot >= kHashSlots) continue;   // unreachable: the list holds slot indices
         int rank;
         const double2 d = term_det<G, MIXED>(p, s.hkey[slot], s.Rb, lane, s.piv + grp * G, &rank);
         if (lane == 0) {
@@ -374,26 +483,10 @@ __device__ double2 flush_table(const DevPlan &p, const RawSmem &s, int *s_n, int
         if (tid == 0) atomicAdd(nterm, (unsigned long long)nl);
         if (lane == 0 && rank_sum) atomicAdd(nterm + 1, (unsigned long long)rank_sum);
     }
-    for (int i = tid; i < kHashSlots; i += kThreads) {
-        s.hkey[i] = kEmptyKey;
-        s.hcnt[i] = make_int2(0, 0);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        s.hkey[slot0] = 0;
-        *s_claimed = 1;
-    }
-    __syncthreads();
     return sum;
 }
 
-template <int G, bool MIXED>
-__global__ void __launch_bounds__(kThreads)
-k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
-               double *__restrict__ prob, double *__restrict__ amp, unsigned long long *nterm) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n, s_claimed;
-    const RawSmem s = carve_raw(smem, p.k);
+__device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) {
     const int tid = threadIdx.x;
     const int k = p.k;
     for (int i = tid; i < k * k; i += kThreads) s.T[i] = p.T[i];
@@ -401,6 +494,18 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
         s.gkey[i] = p.gkey[i];
         s.gneg[i] = p.gneg[i];
     }
+}
+
+template <int G, bool MIXED>
+__global__ void __launch_bounds__(kThreads)
+k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
+               double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
+               unsigned long long *nterm) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_ok, s_n, s_claimed;
+    const RawSmem s = carve_raw(smem, p.k);
+    const int tid = threadIdx.x;
+    load_tables(p, s);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t slot0 = hash_slot(0);
 
@@ -409,91 +514,29 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
             if (tid == 0) {
                 prob[b] = 0.0;
                 if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
+                if (logp) logp[b] = -INFINITY;
             }
             __syncthreads();
             continue;
         }
-        for (int i = tid; i < kHashSlots; i += kThreads) {
-            s.hkey[i] = kEmptyKey;
-            s.hcnt[i] = make_int2(0, 0);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            s.hkey[slot0] = 0;
-            s_claimed = 1;
-        }
-        __syncthreads();
-
         double2 total = make_double2(0.0, 0.0);
-        const uint32_t blo = (uint32_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
-        for (uint32_t base = 0; base < t; base += kThreads) {
-            if (s_claimed + kThreads > (3 * kHashSlots) / 4) {
-                const double2 part = flush_table<G, MIXED>(p, s, &s_n, &s_claimed, slot0, nterm);
-                total.x += part.x;
-                total.y += part.y;
-            }
-            const uint32_t smp = base + tid;
-            const bool valid = smp < t;
-            uint64_t key = 0;
-            uint32_t e = 0;
-            bool empty = true;
-            if (valid && k > 0) {
-                uint32_t blk = 0;
-                uint4 r = philox10(make_uint4(smp, 0u, blo, bhi), k0, k1);
-                uint32_t d = 0;
-                int a = 0;
-                while (a < k) {
-                    if ((d >> 2) != blk) {
-                        blk = d >> 2;
-                        r = philox10(make_uint4(smp, blk, blo, bhi), k0, k1);
-                    }
-                    const uint32_t w = d & 3;
-                    const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
-                    ++d;
-                    const uint32_t *Ta = s.T + a * k;
-                    if (!(u < Ta[k - 1])) break;
-                    int lo = a, hi = k - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (u < Ta[mid]) hi = mid;
-                        else lo = mid + 1;
-                    }
-                    key ^= s.gkey[lo];
-                    e += 1u + 2u * s.gneg[lo];
-                    empty = false;
-                    a = lo + 1;
-                }
-            }
-            const unsigned long long ball = __ballot(valid && empty);
-            if ((tid & 63) == 0 && ball) atomicAdd(&s.hcnt[slot0].x, (int)__popcll(ball));
-            if (valid && !empty) {
-                uint32_t slot = hash_slot(key);
-                while (true) {
-                    const unsigned long long prev =
-                        atomicCAS((unsigned long long *)&s.hkey[slot], (unsigned long long)kEmptyKey,
-                                  (unsigned long long)key);
-                    if (prev == kEmptyKey) {
-                        atomicAdd(&s_claimed, 1);
-                        break;
-                    }
-                    if (prev == key) break;
-                    slot = (slot + 1) & (kHashSlots - 1);
-                }
-                e &= 3;
-                if (e == 0) atomicAdd(&s.hcnt[slot].x, 1);
-                else if (e == 1) atomicAdd(&s.hcnt[slot].y, 1);
-                else if (e == 2) atomicAdd(&s.hcnt[slot].x, -1);
-                else atomicAdd(&s.hcnt[slot].y, -1);
-            }
-            __syncthreads();
+        clear_table(s, &s_claimed, slot0);
+        uint32_t base = 0;
+        while (true) {
+            const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
+            const int nl = prepare_list(s, &s_n);
+            const double2 part = sum_entries<G, MIXED>(p, s, nl, nterm);
+            total.x += part.x;
+            total.y += part.y;
+            if (done) break;
+            clear_table(s, &s_claimed, slot0);
         }
-        const double2 part = flush_table<G, MIXED>(p, s, &s_n, &s_claimed, slot0, nterm);
-        total.x += part.x;
-        total.y += part.y;
         if (tid == 0) {
             const double ax = total.x * p.scale, ay = total.y * p.scale;
-            prob[b] = ax * ax + ay * ay;
+            const double pb = ax * ax + ay * ay;
+            prob[b] = pb;
             if (amp) { amp[2 * b] = ax; amp[2 * b + 1] = ay; }
+            if (logp) logp[b] = log(pb);
         }
         __syncthreads();
     }
@@ -503,7 +546,7 @@ template <int G, bool MIXED>
 __global__ void __launch_bounds__(kThreads)
 k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict__ w, int64_t nkeys,
         const uint64_t *__restrict__ bits, int64_t B, double *__restrict__ prob,
-        double *__restrict__ amp, unsigned long long *nterm) {
+        double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok;
     double2 *out = (double2 *)smem;
@@ -518,6 +561,7 @@ k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict_
             if (tid == 0) {
                 prob[b] = 0.0;
                 if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
+                if (logp) logp[b] = -INFINITY;
             }
             __syncthreads();
             continue;
@@ -540,13 +584,337 @@ k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict_
             total.y += part.y;
         }
         if (tid == 0) {
-            prob[b] = total.x * total.x + total.y * total.y;
+            const double pb = total.x * total.x + total.y * total.y;
+            prob[b] = pb;
             if (amp) { amp[2 * b] = total.x; amp[2 * b + 1] = total.y; }
+            if (logp) logp[b] = log(pb);
             if (nterm) atomicAdd(nterm, (unsigned long long)nkeys);
         }
         if (nterm && lane == 0 && rank_sum) atomicAdd(nterm + 1, (unsigned long long)rank_sum);
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (gradient of L = sum_b g_b log p_b)
+//
+// d log p_b = 2 Re(dA_b / A_b) and d det M = det M tr(M^-1 dM) (Jacobi), so
+// every distinct entry e of bitstring b contributes the holomorphic adjoint
+// Gbar_M = beta_e M_e^-T, beta_e = (g_b / A_b) c_e det M_e, which is pushed
+// back through the low-rank composition M = P[R,:] - 2 A1[R,N] Phi0[N,:]:
+//   Gbar_P[R_i, :]   += Gbar_M[i, :]
+//   Gbar_A1[R_i, c]  += -2 Gbar_M[i, :] . Phi0[c, :]      (c in N)
+//   Gbar_Phi0[c, :]  += -2 sum_i A1[R_i, c] Gbar_M[i, :]   (c in N)
+// The submatrix is recomputed, not stored.  M^-1 comes from Gauss-Jordan in
+// the same one-row-per-lane layout as the forward LU; an LDS tile per lane
+// group turns the permuted rows of M^-1 into both the rows and the columns
+// of Gbar_M.  Each workgroup accumulates into its own partial buffer, which a
+// fixed-order reduction adds up.
+// ---------------------------------------------------------------------------
+
+// Gauss-Jordan inverse with partial pivoting (same pivot rule as lu_det).
+// On return lane r (< m) holds row pos of M^-1 in v, where pos is the step at
+// which its row was the pivot; det = sign * prod(pivots).  Returns false for
+// an exactly singular matrix.
+template <int G>
+__device__ __forceinline__ bool gj_invert(double2 (&a)[G], double2 (&v)[G], int m, int lane,
+                                          double2 *pv, double2 &det, int &pos) {
+    bool active = lane < m;
+    bool live = true;
+    bool neg = false;
+    pos = lane;
+    det = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < G; ++j) v[j] = make_double2((j == lane && lane < m) ? 1.0 : 0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+        if (c < m && live) {
+            double best = active ? fma(a[c].x, a[c].x, a[c].y * a[c].y) : -1.0;
+            int idx = lane;
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                const double vo = __shfl_xor(best, off, G);
+                const int io = __shfl_xor(idx, off, G);
+                if (vo > best || (vo == best && io < idx)) {
+                    best = vo;
+                    idx = io;
+                }
+            }
+            if (best > 0.0) {
+                const int ppos = __shfl(pos, idx, G);
+                neg ^= (ppos != c);
+                if (pos == c) pos = ppos;
+                if (lane == idx) {
+                    pos = c;
+                    active = false;
+                    const double2 u = a[c];
+                    const double inv = 1.0 / fma(u.x, u.x, u.y * u.y);
+                    const double2 ui = make_double2(u.x * inv, -u.y * inv);
+                    pv[c] = u;
+#pragma unroll
+                    for (int j = c + 1; j < G; ++j) pv[j] = c_mul(a[j], ui);
+#pragma unroll
+                    for (int j = 0; j < G; ++j) pv[G + j] = c_mul(v[j], ui);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                det = c_mul(det, pv[c]);
+                if (lane == idx) {
+#pragma unroll
+                    for (int j = c + 1; j < G; ++j) a[j] = pv[j];
+#pragma unroll
+                    for (int j = 0; j < G; ++j) v[j] = pv[G + j];
+                    a[c] = make_double2(1.0, 0.0);
+                } else if (lane < m) {
+                    const double2 l = make_double2(-a[c].x, -a[c].y);
+#pragma unroll
+                    for (int j = c + 1; j < G; ++j) a[j] = c_fma(a[j], l, pv[j]);
+#pragma unroll
+                    for (int j = 0; j < G; ++j) v[j] = c_fma(v[j], l, pv[G + j]);
+                    a[c] = make_double2(0.0, 0.0);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            } else {
+                live = false;
+            }
+        }
+    }
+    if (neg) det = make_double2(-det.x, -det.y);
+    return live;
+}
+
+__device__ __forceinline__ void atomic_add_c(double2 *dst, double2 v) {
+    atomicAdd(&dst->x, v.x);
+    atomicAdd(&dst->y, v.y);
+}
+
+struct GradOut {
+    double2 *P, *Phi0, *A1, *W;   // this workgroup's partial (see GradLayout)
+    double *gsum;
+};
+
+// One entry's adjoint, evaluated by a group of G lanes.  coef = g_b / A_b
+// (times the Raw Estimate scale), ce = the entry's weight.  Adds its row of
+// Gbar_M into srow (summed over entries, scattered into Gbar_P per bitstring).
+// dw (exact mode, nullable): derivatives of the weight with respect to every
+// angle, k values.
+template <int G, bool MIXED>
+__device__ __forceinline__ void adjoint_entry(const DevPlan &p, uint64_t key, double2 ce, double2 coef,
+                              const double2 *dw, const uint8_t *Rb, int lane, double2 *pv,
+                              double2 *tile, double2 (&srow)[G], const GradOut &go) {
+    double2 det;
+    int pos;
+    const Flips f = decode_key(p, key);
+    {
+        double2 a[G], v[G];
+        if (lane < p.m) {
+            compose_row<G, MIXED>(p, Rb[lane], f, a);
+        } else {
+#pragma unroll
+            for (int j = 0; j < G; ++j) a[j] = make_double2(j == lane ? 1.0 : 0.0, 0.0);
+        }
+        if (!gj_invert<G>(a, v, p.m, lane, pv, det, pos)) return;   // det = 0: no contribution
+        if (lane < p.m) {
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (j < p.m) tile[pos * G + j] = v[j];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // weight derivatives (exact mode): dL/dtheta_j gets 2 Re(coef dw_j det)
+    if (dw) {
+        const double2 cd = c_mul(coef, det);
+        for (int j = lane; j < p.k; j += G) atomic_add_c(go.W + j, c_mul(cd, dw[j]));
+    }
+    const double2 beta = c_mul(c_mul(coef, ce), det);
+    if (lane < p.m) {
+        double2 gr[G], gc[G];   // row `lane` and column `lane` of Gbar_M
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (j < p.m) {
+                gr[j] = c_mul(beta, tile[j * G + lane]);
+                gc[j] = c_mul(beta, tile[lane * G + j]);
+            } else {
+                gr[j] = gc[j] = make_double2(0.0, 0.0);
+            }
+            srow[j].x += gr[j].x;
+            srow[j].y += gr[j].y;
+        }
+        if (p.L == 1) {
+            const int Ri = Rb[lane];
+            for_each_mode(f.n0, [&](int c) {
+                const double2 *phi = p.Phi0 + (size_t)c * G;
+                double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    s1 = c_fma(s1, gr[j], phi[j]);
+                    if (j < p.m) s2 = c_fma(s2, p.A1[(size_t)Rb[j] * p.n + c], gc[j]);
+                }
+                atomic_add_c(go.A1 + (size_t)Ri * p.n + c, make_double2(-2.0 * s1.x, -2.0 * s1.y));
+                atomic_add_c(go.Phi0 + (size_t)c * G + lane, make_double2(-2.0 * s2.x, -2.0 * s2.y));
+            });
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ GradOut grad_out(double2 *part, const GradLayout &L) {
+    double2 *base = part + (size_t)blockIdx.x * L.stride;
+    GradOut g;
+    g.P = base + L.oP;
+    g.Phi0 = base + L.oPhi;
+    g.A1 = base + L.oA1;
+    g.W = base + L.oW;
+    g.gsum = (double *)(base + L.oG);
+    return g;
+}
+
+template <int G>
+__device__ __forceinline__ void flush_srow(const DevPlan &p, const uint8_t *Rb, int lane, double2 (&srow)[G],
+                           const GradOut &go) {
+    if (lane < p.m) {
+        double2 *row = go.P + (size_t)Rb[lane] * G;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (j < p.m) atomic_add_c(row + j, srow[j]);
+    }
+}
+
+template <int G, bool MIXED>
+__global__ void __launch_bounds__(kThreads)
+k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
+                   const double *__restrict__ g, double2 *part, GradLayout lay) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_ok, s_n, s_claimed;
+    const RawSmem s = carve_raw(smem, p.k);
+    constexpr int NG = kThreads / G;
+    double2 *tiles = (double2 *)(smem + raw_lds_bytes(p.k));
+    double2 *pvs = tiles + NG * G * G;
+    const int tid = threadIdx.x;
+    const int lane = tid % G, grp = tid / G;
+    load_tables(p, s);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t slot0 = hash_slot(0);
+    const GradOut go = grad_out(part, lay);
+
+    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+        if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) continue;
+        const double gb = g[b];
+        if (gb == 0.0) continue;
+        double2 total = make_double2(0.0, 0.0);
+        clear_table(s, &s_claimed, slot0);
+        uint32_t base = 0;
+        while (true) {
+            const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
+            const int nl = prepare_list(s, &s_n);
+            const double2 part_sum = sum_entries<G, MIXED>(p, s, nl, nullptr);
+            total.x += part_sum.x;
+            total.y += part_sum.y;
+            if (done) break;
+            clear_table(s, &s_claimed, slot0);
+        }
+        const double ax = total.x * p.scale, ay = total.y * p.scale;
+        const double a2 = ax * ax + ay * ay;
+        if (a2 == 0.0) continue;
+        // coef = g_b / A_b * scale
+        const double2 coef = make_double2(gb * ax / a2 * p.scale, -gb * ay / a2 * p.scale);
+        double2 srow[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) srow[j] = make_double2(0.0, 0.0);
+        clear_table(s, &s_claimed, slot0);
+        base = 0;
+        while (true) {
+            const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
+            const int nl = prepare_list(s, &s_n);
+            for (int e = grp; e < nl; e += NG) {
+                const uint16_t slot = s.list[e];
+                const int2 c = s.hcnt[slot];
+                adjoint_entry<G, MIXED>(p, s.hkey[slot], make_double2((double)c.x, (double)c.y), coef,
+                                        nullptr, s.Rb, lane, pvs + grp * 2 * G, tiles + grp * G * G,
+                                        srow, go);
+            }
+            __syncthreads();
+            if (done) break;
+            clear_table(s, &s_claimed, slot0);
+        }
+        flush_srow<G>(p, s.Rb, lane, srow, go);
+        if (tid == 0) atomicAdd(go.gsum, gb);
+        __syncthreads();
+    }
+}
+
+template <int G, bool MIXED>
+__global__ void __launch_bounds__(kThreads)
+k_exact_bwd(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict__ w,
+            const double2 *__restrict__ dw, int64_t nkeys, const uint64_t *__restrict__ bits, int64_t B,
+            const double *__restrict__ g, double2 *part, GradLayout lay) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_ok;
+    constexpr int NG = kThreads / G;
+    double2 *out = (double2 *)smem;
+    double2 *piv = out + kExactChunk;
+    double2 *red = piv + kThreads;
+    double2 *tiles = red + kThreads;
+    double2 *pvs = tiles + NG * G * G;
+    uint8_t *Rb = (uint8_t *)(pvs + NG * 2 * G);
+    const int tid = threadIdx.x;
+    const int lane = tid % G, grp = tid / G;
+    const GradOut go = grad_out(part, lay);
+    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+        if (!load_bitstring(p, bits, b, Rb, &s_ok)) continue;
+        const double gb = g[b];
+        if (gb == 0.0) continue;
+        double2 total = make_double2(0.0, 0.0);
+        for (int64_t c0 = 0; c0 < nkeys; c0 += kExactChunk) {
+            const int ncur = (int)min((int64_t)kExactChunk, nkeys - c0);
+            for (int e = grp; e < ncur; e += NG) {
+                int rank;
+                const double2 d = term_det<G, MIXED>(p, keys[c0 + e], Rb, lane, piv + grp * G, &rank);
+                if (lane == 0) out[e] = c_mul(w[c0 + e], d);
+            }
+            __syncthreads();
+            const double2 ps = ordered_sum(out, ncur, red);
+            total.x += ps.x;
+            total.y += ps.y;
+        }
+        if (tid == 0) red[0] = total;
+        __syncthreads();
+        total = red[0];
+        __syncthreads();
+        const double a2 = total.x * total.x + total.y * total.y;
+        if (a2 == 0.0) continue;
+        const double2 coef = make_double2(gb * total.x / a2, -gb * total.y / a2);
+        double2 srow[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) srow[j] = make_double2(0.0, 0.0);
+        for (int64_t e = grp; e < nkeys; e += NG)
+            adjoint_entry<G, MIXED>(p, keys[e], w[e], coef, dw + (size_t)e * p.k, Rb, lane,
+                                    pvs + grp * 2 * G, tiles + grp * G * G, srow, go);
+        flush_srow<G>(p, Rb, lane, srow, go);
+        if (tid == 0) atomicAdd(go.gsum, gb);
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_zero(double *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// out[e] = sum over workgroups q = 0, 1, ... of part[q][e], in that order.
+__global__ void k_reduce_parts(const double2 *__restrict__ part, int nparts, int stride, double2 *out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= stride) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int q = 0; q < nparts; ++q) {
+        const double2 v = part[(size_t)q * stride + e];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    out[e] = acc;
 }
 
 __global__ void k_zero_u64(unsigned long long *p) {
@@ -558,22 +926,42 @@ constexpr int kMaxGrid = 1 << 20;
 
 template <int G, bool MIXED>
 hipError_t launch_raw_t(const DevPlan &p, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
-                        double *prob, double *amp, unsigned long long *nterm, hipStream_t s) {
+                        double *prob, double *amp, double *logp, unsigned long long *nterm, hipStream_t s) {
     const size_t lds = raw_estimate_lds_bytes(p);
     const int grid = (int)(B < kMaxGrid ? B : kMaxGrid);
     hipLaunchKernelGGL((k_raw_estimate<G, MIXED>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
-                       (uint32_t)t, seed, prob, amp, nterm);
+                       (uint32_t)t, seed, prob, amp, logp, nterm);
     return hipGetLastError();
 }
 
 template <int G, bool MIXED>
 hipError_t launch_exact_t(const DevPlan &p, const uint64_t *keys, const double2 *w, int64_t nkeys,
-                          const uint64_t *bits, int64_t B, double *prob, double *amp,
+                          const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
                           unsigned long long *nterm, hipStream_t s) {
     const size_t lds = exact_lds_bytes(p);
     const int grid = (int)(B < kMaxGrid ? B : kMaxGrid);
     hipLaunchKernelGGL((k_exact<G, MIXED>), dim3(grid), dim3(kThreads), lds, s, p, keys, w, nkeys,
-                       bits, B, prob, amp, nterm);
+                       bits, B, prob, amp, logp, nterm);
+    return hipGetLastError();
+}
+
+template <int G, bool MIXED>
+hipError_t launch_raw_bwd_t(const DevPlan &p, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
+                            const double *g, double2 *part, int nparts, const GradLayout &lay,
+                            hipStream_t s) {
+    const size_t lds = raw_estimate_bwd_lds_bytes(p);
+    hipLaunchKernelGGL((k_raw_estimate_bwd<G, MIXED>), dim3(nparts), dim3(kThreads), lds, s, p, bits, B,
+                       (uint32_t)t, seed, g, part, lay);
+    return hipGetLastError();
+}
+
+template <int G, bool MIXED>
+hipError_t launch_exact_bwd_t(const DevPlan &p, const uint64_t *keys, const double2 *w, const double2 *dw,
+                              int64_t nkeys, const uint64_t *bits, int64_t B, const double *g,
+                              double2 *part, int nparts, const GradLayout &lay, hipStream_t s) {
+    const size_t lds = exact_bwd_lds_bytes(p);
+    hipLaunchKernelGGL((k_exact_bwd<G, MIXED>), dim3(nparts), dim3(kThreads), lds, s, p, keys, w, dw,
+                       nkeys, bits, B, g, part, lay);
     return hipGetLastError();
 }
 
@@ -590,19 +978,87 @@ hipError_t set_lds_limits() {
     if ((e = hipFuncSetAttribute((const void *)k_exact<G, false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
         return e;
-    return hipFuncSetAttribute((const void *)k_exact<G, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if ((e = hipFuncSetAttribute((const void *)k_exact<G, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
+        return e;
+    if constexpr (G <= 16) {
+        if ((e = hipFuncSetAttribute((const void *)k_raw_estimate_bwd<G, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
+            return e;
+        if ((e = hipFuncSetAttribute((const void *)k_raw_estimate_bwd<G, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
+            return e;
+        if ((e = hipFuncSetAttribute((const void *)k_exact_bwd<G, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
+            return e;
+        if ((e = hipFuncSetAttribute((const void *)k_exact_bwd<G, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
 
-size_t raw_estimate_lds_bytes(const DevPlan &p) {
-    const size_t k = (size_t)p.k;
-    return kHashSlots * (16 + 8 + 8 + 2) + 2 * kThreads * 16 + 64 + k * 8 + ((k + 7) & ~(size_t)7) +
-           k * k * 4;
-}
+size_t raw_estimate_lds_bytes(const DevPlan &p) { return raw_lds_bytes(p.k); }
 
 size_t exact_lds_bytes(const DevPlan &) { return kExactChunk * 16 + 2 * kThreads * 16 + 64; }
+
+size_t raw_estimate_bwd_lds_bytes(const DevPlan &p) {
+    const size_t NG = kThreads / p.G;
+    return raw_estimate_lds_bytes(p) + NG * p.G * p.G * 16 + NG * 2 * p.G * 16;
+}
+
+size_t exact_bwd_lds_bytes(const DevPlan &p) {
+    const size_t NG = kThreads / p.G;
+    return kExactChunk * 16 + 2 * kThreads * 16 + NG * p.G * p.G * 16 + NG * 2 * p.G * 16 + 64;
+}
+
+hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s) {
+    const int grid = (int)std::min<size_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, double2 *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_parts, dim3((stride + 255) / 256), dim3(256), 0, s, part, nparts, stride, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_raw_estimate_bwd(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
+                                   int64_t t, uint64_t seed, const double *g, double2 *part, int nparts,
+                                   const GradLayout &lay, hipStream_t s) {
+    hipError_t e = hipSuccess;
+#define XF_RB(GG) \
+    e = mixed ? launch_raw_bwd_t<GG, true>(p, bits, B, t, seed, g, part, nparts, lay, s) \
+              : launch_raw_bwd_t<GG, false>(p, bits, B, t, seed, g, part, nparts, lay, s)
+    switch (p.G) {
+        case 4: XF_RB(4); break;
+        case 8: XF_RB(8); break;
+        case 16: XF_RB(16); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef XF_RB
+    return e;
+}
+
+hipError_t launch_exact_bwd(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
+                            const double2 *dw, int64_t nkeys, const uint64_t *bits, int64_t B,
+                            const double *g, double2 *part, int nparts, const GradLayout &lay,
+                            hipStream_t s) {
+    hipError_t e = hipSuccess;
+#define XF_EB(GG) \
+    e = mixed ? launch_exact_bwd_t<GG, true>(p, keys, w, dw, nkeys, bits, B, g, part, nparts, lay, s) \
+              : launch_exact_bwd_t<GG, false>(p, keys, w, dw, nkeys, bits, B, g, part, nparts, lay, s)
+    switch (p.G) {
+        case 4: XF_EB(4); break;
+        case 8: XF_EB(8); break;
+        case 16: XF_EB(16); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef XF_EB
+    return e;
+}
 
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);
@@ -631,12 +1087,12 @@ hipError_t prepare_kernels(int G) {
     }
 
 hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
-                               int64_t t, uint64_t seed, double *prob, double *amp,
+                               int64_t t, uint64_t seed, double *prob, double *amp, double *logp,
                                unsigned long long *nterm, hipStream_t s) {
     hipError_t e = hipSuccess;
 #define XF_RAW(GG) \
-    e = mixed ? launch_raw_t<GG, true>(p, bits, B, t, seed, prob, amp, nterm, s) \
-              : launch_raw_t<GG, false>(p, bits, B, t, seed, prob, amp, nterm, s)
+    e = mixed ? launch_raw_t<GG, true>(p, bits, B, t, seed, prob, amp, logp, nterm, s) \
+              : launch_raw_t<GG, false>(p, bits, B, t, seed, prob, amp, logp, nterm, s)
     XF_DISPATCH_G(p.G, XF_RAW)
 #undef XF_RAW
     return e;
@@ -644,11 +1100,11 @@ hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, const uint64_t *bit
 
 hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
                         int64_t nkeys, const uint64_t *bits, int64_t B, double *prob, double *amp,
-                        unsigned long long *nterm, hipStream_t s) {
+                        double *logp, unsigned long long *nterm, hipStream_t s) {
     hipError_t e = hipSuccess;
 #define XF_EX(GG) \
-    e = mixed ? launch_exact_t<GG, true>(p, keys, w, nkeys, bits, B, prob, amp, nterm, s) \
-              : launch_exact_t<GG, false>(p, keys, w, nkeys, bits, B, prob, amp, nterm, s)
+    e = mixed ? launch_exact_t<GG, true>(p, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s) \
+              : launch_exact_t<GG, false>(p, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s)
     XF_DISPATCH_G(p.G, XF_EX)
 #undef XF_EX
     return e;

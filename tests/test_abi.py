@@ -123,6 +123,6 @@ def test_null_arguments(xf):
     h = ctypes.c_void_p()
     from paper_2511_12416_amd import _abi
     assert L.xf_plan_create(None, _abi.Bits128(), 0, 0, ctypes.byref(h)) == 1
-    assert L.xf_probabilities(None, None, 0, 0, 0, 0, None, None, None) == 1
+    assert L.xf_probabilities(None, None, 0, 0, 0, 0, None, None, None, None) == 1
     assert L.xf_extent(None, None) == 1
     assert L.xf_plan_destroy(None) == 0
