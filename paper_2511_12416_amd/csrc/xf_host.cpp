@@ -670,7 +670,8 @@ xf_status xf_log_prob_backward(xf_plan *P, const xf_bits128 *d_bits, int64_t B, 
     lay.stride = lay.oG + 1;
     std::vector<cd> red((size_t)lay.stride, 0.0);
     xf::DevPlan d = snapshot(P);
-    const size_t lds = mode == XF_RAW_ESTIMATE ? xf::raw_estimate_bwd_lds_bytes(d) : xf::exact_bwd_lds_bytes(d);
+    const size_t lds = mode == XF_RAW_ESTIMATE ? xf::raw_estimate_bwd_lds_bytes(d, P->precision == XF_MIXED)
+                                               : xf::exact_bwd_lds_bytes(d);
     if (lds > 159 * 1024) return fail(XF_EUNSUPPORTED, "backward needs %zu bytes of LDS (k too large)", lds);
     DeviceGuard guard(P->device);
     if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");

@@ -81,9 +81,9 @@ hipError_t launch_exact_bwd(const DevPlan &p, bool mixed, const uint64_t *keys, 
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
 hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, double2 *out, hipStream_t s);
 hipError_t prepare_kernels(int G);
-size_t raw_estimate_lds_bytes(const DevPlan &p);
+size_t raw_estimate_lds_bytes(const DevPlan &p, bool mixed);
 size_t exact_lds_bytes(const DevPlan &p);
-size_t raw_estimate_bwd_lds_bytes(const DevPlan &p);
+size_t raw_estimate_bwd_lds_bytes(const DevPlan &p, bool mixed);
 size_t exact_bwd_lds_bytes(const DevPlan &p);
 
 }  // namespace xf

@@ -165,40 +165,98 @@ __device__ __forceinline__ void compose_row(const DevPlan &p, int Ri, const Flip
     }
 }
 
+// Row of M for one CPhase layer from explicit sources (used with the LDS
+// copies of a bitstring's factor rows): prow = P[Ri, :] (G entries, FP64),
+// a1row = A1[Ri, :] (n entries), phi = Phi0 (n x G), in FP64 or, when MIXED,
+// FP32 for the correction.
+template <int G, bool MIXED, typename RT>
+__device__ __forceinline__ void compose_row_l1(const double2 *prow, const RT *a1row, const RT *phi,
+                                               const Flips &f, double2 (&a)[G]) {
+    if constexpr (!MIXED) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) a[j] = prow[j];
+        for_each_mode(f.n0, [&](int c) {
+            const double2 al = a1row[c];
+            const double2 s2 = make_double2(-2.0 * al.x, -2.0 * al.y);
+            const double2 *row = phi + (size_t)c * G;
+#pragma unroll
+            for (int j = 0; j < G; ++j) a[j] = c_fma(a[j], s2, row[j]);
+        });
+    } else {
+        float2 acc[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) acc[j] = make_float2(0.f, 0.f);
+        for_each_mode(f.n0, [&](int c) {
+            const float2 al = a1row[c];
+            const float2 *row = phi + (size_t)c * G;
+#pragma unroll
+            for (int j = 0; j < G; ++j) acc[j] = c_fmaf(acc[j], al, row[j]);
+        });
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const double2 b = prow[j];
+            a[j] = make_double2(b.x - 2.0 * (double)acc[j].x, b.y - 2.0 * (double)acc[j].y);
+        }
+    }
+}
+
+// Cross-lane helpers for a group of G consecutive lanes (G = 4..64, within one
+// wave64).  Within a 16-lane DPP row the exchanges are DPP moves (quad
+// permutes, half-row and row mirrors), across rows they are bpermutes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Maximum of v over the group, returned to every lane of the group.
+template <int G>
+__device__ __forceinline__ double group_max(double v) {
+    v = fmax(v, dpp_f64<0xB1>(v));            // lane ^ 1 (quad_perm 1,0,3,2)
+    v = fmax(v, dpp_f64<0x4E>(v));            // lane ^ 2 (quad_perm 2,3,0,1)
+    if constexpr (G >= 8) v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror: quads 0 <-> 1
+    if constexpr (G >= 16) v = fmax(v, dpp_f64<0x140>(v));  // row_mirror: half-rows
+    if constexpr (G >= 32) v = fmax(v, __shfl_xor(v, 16));
+    if constexpr (G >= 64) v = fmax(v, __shfl_xor(v, 32));
+    return v;
+}
+
+// This lane's group's bits of a wave-wide ballot.
+template <int G>
+__device__ __forceinline__ uint64_t group_bits(bool pred) {
+    const uint64_t all = __ballot(pred);
+    if constexpr (G == 64) return all;
+    const int base = (int)(threadIdx.x & 63) & ~(G - 1);
+    return (all >> base) & ((1ull << G) - 1);
+}
+
 // Determinant of the m x m matrix whose row `lane` (< m) is held by lane
 // `lane` of a group of G consecutive lanes (rows >= m are padding).  Partial
 // pivoting: the pivot of column c is the active row with the largest
-// re^2 + im^2 (lowest lane on ties); rows stay in their lanes and the pivot
-// row is broadcast through `piv` (G entries of LDS private to the group).
-// The permutation sign is tracked by virtual row swaps.  Exactly zero pivot
-// column => det = 0.  Every lane of the group returns the determinant.
+// re^2 + im^2 (lowest lane on ties), found by a DPP max and a ballot; rows
+// stay in their lanes and the pivot row is broadcast through `piv` (G entries
+// of LDS private to the group).  The permutation sign is the parity of the
+// inversions between lane order and pivot order, counted from the ballot of
+// still-active rows.  An exactly zero pivot column gives det = 0.  Every lane
+// of the group returns the determinant.
 template <int G>
 __device__ __forceinline__ double2 lu_det(double2 (&a)[G], int m, int lane, double2 *piv) {
     bool active = lane < m;
     bool live = true;   // false once a zero pivot column was met (group-uniform)
-    int pos = lane;
-    bool neg = false;
+    unsigned inversions = 0;
     double2 det = make_double2(1.0, 0.0);
 #pragma unroll
     for (int c = 0; c < G; ++c) {
         if (c < m && live) {
-            double v = active ? fma(a[c].x, a[c].x, a[c].y * a[c].y) : -1.0;
-            int idx = lane;
-#pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) {
-                const double vo = __shfl_xor(v, off, G);
-                const int io = __shfl_xor(idx, off, G);
-                if (vo > v || (vo == v && io < idx)) {
-                    v = vo;
-                    idx = io;
-                }
-            }
-            if (v > 0.0) {
-                const int ppos = __shfl(pos, idx, G);
-                neg ^= (ppos != c);
-                if (pos == c) pos = ppos;
+            const double v = active ? fma(a[c].x, a[c].x, a[c].y * a[c].y) : -1.0;
+            const double vmax = group_max<G>(v);
+            const uint64_t act = group_bits<G>(active);
+            const uint64_t hit = group_bits<G>(active && v == vmax);
+            if (vmax > 0.0 && hit != 0) {
+                const int idx = __ffsll((long long)hit) - 1;
+                inversions += __popcll(act & ((1ull << idx) - 1));
                 if (lane == idx) {
-                    pos = c;
                     active = false;
 #pragma unroll
                     for (int j = c; j < G; ++j) piv[j] = a[j];
@@ -221,10 +279,61 @@ __device__ __forceinline__ double2 lu_det(double2 (&a)[G], int m, int lane, doub
         }
     }
     if (!live) return make_double2(0.0, 0.0);
-    return neg ? make_double2(-det.x, -det.y) : det;
+    return (inversions & 1) ? make_double2(-det.x, -det.y) : det;
 }
 
-// det of the trajectory submatrix for `key`, evaluated by a group of G lanes.
+struct RawSmem {
+    uint64_t *hkey;
+    int2 *hcnt;
+    double2 *piv;
+    double2 *red;
+    uint16_t *list;
+    uint8_t *Rb;
+    uint64_t *gkey;
+    uint8_t *gneg;
+    uint32_t *T;
+    // LDS copies for one-layer circuits (STAGE): P rows of the bitstring
+    // (G x G FP64), its A1 rows (G x n) and Phi0 (n x G), FP64 or FP32 (MIXED)
+    double2 *sP;
+    void *sA1;
+    void *sPhi;
+};
+
+__host__ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// Bytes of the staged copies (0 when not staged).
+__host__ __device__ __forceinline__ size_t stage_bytes(int n, int G, bool mixed) {
+    const size_t el = mixed ? 8 : 16;
+    return (size_t)G * G * 16 + 2 * (size_t)n * G * el;
+}
+
+// Bytes of dynamic LDS the per-bitstring kernels carve (see carve_raw).
+__host__ __device__ __forceinline__ size_t raw_lds_bytes(int kk, int n, int G, bool mixed, bool stage) {
+    const size_t k = (size_t)kk;
+    const size_t base = align16((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + k * 8 +
+                                ((k + 7) & ~(size_t)7) + k * k * 4);
+    return base + (stage ? stage_bytes(n, G, mixed) : 0);
+}
+
+__device__ __forceinline__ RawSmem carve_raw(unsigned char *smem, int k, int n, int G, bool mixed) {
+    RawSmem s;
+    s.hkey = (uint64_t *)smem;
+    s.hcnt = (int2 *)(s.hkey + kHashSlots);
+    s.piv = (double2 *)(s.hcnt + kHashSlots);
+    s.red = s.piv + kThreads;
+    s.list = (uint16_t *)(s.red + kThreads);
+    s.Rb = (uint8_t *)(s.list + kHashSlots);
+    s.gkey = (uint64_t *)(s.Rb + 64);
+    s.gneg = (uint8_t *)(s.gkey + k);
+    s.T = (uint32_t *)(s.gneg + ((k + 7) & ~7));
+    unsigned char *st = smem + align16((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 +
+                                       (size_t)k * 8 + (((size_t)k + 7) & ~(size_t)7) + (size_t)k * k * 4);
+    s.sP = (double2 *)st;
+    s.sA1 = (void *)(st + (size_t)G * G * 16);
+    s.sPhi = (void *)(st + (size_t)G * G * 16 + (size_t)n * G * (mixed ? 8 : 16));
+    return s;
+}
+
 // *rank receives the number of flipped modes (the rank of the correction).
 template <int G, bool MIXED>
 __device__ __forceinline__ double2 term_det(const DevPlan &p, uint64_t key, const uint8_t *Rb,
@@ -239,6 +348,47 @@ __device__ __forceinline__ double2 term_det(const DevPlan &p, uint64_t key, cons
         for (int j = 0; j < G; ++j) a[j] = make_double2(j == lane ? 1.0 : 0.0, 0.0);
     }
     return lu_det<G>(a, p.m, lane, piv);
+}
+
+// Same from the LDS copies of the bitstring's factor rows (one CPhase layer).
+template <int G, bool MIXED>
+__device__ __forceinline__ double2 term_det_staged(const DevPlan &p, uint64_t key, const RawSmem &s,
+                                                   int lane, double2 *piv, int *rank) {
+    using RT = typename std::conditional<MIXED, float2, double2>::type;
+    double2 a[G];
+    const Flips f = decode_key(p, key);
+    *rank = __popcll(f.n0[0]) + __popcll(f.n0[1]);
+    if (lane < p.m) {
+        compose_row_l1<G, MIXED>(s.sP + (size_t)lane * G, (const RT *)s.sA1 + (size_t)lane * p.n,
+                                 (const RT *)s.sPhi, f, a);
+    } else {
+#pragma unroll
+        for (int j = 0; j < G; ++j) a[j] = make_double2(j == lane ? 1.0 : 0.0, 0.0);
+    }
+    return lu_det<G>(a, p.m, lane, piv);
+}
+
+// Copies Phi0 (once per kernel) into LDS.
+template <bool MIXED>
+__device__ __forceinline__ void stage_phi(const DevPlan &p, const RawSmem &s) {
+    const int cnt = p.n * p.G;
+    for (int i = threadIdx.x; i < cnt; i += kThreads) {
+        if constexpr (MIXED) ((float2 *)s.sPhi)[i] = p.fPhi0[i];
+        else ((double2 *)s.sPhi)[i] = p.Phi0[i];
+    }
+}
+
+// Copies bitstring b's rows of P and A1 into LDS (after load_bitstring).
+template <bool MIXED>
+__device__ __forceinline__ void stage_rows(const DevPlan &p, const RawSmem &s) {
+    const int G = p.G, n = p.n, m = p.m;
+    for (int i = threadIdx.x; i < m * G; i += kThreads) s.sP[i] = p.P[(size_t)s.Rb[i / G] * G + (i % G)];
+    for (int i = threadIdx.x; i < m * n; i += kThreads) {
+        const size_t src = (size_t)s.Rb[i / n] * n + (i % n);
+        if constexpr (MIXED) ((float2 *)s.sA1)[i] = p.fA1[src];
+        else ((double2 *)s.sA1)[i] = p.A1[src];
+    }
+    __syncthreads();
 }
 
 // Loads bitstring b; returns false (and writes p = 0) if its weight is not
@@ -290,40 +440,32 @@ __device__ __forceinline__ double2 ordered_sum(const double2 *out, int cnt, doub
     return r;
 }
 
-// Bytes of dynamic LDS the per-bitstring sampler carves (see carve_raw).
-__host__ __device__ __forceinline__ size_t raw_lds_bytes(int kk) {
-    const size_t k = (size_t)kk;
-    const size_t raw = (size_t)kHashSlots * (16 + 8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + k * 8 +
-                       ((k + 7) & ~(size_t)7) + k * k * 4;
-    return (raw + 15) & ~(size_t)15;
-}
-
-struct RawSmem {
-    double2 *out;
-    uint64_t *hkey;
-    int2 *hcnt;
-    double2 *piv;
-    double2 *red;
-    uint16_t *list;
-    uint8_t *Rb;
-    uint64_t *gkey;
-    uint8_t *gneg;
-    uint32_t *T;
-};
-
-__device__ __forceinline__ RawSmem carve_raw(unsigned char *smem, int k) {
-    RawSmem s;
-    s.out = (double2 *)smem;
-    s.hkey = (uint64_t *)(s.out + kHashSlots);
-    s.hcnt = (int2 *)(s.hkey + kHashSlots);
-    s.piv = (double2 *)(s.hcnt + kHashSlots);
-    s.red = s.piv + kThreads;
-    s.list = (uint16_t *)(s.red + kThreads);
-    s.Rb = (uint8_t *)(s.list + kHashSlots);
-    s.gkey = (uint64_t *)(s.Rb + 64);
-    s.gneg = (uint8_t *)(s.gkey + k);
-    s.T = (uint32_t *)(s.gneg + ((k + 7) & ~7));
-    return s;
+// Fixed-order sum over the sorted entries e < nl of the values evaluate()
+// left in their slots (re in hkey, im in hcnt).  Result valid in every thread.
+__device__ __forceinline__ double2 ordered_sum_slots(const RawSmem &s, int nl) {
+    const int tid = threadIdx.x;
+    const int chunk = (nl + kThreads - 1) / kThreads;
+    double2 acc = make_double2(0.0, 0.0);
+    const int lo = tid * chunk, hi = min(nl, lo + chunk);
+    for (int e = lo; e < hi; ++e) {
+        const uint16_t slot = s.list[e];
+        if (slot >= kHashSlots) continue;
+        acc.x += __longlong_as_double((long long)s.hkey[slot]);
+        acc.y += *(const double *)&s.hcnt[slot];
+    }
+    s.red[tid] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            s.red[tid].x += s.red[tid + w].x;
+            s.red[tid].y += s.red[tid + w].y;
+        }
+        __syncthreads();
+    }
+    const double2 r = s.red[0];
+    __syncthreads();
+    return r;
 }
 
 __device__ __forceinline__ uint64_t list_key(const RawSmem &s, uint16_t idx) {
@@ -458,9 +600,12 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
     return true;
 }
 
-// Forward visitor: sum over the sorted entries of count * det, in a fixed order.
-template <int G, bool MIXED>
-__device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &s, int nl, unsigned long long *nterm) {
+// Sum over the sorted entries of count * det, in a fixed order.  Each group
+// evaluates entries e = grp, grp + NG, ...; the product is left in the
+// entry's slot and summed in sorted order by ordered_sum_slots.
+template <int G, bool MIXED, bool STAGE>
+__device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &s, int nl,
+                                               unsigned long long *nterm) {
     const int tid = threadIdx.x;
     const int lane = tid % G, grp = tid / G;
     constexpr int NG = kThreads / G;
@@ -468,17 +613,20 @@ __device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &
     for (int e = grp; e < nl; e += NG) {
         const uint16_t slot = s.list[e];
         if (slot >= kHashSlots) continue;   // unreachable: the list holds slot indices
+        const uint64_t key = s.hkey[slot];
+        const int2 c = s.hcnt[slot];
         int rank;
-        const double2 d = term_det<G, MIXED>(p, s.hkey[slot], s.Rb, lane, s.piv + grp * G, &rank);
+        double2 d;
+        if constexpr (STAGE) d = term_det_staged<G, MIXED>(p, key, s, lane, s.piv + grp * G, &rank);
+        else d = term_det<G, MIXED>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
         if (lane == 0) {
-            const int2 c = s.hcnt[slot];
-            s.out[e] = make_double2((double)c.x * d.x - (double)c.y * d.y,
-                                    (double)c.x * d.y + (double)c.y * d.x);
+            s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+            *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
             rank_sum += (unsigned)rank;
         }
     }
     __syncthreads();
-    const double2 sum = ordered_sum(s.out, nl, s.red);
+    const double2 sum = ordered_sum_slots(s, nl);
     if (nterm) {
         if (tid == 0) atomicAdd(nterm, (unsigned long long)nl);
         if (lane == 0 && rank_sum) atomicAdd(nterm + 1, (unsigned long long)rank_sum);
@@ -496,16 +644,17 @@ __device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) 
     }
 }
 
-template <int G, bool MIXED>
+template <int G, bool MIXED, bool STAGE>
 __global__ void __launch_bounds__(kThreads)
 k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
                double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
                unsigned long long *nterm) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok, s_n, s_claimed;
-    const RawSmem s = carve_raw(smem, p.k);
+    const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
     const int tid = threadIdx.x;
     load_tables(p, s);
+    if constexpr (STAGE) stage_phi<MIXED>(p, s);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t slot0 = hash_slot(0);
 
@@ -519,13 +668,14 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
             __syncthreads();
             continue;
         }
+        if constexpr (STAGE) stage_rows<MIXED>(p, s);
         double2 total = make_double2(0.0, 0.0);
         clear_table(s, &s_claimed, slot0);
         uint32_t base = 0;
         while (true) {
             const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
             const int nl = prepare_list(s, &s_n);
-            const double2 part = sum_entries<G, MIXED>(p, s, nl, nterm);
+            const double2 part = sum_entries<G, MIXED, STAGE>(p, s, nl, nterm);
             total.x += part.x;
             total.y += part.y;
             if (done) break;
@@ -789,9 +939,9 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
                    const double *__restrict__ g, double2 *part, GradLayout lay) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok, s_n, s_claimed;
-    const RawSmem s = carve_raw(smem, p.k);
+    const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
     constexpr int NG = kThreads / G;
-    double2 *tiles = (double2 *)(smem + raw_lds_bytes(p.k));
+    double2 *tiles = (double2 *)(smem + raw_lds_bytes(p.k, p.n, G, MIXED, false));
     double2 *pvs = tiles + NG * G * G;
     const int tid = threadIdx.x;
     const int lane = tid % G, grp = tid / G;
@@ -810,7 +960,7 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
         while (true) {
             const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
             const int nl = prepare_list(s, &s_n);
-            const double2 part_sum = sum_entries<G, MIXED>(p, s, nl, nullptr);
+            const double2 part_sum = sum_entries<G, MIXED, false>(p, s, nl, nullptr);
             total.x += part_sum.x;
             total.y += part_sum.y;
             if (done) break;
@@ -923,13 +1073,28 @@ __global__ void k_zero_u64(unsigned long long *p) {
 }
 
 constexpr int kMaxGrid = 1 << 20;
+constexpr size_t kMaxLds = 159 * 1024;
+
+// LDS copies of the factor rows pay off for one CPhase layer and small eta,
+// when they fit beside the table.
+__host__ __forceinline__ bool use_stage(const DevPlan &p, bool mixed) {
+    return p.L == 1 && p.G <= 16 && raw_lds_bytes(p.k, p.n, p.G, mixed, true) <= kMaxLds;
+}
 
 template <int G, bool MIXED>
 hipError_t launch_raw_t(const DevPlan &p, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
                         double *prob, double *amp, double *logp, unsigned long long *nterm, hipStream_t s) {
-    const size_t lds = raw_estimate_lds_bytes(p);
     const int grid = (int)(B < kMaxGrid ? B : kMaxGrid);
-    hipLaunchKernelGGL((k_raw_estimate<G, MIXED>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
+    if constexpr (G <= 16) {
+        if (use_stage(p, MIXED)) {
+            const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, true);
+            hipLaunchKernelGGL((k_raw_estimate<G, MIXED, true>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
+                               (uint32_t)t, seed, prob, amp, logp, nterm);
+            return hipGetLastError();
+        }
+    }
+    const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, false);
+    hipLaunchKernelGGL((k_raw_estimate<G, MIXED, false>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
                        (uint32_t)t, seed, prob, amp, logp, nterm);
     return hipGetLastError();
 }
@@ -949,7 +1114,7 @@ template <int G, bool MIXED>
 hipError_t launch_raw_bwd_t(const DevPlan &p, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
                             const double *g, double2 *part, int nparts, const GradLayout &lay,
                             hipStream_t s) {
-    const size_t lds = raw_estimate_bwd_lds_bytes(p);
+    const size_t lds = raw_estimate_bwd_lds_bytes(p, MIXED);
     hipLaunchKernelGGL((k_raw_estimate_bwd<G, MIXED>), dim3(nparts), dim3(kThreads), lds, s, p, bits, B,
                        (uint32_t)t, seed, g, part, lay);
     return hipGetLastError();
@@ -967,14 +1132,22 @@ hipError_t launch_exact_bwd_t(const DevPlan &p, const uint64_t *keys, const doub
 
 template <int G>
 hipError_t set_lds_limits() {
-    const int big = 160 * 1024 - 1024;
+    const int big = (int)kMaxLds;
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, false>,
+    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, false, false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
         return e;
-    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, true>,
+    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, true, false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
         return e;
+    if constexpr (G <= 16) {
+        if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, false, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
+            return e;
+        if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, true, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
+            return e;
+    }
     if ((e = hipFuncSetAttribute((const void *)k_exact<G, false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
         return e;
@@ -1000,13 +1173,15 @@ hipError_t set_lds_limits() {
 
 }  // namespace
 
-size_t raw_estimate_lds_bytes(const DevPlan &p) { return raw_lds_bytes(p.k); }
+size_t raw_estimate_lds_bytes(const DevPlan &p, bool mixed) {
+    return raw_lds_bytes(p.k, p.n, p.G, mixed, p.G <= 16 && use_stage(p, mixed));
+}
 
 size_t exact_lds_bytes(const DevPlan &) { return kExactChunk * 16 + 2 * kThreads * 16 + 64; }
 
-size_t raw_estimate_bwd_lds_bytes(const DevPlan &p) {
+size_t raw_estimate_bwd_lds_bytes(const DevPlan &p, bool mixed) {
     const size_t NG = kThreads / p.G;
-    return raw_estimate_lds_bytes(p) + NG * p.G * p.G * 16 + NG * 2 * p.G * 16;
+    return raw_lds_bytes(p.k, p.n, p.G, mixed, false) + NG * p.G * p.G * 16 + NG * 2 * p.G * 16;
 }
 
 size_t exact_bwd_lds_bytes(const DevPlan &p) {
