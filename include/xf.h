@@ -69,9 +69,10 @@ typedef enum {
 typedef enum { XF_EXACT = 0, XF_RAW_ESTIMATE = 1 } xf_mode;
 
 /* XF_FP64: every step in FP64.
- * XF_MIXED: the low-rank correction of each trajectory's submatrix is formed
- * in FP32; the base submatrix, the elimination, the pivot product and the
- * cross-term accumulation stay FP64. */
+ * XF_MIXED: where a trajectory's submatrix is factorised directly (exact mode,
+ * and Raw Estimate under XF_EVAL_LU or where the lemma does not apply), its
+ * low-rank correction is formed in FP32; the base submatrix, the elimination,
+ * the pivot product and the cross-term accumulation stay FP64. */
 typedef enum { XF_FP64 = 0, XF_MIXED = 1 } xf_precision;
 
 /* 128-bit occupation / bitstring: bit p of (w[0] | w[1] << 64) <=> mode p occupied
@@ -155,11 +156,43 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
                                int64_t t, uint64_t seed, const double *d_grad_logp,
                                double *h_grad_rot, double *h_grad_theta, void *hip_stream);
 
+/* How Raw Estimate evaluates the determinant of each distinct flip pattern N
+ * of a bitstring (exact mode and backward always use XF_EVAL_LU).
+ *   XF_EVAL_LU: LU factorisation of the m x m submatrix
+ *     M_N = M_0 - 2 A[R, N] Phi[N, :] (Sec. IV-B Eq. 16-19; m = eta).
+ *   XF_EVAL_AUTO (default): for circuits with one CPhase layer (n_rot = 2),
+ *     the matrix determinant lemma det M_N = det M_0 det(I_r - 2 H[N, N]) with
+ *     H = Phi[act, :] M_0^-1 A[R, act] formed once per bitstring, so that each
+ *     pattern with r = |N| <= 6 costs an r x r determinant.  A bitstring whose
+ *     base M_0 is singular or has 1-norm condition number above 1e4, and any
+ *     pattern with r > 6, is evaluated with the LU instead.  The lemma runs
+ *     in FP64 under both precisions (XF_MIXED then gives FP64 results).
+ *     Other circuits, eta > 16, and sizes whose tables do not fit in LDS use
+ *     the LU. */
+typedef enum { XF_EVAL_AUTO = 0, XF_EVAL_LU = 1 } xf_evaluation;
+xf_status xf_plan_set_evaluation(xf_plan *plan, xf_evaluation evaluation);
+
 /* Work done by the last xf_probabilities call on this plan (synchronises the
  * device): *count = distinct (bitstring, flip-pattern) determinants
  * evaluated; *rank_sum (nullable) = the sum over them of the number of
  * flipped modes, i.e. of the ranks of the low-rank corrections composed. */
 xf_status xf_plan_last_term_count(xf_plan *plan, int64_t *count, int64_t *rank_sum);
+
+/* Same counters plus the arithmetic executed for them (synchronises the
+ * device).  flops counts real FP64-equivalent operations of the
+ * determinant evaluations actually performed: (4/3)(m-1)m(2m-1) + 3m(m-1)
+ * per m x m LU plus 8 m^2 per rank of each composed correction, or, for a
+ * pattern taken by the determinant lemma, the same LU count at size r plus 6,
+ * plus the lemma's per-bitstring setup (Gauss-Jordan inverse of M_0 and the
+ * products forming H, 8 per complex multiply-add).  The sampling is not
+ * counted.  lemma = 1 if the call used the determinant lemma. */
+typedef struct {
+    int64_t determinants;
+    int64_t rank_sum;
+    double flops;
+    int32_t lemma;
+} xf_work;
+xf_status xf_plan_last_work(xf_plan *plan, xf_work *work);
 
 /* Host FP64 helpers for rotations parametrised by anti-Hermitian generators
  * (U = exp(K)), n <= 128:

@@ -25,6 +25,11 @@ class Bits128(ctypes.Structure):
     _fields_ = [("w", ctypes.c_uint64 * 2)]
 
 
+class Work(ctypes.Structure):
+    _fields_ = [("determinants", ctypes.c_int64), ("rank_sum", ctypes.c_int64), ("flops", ctypes.c_double),
+                ("lemma", ctypes.c_int32)]
+
+
 class Circuit(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_rot", ctypes.c_int32), ("rot", ctypes.c_void_p),
                 ("k", ctypes.c_int32), ("pairs", ctypes.c_void_p), ("layer", ctypes.c_void_p),
@@ -33,7 +38,8 @@ class Circuit(ctypes.Structure):
 
 EXPORTS = ["xf_plan_create", "xf_plan_set_params", "xf_plan_refreeze", "xf_plan_destroy",
            "xf_extent", "xf_trajectory_bound", "xf_probabilities", "xf_log_prob_backward",
-           "xf_plan_last_term_count", "xf_expm_antihermitian", "xf_expm_adjoint", "xf_last_error"]
+           "xf_plan_last_term_count", "xf_plan_last_work", "xf_plan_set_evaluation",
+           "xf_expm_antihermitian", "xf_expm_adjoint", "xf_last_error"]
 
 _lib = None
 
@@ -63,6 +69,8 @@ def lib() -> ctypes.CDLL:
     L.xf_probabilities.argtypes = [P, P, I64, S, I64, U64, P, P, P, P]
     L.xf_log_prob_backward.argtypes = [P, P, I64, S, I64, U64, P, P, P, P]
     L.xf_plan_last_term_count.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    L.xf_plan_last_work.argtypes = [P, ctypes.POINTER(Work)]
+    L.xf_plan_set_evaluation.argtypes = [P, S]
     L.xf_expm_antihermitian.argtypes = [I32, P, P]
     L.xf_expm_adjoint.argtypes = [I32, P, P, P]
     L.xf_last_error.argtypes = []

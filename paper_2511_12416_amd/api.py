@@ -18,6 +18,7 @@ from ._abi import check, lib
 
 _MODES = {"exact": _abi.XF_EXACT, "approx": _abi.XF_RAW_ESTIMATE, "raw_estimate": _abi.XF_RAW_ESTIMATE}
 _PREC = {"fp64": _abi.XF_FP64, "mixed": _abi.XF_MIXED}
+_EVAL = {"auto": 0, "lu": 1}
 
 
 def _f64(a) -> np.ndarray:
@@ -112,6 +113,22 @@ class Plan:
         c, r = ctypes.c_int64(), ctypes.c_int64()
         check(lib().xf_plan_last_term_count(self._h, ctypes.byref(c), ctypes.byref(r)))
         return (c.value, r.value) if with_rank else c.value
+
+    def last_work(self) -> dict:
+        """Work of the last probabilities() call: determinants, summed rank of
+        their corrections, FP64-equivalent FLOPs executed, and whether the
+        determinant lemma was used."""
+        w = _abi.Work()
+        check(lib().xf_plan_last_work(self._h, ctypes.byref(w)))
+        return {"determinants": w.determinants, "rank_sum": w.rank_sum, "flops": w.flops,
+                "lemma": bool(w.lemma)}
+
+    def set_evaluation(self, evaluation: str) -> None:
+        """"auto" (determinant lemma where it applies) or "lu" (LU of every
+        distinct submatrix) for Raw Estimate."""
+        if evaluation not in _EVAL:
+            raise ValueError(f"evaluation must be one of {sorted(_EVAL)}")
+        check(lib().xf_plan_set_evaluation(self._h, _EVAL[evaluation]))
 
     # -- the hot path ---------------------------------------------------------
     def probabilities(self, bits: torch.Tensor, mode: str = "exact", t: int = 0, seed: int = 0,

@@ -155,6 +155,8 @@ struct xf_plan {
     DevBuf dkeymode, dT, dgkey, dgmode, dglayer, dgneg, dnterm;
     DevBuf dxkeys, dxw, dxdw;         // exact-mode term list (+ angle derivatives of the weights)
     int64_t nxterms = -1;             // -1: not built for the current parameters
+    xf_evaluation evaluation = XF_EVAL_AUTO;
+    int last_lemma = 0;               // the last xf_probabilities call used the determinant lemma
     bool xterms_have_dw = false;
     // host copies of the factors, for the backward chain rule
     std::vector<std::vector<cd>> Rp;  // R'_l = R_l D0_{l-1} (R'_0 = R_0), n x n each
@@ -521,13 +523,13 @@ xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision pre
         (st = dev_upload(P->dgkey, P->gkey.data(), P->gkey.size() * 8)) ||
         (st = dev_upload(P->dgmode, P->gmode.data(), P->gmode.size() * 8)) ||
         (st = dev_upload(P->dglayer, glayer.data(), glayer.size() * 4)) ||
-        (st = set_gate_tables(P)) || (st = dev_upload(P->dnterm, nullptr, 16)) ||
+        (st = set_gate_tables(P)) || (st = dev_upload(P->dnterm, nullptr, 32)) ||
         (st = refresh_matrices(P)) || (st = refresh_table(P))) {
         plan_free(P);
         delete P;
         return st;
     }
-    if (hipMemset(P->dnterm.p, 0, 16) != hipSuccess) {
+    if (hipMemset(P->dnterm.p, 0, 32) != hipSuccess) {
         plan_free(P);
         delete P;
         return fail(XF_EDEVICE, "hipMemset failed");
@@ -604,24 +606,28 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
     } else if (P->k > 24) {
         return fail(XF_EUNSUPPORTED, "exact mode needs k <= 24 (k = %d)", P->k);
     }
-    if (B == 0) return ok();
-    if (!d_bits || !d_prob) return fail(XF_EINVAL, "d_bits or d_prob is NULL");
+    if (B > 0 && (!d_bits || !d_prob)) return fail(XF_EINVAL, "d_bits or d_prob is NULL");
     DeviceGuard guard(P->device);
     if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
     hipStream_t s = (hipStream_t)hip_stream;
+    if (xf::launch_zero_u64((unsigned long long *)P->dnterm.p, s) != hipSuccess)
+        return fail(XF_EDEVICE, "launch failed: %s", hipGetErrorString(hipGetLastError()));
+    P->last_lemma = 0;
+    if (B == 0) return ok();
     xf_status st;
     if (mode == XF_EXACT && P->nxterms < 0) {
         if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
         if ((st = build_exact_terms(P, false))) return st;
     }
     xf::DevPlan d = snapshot(P);
-    if (xf::launch_zero_u64((unsigned long long *)P->dnterm.p, s) != hipSuccess)
-        return fail(XF_EDEVICE, "launch failed: %s", hipGetErrorString(hipGetLastError()));
     hipError_t e;
     if (mode == XF_RAW_ESTIMATE) {
         d.scale = std::sqrt(extent_of(P->theta)) / (double)t;
-        e = xf::launch_raw_estimate(d, P->precision == XF_MIXED, (const uint64_t *)d_bits, B, t, seed, d_prob,
-                                    d_amp, d_logp, (unsigned long long *)P->dnterm.p, s);
+        const bool mixed = P->precision == XF_MIXED;
+        const int alg = P->evaluation == XF_EVAL_LU ? 1 : 0;
+        e = xf::launch_raw_estimate(d, mixed, alg, (const uint64_t *)d_bits, B, t, seed, d_prob, d_amp, d_logp,
+                                    (unsigned long long *)P->dnterm.p, s);
+        P->last_lemma = xf::raw_estimate_uses_lemma(d, alg) ? 1 : 0;
     } else {
         e = xf::launch_exact(d, P->precision == XF_MIXED, (const uint64_t *)P->dxkeys.p,
                              (const double2 *)P->dxw.p, P->nxterms, (const uint64_t *)d_bits, B, d_prob,
@@ -632,14 +638,34 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
 }
 
 xf_status xf_plan_last_term_count(xf_plan *P, int64_t *count, int64_t *rank_sum) {
-    if (!plan_valid(P) || !count) return fail(XF_EINVAL, "invalid plan or NULL output");
+    if (!count) return fail(XF_EINVAL, "NULL output");
+    xf_work w;
+    const xf_status st = xf_plan_last_work(P, &w);
+    if (st) return st;
+    *count = w.determinants;
+    if (rank_sum) *rank_sum = w.rank_sum;
+    return ok();
+}
+
+xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
+    if (!plan_valid(P) || !work) return fail(XF_EINVAL, "invalid plan or NULL output");
     DeviceGuard guard(P->device);
-    unsigned long long v[2] = {0, 0};
+    if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
+    unsigned long long v[3] = {0, 0, 0};
     if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(v, P->dnterm.p, 16, hipMemcpyDeviceToHost) != hipSuccess)
-        return fail(XF_EDEVICE, "could not read the term counter");
-    *count = (int64_t)v[0];
-    if (rank_sum) *rank_sum = (int64_t)v[1];
+        hipMemcpy(v, P->dnterm.p, 24, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(XF_EDEVICE, "could not read the work counters");
+    work->determinants = (int64_t)v[0];
+    work->rank_sum = (int64_t)v[1];
+    work->flops = (double)v[2];
+    work->lemma = P->last_lemma;
+    return ok();
+}
+
+xf_status xf_plan_set_evaluation(xf_plan *P, xf_evaluation evaluation) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    if (evaluation != XF_EVAL_AUTO && evaluation != XF_EVAL_LU) return fail(XF_EINVAL, "unknown evaluation");
+    P->evaluation = evaluation;
     return ok();
 }
 

@@ -65,9 +65,12 @@ struct GradLayout {
 
 // Launchers (xf_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
-hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
+// algorithm: 0 = automatic (determinant lemma where it applies), 1 = LU per
+// distinct term, 2 = determinant lemma where it applies.
+hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, int algorithm, const uint64_t *bits, int64_t B,
                                int64_t t, uint64_t seed, double *prob, double *amp, double *logp,
                                unsigned long long *nterm, hipStream_t s);
+bool raw_estimate_uses_lemma(const DevPlan &p, int algorithm);
 hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
                         int64_t nkeys, const uint64_t *bits, int64_t B, double *prob, double *amp,
                         double *logp, unsigned long long *nterm, hipStream_t s);

@@ -600,167 +600,34 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
     return true;
 }
 
-// Sum over the sorted entries of count * det, in a fixed order.  Each group
-// evaluates entries e = grp, grp + NG, ...; the product is left in the
-// entry's slot and summed in sorted order by ordered_sum_slots.
-template <int G, bool MIXED, bool STAGE>
-__device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &s, int nl,
-                                               unsigned long long *nterm) {
-    const int tid = threadIdx.x;
-    const int lane = tid % G, grp = tid / G;
-    constexpr int NG = kThreads / G;
-    unsigned rank_sum = 0;
-    for (int e = grp; e < nl; e += NG) {
-        const uint16_t slot = s.list[e];
-        if (slot >= kHashSlots) continue;   // unreachable: the list holds slot indices
-        const uint64_t key = s.hkey[slot];
-        const int2 c = s.hcnt[slot];
-        int rank;
-        double2 d;
-        if constexpr (STAGE) d = term_det_staged<G, MIXED>(p, key, s, lane, s.piv + grp * G, &rank);
-        else d = term_det<G, MIXED>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
-        if (lane == 0) {
-            s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
-            *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
-            rank_sum += (unsigned)rank;
-        }
-    }
-    __syncthreads();
-    const double2 sum = ordered_sum_slots(s, nl);
-    if (nterm) {
-        if (tid == 0) atomicAdd(nterm, (unsigned long long)nl);
-        if (lane == 0 && rank_sum) atomicAdd(nterm + 1, (unsigned long long)rank_sum);
-    }
-    return sum;
+// Work done by one thread, kept in registers and added to the plan's device
+// counters once at the end of a kernel: [0] distinct determinants, [1] sum of
+// their correction ranks, [2] FP64-equivalent FLOPs of the evaluation.
+struct Work {
+    unsigned long long terms = 0, rank = 0, flops = 0;
+};
+
+// Real FLOPs of the partial-pivot LU determinant of a complex m x m matrix.
+__device__ __forceinline__ unsigned long long lu_flops(int m) {
+    return (unsigned long long)((4 * (m - 1) * m * (2 * m - 1)) / 3 + 3 * m * (m - 1));
 }
 
-__device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) {
-    const int tid = threadIdx.x;
-    const int k = p.k;
-    for (int i = tid; i < k * k; i += kThreads) s.T[i] = p.T[i];
-    for (int i = tid; i < k; i += kThreads) {
-        s.gkey[i] = p.gkey[i];
-        s.gneg[i] = p.gneg[i];
-    }
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
-template <int G, bool MIXED, bool STAGE>
-__global__ void __launch_bounds__(kThreads)
-k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
-               double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
-               unsigned long long *nterm) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n, s_claimed;
-    const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
-    const int tid = threadIdx.x;
-    load_tables(p, s);
-    if constexpr (STAGE) stage_phi<MIXED>(p, s);
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    const uint32_t slot0 = hash_slot(0);
-
-    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
-        if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) {
-            if (tid == 0) {
-                prob[b] = 0.0;
-                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
-                if (logp) logp[b] = -INFINITY;
-            }
-            __syncthreads();
-            continue;
-        }
-        if constexpr (STAGE) stage_rows<MIXED>(p, s);
-        double2 total = make_double2(0.0, 0.0);
-        clear_table(s, &s_claimed, slot0);
-        uint32_t base = 0;
-        while (true) {
-            const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
-            const int nl = prepare_list(s, &s_n);
-            const double2 part = sum_entries<G, MIXED, STAGE>(p, s, nl, nterm);
-            total.x += part.x;
-            total.y += part.y;
-            if (done) break;
-            clear_table(s, &s_claimed, slot0);
-        }
-        if (tid == 0) {
-            const double ax = total.x * p.scale, ay = total.y * p.scale;
-            const double pb = ax * ax + ay * ay;
-            prob[b] = pb;
-            if (amp) { amp[2 * b] = ax; amp[2 * b + 1] = ay; }
-            if (logp) logp[b] = log(pb);
-        }
-        __syncthreads();
+// Every thread of the workgroup calls this.
+__device__ __forceinline__ void flush_work(const Work &w, unsigned long long *nterm) {
+    if (!nterm) return;
+    const unsigned long long a = wave_sum(w.terms), b = wave_sum(w.rank), c = wave_sum(w.flops);
+    if ((threadIdx.x & 63) == 0) {
+        if (a) atomicAdd(nterm, a);
+        if (b) atomicAdd(nterm + 1, b);
+        if (c) atomicAdd(nterm + 2, c);
     }
 }
-
-template <int G, bool MIXED>
-__global__ void __launch_bounds__(kThreads)
-k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict__ w, int64_t nkeys,
-        const uint64_t *__restrict__ bits, int64_t B, double *__restrict__ prob,
-        double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok;
-    double2 *out = (double2 *)smem;
-    double2 *piv = out + kExactChunk;
-    double2 *red = piv + kThreads;
-    uint8_t *Rb = (uint8_t *)(red + kThreads);
-    const int tid = threadIdx.x;
-    const int lane = tid % G, grp = tid / G;
-    constexpr int NG = kThreads / G;
-    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
-        if (!load_bitstring(p, bits, b, Rb, &s_ok)) {
-            if (tid == 0) {
-                prob[b] = 0.0;
-                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
-                if (logp) logp[b] = -INFINITY;
-            }
-            __syncthreads();
-            continue;
-        }
-        double2 total = make_double2(0.0, 0.0);
-        unsigned rank_sum = 0;
-        for (int64_t c0 = 0; c0 < nkeys; c0 += kExactChunk) {
-            const int ncur = (int)min((int64_t)kExactChunk, nkeys - c0);
-            for (int e = grp; e < ncur; e += NG) {
-                int rank;
-                const double2 d = term_det<G, MIXED>(p, keys[c0 + e], Rb, lane, piv + grp * G, &rank);
-                if (lane == 0) {
-                    out[e] = c_mul(w[c0 + e], d);
-                    rank_sum += (unsigned)rank;
-                }
-            }
-            __syncthreads();
-            const double2 part = ordered_sum(out, ncur, red);
-            total.x += part.x;
-            total.y += part.y;
-        }
-        if (tid == 0) {
-            const double pb = total.x * total.x + total.y * total.y;
-            prob[b] = pb;
-            if (amp) { amp[2 * b] = total.x; amp[2 * b + 1] = total.y; }
-            if (logp) logp[b] = log(pb);
-            if (nterm) atomicAdd(nterm, (unsigned long long)nkeys);
-        }
-        if (nterm && lane == 0 && rank_sum) atomicAdd(nterm + 1, (unsigned long long)rank_sum);
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Adjoint (gradient of L = sum_b g_b log p_b)
-//
-// d log p_b = 2 Re(dA_b / A_b) and d det M = det M tr(M^-1 dM) (Jacobi), so
-// every distinct entry e of bitstring b contributes the holomorphic adjoint
-// Gbar_M = beta_e M_e^-T, beta_e = (g_b / A_b) c_e det M_e, which is pushed
-// back through the low-rank composition M = P[R,:] - 2 A1[R,N] Phi0[N,:]:
-//   Gbar_P[R_i, :]   += Gbar_M[i, :]
-//   Gbar_A1[R_i, c]  += -2 Gbar_M[i, :] . Phi0[c, :]      (c in N)
-//   Gbar_Phi0[c, :]  += -2 sum_i A1[R_i, c] Gbar_M[i, :]   (c in N)
-// The submatrix is recomputed, not stored.  M^-1 comes from Gauss-Jordan in
-// the same one-row-per-lane layout as the forward LU; an LDS tile per lane
-// group turns the permuted rows of M^-1 into both the rows and the columns
-// of Gbar_M.  Each workgroup accumulates into its own partial buffer, which a
-// fixed-order reduction adds up.
-// ---------------------------------------------------------------------------
 
 // Gauss-Jordan inverse with partial pivoting (same pivot rule as lu_det).
 // On return lane r (< m) holds row pos of M^-1 in v, where pos is the step at
@@ -833,6 +700,480 @@ __device__ __forceinline__ bool gj_invert(double2 (&a)[G], double2 (&v)[G], int 
     if (neg) det = make_double2(-det.x, -det.y);
     return live;
 }
+
+// ---------------------------------------------------------------------------
+// Determinant-lemma evaluation (one CPhase layer).
+//
+// Every submatrix of a bitstring shares the base M_0 = P[R, :]:
+//   M_N = M_0 - 2 A1[R, N] Phi0[N, :]
+//   det M_N = det M_0 * det(I_r - 2 H[N, N]),  H = Phi0[act, :] M_0^-1 A1[R, act]
+// over the modes `act` the CPhase gates touch (the key's bit positions).  The
+// per-bitstring work is one Gauss-Jordan inverse and two thin products; each
+// distinct key then costs an r x r determinant (r = flipped modes, r <= 6 here)
+// evaluated by a single lane.  Bitstrings with kappa_1(M_0) > 1e4 (or an
+// exactly singular M_0) and keys with r > 6 use the row-per-lane LU instead.
+// ---------------------------------------------------------------------------
+constexpr int kLemmaMaxRank = 6;
+constexpr double kLemmaMaxCond = 1e4;
+
+// Bytes of the lemma's persistent LDS: P rows (G x G) and H (kb x kb), FP64.
+__host__ __device__ __forceinline__ size_t lemma_bytes(int G, int kb) {
+    return (size_t)G * G * 16 + align16((size_t)kb * kb * 16);
+}
+
+struct LemmaBits {
+    double2 detB;   // det M_0
+    int ok;         // lemma usable for this bitstring
+};
+
+// Per-bitstring setup; whole workgroup; FP64 throughout.  Gauss-Jordan elimination of
+// [M_0 | I] in LDS (left half in sP, right half in the not yet used hash
+// keys), partial pivoting by row swaps (largest |a|^2, lowest row on ties);
+// rows are not normalised until the end, so each step is one multiplier pass
+// by wave 0 and one update pass by the workgroup.  Then X = M_0^-1 A1[R, act]
+// (in the hash counts) and H = Phi0[act, :] X into sH.
+template <int G>
+__device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem &s, double2 *sH,
+                                                 int *s_flag, double2 *s_det, Work &wk) {
+    const int tid = threadIdx.x, m = p.m, n = p.n, kb = p.keybits;
+    double2 *W = s.sP;                        // m x G, left half
+    double2 *V = (double2 *)s.hkey;           // m x G, right half -> M_0^-1
+    double2 *mult = s.piv;                    // [G] multipliers of the current step
+    double2 *pinv = s.piv + G;                // [G] inverse pivots
+    double2 *X = (double2 *)s.hcnt;           // m x kb
+    for (int i = tid; i < m * G; i += kThreads) {
+        const int r = i / G, c = i % G;
+        W[i] = p.P[(size_t)s.Rb[r] * G + c];
+        V[i] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    if (tid == 0) {
+        *s_flag = 1;
+        *s_det = make_double2(1.0, 0.0);
+    }
+    __syncthreads();
+    // ||M_0||_1 (largest column sum of moduli), kept in red[G]
+    if (tid < 64) {
+        double cs = 0.0;
+        if (tid < m)
+            for (int i = 0; i < m; ++i) {
+                const double2 x = W[i * G + tid];
+                cs += sqrt(x.x * x.x + x.y * x.y);
+            }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
+        if (tid == 0) s.red[G].x = cs;
+    }
+    for (int c = 0; c < m; ++c) {
+        if (tid < 64) {
+            const int lane = tid;
+            double v = -1.0;
+            if (lane >= c && lane < m) {
+                const double2 a = W[lane * G + c];
+                v = fma(a.x, a.x, a.y * a.y);
+            }
+            int idx = lane;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double vo = __shfl_xor(v, off, 64);
+                const int io = __shfl_xor(idx, off, 64);
+                if (vo > v || (vo == v && io < idx)) {
+                    v = vo;
+                    idx = io;
+                }
+            }
+            if (!(v > 0.0)) {
+                if (lane == 0) *s_flag = 0;
+            } else {
+                if (idx != c && lane < G) {
+                    const double2 a = W[c * G + lane], b = W[idx * G + lane];
+                    const double2 x = V[c * G + lane], y = V[idx * G + lane];
+                    W[c * G + lane] = b;
+                    W[idx * G + lane] = a;
+                    V[c * G + lane] = y;
+                    V[idx * G + lane] = x;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const double2 u = W[c * G + c];
+                const double inv = 1.0 / fma(u.x, u.x, u.y * u.y);
+                const double2 ui = make_double2(u.x * inv, -u.y * inv);
+                if (lane < m) mult[lane] = lane == c ? make_double2(0.0, 0.0) : c_mul(W[lane * G + c], ui);
+                if (lane == 0) {
+                    pinv[c] = ui;
+                    const double2 d = c_mul(*s_det, u);
+                    *s_det = idx != c ? make_double2(-d.x, -d.y) : d;
+                }
+            }
+        }
+        __syncthreads();
+        if (!*s_flag) break;
+        // rows i != c: row_i -= mult_i row_c, left columns > c and the right half
+        for (int e = tid; e < m * 2 * G; e += kThreads) {
+            const int i = e / (2 * G), j = e % (2 * G);
+            if (i == c) continue;
+            const double2 l = mult[i];
+            if (j < G) {
+                if (j > c) {
+                    const double2 rc = W[c * G + j];
+                    double2 &a = W[i * G + j];
+                    a = make_double2(a.x - (l.x * rc.x - l.y * rc.y), a.y - (l.x * rc.y + l.y * rc.x));
+                }
+            } else {
+                const double2 rc = V[c * G + j - G];
+                double2 &a = V[i * G + j - G];
+                a = make_double2(a.x - (l.x * rc.x - l.y * rc.y), a.y - (l.x * rc.y + l.y * rc.x));
+            }
+        }
+        __syncthreads();
+    }
+    LemmaBits lb;
+    lb.ok = *s_flag;
+    lb.detB = *s_det;
+    if (!lb.ok) {
+        lb.detB = make_double2(0.0, 0.0);
+        __syncthreads();
+        return lb;
+    }
+    // M_0^-1 rows: divide by the pivots
+    for (int i = tid; i < m * G; i += kThreads) V[i] = c_mul(V[i], pinv[i / G]);
+    __syncthreads();
+    // kappa_1 = ||M_0||_1 ||M_0^-1||_1
+    if (tid < 64) {
+        double cs = 0.0;
+        if (tid < m)
+            for (int i = 0; i < m; ++i) {
+                const double2 x = V[i * G + tid];
+                cs += sqrt(x.x * x.x + x.y * x.y);
+            }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
+        if (tid == 0 && !(cs * s.red[G].x <= kLemmaMaxCond)) *s_flag = 0;
+    }
+    __syncthreads();
+    lb.ok = *s_flag;
+    if (tid == 0) {
+        // elimination (multipliers, updates of the m - 1 other rows over the
+        // remaining left columns and the right half), scaling by the pivots
+        unsigned long long f = 6ull * m * m;
+        for (int c = 0; c < m; ++c) f += 7 + 6ull * (m - 1) + 8ull * (m - 1) * (2 * m - 1 - c);
+        if (lb.ok) f += 8ull * m * m * kb + 8ull * m * kb * kb;   // X and H
+        wk.flops += f;
+    }
+    if (!lb.ok) return lb;
+    // X = M_0^-1 A1[R, act]
+    for (int i = tid; i < m * kb; i += kThreads) {
+        const int j = i / kb, q = i % kb;
+        const int c = p.keymode[q];
+        double2 acc = make_double2(0.0, 0.0);
+        for (int l = 0; l < m; ++l) acc = c_fma(acc, V[j * G + l], p.A1[(size_t)s.Rb[l] * n + c]);
+        X[j * kb + q] = acc;
+    }
+    __syncthreads();
+    // H = Phi0[act, :] X
+    for (int i = tid; i < kb * kb; i += kThreads) {
+        const int q = i / kb, q2 = i % kb;
+        const int c = p.keymode[q];
+        double2 acc = make_double2(0.0, 0.0);
+        for (int j = 0; j < m; ++j) acc = c_fma(acc, p.Phi0[(size_t)c * G + j], X[j * kb + q2]);
+        sH[q * kb + q2] = acc;
+    }
+    __syncthreads();
+    return lb;
+}
+
+// det(I_r - 2 H[N, N]) for the r <= kLemmaMaxRank set bits of key (one lane):
+// LU with partial pivoting (largest |a|^2, lowest row on ties) by row swaps
+// through static-index selects; rows and columns >= r are left untouched.
+__device__ __forceinline__ double2 lemma_small_det(uint64_t key, const double2 *sH, int kb) {
+    constexpr int RM = kLemmaMaxRank;
+    int pos[RM];
+    uint64_t mm = key;
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+        pos[i] = mm ? __ffsll((long long)mm) - 1 : 0;
+        if (mm) ++r;
+        mm &= mm - 1;
+    }
+    double2 a[RM][RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RM; ++j) {
+            double2 v = make_double2(i == j ? 1.0 : 0.0, 0.0);
+            if (i < r && j < r) {
+                const double2 h = sH[pos[i] * kb + pos[j]];
+                v.x -= 2.0 * h.x;
+                v.y -= 2.0 * h.y;
+            }
+            a[i][j] = v;
+        }
+    bool neg = false;
+    double2 det = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < RM; ++c) {
+        if (c < r) {
+            int piv = c;
+            double best = fma(a[c][c].x, a[c][c].x, a[c][c].y * a[c][c].y);
+#pragma unroll
+            for (int i = c + 1; i < RM; ++i) {
+                const double v = fma(a[i][c].x, a[i][c].x, a[i][c].y * a[i][c].y);
+                if (i < r && v > best) {
+                    best = v;
+                    piv = i;
+                }
+            }
+            if (!(best > 0.0)) return make_double2(0.0, 0.0);
+            neg ^= piv != c;
+#pragma unroll
+            for (int i = c + 1; i < RM; ++i) {
+                if (piv == i) {
+#pragma unroll
+                    for (int j = c; j < RM; ++j) {
+                        const double2 t = a[c][j];
+                        a[c][j] = a[i][j];
+                        a[i][j] = t;
+                    }
+                }
+            }
+            det = c_mul(det, a[c][c]);
+            const double inv = 1.0 / best;
+            const double2 ui = make_double2(-a[c][c].x * inv, a[c][c].y * inv);
+#pragma unroll
+            for (int i = c + 1; i < RM; ++i) {
+                if (i < r) {
+                    const double2 l = c_mul(a[i][c], ui);
+#pragma unroll
+                    for (int j = c + 1; j < RM; ++j) a[i][j] = c_fma(a[i][j], l, a[c][j]);
+                }
+            }
+        }
+    }
+    return neg ? make_double2(-det.x, -det.y) : det;
+}
+
+// Lemma pass: every lane takes whole entries; entries it cannot take (r too
+// large, or the bitstring failed the conditioning test) are then evaluated by
+// lane groups with the LU.  Results go into the slots; fixed-order sum.
+// nterm[2] accumulates the executed FP64-equivalent FLOPs.
+template <int G>
+__device__ __forceinline__ double2 sum_entries_lemma(const DevPlan &p, const RawSmem &s, int nl,
+                                                     const double2 *sH, const LemmaBits &lb, Work &wk) {
+    const int tid = threadIdx.x;
+    const int lane = tid % G, grp = tid / G;
+    constexpr int NG = kThreads / G;
+    const int m = p.m;
+    if (lb.ok) {
+        for (int e = tid; e < nl; e += kThreads) {
+            const uint16_t slot = s.list[e];
+            if (slot >= kHashSlots) continue;
+            const uint64_t key = s.hkey[slot];
+            const int r = __popcll(key);
+            if (r > kLemmaMaxRank) continue;
+            const int2 c = s.hcnt[slot];
+            const double2 d = c_mul(lb.detB, lemma_small_det(key, sH, p.keybits));
+            s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+            *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
+            s.list[e] = (uint16_t)(slot | 0x8000u);
+            wk.rank += (unsigned)r;
+            // r x r LU, then the product with det M_0
+            wk.flops += lu_flops(r) + 6;
+        }
+    }
+    __syncthreads();
+    for (int e = grp; e < nl; e += NG) {
+        const uint16_t slot = s.list[e];
+        if (slot >= kHashSlots) continue;   // taken by the lemma pass
+        const uint64_t key = s.hkey[slot];
+        const int2 c = s.hcnt[slot];
+        int rank;
+        const double2 d = term_det<G, false>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
+        if (lane == 0) {
+            s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+            *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
+            wk.rank += (unsigned)rank;
+            wk.flops += lu_flops(m) + 8ull * m * m * rank;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < nl; e += kThreads) s.list[e] &= 0x7FFFu;
+    __syncthreads();
+    if (tid == 0) wk.terms += (unsigned)nl;
+    return ordered_sum_slots(s, nl);
+}
+
+// Sum over the sorted entries of count * det, in a fixed order.  Each group
+// evaluates entries e = grp, grp + NG, ...; the product is left in the
+// entry's slot and summed in sorted order by ordered_sum_slots.
+template <int G, bool MIXED, bool STAGE>
+__device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &s, int nl, Work &wk) {
+    const int tid = threadIdx.x;
+    const int lane = tid % G, grp = tid / G;
+    constexpr int NG = kThreads / G;
+    const int m = p.m;
+    for (int e = grp; e < nl; e += NG) {
+        const uint16_t slot = s.list[e];
+        if (slot >= kHashSlots) continue;   // unreachable: the list holds slot indices
+        const uint64_t key = s.hkey[slot];
+        const int2 c = s.hcnt[slot];
+        int rank;
+        double2 d;
+        if constexpr (STAGE) d = term_det_staged<G, MIXED>(p, key, s, lane, s.piv + grp * G, &rank);
+        else d = term_det<G, MIXED>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
+        if (lane == 0) {
+            s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+            *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
+            wk.rank += (unsigned)rank;
+            wk.flops += lu_flops(m) + 8ull * m * m * rank;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) wk.terms += (unsigned)nl;
+    return ordered_sum_slots(s, nl);
+}
+
+__device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) {
+    const int tid = threadIdx.x;
+    const int k = p.k;
+    for (int i = tid; i < k * k; i += kThreads) s.T[i] = p.T[i];
+    for (int i = tid; i < k; i += kThreads) {
+        s.gkey[i] = p.gkey[i];
+        s.gneg[i] = p.gneg[i];
+    }
+}
+
+// KIND: 0 = row-per-lane LU with factors read from global memory, 1 = the same
+// with the bitstring's factor rows staged in LDS, 2 = determinant lemma (FP64,
+// instantiated with MIXED = false only).
+// Up to G = 16 the LDS footprint allows two workgroups per CU; registers are
+// capped to match (a few loop-invariant values spill around the bitstring loop).
+template <int G, bool MIXED, int KIND>
+__global__ void __launch_bounds__(kThreads, G <= 16 ? 2 : 1)
+k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
+               double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
+               unsigned long long *nterm) {
+    constexpr bool STAGE = KIND == 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_ok, s_n, s_claimed, s_flag;
+    __shared__ double2 s_det;
+    const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
+    double2 *sH = (double2 *)((unsigned char *)s.sP + (size_t)G * G * 16);
+    const int tid = threadIdx.x;
+    Work wk;
+    load_tables(p, s);
+    if constexpr (STAGE) stage_phi<MIXED>(p, s);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t slot0 = hash_slot(0);
+
+    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+        if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) {
+            if (tid == 0) {
+                prob[b] = 0.0;
+                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
+                if (logp) logp[b] = -INFINITY;
+            }
+            __syncthreads();
+            continue;
+        }
+        if constexpr (STAGE) stage_rows<MIXED>(p, s);
+        LemmaBits lb;
+        if constexpr (KIND == 2) lb = lemma_setup<G>(p, s, sH, &s_flag, &s_det, wk);
+        double2 total = make_double2(0.0, 0.0);
+        clear_table(s, &s_claimed, slot0);
+        uint32_t base = 0;
+        while (true) {
+            const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
+            const int nl = prepare_list(s, &s_n);
+            double2 part;
+            if constexpr (KIND == 2) part = sum_entries_lemma<G>(p, s, nl, sH, lb, wk);
+            else part = sum_entries<G, MIXED, STAGE>(p, s, nl, wk);
+            total.x += part.x;
+            total.y += part.y;
+            if (done) break;
+            clear_table(s, &s_claimed, slot0);
+        }
+        if (tid == 0) {
+            const double ax = total.x * p.scale, ay = total.y * p.scale;
+            const double pb = ax * ax + ay * ay;
+            prob[b] = pb;
+            if (amp) { amp[2 * b] = ax; amp[2 * b + 1] = ay; }
+            if (logp) logp[b] = log(pb);
+        }
+        __syncthreads();
+    }
+    flush_work(wk, nterm);
+}
+
+template <int G, bool MIXED>
+__global__ void __launch_bounds__(kThreads)
+k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict__ w, int64_t nkeys,
+        const uint64_t *__restrict__ bits, int64_t B, double *__restrict__ prob,
+        double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_ok;
+    double2 *out = (double2 *)smem;
+    double2 *piv = out + kExactChunk;
+    double2 *red = piv + kThreads;
+    uint8_t *Rb = (uint8_t *)(red + kThreads);
+    const int tid = threadIdx.x;
+    const int lane = tid % G, grp = tid / G;
+    constexpr int NG = kThreads / G;
+    Work wk;
+    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+        if (!load_bitstring(p, bits, b, Rb, &s_ok)) {
+            if (tid == 0) {
+                prob[b] = 0.0;
+                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
+                if (logp) logp[b] = -INFINITY;
+            }
+            __syncthreads();
+            continue;
+        }
+        double2 total = make_double2(0.0, 0.0);
+        for (int64_t c0 = 0; c0 < nkeys; c0 += kExactChunk) {
+            const int ncur = (int)min((int64_t)kExactChunk, nkeys - c0);
+            for (int e = grp; e < ncur; e += NG) {
+                int rank;
+                const double2 d = term_det<G, MIXED>(p, keys[c0 + e], Rb, lane, piv + grp * G, &rank);
+                if (lane == 0) {
+                    out[e] = c_mul(w[c0 + e], d);
+                    wk.rank += (unsigned)rank;
+                    wk.flops += lu_flops(p.m) + 8ull * p.m * p.m * rank;
+                }
+            }
+            __syncthreads();
+            const double2 part = ordered_sum(out, ncur, red);
+            total.x += part.x;
+            total.y += part.y;
+        }
+        if (tid == 0) {
+            const double pb = total.x * total.x + total.y * total.y;
+            prob[b] = pb;
+            if (amp) { amp[2 * b] = total.x; amp[2 * b + 1] = total.y; }
+            if (logp) logp[b] = log(pb);
+            wk.terms += (unsigned long long)nkeys;
+        }
+        __syncthreads();
+    }
+    flush_work(wk, nterm);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (gradient of L = sum_b g_b log p_b)
+//
+// d log p_b = 2 Re(dA_b / A_b) and d det M = det M tr(M^-1 dM) (Jacobi), so
+// every distinct entry e of bitstring b contributes the holomorphic adjoint
+// Gbar_M = beta_e M_e^-T, beta_e = (g_b / A_b) c_e det M_e, which is pushed
+// back through the low-rank composition M = P[R,:] - 2 A1[R,N] Phi0[N,:]:
+//   Gbar_P[R_i, :]   += Gbar_M[i, :]
+//   Gbar_A1[R_i, c]  += -2 Gbar_M[i, :] . Phi0[c, :]      (c in N)
+//   Gbar_Phi0[c, :]  += -2 sum_i A1[R_i, c] Gbar_M[i, :]   (c in N)
+// The submatrix is recomputed, not stored.  M^-1 comes from Gauss-Jordan in
+// the same one-row-per-lane layout as the forward LU; an LDS tile per lane
+// group turns the permuted rows of M^-1 into both the rows and the columns
+// of Gbar_M.  Each workgroup accumulates into its own partial buffer, which a
+// fixed-order reduction adds up.
+// ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void atomic_add_c(double2 *dst, double2 v) {
     atomicAdd(&dst->x, v.x);
@@ -960,7 +1301,8 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
         while (true) {
             const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
             const int nl = prepare_list(s, &s_n);
-            const double2 part_sum = sum_entries<G, MIXED, false>(p, s, nl, nullptr);
+            Work unused;
+            const double2 part_sum = sum_entries<G, MIXED, false>(p, s, nl, unused);
             total.x += part_sum.x;
             total.y += part_sum.y;
             if (done) break;
@@ -1070,6 +1412,7 @@ __global__ void k_reduce_parts(const double2 *__restrict__ part, int nparts, int
 __global__ void k_zero_u64(unsigned long long *p) {
     p[0] = 0ull;
     p[1] = 0ull;
+    p[2] = 0ull;
 }
 
 constexpr int kMaxGrid = 1 << 20;
@@ -1081,20 +1424,38 @@ __host__ __forceinline__ bool use_stage(const DevPlan &p, bool mixed) {
     return p.L == 1 && p.G <= 16 && raw_lds_bytes(p.k, p.n, p.G, mixed, true) <= kMaxLds;
 }
 
+__host__ __forceinline__ size_t lemma_lds(const DevPlan &p) {
+    return raw_lds_bytes(p.k, p.n, p.G, false, false) + lemma_bytes(p.G, p.keybits);
+}
+
+// The lemma needs one CPhase layer, compressed flip-pattern keys and room for
+// H.  It runs in FP64 for both precisions: its per-pattern work is an r x r
+// determinant, too small for FP32 to pay, and H in FP32 loses up to
+// ||M_0^-1|| more digits than the direct FP32 correction.
+__host__ __forceinline__ bool lemma_applies(const DevPlan &p) {
+    return p.L == 1 && p.G <= 16 && p.keykind == 0 && p.keybits >= 1 && lemma_lds(p) <= kMaxLds;
+}
+
 template <int G, bool MIXED>
-hipError_t launch_raw_t(const DevPlan &p, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
-                        double *prob, double *amp, double *logp, unsigned long long *nterm, hipStream_t s) {
+hipError_t launch_raw_t(const DevPlan &p, int algorithm, const uint64_t *bits, int64_t B, int64_t t,
+                        uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
+                        hipStream_t s) {
     const int grid = (int)(B < kMaxGrid ? B : kMaxGrid);
     if constexpr (G <= 16) {
+        if (algorithm != 1 && lemma_applies(p)) {
+            hipLaunchKernelGGL((k_raw_estimate<G, false, 2>), dim3(grid), dim3(kThreads), lemma_lds(p), s, p, bits,
+                               B, (uint32_t)t, seed, prob, amp, logp, nterm);
+            return hipGetLastError();
+        }
         if (use_stage(p, MIXED)) {
             const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, true);
-            hipLaunchKernelGGL((k_raw_estimate<G, MIXED, true>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
+            hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 1>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
                                (uint32_t)t, seed, prob, amp, logp, nterm);
             return hipGetLastError();
         }
     }
     const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, false);
-    hipLaunchKernelGGL((k_raw_estimate<G, MIXED, false>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
+    hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 0>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
                        (uint32_t)t, seed, prob, amp, logp, nterm);
     return hipGetLastError();
 }
@@ -1134,19 +1495,17 @@ template <int G>
 hipError_t set_lds_limits() {
     const int big = (int)kMaxLds;
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, false, false>,
+    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, false, 0>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
         return e;
-    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, true, false>,
+    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, true, 0>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
         return e;
     if constexpr (G <= 16) {
-        if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, false, true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-            return e;
-        if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, true, true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-            return e;
+        for (const void *f : {(const void *)k_raw_estimate<G, false, 1>, (const void *)k_raw_estimate<G, true, 1>,
+                              (const void *)k_raw_estimate<G, false, 2>})
+            if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
+                return e;
     }
     if ((e = hipFuncSetAttribute((const void *)k_exact<G, false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
@@ -1175,6 +1534,10 @@ hipError_t set_lds_limits() {
 
 size_t raw_estimate_lds_bytes(const DevPlan &p, bool mixed) {
     return raw_lds_bytes(p.k, p.n, p.G, mixed, p.G <= 16 && use_stage(p, mixed));
+}
+
+bool raw_estimate_uses_lemma(const DevPlan &p, int algorithm) {
+    return algorithm != 1 && lemma_applies(p);
 }
 
 size_t exact_lds_bytes(const DevPlan &) { return kExactChunk * 16 + 2 * kThreads * 16 + 64; }
@@ -1261,13 +1624,13 @@ hipError_t prepare_kernels(int G) {
         default: return hipErrorInvalidValue; \
     }
 
-hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
+hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, int algorithm, const uint64_t *bits, int64_t B,
                                int64_t t, uint64_t seed, double *prob, double *amp, double *logp,
                                unsigned long long *nterm, hipStream_t s) {
     hipError_t e = hipSuccess;
 #define XF_RAW(GG) \
-    e = mixed ? launch_raw_t<GG, true>(p, bits, B, t, seed, prob, amp, logp, nterm, s) \
-              : launch_raw_t<GG, false>(p, bits, B, t, seed, prob, amp, logp, nterm, s)
+    e = mixed ? launch_raw_t<GG, true>(p, algorithm, bits, B, t, seed, prob, amp, logp, nterm, s) \
+              : launch_raw_t<GG, false>(p, algorithm, bits, B, t, seed, prob, amp, logp, nterm, s)
     XF_DISPATCH_G(p.G, XF_RAW)
 #undef XF_RAW
     return e;

@@ -1,0 +1,196 @@
+"""GPU parity of the determinant-lemma evaluation of Raw Estimate (one CPhase
+layer): det M_N = det M_0 det(I_r - 2 H[N, N]) with H formed once per
+bitstring, against the FP64 oracle (which always evaluates M_N directly), and
+its fallbacks to the LU: singular or ill-conditioned bases M_0, and patterns
+of more than six flipped modes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import gpu_probs, make_plan, oracle_probs, rel_err, sample_indices, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+TOL_MIXED = 1e-5
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_12416_amd as X
+    X.lib()
+    return X
+
+
+def _check(p, ref, tol, label):
+    e = rel_err(p, ref)
+    say(f"  {label}: n={len(p)} max rel err {e.max():.3e} median {np.median(e):.3e}")
+    assert np.all(np.isfinite(p))
+    assert e.max() <= tol, (label, int(np.argmax(e)), p[np.argmax(e)], ref[np.argmax(e)])
+
+
+def _probs(plan, X, bits, t, seed, evaluation):
+    plan.set_evaluation(evaluation)
+    p = gpu_probs(plan, X, bits, "approx", t=t, seed=seed)
+    return p, plan.last_work()
+
+
+def test_lucj_full_batch_lemma_matches_oracle_and_lu(X):
+    w = W.workload(2)
+    say("LUCJ n=32 eta=16 k=46 t=16384 B=10000: lemma vs oracle (sampled) and vs LU (all)")
+    idx = sample_indices(w.B, 24, seed=12)
+    ref = oracle.run_workload(w, index=idx)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        plan = make_plan(w, X, prec)
+        for evaluation in ("auto", "lu"):
+            res[prec, evaluation] = _probs(plan, X, w.bits, w.t, w.seed, evaluation)
+    (pa, wa), (pl, wl) = res["fp64", "auto"], res["fp64", "lu"]
+    assert wa["lemma"] and not wl["lemma"]
+    assert wa["determinants"] == wl["determinants"]
+    assert wa["rank_sum"] == wl["rank_sum"]
+    assert 0 < wa["flops"] < wl["flops"]
+    say(f"  FLOPs lemma {wa['flops']:.3e} LU {wl['flops']:.3e}")
+    _check(pa[idx], ref, TOL_FP64, "lemma vs oracle")
+    _check(pa, pl, TOL_FP64, f"lemma vs LU (all {w.B})")
+    # the lemma runs in FP64 under both precisions
+    assert res["mixed", "auto"][1]["lemma"]
+    assert np.array_equal(res["mixed", "auto"][0], pa)
+    _check(res["mixed", "lu"][0], pl, TOL_MIXED, f"mixed LU vs FP64 LU (all {w.B})")
+
+
+def test_generator_workload_lemma(X):
+    w = W.workload(4)
+    say("generator-parametrised n=32 eta=16 k=24 t=16384 B=4096: lemma vs oracle")
+    idx = sample_indices(w.B, 16, seed=14)
+    ref = oracle.run_workload(w, index=idx)
+    plan = make_plan(w, X)
+    p, wk = _probs(plan, X, w.bits, w.t, w.seed, "auto")
+    assert wk["lemma"]
+    _check(p[idx], ref, TOL_FP64, "lemma fp64")
+
+
+LEMMA_RANDOM = [
+    # seed, n, eta, k, theta_scale          (lane-group size of the LU fallback)
+    (501, 6, 3, 5, 1.5),     # G = 4
+    (502, 11, 5, 14, 2.0),   # G = 8, many flips: patterns with r > 6 fall back
+    (503, 16, 8, 20, 0.8),   # G = 8
+    (504, 22, 11, 30, 0.5),  # G = 16
+    (505, 40, 14, 25, 0.3),  # G = 16, 40 modes
+]
+
+
+@pytest.mark.parametrize("case", LEMMA_RANDOM, ids=[f"n{c[1]}_eta{c[2]}_k{c[3]}" for c in LEMMA_RANDOM])
+def test_random_one_layer_lemma(X, case):
+    seed, n, eta, k, scale = case
+    w = W.random_circuit(seed, n, eta, k, n_rot=2, theta_scale=scale)
+    if w.bits.shape[0] > 200:
+        rng = np.random.default_rng(seed)
+        w.bits = w.bits[np.sort(rng.choice(w.bits.shape[0], 200, replace=False))]
+    say(f"random one-layer lemma {case}")
+    for t, s in ((1, 3), (4000, 21)):
+        ref = oracle_probs(w, w.bits, mode="approx", t=t, seed=s)
+        for prec, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
+            plan = make_plan(w, X, prec)
+            p, wk = _probs(plan, X, w.bits, t, s, "auto")
+            assert wk["lemma"]
+            _check(p, ref, tol, f"t={t} {prec}")
+
+
+def _rotation_with_row(rng, v):
+    """Unitary whose row 0 is v (unit norm) up to a phase."""
+    n = v.shape[0]
+    Z = np.concatenate([v.conj()[:, None], rng.standard_normal((n, n - 1)) + 1j * rng.standard_normal((n, n - 1))],
+                       axis=1)
+    Q, _ = np.linalg.qr(Z)
+    return Q.conj().T
+
+
+@pytest.mark.parametrize("offset", [0.0, 1e-7], ids=["orthogonal", "near_orthogonal"])
+def test_ill_conditioned_base_falls_back(X, offset):
+    """Row 0 of the second rotation is (nearly) orthogonal to the columns of
+    D_0 R_0[:, C], so every bitstring with mode 0 occupied has a (nearly)
+    singular base M_0 = P[R, :] while its flipped submatrices are regular."""
+    say(f"ill-conditioned bases, offset {offset}")
+    rng = W.rng_for(606)
+    n, eta, k = 10, 4, 9
+    R0 = W.haar_unitary(rng, n)
+    pairs = W.random_pairs(rng, n, k)
+    theta = rng.uniform(-2.0, 2.0, k)
+    C = list(range(1, eta + 1))
+    d0 = np.ones(n, dtype=np.complex128)
+    for (a, b), th in zip(pairs, theta):
+        d0[a] *= np.exp(0.5j * th)
+        d0[b] *= np.exp(0.5j * th)
+    Q = d0[:, None] * R0[:, C]
+    _, _, vh = np.linalg.svd(Q.T)
+    z = vh[eta:].conj().T[:, 0]                         # Q.T z = 0
+    v = z + offset * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    v = v / np.linalg.norm(v)
+    R1 = _rotation_with_row(rng, v)
+    rot = np.stack([R0, R1])
+    inp = W.bits_from_modes(C)
+    bits = W.all_fixed_weight(n, eta)
+    # the construction does what it says
+    P = R1 @ Q
+    conds = []
+    for b in bits:
+        R = [q for q in range(n) if (int(b[0]) >> q) & 1]
+        if 0 in R:
+            conds.append(float(np.real(np.linalg.cond(P[R, :], 1))))
+    assert min(conds) > 1e4
+    ref = oracle.probabilities(rot, pairs, np.zeros(k), theta, inp, bits, "approx", 3000, 8)
+    assert np.count_nonzero(ref) > len(bits) // 2
+    plan = X.Plan(rot, pairs, np.zeros(k), theta, inp)
+    p, wk = _probs(plan, X, bits, 3000, 8, "auto")
+    assert wk["lemma"]
+    _check(p, ref, TOL_FP64, "fallback bases")
+
+
+def test_exactly_singular_bases(X):
+    """Identity rotations: every base with R != C is exactly singular (zero
+    rows) and so is every flipped submatrix, giving p = 0 there."""
+    say("exactly singular bases")
+    n = 7
+    rot = np.stack([np.eye(n, dtype=np.complex128)] * 2)
+    pairs, layer, theta = [[0, 1], [2, 5]], [0, 0], [0.4, -0.3]
+    inp = W.bits_from_modes([1, 2, 5])
+    bits = W.all_fixed_weight(n, 3)
+    plan = X.Plan(rot, pairs, layer, theta, inp)
+    p, wk = _probs(plan, X, bits, 64, 3, "auto")
+    assert wk["lemma"]
+    ref = oracle.probabilities(rot, pairs, layer, theta, inp, bits, "approx", 64, 3)
+    np.testing.assert_allclose(p, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_many_flips_fall_back_per_pattern(X):
+    """Large angles over many gates: most patterns flip more than six modes
+    and take the LU, the rest the lemma, within one table flush."""
+    say("per-pattern fallback: n=16 eta=6 k=40 theta~U[-3,3] t=8192")
+    rng = W.rng_for(404)
+    n = 16
+    rot = np.stack([W.haar_unitary(rng, n) for _ in range(2)])
+    pairs = W.random_pairs(rng, n, 40)
+    theta = rng.uniform(-3.0, 3.0, 40)
+    inp = W.bits_from_modes(range(6))
+    bits = W.all_fixed_weight(n, 6)[::997][:8]
+    plan = X.Plan(rot, pairs, np.zeros(40), theta, inp)
+    p, wk = _probs(plan, X, bits, 8192, 9, "auto")
+    assert wk["lemma"]
+    mean_rank = wk["rank_sum"] / wk["determinants"]
+    say(f"  mean flipped modes {mean_rank:.2f}")
+    assert mean_rank > 6
+    ref = oracle.probabilities(rot, pairs, np.zeros(40), theta, inp, bits, "approx", 8192, 9)
+    _check(p, ref, TOL_FP64, "mixed lemma / LU patterns")
+
+
+def test_two_layers_do_not_use_lemma(X):
+    w = W.random_circuit(507, 9, 4, 6, n_rot=3, theta_scale=1.0)
+    plan = make_plan(w, X)
+    _, wk = _probs(plan, X, w.bits, 200, 2, "auto")
+    assert not wk["lemma"]

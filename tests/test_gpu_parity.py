@@ -100,10 +100,12 @@ def test_random_raw_estimate(X, case):
     w = _random_case(*case)
     say(f"random raw estimate {case}")
     for t, seed in ((1, 5), (3000, 77)):
-        plan = make_plan(w, X)
-        p = gpu_probs(plan, X, w.bits, "approx", t=t, seed=seed)
         ref = oracle_probs(w, w.bits, mode="approx", t=t, seed=seed)
-        _check(p, ref, TOL_FP64, f"raw t={t}")
+        plan = make_plan(w, X)
+        for evaluation in ("auto", "lu"):
+            plan.set_evaluation(evaluation)
+            p = gpu_probs(plan, X, w.bits, "approx", t=t, seed=seed)
+            _check(p, ref, TOL_FP64, f"raw t={t} {evaluation}")
 
 
 # ----------------------------------------------------------------------------
@@ -112,11 +114,12 @@ def test_random_raw_estimate(X, case):
 
 def test_config2_lucj_full_batch(X):
     w = W.workload(2)
-    say("config 2: LUCJ n=32 eta=16 k=46 t=16384 B=10000")
+    say("config 2: LUCJ n=32 eta=16 k=46 t=16384 B=10000 (LU per pattern)")
     idx = sample_indices(w.B, 24, seed=2)
     ref = oracle.run_workload(w, index=idx)
     for prec, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
         plan = make_plan(w, X, prec)
+        plan.set_evaluation("lu")
         p = gpu_probs(plan, X, w.bits, "approx", w.t, w.seed)
         assert p.shape == (w.B,)
         _check(p[idx], ref, tol, f"cfg2 {prec}")
@@ -143,6 +146,7 @@ def test_config4_forward_full_batch(X):
     idx = sample_indices(w.B, 16, seed=4)
     ref = oracle.run_workload(w, index=idx)
     plan = make_plan(w, X)
+    plan.set_evaluation("lu")
     p = gpu_probs(plan, X, w.bits, "approx", w.t, w.seed)
     _check(p[idx], ref, TOL_FP64, "cfg4 fp64")
 
@@ -210,6 +214,7 @@ def test_hash_flush_path(X):
     inp = W.bits_from_modes(range(6))
     bits = W.all_fixed_weight(n, 6)[::997][:8]
     plan = X.Plan(rot, pairs, np.zeros(40), theta, inp)
+    plan.set_evaluation("lu")
     p = gpu_probs(plan, X, bits, "approx", t=8192, seed=9)
     nt = plan.last_term_count()
     ref = oracle.probabilities(rot, pairs, np.zeros(40), theta, inp, bits, "approx", 8192, 9)
