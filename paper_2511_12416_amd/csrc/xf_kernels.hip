@@ -510,92 +510,149 @@ __device__ __forceinline__ int prepare_list(const RawSmem &s, int *s_n) {
 }
 
 // Empties the table and re-reserves the slot of the empty flip pattern.
-__device__ __forceinline__ void clear_table(const RawSmem &s, int *s_claimed, uint32_t slot0) {
+// Samples each thread draws per pass of the sampler, and the table fill past
+// which a pass is not started (the table is evaluated and cleared first).
+constexpr int kSamplesPerThread = 4;
+constexpr uint32_t kBatch = (uint32_t)kThreads * kSamplesPerThread;
+constexpr int kFlushAt = (3 * kHashSlots) / 4;
+static_assert(kBatch + 1 <= (uint32_t)kFlushAt, "a fresh table must take a whole batch");
+
+// Sampler position of one workgroup; every thread holds the same values.
+struct Sampler {
+    uint32_t next = 0;   // first sample of the current batch
+    uint32_t j = 0;      // batch number (selects the rotating LDS counters)
+    int claimed = 1;     // table slots in use after the last inserted batch
+};
+
+// Empties the hash table (slot0 keeps the empty flip pattern) and the six
+// sampler counters cnt[0..5].  Whole workgroup.
+__device__ __forceinline__ void clear_table(const RawSmem &s, int *cnt, uint32_t slot0, Sampler &st) {
     const int tid = threadIdx.x;
     __syncthreads();
     for (int i = tid; i < kHashSlots; i += kThreads) {
         s.hkey[i] = kEmptyKey;
         s.hcnt[i] = make_int2(0, 0);
     }
+    if (tid < 6) cnt[tid] = 0;
     __syncthreads();
-    if (tid == 0) {
-        s.hkey[slot0] = 0;
-        *s_claimed = 1;
-    }
+    if (tid == 0) s.hkey[slot0] = 0;
     __syncthreads();
+    st.claimed = 1;
 }
 
-// Draws trajectories of bitstring b (batch index b) from sample `*base`
-// onwards, reducing each to its flip-pattern key in the LDS hash, until either
-// all t samples are in (returns true) or one more batch of kThreads samples
-// could fill the table past three quarters (returns false).  The stopping
-// points depend only on the distinct keys seen, so every pass over the same
-// bitstring empties the table at the same samples.  After each return the
-// caller evaluates the sorted entries (prepare_list) and, if not done, clears
-// the table (clear_table) and calls again.  Whole workgroup; s.T / s.gkey /
-// s.gneg loaded; the table cleared before the first call.
-__device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSmem &s, int *s_claimed,
-                                                   uint32_t slot0, int64_t b, uint32_t t, uint32_t k0,
-                                                   uint32_t k1, uint32_t *base) {
-    const int tid = threadIdx.x;
+// One trajectory of the product distribution (see the sampler definition in
+// the public header): draws words of Philox blocks (smp, d / 4, b) until no
+// further gate succeeds; r is block 0.  Returns the flip-pattern key, the
+// phase exponent e (i^e, e mod 4) and whether no gate was set.
+__device__ __forceinline__ bool draw_trajectory(const DevPlan &p, const RawSmem &s, uint32_t smp, uint4 r,
+                                                uint32_t blo, uint32_t bhi, uint32_t k0, uint32_t k1,
+                                                uint64_t &key, uint32_t &e) {
     const int k = p.k;
+    key = 0;
+    e = 0;
+    bool empty = true;
+    uint32_t blk = 0, d = 0;
+    int a = 0;
+    while (a < k) {
+        if ((d >> 2) != blk) {
+            blk = d >> 2;
+            r = philox10(make_uint4(smp, blk, blo, bhi), k0, k1);
+        }
+        const uint32_t w = d & 3;
+        const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
+        ++d;
+        const uint32_t *Ta = s.T + a * k;
+        if (!(u < Ta[k - 1])) break;
+        int lo = a, hi = k - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (u < Ta[mid]) hi = mid;
+            else lo = mid + 1;
+        }
+        key ^= s.gkey[lo];
+        e += 1u + 2u * s.gneg[lo];
+        empty = false;
+        a = lo + 1;
+    }
+    return empty;
+}
+
+// Draws trajectories of bitstring b (batch index b) in batches of kBatch
+// samples, reducing each to its flip-pattern key in the LDS hash, until either
+// all t samples are in (returns true) or the next batch could push the table
+// past kFlushAt slots (returns false; that batch is drawn again after the
+// table has been evaluated and cleared).  The bound uses the exact count of
+// slots in use plus the batch's non-empty samples, so the stopping points
+// depend only on the samples and every pass over the same bitstring empties
+// the table at the same samples.  One barrier per batch: counts of the
+// batch's non-empty samples and of the slots each batch claims live in three
+// rotating LDS counters each (cnt[0..2], cnt[3..5]), read only after the
+// barrier that follows their last update and cleared two batches before
+// their next use.  Whole workgroup; s.T / s.gkey / s.gneg loaded; the table
+// cleared (clear_table) before the first call and between calls.
+__device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSmem &s, int *cnt,
+                                                   uint32_t slot0, int64_t b, uint32_t t, uint32_t k0,
+                                                   uint32_t k1, Sampler &st) {
+    const int tid = threadIdx.x;
+    const bool leader = (tid & 63) == 0;
     const uint32_t blo = (uint32_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
-    for (; *base < t; *base += kThreads) {
-        if (*s_claimed > 1 && *s_claimed + kThreads > (3 * kHashSlots) / 4) return false;
-        const uint32_t smp = *base + tid;
-        const bool valid = smp < t;
-        uint64_t key = 0;
-        uint32_t e = 0;
-        bool empty = true;
-        if (valid && k > 0) {
-            uint32_t blk = 0;
-            uint4 r = philox10(make_uint4(smp, 0u, blo, bhi), k0, k1);
-            uint32_t d = 0;
-            int a = 0;
-            while (a < k) {
-                if ((d >> 2) != blk) {
-                    blk = d >> 2;
-                    r = philox10(make_uint4(smp, blk, blo, bhi), k0, k1);
-                }
-                const uint32_t w = d & 3;
-                const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
-                ++d;
-                const uint32_t *Ta = s.T + a * k;
-                if (!(u < Ta[k - 1])) break;
-                int lo = a, hi = k - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (u < Ta[mid]) hi = mid;
-                    else lo = mid + 1;
-                }
-                key ^= s.gkey[lo];
-                e += 1u + 2u * s.gneg[lo];
-                empty = false;
-                a = lo + 1;
-            }
+    int *pend = cnt, *added = cnt + 3;
+    for (; st.next < t; st.next += kBatch, ++st.j) {
+        uint64_t key[kSamplesPerThread];
+        uint32_t e[kSamplesPerThread];
+        bool live[kSamplesPerThread], empty[kSamplesPerThread];
+        uint4 r[kSamplesPerThread];
+#pragma unroll
+        for (int q = 0; q < kSamplesPerThread; ++q) {
+            const uint32_t smp = st.next + (uint32_t)(q * kThreads + tid);
+            live[q] = smp < t;
+            r[q] = philox10(make_uint4(smp, 0u, blo, bhi), k0, k1);
         }
-        const unsigned long long ball = __ballot(valid && empty);
-        if ((tid & 63) == 0 && ball) atomicAdd(&s.hcnt[slot0].x, (int)__popcll(ball));
-        if (valid && !empty) {
-            uint32_t slot = hash_slot(key);
-            while (true) {
-                const unsigned long long prev =
-                    atomicCAS((unsigned long long *)&s.hkey[slot], (unsigned long long)kEmptyKey,
-                              (unsigned long long)key);
-                if (prev == kEmptyKey) {
-                    atomicAdd(s_claimed, 1);
-                    break;
-                }
-                if (prev == key) break;
-                slot = (slot + 1) & (kHashSlots - 1);
-            }
-            e &= 3;
-            if (e == 0) atomicAdd(&s.hcnt[slot].x, 1);
-            else if (e == 1) atomicAdd(&s.hcnt[slot].y, 1);
-            else if (e == 2) atomicAdd(&s.hcnt[slot].x, -1);
-            else atomicAdd(&s.hcnt[slot].y, -1);
+        int nonempty = 0;
+#pragma unroll
+        for (int q = 0; q < kSamplesPerThread; ++q) {
+            const uint32_t smp = st.next + (uint32_t)(q * kThreads + tid);
+            empty[q] = true;
+            key[q] = 0;
+            e[q] = 0;
+            if (live[q] && p.k > 0) empty[q] = draw_trajectory(p, s, smp, r[q], blo, bhi, k0, k1, key[q], e[q]);
+            nonempty += (int)__popcll(__ballot(live[q] && !empty[q]));
         }
+        if (leader && nonempty) atomicAdd(&pend[st.j % 3], nonempty);
         __syncthreads();
+        const int pending = pend[st.j % 3];
+        st.claimed += added[(st.j + 2) % 3];
+        if (tid == 0) {
+            pend[(st.j + 2) % 3] = 0;
+            added[(st.j + 1) % 3] = 0;
+        }
+        if (st.claimed > 1 && st.claimed + pending > kFlushAt) return false;
+        int empties = 0, fresh = 0;
+#pragma unroll
+        for (int q = 0; q < kSamplesPerThread; ++q) {
+            empties += (int)__popcll(__ballot(live[q] && empty[q]));
+            if (live[q] && !empty[q]) {
+                uint32_t slot = hash_slot(key[q]);
+                while (true) {
+                    const unsigned long long prev =
+                        atomicCAS((unsigned long long *)&s.hkey[slot], (unsigned long long)kEmptyKey,
+                                  (unsigned long long)key[q]);
+                    if (prev == kEmptyKey) {
+                        ++fresh;
+                        break;
+                    }
+                    if (prev == key[q]) break;
+                    slot = (slot + 1) & (kHashSlots - 1);
+                }
+                const uint32_t eq = e[q] & 3;
+                if (eq == 0) atomicAdd(&s.hcnt[slot].x, 1);
+                else if (eq == 1) atomicAdd(&s.hcnt[slot].y, 1);
+                else if (eq == 2) atomicAdd(&s.hcnt[slot].x, -1);
+                else atomicAdd(&s.hcnt[slot].y, -1);
+            }
+        }
+        if (leader && empties) atomicAdd(&s.hcnt[slot0].x, empties);
+        if (fresh) atomicAdd(&added[st.j % 3], fresh);
     }
     return true;
 }
@@ -1054,7 +1111,8 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
                unsigned long long *nterm) {
     constexpr bool STAGE = KIND == 1;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n, s_claimed, s_flag;
+    __shared__ int s_ok, s_n, s_flag;
+    __shared__ int s_cnt[6];
     __shared__ double2 s_det;
     const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
     double2 *sH = (double2 *)((unsigned char *)s.sP + (size_t)G * G * 16);
@@ -1079,10 +1137,10 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
         LemmaBits lb;
         if constexpr (KIND == 2) lb = lemma_setup<G>(p, s, sH, &s_flag, &s_det, wk);
         double2 total = make_double2(0.0, 0.0);
-        clear_table(s, &s_claimed, slot0);
-        uint32_t base = 0;
+        Sampler st;
+        clear_table(s, s_cnt, slot0, st);
         while (true) {
-            const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
+            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
             const int nl = prepare_list(s, &s_n);
             double2 part;
             if constexpr (KIND == 2) part = sum_entries_lemma<G>(p, s, nl, sH, lb, wk);
@@ -1090,7 +1148,7 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
             total.x += part.x;
             total.y += part.y;
             if (done) break;
-            clear_table(s, &s_claimed, slot0);
+            clear_table(s, s_cnt, slot0, st);
         }
         if (tid == 0) {
             const double ax = total.x * p.scale, ay = total.y * p.scale;
@@ -1279,7 +1337,8 @@ __global__ void __launch_bounds__(kThreads)
 k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
                    const double *__restrict__ g, double2 *part, GradLayout lay) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n, s_claimed;
+    __shared__ int s_ok, s_n;
+    __shared__ int s_cnt[6];
     const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
     constexpr int NG = kThreads / G;
     double2 *tiles = (double2 *)(smem + raw_lds_bytes(p.k, p.n, G, MIXED, false));
@@ -1296,17 +1355,17 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
         const double gb = g[b];
         if (gb == 0.0) continue;
         double2 total = make_double2(0.0, 0.0);
-        clear_table(s, &s_claimed, slot0);
-        uint32_t base = 0;
+        Sampler st;
+        clear_table(s, s_cnt, slot0, st);
         while (true) {
-            const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
+            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
             const int nl = prepare_list(s, &s_n);
             Work unused;
             const double2 part_sum = sum_entries<G, MIXED, false>(p, s, nl, unused);
             total.x += part_sum.x;
             total.y += part_sum.y;
             if (done) break;
-            clear_table(s, &s_claimed, slot0);
+            clear_table(s, s_cnt, slot0, st);
         }
         const double ax = total.x * p.scale, ay = total.y * p.scale;
         const double a2 = ax * ax + ay * ay;
@@ -1316,10 +1375,10 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
         double2 srow[G];
 #pragma unroll
         for (int j = 0; j < G; ++j) srow[j] = make_double2(0.0, 0.0);
-        clear_table(s, &s_claimed, slot0);
-        base = 0;
+        st = Sampler();
+        clear_table(s, s_cnt, slot0, st);
         while (true) {
-            const bool done = sample_until_flush(p, s, &s_claimed, slot0, b, t, k0, k1, &base);
+            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
             const int nl = prepare_list(s, &s_n);
             for (int e = grp; e < nl; e += NG) {
                 const uint16_t slot = s.list[e];
@@ -1330,7 +1389,7 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
             }
             __syncthreads();
             if (done) break;
-            clear_table(s, &s_claimed, slot0);
+            clear_table(s, s_cnt, slot0, st);
         }
         flush_srow<G>(p, s.Rb, lane, srow, go);
         if (tid == 0) atomicAdd(go.gsum, gb);
