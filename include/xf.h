@@ -163,12 +163,13 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
  *   XF_EVAL_AUTO (default): for circuits with one CPhase layer (n_rot = 2),
  *     the matrix determinant lemma det M_N = det M_0 det(I_r - 2 H[N, N]) with
  *     H = Phi[act, :] M_0^-1 A[R, act] formed once per bitstring, so that each
- *     pattern with r = |N| <= 6 costs an r x r determinant.  A bitstring whose
- *     base M_0 is singular or has 1-norm condition number above 1e4, and any
- *     pattern with r > 6, is evaluated with the LU instead.  The lemma runs
- *     in FP64 under both precisions (XF_MIXED then gives FP64 results).
- *     Other circuits, eta > 16, and sizes whose tables do not fit in LDS use
- *     the LU. */
+ *     pattern costs an r x r determinant (r = |N|; one lane for r <= 6, a
+ *     lane group for larger r up to the group size, 4 to 16 lanes by eta).
+ *     A bitstring whose base M_0 is singular or has 1-norm condition number
+ *     above 1e4, and any larger pattern, is evaluated with the LU of M_N
+ *     instead.  The lemma runs in FP64 under both precisions (XF_MIXED then
+ *     gives FP64 results).  Other circuits, eta > 16, and sizes whose tables
+ *     do not fit in LDS use the LU. */
 typedef enum { XF_EVAL_AUTO = 0, XF_EVAL_LU = 1 } xf_evaluation;
 xf_status xf_plan_set_evaluation(xf_plan *plan, xf_evaluation evaluation);
 

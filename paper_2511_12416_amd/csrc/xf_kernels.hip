@@ -49,9 +49,11 @@ __device__ __forceinline__ float2 c_fmaf(float2 acc, float2 a, float2 b) {
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // one 32 x 32 -> 64-bit multiply each (v_mad_u64_u32) instead of
+        // separate low and high halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -1009,9 +1011,11 @@ __device__ __forceinline__ double2 lemma_small_det(uint64_t key, const double2 *
     return neg ? make_double2(-det.x, -det.y) : det;
 }
 
-// Lemma pass: every lane takes whole entries; entries it cannot take (r too
-// large, or the bitstring failed the conditioning test) are then evaluated by
-// lane groups with the LU.  Results go into the slots; fixed-order sum.
+// Lemma pass: every lane takes whole entries with r <= kLemmaMaxRank; the
+// rest are then evaluated by lane groups: the r x r matrix I - 2 H[N, N] with
+// the group LU when r <= G, else (and for every entry of a bitstring that
+// failed the conditioning test) the LU of M_N itself.  Results go into the
+// slots; fixed-order sum.
 // nterm[2] accumulates the executed FP64-equivalent FLOPs.
 template <int G>
 __device__ __forceinline__ double2 sum_entries_lemma(const DevPlan &p, const RawSmem &s, int nl,
@@ -1043,13 +1047,46 @@ __device__ __forceinline__ double2 sum_entries_lemma(const DevPlan &p, const Raw
         if (slot >= kHashSlots) continue;   // taken by the lemma pass
         const uint64_t key = s.hkey[slot];
         const int2 c = s.hcnt[slot];
+        const int r = __popcll(key);
         int rank;
-        const double2 d = term_det<G, false>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
+        double2 d;
+        unsigned long long f;
+        if (lb.ok && r <= G) {
+            // I - 2 H[N, N] with one row per lane, then the group LU
+            uint64_t mm = key;
+            int own = 0;
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                const int q = mm ? __ffsll((long long)mm) - 1 : 0;
+                if (i == lane) own = q;
+                mm &= mm - 1;
+            }
+            double2 a[G];
+            mm = key;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int q = mm ? __ffsll((long long)mm) - 1 : 0;
+                mm &= mm - 1;
+                double2 v = make_double2(j == lane ? 1.0 : 0.0, 0.0);
+                if (lane < r && j < r) {
+                    const double2 h = sH[own * p.keybits + q];
+                    v.x -= 2.0 * h.x;
+                    v.y -= 2.0 * h.y;
+                }
+                a[j] = v;
+            }
+            d = c_mul(lb.detB, lu_det<G>(a, r, lane, s.piv + grp * G));
+            rank = r;
+            f = lu_flops(r) + 6;
+        } else {
+            d = term_det<G, false>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
+            f = lu_flops(m) + 8ull * m * m * rank;
+        }
         if (lane == 0) {
             s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
             *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
             wk.rank += (unsigned)rank;
-            wk.flops += lu_flops(m) + 8ull * m * m * rank;
+            wk.flops += f;
         }
     }
     __syncthreads();
