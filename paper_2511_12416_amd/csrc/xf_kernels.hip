@@ -1,20 +1,26 @@
 // gfx950 kernels of the Born-rule probability path.
 //
 // One workgroup (four wave64s) owns one output bitstring b at a time:
-//   1. Raw Estimate: every lane draws trajectories (Philox4x32-10 words fed to
-//      the next-selected-gate inverse-transform table, Sec. III-B Eq. 10-12),
-//      reduces each to its flip-pattern key and adds its phase i^e to a
-//      Gaussian-integer counter in an LDS hash keyed by the pattern (the
-//      determinant table of Sec. IV-B).  Trajectories with no d_1 choice
-//      (the common case at small angles) are counted with one ballot per wave.
+//   1. Raw Estimate: trajectories are drawn in batches (Philox4x32-10 words
+//      fed to the next-selected-gate inverse-transform table, Sec. III-B
+//      Eq. 10-12).  The first draw of a sample decides whether it selects any
+//      d_1 branch; only those samples (about a third at small angles) are
+//      queued and drawn to the end by the whole workgroup.  Each is reduced to
+//      its flip-pattern key and adds its phase i^e to a Gaussian-integer
+//      counter in an LDS hash keyed by the pattern (the determinant table of
+//      Sec. IV-B); samples with no d_1 choice are counted once per batch.
 //      Exact: the keys and weights come from the plan's shared term list.
-//   2. The distinct keys are sorted, and each is evaluated by a group of G
-//      lanes (G >= eta, one row of the eta x eta submatrix per lane): the row
-//      is composed by the low-rank update of Sec. IV-B Eq. 19 (two-layer form
-//      for L = 2), then an LU with partial pivoting runs in registers with the
-//      pivot row broadcast through LDS; det = sign * prod(pivots) in FP64.
-//   3. weight * det is summed in a fixed order, so results are bitwise
-//      reproducible, and p_b = |A_b|^2.
+//   2. Every distinct key is evaluated.  LU path: a group of G lanes
+//      (G >= eta, one row of the eta x eta submatrix per lane) composes the
+//      rows by the low-rank update of Sec. IV-B Eq. 19 (two-layer form for
+//      L = 2) and runs an LU with partial pivoting in registers, the pivot
+//      row broadcast through LDS; det = sign * prod(pivots) in FP64.
+//      Determinant-lemma path (one CPhase layer): det M_N = det M_0 *
+//      det(I - 2 H[N, N]) with H formed once per bitstring; small patterns
+//      take one lane each.
+//   3. weight * det is summed exactly in 128-bit fixed point, so results are
+//      bitwise reproducible whatever the order of the entries, and
+//      p_b = |A_b|^2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -442,44 +448,130 @@ __device__ __forceinline__ double2 ordered_sum(const double2 *out, int cnt, doub
     return r;
 }
 
-// Fixed-order sum over the sorted entries e < nl of the values evaluate()
-// left in their slots (re in hkey, im in hcnt).  Result valid in every thread.
-__device__ __forceinline__ double2 ordered_sum_slots(const RawSmem &s, int nl) {
+// ---------------------------------------------------------------------------
+// Order-independent summation of the entries' values.  The slots an entry
+// lands in depend on the order of insertion, so the values are added as
+// 128-bit fixed-point integers (exact, hence associative) relative to the
+// largest binary exponent among them: the entry with that exponent is scaled
+// to < 2^115, leaving 12 bits of headroom for up to 2^11 entries; parts below
+// 2^-115 of it are truncated.  Every pass over the same entries therefore
+// gives the same double, whatever the slot and thread assignment.
+// ---------------------------------------------------------------------------
+struct Fix128 {
+    uint64_t lo = 0;
+    int64_t hi = 0;
+};
+
+__device__ __forceinline__ void fix_add(Fix128 &a, uint64_t lo, int64_t hi) {
+    const uint64_t l = a.lo + lo;
+    a.hi += hi + (l < a.lo ? 1 : 0);
+    a.lo = l;
+}
+
+// Exponent field of v (subnormals and zero count as 1 and 0).
+__device__ __forceinline__ int exp_field(double v) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    const int ex = (int)((bits >> 52) & 0x7FF);
+    return ex ? ex : ((bits << 1) ? 1 : 0);
+}
+
+// a += v * 2^(1137 - emax), v's exponent field <= emax, truncated toward zero.
+__device__ __forceinline__ void fix_add_double(Fix128 &a, double v, int emax) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    int ex = (int)((bits >> 52) & 0x7FF);
+    uint64_t M = bits & ((1ull << 52) - 1);
+    if (ex == 0) {
+        if (M == 0) return;
+        ex = 1;
+    } else {
+        M |= 1ull << 52;
+    }
+    const int shift = ex - emax + 62;   // <= 62
+    uint64_t lo, hi;
+    if (shift < 0) {
+        if (shift <= -64) return;
+        lo = M >> (-shift);
+        hi = 0;
+    } else {
+        lo = M << shift;
+        hi = shift ? (M >> (64 - shift)) : 0;
+    }
+    if (bits >> 63) {
+        lo = ~lo + 1;
+        hi = ~hi + (lo == 0 ? 1 : 0);
+    }
+    fix_add(a, lo, (int64_t)hi);
+}
+
+__device__ __forceinline__ double fix_to_double(const Fix128 &a, int emax) {
+    const double v = (double)a.hi * 18446744073709551616.0 + (double)a.lo;
+    return ldexp(v, emax - 1137);
+}
+
+__device__ __forceinline__ void fix_wave_sum(Fix128 &a) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t lo = __shfl_xor((unsigned long long)a.lo, off, 64);
+        const int64_t hi = __shfl_xor((long long)a.hi, off, 64);
+        fix_add(a, lo, hi);
+    }
+}
+
+// Sum of the values that evaluation left in the slots of the entries e < nl
+// (re in hkey, im in hcnt); s_emax is LDS scratch cleared by gather_list.
+// Result valid in every thread.  Whole workgroup.
+__device__ __forceinline__ double2 exact_sum_slots(const RawSmem &s, int nl, int *s_emax) {
     const int tid = threadIdx.x;
-    const int chunk = (nl + kThreads - 1) / kThreads;
-    double2 acc = make_double2(0.0, 0.0);
-    const int lo = tid * chunk, hi = min(nl, lo + chunk);
-    for (int e = lo; e < hi; ++e) {
+    int em = 0;
+    for (int e = tid; e < nl; e += kThreads) {
         const uint16_t slot = s.list[e];
         if (slot >= kHashSlots) continue;
-        acc.x += __longlong_as_double((long long)s.hkey[slot]);
-        acc.y += *(const double *)&s.hcnt[slot];
+        em = max(em, max(exp_field(__longlong_as_double((long long)s.hkey[slot])),
+                         exp_field(*(const double *)&s.hcnt[slot])));
     }
-    s.red[tid] = acc;
-    __syncthreads();
 #pragma unroll
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            s.red[tid].x += s.red[tid + w].x;
-            s.red[tid].y += s.red[tid + w].y;
-        }
-        __syncthreads();
-    }
-    const double2 r = s.red[0];
+    for (int off = 32; off > 0; off >>= 1) em = max(em, __shfl_xor(em, off, 64));
+    if ((tid & 63) == 0 && em) atomicMax(s_emax, em);
     __syncthreads();
-    return r;
+    const int emax = *s_emax;
+    if (emax == 0) return make_double2(0.0, 0.0);
+    if (emax == 0x7FF) return make_double2(__longlong_as_double(0x7FF8000000000000ll), 0.0);
+    Fix128 re, im;
+    for (int e = tid; e < nl; e += kThreads) {
+        const uint16_t slot = s.list[e];
+        if (slot >= kHashSlots) continue;
+        fix_add_double(re, __longlong_as_double((long long)s.hkey[slot]), emax);
+        fix_add_double(im, *(const double *)&s.hcnt[slot], emax);
+    }
+    fix_wave_sum(re);
+    fix_wave_sum(im);
+    uint64_t *part = (uint64_t *)s.red;   // [wave][4]
+    if ((tid & 63) == 0) {
+        const int w = tid >> 6;
+        part[4 * w + 0] = re.lo;
+        part[4 * w + 1] = (uint64_t)re.hi;
+        part[4 * w + 2] = im.lo;
+        part[4 * w + 3] = (uint64_t)im.hi;
+    }
+    __syncthreads();
+    Fix128 R, I;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        fix_add(R, part[4 * w + 0], (int64_t)part[4 * w + 1]);
+        fix_add(I, part[4 * w + 2], (int64_t)part[4 * w + 3]);
+    }
+    __syncthreads();
+    return make_double2(fix_to_double(R, emax), fix_to_double(I, emax));
 }
 
-__device__ __forceinline__ uint64_t list_key(const RawSmem &s, uint16_t idx) {
-    return idx >= kHashSlots ? kEmptyKey : s.hkey[idx];
-}
-
-// Gathers the occupied slots of the hash (non-zero count) into s.list and
-// sorts them by key (keys are distinct), so every later pass over the entries
-// runs in a fixed order.  Returns the number of entries.
-__device__ __forceinline__ int prepare_list(const RawSmem &s, int *s_n) {
+// Gathers the occupied slots of the hash (non-zero count) into s.list, in no
+// particular order, and clears *s_emax.  Returns the number of entries.
+__device__ __forceinline__ int gather_list(const RawSmem &s, int *s_n, int *s_emax) {
     const int tid = threadIdx.x;
-    if (tid == 0) *s_n = 0;
+    if (tid == 0) {
+        *s_n = 0;
+        *s_emax = 0;
+    }
     __syncthreads();
     for (int i = tid; i < kHashSlots; i += kThreads) {
         if (s.hkey[i] != kEmptyKey && (s.hcnt[i].x != 0 || s.hcnt[i].y != 0)) {
@@ -488,27 +580,7 @@ __device__ __forceinline__ int prepare_list(const RawSmem &s, int *s_n) {
         }
     }
     __syncthreads();
-    const int nl = min(*s_n, kHashSlots);
-    int np = 1;
-    while (np < nl) np <<= 1;
-    for (int i = nl + tid; i < np; i += kThreads) s.list[i] = 0xFFFFu;
-    __syncthreads();
-    for (int size = 2; size <= np; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = tid; i < (np >> 1); i += kThreads) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const uint16_t a = s.list[lo], b = s.list[hi];
-                if ((list_key(s, a) > list_key(s, b)) == asc) {
-                    s.list[lo] = b;
-                    s.list[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    return nl;
+    return min(*s_n, kHashSlots);
 }
 
 // Empties the table and re-reserves the slot of the empty flip pattern.
@@ -518,6 +590,8 @@ constexpr int kSamplesPerThread = 4;
 constexpr uint32_t kBatch = (uint32_t)kThreads * kSamplesPerThread;
 constexpr int kFlushAt = (3 * kHashSlots) / 4;
 static_assert(kBatch + 1 <= (uint32_t)kFlushAt, "a fresh table must take a whole batch");
+static_assert(kBatch * 4 <= (uint32_t)kHashSlots * 2 && kBatch * 4 <= (uint32_t)kThreads * 16,
+              "the sample queues live in the list and in the pivot scratch");
 
 // Sampler position of one workgroup; every thread holds the same values.
 struct Sampler {
@@ -583,44 +657,41 @@ __device__ __forceinline__ bool draw_trajectory(const DevPlan &p, const RawSmem 
 // samples, reducing each to its flip-pattern key in the LDS hash, until either
 // all t samples are in (returns true) or the next batch could push the table
 // past kFlushAt slots (returns false; that batch is drawn again after the
-// table has been evaluated and cleared).  The bound uses the exact count of
-// slots in use plus the batch's non-empty samples, so the stopping points
-// depend only on the samples and every pass over the same bitstring empties
-// the table at the same samples.  One barrier per batch: counts of the
-// batch's non-empty samples and of the slots each batch claims live in three
-// rotating LDS counters each (cnt[0..2], cnt[3..5]), read only after the
-// barrier that follows their last update and cleared two batches before
-// their next use.  Whole workgroup; s.T / s.gkey / s.gneg loaded; the table
+// table has been evaluated and cleared).  A batch runs in two phases: every
+// thread takes the first draw of kSamplesPerThread samples, which decides
+// whether the sample sets any gate at all (u < T[0][k-1]); the indices of the
+// samples that do are queued in LDS, and after the barrier the workgroup
+// draws those trajectories to the end and inserts them, so the long draws
+// are spread over all lanes.  The bound uses the exact count of slots in use
+// plus the batch's non-empty samples, so the stopping points depend only on
+// the samples and every pass over the same bitstring empties the table at the
+// same samples.  Counts of the batch's non-empty samples (which are also the
+// queue positions) and of the slots each batch claims live in three rotating
+// LDS counters each (cnt[0..2], cnt[3..5]), read only after the barrier that
+// follows their last update and cleared two batches before their next use;
+// the queue alternates between two buffers (the list and pivot scratch, free
+// while sampling).  Whole workgroup; s.T / s.gkey / s.gneg loaded; the table
 // cleared (clear_table) before the first call and between calls.
 __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSmem &s, int *cnt,
                                                    uint32_t slot0, int64_t b, uint32_t t, uint32_t k0,
                                                    uint32_t k1, Sampler &st) {
     const int tid = threadIdx.x;
-    const bool leader = (tid & 63) == 0;
+    const int lane = tid & 63;
     const uint32_t blo = (uint32_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
+    const uint32_t any = p.k > 0 ? s.T[p.k - 1] : 0u;
     int *pend = cnt, *added = cnt + 3;
     for (; st.next < t; st.next += kBatch, ++st.j) {
-        uint64_t key[kSamplesPerThread];
-        uint32_t e[kSamplesPerThread];
-        bool live[kSamplesPerThread], empty[kSamplesPerThread];
-        uint4 r[kSamplesPerThread];
+        uint32_t *queue = (st.j & 1) ? (uint32_t *)s.piv : (uint32_t *)s.list;
 #pragma unroll
         for (int q = 0; q < kSamplesPerThread; ++q) {
             const uint32_t smp = st.next + (uint32_t)(q * kThreads + tid);
-            live[q] = smp < t;
-            r[q] = philox10(make_uint4(smp, 0u, blo, bhi), k0, k1);
+            const bool hit = smp < t && philox10(make_uint4(smp, 0u, blo, bhi), k0, k1).x < any;
+            const uint64_t ball = __ballot(hit);
+            int at = 0;
+            if (lane == 0 && ball) at = atomicAdd(&pend[st.j % 3], (int)__popcll(ball));
+            at = __shfl(at, 0, 64);
+            if (hit) queue[at + (int)__popcll(ball & ((1ull << lane) - 1))] = smp;
         }
-        int nonempty = 0;
-#pragma unroll
-        for (int q = 0; q < kSamplesPerThread; ++q) {
-            const uint32_t smp = st.next + (uint32_t)(q * kThreads + tid);
-            empty[q] = true;
-            key[q] = 0;
-            e[q] = 0;
-            if (live[q] && p.k > 0) empty[q] = draw_trajectory(p, s, smp, r[q], blo, bhi, k0, k1, key[q], e[q]);
-            nonempty += (int)__popcll(__ballot(live[q] && !empty[q]));
-        }
-        if (leader && nonempty) atomicAdd(&pend[st.j % 3], nonempty);
         __syncthreads();
         const int pending = pend[st.j % 3];
         st.claimed += added[(st.j + 2) % 3];
@@ -629,31 +700,33 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
             added[(st.j + 1) % 3] = 0;
         }
         if (st.claimed > 1 && st.claimed + pending > kFlushAt) return false;
-        int empties = 0, fresh = 0;
-#pragma unroll
-        for (int q = 0; q < kSamplesPerThread; ++q) {
-            empties += (int)__popcll(__ballot(live[q] && empty[q]));
-            if (live[q] && !empty[q]) {
-                uint32_t slot = hash_slot(key[q]);
-                while (true) {
-                    const unsigned long long prev =
-                        atomicCAS((unsigned long long *)&s.hkey[slot], (unsigned long long)kEmptyKey,
-                                  (unsigned long long)key[q]);
-                    if (prev == kEmptyKey) {
-                        ++fresh;
-                        break;
-                    }
-                    if (prev == key[q]) break;
-                    slot = (slot + 1) & (kHashSlots - 1);
-                }
-                const uint32_t eq = e[q] & 3;
-                if (eq == 0) atomicAdd(&s.hcnt[slot].x, 1);
-                else if (eq == 1) atomicAdd(&s.hcnt[slot].y, 1);
-                else if (eq == 2) atomicAdd(&s.hcnt[slot].x, -1);
-                else atomicAdd(&s.hcnt[slot].y, -1);
-            }
+        if (tid == 0) {
+            const int live = (int)min((uint32_t)kBatch, t - st.next);
+            if (live > pending) atomicAdd(&s.hcnt[slot0].x, live - pending);
         }
-        if (leader && empties) atomicAdd(&s.hcnt[slot0].x, empties);
+        int fresh = 0;
+        for (int i = tid; i < pending; i += kThreads) {
+            const uint32_t smp = queue[i];
+            uint64_t key;
+            uint32_t e;
+            draw_trajectory(p, s, smp, philox10(make_uint4(smp, 0u, blo, bhi), k0, k1), blo, bhi, k0, k1, key, e);
+            uint32_t slot = hash_slot(key);
+            while (true) {
+                const unsigned long long prev = atomicCAS((unsigned long long *)&s.hkey[slot],
+                                                          (unsigned long long)kEmptyKey, (unsigned long long)key);
+                if (prev == kEmptyKey) {
+                    ++fresh;
+                    break;
+                }
+                if (prev == key) break;
+                slot = (slot + 1) & (kHashSlots - 1);
+            }
+            e &= 3;
+            if (e == 0) atomicAdd(&s.hcnt[slot].x, 1);
+            else if (e == 1) atomicAdd(&s.hcnt[slot].y, 1);
+            else if (e == 2) atomicAdd(&s.hcnt[slot].x, -1);
+            else atomicAdd(&s.hcnt[slot].y, -1);
+        }
         if (fresh) atomicAdd(&added[st.j % 3], fresh);
     }
     return true;
@@ -790,20 +863,33 @@ struct LemmaBits {
 // keys), partial pivoting by row swaps (largest |a|^2, lowest row on ties);
 // rows are not normalised until the end, so each step is one multiplier pass
 // by wave 0 and one update pass by the workgroup.  Then X = M_0^-1 A1[R, act]
-// (in the hash counts) and H = Phi0[act, :] X into sH.
+// (after V in the hash keys) and H = Phi0[act, :] X into sH.  When
+// m * |act| <= 512 the operands A1[R, act] and Phi0[act, :] are first copied
+// to the hash counts (their loads overlap the elimination).
 template <int G>
 __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem &s, double2 *sH,
                                                  int *s_flag, double2 *s_det, Work &wk) {
     const int tid = threadIdx.x, m = p.m, n = p.n, kb = p.keybits;
     double2 *W = s.sP;                        // m x G, left half
     double2 *V = (double2 *)s.hkey;           // m x G, right half -> M_0^-1
+    double2 *X = V + G * G;                   // m x kb
     double2 *mult = s.piv;                    // [G] multipliers of the current step
     double2 *pinv = s.piv + G;                // [G] inverse pivots
-    double2 *X = (double2 *)s.hcnt;           // m x kb
+    const bool staged = m * kb <= 512;
+    double2 *A1s = (double2 *)s.hcnt;         // m x kb: A1[R, act]
+    double2 *Phs = A1s + 512;                 // kb x m: Phi0[act, :]
     for (int i = tid; i < m * G; i += kThreads) {
         const int r = i / G, c = i % G;
         W[i] = p.P[(size_t)s.Rb[r] * G + c];
         V[i] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    if (staged) {
+        for (int i = tid; i < m * kb; i += kThreads) {
+            const int l = i / kb, q = i % kb;
+            A1s[i] = p.A1[(size_t)s.Rb[l] * n + p.keymode[q]];
+            const int q2 = i / m, j = i % m;
+            Phs[i] = p.Phi0[(size_t)p.keymode[q2] * G + j];
+        }
     }
     if (tid == 0) {
         *s_flag = 1;
@@ -922,18 +1008,26 @@ __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem
     // X = M_0^-1 A1[R, act]
     for (int i = tid; i < m * kb; i += kThreads) {
         const int j = i / kb, q = i % kb;
-        const int c = p.keymode[q];
         double2 acc = make_double2(0.0, 0.0);
-        for (int l = 0; l < m; ++l) acc = c_fma(acc, V[j * G + l], p.A1[(size_t)s.Rb[l] * n + c]);
+        if (staged) {
+            for (int l = 0; l < m; ++l) acc = c_fma(acc, V[j * G + l], A1s[l * kb + q]);
+        } else {
+            const int c = p.keymode[q];
+            for (int l = 0; l < m; ++l) acc = c_fma(acc, V[j * G + l], p.A1[(size_t)s.Rb[l] * n + c]);
+        }
         X[j * kb + q] = acc;
     }
     __syncthreads();
     // H = Phi0[act, :] X
     for (int i = tid; i < kb * kb; i += kThreads) {
         const int q = i / kb, q2 = i % kb;
-        const int c = p.keymode[q];
         double2 acc = make_double2(0.0, 0.0);
-        for (int j = 0; j < m; ++j) acc = c_fma(acc, p.Phi0[(size_t)c * G + j], X[j * kb + q2]);
+        if (staged) {
+            for (int j = 0; j < m; ++j) acc = c_fma(acc, Phs[q * m + j], X[j * kb + q2]);
+        } else {
+            const int c = p.keymode[q];
+            for (int j = 0; j < m; ++j) acc = c_fma(acc, p.Phi0[(size_t)c * G + j], X[j * kb + q2]);
+        }
         sH[q * kb + q2] = acc;
     }
     __syncthreads();
@@ -1019,7 +1113,8 @@ __device__ __forceinline__ double2 lemma_small_det(uint64_t key, const double2 *
 // nterm[2] accumulates the executed FP64-equivalent FLOPs.
 template <int G>
 __device__ __forceinline__ double2 sum_entries_lemma(const DevPlan &p, const RawSmem &s, int nl,
-                                                     const double2 *sH, const LemmaBits &lb, Work &wk) {
+                                                     const double2 *sH, const LemmaBits &lb, Work &wk,
+                                                     int *s_emax) {
     const int tid = threadIdx.x;
     const int lane = tid % G, grp = tid / G;
     constexpr int NG = kThreads / G;
@@ -1093,14 +1188,15 @@ __device__ __forceinline__ double2 sum_entries_lemma(const DevPlan &p, const Raw
     for (int e = tid; e < nl; e += kThreads) s.list[e] &= 0x7FFFu;
     __syncthreads();
     if (tid == 0) wk.terms += (unsigned)nl;
-    return ordered_sum_slots(s, nl);
+    return exact_sum_slots(s, nl, s_emax);
 }
 
-// Sum over the sorted entries of count * det, in a fixed order.  Each group
-// evaluates entries e = grp, grp + NG, ...; the product is left in the
-// entry's slot and summed in sorted order by ordered_sum_slots.
+// Sum over the entries of count * det.  Each group evaluates entries
+// e = grp, grp + NG, ...; the product is left in the entry's slot and summed
+// by exact_sum_slots.
 template <int G, bool MIXED, bool STAGE>
-__device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &s, int nl, Work &wk) {
+__device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &s, int nl, Work &wk,
+                                               int *s_emax) {
     const int tid = threadIdx.x;
     const int lane = tid % G, grp = tid / G;
     constexpr int NG = kThreads / G;
@@ -1123,7 +1219,7 @@ __device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &
     }
     __syncthreads();
     if (tid == 0) wk.terms += (unsigned)nl;
-    return ordered_sum_slots(s, nl);
+    return exact_sum_slots(s, nl, s_emax);
 }
 
 __device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) {
@@ -1148,7 +1244,7 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
                unsigned long long *nterm) {
     constexpr bool STAGE = KIND == 1;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n, s_flag;
+    __shared__ int s_ok, s_n, s_flag, s_emax;
     __shared__ int s_cnt[6];
     __shared__ double2 s_det;
     const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
@@ -1178,10 +1274,10 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
         clear_table(s, s_cnt, slot0, st);
         while (true) {
             const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = prepare_list(s, &s_n);
+            const int nl = gather_list(s, &s_n, &s_emax);
             double2 part;
-            if constexpr (KIND == 2) part = sum_entries_lemma<G>(p, s, nl, sH, lb, wk);
-            else part = sum_entries<G, MIXED, STAGE>(p, s, nl, wk);
+            if constexpr (KIND == 2) part = sum_entries_lemma<G>(p, s, nl, sH, lb, wk, &s_emax);
+            else part = sum_entries<G, MIXED, STAGE>(p, s, nl, wk, &s_emax);
             total.x += part.x;
             total.y += part.y;
             if (done) break;
@@ -1374,7 +1470,7 @@ __global__ void __launch_bounds__(kThreads)
 k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
                    const double *__restrict__ g, double2 *part, GradLayout lay) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n;
+    __shared__ int s_ok, s_n, s_emax;
     __shared__ int s_cnt[6];
     const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
     constexpr int NG = kThreads / G;
@@ -1396,9 +1492,9 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
         clear_table(s, s_cnt, slot0, st);
         while (true) {
             const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = prepare_list(s, &s_n);
+            const int nl = gather_list(s, &s_n, &s_emax);
             Work unused;
-            const double2 part_sum = sum_entries<G, MIXED, false>(p, s, nl, unused);
+            const double2 part_sum = sum_entries<G, MIXED, false>(p, s, nl, unused, &s_emax);
             total.x += part_sum.x;
             total.y += part_sum.y;
             if (done) break;
@@ -1416,7 +1512,7 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
         clear_table(s, s_cnt, slot0, st);
         while (true) {
             const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = prepare_list(s, &s_n);
+            const int nl = gather_list(s, &s_n, &s_emax);
             for (int e = grp; e < nl; e += NG) {
                 const uint16_t slot = s.list[e];
                 const int2 c = s.hcnt[slot];
