@@ -290,6 +290,7 @@ __device__ __forceinline__ double2 lu_det(double2 (&a)[G], int m, int lane, doub
     return (inversions & 1) ? make_double2(-det.x, -det.y) : det;
 }
 
+
 struct RawSmem {
     uint64_t *hkey;
     int2 *hcnt;
@@ -297,9 +298,9 @@ struct RawSmem {
     double2 *red;
     uint16_t *list;
     uint8_t *Rb;
-    uint64_t *gkey;
-    uint8_t *gneg;
-    uint32_t *T;
+    uint64_t *gkey;   // [k] key contribution of gate j, bit 63 = theta_j < 0
+    uint32_t *T;      // [k][kpad] sampling table, row a: 0 before a, all-ones from k on
+    int kpad;         // row stride of T, a multiple of 16
     // LDS copies for one-layer circuits (STAGE): P rows of the bitstring
     // (G x G FP64), its A1 rows (G x n) and Phi0 (n x G), FP64 or FP32 (MIXED)
     double2 *sP;
@@ -315,11 +316,13 @@ __host__ __device__ __forceinline__ size_t stage_bytes(int n, int G, bool mixed)
     return (size_t)G * G * 16 + 2 * (size_t)n * G * el;
 }
 
+__host__ __device__ __forceinline__ int table_stride(int k) { return (k + 15) & ~15; }
+
 // Bytes of dynamic LDS the per-bitstring kernels carve (see carve_raw).
 __host__ __device__ __forceinline__ size_t raw_lds_bytes(int kk, int n, int G, bool mixed, bool stage) {
     const size_t k = (size_t)kk;
-    const size_t base = align16((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + k * 8 +
-                                ((k + 7) & ~(size_t)7) + k * k * 4);
+    const size_t base = align16((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + k * 8) +
+                        k * (size_t)table_stride(kk) * 4;
     return base + (stage ? stage_bytes(n, G, mixed) : 0);
 }
 
@@ -332,10 +335,10 @@ __device__ __forceinline__ RawSmem carve_raw(unsigned char *smem, int k, int n, 
     s.list = (uint16_t *)(s.red + kThreads);
     s.Rb = (uint8_t *)(s.list + kHashSlots);
     s.gkey = (uint64_t *)(s.Rb + 64);
-    s.gneg = (uint8_t *)(s.gkey + k);
-    s.T = (uint32_t *)(s.gneg + ((k + 7) & ~7));
-    unsigned char *st = smem + align16((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 +
-                                       (size_t)k * 8 + (((size_t)k + 7) & ~(size_t)7) + (size_t)k * k * 4);
+    s.kpad = table_stride(k);
+    const size_t toff = align16((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + (size_t)k * 8);
+    s.T = (uint32_t *)(smem + toff);
+    unsigned char *st = smem + toff + (size_t)k * s.kpad * 4;
     s.sP = (double2 *)st;
     s.sA1 = (void *)(st + (size_t)G * G * 16);
     s.sPhi = (void *)(st + (size_t)G * G * 16 + (size_t)n * G * (mixed ? 8 : 16));
@@ -419,7 +422,11 @@ __device__ __forceinline__ bool load_bitstring(const DevPlan &p, const uint64_t 
         *s_ok = ok;
     }
     __syncthreads();
-    return *s_ok != 0;
+    const bool ok = *s_ok != 0;
+    // every thread has read the flag (and may leave the bitstring without
+    // another barrier) before thread 0 can overwrite it for the next one
+    __syncthreads();
+    return ok;
 }
 
 // Fixed-order sum of out[0..cnt): each thread adds a contiguous chunk, then a
@@ -450,128 +457,186 @@ __device__ __forceinline__ double2 ordered_sum(const double2 *out, int cnt, doub
 
 // ---------------------------------------------------------------------------
 // Order-independent summation of the entries' values.  The slots an entry
-// lands in depend on the order of insertion, so the values are added as
-// 128-bit fixed-point integers (exact, hence associative) relative to the
-// largest binary exponent among them: the entry with that exponent is scaled
-// to < 2^115, leaving 12 bits of headroom for up to 2^11 entries; parts below
-// 2^-115 of it are truncated.  Every pass over the same entries therefore
-// gives the same double, whatever the slot and thread assignment.
+// lands in depend on the order of insertion, so the values count * det are
+// added as 192-bit two's-complement fixed-point integers in units of 2^-158
+// (exact, hence associative).  Every determinant is that of a submatrix of a
+// unitary matrix, so |det| <= 1, and the counts of one bitstring add up to at
+// most t < 2^31 in modulus: the running sum stays below 2^190 units.  Parts
+// below 2^-158 are truncated toward zero.  Every pass over the same entries
+// therefore gives the same double, whatever the slot, thread and table
+// assignment.
 // ---------------------------------------------------------------------------
-struct Fix128 {
-    uint64_t lo = 0;
-    int64_t hi = 0;
+struct Fix192 {
+    uint64_t w0 = 0, w1 = 0;
+    int64_t w2 = 0;
 };
 
-__device__ __forceinline__ void fix_add(Fix128 &a, uint64_t lo, int64_t hi) {
-    const uint64_t l = a.lo + lo;
-    a.hi += hi + (l < a.lo ? 1 : 0);
-    a.lo = l;
+struct FixAcc {
+    Fix192 re, im;
+    bool bad = false;   // a NaN, an infinity or a value outside the range was added
+};
+
+__device__ __forceinline__ void fix_add(Fix192 &a, uint64_t x0, uint64_t x1, int64_t x2) {
+    const uint64_t s0 = a.w0 + x0;
+    const uint64_t c0 = s0 < a.w0 ? 1 : 0;
+    const uint64_t s1 = a.w1 + x1;
+    const uint64_t c1 = s1 < a.w1 ? 1 : 0;
+    const uint64_t s1c = s1 + c0;
+    const uint64_t c2 = s1c < s1 ? 1 : 0;
+    a.w0 = s0;
+    a.w1 = s1c;
+    a.w2 += x2 + (int64_t)(c1 + c2);
 }
 
-// Exponent field of v (subnormals and zero count as 1 and 0).
-__device__ __forceinline__ int exp_field(double v) {
+// a += v * 2^158, truncated toward zero.
+__device__ __forceinline__ void fix_add_double(Fix192 &a, bool &bad, double v) {
     const uint64_t bits = (uint64_t)__double_as_longlong(v);
     const int ex = (int)((bits >> 52) & 0x7FF);
-    return ex ? ex : ((bits << 1) ? 1 : 0);
-}
-
-// a += v * 2^(1137 - emax), v's exponent field <= emax, truncated toward zero.
-__device__ __forceinline__ void fix_add_double(Fix128 &a, double v, int emax) {
-    const uint64_t bits = (uint64_t)__double_as_longlong(v);
-    int ex = (int)((bits >> 52) & 0x7FF);
-    uint64_t M = bits & ((1ull << 52) - 1);
-    if (ex == 0) {
-        if (M == 0) return;
-        ex = 1;
-    } else {
-        M |= 1ull << 52;
+    if (ex == 0x7FF) {
+        bad = true;
+        return;
     }
-    const int shift = ex - emax + 62;   // <= 62
-    uint64_t lo, hi;
+    if (ex == 0) return;   // |v| < 2^-1022
+    const uint64_t M = (bits & ((1ull << 52) - 1)) | (1ull << 52);
+    const int shift = ex - 917;   // v * 2^158 = M * 2^shift
+    if (shift > 136) {            // |v| >= 2^32: outside the documented range
+        bad = true;
+        return;
+    }
+    if (shift <= -64) return;
+    uint64_t x0 = 0, x1 = 0, x2 = 0;
     if (shift < 0) {
-        if (shift <= -64) return;
-        lo = M >> (-shift);
-        hi = 0;
+        x0 = M >> (-shift);
+    } else if (shift < 64) {
+        x0 = M << shift;
+        x1 = shift ? (M >> (64 - shift)) : 0;
+    } else if (shift < 128) {
+        const int q = shift - 64;
+        x1 = M << q;
+        x2 = q ? (M >> (64 - q)) : 0;
     } else {
-        lo = M << shift;
-        hi = shift ? (M >> (64 - shift)) : 0;
+        x2 = M << (shift - 128);
     }
     if (bits >> 63) {
-        lo = ~lo + 1;
-        hi = ~hi + (lo == 0 ? 1 : 0);
+        x0 = ~x0 + 1;
+        const uint64_t c0 = x0 == 0 ? 1 : 0;
+        x1 = ~x1 + c0;
+        const uint64_t c1 = (c0 && x1 == 0) ? 1 : 0;
+        x2 = ~x2 + c1;
     }
-    fix_add(a, lo, (int64_t)hi);
+    fix_add(a, x0, x1, (int64_t)x2);
 }
 
-__device__ __forceinline__ double fix_to_double(const Fix128 &a, int emax) {
-    const double v = (double)a.hi * 18446744073709551616.0 + (double)a.lo;
-    return ldexp(v, emax - 1137);
+// Rounded to double through the magnitude (no cancellation between words).
+__device__ __forceinline__ double fix_to_double(Fix192 a) {
+    const bool neg = a.w2 < 0;
+    if (neg) {
+        uint64_t x0 = ~a.w0 + 1;
+        const uint64_t c0 = x0 == 0 ? 1 : 0;
+        uint64_t x1 = ~a.w1 + c0;
+        const uint64_t c1 = (c0 && x1 == 0) ? 1 : 0;
+        a.w0 = x0;
+        a.w1 = x1;
+        a.w2 = (int64_t)(~(uint64_t)a.w2 + c1);
+    }
+    const double m = ((double)(uint64_t)a.w2 * 18446744073709551616.0 + (double)a.w1) * 18446744073709551616.0 +
+                     (double)a.w0;
+    const double v = ldexp(m, -158);
+    return neg ? -v : v;
 }
 
-__device__ __forceinline__ void fix_wave_sum(Fix128 &a) {
+__device__ __forceinline__ void fix_wave_sum(Fix192 &a) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t lo = __shfl_xor((unsigned long long)a.lo, off, 64);
-        const int64_t hi = __shfl_xor((long long)a.hi, off, 64);
-        fix_add(a, lo, hi);
+        const uint64_t x0 = __shfl_xor((unsigned long long)a.w0, off, 64);
+        const uint64_t x1 = __shfl_xor((unsigned long long)a.w1, off, 64);
+        const int64_t x2 = __shfl_xor((long long)a.w2, off, 64);
+        fix_add(a, x0, x1, x2);
     }
 }
 
-// Sum of the values that evaluation left in the slots of the entries e < nl
-// (re in hkey, im in hcnt); s_emax is LDS scratch cleared by gather_list.
-// Result valid in every thread.  Whole workgroup.
-__device__ __forceinline__ double2 exact_sum_slots(const RawSmem &s, int nl, int *s_emax) {
+// Per-bitstring sum kept in LDS between tables, as 7 words: the real and
+// imaginary Fix192 (w0, w1, w2 each) and a flag for bad values.
+constexpr int kAccWords = 7;
+
+__device__ __forceinline__ void acc_clear(uint64_t *sacc) {
+    if (threadIdx.x < kAccWords) sacc[threadIdx.x] = 0;
+}
+
+// *sacc += the values that evaluation left in the slots of the entries e < nl
+// (re in hkey, im in hcnt).  Whole workgroup; uses s.red as scratch.
+__device__ __forceinline__ void accumulate_slots(const RawSmem &s, int nl, uint64_t *sacc) {
     const int tid = threadIdx.x;
-    int em = 0;
+    FixAcc acc;
     for (int e = tid; e < nl; e += kThreads) {
         const uint16_t slot = s.list[e];
         if (slot >= kHashSlots) continue;
-        em = max(em, max(exp_field(__longlong_as_double((long long)s.hkey[slot])),
-                         exp_field(*(const double *)&s.hcnt[slot])));
+        fix_add_double(acc.re, acc.bad, __longlong_as_double((long long)s.hkey[slot]));
+        fix_add_double(acc.im, acc.bad, *(const double *)&s.hcnt[slot]);
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) em = max(em, __shfl_xor(em, off, 64));
-    if ((tid & 63) == 0 && em) atomicMax(s_emax, em);
-    __syncthreads();
-    const int emax = *s_emax;
-    if (emax == 0) return make_double2(0.0, 0.0);
-    if (emax == 0x7FF) return make_double2(__longlong_as_double(0x7FF8000000000000ll), 0.0);
-    Fix128 re, im;
-    for (int e = tid; e < nl; e += kThreads) {
-        const uint16_t slot = s.list[e];
-        if (slot >= kHashSlots) continue;
-        fix_add_double(re, __longlong_as_double((long long)s.hkey[slot]), emax);
-        fix_add_double(im, *(const double *)&s.hcnt[slot], emax);
-    }
-    fix_wave_sum(re);
-    fix_wave_sum(im);
-    uint64_t *part = (uint64_t *)s.red;   // [wave][4]
+    fix_wave_sum(acc.re);
+    fix_wave_sum(acc.im);
+    const bool bad = __ballot(acc.bad) != 0;
+    uint64_t *part = (uint64_t *)s.red;   // [wave][7]
     if ((tid & 63) == 0) {
-        const int w = tid >> 6;
-        part[4 * w + 0] = re.lo;
-        part[4 * w + 1] = (uint64_t)re.hi;
-        part[4 * w + 2] = im.lo;
-        part[4 * w + 3] = (uint64_t)im.hi;
+        uint64_t *q = part + kAccWords * (tid >> 6);
+        q[0] = acc.re.w0;
+        q[1] = acc.re.w1;
+        q[2] = (uint64_t)acc.re.w2;
+        q[3] = acc.im.w0;
+        q[4] = acc.im.w1;
+        q[5] = (uint64_t)acc.im.w2;
+        q[6] = bad ? 1u : 0u;
     }
     __syncthreads();
-    Fix128 R, I;
+    if (tid == 0) {
+        Fix192 R, I;
+        R.w0 = sacc[0];
+        R.w1 = sacc[1];
+        R.w2 = (int64_t)sacc[2];
+        I.w0 = sacc[3];
+        I.w1 = sacc[4];
+        I.w2 = (int64_t)sacc[5];
+        uint64_t b = sacc[6];
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) {
-        fix_add(R, part[4 * w + 0], (int64_t)part[4 * w + 1]);
-        fix_add(I, part[4 * w + 2], (int64_t)part[4 * w + 3]);
+        for (int w = 0; w < kThreads / 64; ++w) {
+            const uint64_t *q = part + kAccWords * w;
+            fix_add(R, q[0], q[1], (int64_t)q[2]);
+            fix_add(I, q[3], q[4], (int64_t)q[5]);
+            b |= q[6];
+        }
+        sacc[0] = R.w0;
+        sacc[1] = R.w1;
+        sacc[2] = (uint64_t)R.w2;
+        sacc[3] = I.w0;
+        sacc[4] = I.w1;
+        sacc[5] = (uint64_t)I.w2;
+        sacc[6] = b;
     }
     __syncthreads();
-    return make_double2(fix_to_double(R, emax), fix_to_double(I, emax));
+}
+
+// The accumulated sum as doubles (call after the last accumulate_slots).
+__device__ __forceinline__ double2 acc_value(const uint64_t *sacc) {
+    if (sacc[6]) {
+        const double nan = __longlong_as_double(0x7FF8000000000000ll);
+        return make_double2(nan, nan);
+    }
+    Fix192 R, I;
+    R.w0 = sacc[0];
+    R.w1 = sacc[1];
+    R.w2 = (int64_t)sacc[2];
+    I.w0 = sacc[3];
+    I.w1 = sacc[4];
+    I.w2 = (int64_t)sacc[5];
+    return make_double2(fix_to_double(R), fix_to_double(I));
 }
 
 // Gathers the occupied slots of the hash (non-zero count) into s.list, in no
-// particular order, and clears *s_emax.  Returns the number of entries.
-__device__ __forceinline__ int gather_list(const RawSmem &s, int *s_n, int *s_emax) {
+// particular order.  Returns the number of entries.
+__device__ __forceinline__ int gather_list(const RawSmem &s, int *s_n) {
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        *s_n = 0;
-        *s_emax = 0;
-    }
+    if (tid == 0) *s_n = 0;
     __syncthreads();
     for (int i = tid; i < kHashSlots; i += kThreads) {
         if (s.hkey[i] != kEmptyKey && (s.hcnt[i].x != 0 || s.hcnt[i].y != 0)) {
@@ -627,6 +692,7 @@ __device__ __forceinline__ bool draw_trajectory(const DevPlan &p, const RawSmem 
     key = 0;
     e = 0;
     bool empty = true;
+    const int kp = s.kpad, nb = kp >> 4;
     uint32_t blk = 0, d = 0;
     int a = 0;
     while (a < k) {
@@ -637,18 +703,27 @@ __device__ __forceinline__ bool draw_trajectory(const DevPlan &p, const RawSmem 
         const uint32_t w = d & 3;
         const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
         ++d;
-        const uint32_t *Ta = s.T + a * k;
-        if (!(u < Ta[k - 1])) break;
-        int lo = a, hi = k - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (u < Ta[mid]) hi = mid;
-            else lo = mid + 1;
-        }
-        key ^= s.gkey[lo];
-        e += 1u + 2u * s.gneg[lo];
+        // The next selected gate is the number of row entries <= u (the row
+        // is non-decreasing); the last entry of each 16-wide block, read
+        // together with T[a][k-1], picks the block, whose entries are then
+        // counted: two dependent LDS round trips instead of a binary search.
+        const uint32_t *Ta = s.T + a * kp;
+        const uint32_t tail = Ta[k - 1];
+        int bs = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            if (b < nb) bs += Ta[16 * b + 15] <= u ? 1 : 0;
+        if (!(u < tail)) break;
+        const uint4 *q = (const uint4 *)(Ta + 16 * bs);
+        const uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+        const int j = 16 * bs + (q0.x <= u) + (q0.y <= u) + (q0.z <= u) + (q0.w <= u) + (q1.x <= u) +
+                      (q1.y <= u) + (q1.z <= u) + (q1.w <= u) + (q2.x <= u) + (q2.y <= u) + (q2.z <= u) +
+                      (q2.w <= u) + (q3.x <= u) + (q3.y <= u) + (q3.z <= u) + (q3.w <= u);
+        const uint64_t g = s.gkey[j];
+        key ^= g & ~(1ull << 63);
+        e += 1u + 2u * (uint32_t)(g >> 63);
         empty = false;
-        a = lo + 1;
+        a = j + 1;
     }
     return empty;
 }
@@ -670,7 +745,7 @@ __device__ __forceinline__ bool draw_trajectory(const DevPlan &p, const RawSmem 
 // LDS counters each (cnt[0..2], cnt[3..5]), read only after the barrier that
 // follows their last update and cleared two batches before their next use;
 // the queue alternates between two buffers (the list and pivot scratch, free
-// while sampling).  Whole workgroup; s.T / s.gkey / s.gneg loaded; the table
+// while sampling).  Whole workgroup; s.T / s.gkey loaded (load_tables); the table
 // cleared (clear_table) before the first call and between calls.
 __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSmem &s, int *cnt,
                                                    uint32_t slot0, int64_t b, uint32_t t, uint32_t k0,
@@ -678,7 +753,7 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const uint32_t blo = (uint32_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
-    const uint32_t any = p.k > 0 ? s.T[p.k - 1] : 0u;
+    const uint32_t any = p.k > 0 ? s.T[p.k - 1] : 0u;   // T[0][k-1]
     int *pend = cnt, *added = cnt + 3;
     for (; st.next < t; st.next += kBatch, ++st.j) {
         uint32_t *queue = (st.j & 1) ? (uint32_t *)s.piv : (uint32_t *)s.list;
@@ -858,11 +933,11 @@ struct LemmaBits {
     int ok;         // lemma usable for this bitstring
 };
 
-// Per-bitstring setup; whole workgroup; FP64 throughout.  Gauss-Jordan elimination of
-// [M_0 | I] in LDS (left half in sP, right half in the not yet used hash
-// keys), partial pivoting by row swaps (largest |a|^2, lowest row on ties);
-// rows are not normalised until the end, so each step is one multiplier pass
-// by wave 0 and one update pass by the workgroup.  Then X = M_0^-1 A1[R, act]
+// Per-bitstring setup; whole workgroup; FP64 throughout.  Gauss-Jordan
+// elimination of [M_0 | I] in LDS (left half in sP, right half in the not yet
+// used hash keys) by wave 0 alone (wave barriers only), partial pivoting by
+// row swaps (largest |a|^2, lowest row on ties); rows are not normalised until
+// the end, so each step is one multiplier pass and one update pass.  Then X = M_0^-1 A1[R, act]
 // (after V in the hash keys) and H = Phi0[act, :] X into sH.  When
 // m * |act| <= 512 the operands A1[R, act] and Phi0[act, :] are first copied
 // to the hash counts (their loads overlap the elimination).
@@ -883,34 +958,42 @@ __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem
         W[i] = p.P[(size_t)s.Rb[r] * G + c];
         V[i] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     }
-    if (staged) {
-        for (int i = tid; i < m * kb; i += kThreads) {
-            const int l = i / kb, q = i % kb;
-            A1s[i] = p.A1[(size_t)s.Rb[l] * n + p.keymode[q]];
-            const int q2 = i / m, j = i % m;
-            Phs[i] = p.Phi0[(size_t)p.keymode[q2] * G + j];
-        }
-    }
     if (tid == 0) {
         *s_flag = 1;
         *s_det = make_double2(1.0, 0.0);
     }
     __syncthreads();
-    // ||M_0||_1 (largest column sum of moduli), kept in red[G]
-    if (tid < 64) {
+    if (tid >= 64) {
+        // waves 1..3 copy the operands of X and H while wave 0 eliminates
+        if (staged) {
+            for (int i = tid - 64; i < m * kb; i += kThreads - 64) {
+                const int l = i / kb, q = i % kb;
+                A1s[i] = p.A1[(size_t)s.Rb[l] * n + p.keymode[q]];
+                const int q2 = i / m, j = i % m;
+                Phs[i] = p.Phi0[(size_t)p.keymode[q2] * G + j];
+            }
+        }
+    } else {
+        // Gauss-Jordan on [W | V] by wave 0 alone: lane handles column
+        // lane % 2G of the 2G-wide augmented rows and every (64 / 2G)-th row.
+        static_assert(2 * G <= 64, "one wave holds a column of the augmented matrix per lane");
+        const int lane = tid;
+        constexpr int NRS = 64 / (2 * G);
+        const int col = lane % (2 * G), rs = lane / (2 * G);
+        double2 *colp = col < G ? W + col : V + (col - G);
+        // ||M_0||_1 (largest column sum of moduli), kept in red[G]
         double cs = 0.0;
-        if (tid < m)
+        if (lane < m)
             for (int i = 0; i < m; ++i) {
-                const double2 x = W[i * G + tid];
+                const double2 x = W[i * G + lane];
                 cs += sqrt(x.x * x.x + x.y * x.y);
             }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
-        if (tid == 0) s.red[G].x = cs;
-    }
-    for (int c = 0; c < m; ++c) {
-        if (tid < 64) {
-            const int lane = tid;
+        if (lane == 0) s.red[G].x = cs;
+        double2 det = make_double2(1.0, 0.0);
+        bool ok = true;
+        for (int c = 0; c < m; ++c) {
             double v = -1.0;
             if (lane >= c && lane < m) {
                 const double2 a = W[lane * G + c];
@@ -927,50 +1010,44 @@ __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem
                 }
             }
             if (!(v > 0.0)) {
-                if (lane == 0) *s_flag = 0;
-            } else {
-                if (idx != c && lane < G) {
-                    const double2 a = W[c * G + lane], b = W[idx * G + lane];
-                    const double2 x = V[c * G + lane], y = V[idx * G + lane];
-                    W[c * G + lane] = b;
-                    W[idx * G + lane] = a;
-                    V[c * G + lane] = y;
-                    V[idx * G + lane] = x;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                const double2 u = W[c * G + c];
-                const double inv = 1.0 / fma(u.x, u.x, u.y * u.y);
-                const double2 ui = make_double2(u.x * inv, -u.y * inv);
-                if (lane < m) mult[lane] = lane == c ? make_double2(0.0, 0.0) : c_mul(W[lane * G + c], ui);
-                if (lane == 0) {
-                    pinv[c] = ui;
-                    const double2 d = c_mul(*s_det, u);
-                    *s_det = idx != c ? make_double2(-d.x, -d.y) : d;
+                ok = false;
+                break;
+            }
+            if (idx != c && rs == 0) {
+                const double2 a = colp[c * G], b = colp[idx * G];
+                colp[c * G] = b;
+                colp[idx * G] = a;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const double2 u = W[c * G + c];
+            const double inv = 1.0 / fma(u.x, u.x, u.y * u.y);
+            const double2 ui = make_double2(u.x * inv, -u.y * inv);
+            if (lane < m) mult[lane] = lane == c ? make_double2(0.0, 0.0) : c_mul(W[lane * G + c], ui);
+            if (lane == 0) pinv[c] = ui;
+            det = c_mul(det, u);
+            if (idx != c) det = make_double2(-det.x, -det.y);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // rows i != c: row_i -= mult_i row_c, left columns > c and the right half
+            if (col >= G || col > c) {
+                const double2 rc = colp[c * G];
+                for (int i = rs; i < m; i += NRS) {
+                    if (i == c) continue;
+                    const double2 l = mult[i];
+                    double2 &x = colp[i * G];
+                    x = make_double2(x.x - (l.x * rc.x - l.y * rc.y), x.y - (l.x * rc.y + l.y * rc.x));
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
-        __syncthreads();
-        if (!*s_flag) break;
-        // rows i != c: row_i -= mult_i row_c, left columns > c and the right half
-        for (int e = tid; e < m * 2 * G; e += kThreads) {
-            const int i = e / (2 * G), j = e % (2 * G);
-            if (i == c) continue;
-            const double2 l = mult[i];
-            if (j < G) {
-                if (j > c) {
-                    const double2 rc = W[c * G + j];
-                    double2 &a = W[i * G + j];
-                    a = make_double2(a.x - (l.x * rc.x - l.y * rc.y), a.y - (l.x * rc.y + l.y * rc.x));
-                }
-            } else {
-                const double2 rc = V[c * G + j - G];
-                double2 &a = V[i * G + j - G];
-                a = make_double2(a.x - (l.x * rc.x - l.y * rc.y), a.y - (l.x * rc.y + l.y * rc.x));
-            }
+        if (lane == 0) {
+            *s_flag = ok ? 1 : 0;
+            *s_det = det;
         }
-        __syncthreads();
     }
+    __syncthreads();
     LemmaBits lb;
     lb.ok = *s_flag;
     lb.detB = *s_det;
@@ -1105,98 +1182,160 @@ __device__ __forceinline__ double2 lemma_small_det(uint64_t key, const double2 *
     return neg ? make_double2(-det.x, -det.y) : det;
 }
 
-// Lemma pass: every lane takes whole entries with r <= kLemmaMaxRank; the
-// rest are then evaluated by lane groups: the r x r matrix I - 2 H[N, N] with
-// the group LU when r <= G, else (and for every entry of a bitstring that
-// failed the conditioning test) the LU of M_N itself.  Results go into the
-// slots; fixed-order sum.
-// nterm[2] accumulates the executed FP64-equivalent FLOPs.
+// Rows of I - 2 H[N, N] for the r set bits of key, one row per lane of a
+// group of GS lanes (rows and columns >= r are those of the identity).
+template <int GS>
+__device__ __forceinline__ void lemma_rows(uint64_t key, int r, int lane, const double2 *sH, int kb,
+                                           double2 (&a)[GS]) {
+    uint64_t mm = key;
+    int own = 0;
+#pragma unroll
+    for (int i = 0; i < GS; ++i) {
+        const int q = mm ? __ffsll((long long)mm) - 1 : 0;
+        if (i == lane) own = q;
+        mm &= mm - 1;
+    }
+    mm = key;
+#pragma unroll
+    for (int j = 0; j < GS; ++j) {
+        const int q = mm ? __ffsll((long long)mm) - 1 : 0;
+        mm &= mm - 1;
+        double2 v = make_double2(j == lane ? 1.0 : 0.0, 0.0);
+        if (lane < r && j < r) {
+            const double2 h = sH[own * kb + q];
+            v.x -= 2.0 * h.x;
+            v.y -= 2.0 * h.y;
+        }
+        a[j] = v;
+    }
+}
+
+// slot value = count * d, the entry marked as evaluated
+__device__ __forceinline__ void put_value(const RawSmem &s, int e, uint16_t slot, int2 c, double2 d) {
+    s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+    *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
+    s.list[e] = (uint16_t)(slot | 0x8000u);
+}
+
+// Evaluation of one table under the determinant lemma, in three passes:
+//   A1 (G = 16): patterns with 6 < r <= 8, the r x r matrix I - 2 H[N, N]
+//      factored by 8-lane groups;
+//   A2: the rest that the per-lane pass cannot take, by G-lane groups: the
+//      r x r matrix when r <= G, else (and for every entry of a bitstring
+//      that failed the conditioning test) the LU of M_N itself;
+//   B: patterns with r <= kLemmaMaxRank, one per lane, after a counting sort
+//      by r so that the lanes of a wave run the same number of steps.
+// Values go into the slots (entries marked in the list until the end) and
+// are summed exactly.
 template <int G>
-__device__ __forceinline__ double2 sum_entries_lemma(const DevPlan &p, const RawSmem &s, int nl,
-                                                     const double2 *sH, const LemmaBits &lb, Work &wk,
-                                                     int *s_emax) {
+__device__ __forceinline__ void sum_entries_lemma(const DevPlan &p, const RawSmem &s, int nl,
+                                                  const double2 *sH, const LemmaBits &lb, Work &wk,
+                                                  uint64_t *sacc) {
     const int tid = threadIdx.x;
-    const int lane = tid % G, grp = tid / G;
-    constexpr int NG = kThreads / G;
-    const int m = p.m;
-    if (lb.ok) {
-        for (int e = tid; e < nl; e += kThreads) {
+    const int m = p.m, kb = p.keybits;
+    constexpr int kMid = G > 8 ? 8 : kLemmaMaxRank;   // largest r of A1 (none when G <= 8)
+    if constexpr (G > 8) {
+        if (lb.ok) {
+            const int l8 = tid & 7, g8 = tid >> 3;
+            for (int e = g8; e < nl; e += kThreads / 8) {
+                const uint16_t slot = s.list[e];
+                if (slot >= kHashSlots) continue;
+                const uint64_t key = s.hkey[slot];
+                const int r = __popcll(key);
+                if (r <= kLemmaMaxRank || r > 8) continue;
+                const int2 c = s.hcnt[slot];
+                double2 a[8];
+                lemma_rows<8>(key, r, l8, sH, kb, a);
+                const double2 d = c_mul(lb.detB, lu_det<8>(a, r, l8, s.piv + g8 * 8));
+                if (l8 == 0) {
+                    put_value(s, e, slot, c, d);
+                    wk.rank += (unsigned)r;
+                    wk.flops += lu_flops(r) + 6;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    {
+        const int lane = tid % G, grp = tid / G;
+        constexpr int NG = kThreads / G;
+        for (int e = grp; e < nl; e += NG) {
             const uint16_t slot = s.list[e];
             if (slot >= kHashSlots) continue;
             const uint64_t key = s.hkey[slot];
             const int r = __popcll(key);
-            if (r > kLemmaMaxRank) continue;
+            if (lb.ok && r <= kMid) continue;
             const int2 c = s.hcnt[slot];
-            const double2 d = c_mul(lb.detB, lemma_small_det(key, sH, p.keybits));
+            const bool small = lb.ok && r <= G;
+            double2 d;
+            int rank;
+            if (small) {
+                double2 a[G];
+                lemma_rows<G>(key, r, lane, sH, kb, a);
+                d = c_mul(lb.detB, lu_det<G>(a, r, lane, s.piv + grp * G));
+                rank = r;
+            } else {
+                d = term_det<G, false>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
+            }
+            if (lane == 0) {
+                put_value(s, e, slot, c, d);
+                wk.rank += (unsigned)rank;
+                wk.flops += small ? lu_flops(r) + 6 : lu_flops(m) + 8ull * m * m * rank;
+            }
+        }
+        __syncthreads();
+    }
+    if (lb.ok) {
+        int *hist = (int *)s.red;             // [9]: bins of r, then the total
+        uint16_t *order = (uint16_t *)s.piv;  // unmarked slots sorted by r
+        if (tid < 9) hist[tid] = 0;
+        __syncthreads();
+        for (int e = tid; e < nl; e += kThreads) {
+            const uint16_t slot = s.list[e];
+            if (slot < kHashSlots) atomicAdd(&hist[__popcll(s.hkey[slot])], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int r = 0; r <= kLemmaMaxRank; ++r) {
+                const int h = hist[r];
+                hist[r] = acc;
+                acc += h;
+            }
+            hist[8] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < nl; e += kThreads) {
+            const uint16_t slot = s.list[e];
+            if (slot < kHashSlots) order[atomicAdd(&hist[__popcll(s.hkey[slot])], 1)] = slot;
+        }
+        __syncthreads();
+        const int nb = hist[8];
+        for (int i = tid; i < nb; i += kThreads) {
+            const uint16_t slot = order[i];
+            const uint64_t key = s.hkey[slot];
+            const int r = __popcll(key);
+            const int2 c = s.hcnt[slot];
+            const double2 d = c_mul(lb.detB, lemma_small_det(key, sH, kb));
             s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
             *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
-            s.list[e] = (uint16_t)(slot | 0x8000u);
             wk.rank += (unsigned)r;
-            // r x r LU, then the product with det M_0
             wk.flops += lu_flops(r) + 6;
         }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = grp; e < nl; e += NG) {
-        const uint16_t slot = s.list[e];
-        if (slot >= kHashSlots) continue;   // taken by the lemma pass
-        const uint64_t key = s.hkey[slot];
-        const int2 c = s.hcnt[slot];
-        const int r = __popcll(key);
-        int rank;
-        double2 d;
-        unsigned long long f;
-        if (lb.ok && r <= G) {
-            // I - 2 H[N, N] with one row per lane, then the group LU
-            uint64_t mm = key;
-            int own = 0;
-#pragma unroll
-            for (int i = 0; i < G; ++i) {
-                const int q = mm ? __ffsll((long long)mm) - 1 : 0;
-                if (i == lane) own = q;
-                mm &= mm - 1;
-            }
-            double2 a[G];
-            mm = key;
-#pragma unroll
-            for (int j = 0; j < G; ++j) {
-                const int q = mm ? __ffsll((long long)mm) - 1 : 0;
-                mm &= mm - 1;
-                double2 v = make_double2(j == lane ? 1.0 : 0.0, 0.0);
-                if (lane < r && j < r) {
-                    const double2 h = sH[own * p.keybits + q];
-                    v.x -= 2.0 * h.x;
-                    v.y -= 2.0 * h.y;
-                }
-                a[j] = v;
-            }
-            d = c_mul(lb.detB, lu_det<G>(a, r, lane, s.piv + grp * G));
-            rank = r;
-            f = lu_flops(r) + 6;
-        } else {
-            d = term_det<G, false>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
-            f = lu_flops(m) + 8ull * m * m * rank;
-        }
-        if (lane == 0) {
-            s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
-            *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
-            wk.rank += (unsigned)rank;
-            wk.flops += f;
-        }
-    }
-    __syncthreads();
     for (int e = tid; e < nl; e += kThreads) s.list[e] &= 0x7FFFu;
     __syncthreads();
     if (tid == 0) wk.terms += (unsigned)nl;
-    return exact_sum_slots(s, nl, s_emax);
+    accumulate_slots(s, nl, sacc);
 }
 
 // Sum over the entries of count * det.  Each group evaluates entries
-// e = grp, grp + NG, ...; the product is left in the entry's slot and summed
-// by exact_sum_slots.
+// e = grp, grp + NG, ...; the product is left in the entry's slot and added
+// to the bitstring's LDS sum.
 template <int G, bool MIXED, bool STAGE>
-__device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &s, int nl, Work &wk,
-                                               int *s_emax) {
+__device__ __forceinline__ void sum_entries(const DevPlan &p, const RawSmem &s, int nl, Work &wk,
+                                            uint64_t *sacc) {
     const int tid = threadIdx.x;
     const int lane = tid % G, grp = tid / G;
     constexpr int NG = kThreads / G;
@@ -1219,17 +1358,18 @@ __device__ __forceinline__ double2 sum_entries(const DevPlan &p, const RawSmem &
     }
     __syncthreads();
     if (tid == 0) wk.terms += (unsigned)nl;
-    return exact_sum_slots(s, nl, s_emax);
+    accumulate_slots(s, nl, sacc);
 }
 
 __device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) {
     const int tid = threadIdx.x;
     const int k = p.k;
-    for (int i = tid; i < k * k; i += kThreads) s.T[i] = p.T[i];
-    for (int i = tid; i < k; i += kThreads) {
-        s.gkey[i] = p.gkey[i];
-        s.gneg[i] = p.gneg[i];
+    const int kp = s.kpad;
+    for (int i = tid; i < k * kp; i += kThreads) {
+        const int a = i / kp, j = i % kp;
+        s.T[i] = j < k ? p.T[a * k + j] : 0xFFFFFFFFu;
     }
+    for (int i = tid; i < k; i += kThreads) s.gkey[i] = p.gkey[i] | ((uint64_t)(p.gneg[i] != 0) << 63);
 }
 
 // KIND: 0 = row-per-lane LU with factors read from global memory, 1 = the same
@@ -1244,8 +1384,9 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
                unsigned long long *nterm) {
     constexpr bool STAGE = KIND == 1;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n, s_flag, s_emax;
+    __shared__ int s_ok, s_n, s_flag;
     __shared__ int s_cnt[6];
+    __shared__ uint64_t s_acc[kAccWords];
     __shared__ double2 s_det;
     const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
     double2 *sH = (double2 *)((unsigned char *)s.sP + (size_t)G * G * 16);
@@ -1269,20 +1410,18 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
         if constexpr (STAGE) stage_rows<MIXED>(p, s);
         LemmaBits lb;
         if constexpr (KIND == 2) lb = lemma_setup<G>(p, s, sH, &s_flag, &s_det, wk);
-        double2 total = make_double2(0.0, 0.0);
         Sampler st;
+        acc_clear(s_acc);
         clear_table(s, s_cnt, slot0, st);
         while (true) {
             const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = gather_list(s, &s_n, &s_emax);
-            double2 part;
-            if constexpr (KIND == 2) part = sum_entries_lemma<G>(p, s, nl, sH, lb, wk, &s_emax);
-            else part = sum_entries<G, MIXED, STAGE>(p, s, nl, wk, &s_emax);
-            total.x += part.x;
-            total.y += part.y;
+            const int nl = gather_list(s, &s_n);
+            if constexpr (KIND == 2) sum_entries_lemma<G>(p, s, nl, sH, lb, wk, s_acc);
+            else sum_entries<G, MIXED, STAGE>(p, s, nl, wk, s_acc);
             if (done) break;
             clear_table(s, s_cnt, slot0, st);
         }
+        const double2 total = acc_value(s_acc);
         if (tid == 0) {
             const double ax = total.x * p.scale, ay = total.y * p.scale;
             const double pb = ax * ax + ay * ay;
@@ -1470,8 +1609,9 @@ __global__ void __launch_bounds__(kThreads)
 k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
                    const double *__restrict__ g, double2 *part, GradLayout lay) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n, s_emax;
+    __shared__ int s_ok, s_n;
     __shared__ int s_cnt[6];
+    __shared__ uint64_t s_acc[kAccWords];
     const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
     constexpr int NG = kThreads / G;
     double2 *tiles = (double2 *)(smem + raw_lds_bytes(p.k, p.n, G, MIXED, false));
@@ -1487,19 +1627,18 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
         if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) continue;
         const double gb = g[b];
         if (gb == 0.0) continue;
-        double2 total = make_double2(0.0, 0.0);
         Sampler st;
+        acc_clear(s_acc);
         clear_table(s, s_cnt, slot0, st);
         while (true) {
             const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = gather_list(s, &s_n, &s_emax);
+            const int nl = gather_list(s, &s_n);
             Work unused;
-            const double2 part_sum = sum_entries<G, MIXED, false>(p, s, nl, unused, &s_emax);
-            total.x += part_sum.x;
-            total.y += part_sum.y;
+            sum_entries<G, MIXED, false>(p, s, nl, unused, s_acc);
             if (done) break;
             clear_table(s, s_cnt, slot0, st);
         }
+        const double2 total = acc_value(s_acc);
         const double ax = total.x * p.scale, ay = total.y * p.scale;
         const double a2 = ax * ax + ay * ay;
         if (a2 == 0.0) continue;
@@ -1512,7 +1651,7 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
         clear_table(s, s_cnt, slot0, st);
         while (true) {
             const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = gather_list(s, &s_n, &s_emax);
+            const int nl = gather_list(s, &s_n);
             for (int e = grp; e < nl; e += NG) {
                 const uint16_t slot = s.list[e];
                 const int2 c = s.hcnt[slot];
