@@ -138,8 +138,10 @@ xf_status xf_trajectory_bound(double eps, double delta, double p_max, double xi,
  *   d_logp  device [B] doubles: log p_b in FP64 (-inf where p_b = 0), or NULL
  * A bitstring whose weight differs from eta, or with bits at or above n, gets
  * p = 0 and A = 0 (passive circuits conserve the weight, Sec. II-B).  B = 0 is
- * a no-op.  Uses plan-owned device scratch; results are bitwise reproducible
- * for fixed inputs. */
+ * a no-op.  Uses plan-owned device scratch (under the determinant lemma, a
+ * workspace of up to 4 GiB holding each bitstring's distinct patterns, grown
+ * on demand, the call then synchronising hip_stream first); results are
+ * bitwise reproducible for fixed inputs. */
 xf_status xf_probabilities(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, xf_mode mode,
                            int64_t t, uint64_t seed, double *d_prob, double *d_amp,
                            double *d_logp, void *hip_stream);
@@ -179,18 +181,24 @@ xf_status xf_plan_set_evaluation(xf_plan *plan, xf_evaluation evaluation);
  * flipped modes, i.e. of the ranks of the low-rank corrections composed. */
 xf_status xf_plan_last_term_count(xf_plan *plan, int64_t *count, int64_t *rank_sum);
 
-/* Same counters plus the arithmetic executed for them (synchronises the
- * device).  flops counts real FP64-equivalent operations of the
- * determinant evaluations actually performed: (4/3)(m-1)m(2m-1) + 3m(m-1)
- * per m x m LU plus 8 m^2 per rank of each composed correction, or, for a
- * pattern taken by the determinant lemma, the same LU count at size r plus 6,
- * plus the lemma's per-bitstring setup (Gauss-Jordan inverse of M_0 and the
- * products forming H, 8 per complex multiply-add).  The sampling is not
- * counted.  lemma = 1 if the call used the determinant lemma. */
+/* Same counters plus the arithmetic executed for them and the kernel times
+ * of the call (synchronises the device).  flops counts real FP64-equivalent
+ * operations of the determinant evaluations actually performed:
+ * (4/3)(m-1)m(2m-1) + 3m(m-1) per m x m LU plus 8 m^2 per rank of each
+ * composed correction, or, for a pattern taken by the determinant lemma, the
+ * same LU count at size r plus 6, plus the lemma's per-bitstring setup
+ * (Gauss-Jordan inverse of M_0 and the products forming H, 8 per complex
+ * multiply-add).  The sampling is not counted.  lemma = 1 if the call used
+ * the determinant lemma; it then runs a sampling kernel and an evaluation
+ * kernel per chunk of bitstrings, timed separately (sample_ms, eval_ms, from
+ * HIP events on the call's stream); other calls run one kernel, reported in
+ * eval_ms. */
 typedef struct {
     int64_t determinants;
     int64_t rank_sum;
     double flops;
+    double sample_ms;
+    double eval_ms;
     int32_t lemma;
 } xf_work;
 xf_status xf_plan_last_work(xf_plan *plan, xf_work *work);

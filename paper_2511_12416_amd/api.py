@@ -116,12 +116,13 @@ class Plan:
 
     def last_work(self) -> dict:
         """Work of the last probabilities() call: determinants, summed rank of
-        their corrections, FP64-equivalent FLOPs executed, and whether the
-        determinant lemma was used."""
+        their corrections, FP64-equivalent FLOPs executed, kernel times in ms
+        (sampling and evaluation kernels under the determinant lemma), and
+        whether the lemma was used."""
         w = _abi.Work()
         check(lib().xf_plan_last_work(self._h, ctypes.byref(w)))
         return {"determinants": w.determinants, "rank_sum": w.rank_sum, "flops": w.flops,
-                "lemma": bool(w.lemma)}
+                "sample_ms": w.sample_ms, "eval_ms": w.eval_ms, "lemma": bool(w.lemma)}
 
     def set_evaluation(self, evaluation: str) -> None:
         """"auto" (determinant lemma where it applies) or "lu" (LU of every

@@ -157,6 +157,12 @@ struct xf_plan {
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
     int last_lemma = 0;               // the last xf_probabilities call used the determinant lemma
+    // determinant-lemma workspace: per-bitstring regions of (pattern, count) entries
+    DevBuf dekey, decnt, decount;
+    // timing of the last call: ev[0] start, then per chunk (mid, end) of the
+    // two lemma kernels, or one end event for a fused kernel
+    std::vector<hipEvent_t> ev;
+    int nev = 0;
     bool xterms_have_dw = false;
     // host copies of the factors, for the backward chain rule
     std::vector<std::vector<cd>> Rp;  // R'_l = R_l D0_{l-1} (R'_0 = R_0), n x n each
@@ -413,9 +419,26 @@ void plan_free(xf_plan *P) {
     for (DevBuf *b : {&P->dP, &P->dPhi0, &P->dA1, &P->dA2, &P->dQ, &P->dR1, &P->fPhi0, &P->fA1,
                       &P->fA2, &P->fQ, &P->fR1, &P->dkeymode, &P->dT, &P->dgkey, &P->dgmode,
                       &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
-                      &P->dgsum})
+                      &P->dgsum, &P->dekey, &P->decnt, &P->decount})
         dev_free(*b);
+    for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+    P->ev.clear();
+    P->nev = 0;
 }
+
+// At least n timing events.
+xf_status ensure_events(xf_plan *P, size_t n) {
+    while (P->ev.size() < n) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return fail(XF_EDEVICE, "hipEventCreate failed");
+        P->ev.push_back(e);
+    }
+    return ok();
+}
+
+// Device-memory budget of the determinant-lemma workspace: bitstrings are
+// processed in chunks whose entry regions fit in it.
+constexpr uint64_t kEntryBudget = 4ull << 30;
 
 xf_status set_gate_tables(xf_plan *P) {
     // signs of the angles (phase i or -i of a d_1 choice)
@@ -613,6 +636,7 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
     if (xf::launch_zero_u64((unsigned long long *)P->dnterm.p, s) != hipSuccess)
         return fail(XF_EDEVICE, "launch failed: %s", hipGetErrorString(hipGetLastError()));
     P->last_lemma = 0;
+    P->nev = 0;
     if (B == 0) return ok();
     xf_status st;
     if (mode == XF_EXACT && P->nxterms < 0) {
@@ -621,17 +645,48 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
     }
     xf::DevPlan d = snapshot(P);
     hipError_t e;
+    if ((st = ensure_events(P, 2))) return st;
+    if (hipEventRecord(P->ev[0], s) != hipSuccess) return fail(XF_EDEVICE, "hipEventRecord failed");
     if (mode == XF_RAW_ESTIMATE) {
         d.scale = std::sqrt(extent_of(P->theta)) / (double)t;
         const bool mixed = P->precision == XF_MIXED;
         const int alg = P->evaluation == XF_EVAL_LU ? 1 : 0;
-        e = xf::launch_raw_estimate(d, mixed, alg, (const uint64_t *)d_bits, B, t, seed, d_prob, d_amp, d_logp,
-                                    (unsigned long long *)P->dnterm.p, s);
-        P->last_lemma = xf::raw_estimate_uses_lemma(d, alg) ? 1 : 0;
+        if (xf::raw_estimate_uses_lemma(d, alg)) {
+            const uint64_t cap = xf::lemma_entry_cap(t);
+            const int64_t per = (int64_t)std::max<uint64_t>(1, kEntryBudget / (cap * 16 + 4));
+            const int64_t chunk = std::min<int64_t>(B, per);
+            const int64_t nchunks = (B + chunk - 1) / chunk;
+            if ((st = ensure_events(P, 1 + 2 * (size_t)nchunks))) return st;
+            if (P->dekey.bytes < (size_t)chunk * cap * 8 || P->decnt.bytes < (size_t)chunk * cap * 8 ||
+                P->decount.bytes < (size_t)chunk * 4) {
+                if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
+                if ((st = dev_upload(P->dekey, nullptr, (size_t)chunk * cap * 8)) ||
+                    (st = dev_upload(P->decnt, nullptr, (size_t)chunk * cap * 8)) ||
+                    (st = dev_upload(P->decount, nullptr, (size_t)chunk * 4)))
+                    return st;
+            }
+            e = hipSuccess;
+            for (int64_t c = 0; c < nchunks && e == hipSuccess; ++c) {
+                const int64_t b0 = c * chunk, nb = std::min(chunk, B - b0);
+                e = xf::launch_lemma_chunk(d, (const uint64_t *)d_bits, b0, nb, t, seed, (uint64_t *)P->dekey.p,
+                                           (int2 *)P->decnt.p, (uint32_t *)P->decount.p, cap, d_prob, d_amp,
+                                           d_logp, (unsigned long long *)P->dnterm.p, P->ev[1 + 2 * c], s);
+                if (e == hipSuccess) e = hipEventRecord(P->ev[2 + 2 * c], s);
+            }
+            P->nev = 1 + 2 * (int)nchunks;
+            P->last_lemma = 1;
+        } else {
+            e = xf::launch_raw_estimate(d, mixed, alg, (const uint64_t *)d_bits, B, t, seed, d_prob, d_amp, d_logp,
+                                        (unsigned long long *)P->dnterm.p, s);
+            if (e == hipSuccess) e = hipEventRecord(P->ev[1], s);
+            P->nev = 2;
+        }
     } else {
         e = xf::launch_exact(d, P->precision == XF_MIXED, (const uint64_t *)P->dxkeys.p,
                              (const double2 *)P->dxw.p, P->nxterms, (const uint64_t *)d_bits, B, d_prob,
                              d_amp, d_logp, (unsigned long long *)P->dnterm.p, s);
+        if (e == hipSuccess) e = hipEventRecord(P->ev[1], s);
+        P->nev = 2;
     }
     if (e != hipSuccess) return fail(XF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ok();
@@ -659,6 +714,16 @@ xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
     work->rank_sum = (int64_t)v[1];
     work->flops = (double)v[2];
     work->lemma = P->last_lemma;
+    work->sample_ms = 0.0;
+    work->eval_ms = 0.0;
+    for (int i = 1; i < P->nev; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, P->ev[i - 1], P->ev[i]) != hipSuccess)
+            return fail(XF_EDEVICE, "hipEventElapsedTime failed");
+        // lemma: odd events close a sampler launch, even ones an evaluation
+        if (P->last_lemma && (i & 1)) work->sample_ms += ms;
+        else work->eval_ms += ms;
+    }
     return ok();
 }
 

@@ -71,6 +71,15 @@ hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, int algorithm, cons
                                int64_t t, uint64_t seed, double *prob, double *amp, double *logp,
                                unsigned long long *nterm, hipStream_t s);
 bool raw_estimate_uses_lemma(const DevPlan &p, int algorithm);
+// Determinant-lemma Raw Estimate for bitstrings [b0, b0 + nb): the sampler
+// kernel writes each bitstring's distinct (pattern, count) entries to its
+// region of ekey / ecnt (cap entries each, count in ecount[i]); ev_mid
+// (nullable) is recorded between it and the evaluation kernel.
+uint64_t lemma_entry_cap(int64_t t);
+hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                              uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,
+                              double *prob, double *amp, double *logp, unsigned long long *nterm,
+                              hipEvent_t ev_mid, hipStream_t s);
 hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
                         int64_t nkeys, const uint64_t *bits, int64_t B, double *prob, double *amp,
                         double *logp, unsigned long long *nterm, hipStream_t s);

@@ -1372,11 +1372,11 @@ __device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) 
     for (int i = tid; i < k; i += kThreads) s.gkey[i] = p.gkey[i] | ((uint64_t)(p.gneg[i] != 0) << 63);
 }
 
-// KIND: 0 = row-per-lane LU with factors read from global memory, 1 = the same
-// with the bitstring's factor rows staged in LDS, 2 = determinant lemma (FP64,
-// instantiated with MIXED = false only).
-// Up to G = 16 the LDS footprint allows two workgroups per CU; registers are
-// capped to match (a few loop-invariant values spill around the bitstring loop).
+// Raw Estimate with the LU per distinct pattern, sampling and evaluation fused
+// per bitstring.  KIND: 0 = factors read from global memory, 1 = the
+// bitstring's factor rows staged in LDS.  Up to G = 16 the LDS footprint
+// allows two workgroups per CU; registers are capped to match (a few
+// loop-invariant values spill around the bitstring loop).
 template <int G, bool MIXED, int KIND>
 __global__ void __launch_bounds__(kThreads, G <= 16 ? 2 : 1)
 k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
@@ -1384,12 +1384,10 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
                unsigned long long *nterm) {
     constexpr bool STAGE = KIND == 1;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n, s_flag;
+    __shared__ int s_ok, s_n;
     __shared__ int s_cnt[6];
     __shared__ uint64_t s_acc[kAccWords];
-    __shared__ double2 s_det;
     const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
-    double2 *sH = (double2 *)((unsigned char *)s.sP + (size_t)G * G * 16);
     const int tid = threadIdx.x;
     Work wk;
     load_tables(p, s);
@@ -1408,20 +1406,159 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
             continue;
         }
         if constexpr (STAGE) stage_rows<MIXED>(p, s);
-        LemmaBits lb;
-        if constexpr (KIND == 2) lb = lemma_setup<G>(p, s, sH, &s_flag, &s_det, wk);
         Sampler st;
         acc_clear(s_acc);
         clear_table(s, s_cnt, slot0, st);
         while (true) {
             const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
             const int nl = gather_list(s, &s_n);
-            if constexpr (KIND == 2) sum_entries_lemma<G>(p, s, nl, sH, lb, wk, s_acc);
-            else sum_entries<G, MIXED, STAGE>(p, s, nl, wk, s_acc);
+            sum_entries<G, MIXED, STAGE>(p, s, nl, wk, s_acc);
             if (done) break;
             clear_table(s, s_cnt, slot0, st);
         }
         const double2 total = acc_value(s_acc);
+        if (tid == 0) {
+            const double ax = total.x * p.scale, ay = total.y * p.scale;
+            const double pb = ax * ax + ay * ay;
+            prob[b] = pb;
+            if (amp) { amp[2 * b] = ax; amp[2 * b + 1] = ay; }
+            if (logp) logp[b] = log(pb);
+        }
+        __syncthreads();
+    }
+    flush_work(wk, nterm);
+}
+
+// ---------------------------------------------------------------------------
+// Raw Estimate under the determinant lemma, in two kernels per chunk of
+// bitstrings, so that each runs at its own occupancy: the sampler needs few
+// registers and no evaluation scratch (three workgroups per CU), the
+// evaluation needs the registers of the per-lane determinants.
+//   k_sample_entries: draws the t trajectories of each bitstring and writes
+//     its distinct (flip pattern, Gaussian-integer count) entries, one table
+//     flush after another, to the bitstring's region of the workspace.
+//   k_eval_entries: forms H for the bitstring and evaluates the entries in
+//     chunks of kHashSlots, summing count * det exactly.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kEntryInvalid = 0xFFFFFFFFu;    // bitstring of the wrong weight: p = 0
+constexpr uint32_t kEntryOverflow = 0xFFFFFFFEu;   // more entries than the region holds
+
+__host__ __device__ __forceinline__ size_t sampler_head_bytes(int k) {
+    return align16((size_t)kHashSlots * (8 + 8 + 2) + (size_t)kThreads * 16 + 64 + (size_t)k * 8);
+}
+__host__ __device__ __forceinline__ size_t sampler_lds_bytes(int k) {
+    return sampler_head_bytes(k) + (size_t)k * table_stride(k) * 4;
+}
+
+// Sampler layout: the hash, the two sample queues (pivot scratch and list)
+// and the tables; no reduction scratch or factor copies.
+__device__ __forceinline__ RawSmem carve_sampler(unsigned char *smem, int k) {
+    RawSmem s;
+    s.hkey = (uint64_t *)smem;
+    s.hcnt = (int2 *)(s.hkey + kHashSlots);
+    s.piv = (double2 *)(s.hcnt + kHashSlots);
+    s.red = nullptr;
+    s.list = (uint16_t *)(s.piv + kThreads);
+    s.Rb = (uint8_t *)(s.list + kHashSlots);
+    s.gkey = (uint64_t *)(s.Rb + 64);
+    s.kpad = table_stride(k);
+    s.T = (uint32_t *)(smem + sampler_head_bytes(k));
+    s.sP = nullptr;
+    s.sA1 = nullptr;
+    s.sPhi = nullptr;
+    return s;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_sample_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
+                 uint64_t *__restrict__ ekey, int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount,
+                 uint64_t cap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_ok, s_n;
+    __shared__ int s_cnt[6];
+    const RawSmem s = carve_sampler(smem, p.k);
+    const int tid = threadIdx.x;
+    load_tables(p, s);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t slot0 = hash_slot(0);
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int64_t b = b0 + i;
+        if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) {
+            if (tid == 0) ecount[i] = kEntryInvalid;
+            continue;
+        }
+        uint64_t *kout = ekey + (size_t)i * cap;
+        int2 *cout = ecnt + (size_t)i * cap;
+        uint64_t cursor = 0;
+        bool overflow = false;
+        Sampler st;
+        clear_table(s, s_cnt, slot0, st);
+        while (true) {
+            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
+            const int nl = gather_list(s, &s_n);
+            if (cursor + (uint64_t)nl <= cap) {
+                for (int e = tid; e < nl; e += kThreads) {
+                    const uint16_t slot = s.list[e];
+                    kout[cursor + e] = s.hkey[slot];
+                    cout[cursor + e] = s.hcnt[slot];
+                }
+            } else {
+                overflow = true;
+            }
+            cursor += (uint64_t)nl;
+            if (done) break;
+            clear_table(s, s_cnt, slot0, st);
+        }
+        if (tid == 0) ecount[i] = overflow ? kEntryOverflow : (uint32_t)cursor;
+    }
+}
+
+template <int G>
+__global__ void __launch_bounds__(kThreads, 2)
+k_eval_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
+               const uint64_t *__restrict__ ekey, const int2 *__restrict__ ecnt,
+               const uint32_t *__restrict__ ecount, uint64_t cap, double *__restrict__ prob,
+               double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_ok, s_flag;
+    __shared__ double2 s_det;
+    __shared__ uint64_t s_acc[kAccWords];
+    const RawSmem s = carve_raw(smem, 0, p.n, G, false);
+    double2 *sH = (double2 *)((unsigned char *)s.sP + (size_t)G * G * 16);
+    const int tid = threadIdx.x;
+    Work wk;
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int64_t b = b0 + i;
+        const uint32_t ne = ecount[i];
+        if (ne == kEntryInvalid) {
+            if (tid == 0) {
+                prob[b] = 0.0;
+                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
+                if (logp) logp[b] = -INFINITY;
+            }
+            continue;
+        }
+        load_bitstring(p, bits, b, s.Rb, &s_ok);
+        double2 total;
+        if (ne == kEntryOverflow) {
+            total = make_double2(__longlong_as_double(0x7FF8000000000000ll), 0.0);
+        } else {
+            const LemmaBits lb = lemma_setup<G>(p, s, sH, &s_flag, &s_det, wk);
+            acc_clear(s_acc);
+            const uint64_t *kin = ekey + (size_t)i * cap;
+            const int2 *cin = ecnt + (size_t)i * cap;
+            for (uint32_t c0 = 0; c0 < ne; c0 += kHashSlots) {
+                const int nc = (int)min((uint32_t)kHashSlots, ne - c0);
+                for (int e = tid; e < nc; e += kThreads) {
+                    s.hkey[e] = kin[c0 + e];
+                    s.hcnt[e] = cin[c0 + e];
+                    s.list[e] = (uint16_t)e;
+                }
+                __syncthreads();
+                sum_entries_lemma<G>(p, s, nc, sH, lb, wk, s_acc);
+            }
+            total = acc_value(s_acc);
+        }
         if (tid == 0) {
             const double ax = total.x * p.scale, ay = total.y * p.scale;
             const double pb = ax * ax + ay * ay;
@@ -1756,7 +1893,7 @@ __host__ __forceinline__ bool use_stage(const DevPlan &p, bool mixed) {
 }
 
 __host__ __forceinline__ size_t lemma_lds(const DevPlan &p) {
-    return raw_lds_bytes(p.k, p.n, p.G, false, false) + lemma_bytes(p.G, p.keybits);
+    return raw_lds_bytes(0, p.n, p.G, false, false) + lemma_bytes(p.G, p.keybits);
 }
 
 // The lemma needs one CPhase layer, compressed flip-pattern keys and room for
@@ -1764,7 +1901,8 @@ __host__ __forceinline__ size_t lemma_lds(const DevPlan &p) {
 // determinant, too small for FP32 to pay, and H in FP32 loses up to
 // ||M_0^-1|| more digits than the direct FP32 correction.
 __host__ __forceinline__ bool lemma_applies(const DevPlan &p) {
-    return p.L == 1 && p.G <= 16 && p.keykind == 0 && p.keybits >= 1 && lemma_lds(p) <= kMaxLds;
+    return p.L == 1 && p.G <= 16 && p.keykind == 0 && p.keybits >= 1 && lemma_lds(p) <= kMaxLds &&
+           sampler_lds_bytes(p.k) <= kMaxLds;
 }
 
 template <int G, bool MIXED>
@@ -1772,12 +1910,8 @@ hipError_t launch_raw_t(const DevPlan &p, int algorithm, const uint64_t *bits, i
                         uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
                         hipStream_t s) {
     const int grid = (int)(B < kMaxGrid ? B : kMaxGrid);
+    (void)algorithm;
     if constexpr (G <= 16) {
-        if (algorithm != 1 && lemma_applies(p)) {
-            hipLaunchKernelGGL((k_raw_estimate<G, false, 2>), dim3(grid), dim3(kThreads), lemma_lds(p), s, p, bits,
-                               B, (uint32_t)t, seed, prob, amp, logp, nterm);
-            return hipGetLastError();
-        }
         if (use_stage(p, MIXED)) {
             const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, true);
             hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 1>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
@@ -1834,7 +1968,7 @@ hipError_t set_lds_limits() {
         return e;
     if constexpr (G <= 16) {
         for (const void *f : {(const void *)k_raw_estimate<G, false, 1>, (const void *)k_raw_estimate<G, true, 1>,
-                              (const void *)k_raw_estimate<G, false, 2>})
+                              (const void *)k_eval_entries<G>, (const void *)k_sample_entries})
             if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
                 return e;
     }
@@ -1869,6 +2003,31 @@ size_t raw_estimate_lds_bytes(const DevPlan &p, bool mixed) {
 
 bool raw_estimate_uses_lemma(const DevPlan &p, int algorithm) {
     return algorithm != 1 && lemma_applies(p);
+}
+
+uint64_t lemma_entry_cap(int64_t t) { return (uint64_t)t + (uint64_t)t / 511 + 2; }
+
+hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                              uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,
+                              double *prob, double *amp, double *logp, unsigned long long *nterm,
+                              hipEvent_t ev_mid, hipStream_t s) {
+    const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
+    hipLaunchKernelGGL(k_sample_entries, dim3(grid), dim3(kThreads), sampler_lds_bytes(p.k), s, p, bits, b0, nb,
+                       (uint32_t)t, seed, ekey, ecnt, ecount, cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
+#define XF_EVAL(GG)                                                                                            \
+    hipLaunchKernelGGL((k_eval_entries<GG>), dim3(grid), dim3(kThreads), lemma_lds(p), s, p, bits, b0, nb, ekey, \
+                       ecnt, ecount, cap, prob, amp, logp, nterm)
+    switch (p.G) {
+        case 4: XF_EVAL(4); break;
+        case 8: XF_EVAL(8); break;
+        case 16: XF_EVAL(16); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef XF_EVAL
+    return hipGetLastError();
 }
 
 size_t exact_lds_bytes(const DevPlan &) { return kExactChunk * 16 + 2 * kThreads * 16 + 64; }
