@@ -66,11 +66,25 @@ def time_steps(plan, bits, mode, t, seed, out, steps, warmup):
     return wall, float(np.mean(kms)), float(np.median(kms))
 
 
+def kernel_split(plan, bits, mode, t, seed, out, steps):
+    """Mean per-kernel times (sampler, evaluation) over `steps` calls, from the
+    HIP events the library records around its launches on the call's stream
+    (read after each call, so this loop is kept apart from the timed one)."""
+    sm, em = [], []
+    for _ in range(steps):
+        plan.probabilities(bits, mode, t, seed, out=out)
+        wk = plan.last_work()
+        sm.append(wk["sample_ms"])
+        em.append(wk["eval_ms"])
+    return float(np.mean(sm)), float(np.mean(em))
+
+
 def measured_traffic():
-    """HBM bytes of one launch from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since those counters were taken."""
+    """HBM bytes of one launch of the evaluation kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source changed since
+    those counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_k_raw_estimate_lucj.json")
+    path = os.path.join(ROOT, "profiles", "traffic_k_eval_entries_lucj.json")
     src = os.path.join(ROOT, "paper_2511_12416_amd", "csrc", "xf_kernels.hip")
     try:
         rec = json.load(open(path))
@@ -151,6 +165,10 @@ def main() -> int:
         results[name] = dict(wall=wall, steps=steps, kmean=kmean, kmed=kmed, ndet=ndet, rank=rank_sum,
                              flops=flops, achieved=flops / (kmean * 1e-3) / 1e12, executed=wk["flops"],
                              executed_tf=wk["flops"] / (kmean * 1e-3) / 1e12, lemma=wk["lemma"])
+        if wk["lemma"]:
+            sms, ems = kernel_split(plan, bits, "approx", w.t, w.seed, out, steps)
+            results[name].update(sample_ms=sms, eval_ms=ems)
+            log(f"{name}: sampler kernel {sms:.3f} ms, evaluation kernel {ems:.3f} ms")
         p_gpu[name] = out.cpu().numpy().copy()
         r = results[name]
         log(f"{name}: {steps} steps {wall * 1e3 / steps:.3f} ms/step (events mean {kmean:.3f} ms), "
@@ -190,14 +208,23 @@ def main() -> int:
         "rel_err_vs_oracle": errs["fp64_auto"],
         "executed_determinants_per_step": r["ndet"],
         "executed_determinants_per_s": r["ndet"] * r["steps"] / r["wall"],
-        "roofline": {"bound": "alu", "achieved": r["achieved"], "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": r["achieved"] / FP64_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "achieved": r["flops"] / (r["eval_ms"] * 1e-3) / 1e12,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": r["flops"] / (r["eval_ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(),
-                     "flops": "LU formulation per executed determinant: (4/3)(m-1)m(2m-1) + 3m(m-1) "
-                              "+ 8 m^2 r",
-                     "kernel": "k_raw_estimate<16, false, 2> (determinant lemma, FP64)",
-                     "kernel_ms": r["kmean"], "flops_per_launch": r["flops"],
-                     "executed_flops_per_launch": r["executed"], "executed_tflops": r["executed_tf"]},
+                     "flops": "algorithmic, per executed determinant in its LU formulation: "
+                              "(4/3)(m-1)m(2m-1) + 3m(m-1) + 8 m^2 r; the lemma evaluates the same "
+                              "determinants with executed_flops_per_launch",
+                     "kernel": "k_eval_entries<16> (determinant lemma, FP64)",
+                     "kernel_ms": r["eval_ms"], "flops_per_launch": r["flops"],
+                     "executed_flops_per_launch": r["executed"],
+                     "executed_tflops": r["executed"] / (r["eval_ms"] * 1e-3) / 1e12,
+                     "call_ms": r["kmean"],
+                     "call_lu_equivalent_tflops": r["achieved"]},
+        "kernels": {"k_sample_entries": {"ms": r["sample_ms"],
+                                         "samples_per_s": terms_per_step / (r["sample_ms"] * 1e-3)},
+                    "k_eval_entries": {"ms": r["eval_ms"],
+                                       "determinants_per_s": r["ndet"] / (r["eval_ms"] * 1e-3)}},
         "lu_evaluation": {
             name: {"value": terms_per_step * q["steps"] / q["wall"], "unit": "terms/s",
                    "ms_per_step": q["wall"] * 1e3 / q["steps"], "kernel_ms": q["kmean"],

@@ -165,7 +165,7 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
  *   XF_EVAL_AUTO (default): for circuits with one CPhase layer (n_rot = 2),
  *     the matrix determinant lemma det M_N = det M_0 det(I_r - 2 H[N, N]) with
  *     H = Phi[act, :] M_0^-1 A[R, act] formed once per bitstring, so that each
- *     pattern costs an r x r determinant (r = |N|; one lane for r <= 6, a
+ *     pattern costs an r x r determinant (r = |N|; one lane for r <= 4, a
  *     lane group for larger r up to the group size, 4 to 16 lanes by eta).
  *     A bitstring whose base M_0 is singular or has 1-norm condition number
  *     above 1e4, and any larger pattern, is evaluated with the LU of M_N

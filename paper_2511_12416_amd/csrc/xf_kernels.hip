@@ -290,6 +290,55 @@ __device__ __forceinline__ double2 lu_det(double2 (&a)[G], int m, int lane, doub
     return (inversions & 1) ? make_double2(-det.x, -det.y) : det;
 }
 
+// The same elimination with the column loop kept rolled: after each step the
+// rows are shifted left by one entry, so the pivot column is always a[0] and
+// every index stays static (no private-memory arrays).  About twice the
+// multiply-adds of lu_det but a tenth of its code, for the rarely taken
+// evaluations of the determinant-lemma kernel, whose code must stay small
+// enough for the instruction cache.  Consumes a.
+template <int G>
+__device__ __forceinline__ double2 lu_det_compact(double2 (&a)[G], int m, int lane, double2 *piv) {
+    bool active = lane < m;
+    bool live = true;
+    unsigned inversions = 0;
+    double2 det = make_double2(1.0, 0.0);
+#pragma unroll 1
+    for (int c = 0; c < m && live; ++c) {
+        const double v = active ? fma(a[0].x, a[0].x, a[0].y * a[0].y) : -1.0;
+        const double vmax = group_max<G>(v);
+        const uint64_t act = group_bits<G>(active);
+        const uint64_t hit = group_bits<G>(active && v == vmax);
+        if (!(vmax > 0.0) || hit == 0) {
+            live = false;
+            continue;
+        }
+        const int idx = __ffsll((long long)hit) - 1;
+        inversions += __popcll(act & ((1ull << idx) - 1));
+        if (lane == idx) {
+            active = false;
+#pragma unroll
+            for (int j = 0; j < G; ++j) piv[j] = a[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double2 u = piv[0];
+        det = c_mul(det, u);
+        if (active) {
+            const double inv = 1.0 / fma(u.x, u.x, u.y * u.y);
+            const double2 l = c_mul(a[0], make_double2(-u.x * inv, u.y * inv));
+#pragma unroll
+            for (int j = 1; j < G; ++j) a[j] = c_fma(a[j], l, piv[j]);
+        }
+#pragma unroll
+        for (int j = 0; j + 1 < G; ++j) a[j] = a[j + 1];
+        a[G - 1] = make_double2(0.0, 0.0);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (!live) return make_double2(0.0, 0.0);
+    return (inversions & 1) ? make_double2(-det.x, -det.y) : det;
+}
+
 
 struct RawSmem {
     uint64_t *hkey;
@@ -916,11 +965,11 @@ __device__ __forceinline__ bool gj_invert(double2 (&a)[G], double2 (&v)[G], int 
 //   det M_N = det M_0 * det(I_r - 2 H[N, N]),  H = Phi0[act, :] M_0^-1 A1[R, act]
 // over the modes `act` the CPhase gates touch (the key's bit positions).  The
 // per-bitstring work is one Gauss-Jordan inverse and two thin products; each
-// distinct key then costs an r x r determinant (r = flipped modes, r <= 6 here)
-// evaluated by a single lane.  Bitstrings with kappa_1(M_0) > 1e4 (or an
-// exactly singular M_0) and keys with r > 6 use the row-per-lane LU instead.
+// distinct key then costs an r x r determinant (r = flipped modes): one lane
+// for r <= kLemmaMaxRank, a lane group above.  Bitstrings with
+// kappa_1(M_0) > 1e4 (or an exactly singular M_0) use the LU of M_N instead.
 // ---------------------------------------------------------------------------
-constexpr int kLemmaMaxRank = 6;
+constexpr int kLemmaMaxRank = 4;
 constexpr double kLemmaMaxCond = 1e4;
 
 // Bytes of the lemma's persistent LDS: P rows (G x G) and H (kb x kb), FP64.
@@ -933,11 +982,10 @@ struct LemmaBits {
     int ok;         // lemma usable for this bitstring
 };
 
-// Per-bitstring setup; whole workgroup; FP64 throughout.  Gauss-Jordan
-// elimination of [M_0 | I] in LDS (left half in sP, right half in the not yet
-// used hash keys) by wave 0 alone (wave barriers only), partial pivoting by
-// row swaps (largest |a|^2, lowest row on ties); rows are not normalised until
-// the end, so each step is one multiplier pass and one update pass.  Then X = M_0^-1 A1[R, act]
+// Per-bitstring setup; whole workgroup; FP64 throughout.  M_0 = P[R, :] is
+// copied to sP; the first G lanes of wave 0 invert it by Gauss-Jordan in
+// registers (one row per lane, the same pivot rule as the LU) into the not yet
+// used hash keys, while the other waves copy the operands of X and H.  Then X = M_0^-1 A1[R, act]
 // (after V in the hash keys) and H = Phi0[act, :] X into sH.  When
 // m * |act| <= 512 the operands A1[R, act] and Phi0[act, :] are first copied
 // to the hash counts (their loads overlap the elimination).
@@ -1182,6 +1230,24 @@ __device__ __forceinline__ double2 lemma_small_det(uint64_t key, const double2 *
     return neg ? make_double2(-det.x, -det.y) : det;
 }
 
+
+// det M_N by a lane group with the rolled elimination (rare fallback paths
+// of the determinant-lemma kernel, kept small in registers and code).
+template <int G>
+__device__ __forceinline__ double2 term_det_compact(const DevPlan &p, uint64_t key, const uint8_t *Rb, int lane,
+                                                    double2 *piv, int *rank) {
+    double2 a[G];
+    const Flips f = decode_key(p, key);
+    *rank = __popcll(f.n0[0]) + __popcll(f.n0[1]) + __popcll(f.n1[0]) + __popcll(f.n1[1]);
+    if (lane < p.m) {
+        compose_row<G, false>(p, Rb[lane], f, a);
+    } else {
+#pragma unroll
+        for (int j = 0; j < G; ++j) a[j] = make_double2(j == lane ? 1.0 : 0.0, 0.0);
+    }
+    return lu_det_compact<G>(a, p.m, lane, piv);
+}
+
 // Rows of I - 2 H[N, N] for the r set bits of key, one row per lane of a
 // group of GS lanes (rows and columns >= r are those of the identity).
 template <int GS>
@@ -1210,108 +1276,79 @@ __device__ __forceinline__ void lemma_rows(uint64_t key, int r, int lane, const 
     }
 }
 
-// slot value = count * d, the entry marked as evaluated
-__device__ __forceinline__ void put_value(const RawSmem &s, int e, uint16_t slot, int2 c, double2 d) {
-    s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
-    *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
-    s.list[e] = (uint16_t)(slot | 0x8000u);
-}
 
-// Evaluation of one table under the determinant lemma, in three passes:
-//   A1 (G = 16): patterns with 6 < r <= 8, the r x r matrix I - 2 H[N, N]
+// Evaluation of one table under the determinant lemma.  The entries are
+// first classified by r, the number of flipped modes:
+//   easy (r <= kLemmaMaxRank): one lane each, taken in order of r (counting
+//      sort) so that the lanes of a wave run the same number of steps;
+//   mid (G = 16, kLemmaMaxRank < r <= 8): the r x r matrix I - 2 H[N, N]
 //      factored by 8-lane groups;
-//   A2: the rest that the per-lane pass cannot take, by G-lane groups: the
-//      r x r matrix when r <= G, else (and for every entry of a bitstring
-//      that failed the conditioning test) the LU of M_N itself;
-//   B: patterns with r <= kLemmaMaxRank, one per lane, after a counting sort
-//      by r so that the lanes of a wave run the same number of steps.
-// Values go into the slots (entries marked in the list until the end) and
-// are summed exactly.
+//   hard (r > that): the r x r matrix by G-lane groups when r <= G, else the
+//      LU of M_N itself.
+// A bitstring that failed the conditioning test (or a table with more mid and
+// hard entries than the short list holds) takes the LU of M_N for every
+// entry.  Values go into the slots and are added to the bitstring's sum.
 template <int G>
 __device__ __forceinline__ void sum_entries_lemma(const DevPlan &p, const RawSmem &s, int nl,
                                                   const double2 *sH, const LemmaBits &lb, Work &wk,
                                                   uint64_t *sacc) {
     const int tid = threadIdx.x;
     const int m = p.m, kb = p.keybits;
-    constexpr int kMid = G > 8 ? 8 : kLemmaMaxRank;   // largest r of A1 (none when G <= 8)
-    if constexpr (G > 8) {
-        if (lb.ok) {
-            const int l8 = tid & 7, g8 = tid >> 3;
-            for (int e = g8; e < nl; e += kThreads / 8) {
-                const uint16_t slot = s.list[e];
-                if (slot >= kHashSlots) continue;
-                const uint64_t key = s.hkey[slot];
-                const int r = __popcll(key);
-                if (r <= kLemmaMaxRank || r > 8) continue;
-                const int2 c = s.hcnt[slot];
-                double2 a[8];
-                lemma_rows<8>(key, r, l8, sH, kb, a);
-                const double2 d = c_mul(lb.detB, lu_det<8>(a, r, l8, s.piv + g8 * 8));
-                if (l8 == 0) {
-                    put_value(s, e, slot, c, d);
-                    wk.rank += (unsigned)r;
-                    wk.flops += lu_flops(r) + 6;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    {
-        const int lane = tid % G, grp = tid / G;
-        constexpr int NG = kThreads / G;
-        for (int e = grp; e < nl; e += NG) {
-            const uint16_t slot = s.list[e];
-            if (slot >= kHashSlots) continue;
-            const uint64_t key = s.hkey[slot];
-            const int r = __popcll(key);
-            if (lb.ok && r <= kMid) continue;
-            const int2 c = s.hcnt[slot];
-            const bool small = lb.ok && r <= G;
-            double2 d;
-            int rank;
-            if (small) {
-                double2 a[G];
-                lemma_rows<G>(key, r, lane, sH, kb, a);
-                d = c_mul(lb.detB, lu_det<G>(a, r, lane, s.piv + grp * G));
-                rank = r;
-            } else {
-                d = term_det<G, false>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
-            }
-            if (lane == 0) {
-                put_value(s, e, slot, c, d);
-                wk.rank += (unsigned)rank;
-                wk.flops += small ? lu_flops(r) + 6 : lu_flops(m) + 8ull * m * m * rank;
-            }
-        }
-        __syncthreads();
-    }
-    if (lb.ok) {
-        int *hist = (int *)s.red;             // [9]: bins of r, then the total
-        uint16_t *order = (uint16_t *)s.piv;  // unmarked slots sorted by r
-        if (tid < 9) hist[tid] = 0;
+    const int lane = tid % G, grp = tid / G;
+    constexpr int NG = kThreads / G;
+    constexpr int kMid = G > 8 ? 8 : kLemmaMaxRank;     // largest r of the mid class
+    constexpr int kHardCap = (kThreads * 16 - 64) / 2;  // u16 entries after 64 B of counters
+    int *cnt = (int *)s.red;              // [0..6] easy bins, 7 easy, 8 mid, 9 hard, 10/11 cursors
+    uint16_t *order = (uint16_t *)s.piv;  // easy entries by r (the pivot scratch is free until then)
+    uint16_t *hard = (uint16_t *)s.red + 32;
+    bool full_lu = !lb.ok;
+    if (!full_lu) {
+        if (tid < 12) cnt[tid] = 0;
         __syncthreads();
         for (int e = tid; e < nl; e += kThreads) {
-            const uint16_t slot = s.list[e];
-            if (slot < kHashSlots) atomicAdd(&hist[__popcll(s.hkey[slot])], 1);
+            const int r = __popcll(s.hkey[s.list[e]]);
+            atomicAdd(&cnt[r <= kLemmaMaxRank ? r : (r <= kMid ? 8 : 9)], 1);
         }
         __syncthreads();
         if (tid == 0) {
             int acc = 0;
             for (int r = 0; r <= kLemmaMaxRank; ++r) {
-                const int h = hist[r];
-                hist[r] = acc;
+                const int h = cnt[r];
+                cnt[r] = acc;
                 acc += h;
             }
-            hist[8] = acc;
+            cnt[7] = acc;
+            cnt[10] = 0;
+            cnt[11] = cnt[8];
         }
         __syncthreads();
+        full_lu = cnt[8] + cnt[9] > kHardCap;
+    }
+    if (full_lu) {
+        for (int e = grp; e < nl; e += NG) {
+            const uint16_t slot = s.list[e];
+            const uint64_t key = s.hkey[slot];
+            const int2 c = s.hcnt[slot];
+            int rank;
+            const double2 d = term_det_compact<G>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
+            if (lane == 0) {
+                s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+                *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
+                wk.rank += (unsigned)rank;
+                wk.flops += lu_flops(m) + 8ull * m * m * rank;
+            }
+        }
+        __syncthreads();
+    } else {
+        const int n_easy = cnt[7], n_mid = cnt[8], n_hard = cnt[9];
         for (int e = tid; e < nl; e += kThreads) {
             const uint16_t slot = s.list[e];
-            if (slot < kHashSlots) order[atomicAdd(&hist[__popcll(s.hkey[slot])], 1)] = slot;
+            const int r = __popcll(s.hkey[slot]);
+            if (r <= kLemmaMaxRank) order[atomicAdd(&cnt[r], 1)] = slot;
+            else hard[atomicAdd(&cnt[r <= kMid ? 10 : 11], 1)] = slot;
         }
         __syncthreads();
-        const int nb = hist[8];
-        for (int i = tid; i < nb; i += kThreads) {
+        for (int i = tid; i < n_easy; i += kThreads) {
             const uint16_t slot = order[i];
             const uint64_t key = s.hkey[slot];
             const int r = __popcll(key);
@@ -1323,9 +1360,49 @@ __device__ __forceinline__ void sum_entries_lemma(const DevPlan &p, const RawSme
             wk.flops += lu_flops(r) + 6;
         }
         __syncthreads();
+        if constexpr (G > 8) {
+            const int l8 = tid & 7, g8 = tid >> 3;
+            for (int i = g8; i < n_mid; i += kThreads / 8) {
+                const uint16_t slot = hard[i];
+                const uint64_t key = s.hkey[slot];
+                const int r = __popcll(key);
+                const int2 c = s.hcnt[slot];
+                double2 a[8];
+                lemma_rows<8>(key, r, l8, sH, kb, a);
+                const double2 d = c_mul(lb.detB, lu_det<8>(a, r, l8, s.piv + g8 * 8));
+                if (l8 == 0) {
+                    s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+                    *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
+                    wk.rank += (unsigned)r;
+                    wk.flops += lu_flops(r) + 6;
+                }
+            }
+            __syncthreads();
+        }
+        for (int i = n_mid + grp; i < n_mid + n_hard; i += NG) {
+            const uint16_t slot = hard[i];
+            const uint64_t key = s.hkey[slot];
+            const int r = __popcll(key);
+            const int2 c = s.hcnt[slot];
+            double2 d;
+            int rank;
+            if (r <= G) {
+                double2 a[G];
+                lemma_rows<G>(key, r, lane, sH, kb, a);
+                d = c_mul(lb.detB, lu_det<G>(a, r, lane, s.piv + grp * G));
+                rank = r;
+            } else {
+                d = term_det_compact<G>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
+            }
+            if (lane == 0) {
+                s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+                *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
+                wk.rank += (unsigned)rank;
+                wk.flops += r <= G ? lu_flops(r) + 6 : lu_flops(m) + 8ull * m * m * rank;
+            }
+        }
+        __syncthreads();
     }
-    for (int e = tid; e < nl; e += kThreads) s.list[e] &= 0x7FFFu;
-    __syncthreads();
     if (tid == 0) wk.terms += (unsigned)nl;
     accumulate_slots(s, nl, sacc);
 }
