@@ -139,9 +139,9 @@ xf_status xf_trajectory_bound(double eps, double delta, double p_max, double xi,
  * A bitstring whose weight differs from eta, or with bits at or above n, gets
  * p = 0 and A = 0 (passive circuits conserve the weight, Sec. II-B).  B = 0 is
  * a no-op.  Uses plan-owned device scratch (under the determinant lemma, a
- * workspace of up to 4 GiB holding each bitstring's distinct patterns, grown
- * on demand, the call then synchronising hip_stream first); results are
- * bitwise reproducible for fixed inputs. */
+ * workspace holding each bitstring's distinct patterns, see
+ * xf_plan_set_workspace_limit, grown on demand, the call then synchronising
+ * hip_stream first); results are bitwise reproducible for fixed inputs. */
 xf_status xf_probabilities(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, xf_mode mode,
                            int64_t t, uint64_t seed, double *d_prob, double *d_amp,
                            double *d_logp, void *hip_stream);
@@ -174,6 +174,14 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
  *     do not fit in LDS use the LU. */
 typedef enum { XF_EVAL_AUTO = 0, XF_EVAL_LU = 1 } xf_evaluation;
 xf_status xf_plan_set_evaluation(xf_plan *plan, xf_evaluation evaluation);
+
+/* Device memory the determinant-lemma path may use for its workspace
+ * (default 4 GiB; bytes > 0).  Each bitstring needs (t + t/511 + 2) * 16 + 4
+ * bytes; the batch is processed in chunks of as many bitstrings as fit, at
+ * least one.  Results do not depend on the chunking.  Takes effect at the next
+ * xf_probabilities call; a workspace already allocated is kept while large
+ * enough. */
+xf_status xf_plan_set_workspace_limit(xf_plan *plan, uint64_t bytes);
 
 /* Work done by the last xf_probabilities call on this plan (synchronises the
  * device): *count = distinct (bitstring, flip-pattern) determinants

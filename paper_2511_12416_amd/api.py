@@ -131,6 +131,11 @@ class Plan:
             raise ValueError(f"evaluation must be one of {sorted(_EVAL)}")
         check(lib().xf_plan_set_evaluation(self._h, _EVAL[evaluation]))
 
+    def set_workspace_limit(self, nbytes: int) -> None:
+        """Device memory the determinant-lemma workspace may use (bitstrings
+        are processed in chunks that fit, at least one at a time)."""
+        check(lib().xf_plan_set_workspace_limit(self._h, int(nbytes)))
+
     # -- the hot path ---------------------------------------------------------
     def probabilities(self, bits: torch.Tensor, mode: str = "exact", t: int = 0, seed: int = 0,
                       out: Optional[torch.Tensor] = None, amp: Optional[torch.Tensor] = None,

@@ -159,6 +159,7 @@ struct xf_plan {
     int last_lemma = 0;               // the last xf_probabilities call used the determinant lemma
     // determinant-lemma workspace: per-bitstring regions of (pattern, count) entries
     DevBuf dekey, decnt, decount;
+    uint64_t entry_budget = 4ull << 30;   // bytes of workspace the chunking aims at
     // timing of the last call: ev[0] start, then per chunk (mid, end) of the
     // two lemma kernels, or one end event for a fused kernel
     std::vector<hipEvent_t> ev;
@@ -436,9 +437,7 @@ xf_status ensure_events(xf_plan *P, size_t n) {
     return ok();
 }
 
-// Device-memory budget of the determinant-lemma workspace: bitstrings are
-// processed in chunks whose entry regions fit in it.
-constexpr uint64_t kEntryBudget = 4ull << 30;
+
 
 xf_status set_gate_tables(xf_plan *P) {
     // signs of the angles (phase i or -i of a d_1 choice)
@@ -653,7 +652,8 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
         const int alg = P->evaluation == XF_EVAL_LU ? 1 : 0;
         if (xf::raw_estimate_uses_lemma(d, alg)) {
             const uint64_t cap = xf::lemma_entry_cap(t);
-            const int64_t per = (int64_t)std::max<uint64_t>(1, kEntryBudget / (cap * 16 + 4));
+            // bitstrings are processed in chunks whose entry regions fit in the budget
+            const int64_t per = (int64_t)std::max<uint64_t>(1, P->entry_budget / (cap * 16 + 4));
             const int64_t chunk = std::min<int64_t>(B, per);
             const int64_t nchunks = (B + chunk - 1) / chunk;
             if ((st = ensure_events(P, 1 + 2 * (size_t)nchunks))) return st;
@@ -724,6 +724,13 @@ xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
         if (P->last_lemma && (i & 1)) work->sample_ms += ms;
         else work->eval_ms += ms;
     }
+    return ok();
+}
+
+xf_status xf_plan_set_workspace_limit(xf_plan *P, uint64_t bytes) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    if (bytes == 0) return fail(XF_EINVAL, "workspace limit must be positive");
+    P->entry_budget = bytes;
     return ok();
 }
 

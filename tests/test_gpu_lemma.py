@@ -194,3 +194,23 @@ def test_two_layers_do_not_use_lemma(X):
     plan = make_plan(w, X)
     _, wk = _probs(plan, X, w.bits, 200, 2, "auto")
     assert not wk["lemma"]
+
+
+def test_workspace_chunking_is_invisible(X):
+    """A workspace limit that forces chunks of a few bitstrings gives bitwise
+    the same probabilities as one chunk, and both match the oracle."""
+    w = W.random_circuit(508, 14, 7, 12, n_rot=2, theta_scale=1.0)
+    w.bits = w.bits[:300]
+    say(f"workspace chunking: {w.bits.shape[0]} bitstrings, t=3000")
+    plan = make_plan(w, X)
+    p1, wk1 = _probs(plan, X, w.bits, 3000, 6, "auto")
+    cap = 3000 + 3000 // 511 + 2
+    plan.set_workspace_limit(7 * (cap * 16 + 4))
+    p7, wk7 = _probs(plan, X, w.bits, 3000, 6, "auto")
+    plan.set_workspace_limit(1)
+    p_one, _ = _probs(plan, X, w.bits, 3000, 6, "auto")
+    assert wk1["lemma"] and wk7["lemma"]
+    assert np.array_equal(p1, p7) and np.array_equal(p1, p_one)
+    assert wk1["determinants"] == wk7["determinants"]
+    ref = oracle_probs(w, w.bits, mode="approx", t=3000, seed=6)
+    _check(p7, ref, TOL_FP64, "chunks of 7")
