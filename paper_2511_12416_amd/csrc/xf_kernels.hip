@@ -683,11 +683,12 @@ __device__ __forceinline__ double2 acc_value(const uint64_t *sacc) {
 
 // Gathers the occupied slots of the hash (non-zero count) into s.list, in no
 // particular order.  Returns the number of entries.
+template <int NT = kThreads>
 __device__ __forceinline__ int gather_list(const RawSmem &s, int *s_n) {
     const int tid = threadIdx.x;
     if (tid == 0) *s_n = 0;
     __syncthreads();
-    for (int i = tid; i < kHashSlots; i += kThreads) {
+    for (int i = tid; i < kHashSlots; i += NT) {
         if (s.hkey[i] != kEmptyKey && (s.hcnt[i].x != 0 || s.hcnt[i].y != 0)) {
             const int at = atomicAdd(s_n, 1);
             if (at < kHashSlots) s.list[at] = (uint16_t)i;
@@ -698,10 +699,9 @@ __device__ __forceinline__ int gather_list(const RawSmem &s, int *s_n) {
 }
 
 // Empties the table and re-reserves the slot of the empty flip pattern.
-// Samples each thread draws per pass of the sampler, and the table fill past
-// which a pass is not started (the table is evaluated and cleared first).
-constexpr int kSamplesPerThread = 4;
-constexpr uint32_t kBatch = (uint32_t)kThreads * kSamplesPerThread;
+// Samples per pass of the sampler, and the table fill past which a pass is
+// not started (the table is evaluated and cleared first).
+constexpr uint32_t kBatch = 1024;
 constexpr int kFlushAt = (3 * kHashSlots) / 4;
 static_assert(kBatch + 1 <= (uint32_t)kFlushAt, "a fresh table must take a whole batch");
 static_assert(kBatch * 4 <= (uint32_t)kHashSlots * 2 && kBatch * 4 <= (uint32_t)kThreads * 16,
@@ -716,10 +716,11 @@ struct Sampler {
 
 // Empties the hash table (slot0 keeps the empty flip pattern) and the six
 // sampler counters cnt[0..5].  Whole workgroup.
+template <int NT = kThreads>
 __device__ __forceinline__ void clear_table(const RawSmem &s, int *cnt, uint32_t slot0, Sampler &st) {
     const int tid = threadIdx.x;
     __syncthreads();
-    for (int i = tid; i < kHashSlots; i += kThreads) {
+    for (int i = tid; i < kHashSlots; i += NT) {
         s.hkey[i] = kEmptyKey;
         s.hcnt[i] = make_int2(0, 0);
     }
@@ -782,7 +783,7 @@ __device__ __forceinline__ bool draw_trajectory(const DevPlan &p, const RawSmem 
 // all t samples are in (returns true) or the next batch could push the table
 // past kFlushAt slots (returns false; that batch is drawn again after the
 // table has been evaluated and cleared).  A batch runs in two phases: every
-// thread takes the first draw of kSamplesPerThread samples, which decides
+// thread takes the first draw of kBatch / NT samples, which decides
 // whether the sample sets any gate at all (u < T[0][k-1]); the indices of the
 // samples that do are queued in LDS, and after the barrier the workgroup
 // draws those trajectories to the end and inserts them, so the long draws
@@ -796,6 +797,7 @@ __device__ __forceinline__ bool draw_trajectory(const DevPlan &p, const RawSmem 
 // the queue alternates between two buffers (the list and pivot scratch, free
 // while sampling).  Whole workgroup; s.T / s.gkey loaded (load_tables); the table
 // cleared (clear_table) before the first call and between calls.
+template <int NT = kThreads>
 __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSmem &s, int *cnt,
                                                    uint32_t slot0, int64_t b, uint32_t t, uint32_t k0,
                                                    uint32_t k1, Sampler &st) {
@@ -804,11 +806,13 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
     const uint32_t blo = (uint32_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
     const uint32_t any = p.k > 0 ? s.T[p.k - 1] : 0u;   // T[0][k-1]
     int *pend = cnt, *added = cnt + 3;
+    constexpr int SPT = (int)(kBatch / NT);   // samples per thread per batch
+    static_assert(SPT * NT == (int)kBatch, "the batch is a whole number of samples per thread");
     for (; st.next < t; st.next += kBatch, ++st.j) {
         uint32_t *queue = (st.j & 1) ? (uint32_t *)s.piv : (uint32_t *)s.list;
 #pragma unroll
-        for (int q = 0; q < kSamplesPerThread; ++q) {
-            const uint32_t smp = st.next + (uint32_t)(q * kThreads + tid);
+        for (int q = 0; q < SPT; ++q) {
+            const uint32_t smp = st.next + (uint32_t)(q * NT + tid);
             const bool hit = smp < t && philox10(make_uint4(smp, 0u, blo, bhi), k0, k1).x < any;
             const uint64_t ball = __ballot(hit);
             int at = 0;
@@ -829,7 +833,7 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
             if (live > pending) atomicAdd(&s.hcnt[slot0].x, live - pending);
         }
         int fresh = 0;
-        for (int i = tid; i < pending; i += kThreads) {
+        for (int i = tid; i < pending; i += NT) {
             const uint32_t smp = queue[i];
             uint64_t key;
             uint32_t e;
@@ -1438,15 +1442,16 @@ __device__ __forceinline__ void sum_entries(const DevPlan &p, const RawSmem &s, 
     accumulate_slots(s, nl, sacc);
 }
 
+template <int NT = kThreads>
 __device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) {
     const int tid = threadIdx.x;
     const int k = p.k;
     const int kp = s.kpad;
-    for (int i = tid; i < k * kp; i += kThreads) {
+    for (int i = tid; i < k * kp; i += NT) {
         const int a = i / kp, j = i % kp;
         s.T[i] = j < k ? p.T[a * k + j] : 0xFFFFFFFFu;
     }
-    for (int i = tid; i < k; i += kThreads) s.gkey[i] = p.gkey[i] | ((uint64_t)(p.gneg[i] != 0) << 63);
+    for (int i = tid; i < k; i += NT) s.gkey[i] = p.gkey[i] | ((uint64_t)(p.gneg[i] != 0) << 63);
 }
 
 // Raw Estimate with the LU per distinct pattern, sampling and evaluation fused
@@ -1518,6 +1523,9 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
 //     chunks of kHashSlots, summing count * det exactly.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kEntryInvalid = 0xFFFFFFFFu;    // bitstring of the wrong weight: p = 0
+// The sampler kernel runs eight waves per workgroup: its LDS (the table) then
+// serves twice the waves, and its few registers allow them.
+constexpr int kSamplerThreads = 512;
 constexpr uint32_t kEntryOverflow = 0xFFFFFFFEu;   // more entries than the region holds
 
 __host__ __device__ __forceinline__ size_t sampler_head_bytes(int k) {
@@ -1546,7 +1554,8 @@ __device__ __forceinline__ RawSmem carve_sampler(unsigned char *smem, int k) {
     return s;
 }
 
-__global__ void __launch_bounds__(kThreads)
+template <int NT>
+__global__ void __launch_bounds__(NT)
 k_sample_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
                  uint64_t *__restrict__ ekey, int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount,
                  uint64_t cap) {
@@ -1555,7 +1564,7 @@ k_sample_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64
     __shared__ int s_cnt[6];
     const RawSmem s = carve_sampler(smem, p.k);
     const int tid = threadIdx.x;
-    load_tables(p, s);
+    load_tables<NT>(p, s);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t slot0 = hash_slot(0);
     for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
@@ -1569,12 +1578,12 @@ k_sample_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64
         uint64_t cursor = 0;
         bool overflow = false;
         Sampler st;
-        clear_table(s, s_cnt, slot0, st);
+        clear_table<NT>(s, s_cnt, slot0, st);
         while (true) {
-            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = gather_list(s, &s_n);
+            const bool done = sample_until_flush<NT>(p, s, s_cnt, slot0, b, t, k0, k1, st);
+            const int nl = gather_list<NT>(s, &s_n);
             if (cursor + (uint64_t)nl <= cap) {
-                for (int e = tid; e < nl; e += kThreads) {
+                for (int e = tid; e < nl; e += NT) {
                     const uint16_t slot = s.list[e];
                     kout[cursor + e] = s.hkey[slot];
                     cout[cursor + e] = s.hcnt[slot];
@@ -1584,7 +1593,7 @@ k_sample_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64
             }
             cursor += (uint64_t)nl;
             if (done) break;
-            clear_table(s, s_cnt, slot0, st);
+            clear_table<NT>(s, s_cnt, slot0, st);
         }
         if (tid == 0) ecount[i] = overflow ? kEntryOverflow : (uint32_t)cursor;
     }
@@ -2045,7 +2054,7 @@ hipError_t set_lds_limits() {
         return e;
     if constexpr (G <= 16) {
         for (const void *f : {(const void *)k_raw_estimate<G, false, 1>, (const void *)k_raw_estimate<G, true, 1>,
-                              (const void *)k_eval_entries<G>, (const void *)k_sample_entries})
+                              (const void *)k_eval_entries<G>, (const void *)k_sample_entries<kSamplerThreads>})
             if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
                 return e;
     }
@@ -2089,8 +2098,8 @@ hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0
                               double *prob, double *amp, double *logp, unsigned long long *nterm,
                               hipEvent_t ev_mid, hipStream_t s) {
     const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
-    hipLaunchKernelGGL(k_sample_entries, dim3(grid), dim3(kThreads), sampler_lds_bytes(p.k), s, p, bits, b0, nb,
-                       (uint32_t)t, seed, ekey, ecnt, ecount, cap);
+    hipLaunchKernelGGL((k_sample_entries<kSamplerThreads>), dim3(grid), dim3(kSamplerThreads),
+                       sampler_lds_bytes(p.k), s, p, bits, b0, nb, (uint32_t)t, seed, ekey, ecnt, ecount, cap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
