@@ -290,54 +290,6 @@ __device__ __forceinline__ double2 lu_det(double2 (&a)[G], int m, int lane, doub
     return (inversions & 1) ? make_double2(-det.x, -det.y) : det;
 }
 
-// The same elimination with the column loop kept rolled: after each step the
-// rows are shifted left by one entry, so the pivot column is always a[0] and
-// every index stays static (no private-memory arrays).  About twice the
-// multiply-adds of lu_det but a tenth of its code, for the rarely taken
-// evaluations of the determinant-lemma kernel, whose code must stay small
-// enough for the instruction cache.  Consumes a.
-template <int G>
-__device__ __forceinline__ double2 lu_det_compact(double2 (&a)[G], int m, int lane, double2 *piv) {
-    bool active = lane < m;
-    bool live = true;
-    unsigned inversions = 0;
-    double2 det = make_double2(1.0, 0.0);
-#pragma unroll 1
-    for (int c = 0; c < m && live; ++c) {
-        const double v = active ? fma(a[0].x, a[0].x, a[0].y * a[0].y) : -1.0;
-        const double vmax = group_max<G>(v);
-        const uint64_t act = group_bits<G>(active);
-        const uint64_t hit = group_bits<G>(active && v == vmax);
-        if (!(vmax > 0.0) || hit == 0) {
-            live = false;
-            continue;
-        }
-        const int idx = __ffsll((long long)hit) - 1;
-        inversions += __popcll(act & ((1ull << idx) - 1));
-        if (lane == idx) {
-            active = false;
-#pragma unroll
-            for (int j = 0; j < G; ++j) piv[j] = a[j];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const double2 u = piv[0];
-        det = c_mul(det, u);
-        if (active) {
-            const double inv = 1.0 / fma(u.x, u.x, u.y * u.y);
-            const double2 l = c_mul(a[0], make_double2(-u.x * inv, u.y * inv));
-#pragma unroll
-            for (int j = 1; j < G; ++j) a[j] = c_fma(a[j], l, piv[j]);
-        }
-#pragma unroll
-        for (int j = 0; j + 1 < G; ++j) a[j] = a[j + 1];
-        a[G - 1] = make_double2(0.0, 0.0);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
-    if (!live) return make_double2(0.0, 0.0);
-    return (inversions & 1) ? make_double2(-det.x, -det.y) : det;
-}
 
 
 struct RawSmem {
@@ -603,6 +555,11 @@ __device__ __forceinline__ void fix_wave_sum(Fix192 &a) {
         fix_add(a, x0, x1, x2);
     }
 }
+
+// Markers in the per-bitstring entry counts of the determinant-lemma workspace.
+constexpr uint32_t kEntryInvalid = 0xFFFFFFFFu;    // bitstring of the wrong weight: p = 0
+constexpr uint32_t kEntryOverflow = 0xFFFFFFFEu;   // more entries than the region holds
+constexpr uint32_t kEntryDeferred = 0xFFFFFFFDu;   // left to the LU kernel (see k_eval_entries)
 
 // Per-bitstring sum kept in LDS between tables, as 7 words: the real and
 // imaginary Fix192 (w0, w1, w2 each) and a flag for bad values.
@@ -1235,22 +1192,6 @@ __device__ __forceinline__ double2 lemma_small_det(uint64_t key, const double2 *
 }
 
 
-// det M_N by a lane group with the rolled elimination (rare fallback paths
-// of the determinant-lemma kernel, kept small in registers and code).
-template <int G>
-__device__ __forceinline__ double2 term_det_compact(const DevPlan &p, uint64_t key, const uint8_t *Rb, int lane,
-                                                    double2 *piv, int *rank) {
-    double2 a[G];
-    const Flips f = decode_key(p, key);
-    *rank = __popcll(f.n0[0]) + __popcll(f.n0[1]) + __popcll(f.n1[0]) + __popcll(f.n1[1]);
-    if (lane < p.m) {
-        compose_row<G, false>(p, Rb[lane], f, a);
-    } else {
-#pragma unroll
-        for (int j = 0; j < G; ++j) a[j] = make_double2(j == lane ? 1.0 : 0.0, 0.0);
-    }
-    return lu_det_compact<G>(a, p.m, lane, piv);
-}
 
 // Rows of I - 2 H[N, N] for the r set bits of key, one row per lane of a
 // group of GS lanes (rows and columns >= r are those of the identity).
@@ -1285,130 +1226,108 @@ __device__ __forceinline__ void lemma_rows(uint64_t key, int r, int lane, const 
 // first classified by r, the number of flipped modes:
 //   easy (r <= kLemmaMaxRank): one lane each, taken in order of r (counting
 //      sort) so that the lanes of a wave run the same number of steps;
-//   mid (G = 16, kLemmaMaxRank < r <= 8): the r x r matrix I - 2 H[N, N]
-//      factored by 8-lane groups;
-//   hard (r > that): the r x r matrix by G-lane groups when r <= G, else the
-//      LU of M_N itself.
-// A bitstring that failed the conditioning test (or a table with more mid and
-// hard entries than the short list holds) takes the LU of M_N for every
-// entry.  Values go into the slots and are added to the bitstring's sum.
+//   mid (kLemmaMaxRank < r <= 8): the r x r matrix I - 2 H[N, N] factored by
+//      8-lane groups;
+//   hard (8 < r <= G): the same with G-lane groups.
+// A table with a larger pattern (r > G, nine or more flipped CPhase gates,
+// or more mid and hard patterns than the short list holds) is not
+// evaluated: the call returns false and the bitstring is left to the LU
+// kernel, which keeps the composition of M_N out of this kernel.  Values go
+// into the slots and are added to the bitstring's sum.
+constexpr int kLemmaMid = 8;
+
 template <int G>
-__device__ __forceinline__ void sum_entries_lemma(const DevPlan &p, const RawSmem &s, int nl,
+__device__ __forceinline__ bool sum_entries_lemma(const DevPlan &p, const RawSmem &s, int nl,
                                                   const double2 *sH, const LemmaBits &lb, Work &wk,
                                                   uint64_t *sacc) {
     const int tid = threadIdx.x;
-    const int m = p.m, kb = p.keybits;
-    const int lane = tid % G, grp = tid / G;
-    constexpr int NG = kThreads / G;
-    constexpr int kMid = G > 8 ? 8 : kLemmaMaxRank;     // largest r of the mid class
-    constexpr int kHardCap = (kThreads * 16 - 64) / 2;  // u16 entries after 64 B of counters
-    int *cnt = (int *)s.red;              // [0..6] easy bins, 7 easy, 8 mid, 9 hard, 10/11 cursors
+    const int kb = p.keybits;
+    int *cnt = (int *)s.red;  // [0..4] easy bins, 7 easy, 8 mid, 9 larger, 10 mid / 11 hard cursor, 12 hard
     uint16_t *order = (uint16_t *)s.piv;  // easy entries by r (the pivot scratch is free until then)
-    uint16_t *hard = (uint16_t *)s.red + 32;
-    bool full_lu = !lb.ok;
-    if (!full_lu) {
-        if (tid < 12) cnt[tid] = 0;
-        __syncthreads();
-        for (int e = tid; e < nl; e += kThreads) {
-            const int r = __popcll(s.hkey[s.list[e]]);
-            atomicAdd(&cnt[r <= kLemmaMaxRank ? r : (r <= kMid ? 8 : 9)], 1);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int acc = 0;
-            for (int r = 0; r <= kLemmaMaxRank; ++r) {
-                const int h = cnt[r];
-                cnt[r] = acc;
-                acc += h;
-            }
-            cnt[7] = acc;
-            cnt[10] = 0;
-            cnt[11] = cnt[8];
-        }
-        __syncthreads();
-        full_lu = cnt[8] + cnt[9] > kHardCap;
+    uint16_t *mid = (uint16_t *)s.red + 32;
+    constexpr int kMidCap = (kThreads * 16 - 64) / 2;   // u16 entries after 64 B of counters
+    constexpr int kHardMax = G > kLemmaMid ? G : kLemmaMid;
+    if (tid < 13) cnt[tid] = 0;
+    __syncthreads();
+    for (int e = tid; e < nl; e += kThreads) {
+        const int r = __popcll(s.hkey[s.list[e]]);
+        atomicAdd(&cnt[r <= kLemmaMaxRank ? r : (r <= kLemmaMid ? 8 : (r <= kHardMax ? 12 : 9))], 1);
     }
-    if (full_lu) {
-        for (int e = grp; e < nl; e += NG) {
-            const uint16_t slot = s.list[e];
-            const uint64_t key = s.hkey[slot];
-            const int2 c = s.hcnt[slot];
-            int rank;
-            const double2 d = term_det_compact<G>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
-            if (lane == 0) {
-                s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
-                *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
-                wk.rank += (unsigned)rank;
-                wk.flops += lu_flops(m) + 8ull * m * m * rank;
-            }
+    __syncthreads();
+    if (cnt[9] > 0 || cnt[8] + cnt[12] > kMidCap) return false;
+    if (tid == 0) {
+        int acc = 0;
+        for (int r = 0; r <= kLemmaMaxRank; ++r) {
+            const int h = cnt[r];
+            cnt[r] = acc;
+            acc += h;
         }
-        __syncthreads();
-    } else {
-        const int n_easy = cnt[7], n_mid = cnt[8], n_hard = cnt[9];
-        for (int e = tid; e < nl; e += kThreads) {
-            const uint16_t slot = s.list[e];
-            const int r = __popcll(s.hkey[slot]);
-            if (r <= kLemmaMaxRank) order[atomicAdd(&cnt[r], 1)] = slot;
-            else hard[atomicAdd(&cnt[r <= kMid ? 10 : 11], 1)] = slot;
-        }
-        __syncthreads();
-        for (int i = tid; i < n_easy; i += kThreads) {
-            const uint16_t slot = order[i];
-            const uint64_t key = s.hkey[slot];
-            const int r = __popcll(key);
-            const int2 c = s.hcnt[slot];
-            const double2 d = c_mul(lb.detB, lemma_small_det(key, sH, kb));
-            s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
-            *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
-            wk.rank += (unsigned)r;
-            wk.flops += lu_flops(r) + 6;
-        }
-        __syncthreads();
-        if constexpr (G > 8) {
-            const int l8 = tid & 7, g8 = tid >> 3;
-            for (int i = g8; i < n_mid; i += kThreads / 8) {
-                const uint16_t slot = hard[i];
-                const uint64_t key = s.hkey[slot];
-                const int r = __popcll(key);
-                const int2 c = s.hcnt[slot];
-                double2 a[8];
-                lemma_rows<8>(key, r, l8, sH, kb, a);
-                const double2 d = c_mul(lb.detB, lu_det<8>(a, r, l8, s.piv + g8 * 8));
-                if (l8 == 0) {
-                    s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
-                    *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
-                    wk.rank += (unsigned)r;
-                    wk.flops += lu_flops(r) + 6;
-                }
-            }
-            __syncthreads();
-        }
-        for (int i = n_mid + grp; i < n_mid + n_hard; i += NG) {
-            const uint16_t slot = hard[i];
+        cnt[7] = acc;
+        cnt[10] = 0;
+        cnt[11] = cnt[8];
+    }
+    __syncthreads();
+    const int n_easy = cnt[7], n_mid = cnt[8], n_hard = cnt[12];
+    for (int e = tid; e < nl; e += kThreads) {
+        const uint16_t slot = s.list[e];
+        const int r = __popcll(s.hkey[slot]);
+        if (r <= kLemmaMaxRank) order[atomicAdd(&cnt[r], 1)] = slot;
+        else mid[atomicAdd(&cnt[r <= kLemmaMid ? 10 : 11], 1)] = slot;
+    }
+    __syncthreads();
+    for (int i = tid; i < n_easy; i += kThreads) {
+        const uint16_t slot = order[i];
+        const uint64_t key = s.hkey[slot];
+        const int r = __popcll(key);
+        const int2 c = s.hcnt[slot];
+        const double2 d = c_mul(lb.detB, lemma_small_det(key, sH, kb));
+        s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+        *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
+        wk.rank += (unsigned)r;
+        wk.flops += lu_flops(r) + 6;
+    }
+    __syncthreads();
+    {
+        const int l8 = tid & 7, g8 = tid >> 3;
+        for (int i = g8; i < n_mid; i += kThreads / 8) {
+            const uint16_t slot = mid[i];
             const uint64_t key = s.hkey[slot];
             const int r = __popcll(key);
             const int2 c = s.hcnt[slot];
-            double2 d;
-            int rank;
-            if (r <= G) {
-                double2 a[G];
-                lemma_rows<G>(key, r, lane, sH, kb, a);
-                d = c_mul(lb.detB, lu_det<G>(a, r, lane, s.piv + grp * G));
-                rank = r;
-            } else {
-                d = term_det_compact<G>(p, key, s.Rb, lane, s.piv + grp * G, &rank);
+            double2 a[kLemmaMid];
+            lemma_rows<kLemmaMid>(key, r, l8, sH, kb, a);
+            const double2 d = c_mul(lb.detB, lu_det<kLemmaMid>(a, r, l8, s.piv + g8 * kLemmaMid));
+            if (l8 == 0) {
+                s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
+                *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
+                wk.rank += (unsigned)r;
+                wk.flops += lu_flops(r) + 6;
             }
+        }
+        __syncthreads();
+    }
+    if constexpr (G > kLemmaMid) {
+        const int lane = tid % G, grp = tid / G;
+        for (int i = n_mid + grp; i < n_mid + n_hard; i += kThreads / G) {
+            const uint16_t slot = mid[i];
+            const uint64_t key = s.hkey[slot];
+            const int r = __popcll(key);
+            const int2 c = s.hcnt[slot];
+            double2 a[G];
+            lemma_rows<G>(key, r, lane, sH, kb, a);
+            const double2 d = c_mul(lb.detB, lu_det<G>(a, r, lane, s.piv + grp * G));
             if (lane == 0) {
                 s.hkey[slot] = (uint64_t)__double_as_longlong((double)c.x * d.x - (double)c.y * d.y);
                 *(double *)&s.hcnt[slot] = (double)c.x * d.y + (double)c.y * d.x;
-                wk.rank += (unsigned)rank;
-                wk.flops += r <= G ? lu_flops(r) + 6 : lu_flops(m) + 8ull * m * m * rank;
+                wk.rank += (unsigned)r;
+                wk.flops += lu_flops(r) + 6;
             }
         }
         __syncthreads();
     }
     if (tid == 0) wk.terms += (unsigned)nl;
     accumulate_slots(s, nl, sacc);
+    return true;
 }
 
 // Sum over the entries of count * det.  Each group evaluates entries
@@ -1461,9 +1380,9 @@ __device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) 
 // loop-invariant values spill around the bitstring loop).
 template <int G, bool MIXED, int KIND>
 __global__ void __launch_bounds__(kThreads, G <= 16 ? 2 : 1)
-k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
+k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
                double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
-               unsigned long long *nterm) {
+               unsigned long long *nterm, const uint32_t *__restrict__ only) {
     constexpr bool STAGE = KIND == 1;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok, s_n;
@@ -1472,12 +1391,19 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
     const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
     const int tid = threadIdx.x;
     Work wk;
-    load_tables(p, s);
-    if constexpr (STAGE) stage_phi<MIXED>(p, s);
+    bool loaded = false;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t slot0 = hash_slot(0);
 
-    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        // with `only`, just the bitstrings the lemma kernels deferred
+        if (only && only[i] != kEntryDeferred) continue;
+        const int64_t b = b0 + i;
+        if (!loaded) {
+            load_tables(p, s);
+            if constexpr (STAGE) stage_phi<MIXED>(p, s);
+            loaded = true;
+        }
         if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) {
             if (tid == 0) {
                 prob[b] = 0.0;
@@ -1522,11 +1448,9 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t
 //   k_eval_entries: forms H for the bitstring and evaluates the entries in
 //     chunks of kHashSlots, summing count * det exactly.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kEntryInvalid = 0xFFFFFFFFu;    // bitstring of the wrong weight: p = 0
 // The sampler kernel runs eight waves per workgroup: its LDS (the table) then
 // serves twice the waves, and its few registers allow them.
 constexpr int kSamplerThreads = 512;
-constexpr uint32_t kEntryOverflow = 0xFFFFFFFEu;   // more entries than the region holds
 
 __host__ __device__ __forceinline__ size_t sampler_head_bytes(int k) {
     return align16((size_t)kHashSlots * (8 + 8 + 2) + (size_t)kThreads * 16 + 64 + (size_t)k * 8);
@@ -1603,7 +1527,7 @@ template <int G>
 __global__ void __launch_bounds__(kThreads, 2)
 k_eval_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
                const uint64_t *__restrict__ ekey, const int2 *__restrict__ ecnt,
-               const uint32_t *__restrict__ ecount, uint64_t cap, double *__restrict__ prob,
+               uint32_t *__restrict__ ecount, uint64_t cap, double *__restrict__ prob,
                double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok, s_flag;
@@ -1630,10 +1554,11 @@ k_eval_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t
             total = make_double2(__longlong_as_double(0x7FF8000000000000ll), 0.0);
         } else {
             const LemmaBits lb = lemma_setup<G>(p, s, sH, &s_flag, &s_det, wk);
+            bool ok = lb.ok;
             acc_clear(s_acc);
             const uint64_t *kin = ekey + (size_t)i * cap;
             const int2 *cin = ecnt + (size_t)i * cap;
-            for (uint32_t c0 = 0; c0 < ne; c0 += kHashSlots) {
+            for (uint32_t c0 = 0; ok && c0 < ne; c0 += kHashSlots) {
                 const int nc = (int)min((uint32_t)kHashSlots, ne - c0);
                 for (int e = tid; e < nc; e += kThreads) {
                     s.hkey[e] = kin[c0 + e];
@@ -1641,7 +1566,14 @@ k_eval_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t
                     s.list[e] = (uint16_t)e;
                 }
                 __syncthreads();
-                sum_entries_lemma<G>(p, s, nc, sH, lb, wk, s_acc);
+                ok = sum_entries_lemma<G>(p, s, nc, sH, lb, wk, s_acc);
+            }
+            if (!ok) {
+                // ill-conditioned base or a pattern with r > G: the LU kernel
+                // that follows recomputes this bitstring
+                if (tid == 0) ecount[i] = kEntryDeferred;
+                __syncthreads();
+                continue;
             }
             total = acc_value(s_acc);
         }
@@ -2000,14 +1932,14 @@ hipError_t launch_raw_t(const DevPlan &p, int algorithm, const uint64_t *bits, i
     if constexpr (G <= 16) {
         if (use_stage(p, MIXED)) {
             const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, true);
-            hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 1>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
-                               (uint32_t)t, seed, prob, amp, logp, nterm);
+            hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 1>), dim3(grid), dim3(kThreads), lds, s, p, bits,
+                               (int64_t)0, B, (uint32_t)t, seed, prob, amp, logp, nterm, nullptr);
             return hipGetLastError();
         }
     }
     const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, false);
-    hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 0>), dim3(grid), dim3(kThreads), lds, s, p, bits, B,
-                       (uint32_t)t, seed, prob, amp, logp, nterm);
+    hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 0>), dim3(grid), dim3(kThreads), lds, s, p, bits, (int64_t)0, B,
+                       (uint32_t)t, seed, prob, amp, logp, nterm, nullptr);
     return hipGetLastError();
 }
 
@@ -2103,9 +2035,22 @@ hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
+    // then the LU kernel for the bitstrings the evaluation deferred (a
+    // workgroup per bitstring that returns at once for the others)
 #define XF_EVAL(GG)                                                                                            \
-    hipLaunchKernelGGL((k_eval_entries<GG>), dim3(grid), dim3(kThreads), lemma_lds(p), s, p, bits, b0, nb, ekey, \
-                       ecnt, ecount, cap, prob, amp, logp, nterm)
+    do {                                                                                                       \
+        hipLaunchKernelGGL((k_eval_entries<GG>), dim3(grid), dim3(kThreads), lemma_lds(p), s, p, bits, b0, nb,   \
+                           ekey, ecnt, ecount, cap, prob, amp, logp, nterm);                                   \
+        if ((e = hipGetLastError()) != hipSuccess) return e;                                                   \
+        if (use_stage(p, false))                                                                               \
+            hipLaunchKernelGGL((k_raw_estimate<GG, false, 1>), dim3(grid), dim3(kThreads),                     \
+                               raw_lds_bytes(p.k, p.n, GG, false, true), s, p, bits, b0, nb, (uint32_t)t, seed,   \
+                               prob, amp, logp, nterm, ecount);                                                \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_raw_estimate<GG, false, 0>), dim3(grid), dim3(kThreads),                     \
+                               raw_lds_bytes(p.k, p.n, GG, false, false), s, p, bits, b0, nb, (uint32_t)t, seed,  \
+                               prob, amp, logp, nterm, ecount);                                                \
+    } while (0)
     switch (p.G) {
         case 4: XF_EVAL(4); break;
         case 8: XF_EVAL(8); break;
