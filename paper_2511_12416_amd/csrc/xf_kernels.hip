@@ -2035,19 +2035,21 @@ hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
-    // then the LU kernel for the bitstrings the evaluation deferred (a
-    // workgroup per bitstring that returns at once for the others)
+    // then the LU kernel for the bitstrings the evaluation deferred, on a
+    // smaller grid (its workgroups skip the other bitstrings at once; the
+    // deferred ones are rare)
+    const int grid_lu = grid < 2048 ? grid : 2048;
 #define XF_EVAL(GG)                                                                                            \
     do {                                                                                                       \
         hipLaunchKernelGGL((k_eval_entries<GG>), dim3(grid), dim3(kThreads), lemma_lds(p), s, p, bits, b0, nb,   \
                            ekey, ecnt, ecount, cap, prob, amp, logp, nterm);                                   \
         if ((e = hipGetLastError()) != hipSuccess) return e;                                                   \
         if (use_stage(p, false))                                                                               \
-            hipLaunchKernelGGL((k_raw_estimate<GG, false, 1>), dim3(grid), dim3(kThreads),                     \
+            hipLaunchKernelGGL((k_raw_estimate<GG, false, 1>), dim3(grid_lu), dim3(kThreads),                  \
                                raw_lds_bytes(p.k, p.n, GG, false, true), s, p, bits, b0, nb, (uint32_t)t, seed,   \
                                prob, amp, logp, nterm, ecount);                                                \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_raw_estimate<GG, false, 0>), dim3(grid), dim3(kThreads),                     \
+            hipLaunchKernelGGL((k_raw_estimate<GG, false, 0>), dim3(grid_lu), dim3(kThreads),                  \
                                raw_lds_bytes(p.k, p.n, GG, false, false), s, p, bits, b0, nb, (uint32_t)t, seed,  \
                                prob, amp, logp, nterm, ecount);                                                \
     } while (0)
