@@ -31,6 +31,7 @@ def X():
 
 
 def _check(p, ref, tol, label):
+    assert np.count_nonzero(ref) > 0, f"{label}: every reference probability is zero"
     e = rel_err(p, ref)
     say(f"  {label}: n={len(p)} max rel err {e.max():.3e} median {np.median(e):.3e}")
     assert np.all(np.isfinite(p))
