@@ -65,8 +65,9 @@ struct GradLayout {
 
 // Launchers (xf_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
-// algorithm: 0 = automatic (determinant lemma where it applies), 1 = LU per
-// distinct term, 2 = determinant lemma where it applies.
+// The fused Raw Estimate kernel (LU per distinct pattern) over the whole
+// batch; the determinant-lemma path is launch_lemma_chunk.  algorithm is the
+// plan's evaluation choice (0 automatic, 1 LU), used by raw_estimate_uses_lemma.
 hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, int algorithm, const uint64_t *bits, int64_t B,
                                int64_t t, uint64_t seed, double *prob, double *amp, double *logp,
                                unsigned long long *nterm, hipStream_t s);
