@@ -47,7 +47,9 @@
  *   - On any error the call returns a non-zero xf_status, writes nothing to
  *     its outputs, and xf_last_error() describes the problem.
  *   - A plan may be used from one host thread at a time; distinct plans are
- *     independent.
+ *     independent.  Calls on one plan share its device scratch (counters,
+ *     workspace): issue them on one stream, or synchronise between calls on
+ *     different streams.
  */
 #ifndef XF_H
 #define XF_H
