@@ -938,15 +938,95 @@ __host__ __device__ __forceinline__ size_t lemma_bytes(int G, int kb) {
     return (size_t)G * G * 16 + align16((size_t)kb * kb * 16);
 }
 
+// Inverse and determinant of the m x m matrix W (LDS, row stride G, m <= G <=
+// 16) by Gauss-Jordan on the augmented rows [W | I], held in the registers of
+// one wave: lane 16 q + i holds columns q G/2 .. q G/2 + G/2 - 1 of row i.
+// Pivoting as in lu_det (the unused row with the largest |a|^2 in the
+// column, lowest row on ties; a DPP max and a ballot); rows stay in their
+// lanes, so row p_c (the pivot of column c) ends as u_c e_c on the left and
+// as u_c times row c of W^-1 on the right.  Each step sends the pivot row and
+// the multiplier column through LDS (xbuf: 2 (2G + 16) entries, one half per
+// step parity).  det W = sign(c -> p_c) prod u_c.  Writes W^-1 to Minv (row
+// stride G) and returns true, or returns false without writing when a pivot
+// column is exactly zero.  Whole wave, wave-uniform m.
+template <int G>
+__device__ __forceinline__ bool gj_inverse_wave(const double2 *W, int m, double2 *Minv, double2 *xbuf,
+                                                double2 &det_out) {
+    static_assert(G % 2 == 0 && G <= 16, "four quarters of G / 2 columns per row");
+    constexpr int CPL = G / 2;
+    const int lane = threadIdx.x & 63, q = lane >> 4, i = lane & 15;
+    double2 a[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int col = q * CPL + j;
+        double2 v = make_double2(0.0, 0.0);
+        if (i < m) v = col < G ? W[i * G + col] : make_double2(col - G == i ? 1.0 : 0.0, 0.0);
+        a[j] = v;
+    }
+    bool active = i < m, live = true;
+    unsigned inversions = 0;
+    double2 det = make_double2(1.0, 0.0), pinv = make_double2(0.0, 0.0);
+    int pstep = 0;
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+        if (c < m && live) {
+            const int qc = c / CPL, jc = c % CPL;
+            const double v = (active && q == qc) ? fma(a[jc].x, a[jc].x, a[jc].y * a[jc].y) : -1.0;
+            const double vmax = group_max<16>(v);
+            const uint64_t hit = (__ballot(q == qc && active && v == vmax && vmax > 0.0) >> (16 * qc)) & 0xFFFFull;
+            if (hit == 0) {
+                live = false;
+            } else {
+                const int p = __ffsll((long long)hit) - 1;
+                inversions += __popcll(__ballot(active) & ((1ull << p) - 1));
+                double2 *prow = xbuf + (c & 1) * (2 * G + 16);
+                double2 *mcol = prow + 2 * G;
+                if (i == p) {
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) prow[q * CPL + j] = a[j];
+                }
+                if (q == qc) mcol[i] = a[jc];
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const double2 u = mcol[p];
+                const double2 mi = mcol[i];
+                double2 r[CPL];
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) r[j] = prow[q * CPL + j];
+                det = c_mul(det, u);
+                const double inv = 1.0 / fma(u.x, u.x, u.y * u.y);
+                const double2 ui = make_double2(u.x * inv, -u.y * inv);
+                if (i == p) {
+                    pstep = c;
+                    pinv = ui;
+                    active = false;
+                } else if (i < m) {
+                    const double2 l = c_mul(mi, ui);
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j)
+                        a[j] = make_double2(a[j].x - (l.x * r[j].x - l.y * r[j].y),
+                                            a[j].y - (l.x * r[j].y + l.y * r[j].x));
+                }
+            }
+        }
+    }
+    if (!live) return false;
+    if (q >= 2 && i < m) {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) Minv[pstep * G + (q - 2) * CPL + j] = c_mul(a[j], pinv);
+    }
+    det_out = (inversions & 1) ? make_double2(-det.x, -det.y) : det;
+    return true;
+}
+
 struct LemmaBits {
     double2 detB;   // det M_0
     int ok;         // lemma usable for this bitstring
 };
 
 // Per-bitstring setup; whole workgroup; FP64 throughout.  M_0 = P[R, :] is
-// copied to sP; the first G lanes of wave 0 invert it by Gauss-Jordan in
-// registers (one row per lane, the same pivot rule as the LU) into the not yet
-// used hash keys, while the other waves copy the operands of X and H.  Then X = M_0^-1 A1[R, act]
+// copied to sP; wave 0 inverts it (gj_inverse_wave) into the not yet used
+// hash keys, while the other waves copy the operands of X and H.  Then X = M_0^-1 A1[R, act]
 // (after V in the hash keys) and H = Phi0[act, :] X into sH.  When
 // m * |act| <= 512 the operands A1[R, act] and Phi0[act, :] are first copied
 // to the hash counts (their loads overlap the elimination).
@@ -957,15 +1037,12 @@ __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem
     double2 *W = s.sP;                        // m x G, left half
     double2 *V = (double2 *)s.hkey;           // m x G, right half -> M_0^-1
     double2 *X = V + G * G;                   // m x kb
-    double2 *mult = s.piv;                    // [G] multipliers of the current step
-    double2 *pinv = s.piv + G;                // [G] inverse pivots
     const bool staged = m * kb <= 512;
     double2 *A1s = (double2 *)s.hcnt;         // m x kb: A1[R, act]
     double2 *Phs = A1s + 512;                 // kb x m: Phi0[act, :]
     for (int i = tid; i < m * G; i += kThreads) {
         const int r = i / G, c = i % G;
         W[i] = p.P[(size_t)s.Rb[r] * G + c];
-        V[i] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     }
     if (tid == 0) {
         *s_flag = 1;
@@ -983,13 +1060,7 @@ __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem
             }
         }
     } else {
-        // Gauss-Jordan on [W | V] by wave 0 alone: lane handles column
-        // lane % 2G of the 2G-wide augmented rows and every (64 / 2G)-th row.
-        static_assert(2 * G <= 64, "one wave holds a column of the augmented matrix per lane");
         const int lane = tid;
-        constexpr int NRS = 64 / (2 * G);
-        const int col = lane % (2 * G), rs = lane / (2 * G);
-        double2 *colp = col < G ? W + col : V + (col - G);
         // ||M_0||_1 (largest column sum of moduli), kept in red[G]
         double cs = 0.0;
         if (lane < m)
@@ -1000,57 +1071,8 @@ __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
         if (lane == 0) s.red[G].x = cs;
-        double2 det = make_double2(1.0, 0.0);
-        bool ok = true;
-        for (int c = 0; c < m; ++c) {
-            double v = -1.0;
-            if (lane >= c && lane < m) {
-                const double2 a = W[lane * G + c];
-                v = fma(a.x, a.x, a.y * a.y);
-            }
-            int idx = lane;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double vo = __shfl_xor(v, off, 64);
-                const int io = __shfl_xor(idx, off, 64);
-                if (vo > v || (vo == v && io < idx)) {
-                    v = vo;
-                    idx = io;
-                }
-            }
-            if (!(v > 0.0)) {
-                ok = false;
-                break;
-            }
-            if (idx != c && rs == 0) {
-                const double2 a = colp[c * G], b = colp[idx * G];
-                colp[c * G] = b;
-                colp[idx * G] = a;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            const double2 u = W[c * G + c];
-            const double inv = 1.0 / fma(u.x, u.x, u.y * u.y);
-            const double2 ui = make_double2(u.x * inv, -u.y * inv);
-            if (lane < m) mult[lane] = lane == c ? make_double2(0.0, 0.0) : c_mul(W[lane * G + c], ui);
-            if (lane == 0) pinv[c] = ui;
-            det = c_mul(det, u);
-            if (idx != c) det = make_double2(-det.x, -det.y);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            // rows i != c: row_i -= mult_i row_c, left columns > c and the right half
-            if (col >= G || col > c) {
-                const double2 rc = colp[c * G];
-                for (int i = rs; i < m; i += NRS) {
-                    if (i == c) continue;
-                    const double2 l = mult[i];
-                    double2 &x = colp[i * G];
-                    x = make_double2(x.x - (l.x * rc.x - l.y * rc.y), x.y - (l.x * rc.y + l.y * rc.x));
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
+        double2 det = make_double2(0.0, 0.0);
+        const bool ok = gj_inverse_wave<G>(W, m, V, s.piv, det);
         if (lane == 0) {
             *s_flag = ok ? 1 : 0;
             *s_det = det;
@@ -1065,9 +1087,6 @@ __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem
         __syncthreads();
         return lb;
     }
-    // M_0^-1 rows: divide by the pivots
-    for (int i = tid; i < m * G; i += kThreads) V[i] = c_mul(V[i], pinv[i / G]);
-    __syncthreads();
     // kappa_1 = ||M_0||_1 ||M_0^-1||_1
     if (tid < 64) {
         double cs = 0.0;
