@@ -461,3 +461,130 @@ def test_expm_adjoint_matches_finite_differences():
             fd = (L(Kp) - L(Km)) / (2 * h)
             an = GK[p, q].real if comp == 1.0 else GK[p, q].imag
             assert abs(fd - an) < 1e-7, (p, q, comp, fd, an)
+
+
+# ----------------------------------------------------------------------------
+# Eq. 6 derived independently (Raw Estimate, Sec. III-A)
+#
+# The estimator averages t i.i.d. complex samples Z_s = sqrt(xi*) phase(x_s)
+# det V(x_s)[R, C] with mean A (|A|^2 = p <= p_max).  Every determinant is that
+# of a submatrix of a unitary matrix, so |det| <= 1 and |Z_s| <= sqrt(xi*);
+# the centred steps (Z_s - A) / t are bounded by c / t with
+# c = sqrt(xi*) + sqrt(p_max).  Their partial sums form a martingale in the
+# plane, so the large-deviation bound for vector-valued martingales with
+# steps of norm <= 1 (T. P. Hayes, "A large-deviation inequality for
+# vector-valued martingales", 2005): P(|X_n| >= a) < 2 e^2 exp(-a^2 / (2 n)),
+# applied to X_t = (t / c) sum_s (Z_s - A) / t, gives
+#     P(|A_hat - A| >= r) < 2 e^2 exp(-t r^2 / (2 c^2)).
+# An amplitude within r of A gives |p_hat - p| <= (2 sqrt(p_max) + r) r,
+# which equals eps for the root r of that quadratic.  The trajectory count of
+# Eq. 6 must be the smallest t for which the tail is at most delta.  The test
+# finds r by bisection and t by an integer search on the tail itself, so it
+# does not restate the closed form.
+# ----------------------------------------------------------------------------
+
+def _hayes_tail(a: float, steps: int) -> float:
+    return 2.0 * math.e ** 2 * math.exp(-a * a / (2.0 * steps))
+
+
+def _amplitude_radius(eps: float, p_max: float) -> float:
+    """Largest r with (2 sqrt(p_max) + r) r <= eps, by bisection."""
+    lo, hi = 0.0, math.sqrt(eps) + 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if (2.0 * math.sqrt(p_max) + mid) * mid <= eps:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+def _derived_count(eps, delta, p_max, xi):
+    c = math.sqrt(xi) + math.sqrt(p_max)
+    r = _amplitude_radius(eps, p_max)
+
+    def tail(t):
+        return _hayes_tail(r * t / c, t)
+
+    hi = 1
+    while tail(hi) > delta:
+        hi *= 2
+    lo = hi // 2 if hi > 1 else 0      # tail(lo) > delta (or lo = 0)
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if tail(mid) > delta:
+            lo = mid
+        else:
+            hi = mid
+    return hi, tail
+
+
+_EQ6_GRID = [(eps, delta, p_max, xi)
+             for eps in (1e-3, 7.3e-3, 0.05)
+             for delta in (1e-6, 0.013, 0.2)
+             for p_max in (0.0, 0.011, 0.37, 1.0)
+             for xi in (1.0, 1.732, 5.281, 228.091)]
+
+
+def test_trajectory_bound_is_the_smallest_count_the_tail_bound_allows():
+    for eps, delta, p_max, xi in _EQ6_GRID:
+        t = oracle.trajectory_bound(eps, delta, p_max, xi)
+        want, tail = _derived_count(eps, delta, p_max, xi)
+        assert t == want, (eps, delta, p_max, xi, t, want)
+        assert tail(t) <= delta < tail(t - 1)
+
+
+def test_trajectory_bound_pin_catches_a_wrong_log_or_constant():
+    """The derivation above separates Eq. 6 from plausible misreadings: a
+    base-10 logarithm, or e^2 in place of 2 e^2 inside the logarithm."""
+    def variant(eps, delta, p_max, xi, log, const):
+        num = (math.sqrt(xi) + math.sqrt(p_max)) ** 2
+        den = (math.sqrt(p_max + eps) - math.sqrt(p_max)) ** 2
+        return math.ceil(2.0 * num / den * log(const / delta))
+
+    for log, const in ((math.log10, 2 * math.e ** 2), (math.log, math.e ** 2), (math.log, 2.0)):
+        wrong = sum(variant(*g, log, const) != _derived_count(*g)[0] for g in _EQ6_GRID)
+        assert wrong == len(_EQ6_GRID), (log, const, wrong)
+
+
+def test_amplitude_radius_bounds_the_probability_error():
+    """Brute force over amplitudes |A|^2 <= p_max and estimates within r of A:
+    the worst |p_hat - p| approaches eps and never exceeds it."""
+    rng = np.random.default_rng(61)
+    for eps, p_max in ((1e-3, 0.3), (0.05, 1.0), (0.02, 0.0)):
+        r = _amplitude_radius(eps, p_max)
+        a = np.sqrt(p_max) * np.sqrt(rng.uniform(0, 1, 20000)) * np.exp(2j * np.pi * rng.uniform(0, 1, 20000))
+        a[:100] = math.sqrt(p_max)           # the extreme modulus
+        d = r * np.sqrt(rng.uniform(0, 1, 20000)) * np.exp(2j * np.pi * rng.uniform(0, 1, 20000))
+        d[:100] = r                          # aligned with the extreme amplitude
+        err = np.abs(np.abs(a + d) ** 2 - np.abs(a) ** 2)
+        assert err.max() <= eps * (1 + 1e-12)
+        assert err.max() >= eps * (1 - 1e-9)
+
+
+def test_sampled_determinants_are_bounded_by_one():
+    """The step bound uses |det V(x)[R, C]| <= 1 (V(x) unitary): checked on
+    the oracle's own determinant for submatrices of Haar unitaries."""
+    rng = np.random.default_rng(62)
+    worst = 0.0
+    for _ in range(200):
+        n = int(rng.integers(2, 12))
+        m = int(rng.integers(1, n + 1))
+        U = W.haar_unitary(rng, n)
+        R = np.sort(rng.choice(n, m, replace=False))
+        C = np.sort(rng.choice(n, m, replace=False))
+        worst = max(worst, abs(oracle.det(U[np.ix_(R, C)])))
+    assert worst <= 1.0 + 1e-12
+
+
+def test_hayes_bound_holds_for_bounded_planar_walks():
+    """Monte Carlo of worst-case-like planar martingales (steps of norm exactly
+    1 in random directions, and +-1 along one axis): the empirical tail stays
+    below the bound used above."""
+    rng = np.random.default_rng(63)
+    n, trials = 200, 20000
+    ang = rng.uniform(0, 2 * np.pi, (trials, n))
+    walks = [np.abs(np.exp(1j * ang).sum(1)), np.abs(rng.choice([-1.0, 1.0], (trials, n)).sum(1))]
+    for x in walks:
+        for a in (20.0, 30.0, 40.0):
+            assert (x >= a).mean() <= _hayes_tail(a, n)
