@@ -1,0 +1,75 @@
+// Small utility kernels: zero fill, fixed-order reduction of per-workgroup
+// partial sums, counter reset.
+#include "xf_device.h"
+
+namespace xf {
+namespace {
+__global__ void k_fill_zero(double *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// out[e] = sum over workgroups q = 0, 1, ... of part[q][e], in that order.
+__global__ void k_reduce_parts(const double2 *__restrict__ part, int nparts, int stride, double2 *out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= stride) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int q = 0; q < nparts; ++q) {
+        const double2 v = part[(size_t)q * stride + e];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    out[e] = acc;
+}
+
+__global__ void k_zero_u64(unsigned long long *p) {
+    p[0] = 0ull;
+    p[1] = 0ull;
+    p[2] = 0ull;
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s) {
+    const int grid = (int)std::min<size_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, double2 *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_parts, dim3((stride + 255) / 256), dim3(256), 0, s, part, nparts, stride, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t prepare_kernels(int G) {
+    hipError_t e;
+    if ((e = prepare_fused_small(G)) != hipSuccess) return e;
+    if ((e = prepare_fused_g32(G)) != hipSuccess) return e;
+    if ((e = prepare_fused_g64(G)) != hipSuccess) return e;
+    if ((e = prepare_fused_g64x(G)) != hipSuccess) return e;
+    if ((e = prepare_lemma(G)) != hipSuccess) return e;
+    return prepare_bwd(G);
+}
+
+hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, int, const uint64_t *bits, int64_t B, int64_t t,
+                               uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
+                               hipStream_t s) {
+    if (p.G <= 16) return fused_raw_small(p, mixed, bits, B, t, seed, prob, amp, logp, nterm, s);
+    if (p.G == 32) return fused_raw_g32(p, mixed, bits, B, t, seed, prob, amp, logp, nterm, s);
+    return fused_raw_g64(p, mixed, bits, B, t, seed, prob, amp, logp, nterm, s);
+}
+
+hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
+                        const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
+                        unsigned long long *nterm, hipStream_t s) {
+    if (p.G <= 16) return fused_exact_small(p, mixed, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s);
+    if (p.G == 32) return fused_exact_g32(p, mixed, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s);
+    return fused_exact_g64(p, mixed, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s);
+}
+
+}  // namespace xf

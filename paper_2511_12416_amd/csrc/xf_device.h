@@ -1,29 +1,15 @@
-// gfx950 kernels of the Born-rule probability path.
-//
-// One workgroup (four wave64s) owns one output bitstring b at a time:
-//   1. Raw Estimate: trajectories are drawn in batches (Philox4x32-10 words
-//      fed to the next-selected-gate inverse-transform table, Sec. III-B
-//      Eq. 10-12).  The first draw of a sample decides whether it selects any
-//      d_1 branch; only those samples (about a third at small angles) are
-//      queued and drawn to the end by the whole workgroup.  Each is reduced to
-//      its flip-pattern key and adds its phase i^e to a Gaussian-integer
-//      counter in an LDS hash keyed by the pattern (the determinant table of
-//      Sec. IV-B); samples with no d_1 choice are counted once per batch.
-//      Exact: the keys and weights come from the plan's shared term list.
-//   2. Every distinct key is evaluated.  LU path: a group of G lanes
-//      (G >= eta, one row of the eta x eta submatrix per lane) composes the
-//      rows by the low-rank update of Sec. IV-B Eq. 19 (two-layer form for
-//      L = 2) and runs an LU with partial pivoting in registers, the pivot
-//      row broadcast through LDS; det = sign * prod(pivots) in FP64.
-//      Determinant-lemma path (one CPhase layer): det M_N = det M_0 *
-//      det(I - 2 H[N, N]) with H formed once per bitstring; small patterns
-//      take one lane each.
-//   3. weight * det is summed exactly in 128-bit fixed point, so results are
-//      bitwise reproducible whatever the order of the entries, and
-//      p_b = |A_b|^2.
+// Device-side building blocks shared by the gfx950 kernels of the Born-rule
+// probability path: complex FP64 helpers, Philox4x32-10, the per-bitstring LDS
+// layout, the trajectory sampler with its pattern hash, the register LU and
+// Gauss-Jordan of a lane group, the exact fixed-point accumulator and the
+// per-bitstring determinant-lemma setup.  Everything here is inline; each
+// kernel translation unit includes it.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "xf_internal.h"
 
@@ -1392,81 +1378,6 @@ __device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) 
     for (int i = tid; i < k; i += NT) s.gkey[i] = p.gkey[i] | ((uint64_t)(p.gneg[i] != 0) << 63);
 }
 
-// Raw Estimate with the LU per distinct pattern, sampling and evaluation fused
-// per bitstring.  KIND: 0 = factors read from global memory, 1 = the
-// bitstring's factor rows staged in LDS.  Up to G = 16 the LDS footprint
-// allows two workgroups per CU; registers are capped to match (a few
-// loop-invariant values spill around the bitstring loop).
-template <int G, bool MIXED, int KIND>
-__global__ void __launch_bounds__(kThreads, G <= 16 ? 2 : 1)
-k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
-               double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
-               unsigned long long *nterm, const uint32_t *__restrict__ only) {
-    constexpr bool STAGE = KIND == 1;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n;
-    __shared__ int s_cnt[6];
-    __shared__ uint64_t s_acc[kAccWords];
-    const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
-    const int tid = threadIdx.x;
-    Work wk;
-    bool loaded = false;
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    const uint32_t slot0 = hash_slot(0);
-
-    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
-        // with `only`, just the bitstrings the lemma kernels deferred
-        if (only && only[i] != kEntryDeferred) continue;
-        const int64_t b = b0 + i;
-        if (!loaded) {
-            load_tables(p, s);
-            if constexpr (STAGE) stage_phi<MIXED>(p, s);
-            loaded = true;
-        }
-        if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) {
-            if (tid == 0) {
-                prob[b] = 0.0;
-                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
-                if (logp) logp[b] = -INFINITY;
-            }
-            __syncthreads();
-            continue;
-        }
-        if constexpr (STAGE) stage_rows<MIXED>(p, s);
-        Sampler st;
-        acc_clear(s_acc);
-        clear_table(s, s_cnt, slot0, st);
-        while (true) {
-            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = gather_list(s, &s_n);
-            sum_entries<G, MIXED, STAGE>(p, s, nl, wk, s_acc);
-            if (done) break;
-            clear_table(s, s_cnt, slot0, st);
-        }
-        const double2 total = acc_value(s_acc);
-        if (tid == 0) {
-            const double ax = total.x * p.scale, ay = total.y * p.scale;
-            const double pb = ax * ax + ay * ay;
-            prob[b] = pb;
-            if (amp) { amp[2 * b] = ax; amp[2 * b + 1] = ay; }
-            if (logp) logp[b] = log(pb);
-        }
-        __syncthreads();
-    }
-    flush_work(wk, nterm);
-}
-
-// ---------------------------------------------------------------------------
-// Raw Estimate under the determinant lemma, in two kernels per chunk of
-// bitstrings, so that each runs at its own occupancy: the sampler needs few
-// registers and no evaluation scratch (three workgroups per CU), the
-// evaluation needs the registers of the per-lane determinants.
-//   k_sample_entries: draws the t trajectories of each bitstring and writes
-//     its distinct (flip pattern, Gaussian-integer count) entries, one table
-//     flush after another, to the bitstring's region of the workspace.
-//   k_eval_entries: forms H for the bitstring and evaluates the entries in
-//     chunks of kHashSlots, summing count * det exactly.
-// ---------------------------------------------------------------------------
 // The sampler kernel runs eight waves per workgroup: its LDS (the table) then
 // serves twice the waves, and its few registers allow them.
 constexpr int kSamplerThreads = 512;
@@ -1497,429 +1408,6 @@ __device__ __forceinline__ RawSmem carve_sampler(unsigned char *smem, int k) {
     return s;
 }
 
-template <int NT>
-__global__ void __launch_bounds__(NT)
-k_sample_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
-                 uint64_t *__restrict__ ekey, int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount,
-                 uint64_t cap) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n;
-    __shared__ int s_cnt[6];
-    const RawSmem s = carve_sampler(smem, p.k);
-    const int tid = threadIdx.x;
-    load_tables<NT>(p, s);
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    const uint32_t slot0 = hash_slot(0);
-    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
-        const int64_t b = b0 + i;
-        if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) {
-            if (tid == 0) ecount[i] = kEntryInvalid;
-            continue;
-        }
-        uint64_t *kout = ekey + (size_t)i * cap;
-        int2 *cout = ecnt + (size_t)i * cap;
-        uint64_t cursor = 0;
-        bool overflow = false;
-        Sampler st;
-        clear_table<NT>(s, s_cnt, slot0, st);
-        while (true) {
-            const bool done = sample_until_flush<NT>(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = gather_list<NT>(s, &s_n);
-            if (cursor + (uint64_t)nl <= cap) {
-                for (int e = tid; e < nl; e += NT) {
-                    const uint16_t slot = s.list[e];
-                    kout[cursor + e] = s.hkey[slot];
-                    cout[cursor + e] = s.hcnt[slot];
-                }
-            } else {
-                overflow = true;
-            }
-            cursor += (uint64_t)nl;
-            if (done) break;
-            clear_table<NT>(s, s_cnt, slot0, st);
-        }
-        if (tid == 0) ecount[i] = overflow ? kEntryOverflow : (uint32_t)cursor;
-    }
-}
-
-template <int G>
-__global__ void __launch_bounds__(kThreads, 2)
-k_eval_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
-               const uint64_t *__restrict__ ekey, const int2 *__restrict__ ecnt,
-               uint32_t *__restrict__ ecount, uint64_t cap, double *__restrict__ prob,
-               double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_flag;
-    __shared__ double2 s_det;
-    __shared__ uint64_t s_acc[kAccWords];
-    const RawSmem s = carve_raw(smem, 0, p.n, G, false);
-    double2 *sH = (double2 *)((unsigned char *)s.sP + (size_t)G * G * 16);
-    const int tid = threadIdx.x;
-    Work wk;
-    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
-        const int64_t b = b0 + i;
-        const uint32_t ne = ecount[i];
-        if (ne == kEntryInvalid) {
-            if (tid == 0) {
-                prob[b] = 0.0;
-                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
-                if (logp) logp[b] = -INFINITY;
-            }
-            continue;
-        }
-        load_bitstring(p, bits, b, s.Rb, &s_ok);
-        double2 total;
-        if (ne == kEntryOverflow) {
-            total = make_double2(__longlong_as_double(0x7FF8000000000000ll), 0.0);
-        } else {
-            const LemmaBits lb = lemma_setup<G>(p, s, sH, &s_flag, &s_det, wk);
-            bool ok = lb.ok;
-            acc_clear(s_acc);
-            const uint64_t *kin = ekey + (size_t)i * cap;
-            const int2 *cin = ecnt + (size_t)i * cap;
-            for (uint32_t c0 = 0; ok && c0 < ne; c0 += kHashSlots) {
-                const int nc = (int)min((uint32_t)kHashSlots, ne - c0);
-                for (int e = tid; e < nc; e += kThreads) {
-                    s.hkey[e] = kin[c0 + e];
-                    s.hcnt[e] = cin[c0 + e];
-                    s.list[e] = (uint16_t)e;
-                }
-                __syncthreads();
-                ok = sum_entries_lemma<G>(p, s, nc, sH, lb, wk, s_acc);
-            }
-            if (!ok) {
-                // ill-conditioned base or a pattern with r > G: the LU kernel
-                // that follows recomputes this bitstring
-                if (tid == 0) ecount[i] = kEntryDeferred;
-                __syncthreads();
-                continue;
-            }
-            total = acc_value(s_acc);
-        }
-        if (tid == 0) {
-            const double ax = total.x * p.scale, ay = total.y * p.scale;
-            const double pb = ax * ax + ay * ay;
-            prob[b] = pb;
-            if (amp) { amp[2 * b] = ax; amp[2 * b + 1] = ay; }
-            if (logp) logp[b] = log(pb);
-        }
-        __syncthreads();
-    }
-    flush_work(wk, nterm);
-}
-
-template <int G, bool MIXED>
-__global__ void __launch_bounds__(kThreads)
-k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict__ w, int64_t nkeys,
-        const uint64_t *__restrict__ bits, int64_t B, double *__restrict__ prob,
-        double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok;
-    double2 *out = (double2 *)smem;
-    double2 *piv = out + kExactChunk;
-    double2 *red = piv + kThreads;
-    uint8_t *Rb = (uint8_t *)(red + kThreads);
-    const int tid = threadIdx.x;
-    const int lane = tid % G, grp = tid / G;
-    constexpr int NG = kThreads / G;
-    Work wk;
-    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
-        if (!load_bitstring(p, bits, b, Rb, &s_ok)) {
-            if (tid == 0) {
-                prob[b] = 0.0;
-                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
-                if (logp) logp[b] = -INFINITY;
-            }
-            __syncthreads();
-            continue;
-        }
-        double2 total = make_double2(0.0, 0.0);
-        for (int64_t c0 = 0; c0 < nkeys; c0 += kExactChunk) {
-            const int ncur = (int)min((int64_t)kExactChunk, nkeys - c0);
-            for (int e = grp; e < ncur; e += NG) {
-                int rank;
-                const double2 d = term_det<G, MIXED>(p, keys[c0 + e], Rb, lane, piv + grp * G, &rank);
-                if (lane == 0) {
-                    out[e] = c_mul(w[c0 + e], d);
-                    wk.rank += (unsigned)rank;
-                    wk.flops += lu_flops(p.m) + 8ull * p.m * p.m * rank;
-                }
-            }
-            __syncthreads();
-            const double2 part = ordered_sum(out, ncur, red);
-            total.x += part.x;
-            total.y += part.y;
-        }
-        if (tid == 0) {
-            const double pb = total.x * total.x + total.y * total.y;
-            prob[b] = pb;
-            if (amp) { amp[2 * b] = total.x; amp[2 * b + 1] = total.y; }
-            if (logp) logp[b] = log(pb);
-            wk.terms += (unsigned long long)nkeys;
-        }
-        __syncthreads();
-    }
-    flush_work(wk, nterm);
-}
-
-// ---------------------------------------------------------------------------
-// Adjoint (gradient of L = sum_b g_b log p_b)
-//
-// d log p_b = 2 Re(dA_b / A_b) and d det M = det M tr(M^-1 dM) (Jacobi), so
-// every distinct entry e of bitstring b contributes the holomorphic adjoint
-// Gbar_M = beta_e M_e^-T, beta_e = (g_b / A_b) c_e det M_e, which is pushed
-// back through the low-rank composition M = P[R,:] - 2 A1[R,N] Phi0[N,:]:
-//   Gbar_P[R_i, :]   += Gbar_M[i, :]
-//   Gbar_A1[R_i, c]  += -2 Gbar_M[i, :] . Phi0[c, :]      (c in N)
-//   Gbar_Phi0[c, :]  += -2 sum_i A1[R_i, c] Gbar_M[i, :]   (c in N)
-// The submatrix is recomputed, not stored.  M^-1 comes from Gauss-Jordan in
-// the same one-row-per-lane layout as the forward LU; an LDS tile per lane
-// group turns the permuted rows of M^-1 into both the rows and the columns
-// of Gbar_M.  Each workgroup accumulates into its own partial buffer, which a
-// fixed-order reduction adds up.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void atomic_add_c(double2 *dst, double2 v) {
-    atomicAdd(&dst->x, v.x);
-    atomicAdd(&dst->y, v.y);
-}
-
-struct GradOut {
-    double2 *P, *Phi0, *A1, *W;   // this workgroup's partial (see GradLayout)
-    double *gsum;
-};
-
-// One entry's adjoint, evaluated by a group of G lanes.  coef = g_b / A_b
-// (times the Raw Estimate scale), ce = the entry's weight.  Adds its row of
-// Gbar_M into srow (summed over entries, scattered into Gbar_P per bitstring).
-// dw (exact mode, nullable): derivatives of the weight with respect to every
-// angle, k values.
-template <int G, bool MIXED>
-__device__ __forceinline__ void adjoint_entry(const DevPlan &p, uint64_t key, double2 ce, double2 coef,
-                              const double2 *dw, const uint8_t *Rb, int lane, double2 *pv,
-                              double2 *tile, double2 (&srow)[G], const GradOut &go) {
-    double2 det;
-    int pos;
-    const Flips f = decode_key(p, key);
-    {
-        double2 a[G], v[G];
-        if (lane < p.m) {
-            compose_row<G, MIXED>(p, Rb[lane], f, a);
-        } else {
-#pragma unroll
-            for (int j = 0; j < G; ++j) a[j] = make_double2(j == lane ? 1.0 : 0.0, 0.0);
-        }
-        if (!gj_invert<G>(a, v, p.m, lane, pv, det, pos)) return;   // det = 0: no contribution
-        if (lane < p.m) {
-#pragma unroll
-            for (int j = 0; j < G; ++j)
-                if (j < p.m) tile[pos * G + j] = v[j];
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // weight derivatives (exact mode): dL/dtheta_j gets 2 Re(coef dw_j det)
-    if (dw) {
-        const double2 cd = c_mul(coef, det);
-        for (int j = lane; j < p.k; j += G) atomic_add_c(go.W + j, c_mul(cd, dw[j]));
-    }
-    const double2 beta = c_mul(c_mul(coef, ce), det);
-    if (lane < p.m) {
-        double2 gr[G], gc[G];   // row `lane` and column `lane` of Gbar_M
-#pragma unroll
-        for (int j = 0; j < G; ++j) {
-            if (j < p.m) {
-                gr[j] = c_mul(beta, tile[j * G + lane]);
-                gc[j] = c_mul(beta, tile[lane * G + j]);
-            } else {
-                gr[j] = gc[j] = make_double2(0.0, 0.0);
-            }
-            srow[j].x += gr[j].x;
-            srow[j].y += gr[j].y;
-        }
-        if (p.L == 1) {
-            const int Ri = Rb[lane];
-            for_each_mode(f.n0, [&](int c) {
-                const double2 *phi = p.Phi0 + (size_t)c * G;
-                double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
-#pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    s1 = c_fma(s1, gr[j], phi[j]);
-                    if (j < p.m) s2 = c_fma(s2, p.A1[(size_t)Rb[j] * p.n + c], gc[j]);
-                }
-                atomic_add_c(go.A1 + (size_t)Ri * p.n + c, make_double2(-2.0 * s1.x, -2.0 * s1.y));
-                atomic_add_c(go.Phi0 + (size_t)c * G + lane, make_double2(-2.0 * s2.x, -2.0 * s2.y));
-            });
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ GradOut grad_out(double2 *part, const GradLayout &L) {
-    double2 *base = part + (size_t)blockIdx.x * L.stride;
-    GradOut g;
-    g.P = base + L.oP;
-    g.Phi0 = base + L.oPhi;
-    g.A1 = base + L.oA1;
-    g.W = base + L.oW;
-    g.gsum = (double *)(base + L.oG);
-    return g;
-}
-
-template <int G>
-__device__ __forceinline__ void flush_srow(const DevPlan &p, const uint8_t *Rb, int lane, double2 (&srow)[G],
-                           const GradOut &go) {
-    if (lane < p.m) {
-        double2 *row = go.P + (size_t)Rb[lane] * G;
-#pragma unroll
-        for (int j = 0; j < G; ++j)
-            if (j < p.m) atomic_add_c(row + j, srow[j]);
-    }
-}
-
-template <int G, bool MIXED>
-__global__ void __launch_bounds__(kThreads)
-k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
-                   const double *__restrict__ g, double2 *part, GradLayout lay) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n;
-    __shared__ int s_cnt[6];
-    __shared__ uint64_t s_acc[kAccWords];
-    const RawSmem s = carve_raw(smem, p.k, p.n, G, MIXED);
-    constexpr int NG = kThreads / G;
-    double2 *tiles = (double2 *)(smem + raw_lds_bytes(p.k, p.n, G, MIXED, false));
-    double2 *pvs = tiles + NG * G * G;
-    const int tid = threadIdx.x;
-    const int lane = tid % G, grp = tid / G;
-    load_tables(p, s);
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    const uint32_t slot0 = hash_slot(0);
-    const GradOut go = grad_out(part, lay);
-
-    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
-        if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) continue;
-        const double gb = g[b];
-        if (gb == 0.0) continue;
-        Sampler st;
-        acc_clear(s_acc);
-        clear_table(s, s_cnt, slot0, st);
-        while (true) {
-            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = gather_list(s, &s_n);
-            Work unused;
-            sum_entries<G, MIXED, false>(p, s, nl, unused, s_acc);
-            if (done) break;
-            clear_table(s, s_cnt, slot0, st);
-        }
-        const double2 total = acc_value(s_acc);
-        const double ax = total.x * p.scale, ay = total.y * p.scale;
-        const double a2 = ax * ax + ay * ay;
-        if (a2 == 0.0) continue;
-        // coef = g_b / A_b * scale
-        const double2 coef = make_double2(gb * ax / a2 * p.scale, -gb * ay / a2 * p.scale);
-        double2 srow[G];
-#pragma unroll
-        for (int j = 0; j < G; ++j) srow[j] = make_double2(0.0, 0.0);
-        st = Sampler();
-        clear_table(s, s_cnt, slot0, st);
-        while (true) {
-            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = gather_list(s, &s_n);
-            for (int e = grp; e < nl; e += NG) {
-                const uint16_t slot = s.list[e];
-                const int2 c = s.hcnt[slot];
-                adjoint_entry<G, MIXED>(p, s.hkey[slot], make_double2((double)c.x, (double)c.y), coef,
-                                        nullptr, s.Rb, lane, pvs + grp * 2 * G, tiles + grp * G * G,
-                                        srow, go);
-            }
-            __syncthreads();
-            if (done) break;
-            clear_table(s, s_cnt, slot0, st);
-        }
-        flush_srow<G>(p, s.Rb, lane, srow, go);
-        if (tid == 0) atomicAdd(go.gsum, gb);
-        __syncthreads();
-    }
-}
-
-template <int G, bool MIXED>
-__global__ void __launch_bounds__(kThreads)
-k_exact_bwd(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict__ w,
-            const double2 *__restrict__ dw, int64_t nkeys, const uint64_t *__restrict__ bits, int64_t B,
-            const double *__restrict__ g, double2 *part, GradLayout lay) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok;
-    constexpr int NG = kThreads / G;
-    double2 *out = (double2 *)smem;
-    double2 *piv = out + kExactChunk;
-    double2 *red = piv + kThreads;
-    double2 *tiles = red + kThreads;
-    double2 *pvs = tiles + NG * G * G;
-    uint8_t *Rb = (uint8_t *)(pvs + NG * 2 * G);
-    const int tid = threadIdx.x;
-    const int lane = tid % G, grp = tid / G;
-    const GradOut go = grad_out(part, lay);
-    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
-        if (!load_bitstring(p, bits, b, Rb, &s_ok)) continue;
-        const double gb = g[b];
-        if (gb == 0.0) continue;
-        double2 total = make_double2(0.0, 0.0);
-        for (int64_t c0 = 0; c0 < nkeys; c0 += kExactChunk) {
-            const int ncur = (int)min((int64_t)kExactChunk, nkeys - c0);
-            for (int e = grp; e < ncur; e += NG) {
-                int rank;
-                const double2 d = term_det<G, MIXED>(p, keys[c0 + e], Rb, lane, piv + grp * G, &rank);
-                if (lane == 0) out[e] = c_mul(w[c0 + e], d);
-            }
-            __syncthreads();
-            const double2 ps = ordered_sum(out, ncur, red);
-            total.x += ps.x;
-            total.y += ps.y;
-        }
-        if (tid == 0) red[0] = total;
-        __syncthreads();
-        total = red[0];
-        __syncthreads();
-        const double a2 = total.x * total.x + total.y * total.y;
-        if (a2 == 0.0) continue;
-        const double2 coef = make_double2(gb * total.x / a2, -gb * total.y / a2);
-        double2 srow[G];
-#pragma unroll
-        for (int j = 0; j < G; ++j) srow[j] = make_double2(0.0, 0.0);
-        for (int64_t e = grp; e < nkeys; e += NG)
-            adjoint_entry<G, MIXED>(p, keys[e], w[e], coef, dw + (size_t)e * p.k, Rb, lane,
-                                    pvs + grp * 2 * G, tiles + grp * G * G, srow, go);
-        flush_srow<G>(p, Rb, lane, srow, go);
-        if (tid == 0) atomicAdd(go.gsum, gb);
-        __syncthreads();
-    }
-}
-
-__global__ void k_fill_zero(double *p, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
-}
-
-// out[e] = sum over workgroups q = 0, 1, ... of part[q][e], in that order.
-__global__ void k_reduce_parts(const double2 *__restrict__ part, int nparts, int stride, double2 *out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= stride) return;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int q = 0; q < nparts; ++q) {
-        const double2 v = part[(size_t)q * stride + e];
-        acc.x += v.x;
-        acc.y += v.y;
-    }
-    out[e] = acc;
-}
-
-__global__ void k_zero_u64(unsigned long long *p) {
-    p[0] = 0ull;
-    p[1] = 0ull;
-    p[2] = 0ull;
-}
-
 constexpr int kMaxGrid = 1 << 20;
 constexpr size_t kMaxLds = 159 * 1024;
 
@@ -1942,252 +1430,5 @@ __host__ __forceinline__ bool lemma_applies(const DevPlan &p) {
            sampler_lds_bytes(p.k) <= kMaxLds;
 }
 
-template <int G, bool MIXED>
-hipError_t launch_raw_t(const DevPlan &p, int algorithm, const uint64_t *bits, int64_t B, int64_t t,
-                        uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
-                        hipStream_t s) {
-    const int grid = (int)(B < kMaxGrid ? B : kMaxGrid);
-    (void)algorithm;
-    if constexpr (G <= 16) {
-        if (use_stage(p, MIXED)) {
-            const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, true);
-            hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 1>), dim3(grid), dim3(kThreads), lds, s, p, bits,
-                               (int64_t)0, B, (uint32_t)t, seed, prob, amp, logp, nterm, nullptr);
-            return hipGetLastError();
-        }
-    }
-    const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, false);
-    hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 0>), dim3(grid), dim3(kThreads), lds, s, p, bits, (int64_t)0, B,
-                       (uint32_t)t, seed, prob, amp, logp, nterm, nullptr);
-    return hipGetLastError();
-}
-
-template <int G, bool MIXED>
-hipError_t launch_exact_t(const DevPlan &p, const uint64_t *keys, const double2 *w, int64_t nkeys,
-                          const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
-                          unsigned long long *nterm, hipStream_t s) {
-    const size_t lds = exact_lds_bytes(p);
-    const int grid = (int)(B < kMaxGrid ? B : kMaxGrid);
-    hipLaunchKernelGGL((k_exact<G, MIXED>), dim3(grid), dim3(kThreads), lds, s, p, keys, w, nkeys,
-                       bits, B, prob, amp, logp, nterm);
-    return hipGetLastError();
-}
-
-template <int G, bool MIXED>
-hipError_t launch_raw_bwd_t(const DevPlan &p, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
-                            const double *g, double2 *part, int nparts, const GradLayout &lay,
-                            hipStream_t s) {
-    const size_t lds = raw_estimate_bwd_lds_bytes(p, MIXED);
-    hipLaunchKernelGGL((k_raw_estimate_bwd<G, MIXED>), dim3(nparts), dim3(kThreads), lds, s, p, bits, B,
-                       (uint32_t)t, seed, g, part, lay);
-    return hipGetLastError();
-}
-
-template <int G, bool MIXED>
-hipError_t launch_exact_bwd_t(const DevPlan &p, const uint64_t *keys, const double2 *w, const double2 *dw,
-                              int64_t nkeys, const uint64_t *bits, int64_t B, const double *g,
-                              double2 *part, int nparts, const GradLayout &lay, hipStream_t s) {
-    const size_t lds = exact_bwd_lds_bytes(p);
-    hipLaunchKernelGGL((k_exact_bwd<G, MIXED>), dim3(nparts), dim3(kThreads), lds, s, p, keys, w, dw,
-                       nkeys, bits, B, g, part, lay);
-    return hipGetLastError();
-}
-
-template <int G>
-hipError_t set_lds_limits() {
-    const int big = (int)kMaxLds;
-    hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, false, 0>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void *)k_raw_estimate<G, true, 0>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-        return e;
-    if constexpr (G <= 16) {
-        for (const void *f : {(const void *)k_raw_estimate<G, false, 1>, (const void *)k_raw_estimate<G, true, 1>,
-                              (const void *)k_eval_entries<G>, (const void *)k_sample_entries<kSamplerThreads>})
-            if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-                return e;
-    }
-    if ((e = hipFuncSetAttribute((const void *)k_exact<G, false>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void *)k_exact<G, true>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-        return e;
-    if constexpr (G <= 16) {
-        if ((e = hipFuncSetAttribute((const void *)k_raw_estimate_bwd<G, false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-            return e;
-        if ((e = hipFuncSetAttribute((const void *)k_raw_estimate_bwd<G, true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-            return e;
-        if ((e = hipFuncSetAttribute((const void *)k_exact_bwd<G, false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-            return e;
-        if ((e = hipFuncSetAttribute((const void *)k_exact_bwd<G, true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
-            return e;
-    }
-    return hipSuccess;
-}
-
 }  // namespace
-
-size_t raw_estimate_lds_bytes(const DevPlan &p, bool mixed) {
-    return raw_lds_bytes(p.k, p.n, p.G, mixed, p.G <= 16 && use_stage(p, mixed));
-}
-
-bool raw_estimate_uses_lemma(const DevPlan &p, int algorithm) {
-    return algorithm != 1 && lemma_applies(p);
-}
-
-uint64_t lemma_entry_cap(int64_t t) { return (uint64_t)t + (uint64_t)t / 511 + 2; }
-
-hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
-                              uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,
-                              double *prob, double *amp, double *logp, unsigned long long *nterm,
-                              hipEvent_t ev_mid, hipStream_t s) {
-    const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
-    hipLaunchKernelGGL((k_sample_entries<kSamplerThreads>), dim3(grid), dim3(kSamplerThreads),
-                       sampler_lds_bytes(p.k), s, p, bits, b0, nb, (uint32_t)t, seed, ekey, ecnt, ecount, cap);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
-    // then the LU kernel for the bitstrings the evaluation deferred, on a
-    // smaller grid (its workgroups skip the other bitstrings at once; the
-    // deferred ones are rare)
-    const int grid_lu = grid < 2048 ? grid : 2048;
-#define XF_EVAL(GG)                                                                                            \
-    do {                                                                                                       \
-        hipLaunchKernelGGL((k_eval_entries<GG>), dim3(grid), dim3(kThreads), lemma_lds(p), s, p, bits, b0, nb,   \
-                           ekey, ecnt, ecount, cap, prob, amp, logp, nterm);                                   \
-        if ((e = hipGetLastError()) != hipSuccess) return e;                                                   \
-        if (use_stage(p, false))                                                                               \
-            hipLaunchKernelGGL((k_raw_estimate<GG, false, 1>), dim3(grid_lu), dim3(kThreads),                  \
-                               raw_lds_bytes(p.k, p.n, GG, false, true), s, p, bits, b0, nb, (uint32_t)t, seed,   \
-                               prob, amp, logp, nterm, ecount);                                                \
-        else                                                                                                   \
-            hipLaunchKernelGGL((k_raw_estimate<GG, false, 0>), dim3(grid_lu), dim3(kThreads),                  \
-                               raw_lds_bytes(p.k, p.n, GG, false, false), s, p, bits, b0, nb, (uint32_t)t, seed,  \
-                               prob, amp, logp, nterm, ecount);                                                \
-    } while (0)
-    switch (p.G) {
-        case 4: XF_EVAL(4); break;
-        case 8: XF_EVAL(8); break;
-        case 16: XF_EVAL(16); break;
-        default: return hipErrorInvalidValue;
-    }
-#undef XF_EVAL
-    return hipGetLastError();
-}
-
-size_t exact_lds_bytes(const DevPlan &) { return kExactChunk * 16 + 2 * kThreads * 16 + 64; }
-
-size_t raw_estimate_bwd_lds_bytes(const DevPlan &p, bool mixed) {
-    const size_t NG = kThreads / p.G;
-    return raw_lds_bytes(p.k, p.n, p.G, mixed, false) + NG * p.G * p.G * 16 + NG * 2 * p.G * 16;
-}
-
-size_t exact_bwd_lds_bytes(const DevPlan &p) {
-    const size_t NG = kThreads / p.G;
-    return kExactChunk * 16 + 2 * kThreads * 16 + NG * p.G * p.G * 16 + NG * 2 * p.G * 16 + 64;
-}
-
-hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s) {
-    const int grid = (int)std::min<size_t>((count + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fill_zero, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, p, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, double2 *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_parts, dim3((stride + 255) / 256), dim3(256), 0, s, part, nparts, stride, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_raw_estimate_bwd(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
-                                   int64_t t, uint64_t seed, const double *g, double2 *part, int nparts,
-                                   const GradLayout &lay, hipStream_t s) {
-    hipError_t e = hipSuccess;
-#define XF_RB(GG) \
-    e = mixed ? launch_raw_bwd_t<GG, true>(p, bits, B, t, seed, g, part, nparts, lay, s) \
-              : launch_raw_bwd_t<GG, false>(p, bits, B, t, seed, g, part, nparts, lay, s)
-    switch (p.G) {
-        case 4: XF_RB(4); break;
-        case 8: XF_RB(8); break;
-        case 16: XF_RB(16); break;
-        default: return hipErrorInvalidValue;
-    }
-#undef XF_RB
-    return e;
-}
-
-hipError_t launch_exact_bwd(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
-                            const double2 *dw, int64_t nkeys, const uint64_t *bits, int64_t B,
-                            const double *g, double2 *part, int nparts, const GradLayout &lay,
-                            hipStream_t s) {
-    hipError_t e = hipSuccess;
-#define XF_EB(GG) \
-    e = mixed ? launch_exact_bwd_t<GG, true>(p, keys, w, dw, nkeys, bits, B, g, part, nparts, lay, s) \
-              : launch_exact_bwd_t<GG, false>(p, keys, w, dw, nkeys, bits, B, g, part, nparts, lay, s)
-    switch (p.G) {
-        case 4: XF_EB(4); break;
-        case 8: XF_EB(8); break;
-        case 16: XF_EB(16); break;
-        default: return hipErrorInvalidValue;
-    }
-#undef XF_EB
-    return e;
-}
-
-hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);
-    return hipGetLastError();
-}
-
-hipError_t prepare_kernels(int G) {
-    switch (G) {
-        case 4: return set_lds_limits<4>();
-        case 8: return set_lds_limits<8>();
-        case 16: return set_lds_limits<16>();
-        case 32: return set_lds_limits<32>();
-        case 64: return set_lds_limits<64>();
-    }
-    return hipErrorInvalidValue;
-}
-
-#define XF_DISPATCH_G(G, CALL) \
-    switch (G) {               \
-        case 4: CALL(4); break; \
-        case 8: CALL(8); break; \
-        case 16: CALL(16); break; \
-        case 32: CALL(32); break; \
-        case 64: CALL(64); break; \
-        default: return hipErrorInvalidValue; \
-    }
-
-hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, int algorithm, const uint64_t *bits, int64_t B,
-                               int64_t t, uint64_t seed, double *prob, double *amp, double *logp,
-                               unsigned long long *nterm, hipStream_t s) {
-    hipError_t e = hipSuccess;
-#define XF_RAW(GG) \
-    e = mixed ? launch_raw_t<GG, true>(p, algorithm, bits, B, t, seed, prob, amp, logp, nterm, s) \
-              : launch_raw_t<GG, false>(p, algorithm, bits, B, t, seed, prob, amp, logp, nterm, s)
-    XF_DISPATCH_G(p.G, XF_RAW)
-#undef XF_RAW
-    return e;
-}
-
-hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
-                        int64_t nkeys, const uint64_t *bits, int64_t B, double *prob, double *amp,
-                        double *logp, unsigned long long *nterm, hipStream_t s) {
-    hipError_t e = hipSuccess;
-#define XF_EX(GG) \
-    e = mixed ? launch_exact_t<GG, true>(p, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s) \
-              : launch_exact_t<GG, false>(p, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s)
-    XF_DISPATCH_G(p.G, XF_EX)
-#undef XF_EX
-    return e;
-}
-
 }  // namespace xf

@@ -1,5 +1,5 @@
 // Internal definitions shared by the host plan code (xf_host.cpp) and the
-// gfx950 kernels (xf_kernels.hip).  Not part of the public ABI.
+// gfx950 kernels (k_*.hip).  Not part of the public ABI.
 #pragma once
 
 #include <stddef.h>
@@ -63,7 +63,7 @@ struct GradLayout {
     int stride, oP, oPhi, oA1, oW, oG;
 };
 
-// Launchers (xf_kernels.hip).  Return hipSuccess or the launch error.
+// Launchers (k_*.hip).  Return hipSuccess or the launch error.
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
 // The fused Raw Estimate kernel (LU per distinct pattern) over the whole
 // batch; the determinant-lemma path is launch_lemma_chunk.  algorithm is the
@@ -93,7 +93,37 @@ hipError_t launch_exact_bwd(const DevPlan &p, bool mixed, const uint64_t *keys, 
                             hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
 hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, double2 *out, hipStream_t s);
+// Raises the dynamic-LDS limit of every kernel instantiated for lane-group
+// size G (k_misc.hip calls the per-file functions).
 hipError_t prepare_kernels(int G);
+hipError_t prepare_fused_small(int G);
+hipError_t prepare_fused_g32(int G);
+hipError_t prepare_fused_g64(int G);
+hipError_t prepare_fused_g64x(int G);
+// Fused LU kernels per lane-group size (k_fused_small.hip: G = 4, 8, 16;
+// k_fused_g32.hip, k_fused_g64.hip); hipErrorInvalidValue for other G.
+hipError_t fused_raw_small(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
+                           double *prob, double *amp, double *logp, unsigned long long *nterm, hipStream_t s);
+hipError_t fused_raw_g32(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
+                         double *prob, double *amp, double *logp, unsigned long long *nterm, hipStream_t s);
+hipError_t fused_raw_g64(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
+                         double *prob, double *amp, double *logp, unsigned long long *nterm, hipStream_t s);
+hipError_t fused_exact_small(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
+                             const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
+                             unsigned long long *nterm, hipStream_t s);
+hipError_t fused_exact_g32(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
+                           const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
+                           unsigned long long *nterm, hipStream_t s);
+hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
+                           const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
+                           unsigned long long *nterm, hipStream_t s);
+hipError_t prepare_lemma(int G);
+hipError_t prepare_bwd(int G);
+// The fused LU kernel restricted to the bitstrings whose ecount entry is
+// kEntryDeferred (the lemma evaluation could not take them).
+hipError_t launch_raw_deferred(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                               uint64_t seed, double *prob, double *amp, double *logp,
+                               unsigned long long *nterm, const uint32_t *ecount, int grid, hipStream_t s);
 size_t raw_estimate_lds_bytes(const DevPlan &p, bool mixed);
 size_t exact_lds_bytes(const DevPlan &p);
 size_t raw_estimate_bwd_lds_bytes(const DevPlan &p, bool mixed);
