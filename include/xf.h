@@ -210,6 +210,7 @@ typedef struct {
     double sample_ms;
     double eval_ms;
     int32_t lemma;
+    int32_t backward_lemma;   /* the last xf_log_prob_backward call used the determinant lemma */
 } xf_work;
 xf_status xf_plan_last_work(xf_plan *plan, xf_work *work);
 

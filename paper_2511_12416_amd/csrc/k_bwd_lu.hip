@@ -17,17 +17,20 @@ namespace {
 // The submatrix is recomputed, not stored.  M^-1 comes from Gauss-Jordan in
 // the same one-row-per-lane layout as the forward LU; an LDS tile per lane
 // group turns the permuted rows of M^-1 into both the rows and the columns
-// of Gbar_M.  Each workgroup accumulates into its own partial buffer, which a
-// fixed-order reduction adds up.
+// of Gbar_M.  Every lane group accumulates into its own partial buffer, in
+// which each of its lanes owns the entries it adds to (its row R_i, its
+// column of Phi0, its angles), so the adds are plain read-modify-writes in
+// program order; a fixed-order reduction over all partials follows.  The
+// result is bitwise reproducible.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void atomic_add_c(double2 *dst, double2 v) {
-    atomicAdd(&dst->x, v.x);
-    atomicAdd(&dst->y, v.y);
+__device__ __forceinline__ void add_c(double2 *dst, double2 v) {
+    dst->x += v.x;
+    dst->y += v.y;
 }
 
 struct GradOut {
-    double2 *P, *Phi0, *A1, *W;   // this workgroup's partial (see GradLayout)
+    double2 *P, *Phi0, *A1, *W;   // this lane group's partial (see GradLayout)
     double *gsum;
 };
 
@@ -63,7 +66,7 @@ __device__ __forceinline__ void adjoint_entry(const DevPlan &p, uint64_t key, do
     // weight derivatives (exact mode): dL/dtheta_j gets 2 Re(coef dw_j det)
     if (dw) {
         const double2 cd = c_mul(coef, det);
-        for (int j = lane; j < p.k; j += G) atomic_add_c(go.W + j, c_mul(cd, dw[j]));
+        for (int j = lane; j < p.k; j += G) add_c(go.W + j, c_mul(cd, dw[j]));
     }
     const double2 beta = c_mul(c_mul(coef, ce), det);
     if (lane < p.m) {
@@ -81,25 +84,29 @@ __device__ __forceinline__ void adjoint_entry(const DevPlan &p, uint64_t key, do
         }
         if (p.L == 1) {
             const int Ri = Rb[lane];
-            for_each_mode(f.n0, [&](int c) {
-                const double2 *phi = p.Phi0 + (size_t)c * G;
-                double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+            for (int w = 0; w < 2; ++w) {
+                for (uint64_t mm = f.n0[w]; mm; mm &= mm - 1) {
+                    const int c = 64 * w + __ffsll((long long)mm) - 1;
+                    const double2 *phi = p.Phi0 + (size_t)c * G;
+                    double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
 #pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    s1 = c_fma(s1, gr[j], phi[j]);
-                    if (j < p.m) s2 = c_fma(s2, p.A1[(size_t)Rb[j] * p.n + c], gc[j]);
+                    for (int j = 0; j < G; ++j) {
+                        s1 = c_fma(s1, gr[j], phi[j]);
+                        if (j < p.m) s2 = c_fma(s2, p.A1[(size_t)Rb[j] * p.n + c], gc[j]);
+                    }
+                    add_c(go.A1 + (size_t)Ri * p.n + c, make_double2(-2.0 * s1.x, -2.0 * s1.y));
+                    add_c(go.Phi0 + (size_t)c * G + lane, make_double2(-2.0 * s2.x, -2.0 * s2.y));
                 }
-                atomic_add_c(go.A1 + (size_t)Ri * p.n + c, make_double2(-2.0 * s1.x, -2.0 * s1.y));
-                atomic_add_c(go.Phi0 + (size_t)c * G + lane, make_double2(-2.0 * s2.x, -2.0 * s2.y));
-            });
+            }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ GradOut grad_out(double2 *part, const GradLayout &L) {
-    double2 *base = part + (size_t)blockIdx.x * L.stride;
+// Partial of lane group grp of this workgroup (kThreads / G groups each).
+__device__ __forceinline__ GradOut grad_out(double2 *part, const GradLayout &L, int ngroups, int grp) {
+    double2 *base = part + ((size_t)blockIdx.x * ngroups + grp) * L.stride;
     GradOut g;
     g.P = base + L.oP;
     g.Phi0 = base + L.oPhi;
@@ -116,14 +123,14 @@ __device__ __forceinline__ void flush_srow(const DevPlan &p, const uint8_t *Rb, 
         double2 *row = go.P + (size_t)Rb[lane] * G;
 #pragma unroll
         for (int j = 0; j < G; ++j)
-            if (j < p.m) atomic_add_c(row + j, srow[j]);
+            if (j < p.m) add_c(row + j, srow[j]);
     }
 }
 
 template <int G, bool MIXED>
 __global__ void __launch_bounds__(kThreads)
-k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint32_t t, uint64_t seed,
-                   const double *__restrict__ g, double2 *part, GradLayout lay) {
+k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
+                   const double *__restrict__ g, double2 *part, GradLayout lay, const uint32_t *__restrict__ only) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok, s_n;
     __shared__ int s_cnt[6];
@@ -137,9 +144,12 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
     load_tables(p, s);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t slot0 = hash_slot(0);
-    const GradOut go = grad_out(part, lay);
+    const GradOut go = grad_out(part, lay, NG, grp);
 
-    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        // with `only`, just the bitstrings the lemma backward deferred
+        if (only && only[i] != kEntryDeferred) continue;
+        const int64_t b = b0 + i;
         if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) continue;
         const double gb = g[b];
         if (gb == 0.0) continue;
@@ -180,7 +190,7 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t B, uint
             clear_table(s, s_cnt, slot0, st);
         }
         flush_srow<G>(p, s.Rb, lane, srow, go);
-        if (tid == 0) atomicAdd(go.gsum, gb);
+        if (tid == 0) *go.gsum += gb;
         __syncthreads();
     }
 }
@@ -201,7 +211,7 @@ k_exact_bwd(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restr
     uint8_t *Rb = (uint8_t *)(pvs + NG * 2 * G);
     const int tid = threadIdx.x;
     const int lane = tid % G, grp = tid / G;
-    const GradOut go = grad_out(part, lay);
+    const GradOut go = grad_out(part, lay, NG, grp);
     for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
         if (!load_bitstring(p, bits, b, Rb, &s_ok)) continue;
         const double gb = g[b];
@@ -233,18 +243,18 @@ k_exact_bwd(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restr
             adjoint_entry<G, MIXED>(p, keys[e], w[e], coef, dw + (size_t)e * p.k, Rb, lane,
                                     pvs + grp * 2 * G, tiles + grp * G * G, srow, go);
         flush_srow<G>(p, Rb, lane, srow, go);
-        if (tid == 0) atomicAdd(go.gsum, gb);
+        if (tid == 0) *go.gsum += gb;
         __syncthreads();
     }
 }
 
 template <int G, bool MIXED>
-hipError_t launch_raw_bwd_t(const DevPlan &p, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
-                            const double *g, double2 *part, int nparts, const GradLayout &lay,
-                            hipStream_t s) {
+hipError_t launch_raw_bwd_t(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                            uint64_t seed, const double *g, double2 *part, int nwg, const GradLayout &lay,
+                            const uint32_t *only, hipStream_t s) {
     const size_t lds = raw_estimate_bwd_lds_bytes(p, MIXED);
-    hipLaunchKernelGGL((k_raw_estimate_bwd<G, MIXED>), dim3(nparts), dim3(kThreads), lds, s, p, bits, B,
-                       (uint32_t)t, seed, g, part, lay);
+    hipLaunchKernelGGL((k_raw_estimate_bwd<G, MIXED>), dim3(nwg), dim3(kThreads), lds, s, p, bits, b0, nb,
+                       (uint32_t)t, seed, g, part, lay, only);
     return hipGetLastError();
 }
 
@@ -280,13 +290,13 @@ size_t exact_bwd_lds_bytes(const DevPlan &p) {
     return kExactChunk * 16 + 2 * kThreads * 16 + NG * p.G * p.G * 16 + NG * 2 * p.G * 16 + 64;
 }
 
-hipError_t launch_raw_estimate_bwd(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
-                                   int64_t t, uint64_t seed, const double *g, double2 *part, int nparts,
-                                   const GradLayout &lay, hipStream_t s) {
+hipError_t launch_raw_estimate_bwd(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t b0, int64_t nb,
+                                   int64_t t, uint64_t seed, const double *g, double2 *part, int nwg,
+                                   const GradLayout &lay, const uint32_t *only, hipStream_t s) {
     hipError_t e = hipSuccess;
 #define XF_RB(GG) \
-    e = mixed ? launch_raw_bwd_t<GG, true>(p, bits, B, t, seed, g, part, nparts, lay, s) \
-              : launch_raw_bwd_t<GG, false>(p, bits, B, t, seed, g, part, nparts, lay, s)
+    e = mixed ? launch_raw_bwd_t<GG, true>(p, bits, b0, nb, t, seed, g, part, nwg, lay, only, s) \
+              : launch_raw_bwd_t<GG, false>(p, bits, b0, nb, t, seed, g, part, nwg, lay, only, s)
     switch (p.G) {
         case 4: XF_RB(4); break;
         case 8: XF_RB(8); break;

@@ -2,7 +2,9 @@
 // eta <= 16: a sampling kernel that writes each bitstring's distinct flip
 // patterns with their Gaussian-integer counts to a workspace, and an
 // evaluation kernel that forms the bitstring's H once and takes an r x r
-// determinant per pattern.
+// determinant per pattern; and the adjoint of the same evaluation
+// (k_bwd_entries, lemma_bwd.h).
+#include "lemma_bwd.h"
 #include "xf_device.h"
 
 namespace xf {
@@ -70,7 +72,7 @@ k_eval_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t
                uint32_t *__restrict__ ecount, uint64_t cap, double *__restrict__ prob,
                double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_flag;
+    __shared__ int s_ok, s_flag[2];
     __shared__ double2 s_det;
     __shared__ uint64_t s_acc[kAccWords];
     const RawSmem s = carve_raw(smem, 0, p.n, G, false);
@@ -93,7 +95,7 @@ k_eval_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t
         if (ne == kEntryOverflow) {
             total = make_double2(__longlong_as_double(0x7FF8000000000000ll), 0.0);
         } else {
-            const LemmaBits lb = lemma_setup<G>(p, s, sH, &s_flag, &s_det, wk);
+            const LemmaBits lb = lemma_setup<G>(p, s, sH, s_flag, &s_det, wk);
             bool ok = lb.ok;
             acc_clear(s_acc);
             const uint64_t *kin = ekey + (size_t)i * cap;
@@ -133,7 +135,8 @@ template <int G>
 hipError_t set_lds_limits_lemma() {
     const int big = (int)kMaxLds;
     hipError_t e;
-    for (const void *f : {(const void *)k_eval_entries<G>, (const void *)k_sample_entries<kSamplerThreads>})
+    for (const void *f : {(const void *)k_eval_entries<G>, (const void *)k_sample_entries<kSamplerThreads>,
+                          (const void *)k_bwd_entries<G>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess) return e;
     return hipSuccess;
 }
@@ -176,6 +179,41 @@ hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0
     // smaller grid (its workgroups skip the other bitstrings at once; the
     // deferred ones are rare)
     return launch_raw_deferred(p, bits, b0, nb, t, seed, prob, amp, logp, nterm, ecount, grid < 2048 ? grid : 2048, s);
+}
+
+size_t bwd_lemma_lds(const DevPlan &p) { return lemma_lds(p) + bwd_lemma_extra(p.G, p.keybits); }
+
+bool backward_uses_lemma(const DevPlan &p, int algorithm) {
+    return algorithm != 1 && lemma_applies(p) && bwd_lemma_lds(p) <= kMaxLds;
+}
+
+hipError_t launch_lemma_bwd_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                                  uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,
+                                  const double *g, double2 *part, int nparts, const GradLayout &lay,
+                                  hipStream_t s) {
+    const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
+    hipLaunchKernelGGL((k_sample_entries<kSamplerThreads>), dim3(grid), dim3(kSamplerThreads),
+                       sampler_lds_bytes(p.k), s, p, bits, b0, nb, (uint32_t)t, seed, ekey, ecnt, ecount, cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int bg = nparts < nb ? nparts : (int)nb;
+    const size_t lds = bwd_lemma_lds(p);
+    switch (p.G) {
+        case 4:
+            hipLaunchKernelGGL((k_bwd_entries<4>), dim3(bg), dim3(kThreads), lds, s, p, bits, b0, nb, ekey, ecnt,
+                               ecount, cap, g, part, lay);
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_bwd_entries<8>), dim3(bg), dim3(kThreads), lds, s, p, bits, b0, nb, ekey, ecnt,
+                               ecount, cap, g, part, lay);
+            break;
+        case 16:
+            hipLaunchKernelGGL((k_bwd_entries<16>), dim3(bg), dim3(kThreads), lds, s, p, bits, b0, nb, ekey, ecnt,
+                               ecount, cap, g, part, lay);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t prepare_lemma(int G) {

@@ -1016,6 +1016,7 @@ struct LemmaBits {
 // (after V in the hash keys) and H = Phi0[act, :] X into sH.  When
 // m * |act| <= 512 the operands A1[R, act] and Phi0[act, :] are first copied
 // to the hash counts (their loads overlap the elimination).
+// s_flag: two ints of LDS (inverse found; conditioning acceptable).
 template <int G>
 __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem &s, double2 *sH,
                                                  int *s_flag, double2 *s_det, Work &wk) {
@@ -1073,7 +1074,8 @@ __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem
         __syncthreads();
         return lb;
     }
-    // kappa_1 = ||M_0||_1 ||M_0^-1||_1
+    // kappa_1 = ||M_0||_1 ||M_0^-1||_1, into its own flag (s_flag[0] may
+    // still be read by other waves)
     if (tid < 64) {
         double cs = 0.0;
         if (tid < m)
@@ -1083,10 +1085,10 @@ __device__ __forceinline__ LemmaBits lemma_setup(const DevPlan &p, const RawSmem
             }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
-        if (tid == 0 && !(cs * s.red[G].x <= kLemmaMaxCond)) *s_flag = 0;
+        if (tid == 0) s_flag[1] = cs * s.red[G].x <= kLemmaMaxCond ? 1 : 0;
     }
     __syncthreads();
-    lb.ok = *s_flag;
+    lb.ok = s_flag[1];
     if (tid == 0) {
         // elimination (multipliers, updates of the m - 1 other rows over the
         // remaining left columns and the right half), scaling by the pivots

@@ -157,6 +157,7 @@ struct xf_plan {
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
     int last_lemma = 0;               // the last xf_probabilities call used the determinant lemma
+    int last_bwd_lemma = 0;           // the last xf_log_prob_backward call used the determinant lemma
     // determinant-lemma workspace: per-bitstring regions of (pattern, count) entries
     DevBuf dekey, decnt, decount;
     uint64_t entry_budget = 4ull << 30;   // bytes of workspace the chunking aims at
@@ -439,6 +440,21 @@ xf_status ensure_events(xf_plan *P, size_t n) {
 
 
 
+// Workspace of the determinant-lemma kernels for chunks of `chunk` bitstrings
+// with `cap` entries each (grown on demand; synchronises s before a resize).
+xf_status ensure_lemma_workspace(xf_plan *P, int64_t chunk, uint64_t cap, hipStream_t s) {
+    if (P->dekey.bytes >= (size_t)chunk * cap * 8 && P->decnt.bytes >= (size_t)chunk * cap * 8 &&
+        P->decount.bytes >= (size_t)chunk * 4)
+        return XF_OK;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
+    xf_status st;
+    if ((st = dev_upload(P->dekey, nullptr, (size_t)chunk * cap * 8)) ||
+        (st = dev_upload(P->decnt, nullptr, (size_t)chunk * cap * 8)) ||
+        (st = dev_upload(P->decount, nullptr, (size_t)chunk * 4)))
+        return st;
+    return XF_OK;
+}
+
 xf_status set_gate_tables(xf_plan *P) {
     // signs of the angles (phase i or -i of a d_1 choice)
     P->gneg.assign(std::max(P->k, 1), 0);
@@ -657,14 +673,7 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
             const int64_t chunk = std::min<int64_t>(B, per);
             const int64_t nchunks = (B + chunk - 1) / chunk;
             if ((st = ensure_events(P, 1 + 2 * (size_t)nchunks))) return st;
-            if (P->dekey.bytes < (size_t)chunk * cap * 8 || P->decnt.bytes < (size_t)chunk * cap * 8 ||
-                P->decount.bytes < (size_t)chunk * 4) {
-                if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
-                if ((st = dev_upload(P->dekey, nullptr, (size_t)chunk * cap * 8)) ||
-                    (st = dev_upload(P->decnt, nullptr, (size_t)chunk * cap * 8)) ||
-                    (st = dev_upload(P->decount, nullptr, (size_t)chunk * 4)))
-                    return st;
-            }
+            if ((st = ensure_lemma_workspace(P, chunk, cap, s))) return st;
             e = hipSuccess;
             for (int64_t c = 0; c < nchunks && e == hipSuccess; ++c) {
                 const int64_t b0 = c * chunk, nb = std::min(chunk, B - b0);
@@ -714,6 +723,7 @@ xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
     work->rank_sum = (int64_t)v[1];
     work->flops = (double)v[2];
     work->lemma = P->last_lemma;
+    work->backward_lemma = P->last_bwd_lemma;
     work->sample_ms = 0.0;
     work->eval_ms = 0.0;
     for (int i = 1; i < P->nev; ++i) {
@@ -780,29 +790,60 @@ xf_status xf_log_prob_backward(xf_plan *P, const xf_bits128 *d_bits, int64_t B, 
             if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
             if ((st = build_exact_terms(P, true))) return st;
         }
-        const int nparts = (int)std::min<int64_t>(B, 1024);
+        const bool mixed = P->precision == XF_MIXED;
+        const int ngroups = xf::kThreads / G;   // partials per LU-backward workgroup
+        const bool lemma = mode == XF_RAW_ESTIMATE && xf::backward_uses_lemma(d, P->evaluation == XF_EVAL_LU ? 1 : 0);
+        if (mode == XF_RAW_ESTIMATE) d.scale = std::sqrt(extent_of(P->theta)) / (double)t;
+        // partials: [lemma workgroups][LU workgroups x lane groups]
+        int64_t chunk = B, nchunks = 1;
+        uint64_t cap = 0;
+        int n_lemma = 0, n_lu = 0;
+        if (lemma) {
+            cap = xf::lemma_entry_cap(t);
+            const int64_t per = (int64_t)std::max<uint64_t>(1, P->entry_budget / (cap * 16 + 4));
+            chunk = std::min<int64_t>(B, per);
+            nchunks = (B + chunk - 1) / chunk;
+            n_lemma = (int)std::min<int64_t>(chunk, 1024);
+            n_lu = 64;   // deferred bitstrings only (rare)
+            if ((st = ensure_lemma_workspace(P, chunk, cap, s))) return st;
+        } else {
+            n_lu = (int)std::min<int64_t>(B, 256);
+        }
+        const int nparts = n_lemma + n_lu * ngroups;
         const size_t part_bytes = (size_t)nparts * lay.stride * 16;
         if ((st = dev_upload(P->dpart, nullptr, part_bytes)) || (st = dev_upload(P->dgsum, nullptr, (size_t)lay.stride * 16)))
             return st;
         hipError_t e = xf::launch_fill_zero((double *)P->dpart.p, part_bytes / 8, s);
+        double2 *part = (double2 *)P->dpart.p;
+        double2 *part_lu = part + (size_t)n_lemma * lay.stride;
         if (e == hipSuccess) {
-            if (mode == XF_RAW_ESTIMATE) {
-                d.scale = std::sqrt(extent_of(P->theta)) / (double)t;
-                e = xf::launch_raw_estimate_bwd(d, P->precision == XF_MIXED, (const uint64_t *)d_bits, B, t, seed,
-                                                d_grad_logp, (double2 *)P->dpart.p, nparts, lay, s);
+            if (lemma) {
+                for (int64_t c = 0; c < nchunks && e == hipSuccess; ++c) {
+                    const int64_t b0 = c * chunk, nb = std::min(chunk, B - b0);
+                    e = xf::launch_lemma_bwd_chunk(d, (const uint64_t *)d_bits, b0, nb, t, seed,
+                                                   (uint64_t *)P->dekey.p, (int2 *)P->decnt.p,
+                                                   (uint32_t *)P->decount.p, cap, d_grad_logp, part, n_lemma, lay, s);
+                    if (e == hipSuccess)
+                        e = xf::launch_raw_estimate_bwd(d, mixed, (const uint64_t *)d_bits, b0, nb, t, seed,
+                                                        d_grad_logp, part_lu, n_lu, lay,
+                                                        (const uint32_t *)P->decount.p, s);
+                }
+            } else if (mode == XF_RAW_ESTIMATE) {
+                e = xf::launch_raw_estimate_bwd(d, mixed, (const uint64_t *)d_bits, 0, B, t, seed, d_grad_logp,
+                                                part_lu, n_lu, lay, nullptr, s);
             } else {
-                e = xf::launch_exact_bwd(d, P->precision == XF_MIXED, (const uint64_t *)P->dxkeys.p,
-                                         (const double2 *)P->dxw.p, (const double2 *)P->dxdw.p, P->nxterms,
-                                         (const uint64_t *)d_bits, B, d_grad_logp, (double2 *)P->dpart.p, nparts,
-                                         lay, s);
+                e = xf::launch_exact_bwd(d, mixed, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p,
+                                         (const double2 *)P->dxdw.p, P->nxterms, (const uint64_t *)d_bits, B,
+                                         d_grad_logp, part_lu, n_lu, lay, s);
             }
         }
         if (e == hipSuccess)
-            e = xf::launch_reduce_parts((const double2 *)P->dpart.p, nparts, lay.stride, (double2 *)P->dgsum.p, s);
+            e = xf::launch_reduce_parts(part, nparts, lay.stride, (double2 *)P->dgsum.p, s);
         if (e != hipSuccess) return fail(XF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
         if (hipMemcpyAsync(red.data(), P->dgsum.p, (size_t)lay.stride * 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return fail(XF_EDEVICE, "could not read back the gradient sums");
+        P->last_bwd_lemma = lemma ? 1 : 0;
     }
     // Host FP64 chain rule from the factors back to rotations and angles.
     // All Gbar below are holomorphic adjoints: dL = 2 Re sum Gbar .* dZ.

@@ -53,7 +53,8 @@ struct DevPlan {
     double scale;             // Raw Estimate: sqrt(xi*) / t
 };
 
-// One workgroup's partial gradient (complex entries, offsets in double2):
+// One partial gradient (of a workgroup of the lemma backward, or of a lane
+// group of the LU backward; complex entries, offsets in double2):
 //   oP   Gbar_P    n x G (row stride G)
 //   oPhi Gbar_Phi0 n x G (row stride G)
 //   oA1  Gbar_A1   n x n
@@ -81,12 +82,26 @@ hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0
                               uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,
                               double *prob, double *amp, double *logp, unsigned long long *nterm,
                               hipEvent_t ev_mid, hipStream_t s);
+// Determinant-lemma backward for bitstrings [b0, b0 + nb): the sampler kernel
+// refills the workspace, then k_bwd_entries adds each bitstring's adjoint into
+// workgroup partial i of part (nparts of them, stride lay.stride); bitstrings
+// it cannot take get ecount = kEntryDeferred (see launch_raw_estimate_bwd).
+bool backward_uses_lemma(const DevPlan &p, int algorithm);
+size_t bwd_lemma_lds(const DevPlan &p);
+hipError_t launch_lemma_bwd_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                                  uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,
+                                  const double *g, double2 *part, int nparts, const GradLayout &lay,
+                                  hipStream_t s);
 hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
                         int64_t nkeys, const uint64_t *bits, int64_t B, double *prob, double *amp,
                         double *logp, unsigned long long *nterm, hipStream_t s);
-hipError_t launch_raw_estimate_bwd(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B,
-                                   int64_t t, uint64_t seed, const double *g, double2 *part, int nparts,
-                                   const GradLayout &lay, hipStream_t s);
+// LU backward kernels: every lane group (kThreads / G per workgroup) adds into
+// its own partial, so nwg workgroups use nwg * kThreads / G partials.  With
+// only != NULL just the bitstrings i of [b0, b0 + nb) with only[i] ==
+// kEntryDeferred are taken.
+hipError_t launch_raw_estimate_bwd(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t b0, int64_t nb,
+                                   int64_t t, uint64_t seed, const double *g, double2 *part, int nwg,
+                                   const GradLayout &lay, const uint32_t *only, hipStream_t s);
 hipError_t launch_exact_bwd(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
                             const double2 *dw, int64_t nkeys, const uint64_t *bits, int64_t B,
                             const double *g, double2 *part, int nparts, const GradLayout &lay,

@@ -113,12 +113,7 @@ def _rotation_with_row(rng, v):
     return Q.conj().T
 
 
-@pytest.mark.parametrize("offset", [0.0, 1e-7], ids=["orthogonal", "near_orthogonal"])
-def test_ill_conditioned_base_falls_back(X, offset):
-    """Row 0 of the second rotation is (nearly) orthogonal to the columns of
-    D_0 R_0[:, C], so every bitstring with mode 0 occupied has a (nearly)
-    singular base M_0 = P[R, :] while its flipped submatrices are regular."""
-    say(f"ill-conditioned bases, offset {offset}")
+def _ill_conditioned_circuit(offset):
     rng = W.rng_for(606)
     n, eta, k = 10, 4, 9
     R0 = W.haar_unitary(rng, n)
@@ -146,12 +141,66 @@ def test_ill_conditioned_base_falls_back(X, offset):
         if 0 in R:
             conds.append(float(np.real(np.linalg.cond(P[R, :], 1))))
     assert min(conds) > 1e4
+    return rot, pairs, theta, inp, bits
+
+
+@pytest.mark.parametrize("offset", [0.0, 1e-7], ids=["orthogonal", "near_orthogonal"])
+def test_ill_conditioned_base_falls_back(X, offset):
+    """Row 0 of the second rotation is (nearly) orthogonal to the columns of
+    D_0 R_0[:, C], so every bitstring with mode 0 occupied has a (nearly)
+    singular base M_0 = P[R, :] while its flipped submatrices are regular."""
+    say(f"ill-conditioned bases, offset {offset}")
+    rot, pairs, theta, inp, bits = _ill_conditioned_circuit(offset)
+    k = len(theta)
     ref = oracle.probabilities(rot, pairs, np.zeros(k), theta, inp, bits, "approx", 3000, 8)
     assert np.count_nonzero(ref) > len(bits) // 2
     plan = X.Plan(rot, pairs, np.zeros(k), theta, inp)
     p, wk = _probs(plan, X, bits, 3000, 8, "auto")
     assert wk["lemma"]
     _check(p, ref, TOL_FP64, "fallback bases")
+
+
+def _grad_rel(a, b, floor=1e-6):
+    scale = max(np.max(np.abs(b)), 1e-300)
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(b), floor * scale)))
+
+
+@pytest.mark.parametrize("offset", [0.0, 1e-7], ids=["orthogonal", "near_orthogonal"])
+def test_backward_defers_ill_conditioned_bases(X, offset):
+    """The lemma backward leaves bitstrings with an ill-conditioned base to
+    the LU backward within the same call; the gradient matches the oracle."""
+    say(f"backward with ill-conditioned bases, offset {offset}")
+    rot, pairs, theta, inp, bits = _ill_conditioned_circuit(offset)
+    k = len(theta)
+    g = np.random.default_rng(7).standard_normal(len(bits))
+    plan = X.Plan(rot, pairs, np.zeros(k), theta, inp)
+    grot, gth = plan.log_prob_backward(X.bits_tensor(bits), torch.tensor(g, device="cuda"), "approx", 3000, 8)
+    assert plan.last_work()["backward_lemma"]
+    orot, oth = oracle.log_prob_grad(rot, pairs, np.zeros(k), theta, inp, bits, g, "approx", 3000, 8)
+    er, et = _grad_rel(grot, orot), _grad_rel(gth, oth)
+    say(f"  rotation grad rel err {er:.2e}, angle grad rel err {et:.2e}")
+    assert er < 1e-8 and et < 1e-8
+
+
+def test_backward_with_many_flips(X):
+    """Patterns flipping up to G modes (lane-group adjugates) and beyond (LU
+    backward for those bitstrings) in one backward call."""
+    say("backward, many flips: n=16 eta=6 k=40 theta~U[-3,3] t=4096")
+    rng = W.rng_for(404)
+    n = 16
+    rot = np.stack([W.haar_unitary(rng, n) for _ in range(2)])
+    pairs = W.random_pairs(rng, n, 40)
+    theta = rng.uniform(-3.0, 3.0, 40)
+    inp = W.bits_from_modes(range(6))
+    bits = W.all_fixed_weight(n, 6)[::997][:8]
+    g = np.random.default_rng(8).standard_normal(len(bits))
+    plan = X.Plan(rot, pairs, np.zeros(40), theta, inp)
+    grot, gth = plan.log_prob_backward(X.bits_tensor(bits), torch.tensor(g, device="cuda"), "approx", 4096, 9)
+    assert plan.last_work()["backward_lemma"]
+    orot, oth = oracle.log_prob_grad(rot, pairs, np.zeros(40), theta, inp, bits, g, "approx", 4096, 9)
+    er, et = _grad_rel(grot, orot), _grad_rel(gth, oth)
+    say(f"  rotation grad rel err {er:.2e}, angle grad rel err {et:.2e}")
+    assert er < 1e-8 and et < 1e-8
 
 
 def test_exactly_singular_bases(X):
