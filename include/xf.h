@@ -148,6 +148,27 @@ xf_status xf_probabilities(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, x
                            int64_t t, uint64_t seed, double *d_prob, double *d_amp,
                            double *d_logp, void *hip_stream);
 
+/* No-allocation variant of xf_probabilities, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  Same arguments, results (bitwise) and errors as
+ * xf_probabilities, except:
+ *   - the determinant-lemma workspace is a fixed device array of 256 MiB per
+ *     device, held until the process ends; bitstrings are processed in chunks
+ *     of floor(2^28 / ((t + t/511 + 2) * 16 + 4)), and XF_EUNSUPPORTED is
+ *     returned if one bitstring does not fit (t above about 1.67e7);
+ *   - no device memory, pinned host memory or event is allocated and no
+ *     kernel time is recorded (xf_plan_last_work reports zero times); the
+ *     first call on a device looks up the array's device address;
+ *   - exact mode needs the term list that an earlier xf_probabilities call on
+ *     the plan built for the current parameters (XF_EUNSUPPORTED otherwise).
+ * All calls on one device share its array and leave their contents in it (no
+ * part of it needs to start at zero): calls that overlap in time on one
+ * device, from different streams, plans or host threads, race and give wrong
+ * results; serialise them. */
+xf_status xf_probabilities_noalloc(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, xf_mode mode,
+                                   int64_t t, uint64_t seed, double *d_prob, double *d_amp,
+                                   double *d_logp, void *hip_stream);
+
 /* Gradient of L = sum_b g_b log p_b, g = d_grad_logp (device [B] doubles),
  * with respect to every rotation entry (h_grad_rot, host [n_rot][n][n][2],
  * as dL/dRe + i dL/dIm) and every angle (h_grad_theta, host [k]).  Same

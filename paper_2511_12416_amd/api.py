@@ -160,6 +160,22 @@ class Plan:
             return out, torch.view_as_complex(amp)
         return out
 
+    def probabilities_noalloc(self, bits: torch.Tensor, out: torch.Tensor, mode: str = "approx", t: int = 0,
+                              seed: int = 0, amp: Optional[torch.Tensor] = None,
+                              logp: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """probabilities() through xf_probabilities_noalloc: the library
+        allocates nothing (its workspace is a fixed per-device array), so the
+        caller passes every output tensor."""
+        bits = bits.contiguous()
+        if bits.device != self.device or bits.dtype != torch.int64:
+            raise ValueError("bits must be an int64 tensor on the plan's device")
+        check(lib().xf_probabilities_noalloc(self._h, bits.data_ptr(), bits.shape[0], _MODES[mode], int(t),
+                                             int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(),
+                                             amp.data_ptr() if amp is not None else None,
+                                             logp.data_ptr() if logp is not None else None,
+                                             _stream_handle(self.device)))
+        return out
+
     def log_prob_backward(self, bits: torch.Tensor, grad_logp: torch.Tensor, mode: str = "exact",
                           t: int = 0, seed: int = 0):
         """(dL/drot as complex [n_rot, n, n], dL/dtheta [k]) for L = sum_b g_b log p_b."""

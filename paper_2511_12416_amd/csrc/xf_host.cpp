@@ -631,8 +631,17 @@ xf_status xf_trajectory_bound(double eps, double delta, double p_max, double xi,
     return ok();
 }
 
-xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_mode mode, int64_t t,
-                           uint64_t seed, double *d_prob, double *d_amp, double *d_logp, void *hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// Shared by xf_probabilities and xf_probabilities_noalloc.  With noalloc the
+// determinant-lemma workspace is the fixed device scratch, no timing events
+// are recorded, and nothing is allocated (exact mode then needs the term list
+// an earlier call built).
+xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_mode mode, int64_t t,
+                             uint64_t seed, double *d_prob, double *d_amp, double *d_logp, void *hip_stream,
+                             bool noalloc) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
     if (B < 0) return fail(XF_EINVAL, "B < 0");
     if (mode != XF_EXACT && mode != XF_RAW_ESTIMATE) return fail(XF_EINVAL, "unknown mode");
@@ -645,60 +654,107 @@ xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_m
         return fail(XF_EUNSUPPORTED, "exact mode needs k <= 24 (k = %d)", P->k);
     }
     if (B > 0 && (!d_bits || !d_prob)) return fail(XF_EINVAL, "d_bits or d_prob is NULL");
+    if (noalloc && mode == XF_EXACT && P->nxterms < 0 && B > 0)
+        return fail(XF_EUNSUPPORTED, "exact mode without allocation needs the term list of an earlier "
+                                     "xf_probabilities call with the current parameters");
     DeviceGuard guard(P->device);
     if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
     hipStream_t s = (hipStream_t)hip_stream;
+    xf::DevPlan d = snapshot(P);
+    const bool mixed = P->precision == XF_MIXED;
+    const int alg = P->evaluation == XF_EVAL_LU ? 1 : 0;
+    const bool lemma = mode == XF_RAW_ESTIMATE && xf::raw_estimate_uses_lemma(d, alg);
+    // lemma workspace: chunks of bitstrings whose entry regions fit
+    uint64_t cap = 0;
+    int64_t chunk = B, nchunks = 1;
+    uint64_t *ekey = nullptr;
+    int2 *ecnt = nullptr;
+    uint32_t *ecount = nullptr;
+    if (lemma && B > 0) {
+        cap = xf::lemma_entry_cap(t);
+        const uint64_t per_bits = cap * 16 + 4;
+        if (noalloc) {
+            if (per_bits > xf::kNoAllocScratchBytes)
+                return fail(XF_EUNSUPPORTED, "t = %lld needs %llu bytes of scratch per bitstring; the no-allocation "
+                            "scratch holds %llu", (long long)t, (unsigned long long)per_bits,
+                            (unsigned long long)xf::kNoAllocScratchBytes);
+            chunk = std::min<int64_t>(B, (int64_t)(xf::kNoAllocScratchBytes / per_bits));
+        } else {
+            chunk = std::min<int64_t>(B, (int64_t)std::max<uint64_t>(1, P->entry_budget / per_bits));
+        }
+        nchunks = (B + chunk - 1) / chunk;
+    }
+    xf_status st;
+    if (!noalloc) {
+        if (mode == XF_EXACT && P->nxterms < 0 && B > 0) {
+            if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
+            if ((st = build_exact_terms(P, false))) return st;
+        }
+        if ((st = ensure_events(P, lemma ? 1 + 2 * (size_t)nchunks : 2))) return st;
+        if (lemma && B > 0) {
+            if ((st = ensure_lemma_workspace(P, chunk, cap, s))) return st;
+            ekey = (uint64_t *)P->dekey.p;
+            ecnt = (int2 *)P->decnt.p;
+            ecount = (uint32_t *)P->decount.p;
+        }
+    } else if (lemma && B > 0) {
+        void *base = nullptr;
+        if (xf::noalloc_scratch(P->device, &base) != hipSuccess)
+            return fail(XF_EDEVICE, "could not resolve the device scratch");
+        ekey = (uint64_t *)base;
+        ecnt = (int2 *)((unsigned char *)base + (size_t)chunk * cap * 8);
+        ecount = (uint32_t *)((unsigned char *)base + (size_t)chunk * cap * 16);
+    }
     if (xf::launch_zero_u64((unsigned long long *)P->dnterm.p, s) != hipSuccess)
         return fail(XF_EDEVICE, "launch failed: %s", hipGetErrorString(hipGetLastError()));
     P->last_lemma = 0;
     P->nev = 0;
     if (B == 0) return ok();
-    xf_status st;
-    if (mode == XF_EXACT && P->nxterms < 0) {
-        if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
-        if ((st = build_exact_terms(P, false))) return st;
-    }
-    xf::DevPlan d = snapshot(P);
-    hipError_t e;
-    if ((st = ensure_events(P, 2))) return st;
-    if (hipEventRecord(P->ev[0], s) != hipSuccess) return fail(XF_EDEVICE, "hipEventRecord failed");
+    const bool timed = !noalloc;
+    hipError_t e = hipSuccess;
+    if (timed && hipEventRecord(P->ev[0], s) != hipSuccess) return fail(XF_EDEVICE, "hipEventRecord failed");
     if (mode == XF_RAW_ESTIMATE) {
         d.scale = std::sqrt(extent_of(P->theta)) / (double)t;
-        const bool mixed = P->precision == XF_MIXED;
-        const int alg = P->evaluation == XF_EVAL_LU ? 1 : 0;
-        if (xf::raw_estimate_uses_lemma(d, alg)) {
-            const uint64_t cap = xf::lemma_entry_cap(t);
-            // bitstrings are processed in chunks whose entry regions fit in the budget
-            const int64_t per = (int64_t)std::max<uint64_t>(1, P->entry_budget / (cap * 16 + 4));
-            const int64_t chunk = std::min<int64_t>(B, per);
-            const int64_t nchunks = (B + chunk - 1) / chunk;
-            if ((st = ensure_events(P, 1 + 2 * (size_t)nchunks))) return st;
-            if ((st = ensure_lemma_workspace(P, chunk, cap, s))) return st;
-            e = hipSuccess;
+        if (lemma) {
             for (int64_t c = 0; c < nchunks && e == hipSuccess; ++c) {
                 const int64_t b0 = c * chunk, nb = std::min(chunk, B - b0);
-                e = xf::launch_lemma_chunk(d, (const uint64_t *)d_bits, b0, nb, t, seed, (uint64_t *)P->dekey.p,
-                                           (int2 *)P->decnt.p, (uint32_t *)P->decount.p, cap, d_prob, d_amp,
-                                           d_logp, (unsigned long long *)P->dnterm.p, P->ev[1 + 2 * c], s);
-                if (e == hipSuccess) e = hipEventRecord(P->ev[2 + 2 * c], s);
+                e = xf::launch_lemma_chunk(d, (const uint64_t *)d_bits, b0, nb, t, seed, ekey, ecnt, ecount, cap,
+                                           d_prob, d_amp, d_logp, (unsigned long long *)P->dnterm.p,
+                                           timed ? P->ev[1 + 2 * c] : nullptr, s);
+                if (e == hipSuccess && timed) e = hipEventRecord(P->ev[2 + 2 * c], s);
             }
-            P->nev = 1 + 2 * (int)nchunks;
+            P->nev = timed ? 1 + 2 * (int)nchunks : 0;
             P->last_lemma = 1;
         } else {
             e = xf::launch_raw_estimate(d, mixed, alg, (const uint64_t *)d_bits, B, t, seed, d_prob, d_amp, d_logp,
                                         (unsigned long long *)P->dnterm.p, s);
-            if (e == hipSuccess) e = hipEventRecord(P->ev[1], s);
-            P->nev = 2;
+            if (e == hipSuccess && timed) e = hipEventRecord(P->ev[1], s);
+            P->nev = timed ? 2 : 0;
         }
     } else {
-        e = xf::launch_exact(d, P->precision == XF_MIXED, (const uint64_t *)P->dxkeys.p,
-                             (const double2 *)P->dxw.p, P->nxterms, (const uint64_t *)d_bits, B, d_prob,
-                             d_amp, d_logp, (unsigned long long *)P->dnterm.p, s);
-        if (e == hipSuccess) e = hipEventRecord(P->ev[1], s);
-        P->nev = 2;
+        e = xf::launch_exact(d, mixed, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p, P->nxterms,
+                             (const uint64_t *)d_bits, B, d_prob, d_amp, d_logp,
+                             (unsigned long long *)P->dnterm.p, s);
+        if (e == hipSuccess && timed) e = hipEventRecord(P->ev[1], s);
+        P->nev = timed ? 2 : 0;
     }
     if (e != hipSuccess) return fail(XF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+xf_status xf_probabilities(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_mode mode, int64_t t,
+                           uint64_t seed, double *d_prob, double *d_amp, double *d_logp, void *hip_stream) {
+    return probabilities_impl(P, d_bits, B, mode, t, seed, d_prob, d_amp, d_logp, hip_stream, false);
+}
+
+xf_status xf_probabilities_noalloc(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf_mode mode, int64_t t,
+                                   uint64_t seed, double *d_prob, double *d_amp, double *d_logp,
+                                   void *hip_stream) {
+    return probabilities_impl(P, d_bits, B, mode, t, seed, d_prob, d_amp, d_logp, hip_stream, true);
 }
 
 xf_status xf_plan_last_term_count(xf_plan *P, int64_t *count, int64_t *rank_sum) {

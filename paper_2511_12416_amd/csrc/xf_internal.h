@@ -18,6 +18,8 @@ constexpr int kThreads = 256;
 constexpr int kHashSlots = 2048;
 // Chunk of the shared exact-mode term list evaluated per LDS pass.
 constexpr int kExactChunk = 2048;
+// Bytes of the fixed device scratch of xf_probabilities_noalloc (per device).
+constexpr size_t kNoAllocScratchBytes = 256ull << 20;
 // Empty-slot marker; valid keys use at most 63 bits.
 constexpr uint64_t kEmptyKey = ~0ull;
 
@@ -139,6 +141,9 @@ hipError_t prepare_bwd(int G);
 hipError_t launch_raw_deferred(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
                                uint64_t seed, double *prob, double *amp, double *logp,
                                unsigned long long *nterm, const uint32_t *ecount, int grid, hipStream_t s);
+// Device address of the no-allocation scratch on `device` (current), looked up
+// once per device (k_noalloc.hip).
+hipError_t noalloc_scratch(int device, void **ptr);
 size_t raw_estimate_lds_bytes(const DevPlan &p, bool mixed);
 size_t exact_lds_bytes(const DevPlan &p);
 size_t raw_estimate_bwd_lds_bytes(const DevPlan &p, bool mixed);

@@ -1,0 +1,80 @@
+"""xf_probabilities_noalloc (fixed per-device scratch, no allocation) against
+xf_probabilities through the C ABI: bitwise equal results on two calls in a
+row, the second with a smaller batch of another circuit; a clear error when
+one bitstring's workspace does not fit the scratch."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import make_plan, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_12416_amd as X
+    X.lib()
+    return X
+
+
+def _both(X, plan, bits, t, seed):
+    lib = X.lib()
+    B = bits.shape[0]
+    stream = torch.cuda.current_stream().cuda_stream
+    outs = []
+    for fn in (lib.xf_probabilities, lib.xf_probabilities_noalloc):
+        p = torch.full((B,), -1.0, dtype=torch.float64, device="cuda")
+        a = torch.full((B, 2), -1.0, dtype=torch.float64, device="cuda")
+        lp = torch.full((B,), -1.0, dtype=torch.float64, device="cuda")
+        X._abi.check(fn(plan._h, bits.data_ptr(), B, X._abi.XF_RAW_ESTIMATE, t, seed, p.data_ptr(),
+                        a.data_ptr(), lp.data_ptr(), ctypes.c_void_p(stream)))
+        torch.cuda.synchronize()
+        outs.append((p.cpu().numpy(), a.cpu().numpy(), lp.cpu().numpy()))
+    return outs
+
+
+def test_noalloc_matches_allocating_call_twice(X):
+    # 1: the LUCJ workload at full batch (several scratch chunks of about 1000
+    # bitstrings each), determinant-lemma path
+    w = W.workload(2)
+    say(f"no-allocation call 1: {w.name}")
+    plan = make_plan(w, X)
+    (p1, a1, l1), (q1, b1, m1) = _both(X, plan, X.bits_tensor(w.bits), w.t, w.seed)
+    assert plan.last_work()["lemma"]
+    assert np.array_equal(p1, q1) and np.array_equal(a1, b1) and np.array_equal(l1, m1)
+    assert np.count_nonzero(p1) == w.B
+    # 2: a smaller batch of the generator workload (one chunk)
+    w2 = W.workload(4, B=1500)
+    say(f"no-allocation call 2: {w2.name} B={w2.B} t=4096")
+    plan2 = make_plan(w2, X)
+    (p2, a2, l2), (q2, b2, m2) = _both(X, plan2, X.bits_tensor(w2.bits), 4096, 77)
+    assert np.array_equal(p2, q2) and np.array_equal(a2, b2) and np.array_equal(l2, m2)
+    assert np.count_nonzero(p2) == w2.B
+
+
+def test_noalloc_rejects_a_workspace_beyond_the_scratch(X):
+    w = W.workload(2, B=4)
+    plan = make_plan(w, X)
+    out = torch.empty(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(X.XfError) as e:
+        plan.probabilities_noalloc(X.bits_tensor(w.bits), out, "approx", (1 << 31) - 1, 1)
+    assert e.value.status == 2 and "scratch" in str(e.value)
+
+
+def test_noalloc_exact_needs_a_built_term_list(X):
+    w = W.workload(1)
+    plan = make_plan(w, X)
+    bits = X.bits_tensor(w.bits)
+    out = torch.empty(w.B, dtype=torch.float64, device="cuda")
+    with pytest.raises(X.XfError) as e:
+        plan.probabilities_noalloc(bits, out, "exact")
+    assert e.value.status == 2
+    ref = plan.probabilities(bits, "exact").cpu().numpy()
+    plan.probabilities_noalloc(bits, out, "exact")
+    assert np.array_equal(out.cpu().numpy(), ref)
