@@ -232,6 +232,8 @@ typedef struct {
     double eval_ms;
     int32_t lemma;
     int32_t backward_lemma;   /* the last xf_log_prob_backward call used the determinant lemma */
+    int32_t general;          /* the call used the general determinant-lemma kernel (see below) */
+    int64_t fp32_bases;       /* bases (per block) whose lemma products ran in FP32 (XF_MIXED) */
 } xf_work;
 xf_status xf_plan_last_work(xf_plan *plan, xf_work *work);
 

@@ -76,7 +76,8 @@ template <int G, bool MIXED>
 __global__ void __launch_bounds__(kThreads)
 k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict__ w, int64_t nkeys,
         const uint64_t *__restrict__ bits, int64_t B, double *__restrict__ prob,
-        double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
+        double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm,
+        const uint32_t *__restrict__ only) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok;
     double2 *out = (double2 *)smem;
@@ -88,6 +89,8 @@ k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict_
     constexpr int NG = kThreads / G;
     Work wk;
     for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+        // with `only`, just the bitstrings the lemma evaluation deferred
+        if (only && only[b] != kEntryDeferred) continue;
         if (!load_bitstring(p, bits, b, Rb, &s_ok)) {
             if (tid == 0) {
                 prob[b] = 0.0;
@@ -126,34 +129,33 @@ k_exact(DevPlan p, const uint64_t *__restrict__ keys, const double2 *__restrict_
     flush_work(wk, nterm);
 }
 
+// Bitstrings [b0, b0 + nb) (only: those with only[i] == kEntryDeferred) on a
+// grid of `grid` workgroups.
 template <int G, bool MIXED>
-hipError_t launch_raw_t(const DevPlan &p, int algorithm, const uint64_t *bits, int64_t B, int64_t t,
-                        uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
-                        hipStream_t s) {
-    const int grid = (int)(B < kMaxGrid ? B : kMaxGrid);
-    (void)algorithm;
+hipError_t launch_raw_t(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t, uint64_t seed,
+                        double *prob, double *amp, double *logp, unsigned long long *nterm, const uint32_t *only,
+                        int grid, hipStream_t s) {
     if constexpr (G <= 16) {
         if (use_stage(p, MIXED)) {
             const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, true);
-            hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 1>), dim3(grid), dim3(kThreads), lds, s, p, bits,
-                               (int64_t)0, B, (uint32_t)t, seed, prob, amp, logp, nterm, nullptr);
+            hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 1>), dim3(grid), dim3(kThreads), lds, s, p, bits, b0, nb,
+                               (uint32_t)t, seed, prob, amp, logp, nterm, only);
             return hipGetLastError();
         }
     }
     const size_t lds = raw_lds_bytes(p.k, p.n, G, MIXED, false);
-    hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 0>), dim3(grid), dim3(kThreads), lds, s, p, bits, (int64_t)0, B,
-                       (uint32_t)t, seed, prob, amp, logp, nterm, nullptr);
+    hipLaunchKernelGGL((k_raw_estimate<G, MIXED, 0>), dim3(grid), dim3(kThreads), lds, s, p, bits, b0, nb,
+                       (uint32_t)t, seed, prob, amp, logp, nterm, only);
     return hipGetLastError();
 }
 
 template <int G, bool MIXED>
 hipError_t launch_exact_t(const DevPlan &p, const uint64_t *keys, const double2 *w, int64_t nkeys,
                           const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
-                          unsigned long long *nterm, hipStream_t s) {
+                          unsigned long long *nterm, const uint32_t *only, int grid, hipStream_t s) {
     const size_t lds = exact_lds_bytes(p);
-    const int grid = (int)(B < kMaxGrid ? B : kMaxGrid);
     hipLaunchKernelGGL((k_exact<G, MIXED>), dim3(grid), dim3(kThreads), lds, s, p, keys, w, nkeys,
-                       bits, B, prob, amp, logp, nterm);
+                       bits, B, prob, amp, logp, nterm, only);
     return hipGetLastError();
 }
 

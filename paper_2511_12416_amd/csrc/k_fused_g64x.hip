@@ -5,10 +5,10 @@ namespace xf {
 
 hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
                            const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
-                           unsigned long long *nterm, hipStream_t s) {
+                           unsigned long long *nterm, const uint32_t *only, int grid, hipStream_t s) {
     switch (p.G) {
-        case 64: return mixed ? launch_exact_t<64, true>(p, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s)
-                         : launch_exact_t<64, false>(p, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s);
+        case 64: return mixed ? launch_exact_t<64, true>(p, keys, w, nkeys, bits, B, prob, amp, logp, nterm, only, grid, s)
+                         : launch_exact_t<64, false>(p, keys, w, nkeys, bits, B, prob, amp, logp, nterm, only, grid, s);
     }
     return hipErrorInvalidValue;
 }

@@ -5,6 +5,7 @@
 // determinant per pattern; and the adjoint of the same evaluation
 // (k_bwd_entries, lemma_bwd.h).
 #include "lemma_bwd.h"
+#include "sample_entries.h"
 #include "xf_device.h"
 
 namespace xf {
@@ -20,51 +21,6 @@ namespace {
 //   k_eval_entries: forms H for the bitstring and evaluates the entries in
 //     chunks of kHashSlots, summing count * det exactly.
 // ---------------------------------------------------------------------------
-template <int NT>
-__global__ void __launch_bounds__(NT)
-k_sample_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
-                 uint64_t *__restrict__ ekey, int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount,
-                 uint64_t cap) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_ok, s_n;
-    __shared__ int s_cnt[6];
-    const RawSmem s = carve_sampler(smem, p.k);
-    const int tid = threadIdx.x;
-    load_tables<NT>(p, s);
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    const uint32_t slot0 = hash_slot(0);
-    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
-        const int64_t b = b0 + i;
-        if (!load_bitstring(p, bits, b, s.Rb, &s_ok)) {
-            if (tid == 0) ecount[i] = kEntryInvalid;
-            continue;
-        }
-        uint64_t *kout = ekey + (size_t)i * cap;
-        int2 *cout = ecnt + (size_t)i * cap;
-        uint64_t cursor = 0;
-        bool overflow = false;
-        Sampler st;
-        clear_table<NT>(s, s_cnt, slot0, st);
-        while (true) {
-            const bool done = sample_until_flush<NT>(p, s, s_cnt, slot0, b, t, k0, k1, st);
-            const int nl = gather_list<NT>(s, &s_n);
-            if (cursor + (uint64_t)nl <= cap) {
-                for (int e = tid; e < nl; e += NT) {
-                    const uint16_t slot = s.list[e];
-                    kout[cursor + e] = s.hkey[slot];
-                    cout[cursor + e] = s.hcnt[slot];
-                }
-            } else {
-                overflow = true;
-            }
-            cursor += (uint64_t)nl;
-            if (done) break;
-            clear_table<NT>(s, s_cnt, slot0, st);
-        }
-        if (tid == 0) ecount[i] = overflow ? kEntryOverflow : (uint32_t)cursor;
-    }
-}
-
 template <int G>
 __global__ void __launch_bounds__(kThreads, 2)
 k_eval_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
@@ -178,7 +134,8 @@ hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0
     // then the LU kernel for the bitstrings the evaluation deferred, on a
     // smaller grid (its workgroups skip the other bitstrings at once; the
     // deferred ones are rare)
-    return launch_raw_deferred(p, bits, b0, nb, t, seed, prob, amp, logp, nterm, ecount, grid < 2048 ? grid : 2048, s);
+    return launch_raw_estimate(p, false, bits, b0, nb, t, seed, prob, amp, logp, nterm, ecount,
+                               grid < 2048 ? grid : 2048, s);
 }
 
 size_t bwd_lemma_lds(const DevPlan &p) { return lemma_lds(p) + bwd_lemma_extra(p.G, p.keybits); }

@@ -26,6 +26,7 @@ __global__ void k_zero_u64(unsigned long long *p) {
     p[0] = 0ull;
     p[1] = 0ull;
     p[2] = 0ull;
+    p[3] = 0ull;
 }
 
 }  // namespace
@@ -53,23 +54,32 @@ hipError_t prepare_kernels(int G) {
     if ((e = prepare_fused_g64(G)) != hipSuccess) return e;
     if ((e = prepare_fused_g64x(G)) != hipSuccess) return e;
     if ((e = prepare_lemma(G)) != hipSuccess) return e;
+    if ((e = prepare_gen()) != hipSuccess) return e;
     return prepare_bwd(G);
 }
 
-hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, int, const uint64_t *bits, int64_t B, int64_t t,
+size_t raw_estimate_lds_bytes(const DevPlan &p, bool mixed) {
+    return raw_lds_bytes(p.k, p.n, p.G, mixed, p.G <= 16 && use_stage(p, mixed));
+}
+
+size_t exact_lds_bytes(const DevPlan &) { return kExactChunk * 16 + 2 * kThreads * 16 + 64; }
+
+hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
                                uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
-                               hipStream_t s) {
-    if (p.G <= 16) return fused_raw_small(p, mixed, bits, B, t, seed, prob, amp, logp, nterm, s);
-    if (p.G == 32) return fused_raw_g32(p, mixed, bits, B, t, seed, prob, amp, logp, nterm, s);
-    return fused_raw_g64(p, mixed, bits, B, t, seed, prob, amp, logp, nterm, s);
+                               const uint32_t *only, int grid, hipStream_t s) {
+    if (grid <= 0) grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
+    if (p.G <= 16) return fused_raw_small(p, mixed, bits, b0, nb, t, seed, prob, amp, logp, nterm, only, grid, s);
+    if (p.G == 32) return fused_raw_g32(p, mixed, bits, b0, nb, t, seed, prob, amp, logp, nterm, only, grid, s);
+    return fused_raw_g64(p, mixed, bits, b0, nb, t, seed, prob, amp, logp, nterm, only, grid, s);
 }
 
 hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
                         const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
-                        unsigned long long *nterm, hipStream_t s) {
-    if (p.G <= 16) return fused_exact_small(p, mixed, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s);
-    if (p.G == 32) return fused_exact_g32(p, mixed, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s);
-    return fused_exact_g64(p, mixed, keys, w, nkeys, bits, B, prob, amp, logp, nterm, s);
+                        unsigned long long *nterm, const uint32_t *only, int grid, hipStream_t s) {
+    if (grid <= 0) grid = (int)(B < kMaxGrid ? B : kMaxGrid);
+    if (p.G <= 16) return fused_exact_small(p, mixed, keys, w, nkeys, bits, B, prob, amp, logp, nterm, only, grid, s);
+    if (p.G == 32) return fused_exact_g32(p, mixed, keys, w, nkeys, bits, B, prob, amp, logp, nterm, only, grid, s);
+    return fused_exact_g64(p, mixed, keys, w, nkeys, bits, B, prob, amp, logp, nterm, only, grid, s);
 }
 
 }  // namespace xf

@@ -1,0 +1,612 @@
+// General determinant-lemma evaluation: exact mode and Raw Estimate, one or
+// two CPhase layers, bases of up to 32 rows, optionally split into two
+// independent blocks of modes.
+//
+// For one CPhase layer the trajectory submatrix is M_N = M_0 - 2 U[:, N] V[N, :]
+// with M_0 = P[R, :], U = A1[R, act], V = Phi0[act, :] (Sec. IV-B Eq. 16-19);
+// for two layers (the same form applied twice) U = [T[R, act0] | R'_2[R, act1]],
+// V = [Phi0[act0, :]; Q[act1, :] - 2 R'_1[act1, N0] Phi0[N0, :]], whose last
+// term depends on the layer-0 pattern N0.  The matrix determinant lemma gives
+//   det M_N = det M_0 det S_N,  S_N = I - 2 (V M_0^-1 U)[N, N],
+// and with H = [Phi0[act0, :]; Q[act1, :]] M_0^-1 U formed once per bitstring,
+// row i of S_N (flipped mode n_i, position p_i in act) is
+//   delta_ij - 2 H[p_i, p_j]                                  (n_i in N0)
+//   delta_ij - 2 (H[p_i, p_j] - 2 sum_{l in N0} R'_1[n_i, n_l] H[p_l, p_j])  (n_i in N1).
+//
+// Block factorisation: when every rotation layer is block-diagonal over a
+// partition of the modes (for instance spin-restricted layers U (+) U),
+// V(x) is block-diagonal for every trajectory (the CPhase layers are
+// diagonal), so det V(x)[R, C] is the product of the blocks' determinants
+// (zero unless R and C have the same number of modes in every block), and
+// each block has its own base, H and S_N.
+//
+// Per bitstring (one workgroup): for each block, the base M_0 is inverted by
+// Gauss-Jordan in LDS with partial pivoting (the whole workgroup updates, one
+// wave searches the pivot), checked for conditioning (kappa_1 <= 1e4, else
+// the bitstring is left to the LU kernels), and X = M_0^-1 U, H = V X are
+// formed on the matrix cores (v_mfma_f64_16x16x4f64; with MIXED,
+// v_mfma_f32_16x16x4f32 on FP32-rounded operands).  Then every distinct
+// pattern takes an r x r determinant per block: one lane for r <= 4, lane
+// groups of 8, 16 or 32 above; the weighted determinants are summed exactly.
+#pragma once
+#include "xf_device.h"
+
+namespace xf {
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int kGenMaxM = 32;      // rows of a block's base
+constexpr int kGenMaxKb = 64;     // active modes of a block (both layers)
+constexpr int kGenMaxRank = 32;   // flipped modes of a block in one pattern
+// Mixed precision forms X and H on the FP32 matrix cores only for bases with
+// kappa_1(M_0) at most this (the FP32 error of H grows with ||M_0^-1||);
+// other bases use FP64.
+constexpr double kMixedMaxCond = 50.0;
+// Setup scratch (the augmented base and X) overlays the entry slots, pivot
+// scratch and reduction scratch of the RawSmem layout: 40960 bytes.
+constexpr size_t kGenSetupBytes = (size_t)kHashSlots * 16 + 2 * (size_t)kThreads * 16;
+// Bytes of the RawSmem layout without sampling tables or staged factors.
+constexpr size_t kGenBaseBytes = ((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + 15) & ~(size_t)15;
+
+// C (M x N) = A (M x K) B (K x N), complex, on the matrix cores.  a_at(i, k)
+// and b_at(k, j) return operands, c_put(i, j, v) stores a result.  Each wave
+// of the workgroup computes whole 16 x 16 tiles of C: per 4-wide slice of K,
+// lane l supplies A[16 tm + l % 16][k0 + l / 16] and B[k0 + l / 16][16 tn + l % 16]
+// and the four real products re.re, -im.im, re.im, im.re accumulate into the
+// real and imaginary tiles.  Lane l then holds, in element r, C[16 tm + i][16 tn + l % 16]
+// with i = l / 16 + 4 r for the FP64 instruction and i = 4 (l / 16) + r for
+// the FP32 one (the two order their output rows differently).  Out-of-range
+// operands are zero.
+template <bool F32, class FA, class FB, class FC>
+__device__ __forceinline__ void cgemm_mfma(int M, int N, int K, FA a_at, FB b_at, FC c_put) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = kThreads / 64;
+    const int tm_n = (M + 15) / 16, tn_n = (N + 15) / 16;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = wave; t < tm_n * tn_n; t += NW) {
+        const int tm = t / tn_n, tn = t % tn_n;
+        const int row = tm * 16 + li, col = tn * 16 + li;
+        if constexpr (!F32) {
+            d4v cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < K; k0 += 4) {
+                const int k = k0 + lk;
+                const double2 a = (row < M && k < K) ? a_at(row, k) : make_double2(0.0, 0.0);
+                const double2 b = (k < K && col < N) ? b_at(k, col) : make_double2(0.0, 0.0);
+                cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+                cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int orow = tm * 16 + lk + 4 * r;
+                if (orow < M && col < N) c_put(orow, col, make_double2(cr[r], ci[r]));
+            }
+        } else {
+            f4v cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+            for (int k0 = 0; k0 < K; k0 += 4) {
+                const int k = k0 + lk;
+                const double2 a = (row < M && k < K) ? a_at(row, k) : make_double2(0.0, 0.0);
+                const double2 b = (k < K && col < N) ? b_at(k, col) : make_double2(0.0, 0.0);
+                const float ax = (float)a.x, ay = (float)a.y, bx = (float)b.x, by = (float)b.y;
+                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, bx, cr, 0, 0, 0);
+                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ay, by, cr, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, by, ci, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(ay, bx, ci, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int orow = tm * 16 + 4 * lk + r;
+                if (orow < M && col < N) c_put(orow, col, make_double2((double)cr[r], (double)ci[r]));
+            }
+        }
+    }
+}
+
+// Per-bitstring shared state of the general evaluation.
+struct GenShared {
+    int ok;                        // row counts / base status
+    int piv[kGenMaxM];             // pivot row of each column (Gauss-Jordan)
+    double2 uinv[kGenMaxM];        // 1 / pivot
+    double2 l[kGenMaxM];           // multipliers of the current step
+    double2 det;                   // product of the blocks' det M_0
+    double norm;                   // ||M_0||_1 of the current block
+    double kappa;                  // kappa_1(M_0) of the current block
+    int nrow[2];                   // rows of R in each block
+    uint8_t rows[2][kGenMaxM];     // those rows (modes), ascending
+};
+
+__device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+
+// Setup of block blk for the loaded bitstring: inverse of M_0 by
+// Gauss-Jordan (augmented rows [M_0 | I] in the setup scratch W, row stride
+// 2m; rows stay in place, row piv[c] ends as u_c e_c | u_c M_0^-1[c, :]),
+// conditioning test, then X = M_0^-1 U and H = V X.  Returns false if M_0 is
+// singular or kappa_1(M_0) > kLemmaMaxCond.  Whole workgroup.
+template <bool MIXED>
+__device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan &g, int blk, unsigned char *scratch,
+                                                double2 *H, GenShared &sh, Work &wk) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int m = g.mb[blk], kb = g.kb[blk], kb0 = g.kb0[blk], n = p.n, G = p.G;
+    const uint8_t *rows = sh.rows[blk];
+    const uint8_t *col = g.col + blk * kGenMaxM;
+    const uint8_t *act = g.act + blk * kGenMaxKb;
+    double2 *W = (double2 *)scratch;
+    const int ld = 2 * m;
+    double2 *X = (double2 *)(scratch + align16((size_t)m * ld * 16));
+    if (m == 0) {
+        for (int e = tid; e < kb * kb; e += kThreads) H[e] = make_double2(0.0, 0.0);
+        __syncthreads();
+        return true;
+    }
+    for (int e = tid; e < m * ld; e += kThreads) {
+        const int i = e / ld, j = e % ld;
+        W[e] = j < m ? p.P[(size_t)rows[i] * G + col[j]] : make_double2(j - m == i ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double cs = 0.0;
+        if (lane < m)
+            for (int i = 0; i < m; ++i) cs += sqrt(cabs2(W[i * ld + lane]));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
+        if (lane == 0) sh.norm = cs;
+    }
+    uint64_t used = 0;          // wave 0: rows already used as pivots
+    unsigned inversions = 0;    // wave 0
+    double2 det = make_double2(1.0, 0.0);   // wave 0
+    for (int c = 0; c < m; ++c) {
+        if (tid < 64) {
+            const bool act_row = lane < m && !((used >> lane) & 1);
+            const double v = act_row ? cabs2(W[lane * ld + c]) : -1.0;
+            double best = v;
+            int idx = lane;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double vo = __shfl_xor(best, off, 64);
+                const int io = __shfl_xor(idx, off, 64);
+                if (vo > best || (vo == best && io < idx)) {
+                    best = vo;
+                    idx = io;
+                }
+            }
+            if (best > 0.0) {
+                inversions += __popcll(~used & ((1ull << idx) - 1) & ((1ull << m) - 1));
+                used |= 1ull << idx;
+                const double2 u = W[idx * ld + c];
+                det = c_mul(det, u);
+                if (lane == 0) {
+                    sh.piv[c] = idx;
+                    const double inv = 1.0 / best;
+                    sh.uinv[c] = make_double2(u.x * inv, -u.y * inv);
+                }
+            } else if (lane == 0) {
+                sh.piv[c] = -1;
+            }
+        }
+        __syncthreads();
+        const int pr = sh.piv[c];
+        if (pr < 0) {
+            __syncthreads();
+            return false;   // exactly singular base
+        }
+        const double2 ui = sh.uinv[c];
+        if (tid < m && tid != pr) {
+            const double2 a = W[tid * ld + c];
+            sh.l[tid] = make_double2(-(a.x * ui.x - a.y * ui.y), -(a.x * ui.y + a.y * ui.x));
+        }
+        __syncthreads();
+        const int w = ld - c - 1;
+        for (int e = tid; e < m * w; e += kThreads) {
+            const int i = e / w, j = c + 1 + e % w;
+            if (i != pr) W[i * ld + j] = c_fma(W[i * ld + j], sh.l[i], W[pr * ld + j]);
+        }
+        __syncthreads();
+    }
+    // det M_0 (wave 0) and the conditioning: ||M_0^-1||_1 from rows piv[c] / u_c
+    if (tid < 64) {
+        double cs = 0.0;
+        if (lane < m)
+            for (int c = 0; c < m; ++c) cs += sqrt(cabs2(c_mul(W[sh.piv[c] * ld + m + lane], sh.uinv[c])));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
+        if (lane == 0) {
+            if (inversions & 1) det = make_double2(-det.x, -det.y);
+            sh.det = c_mul(sh.det, det);
+            sh.ok = cs * sh.norm <= kLemmaMaxCond ? 1 : 2;
+            sh.kappa = cs * sh.norm;
+            // Gauss-Jordan (m steps of m - 1 row updates over 2m - c - 1
+            // columns), conditioning, X and H
+            unsigned long long f = 0;
+            for (int c = 0; c < m; ++c) f += 11ull * (m - 1) + 8ull * (m - 1) * (2 * m - c - 1);
+            f += 8ull * m * m * kb + 8ull * kb * m * kb;
+            wk.flops += f;
+        }
+    }
+    __syncthreads();
+    if (sh.ok != 1) return false;
+    // X = M_0^-1 U (m x kb), then H = V X (kb x kb), V = [Phi0[act0, cols]; Q[act1, cols]]
+    const double2 *A1 = p.A1, *A2 = p.A2, *Phi0 = p.Phi0, *Q = p.Q;
+    auto minv = [&](int i, int k) { return c_mul(W[sh.piv[i] * ld + m + k], sh.uinv[i]); };
+    auto uop = [&](int k, int q) { return (q < kb0 ? A1 : A2)[(size_t)rows[k] * n + act[q]]; };
+    auto xput = [&](int i, int q, double2 v) { X[i * kb + q] = v; };
+    auto vop = [&](int q, int k) { return (q < kb0 ? Phi0 : Q)[(size_t)act[q] * G + col[k]]; };
+    auto xop = [&](int k, int q) { return X[k * kb + q]; };
+    auto hput = [&](int q, int q2, double2 v) { H[q * kb + q2] = v; };
+    if (MIXED && sh.kappa <= kMixedMaxCond) {
+        cgemm_mfma<true>(m, kb, m, minv, uop, xput);
+        __syncthreads();
+        cgemm_mfma<true>(kb, kb, m, vop, xop, hput);
+        if (tid == 0) ++wk.fp32;
+    } else {
+        cgemm_mfma<false>(m, kb, m, minv, uop, xput);
+        __syncthreads();
+        cgemm_mfma<false>(kb, kb, m, vop, xop, hput);
+    }
+    __syncthreads();
+    return true;
+}
+
+// Flipped modes of block blk in a pattern: the first NP of them (layer-0
+// modes ascending, then layer-1 modes ascending) with their positions in the
+// block's H; r0 layer-0 modes, r in all.
+template <int NP>
+__device__ __forceinline__ void gen_pattern(const GenPlan &g, const Flips &f, int blk, int &r0, int &r,
+                                            int (&pos)[NP], int (&md)[NP]) {
+    uint64_t a0 = f.n0[0] & g.bmask[blk][0], a1 = f.n0[1] & g.bmask[blk][1];
+    uint64_t b0 = f.n1[0] & g.bmask[blk][0], b1 = f.n1[1] & g.bmask[blk][1];
+    r0 = __popcll(a0) + __popcll(a1);
+    r = r0 + __popcll(b0) + __popcll(b1);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        int q = 0, ps = 0;
+        if (a0) {
+            q = __ffsll((long long)a0) - 1;
+            a0 &= a0 - 1;
+            ps = g.pos0[q];
+        } else if (a1) {
+            q = 64 + __ffsll((long long)a1) - 1;
+            a1 &= a1 - 1;
+            ps = g.pos0[q];
+        } else if (b0) {
+            q = __ffsll((long long)b0) - 1;
+            b0 &= b0 - 1;
+            ps = g.pos1[q];
+        } else if (b1) {
+            q = 64 + __ffsll((long long)b1) - 1;
+            b1 &= b1 - 1;
+            ps = g.pos1[q];
+        }
+        pos[i] = ps;
+        md[i] = q;
+    }
+}
+
+// Entry (i, j) of S_N for block blk (i, j < r); L2: two CPhase layers.
+template <int NP>
+__device__ __forceinline__ double2 gen_s_entry(const DevPlan &p, const double2 *H, int kb, int i, int j, int r0,
+                                               const int (&pos)[NP], const int (&md)[NP]) {
+    double2 h = H[pos[i] * kb + pos[j]];
+    if (p.L == 2 && i >= r0) {
+        double2 corr = make_double2(0.0, 0.0);
+        for (int l = 0; l < r0 && l < NP; ++l) corr = c_fma(corr, p.R1[(size_t)md[i] * p.n + md[l]], H[pos[l] * kb + pos[j]]);
+        h.x -= 2.0 * corr.x;
+        h.y -= 2.0 * corr.y;
+    }
+    return make_double2((i == j ? 1.0 : 0.0) - 2.0 * h.x, -2.0 * h.y);
+}
+
+// det of a 4 x 4 (top-left r x r of a, identity elsewhere) by LU with
+// partial pivoting (largest |a|^2, lowest row on ties), row swaps through
+// static-index selects; 0 for an exactly singular matrix.
+__device__ __forceinline__ double2 small_det4(double2 (&a)[4][4], int r) {
+    bool neg = false;
+    double2 det = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c < r) {
+            int piv = c;
+            double best = cabs2(a[c][c]);
+#pragma unroll
+            for (int i = c + 1; i < 4; ++i) {
+                const double v = cabs2(a[i][c]);
+                if (i < r && v > best) {
+                    best = v;
+                    piv = i;
+                }
+            }
+            if (!(best > 0.0)) return make_double2(0.0, 0.0);
+            neg ^= piv != c;
+#pragma unroll
+            for (int i = c + 1; i < 4; ++i) {
+                if (piv == i) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const double2 t = a[c][j];
+                        a[c][j] = a[i][j];
+                        a[i][j] = t;
+                    }
+                }
+            }
+            det = c_mul(det, a[c][c]);
+            const double inv = 1.0 / best;
+            const double2 ui = make_double2(-a[c][c].x * inv, a[c][c].y * inv);
+#pragma unroll
+            for (int i = c + 1; i < 4; ++i) {
+                if (i < r) {
+                    const double2 l = c_mul(a[i][c], ui);
+#pragma unroll
+                    for (int j = c + 1; j < 4; ++j) a[i][j] = c_fma(a[i][j], l, a[c][j]);
+                }
+            }
+        }
+    }
+    return neg ? make_double2(-det.x, -det.y) : det;
+}
+
+// Product over blocks of det S_N for a pattern whose blocks flip at most 4
+// modes each (one lane).
+__device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan &g, const double2 *Hbase,
+                                                const Flips &f) {
+    double2 det = make_double2(1.0, 0.0);
+    for (int blk = 0; blk < g.nblk; ++blk) {
+        int r0, r, pos[4], md[4];
+        gen_pattern<4>(g, f, blk, r0, r, pos, md);
+        if (r == 0) continue;
+        const double2 *H = Hbase + g.hoff[blk];
+        double2 a[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                a[i][j] = (i < r && j < r) ? gen_s_entry<4>(p, H, g.kb[blk], i, j, r0, pos, md)
+                                           : make_double2(i == j ? 1.0 : 0.0, 0.0);
+        det = c_mul(det, small_det4(a, r));
+    }
+    return det;
+}
+
+// Same by a group of GS lanes (row `lane` of S per lane; blocks flip at most
+// GS modes each); every lane of the group returns the product.
+template <int GS>
+__device__ __forceinline__ double2 gen_det_group(const DevPlan &p, const GenPlan &g, const double2 *Hbase,
+                                                 const Flips &f, int lane, double2 *piv) {
+    double2 det = make_double2(1.0, 0.0);
+    for (int blk = 0; blk < g.nblk; ++blk) {
+        int r0, r, pos[GS], md[GS];
+        gen_pattern<GS>(g, f, blk, r0, r, pos, md);
+        if (r == 0) continue;
+        const double2 *H = Hbase + g.hoff[blk];
+        double2 a[GS];
+#pragma unroll
+        for (int j = 0; j < GS; ++j)
+            a[j] = (lane < r && j < r) ? gen_s_entry<GS>(p, H, g.kb[blk], lane, j, r0, pos, md)
+                                       : make_double2(j == lane ? 1.0 : 0.0, 0.0);
+        det = c_mul(det, lu_det<GS>(a, r, lane, piv));
+    }
+    return det;
+}
+
+// Largest number of flipped modes of any block in the pattern.
+__device__ __forceinline__ int gen_max_rank(const GenPlan &g, const Flips &f) {
+    int rm = 0;
+    for (int blk = 0; blk < g.nblk; ++blk) {
+        const int r = __popcll(f.n0[0] & g.bmask[blk][0]) + __popcll(f.n0[1] & g.bmask[blk][1]) +
+                      __popcll(f.n1[0] & g.bmask[blk][0]) + __popcll(f.n1[1] & g.bmask[blk][1]);
+        rm = max(rm, r);
+    }
+    return rm;
+}
+
+// Evaluates the nl entries in the slots (keys in s.hkey; weights in s.hcnt
+// as Gaussian-integer counts, or, with w != nullptr, w[e] for entry e) and
+// adds weight * det M_0 * prod det S_N to the bitstring's exact sum.  Entries
+// are classified by their largest block rank (counting sort into s.piv) so
+// that lanes and lane groups of a pass take like patterns.  Returns false if a
+// block flips more than kGenMaxRank modes.
+__device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan &g, const RawSmem &s, int nl,
+                                                const double2 *Hbase, double2 *gpiv, const double2 *w,
+                                                double2 detB, Work &wk, uint64_t *sacc) {
+    const int tid = threadIdx.x;
+    int *cnt = (int *)s.red;   // [0..4] bins (lane, 8, 16, 32, too large), [8..12] cursors
+    uint16_t *order = (uint16_t *)s.piv;
+    if (tid < 16) cnt[tid] = 0;
+    __syncthreads();
+    for (int e = tid; e < nl; e += kThreads) {
+        const int r = gen_max_rank(g, decode_key(p, s.hkey[e]));
+        atomicAdd(&cnt[r <= 4 ? 0 : (r <= 8 ? 1 : (r <= 16 ? 2 : (r <= 32 ? 3 : 4)))], 1);
+    }
+    __syncthreads();
+    if (cnt[4] > 0) return false;
+    const int n0 = cnt[0], n1 = cnt[1], n2 = cnt[2], n3 = cnt[3];
+    __syncthreads();
+    if (tid == 0) {
+        cnt[8] = 0;
+        cnt[9] = n0;
+        cnt[10] = n0 + n1;
+        cnt[11] = n0 + n1 + n2;
+    }
+    __syncthreads();
+    for (int e = tid; e < nl; e += kThreads) {
+        const int r = gen_max_rank(g, decode_key(p, s.hkey[e]));
+        order[atomicAdd(&cnt[8 + (r <= 4 ? 0 : (r <= 8 ? 1 : (r <= 16 ? 2 : 3)))], 1)] = (uint16_t)e;
+    }
+    __syncthreads();
+    // value of entry e: weight * detB * prod det S, into its slot
+    auto store = [&](int e, double2 dS) {
+        const double2 d = c_mul(detB, dS);
+        double2 v;
+        if (w) {
+            v = c_mul(w[e], d);
+        } else {
+            const int2 c = s.hcnt[e];
+            v = make_double2((double)c.x * d.x - (double)c.y * d.y, (double)c.x * d.y + (double)c.y * d.x);
+        }
+        s.hkey[e] = (uint64_t)__double_as_longlong(v.x);
+        *(double *)&s.hcnt[e] = v.y;
+    };
+    // all decodes of a pass happen before its stores overwrite keys: each
+    // entry is read and written by the same lane (group)
+    for (int i = tid; i < n0; i += kThreads) {
+        const int e = order[i];
+        const Flips f = decode_key(p, s.hkey[e]);
+        store(e, gen_det_lane(p, g, Hbase, f));
+    }
+    {
+        const int l8 = tid & 7, g8 = tid >> 3;
+        for (int i = n0 + g8; i < n0 + n1; i += kThreads / 8) {
+            const int e = order[i];
+            const Flips f = decode_key(p, s.hkey[e]);
+            const double2 dS = gen_det_group<8>(p, g, Hbase, f, l8, gpiv + g8 * 8);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (l8 == 0) store(e, dS);
+        }
+    }
+    {
+        const int l16 = tid & 15, g16 = tid >> 4;
+        for (int i = n0 + n1 + g16; i < n0 + n1 + n2; i += kThreads / 16) {
+            const int e = order[i];
+            const Flips f = decode_key(p, s.hkey[e]);
+            const double2 dS = gen_det_group<16>(p, g, Hbase, f, l16, gpiv + g16 * 16);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (l16 == 0) store(e, dS);
+        }
+    }
+    {
+        const int l32 = tid & 31, g32 = tid >> 5;
+        for (int i = n0 + n1 + n2 + g32; i < n0 + n1 + n2 + n3; i += kThreads / 32) {
+            const int e = order[i];
+            const Flips f = decode_key(p, s.hkey[e]);
+            const double2 dS = gen_det_group<32>(p, g, Hbase, f, l32, gpiv + g32 * 32);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (l32 == 0) store(e, dS);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) wk.terms += (unsigned)nl;
+    // every slot e < nl holds a value: accumulate_slots reads s.list
+    for (int e = tid; e < nl; e += kThreads) s.list[e] = (uint16_t)e;
+    __syncthreads();
+    accumulate_slots(s, nl, sacc);
+    return true;
+}
+
+// Raw Estimate (EXACT = false; the entries of bitstring i are in the
+// workspace, written by k_sample_entries) or exact mode (EXACT = true; the
+// plan's shared term list, ecount[i] is only written to defer).  Bitstrings
+// whose base is singular or ill-conditioned, or with a pattern beyond
+// kGenMaxRank in a block, get ecount[i] = kEntryDeferred and are left to the
+// LU kernels.
+template <bool EXACT, bool MIXED>
+__global__ void __launch_bounds__(kThreads, 1)
+k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
+           const uint64_t *__restrict__ ekey, const int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount,
+           uint64_t cap, const uint64_t *__restrict__ xkeys, const double2 *__restrict__ xw, int64_t nkeys,
+           double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
+           unsigned long long *nterm) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_ok;
+    __shared__ GenShared sh;
+    __shared__ uint64_t s_acc[kAccWords];
+    const RawSmem s = carve_raw(smem, 0, p.n, 4, false);
+    double2 *Hbase = (double2 *)(smem + kGenBaseBytes);
+    double2 *gpiv = Hbase + g.hsize;   // kThreads entries: LU pivot rows of the lane groups
+    const int tid = threadIdx.x;
+    Work wk;
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int64_t b = b0 + i;
+        uint32_t ne = 0;
+        bool zero = false;
+        if constexpr (!EXACT) {
+            ne = ecount[i];
+            zero = ne == kEntryInvalid;
+        }
+        if (!zero) zero = !load_bitstring(p, bits, b, s.Rb, &s_ok);
+        if (!zero) {
+            if (tid == 0) {
+                // rows of R in each block; an amplitude needs as many as the input has
+                sh.nrow[0] = sh.nrow[1] = 0;
+                sh.ok = 1;
+                for (int r = 0; r < p.m; ++r) {
+                    const int q = s.Rb[r];
+                    const int blk = g.blk[q];
+                    if (sh.nrow[blk] < kGenMaxM) sh.rows[blk][sh.nrow[blk]] = (uint8_t)q;
+                    ++sh.nrow[blk];
+                }
+                for (int blk = 0; blk < g.nblk; ++blk)
+                    if (sh.nrow[blk] != g.mb[blk]) sh.ok = 0;
+                sh.det = make_double2(1.0, 0.0);
+            }
+            __syncthreads();
+            zero = sh.ok == 0;
+            __syncthreads();
+        }
+        if (zero) {
+            if (tid == 0) {
+                prob[b] = 0.0;
+                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
+                if (logp) logp[b] = -INFINITY;
+                if constexpr (EXACT) ecount[i] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        if constexpr (!EXACT) {
+            if (ne == kEntryOverflow) {
+                if (tid == 0) {
+                    const double nan = __longlong_as_double(0x7FF8000000000000ll);
+                    prob[b] = nan;
+                    if (amp) { amp[2 * b] = nan; amp[2 * b + 1] = nan; }
+                    if (logp) logp[b] = nan;
+                }
+                __syncthreads();
+                continue;
+            }
+        }
+        bool ok = true;
+        for (int blk = 0; blk < g.nblk && ok; ++blk)
+            ok = gen_setup_block<MIXED>(p, g, blk, (unsigned char *)smem, Hbase + g.hoff[blk], sh, wk);
+        const double2 detB = sh.det;
+        acc_clear(s_acc);
+        __syncthreads();
+        const int64_t nent = EXACT ? nkeys : (int64_t)ne;
+        for (int64_t c0 = 0; ok && c0 < nent; c0 += kHashSlots) {
+            const int nc = (int)min((int64_t)kHashSlots, nent - c0);
+            for (int e = tid; e < nc; e += kThreads) {
+                if constexpr (EXACT) {
+                    s.hkey[e] = xkeys[c0 + e];
+                } else {
+                    s.hkey[e] = ekey[(size_t)i * cap + c0 + e];
+                    s.hcnt[e] = ecnt[(size_t)i * cap + c0 + e];
+                }
+            }
+            __syncthreads();
+            ok = gen_sum_entries(p, g, s, nc, Hbase, gpiv, EXACT ? xw + c0 : nullptr, detB, wk, s_acc);
+        }
+        if (!ok) {
+            if (tid == 0) ecount[i] = kEntryDeferred;
+            __syncthreads();
+            continue;
+        }
+        const double2 total = acc_value(s_acc);
+        if (tid == 0) {
+            const double sc = EXACT ? 1.0 : p.scale;
+            const double ax = total.x * sc, ay = total.y * sc;
+            const double pb = ax * ax + ay * ay;
+            prob[b] = pb;
+            if (amp) { amp[2 * b] = ax; amp[2 * b + 1] = ay; }
+            if (logp) logp[b] = log(pb);
+            if constexpr (EXACT) ecount[i] = 0;
+        }
+        __syncthreads();
+    }
+    flush_work(wk, nterm);
+}
+
+}  // namespace
+}  // namespace xf

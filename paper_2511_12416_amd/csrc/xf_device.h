@@ -805,9 +805,10 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
 
 // Work done by one thread, kept in registers and added to the plan's device
 // counters once at the end of a kernel: [0] distinct determinants, [1] sum of
-// their correction ranks, [2] FP64-equivalent FLOPs of the evaluation.
+// their correction ranks, [2] FP64-equivalent FLOPs of the evaluation, [3]
+// bases whose lemma products ran on the FP32 matrix cores.
 struct Work {
-    unsigned long long terms = 0, rank = 0, flops = 0;
+    unsigned long long terms = 0, rank = 0, flops = 0, fp32 = 0;
 };
 
 // Real FLOPs of the partial-pivot LU determinant of a complex m x m matrix.
@@ -824,11 +825,13 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 // Every thread of the workgroup calls this.
 __device__ __forceinline__ void flush_work(const Work &w, unsigned long long *nterm) {
     if (!nterm) return;
-    const unsigned long long a = wave_sum(w.terms), b = wave_sum(w.rank), c = wave_sum(w.flops);
+    const unsigned long long a = wave_sum(w.terms), b = wave_sum(w.rank), c = wave_sum(w.flops),
+                             d = wave_sum(w.fp32);
     if ((threadIdx.x & 63) == 0) {
         if (a) atomicAdd(nterm, a);
         if (b) atomicAdd(nterm + 1, b);
         if (c) atomicAdd(nterm + 2, c);
+        if (d) atomicAdd(nterm + 3, d);
     }
 }
 

@@ -154,6 +154,10 @@ struct xf_plan {
     DevBuf dP, dPhi0, dA1, dA2, dQ, dR1, fPhi0, fA1, fA2, fQ, fR1;
     DevBuf dkeymode, dT, dgkey, dgmode, dglayer, dgneg, dnterm;
     DevBuf dxkeys, dxw, dxdw;         // exact-mode term list (+ angle derivatives of the weights)
+    // general determinant-lemma evaluation: blocks of modes and their active lists
+    xf::GenPlan gen{};
+    DevBuf dgcol, dgact, dgpos0, dgpos1, dgblk, dflags;
+    int last_gen = 0;                 // the last xf_probabilities call used the general lemma kernel
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
     int last_lemma = 0;               // the last xf_probabilities call used the determinant lemma
@@ -233,6 +237,82 @@ double extent_of(const std::vector<double> &theta) {
     return xi;
 }
 
+// Blocks of modes for the general lemma evaluation: the connected components
+// of the union of the rotation layers' nonzero patterns (every layer is then
+// block-diagonal over them); two components give two blocks, any other count
+// one block of all modes.  Per block: its input columns, the modes each CPhase
+// layer touches in it, and their positions.
+xf_status refresh_gen(xf_plan *P) {
+    const int n = P->n, m = P->m;
+    std::vector<int> parent(n);
+    for (int i = 0; i < n; ++i) parent[i] = i;
+    auto find = [&](int x) {
+        while (parent[x] != x) x = parent[x] = parent[parent[x]];
+        return x;
+    };
+    for (int l = 0; l < P->n_rot; ++l)
+        for (int r = 0; r < n; ++r)
+            for (int c = 0; c < n; ++c) {
+                const double *z = &P->rot[2 * ((size_t)l * n * n + (size_t)r * n + c)];
+                if (z[0] != 0.0 || z[1] != 0.0) parent[find(r)] = find(c);
+            }
+    std::vector<int> roots;
+    for (int i = 0; i < n; ++i)
+        if (find(i) == i) roots.push_back(i);
+    xf::GenPlan &g = P->gen;
+    g = xf::GenPlan{};
+    g.nblk = roots.size() == 2 ? 2 : 1;
+    std::vector<int8_t> blk(128, 0), pos0(128, -1), pos1(128, -1);
+    for (int q = 0; q < n; ++q) blk[q] = (int8_t)(g.nblk == 2 && find(q) == roots[1] ? 1 : 0);
+    std::vector<uint8_t> col(2 * 32, 0), act(2 * 64, 0);
+    bool fits = true;
+    int hoff = 0;
+    for (int b = 0; b < g.nblk; ++b) {
+        g.bmask[b][0] = g.bmask[b][1] = 0;
+        for (int q = 0; q < n; ++q)
+            if (blk[q] == b) g.bmask[b][q >> 6] |= 1ull << (q & 63);
+        int mb = 0;
+        for (int a = 0; a < m; ++a)
+            if (blk[P->C[a]] == b) {
+                if (mb < 32) col[b * 32 + mb] = (uint8_t)a;
+                ++mb;
+            }
+        g.mb[b] = mb;
+        std::vector<int> a0, a1;
+        for (int j = 0; j < P->k; ++j)
+            for (int side = 0; side < 2; ++side) {
+                const int q = P->pairs[2 * j + side];
+                if (blk[q] != b) continue;
+                (P->layer[j] == 0 ? a0 : a1).push_back(q);
+            }
+        for (auto *v : {&a0, &a1}) {
+            std::sort(v->begin(), v->end());
+            v->erase(std::unique(v->begin(), v->end()), v->end());
+        }
+        g.kb0[b] = (int)a0.size();
+        g.kb[b] = (int)(a0.size() + a1.size());
+        if (mb > 32 || g.kb[b] > 64) fits = false;
+        for (size_t i = 0; i < a0.size() && i < 64; ++i) act[b * 64 + i] = (uint8_t)a0[i], pos0[a0[i]] = (int8_t)i;
+        for (size_t i = 0; i < a1.size() && a0.size() + i < 64; ++i)
+            act[b * 64 + a0.size() + i] = (uint8_t)a1[i], pos1[a1[i]] = (int8_t)(a0.size() + i);
+        g.hoff[b] = hoff;
+        hoff += g.kb[b] * g.kb[b];
+    }
+    g.hsize = hoff;
+    if (!fits) g.nblk = 0;   // the general evaluation does not apply
+    xf_status st;
+    if ((st = dev_upload(P->dgcol, col.data(), col.size())) || (st = dev_upload(P->dgact, act.data(), act.size())) ||
+        (st = dev_upload(P->dgpos0, pos0.data(), 128)) || (st = dev_upload(P->dgpos1, pos1.data(), 128)) ||
+        (st = dev_upload(P->dgblk, blk.data(), 128)))
+        return st;
+    g.col = (const uint8_t *)P->dgcol.p;
+    g.act = (const uint8_t *)P->dgact.p;
+    g.pos0 = (const int8_t *)P->dgpos0.p;
+    g.pos1 = (const int8_t *)P->dgpos1.p;
+    g.blk = (const int8_t *)P->dgblk.p;
+    return XF_OK;
+}
+
 // Host FP64 precompute of the low-rank factors, uploaded to the device.
 xf_status refresh_matrices(xf_plan *P) {
     const int n = P->n, m = P->m, G = P->G, L = P->L;
@@ -310,7 +390,7 @@ xf_status refresh_matrices(xf_plan *P) {
             return st;
     }
     P->nxterms = -1;
-    return XF_OK;
+    return refresh_gen(P);
 }
 
 xf_status refresh_table(xf_plan *P) {
@@ -421,7 +501,8 @@ void plan_free(xf_plan *P) {
     for (DevBuf *b : {&P->dP, &P->dPhi0, &P->dA1, &P->dA2, &P->dQ, &P->dR1, &P->fPhi0, &P->fA1,
                       &P->fA2, &P->fQ, &P->fR1, &P->dkeymode, &P->dT, &P->dgkey, &P->dgmode,
                       &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
-                      &P->dgsum, &P->dekey, &P->decnt, &P->decount})
+                      &P->dgsum, &P->dekey, &P->decnt, &P->decount, &P->dgcol, &P->dgact, &P->dgpos0,
+                      &P->dgpos1, &P->dgblk, &P->dflags})
         dev_free(*b);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();
@@ -663,7 +744,11 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
     xf::DevPlan d = snapshot(P);
     const bool mixed = P->precision == XF_MIXED;
     const int alg = P->evaluation == XF_EVAL_LU ? 1 : 0;
-    const bool lemma = mode == XF_RAW_ESTIMATE && xf::raw_estimate_uses_lemma(d, alg);
+    // evaluation: the eta <= 16 one-layer lemma kernels, else the general
+    // lemma kernel where its sizes fit, else the LU per pattern
+    const bool fast = mode == XF_RAW_ESTIMATE && xf::raw_estimate_uses_lemma(d, alg);
+    const bool gen = !fast && alg == 0 && xf::gen_applies(d, P->gen);
+    const bool lemma = mode == XF_RAW_ESTIMATE && (fast || gen);   // sampler + evaluation kernels
     // lemma workspace: chunks of bitstrings whose entry regions fit
     uint64_t cap = 0;
     int64_t chunk = B, nchunks = 1;
@@ -684,6 +769,8 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
         }
         nchunks = (B + chunk - 1) / chunk;
     }
+    if (noalloc && mode == XF_EXACT && gen && (uint64_t)B * 4 > xf::kNoAllocScratchBytes)
+        return fail(XF_EUNSUPPORTED, "B = %lld exceeds the no-allocation scratch in exact mode", (long long)B);
     xf_status st;
     if (!noalloc) {
         if (mode == XF_EXACT && P->nxterms < 0 && B > 0) {
@@ -697,44 +784,66 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
             ecnt = (int2 *)P->decnt.p;
             ecount = (uint32_t *)P->decount.p;
         }
-    } else if (lemma && B > 0) {
+        if (mode == XF_EXACT && gen && B > 0 && P->dflags.bytes < (size_t)B * 4) {
+            if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
+            if ((st = dev_upload(P->dflags, nullptr, (size_t)B * 4))) return st;
+        }
+        if (mode == XF_EXACT) ecount = (uint32_t *)P->dflags.p;
+    } else if ((lemma || (mode == XF_EXACT && gen)) && B > 0) {
         void *base = nullptr;
         if (xf::noalloc_scratch(P->device, &base) != hipSuccess)
             return fail(XF_EDEVICE, "could not resolve the device scratch");
-        ekey = (uint64_t *)base;
-        ecnt = (int2 *)((unsigned char *)base + (size_t)chunk * cap * 8);
-        ecount = (uint32_t *)((unsigned char *)base + (size_t)chunk * cap * 16);
+        if (lemma) {
+            ekey = (uint64_t *)base;
+            ecnt = (int2 *)((unsigned char *)base + (size_t)chunk * cap * 8);
+            ecount = (uint32_t *)((unsigned char *)base + (size_t)chunk * cap * 16);
+        } else {
+            ecount = (uint32_t *)base;
+        }
     }
     if (xf::launch_zero_u64((unsigned long long *)P->dnterm.p, s) != hipSuccess)
         return fail(XF_EDEVICE, "launch failed: %s", hipGetErrorString(hipGetLastError()));
     P->last_lemma = 0;
+    P->last_gen = 0;
     P->nev = 0;
     if (B == 0) return ok();
     const bool timed = !noalloc;
     hipError_t e = hipSuccess;
     if (timed && hipEventRecord(P->ev[0], s) != hipSuccess) return fail(XF_EDEVICE, "hipEventRecord failed");
+    unsigned long long *nterm = (unsigned long long *)P->dnterm.p;
     if (mode == XF_RAW_ESTIMATE) {
         d.scale = std::sqrt(extent_of(P->theta)) / (double)t;
         if (lemma) {
             for (int64_t c = 0; c < nchunks && e == hipSuccess; ++c) {
                 const int64_t b0 = c * chunk, nb = std::min(chunk, B - b0);
-                e = xf::launch_lemma_chunk(d, (const uint64_t *)d_bits, b0, nb, t, seed, ekey, ecnt, ecount, cap,
-                                           d_prob, d_amp, d_logp, (unsigned long long *)P->dnterm.p,
-                                           timed ? P->ev[1 + 2 * c] : nullptr, s);
+                hipEvent_t mid = timed ? P->ev[1 + 2 * c] : nullptr;
+                if (fast)
+                    e = xf::launch_lemma_chunk(d, (const uint64_t *)d_bits, b0, nb, t, seed, ekey, ecnt, ecount, cap,
+                                               d_prob, d_amp, d_logp, nterm, mid, s);
+                else
+                    e = xf::launch_gen_chunk(d, P->gen, mixed, (const uint64_t *)d_bits, b0, nb, t, seed, ekey, ecnt,
+                                             ecount, cap, d_prob, d_amp, d_logp, nterm, mid, s);
                 if (e == hipSuccess && timed) e = hipEventRecord(P->ev[2 + 2 * c], s);
             }
             P->nev = timed ? 1 + 2 * (int)nchunks : 0;
             P->last_lemma = 1;
+            P->last_gen = gen ? 1 : 0;
         } else {
-            e = xf::launch_raw_estimate(d, mixed, alg, (const uint64_t *)d_bits, B, t, seed, d_prob, d_amp, d_logp,
-                                        (unsigned long long *)P->dnterm.p, s);
+            e = xf::launch_raw_estimate(d, mixed, (const uint64_t *)d_bits, 0, B, t, seed, d_prob, d_amp, d_logp,
+                                        nterm, nullptr, 0, s);
             if (e == hipSuccess && timed) e = hipEventRecord(P->ev[1], s);
             P->nev = timed ? 2 : 0;
         }
     } else {
-        e = xf::launch_exact(d, mixed, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p, P->nxterms,
-                             (const uint64_t *)d_bits, B, d_prob, d_amp, d_logp,
-                             (unsigned long long *)P->dnterm.p, s);
+        if (gen) {
+            e = xf::launch_gen_exact(d, P->gen, mixed, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p,
+                                     P->nxterms, (const uint64_t *)d_bits, B, ecount, d_prob, d_amp, d_logp, nterm,
+                                     nullptr, s);
+            P->last_gen = 1;
+        } else {
+            e = xf::launch_exact(d, mixed, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p, P->nxterms,
+                                 (const uint64_t *)d_bits, B, d_prob, d_amp, d_logp, nterm, nullptr, 0, s);
+        }
         if (e == hipSuccess && timed) e = hipEventRecord(P->ev[1], s);
         P->nev = timed ? 2 : 0;
     }
@@ -771,15 +880,17 @@ xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
     if (!plan_valid(P) || !work) return fail(XF_EINVAL, "invalid plan or NULL output");
     DeviceGuard guard(P->device);
     if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
-    unsigned long long v[3] = {0, 0, 0};
+    unsigned long long v[4] = {0, 0, 0, 0};
     if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(v, P->dnterm.p, 24, hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(v, P->dnterm.p, 32, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(XF_EDEVICE, "could not read the work counters");
     work->determinants = (int64_t)v[0];
     work->rank_sum = (int64_t)v[1];
     work->flops = (double)v[2];
     work->lemma = P->last_lemma;
     work->backward_lemma = P->last_bwd_lemma;
+    work->general = P->last_gen;
+    work->fp32_bases = (int64_t)v[3];
     work->sample_ms = 0.0;
     work->eval_ms = 0.0;
     for (int i = 1; i < P->nev; ++i) {

@@ -55,6 +55,22 @@ struct DevPlan {
     double scale;             // Raw Estimate: sqrt(xi*) / t
 };
 
+// Plan data of the general determinant-lemma evaluation (lemma_gen.h): the
+// modes split into nblk blocks over which every rotation layer is
+// block-diagonal, and per block its share of the input (mb columns), its
+// modes touched by CPhase layer 0 (kb0 of them) and layer 1 (kb - kb0).
+struct GenPlan {
+    int nblk;                   // 1 or 2
+    int mb[2];                  // input modes (= base rows) of each block
+    int kb0[2], kb[2];          // active modes of layer 0 / of both layers per block
+    int hoff[2], hsize;         // offset of each block's H in the H region; its size (complex entries)
+    uint64_t bmask[2][2];       // modes of each block (128-bit masks)
+    const uint8_t *col;         // [2][32]: input-column indices (into C) of each block
+    const uint8_t *act;         // [2][64]: active modes of each block, layer 0 then layer 1
+    const int8_t *pos0, *pos1;  // [128]: position of a mode in its block's active list (layer 0 / 1), or -1
+    const int8_t *blk;          // [128]: block of each mode
+};
+
 // One partial gradient (of a workgroup of the lemma backward, or of a lane
 // group of the LU backward; complex entries, offsets in double2):
 //   oP   Gbar_P    n x G (row stride G)
@@ -68,12 +84,15 @@ struct GradLayout {
 
 // Launchers (k_*.hip).  Return hipSuccess or the launch error.
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
-// The fused Raw Estimate kernel (LU per distinct pattern) over the whole
-// batch; the determinant-lemma path is launch_lemma_chunk.  algorithm is the
-// plan's evaluation choice (0 automatic, 1 LU), used by raw_estimate_uses_lemma.
-hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, int algorithm, const uint64_t *bits, int64_t B,
-                               int64_t t, uint64_t seed, double *prob, double *amp, double *logp,
-                               unsigned long long *nterm, hipStream_t s);
+// The fused Raw Estimate kernel (LU per distinct pattern) over the bitstrings
+// [b0, b0 + nb) (with only != NULL: those with only[i] == kEntryDeferred) on
+// `grid` workgroups (grid <= 0: one per bitstring, at most 2^20); the
+// determinant-lemma paths are launch_lemma_chunk and launch_gen_chunk.
+// raw_estimate_uses_lemma: the eta <= 16 one-layer lemma kernels apply
+// (algorithm 0 automatic, 1 LU).
+hipError_t launch_raw_estimate(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                               uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
+                               const uint32_t *only, int grid, hipStream_t s);
 bool raw_estimate_uses_lemma(const DevPlan &p, int algorithm);
 // Determinant-lemma Raw Estimate for bitstrings [b0, b0 + nb): the sampler
 // kernel writes each bitstring's distinct (pattern, count) entries to its
@@ -94,9 +113,11 @@ hipError_t launch_lemma_bwd_chunk(const DevPlan &p, const uint64_t *bits, int64_
                                   uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,
                                   const double *g, double2 *part, int nparts, const GradLayout &lay,
                                   hipStream_t s);
-hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w,
-                        int64_t nkeys, const uint64_t *bits, int64_t B, double *prob, double *amp,
-                        double *logp, unsigned long long *nterm, hipStream_t s);
+// Exact mode with the LU per term over bitstrings [0, B) (only: those with
+// only[b] == kEntryDeferred); grid <= 0: one workgroup per bitstring.
+hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
+                        const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
+                        unsigned long long *nterm, const uint32_t *only, int grid, hipStream_t s);
 // LU backward kernels: every lane group (kThreads / G per workgroup) adds into
 // its own partial, so nwg workgroups use nwg * kThreads / G partials.  With
 // only != NULL just the bitstrings i of [b0, b0 + nb) with only[i] ==
@@ -117,30 +138,44 @@ hipError_t prepare_fused_small(int G);
 hipError_t prepare_fused_g32(int G);
 hipError_t prepare_fused_g64(int G);
 hipError_t prepare_fused_g64x(int G);
-// Fused LU kernels per lane-group size (k_fused_small.hip: G = 4, 8, 16;
-// k_fused_g32.hip, k_fused_g64.hip); hipErrorInvalidValue for other G.
-hipError_t fused_raw_small(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
-                           double *prob, double *amp, double *logp, unsigned long long *nterm, hipStream_t s);
-hipError_t fused_raw_g32(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
-                         double *prob, double *amp, double *logp, unsigned long long *nterm, hipStream_t s);
-hipError_t fused_raw_g64(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t B, int64_t t, uint64_t seed,
-                         double *prob, double *amp, double *logp, unsigned long long *nterm, hipStream_t s);
-hipError_t fused_exact_small(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
-                             const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
-                             unsigned long long *nterm, hipStream_t s);
-hipError_t fused_exact_g32(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
-                           const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
-                           unsigned long long *nterm, hipStream_t s);
-hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
-                           const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
-                           unsigned long long *nterm, hipStream_t s);
 hipError_t prepare_lemma(int G);
 hipError_t prepare_bwd(int G);
-// The fused LU kernel restricted to the bitstrings whose ecount entry is
-// kEntryDeferred (the lemma evaluation could not take them).
-hipError_t launch_raw_deferred(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
-                               uint64_t seed, double *prob, double *amp, double *logp,
-                               unsigned long long *nterm, const uint32_t *ecount, int grid, hipStream_t s);
+// Fused LU kernels per lane-group size (k_fused_small.hip: G = 4, 8, 16;
+// k_fused_g32.hip, k_fused_g64.hip); hipErrorInvalidValue for other G.
+hipError_t fused_raw_small(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                           uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
+                           const uint32_t *only, int grid, hipStream_t s);
+hipError_t fused_raw_g32(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                         uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
+                         const uint32_t *only, int grid, hipStream_t s);
+hipError_t fused_raw_g64(const DevPlan &p, bool mixed, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
+                         uint64_t seed, double *prob, double *amp, double *logp, unsigned long long *nterm,
+                         const uint32_t *only, int grid, hipStream_t s);
+hipError_t fused_exact_small(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
+                             const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
+                             unsigned long long *nterm, const uint32_t *only, int grid, hipStream_t s);
+hipError_t fused_exact_g32(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
+                           const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
+                           unsigned long long *nterm, const uint32_t *only, int grid, hipStream_t s);
+hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,
+                           const uint64_t *bits, int64_t B, double *prob, double *amp, double *logp,
+                           unsigned long long *nterm, const uint32_t *only, int grid, hipStream_t s);
+// General determinant-lemma evaluation (k_lemma_gen.hip).  gen_applies: the
+// plan's sizes fit its LDS layout.  launch_gen_chunk: Raw Estimate for
+// bitstrings [b0, b0 + nb) (sampler kernel into the workspace, evaluation,
+// then the LU kernel for the bitstrings it deferred).  launch_gen_exact: exact
+// mode over [0, B) with flags[B] marking deferred bitstrings, then the LU kernel
+// for those.
+bool gen_applies(const DevPlan &p, const GenPlan &g);
+hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, const uint64_t *bits, int64_t b0,
+                            int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount,
+                            uint64_t cap, double *prob, double *amp, double *logp, unsigned long long *nterm,
+                            hipEvent_t ev_mid, hipStream_t s);
+hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, const uint64_t *keys, const double2 *w,
+                            int64_t nkeys, const uint64_t *bits, int64_t B, uint32_t *flags, double *prob,
+                            double *amp, double *logp, unsigned long long *nterm, hipEvent_t ev_mid,
+                            hipStream_t s);
+hipError_t prepare_gen();
 // Device address of the no-allocation scratch on `device` (current), looked up
 // once per device (k_noalloc.hip).
 hipError_t noalloc_scratch(int device, void **ptr);

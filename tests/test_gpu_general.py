@@ -1,0 +1,135 @@
+"""GPU parity of the general determinant-lemma evaluation (exact mode, one or
+two CPhase layers, bases of up to 32 rows, block-diagonal rotations split into
+blocks) against the FP64 oracle, which always builds each trajectory's full
+mode matrix and factorises its submatrix directly, and against the LU
+evaluation of the same library."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import gpu_probs, make_plan, oracle_probs, rel_err, sample_indices, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+TOL_MIXED = 1e-5
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_12416_amd as X
+    X.lib()
+    return X
+
+
+def _check(p, ref, tol, label):
+    assert np.count_nonzero(ref) > 0, f"{label}: every reference probability is zero"
+    e = rel_err(p, ref)
+    say(f"  {label}: n={len(p)} max rel err {e.max():.3e} median {np.median(e):.3e}")
+    assert np.all(np.isfinite(p))
+    assert e.max() <= tol, (label, int(np.argmax(e)), p[np.argmax(e)], ref[np.argmax(e)])
+
+
+CASES = [
+    # seed, n, eta, k, n_rot, spin, theta_scale, mode
+    (901, 8, 3, 5, 2, False, 1.0, "exact"),
+    (902, 12, 6, 8, 2, True, 0.8, "exact"),      # two blocks
+    (903, 10, 4, 6, 3, False, 1.0, "exact"),     # two CPhase layers
+    (904, 16, 8, 10, 3, True, 0.7, "exact"),     # two layers, two blocks
+    (905, 40, 24, 12, 2, False, 0.5, "exact"),   # eta = 24 in one block
+    (906, 14, 6, 9, 3, True, 0.9, "approx"),     # two layers, two blocks
+    (907, 44, 20, 16, 3, True, 0.6, "approx"),   # two layers, blocks of 10 rows
+    (908, 48, 28, 10, 2, False, 0.6, "approx"),  # one layer, eta = 28
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[7]}_n{c[1]}_eta{c[2]}_k{c[3]}_L{c[4] - 1}" for c in CASES])
+def test_general_lemma_matches_oracle_and_lu(X, case):
+    seed, n, eta, k, n_rot, spin, scale, mode = case
+    inp = None
+    if spin:
+        inp = list(range(eta // 2)) + list(range(n // 2, n // 2 + eta - eta // 2))
+    w = W.random_circuit(seed, n, eta, k, n_rot=n_rot, theta_scale=scale, spin=spin, input_modes=inp,
+                         max_bits=256)
+    count = 256 if n < 40 else 32
+    if spin:
+        # outputs in the input's spin sector (others have p = 0)
+        bits = W.spin_bitstrings(np.random.default_rng(seed), n // 2, eta // 2, eta - eta // 2, count)
+    else:
+        bits = w.bits[:count]
+    t, smp = (1000, 41) if mode == "approx" else (0, 0)
+    say(f"general lemma {case}: {len(bits)} bitstrings")
+    ref = oracle_probs(w, bits, mode=mode, t=t, seed=smp)
+    for prec, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
+        plan = make_plan(w, X, prec)
+        p = gpu_probs(plan, X, bits, mode, t, smp)
+        wk = plan.last_work()
+        assert wk["general"], "the general lemma kernel was expected"
+        _check(p, ref, tol, f"{prec} general")
+        plan.set_evaluation("lu")
+        q = gpu_probs(plan, X, bits, mode, t, smp)
+        assert not plan.last_work()["general"]
+        _check(q, ref, tol, f"{prec} LU")
+
+
+def test_config3_exact_general_vs_oracle(X):
+    w = W.workload(3)
+    say("config 3 (general lemma, exact): n=52 eta=26 k=12, all 4096 terms, B=4096")
+    idx = sample_indices(w.B, 24, seed=33)
+    ref = oracle.run_workload(w, index=idx)
+    plan = make_plan(w, X)
+    p = gpu_probs(plan, X, w.bits, "exact")
+    wk = plan.last_work()
+    assert wk["general"]
+    _check(p[idx], ref, TOL_FP64, "cfg3 fp64")
+    p2 = gpu_probs(plan, X, w.bits, "exact")
+    assert np.array_equal(p, p2)
+
+
+def test_config5_general_vs_oracle(X):
+    w = W.workload(5)
+    say("config 5 (general lemma, two layers, two blocks): n=100 eta=25a+25b k=40 t=65536 B=1e5")
+    idx = sample_indices(w.B, 16, seed=55)
+    ref = oracle.run_workload(w, index=idx)
+    for prec, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
+        plan = make_plan(w, X, prec)
+        p = gpu_probs(plan, X, w.bits, "approx", w.t, w.seed)
+        wk = plan.last_work()
+        assert wk["general"] and wk["lemma"]
+        say(f"  {prec}: {wk['fp32_bases']} of {2 * w.B} bases in FP32, {wk['determinants']} patterns")
+        _check(p[idx], ref, tol, f"cfg5 {prec}")
+
+
+def test_exact_general_defers_ill_conditioned_bases(X):
+    """Row 0 of the second rotation (nearly) orthogonal to the columns of
+    D_0 R_0[:, C]: bases with mode 0 occupied are ill-conditioned, their
+    bitstrings go to the LU kernel within the same exact-mode call."""
+    say("exact mode, ill-conditioned bases")
+    rng = W.rng_for(707)
+    n, eta, k = 9, 4, 5
+    R0 = W.haar_unitary(rng, n)
+    pairs = W.random_pairs(rng, n, k)
+    theta = rng.uniform(-1.0, 1.0, k)
+    C = list(range(1, eta + 1))
+    d0 = np.ones(n, dtype=np.complex128)
+    for (a, b), th in zip(pairs, theta):
+        d0[a] *= np.exp(0.5j * th)
+        d0[b] *= np.exp(0.5j * th)
+    Q = d0[:, None] * R0[:, C]
+    _, _, vh = np.linalg.svd(Q.T)
+    v = vh[eta:].conj().T[:, 0]
+    Z = np.concatenate([v.conj()[:, None], rng.standard_normal((n, n - 1)) + 1j * rng.standard_normal((n, n - 1))],
+                       axis=1)
+    R1 = np.linalg.qr(Z)[0].conj().T
+    rot = np.stack([R0, R1])
+    inp = W.bits_from_modes(C)
+    bits = W.all_fixed_weight(n, eta)
+    ref = oracle.probabilities(rot, pairs, np.zeros(k), theta, inp, bits, "exact")
+    plan = X.Plan(rot, pairs, np.zeros(k), theta, inp)
+    p = gpu_probs(plan, X, bits, "exact")
+    assert plan.last_work()["general"]
+    _check(p, ref, TOL_FP64, "deferred exact")

@@ -241,11 +241,18 @@ def test_many_flips_fall_back_per_pattern(X):
     _check(p, ref, TOL_FP64, "mixed lemma / LU patterns")
 
 
-def test_two_layers_do_not_use_lemma(X):
+def test_two_layers_use_the_general_lemma(X):
+    """Two CPhase layers are outside the eta <= 16 one-layer kernels and go to
+    the general lemma kernel (or, with the LU evaluation, to the LU)."""
     w = W.random_circuit(507, 9, 4, 6, n_rot=3, theta_scale=1.0)
     plan = make_plan(w, X)
-    _, wk = _probs(plan, X, w.bits, 200, 2, "auto")
-    assert not wk["lemma"]
+    p, wk = _probs(plan, X, w.bits, 200, 2, "auto")
+    assert wk["lemma"] and wk["general"]
+    q, wk = _probs(plan, X, w.bits, 200, 2, "lu")
+    assert not wk["lemma"] and not wk["general"]
+    ref = oracle_probs(w, w.bits, mode="approx", t=200, seed=2)
+    _check(p, ref, TOL_FP64, "general")
+    _check(q, ref, TOL_FP64, "LU")
 
 
 def test_workspace_chunking_is_invisible(X):
