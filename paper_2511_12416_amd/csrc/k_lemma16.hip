@@ -46,11 +46,11 @@ k_eval_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t
             }
             continue;
         }
+        // patterns that overflowed the workspace region: the LU kernel takes it
+        if (ne == kEntryDeferred) continue;
         load_bitstring(p, bits, b, s.Rb, &s_ok);
         double2 total;
-        if (ne == kEntryOverflow) {
-            total = make_double2(__longlong_as_double(0x7FF8000000000000ll), 0.0);
-        } else {
+        {
             const LemmaBits lb = lemma_setup<G>(p, s, sH, s_flag, &s_det, wk);
             bool ok = lb.ok;
             acc_clear(s_acc);
@@ -103,7 +103,14 @@ bool raw_estimate_uses_lemma(const DevPlan &p, int algorithm) {
     return algorithm != 1 && lemma_applies(p);
 }
 
-uint64_t lemma_entry_cap(int64_t t) { return (uint64_t)t + (uint64_t)t / 511 + 2; }
+// Entries of a bitstring's workspace region: enough for every pattern of t
+// samples (with the tables' reserved empty-pattern slots), at most
+// kEntryCapMax; a bitstring with more distinct patterns is left to the LU
+// kernels.
+uint64_t lemma_entry_cap(int64_t t) {
+    const uint64_t full = (uint64_t)t + (uint64_t)t / 511 + 2;
+    return full < kEntryCapMax ? full : kEntryCapMax;
+}
 
 hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
                               uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,

@@ -6,7 +6,7 @@
 namespace xf {
 namespace {
 
-size_t gen_lds_bytes(const GenPlan &g) { return kGenBaseBytes + (size_t)g.hsize * 16 + (size_t)kThreads * 16; }
+size_t gen_lds_bytes(const GenPlan &g) { return kGenBaseBytes + gen_tables_bytes(g); }
 
 // Dynamic LDS limit of k_gen_eval: the static per-bitstring state takes the
 // rest of the 160 KiB.
@@ -51,8 +51,12 @@ hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, cons
         launch_gen_t<false, false>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, nullptr, nullptr, 0, prob, amp, logp,
                                    nterm, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_raw_estimate(p, false, bits, b0, nb, t, seed, prob, amp, logp, nterm, ecount,
-                               grid < 2048 ? grid : 2048, s);
+    // then the bitstrings the evaluation deferred, on a smaller grid (its
+    // workgroups skip the other bitstrings at once)
+    hipLaunchKernelGGL((k_gen_lu<false>), dim3(grid < 2048 ? grid : 2048), dim3(kThreads),
+                       raw_lds_bytes(p.k, p.n, 4, false, false), s, p, g, bits, b0, nb, (uint32_t)t, seed, ecount,
+                       nullptr, nullptr, (int64_t)0, prob, amp, logp, nterm);
+    return hipGetLastError();
 }
 
 hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, const uint64_t *keys, const double2 *w,
@@ -69,13 +73,16 @@ hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, cons
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
     const int grid = (int)(B < 2048 ? B : 2048);
-    return launch_exact(p, false, keys, w, nkeys, bits, B, prob, amp, logp, nterm, flags, grid, s);
+    hipLaunchKernelGGL((k_gen_lu<true>), dim3(grid), dim3(kThreads), raw_lds_bytes(0, p.n, 4, false, false), s, p, g,
+                       bits, (int64_t)0, B, 0u, (uint64_t)0, flags, keys, w, nkeys, prob, amp, logp, nterm);
+    return hipGetLastError();
 }
 
 hipError_t prepare_gen() {
     hipError_t e;
     for (const void *f : {(const void *)k_gen_eval<false, false>, (const void *)k_gen_eval<false, true>,
-                          (const void *)k_gen_eval<true, false>, (const void *)k_gen_eval<true, true>})
+                          (const void *)k_gen_eval<true, false>, (const void *)k_gen_eval<true, true>,
+                          (const void *)k_gen_lu<false>, (const void *)k_gen_lu<true>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGenMaxLds)) != hipSuccess)
             return e;
     return hipFuncSetAttribute((const void *)k_sample_entries<kSamplerThreads>,

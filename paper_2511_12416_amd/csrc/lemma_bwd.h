@@ -337,16 +337,12 @@ k_bwd_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t 
     for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
         const int64_t b = b0 + i;
         const uint32_t ne = ecount[i];
-        if (ne == kEntryInvalid) continue;
+        // wrong weight, or patterns that overflowed the workspace region (the
+        // LU backward resamples those)
+        if (ne == kEntryInvalid || ne == kEntryDeferred) continue;
         const double gb = g[b];
         if (gb == 0.0) continue;
         load_bitstring(p, bits, b, s.Rb, &s_ok);
-        if (ne == kEntryOverflow) {
-            // impossible by the workspace bound; the LU backward resamples it
-            if (tid == 0) ecount[i] = kEntryDeferred;
-            __syncthreads();
-            continue;
-        }
         const LemmaBits lb = lemma_setup<G>(p, s, sH, s_flag, &s_det, wk);
         if (!lb.ok) {
             if (tid == 0) ecount[i] = kEntryDeferred;

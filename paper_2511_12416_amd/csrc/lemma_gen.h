@@ -40,6 +40,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kGenMaxM = 32;      // rows of a block's base
 constexpr int kGenMaxKb = 64;     // active modes of a block (both layers)
 constexpr int kGenMaxRank = 32;   // flipped modes of a block in one pattern
+constexpr int kGenMaxSteps = kGenMaxM / 4;   // 4-wide K slices of a product over a base
 // Mixed precision forms X and H on the FP32 matrix cores only for bases with
 // kappa_1(M_0) at most this (the FP32 error of H grows with ||M_0^-1||);
 // other bases use FP64.
@@ -49,35 +50,95 @@ constexpr double kMixedMaxCond = 50.0;
 constexpr size_t kGenSetupBytes = (size_t)kHashSlots * 16 + 2 * (size_t)kThreads * 16;
 // Bytes of the RawSmem layout without sampling tables or staged factors.
 constexpr size_t kGenBaseBytes = ((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + 15) & ~(size_t)15;
+constexpr uint16_t kNoPos = 0xFFFF;
 
-// C (M x N) = A (M x K) B (K x N), complex, on the matrix cores.  a_at(i, k)
-// and b_at(k, j) return operands, c_put(i, j, v) stores a result.  Each wave
-// of the workgroup computes whole 16 x 16 tiles of C: per 4-wide slice of K,
-// lane l supplies A[16 tm + l % 16][k0 + l / 16] and B[k0 + l / 16][16 tn + l % 16]
-// and the four real products re.re, -im.im, re.im, im.re accumulate into the
-// real and imaginary tiles.  Lane l then holds, in element r, C[16 tm + i][16 tn + l % 16]
-// with i = l / 16 + 4 r for the FP64 instruction and i = 4 (l / 16) + r for
-// the FP32 one (the two order their output rows differently).  Out-of-range
-// operands are zero.
+// Plan tables the general kernels keep in LDS (after the RawSmem layout):
+// every block's H (kb x hld, hld odd so that a lane group's rows fall in
+// different banks), the lane groups' LU pivot rows, R'_1[act1, act0] of every
+// block (two CPhase layers), the key-bit table, and the blocks' active modes
+// and input columns.
+struct GenLds {
+    double2 *H, *gpiv, *R1a;
+    uint16_t *kbt;
+    uint8_t *act, *col;
+};
+
+__host__ __device__ __forceinline__ size_t gen_tables_bytes(const GenPlan &g) {
+    return align16((size_t)g.hsize * 16) + (size_t)kThreads * 16 + align16((size_t)g.r1size * 16) + 256 + 128 + 64;
+}
+
+__device__ __forceinline__ GenLds carve_gen(unsigned char *smem, const GenPlan &g) {
+    GenLds t;
+    unsigned char *q = smem + kGenBaseBytes;
+    t.H = (double2 *)q;
+    q += align16((size_t)g.hsize * 16);
+    t.gpiv = (double2 *)q;
+    q += (size_t)kThreads * 16;
+    t.R1a = (double2 *)q;
+    q += align16((size_t)g.r1size * 16);
+    t.kbt = (uint16_t *)q;
+    t.act = q + 256;
+    t.col = q + 256 + 128;
+    return t;
+}
+
+// Copies the plan tables into LDS (once per workgroup).
+__device__ __forceinline__ void load_gen_tables(const DevPlan &p, const GenPlan &g, const GenLds &t) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 128; e += kThreads) t.kbt[e] = g.kbt[e];
+    for (int e = tid; e < 2 * kGenMaxKb; e += kThreads) t.act[e] = g.act[e];
+    for (int e = tid; e < 2 * kGenMaxM; e += kThreads) t.col[e] = g.col[e];
+    if (p.L == 2) {
+        for (int blk = 0; blk < g.nblk; ++blk) {
+            const int kb0 = g.kb0[blk], kb1 = g.kb[blk] - kb0;
+            const uint8_t *act = g.act + blk * kGenMaxKb;
+            for (int e = tid; e < kb1 * kb0; e += kThreads) {
+                const int p1 = e / kb0, p0 = e % kb0;
+                t.R1a[g.r1off[blk] + e] = p.R1[(size_t)act[kb0 + p1] * p.n + act[p0]];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// C (M x N) = A (M x K) B (K x N), complex, on the matrix cores, K <= 32.
+// a_at(i, k) and b_at(k, j) return operands, c_put(i, j, v) stores a result.
+// Each wave of the workgroup computes whole 16 x 16 tiles of C: lane l
+// supplies A[16 tm + l % 16][k0 + l / 16] and B[k0 + l / 16][16 tn + l % 16]
+// for every 4-wide slice k0 of K (all loaded before the first product, so
+// their latencies overlap), and the four real products re.re, -im.im, re.im,
+// im.re accumulate into the real and imaginary tiles.  Lane l then holds, in
+// element r, C[16 tm + i][16 tn + l % 16] with i = l / 16 + 4 r for the FP64
+// instruction and i = 4 (l / 16) + r for the FP32 one (the two order their
+// output rows differently).  Out-of-range operands are zero.
 template <bool F32, class FA, class FB, class FC>
 __device__ __forceinline__ void cgemm_mfma(int M, int N, int K, FA a_at, FB b_at, FC c_put) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NW = kThreads / 64;
     const int tm_n = (M + 15) / 16, tn_n = (N + 15) / 16;
     const int li = lane & 15, lk = lane >> 4;
+    const int ns = (K + 3) / 4;
     for (int t = wave; t < tm_n * tn_n; t += NW) {
         const int tm = t / tn_n, tn = t % tn_n;
         const int row = tm * 16 + li, col = tn * 16 + li;
+        double2 av[kGenMaxSteps], bv[kGenMaxSteps];
+#pragma unroll
+        for (int st = 0; st < kGenMaxSteps; ++st) {
+            const int k = 4 * st + lk;
+            av[st] = (st < ns && row < M && k < K) ? a_at(row, k) : make_double2(0.0, 0.0);
+            bv[st] = (st < ns && k < K && col < N) ? b_at(k, col) : make_double2(0.0, 0.0);
+        }
         if constexpr (!F32) {
             d4v cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
-            for (int k0 = 0; k0 < K; k0 += 4) {
-                const int k = k0 + lk;
-                const double2 a = (row < M && k < K) ? a_at(row, k) : make_double2(0.0, 0.0);
-                const double2 b = (k < K && col < N) ? b_at(k, col) : make_double2(0.0, 0.0);
-                cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
-                cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
-                ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
-                ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+#pragma unroll
+            for (int st = 0; st < kGenMaxSteps; ++st) {
+                if (st < ns) {
+                    const double2 a = av[st], b = bv[st];
+                    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+                    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+                    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+                    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+                }
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -86,15 +147,16 @@ __device__ __forceinline__ void cgemm_mfma(int M, int N, int K, FA a_at, FB b_at
             }
         } else {
             f4v cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-            for (int k0 = 0; k0 < K; k0 += 4) {
-                const int k = k0 + lk;
-                const double2 a = (row < M && k < K) ? a_at(row, k) : make_double2(0.0, 0.0);
-                const double2 b = (k < K && col < N) ? b_at(k, col) : make_double2(0.0, 0.0);
-                const float ax = (float)a.x, ay = (float)a.y, bx = (float)b.x, by = (float)b.y;
-                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, bx, cr, 0, 0, 0);
-                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ay, by, cr, 0, 0, 0);
-                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, by, ci, 0, 0, 0);
-                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(ay, bx, ci, 0, 0, 0);
+#pragma unroll
+            for (int st = 0; st < kGenMaxSteps; ++st) {
+                if (st < ns) {
+                    const float ax = (float)av[st].x, ay = (float)av[st].y;
+                    const float bx = (float)bv[st].x, by = (float)bv[st].y;
+                    cr = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, bx, cr, 0, 0, 0);
+                    cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ay, by, cr, 0, 0, 0);
+                    ci = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, by, ci, 0, 0, 0);
+                    ci = __builtin_amdgcn_mfma_f32_16x16x4f32(ay, bx, ci, 0, 0, 0);
+                }
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -105,7 +167,7 @@ __device__ __forceinline__ void cgemm_mfma(int M, int N, int K, FA a_at, FB b_at
     }
 }
 
-// Per-bitstring shared state of the general evaluation.
+// Per-bitstring shared state of the general kernels.
 struct GenShared {
     int ok;                        // row counts / base status
     int piv[kGenMaxM];             // pivot row of each column (Gauss-Jordan)
@@ -120,24 +182,43 @@ struct GenShared {
 
 __device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
 
+// Rows of the loaded bitstring in each block (thread 0); sh.ok = 0 if a
+// block's count differs from the input's (the amplitude is then zero).
+__device__ __forceinline__ void gen_rows(const DevPlan &p, const GenPlan &g, const uint8_t *Rb, GenShared &sh) {
+    if (threadIdx.x == 0) {
+        sh.nrow[0] = sh.nrow[1] = 0;
+        sh.ok = 1;
+        for (int r = 0; r < p.m; ++r) {
+            const int q = Rb[r];
+            const int blk = g.blk[q];
+            if (sh.nrow[blk] < kGenMaxM) sh.rows[blk][sh.nrow[blk]] = (uint8_t)q;
+            ++sh.nrow[blk];
+        }
+        for (int blk = 0; blk < g.nblk; ++blk)
+            if (sh.nrow[blk] != g.mb[blk]) sh.ok = 0;
+        sh.det = make_double2(1.0, 0.0);
+    }
+}
+
 // Setup of block blk for the loaded bitstring: inverse of M_0 by
 // Gauss-Jordan (augmented rows [M_0 | I] in the setup scratch W, row stride
 // 2m; rows stay in place, row piv[c] ends as u_c e_c | u_c M_0^-1[c, :]),
 // conditioning test, then X = M_0^-1 U and H = V X.  Returns false if M_0 is
 // singular or kappa_1(M_0) > kLemmaMaxCond.  Whole workgroup.
 template <bool MIXED>
-__device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan &g, int blk, unsigned char *scratch,
-                                                double2 *H, GenShared &sh, Work &wk) {
+__device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan &g, const GenLds &T, int blk,
+                                                unsigned char *scratch, GenShared &sh, Work &wk) {
     const int tid = threadIdx.x, lane = tid & 63;
-    const int m = g.mb[blk], kb = g.kb[blk], kb0 = g.kb0[blk], n = p.n, G = p.G;
+    const int m = g.mb[blk], kb = g.kb[blk], kb0 = g.kb0[blk], hld = g.hld[blk], n = p.n, G = p.G;
     const uint8_t *rows = sh.rows[blk];
-    const uint8_t *col = g.col + blk * kGenMaxM;
-    const uint8_t *act = g.act + blk * kGenMaxKb;
+    const uint8_t *col = T.col + blk * kGenMaxM;
+    const uint8_t *act = T.act + blk * kGenMaxKb;
+    double2 *H = T.H + g.hoff[blk];
     double2 *W = (double2 *)scratch;
     const int ld = 2 * m;
     double2 *X = (double2 *)(scratch + align16((size_t)m * ld * 16));
     if (m == 0) {
-        for (int e = tid; e < kb * kb; e += kThreads) H[e] = make_double2(0.0, 0.0);
+        for (int e = tid; e < kb * hld; e += kThreads) H[e] = make_double2(0.0, 0.0);
         __syncthreads();
         return true;
     }
@@ -234,7 +315,7 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
     auto xput = [&](int i, int q, double2 v) { X[i * kb + q] = v; };
     auto vop = [&](int q, int k) { return (q < kb0 ? Phi0 : Q)[(size_t)act[q] * G + col[k]]; };
     auto xop = [&](int k, int q) { return X[k * kb + q]; };
-    auto hput = [&](int q, int q2, double2 v) { H[q * kb + q2] = v; };
+    auto hput = [&](int q, int q2, double2 v) { H[q * hld + q2] = v; };
     if (MIXED && sh.kappa <= kMixedMaxCond) {
         cgemm_mfma<true>(m, kb, m, minv, uop, xput);
         __syncthreads();
@@ -249,49 +330,45 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
     return true;
 }
 
-// Flipped modes of block blk in a pattern: the first NP of them (layer-0
-// modes ascending, then layer-1 modes ascending) with their positions in the
-// block's H; r0 layer-0 modes, r in all.
-template <int NP>
-__device__ __forceinline__ void gen_pattern(const GenPlan &g, const Flips &f, int blk, int &r0, int &r,
-                                            int (&pos)[NP], int (&md)[NP]) {
-    uint64_t a0 = f.n0[0] & g.bmask[blk][0], a1 = f.n0[1] & g.bmask[blk][1];
-    uint64_t b0 = f.n1[0] & g.bmask[blk][0], b1 = f.n1[1] & g.bmask[blk][1];
-    r0 = __popcll(a0) + __popcll(a1);
-    r = r0 + __popcll(b0) + __popcll(b1);
+// Flipped positions of a pattern in each block's H (bit p of pm[blk] <=>
+// position p flipped), from the key bits through the LDS key-bit table: a
+// compressed key bit names one (block, position); a trajectory bit (gate)
+// names two, which cancel where gates share a mode.
+__device__ __forceinline__ void gen_masks(const uint16_t *kbt, uint64_t key, uint64_t (&pm)[2]) {
+    pm[0] = pm[1] = 0;
+    while (key) {
+        const int j = __ffsll((long long)key) - 1;
+        key &= key - 1;
 #pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        int q = 0, ps = 0;
-        if (a0) {
-            q = __ffsll((long long)a0) - 1;
-            a0 &= a0 - 1;
-            ps = g.pos0[q];
-        } else if (a1) {
-            q = 64 + __ffsll((long long)a1) - 1;
-            a1 &= a1 - 1;
-            ps = g.pos0[q];
-        } else if (b0) {
-            q = __ffsll((long long)b0) - 1;
-            b0 &= b0 - 1;
-            ps = g.pos1[q];
-        } else if (b1) {
-            q = 64 + __ffsll((long long)b1) - 1;
-            b1 &= b1 - 1;
-            ps = g.pos1[q];
+        for (int e = 0; e < 2; ++e) {
+            const uint16_t v = kbt[2 * j + e];
+            if (v != kNoPos) pm[v >> 8] ^= 1ull << (v & 0xFF);
         }
-        pos[i] = ps;
-        md[i] = q;
     }
 }
 
-// Entry (i, j) of S_N for block blk (i, j < r); L2: two CPhase layers.
+// The first NP set bits of mask, ascending.
 template <int NP>
-__device__ __forceinline__ double2 gen_s_entry(const DevPlan &p, const double2 *H, int kb, int i, int j, int r0,
-                                               const int (&pos)[NP], const int (&md)[NP]) {
-    double2 h = H[pos[i] * kb + pos[j]];
-    if (p.L == 2 && i >= r0) {
+__device__ __forceinline__ void mask_positions(uint64_t mask, int (&pos)[NP]) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        pos[i] = mask ? __ffsll((long long)mask) - 1 : 0;
+        mask &= mask - 1;
+    }
+}
+
+// Entry (i, j) of S_N in a block (i, j < r; positions pos, r0 of them in
+// layer 0): delta_ij - 2 H[p_i, p_j], with the layer-1 correction for two
+// CPhase layers.
+template <int NP>
+__device__ __forceinline__ double2 gen_s_entry(bool two_layers, const double2 *H, int hld, const double2 *R1a,
+                                               int kb0, int i, int j, int r0, const int (&pos)[NP]) {
+    double2 h = H[pos[i] * hld + pos[j]];
+    if (two_layers && i >= r0) {
         double2 corr = make_double2(0.0, 0.0);
-        for (int l = 0; l < r0 && l < NP; ++l) corr = c_fma(corr, p.R1[(size_t)md[i] * p.n + md[l]], H[pos[l] * kb + pos[j]]);
+#pragma unroll
+        for (int l = 0; l < NP; ++l)
+            if (l < r0) corr = c_fma(corr, R1a[(pos[i] - kb0) * kb0 + pos[l]], H[pos[l] * hld + pos[j]]);
         h.x -= 2.0 * corr.x;
         h.y -= 2.0 * corr.y;
     }
@@ -347,21 +424,25 @@ __device__ __forceinline__ double2 small_det4(double2 (&a)[4][4], int r) {
 }
 
 // Product over blocks of det S_N for a pattern whose blocks flip at most 4
-// modes each (one lane).
-__device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan &g, const double2 *Hbase,
-                                                const Flips &f) {
+// positions each (one lane).
+__device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan &g, const GenLds &T,
+                                                const uint64_t (&pm)[2]) {
     double2 det = make_double2(1.0, 0.0);
     for (int blk = 0; blk < g.nblk; ++blk) {
-        int r0, r, pos[4], md[4];
-        gen_pattern<4>(g, f, blk, r0, r, pos, md);
+        const int r = __popcll(pm[blk]);
         if (r == 0) continue;
-        const double2 *H = Hbase + g.hoff[blk];
+        const int kb0 = g.kb0[blk];
+        const int r0 = __popcll(pm[blk] & (kb0 >= 64 ? ~0ull : ((1ull << kb0) - 1)));
+        int pos[4];
+        mask_positions<4>(pm[blk], pos);
+        const double2 *H = T.H + g.hoff[blk];
+        const double2 *R1a = T.R1a + g.r1off[blk];
         double2 a[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                a[i][j] = (i < r && j < r) ? gen_s_entry<4>(p, H, g.kb[blk], i, j, r0, pos, md)
+                a[i][j] = (i < r && j < r) ? gen_s_entry<4>(p.L == 2, H, g.hld[blk], R1a, kb0, i, j, r0, pos)
                                            : make_double2(i == j ? 1.0 : 0.0, 0.0);
         det = c_mul(det, small_det4(a, r));
     }
@@ -369,54 +450,53 @@ __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan 
 }
 
 // Same by a group of GS lanes (row `lane` of S per lane; blocks flip at most
-// GS modes each); every lane of the group returns the product.
+// GS positions each); every lane of the group returns the product.
 template <int GS>
-__device__ __forceinline__ double2 gen_det_group(const DevPlan &p, const GenPlan &g, const double2 *Hbase,
-                                                 const Flips &f, int lane, double2 *piv) {
+__device__ __forceinline__ double2 gen_det_group(const DevPlan &p, const GenPlan &g, const GenLds &T,
+                                                 const uint64_t (&pm)[2], int lane, double2 *piv) {
     double2 det = make_double2(1.0, 0.0);
     for (int blk = 0; blk < g.nblk; ++blk) {
-        int r0, r, pos[GS], md[GS];
-        gen_pattern<GS>(g, f, blk, r0, r, pos, md);
+        const int r = __popcll(pm[blk]);
         if (r == 0) continue;
-        const double2 *H = Hbase + g.hoff[blk];
+        const int kb0 = g.kb0[blk];
+        const int r0 = __popcll(pm[blk] & (kb0 >= 64 ? ~0ull : ((1ull << kb0) - 1)));
+        int pos[GS];
+        mask_positions<GS>(pm[blk], pos);
+        const double2 *H = T.H + g.hoff[blk];
+        const double2 *R1a = T.R1a + g.r1off[blk];
         double2 a[GS];
 #pragma unroll
         for (int j = 0; j < GS; ++j)
-            a[j] = (lane < r && j < r) ? gen_s_entry<GS>(p, H, g.kb[blk], lane, j, r0, pos, md)
+            a[j] = (lane < r && j < r) ? gen_s_entry<GS>(p.L == 2, H, g.hld[blk], R1a, kb0, lane, j, r0, pos)
                                        : make_double2(j == lane ? 1.0 : 0.0, 0.0);
         det = c_mul(det, lu_det<GS>(a, r, lane, piv));
     }
     return det;
 }
 
-// Largest number of flipped modes of any block in the pattern.
-__device__ __forceinline__ int gen_max_rank(const GenPlan &g, const Flips &f) {
-    int rm = 0;
-    for (int blk = 0; blk < g.nblk; ++blk) {
-        const int r = __popcll(f.n0[0] & g.bmask[blk][0]) + __popcll(f.n0[1] & g.bmask[blk][1]) +
-                      __popcll(f.n1[0] & g.bmask[blk][0]) + __popcll(f.n1[1] & g.bmask[blk][1]);
-        rm = max(rm, r);
-    }
-    return rm;
+__device__ __forceinline__ int gen_max_rank(const uint64_t (&pm)[2]) {
+    return max(__popcll(pm[0]), __popcll(pm[1]));
 }
+
+__device__ __forceinline__ int rank_bin(int r) { return r <= 4 ? 0 : (r <= 8 ? 1 : (r <= 16 ? 2 : (r <= 32 ? 3 : 4))); }
 
 // Evaluates the nl entries in the slots (keys in s.hkey; weights in s.hcnt
 // as Gaussian-integer counts, or, with w != nullptr, w[e] for entry e) and
 // adds weight * det M_0 * prod det S_N to the bitstring's exact sum.  Entries
 // are classified by their largest block rank (counting sort into s.piv) so
 // that lanes and lane groups of a pass take like patterns.  Returns false if a
-// block flips more than kGenMaxRank modes.
-__device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan &g, const RawSmem &s, int nl,
-                                                const double2 *Hbase, double2 *gpiv, const double2 *w,
-                                                double2 detB, Work &wk, uint64_t *sacc) {
+// block flips more than kGenMaxRank positions.
+__device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan &g, const GenLds &T, const RawSmem &s,
+                                                int nl, const double2 *w, double2 detB, Work &wk, uint64_t *sacc) {
     const int tid = threadIdx.x;
-    int *cnt = (int *)s.red;   // [0..4] bins (lane, 8, 16, 32, too large), [8..12] cursors
+    int *cnt = (int *)s.red;   // [0..4] bins (lane, 8, 16, 32, too large), [8..11] cursors
     uint16_t *order = (uint16_t *)s.piv;
     if (tid < 16) cnt[tid] = 0;
     __syncthreads();
     for (int e = tid; e < nl; e += kThreads) {
-        const int r = gen_max_rank(g, decode_key(p, s.hkey[e]));
-        atomicAdd(&cnt[r <= 4 ? 0 : (r <= 8 ? 1 : (r <= 16 ? 2 : (r <= 32 ? 3 : 4)))], 1);
+        uint64_t pm[2];
+        gen_masks(T.kbt, s.hkey[e], pm);
+        atomicAdd(&cnt[rank_bin(gen_max_rank(pm))], 1);
     }
     __syncthreads();
     if (cnt[4] > 0) return false;
@@ -430,11 +510,13 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
     }
     __syncthreads();
     for (int e = tid; e < nl; e += kThreads) {
-        const int r = gen_max_rank(g, decode_key(p, s.hkey[e]));
-        order[atomicAdd(&cnt[8 + (r <= 4 ? 0 : (r <= 8 ? 1 : (r <= 16 ? 2 : 3)))], 1)] = (uint16_t)e;
+        uint64_t pm[2];
+        gen_masks(T.kbt, s.hkey[e], pm);
+        order[atomicAdd(&cnt[8 + rank_bin(gen_max_rank(pm))], 1)] = (uint16_t)e;
     }
     __syncthreads();
-    // value of entry e: weight * detB * prod det S, into its slot
+    // value of entry e: weight * detB * prod det S, into its slot (each entry
+    // is read and written by the same lane or lane group)
     auto store = [&](int e, double2 dS) {
         const double2 d = c_mul(detB, dS);
         double2 v;
@@ -447,47 +529,61 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
         s.hkey[e] = (uint64_t)__double_as_longlong(v.x);
         *(double *)&s.hcnt[e] = v.y;
     };
-    // all decodes of a pass happen before its stores overwrite keys: each
-    // entry is read and written by the same lane (group)
+    unsigned long long rank = 0;
     for (int i = tid; i < n0; i += kThreads) {
         const int e = order[i];
-        const Flips f = decode_key(p, s.hkey[e]);
-        store(e, gen_det_lane(p, g, Hbase, f));
+        uint64_t pm[2];
+        gen_masks(T.kbt, s.hkey[e], pm);
+        rank += __popcll(pm[0]) + __popcll(pm[1]);
+        store(e, gen_det_lane(p, g, T, pm));
     }
     {
         const int l8 = tid & 7, g8 = tid >> 3;
         for (int i = n0 + g8; i < n0 + n1; i += kThreads / 8) {
             const int e = order[i];
-            const Flips f = decode_key(p, s.hkey[e]);
-            const double2 dS = gen_det_group<8>(p, g, Hbase, f, l8, gpiv + g8 * 8);
+            uint64_t pm[2];
+            gen_masks(T.kbt, s.hkey[e], pm);
+            const double2 dS = gen_det_group<8>(p, g, T, pm, l8, T.gpiv + g8 * 8);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            if (l8 == 0) store(e, dS);
+            if (l8 == 0) {
+                rank += __popcll(pm[0]) + __popcll(pm[1]);
+                store(e, dS);
+            }
         }
     }
     {
         const int l16 = tid & 15, g16 = tid >> 4;
         for (int i = n0 + n1 + g16; i < n0 + n1 + n2; i += kThreads / 16) {
             const int e = order[i];
-            const Flips f = decode_key(p, s.hkey[e]);
-            const double2 dS = gen_det_group<16>(p, g, Hbase, f, l16, gpiv + g16 * 16);
+            uint64_t pm[2];
+            gen_masks(T.kbt, s.hkey[e], pm);
+            const double2 dS = gen_det_group<16>(p, g, T, pm, l16, T.gpiv + g16 * 16);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            if (l16 == 0) store(e, dS);
+            if (l16 == 0) {
+                rank += __popcll(pm[0]) + __popcll(pm[1]);
+                store(e, dS);
+            }
         }
     }
     {
         const int l32 = tid & 31, g32 = tid >> 5;
         for (int i = n0 + n1 + n2 + g32; i < n0 + n1 + n2 + n3; i += kThreads / 32) {
             const int e = order[i];
-            const Flips f = decode_key(p, s.hkey[e]);
-            const double2 dS = gen_det_group<32>(p, g, Hbase, f, l32, gpiv + g32 * 32);
+            uint64_t pm[2];
+            gen_masks(T.kbt, s.hkey[e], pm);
+            const double2 dS = gen_det_group<32>(p, g, T, pm, l32, T.gpiv + g32 * 32);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            if (l32 == 0) store(e, dS);
+            if (l32 == 0) {
+                rank += __popcll(pm[0]) + __popcll(pm[1]);
+                store(e, dS);
+            }
         }
     }
     __syncthreads();
+    wk.rank += rank;
     if (tid == 0) wk.terms += (unsigned)nl;
     // every slot e < nl holds a value: accumulate_slots reads s.list
     for (int e = tid; e < nl; e += kThreads) s.list[e] = (uint16_t)e;
@@ -496,12 +592,28 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
     return true;
 }
 
+__device__ __forceinline__ void write_zero(int64_t b, double *prob, double *amp, double *logp) {
+    prob[b] = 0.0;
+    if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
+    if (logp) logp[b] = -INFINITY;
+}
+
+__device__ __forceinline__ void write_result(int64_t b, double2 total, double sc, double *prob, double *amp,
+                                             double *logp) {
+    const double ax = total.x * sc, ay = total.y * sc;
+    const double pb = ax * ax + ay * ay;
+    prob[b] = pb;
+    if (amp) { amp[2 * b] = ax; amp[2 * b + 1] = ay; }
+    if (logp) logp[b] = log(pb);
+}
+
 // Raw Estimate (EXACT = false; the entries of bitstring i are in the
 // workspace, written by k_sample_entries) or exact mode (EXACT = true; the
-// plan's shared term list, ecount[i] is only written to defer).  Bitstrings
+// plan's shared term list, ecount[i] is a flag written here).  Bitstrings
 // whose base is singular or ill-conditioned, or with a pattern beyond
-// kGenMaxRank in a block, get ecount[i] = kEntryDeferred and are left to the
-// LU kernels.
+// kGenMaxRank in a block, get ecount[i] = kEntryDeferred, as do (from the
+// sampler) those whose patterns overflowed the workspace region; they are
+// left to k_gen_lu.
 template <bool EXACT, bool MIXED>
 __global__ void __launch_bounds__(kThreads, 1)
 k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
@@ -514,63 +626,37 @@ k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, 
     __shared__ GenShared sh;
     __shared__ uint64_t s_acc[kAccWords];
     const RawSmem s = carve_raw(smem, 0, p.n, 4, false);
-    double2 *Hbase = (double2 *)(smem + kGenBaseBytes);
-    double2 *gpiv = Hbase + g.hsize;   // kThreads entries: LU pivot rows of the lane groups
+    const GenLds T = carve_gen(smem, g);
     const int tid = threadIdx.x;
     Work wk;
+    load_gen_tables(p, g, T);
     for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
         const int64_t b = b0 + i;
         uint32_t ne = 0;
         bool zero = false;
         if constexpr (!EXACT) {
             ne = ecount[i];
+            if (ne == kEntryDeferred) continue;   // overflowed its region: k_gen_lu takes it
             zero = ne == kEntryInvalid;
         }
         if (!zero) zero = !load_bitstring(p, bits, b, s.Rb, &s_ok);
         if (!zero) {
-            if (tid == 0) {
-                // rows of R in each block; an amplitude needs as many as the input has
-                sh.nrow[0] = sh.nrow[1] = 0;
-                sh.ok = 1;
-                for (int r = 0; r < p.m; ++r) {
-                    const int q = s.Rb[r];
-                    const int blk = g.blk[q];
-                    if (sh.nrow[blk] < kGenMaxM) sh.rows[blk][sh.nrow[blk]] = (uint8_t)q;
-                    ++sh.nrow[blk];
-                }
-                for (int blk = 0; blk < g.nblk; ++blk)
-                    if (sh.nrow[blk] != g.mb[blk]) sh.ok = 0;
-                sh.det = make_double2(1.0, 0.0);
-            }
+            gen_rows(p, g, s.Rb, sh);
             __syncthreads();
             zero = sh.ok == 0;
             __syncthreads();
         }
         if (zero) {
             if (tid == 0) {
-                prob[b] = 0.0;
-                if (amp) { amp[2 * b] = 0.0; amp[2 * b + 1] = 0.0; }
-                if (logp) logp[b] = -INFINITY;
+                write_zero(b, prob, amp, logp);
                 if constexpr (EXACT) ecount[i] = 0;
             }
             __syncthreads();
             continue;
         }
-        if constexpr (!EXACT) {
-            if (ne == kEntryOverflow) {
-                if (tid == 0) {
-                    const double nan = __longlong_as_double(0x7FF8000000000000ll);
-                    prob[b] = nan;
-                    if (amp) { amp[2 * b] = nan; amp[2 * b + 1] = nan; }
-                    if (logp) logp[b] = nan;
-                }
-                __syncthreads();
-                continue;
-            }
-        }
         bool ok = true;
         for (int blk = 0; blk < g.nblk && ok; ++blk)
-            ok = gen_setup_block<MIXED>(p, g, blk, (unsigned char *)smem, Hbase + g.hoff[blk], sh, wk);
+            ok = gen_setup_block<MIXED>(p, g, T, blk, (unsigned char *)smem, sh, wk);
         const double2 detB = sh.det;
         acc_clear(s_acc);
         __syncthreads();
@@ -586,7 +672,7 @@ k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, 
                 }
             }
             __syncthreads();
-            ok = gen_sum_entries(p, g, s, nc, Hbase, gpiv, EXACT ? xw + c0 : nullptr, detB, wk, s_acc);
+            ok = gen_sum_entries(p, g, T, s, nc, EXACT ? xw + c0 : nullptr, detB, wk, s_acc);
         }
         if (!ok) {
             if (tid == 0) ecount[i] = kEntryDeferred;
@@ -595,14 +681,166 @@ k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, 
         }
         const double2 total = acc_value(s_acc);
         if (tid == 0) {
-            const double sc = EXACT ? 1.0 : p.scale;
-            const double ax = total.x * sc, ay = total.y * sc;
-            const double pb = ax * ax + ay * ay;
-            prob[b] = pb;
-            if (amp) { amp[2 * b] = ax; amp[2 * b + 1] = ay; }
-            if (logp) logp[b] = log(pb);
+            write_result(b, total, EXACT ? 1.0 : p.scale, prob, amp, logp);
             if constexpr (EXACT) ecount[i] = 0;
         }
+        __syncthreads();
+    }
+    flush_work(wk, nterm);
+}
+
+// ---------------------------------------------------------------------------
+// Fallback for the bitstrings the general evaluation left (flag
+// kEntryDeferred): every pattern's submatrix M_N is factorised directly,
+// block by block, by lane groups of 32 (one row of the block per lane),
+// composing the rows from the low-rank form of Sec. IV-B Eq. 19 (two-layer
+// form for two CPhase layers) restricted to the block.  Raw Estimate samples
+// the bitstring again with its LDS hash.
+// ---------------------------------------------------------------------------
+
+// Row i (mode Ri) of block blk of M_N over the block's columns, from global
+// memory; lanes >= m give identity rows.
+__device__ __forceinline__ void gen_lu_row(const DevPlan &p, const GenPlan &g, const GenShared &sh, const Flips &f,
+                                           int blk, int lane, double2 (&a)[32]) {
+    const int m = g.mb[blk], n = p.n, G = p.G;
+    const uint8_t *col = g.col + blk * kGenMaxM;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) a[j] = make_double2(j == lane ? 1.0 : 0.0, 0.0);
+    if (lane >= m) return;
+    const int Ri = sh.rows[blk][lane];
+    const size_t rn = (size_t)Ri * n;
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+        if (j < m) a[j] = p.P[(size_t)Ri * G + col[j]];
+    const uint64_t n0[2] = {f.n0[0] & g.bmask[blk][0], f.n0[1] & g.bmask[blk][1]};
+    const uint64_t n1[2] = {f.n1[0] & g.bmask[blk][0], f.n1[1] & g.bmask[blk][1]};
+    for (int w0 = 0; w0 < 2; ++w0)
+        for (uint64_t mm = n0[w0]; mm; mm &= mm - 1) {
+            const int c = 64 * w0 + __ffsll((long long)mm) - 1;
+            double2 al = p.A1[rn + c];
+            if (p.L == 2) {
+                for (int w1 = 0; w1 < 2; ++w1)
+                    for (uint64_t qq = n1[w1]; qq; qq &= qq - 1) {
+                        const int q = 64 * w1 + __ffsll((long long)qq) - 1;
+                        const double2 t = p.A2[rn + q], r = p.R1[(size_t)q * n + c];
+                        al = c_fma(al, make_double2(-2.0 * t.x, -2.0 * t.y), r);
+                    }
+            }
+            const double2 s2 = make_double2(-2.0 * al.x, -2.0 * al.y);
+            const double2 *phi = p.Phi0 + (size_t)c * G;
+#pragma unroll
+            for (int j = 0; j < 32; ++j)
+                if (j < m) a[j] = c_fma(a[j], s2, phi[col[j]]);
+        }
+    if (p.L == 2) {
+        for (int w1 = 0; w1 < 2; ++w1)
+            for (uint64_t qq = n1[w1]; qq; qq &= qq - 1) {
+                const int q = 64 * w1 + __ffsll((long long)qq) - 1;
+                const double2 t = p.A2[rn + q];
+                const double2 s2 = make_double2(-2.0 * t.x, -2.0 * t.y);
+                const double2 *qrow = p.Q + (size_t)q * G;
+#pragma unroll
+                for (int j = 0; j < 32; ++j)
+                    if (j < m) a[j] = c_fma(a[j], s2, qrow[col[j]]);
+            }
+    }
+}
+
+// Slot values (weight * det M_N) of the nl entries whose slots are list[e]
+// (keys in s.hkey, counts in s.hcnt, or exact weights w[e] with list[e] = e),
+// then their exact sum.
+__device__ __forceinline__ void gen_lu_entries(const DevPlan &p, const GenPlan &g, const GenShared &sh,
+                                               const RawSmem &s, int nl, const double2 *w, Work &wk,
+                                               uint64_t *sacc) {
+    const int tid = threadIdx.x, lane = tid & 31, grp = tid >> 5;
+    for (int e = grp; e < nl; e += kThreads / 32) {
+        const uint16_t slot = s.list[e];
+        const Flips f = decode_key(p, s.hkey[slot]);
+        double2 det = make_double2(1.0, 0.0);
+        for (int blk = 0; blk < g.nblk; ++blk) {
+            double2 a[32];
+            gen_lu_row(p, g, sh, f, blk, lane, a);
+            det = c_mul(det, lu_det<32>(a, g.mb[blk], lane, s.piv + grp * 32));
+        }
+        if (lane == 0) {
+            double2 v;
+            if (w) {
+                v = c_mul(w[e], det);
+            } else {
+                const int2 c = s.hcnt[slot];
+                v = make_double2((double)c.x * det.x - (double)c.y * det.y, (double)c.x * det.y + (double)c.y * det.x);
+            }
+            s.hkey[slot] = (uint64_t)__double_as_longlong(v.x);
+            *(double *)&s.hcnt[slot] = v.y;
+            wk.terms += 1;
+            for (int blk = 0; blk < g.nblk; ++blk) wk.flops += lu_flops(g.mb[blk]);
+        }
+    }
+    __syncthreads();
+    accumulate_slots(s, nl, sacc);
+}
+
+template <bool EXACT>
+__global__ void __launch_bounds__(kThreads, 1)
+k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
+         const uint32_t *__restrict__ flags, const uint64_t *__restrict__ xkeys, const double2 *__restrict__ xw,
+         int64_t nkeys, double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
+         unsigned long long *nterm) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_ok, s_n;
+    __shared__ int s_cnt[6];
+    __shared__ GenShared sh;
+    __shared__ uint64_t s_acc[kAccWords];
+    const RawSmem s = carve_raw(smem, EXACT ? 0 : p.k, p.n, 4, false);
+    const int tid = threadIdx.x;
+    Work wk;
+    bool loaded = false;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t slot0 = hash_slot(0);
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        if (flags[i] != kEntryDeferred) continue;
+        const int64_t b = b0 + i;
+        if (!EXACT && !loaded) {
+            load_tables(p, s);
+            loaded = true;
+        }
+        bool zero = !load_bitstring(p, bits, b, s.Rb, &s_ok);
+        if (!zero) {
+            gen_rows(p, g, s.Rb, sh);
+            __syncthreads();
+            zero = sh.ok == 0;
+            __syncthreads();
+        }
+        if (zero) {
+            if (tid == 0) write_zero(b, prob, amp, logp);
+            __syncthreads();
+            continue;
+        }
+        acc_clear(s_acc);
+        if constexpr (EXACT) {
+            for (int64_t c0 = 0; c0 < nkeys; c0 += kHashSlots) {
+                const int nc = (int)min((int64_t)kHashSlots, nkeys - c0);
+                __syncthreads();
+                for (int e = tid; e < nc; e += kThreads) {
+                    s.hkey[e] = xkeys[c0 + e];
+                    s.list[e] = (uint16_t)e;
+                }
+                __syncthreads();
+                gen_lu_entries(p, g, sh, s, nc, xw + c0, wk, s_acc);
+            }
+        } else {
+            Sampler st;
+            clear_table(s, s_cnt, slot0, st);
+            while (true) {
+                const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
+                const int nl = gather_list(s, &s_n);
+                gen_lu_entries(p, g, sh, s, nl, nullptr, wk, s_acc);
+                if (done) break;
+                clear_table(s, s_cnt, slot0, st);
+            }
+        }
+        const double2 total = acc_value(s_acc);
+        if (tid == 0) write_result(b, total, EXACT ? 1.0 : p.scale, prob, amp, logp);
         __syncthreads();
     }
     flush_work(wk, nterm);

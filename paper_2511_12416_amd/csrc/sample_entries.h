@@ -51,7 +51,8 @@ k_sample_entries(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64
             if (done) break;
             clear_table<NT>(s, s_cnt, slot0, st);
         }
-        if (tid == 0) ecount[i] = overflow ? kEntryOverflow : (uint32_t)cursor;
+        // a bitstring whose patterns overflow its region is left to the LU kernels
+        if (tid == 0) ecount[i] = overflow ? kEntryDeferred : (uint32_t)cursor;
     }
 }
 

@@ -156,7 +156,7 @@ struct xf_plan {
     DevBuf dxkeys, dxw, dxdw;         // exact-mode term list (+ angle derivatives of the weights)
     // general determinant-lemma evaluation: blocks of modes and their active lists
     xf::GenPlan gen{};
-    DevBuf dgcol, dgact, dgpos0, dgpos1, dgblk, dflags;
+    DevBuf dgcol, dgact, dgpos0, dgpos1, dgblk, dgkbt, dflags;
     int last_gen = 0;                 // the last xf_probabilities call used the general lemma kernel
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
@@ -164,7 +164,7 @@ struct xf_plan {
     int last_bwd_lemma = 0;           // the last xf_log_prob_backward call used the determinant lemma
     // determinant-lemma workspace: per-bitstring regions of (pattern, count) entries
     DevBuf dekey, decnt, decount;
-    uint64_t entry_budget = 4ull << 30;   // bytes of workspace the chunking aims at
+    uint64_t entry_budget = 16ull << 30;  // bytes of workspace the chunking aims at
     // timing of the last call: ev[0] start, then per chunk (mid, end) of the
     // two lemma kernels, or one end event for a fused kernel
     std::vector<hipEvent_t> ev;
@@ -266,7 +266,7 @@ xf_status refresh_gen(xf_plan *P) {
     for (int q = 0; q < n; ++q) blk[q] = (int8_t)(g.nblk == 2 && find(q) == roots[1] ? 1 : 0);
     std::vector<uint8_t> col(2 * 32, 0), act(2 * 64, 0);
     bool fits = true;
-    int hoff = 0;
+    int hoff = 0, r1 = 0;
     for (int b = 0; b < g.nblk; ++b) {
         g.bmask[b][0] = g.bmask[b][1] = 0;
         for (int q = 0; q < n; ++q)
@@ -296,20 +296,38 @@ xf_status refresh_gen(xf_plan *P) {
         for (size_t i = 0; i < a1.size() && a0.size() + i < 64; ++i)
             act[b * 64 + a0.size() + i] = (uint8_t)a1[i], pos1[a1[i]] = (int8_t)(a0.size() + i);
         g.hoff[b] = hoff;
-        hoff += g.kb[b] * g.kb[b];
+        g.hld[b] = g.kb[b] | 1;
+        hoff += g.kb[b] * g.hld[b];
+        g.r1off[b] = r1;
+        r1 += g.kb0[b] * (g.kb[b] - g.kb0[b]);
     }
     g.hsize = hoff;
+    g.r1size = r1;
+    // key-bit table: a compressed key bit flips one (layer, mode); a
+    // trajectory bit flips the two modes of gate j in its layer
+    std::vector<uint16_t> kbt(128, 0xFFFF);
+    auto code = [&](int layer, int q) -> uint16_t {
+        const int ps = layer == 0 ? pos0[q] : pos1[q];
+        return ps < 0 ? 0xFFFF : (uint16_t)((blk[q] << 8) | ps);
+    };
+    if (P->keykind == 0) {
+        for (int i = 0; i < P->keybits && i < 64; ++i) kbt[2 * i] = code(i < P->off1 ? 0 : 1, P->keymode[i]);
+    } else if (P->keykind == 1) {
+        for (int j = 0; j < P->k && j < 64; ++j)
+            for (int side = 0; side < 2; ++side) kbt[2 * j + side] = code(P->layer[j], P->pairs[2 * j + side]);
+    }
     if (!fits) g.nblk = 0;   // the general evaluation does not apply
     xf_status st;
     if ((st = dev_upload(P->dgcol, col.data(), col.size())) || (st = dev_upload(P->dgact, act.data(), act.size())) ||
         (st = dev_upload(P->dgpos0, pos0.data(), 128)) || (st = dev_upload(P->dgpos1, pos1.data(), 128)) ||
-        (st = dev_upload(P->dgblk, blk.data(), 128)))
+        (st = dev_upload(P->dgblk, blk.data(), 128)) || (st = dev_upload(P->dgkbt, kbt.data(), 256)))
         return st;
     g.col = (const uint8_t *)P->dgcol.p;
     g.act = (const uint8_t *)P->dgact.p;
     g.pos0 = (const int8_t *)P->dgpos0.p;
     g.pos1 = (const int8_t *)P->dgpos1.p;
     g.blk = (const int8_t *)P->dgblk.p;
+    g.kbt = (const uint16_t *)P->dgkbt.p;
     return XF_OK;
 }
 
@@ -502,7 +520,7 @@ void plan_free(xf_plan *P) {
                       &P->fA2, &P->fQ, &P->fR1, &P->dkeymode, &P->dT, &P->dgkey, &P->dgmode,
                       &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
                       &P->dgsum, &P->dekey, &P->decnt, &P->decount, &P->dgcol, &P->dgact, &P->dgpos0,
-                      &P->dgpos1, &P->dgblk, &P->dflags})
+                      &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dflags})
         dev_free(*b);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();

@@ -18,6 +18,9 @@ constexpr int kThreads = 256;
 constexpr int kHashSlots = 2048;
 // Chunk of the shared exact-mode term list evaluated per LDS pass.
 constexpr int kExactChunk = 2048;
+// Largest workspace region (entries) of one bitstring in the determinant-lemma
+// paths.
+constexpr uint64_t kEntryCapMax = 8192;
 // Bytes of the fixed device scratch of xf_probabilities_noalloc (per device).
 constexpr size_t kNoAllocScratchBytes = 256ull << 20;
 // Empty-slot marker; valid keys use at most 63 bits.
@@ -64,11 +67,14 @@ struct GenPlan {
     int mb[2];                  // input modes (= base rows) of each block
     int kb0[2], kb[2];          // active modes of layer 0 / of both layers per block
     int hoff[2], hsize;         // offset of each block's H in the H region; its size (complex entries)
+    int hld[2];                 // row stride of each block's H (odd)
+    int r1off[2], r1size;       // two layers: offset of each block's R'_1[act1, act0]; total size
     uint64_t bmask[2][2];       // modes of each block (128-bit masks)
     const uint8_t *col;         // [2][32]: input-column indices (into C) of each block
     const uint8_t *act;         // [2][64]: active modes of each block, layer 0 then layer 1
     const int8_t *pos0, *pos1;  // [128]: position of a mode in its block's active list (layer 0 / 1), or -1
     const int8_t *blk;          // [128]: block of each mode
+    const uint16_t *kbt;        // [64][2]: (block << 8 | position) of the modes a key bit flips, or 0xFFFF
 };
 
 // One partial gradient (of a workgroup of the lemma backward, or of a lane

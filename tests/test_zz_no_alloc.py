@@ -1,7 +1,7 @@
 """xf_probabilities_noalloc (fixed per-device scratch, no allocation) against
 xf_probabilities through the C ABI: bitwise equal results on two calls in a
 row, the second with a smaller batch of another circuit; a clear error when
-one bitstring's workspace does not fit the scratch."""
+bitstrings whose patterns overflow their workspace region."""
 import ctypes
 
 import numpy as np
@@ -58,13 +58,22 @@ def test_noalloc_matches_allocating_call_twice(X):
     assert np.count_nonzero(p2) == w2.B
 
 
-def test_noalloc_rejects_a_workspace_beyond_the_scratch(X):
-    w = W.workload(2, B=4)
-    plan = make_plan(w, X)
-    out = torch.empty(4, dtype=torch.float64, device="cuda")
-    with pytest.raises(X.XfError) as e:
-        plan.probabilities_noalloc(X.bits_tensor(w.bits), out, "approx", (1 << 31) - 1, 1)
-    assert e.value.status == 2 and "scratch" in str(e.value)
+def test_noalloc_overflowing_regions_match(X):
+    """Large angles: every sample is a distinct pattern, more than a
+    workspace region holds, so the bitstrings are left to the LU kernel; the
+    no-allocation call agrees bitwise with the allocating one."""
+    rng = W.rng_for(404)
+    n = 16
+    rot = np.stack([W.haar_unitary(rng, n) for _ in range(2)])
+    pairs = W.random_pairs(rng, n, 40)
+    theta = rng.uniform(-3.0, 3.0, 40)
+    inp = W.bits_from_modes(range(6))
+    bits = W.all_fixed_weight(n, 6)[::997][:8]
+    plan = X.Plan(rot, pairs, np.zeros(40), theta, inp)
+    say("no-allocation call with overflowing regions: n=16 eta=6 k=40 theta~U[-3,3] t=12000")
+    (p1, a1, l1), (q1, b1, m1) = _both(X, plan, X.bits_tensor(bits), 12000, 5)
+    assert np.array_equal(p1, q1) and np.array_equal(a1, b1) and np.array_equal(l1, m1)
+    assert np.count_nonzero(p1) == len(bits)
 
 
 def test_noalloc_exact_needs_a_built_term_list(X):
