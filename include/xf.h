@@ -198,6 +198,16 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
 typedef enum { XF_EVAL_AUTO = 0, XF_EVAL_LU = 1 } xf_evaluation;
 xf_status xf_plan_set_evaluation(xf_plan *plan, xf_evaluation evaluation);
 
+/* XF_MIXED under the general determinant-lemma evaluation (see
+ * xf_plan_set_evaluation): the products forming H from a bitstring's base
+ * (X = M_B^-1 U, H = V X, the composition of Sec. IV-B Eq. 16-19 moved onto
+ * the base) run on the FP32 matrix cores for bases with 1-norm condition
+ * number at most kappa_max, and in FP64 otherwise; the base inverse, the
+ * per-pattern determinants and the accumulation stay FP64.  The FP32 error of
+ * H grows with ||M_B^-1||, so kappa_max trades speed for accuracy (default
+ * 100; 0 gives FP64 results).  kappa_max >= 0, else XF_EINVAL. */
+xf_status xf_plan_set_mixed_condition(xf_plan *plan, double kappa_max);
+
 /* Device memory the determinant-lemma path may use for its workspace
  * (default 4 GiB; bytes > 0).  Each bitstring needs (t + t/511 + 2) * 16 + 4
  * bytes; the batch is processed in chunks of as many bitstrings as fit, at

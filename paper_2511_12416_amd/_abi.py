@@ -41,7 +41,7 @@ class Circuit(ctypes.Structure):
 EXPORTS = ["xf_plan_create", "xf_plan_set_params", "xf_plan_refreeze", "xf_plan_destroy",
            "xf_extent", "xf_trajectory_bound", "xf_probabilities", "xf_probabilities_noalloc",
            "xf_log_prob_backward",
-           "xf_plan_last_term_count", "xf_plan_last_work", "xf_plan_set_evaluation", "xf_plan_set_workspace_limit",
+           "xf_plan_last_term_count", "xf_plan_last_work", "xf_plan_set_evaluation", "xf_plan_set_workspace_limit", "xf_plan_set_mixed_condition",
            "xf_expm_antihermitian", "xf_expm_adjoint", "xf_last_error"]
 
 _lib = None
@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
     L.xf_plan_last_work.argtypes = [P, ctypes.POINTER(Work)]
     L.xf_plan_set_evaluation.argtypes = [P, S]
     L.xf_plan_set_workspace_limit.argtypes = [P, U64]
+    L.xf_plan_set_mixed_condition.argtypes = [P, D]
     L.xf_expm_antihermitian.argtypes = [I32, P, P]
     L.xf_expm_adjoint.argtypes = [I32, P, P, P]
     L.xf_last_error.argtypes = []

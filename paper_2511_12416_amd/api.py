@@ -133,6 +133,11 @@ class Plan:
             raise ValueError(f"evaluation must be one of {sorted(_EVAL)}")
         check(lib().xf_plan_set_evaluation(self._h, _EVAL[evaluation]))
 
+    def set_mixed_condition(self, kappa_max: float) -> None:
+        """Mixed precision: bases with kappa_1 <= kappa_max form H on the FP32
+        matrix cores, others in FP64."""
+        check(lib().xf_plan_set_mixed_condition(self._h, float(kappa_max)))
+
     def set_workspace_limit(self, nbytes: int) -> None:
         """Device memory the determinant-lemma workspace may use (bitstrings
         are processed in chunks that fit, at least one at a time)."""

@@ -41,10 +41,6 @@ constexpr int kGenMaxM = 32;      // rows of a block's base
 constexpr int kGenMaxKb = 64;     // active modes of a block (both layers)
 constexpr int kGenMaxRank = 32;   // flipped modes of a block in one pattern
 constexpr int kGenMaxSteps = kGenMaxM / 4;   // 4-wide K slices of a product over a base
-// Mixed precision forms X and H on the FP32 matrix cores only for bases with
-// kappa_1(M_0) at most this (the FP32 error of H grows with ||M_0^-1||);
-// other bases use FP64.
-constexpr double kMixedMaxCond = 50.0;
 // Setup scratch (the augmented base and X) overlays the entry slots, pivot
 // scratch and reduction scratch of the RawSmem layout: 40960 bytes.
 constexpr size_t kGenSetupBytes = (size_t)kHashSlots * 16 + 2 * (size_t)kThreads * 16;
@@ -178,6 +174,7 @@ struct GenShared {
     double kappa;                  // kappa_1(M_0) of the current block
     int nrow[2];                   // rows of R in each block
     uint8_t rows[2][kGenMaxM];     // those rows (modes), ascending
+    uint64_t shift[2];             // positions of each block's base pattern N* (see gen_setup_block)
 };
 
 __device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
@@ -197,14 +194,24 @@ __device__ __forceinline__ void gen_rows(const DevPlan &p, const GenPlan &g, con
         for (int blk = 0; blk < g.nblk; ++blk)
             if (sh.nrow[blk] != g.mb[blk]) sh.ok = 0;
         sh.det = make_double2(1.0, 0.0);
+        sh.shift[0] = sh.shift[1] = 0;
     }
 }
 
-// Setup of block blk for the loaded bitstring: inverse of M_0 by
-// Gauss-Jordan (augmented rows [M_0 | I] in the setup scratch W, row stride
-// 2m; rows stay in place, row piv[c] ends as u_c e_c | u_c M_0^-1[c, :]),
-// conditioning test, then X = M_0^-1 U and H = V X.  Returns false if M_0 is
-// singular or kappa_1(M_0) > kLemmaMaxCond.  Whole workgroup.
+// Setup of block blk for the loaded bitstring: the base M_B = M_{N*} (N* the
+// base pattern, empty at first) is inverted by Gauss-Jordan (augmented rows
+// [M_B | I] in the setup scratch W, row stride 2m; rows stay in place, row
+// piv[c] ends as u_c e_c | u_c M_B^-1[c, :]) and checked for conditioning;
+// then X = M_B^-1 U and H = V X.  For one CPhase layer a singular or
+// ill-conditioned M_0 is replaced by M_{N*} with N* the flips of one gate
+// (the first few gates touching the block are tried in turn): with
+// Delta = N xor N* and sigma = -1 on N* \ N, +1 on N \ N*,
+//   M_N = M_{N*} - 2 U[:, Delta] diag(sigma) V[Delta, :],
+//   det M_N = det M_{N*} det(I - 2 diag(sigma) H[Delta, Delta]).
+// Returns false if no base was acceptable (kappa_1 > kLemmaMaxCond or
+// singular).  Whole workgroup.
+constexpr int kGenBaseTries = 4;
+
 template <bool MIXED>
 __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan &g, const GenLds &T, int blk,
                                                 unsigned char *scratch, GenShared &sh, Work &wk) {
@@ -222,9 +229,29 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
         __syncthreads();
         return true;
     }
+    int gate = -1;   // base pattern: the flips of this gate in the block (-1: none)
+    for (int attempt = 0;; ++attempt) {
+    uint64_t bmask = 0;   // positions of N* in this block
+    if (gate >= 0) {
+        for (int e = 0; e < 2; ++e) {
+            const uint16_t v = g.gpos[2 * gate + e];
+            if (v != kNoPos && (v >> 8) == blk) bmask ^= 1ull << (v & 0xFF);
+        }
+    }
     for (int e = tid; e < m * ld; e += kThreads) {
         const int i = e / ld, j = e % ld;
-        W[e] = j < m ? p.P[(size_t)rows[i] * G + col[j]] : make_double2(j - m == i ? 1.0 : 0.0, 0.0);
+        double2 v;
+        if (j < m) {
+            v = p.P[(size_t)rows[i] * G + col[j]];
+            for (uint64_t mm = bmask; mm; mm &= mm - 1) {
+                const int c = act[__ffsll((long long)mm) - 1];
+                const double2 a1 = p.A1[(size_t)rows[i] * n + c];
+                v = c_fma(v, make_double2(-2.0 * a1.x, -2.0 * a1.y), p.Phi0[(size_t)c * G + col[j]]);
+            }
+        } else {
+            v = make_double2(j - m == i ? 1.0 : 0.0, 0.0);
+        }
+        W[e] = v;
     }
     __syncthreads();
     if (tid < 64) {
@@ -238,6 +265,7 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
     uint64_t used = 0;          // wave 0: rows already used as pivots
     unsigned inversions = 0;    // wave 0
     double2 det = make_double2(1.0, 0.0);   // wave 0
+    bool singular = false;
     for (int c = 0; c < m; ++c) {
         if (tid < 64) {
             const bool act_row = lane < m && !((used >> lane) & 1);
@@ -270,8 +298,8 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
         __syncthreads();
         const int pr = sh.piv[c];
         if (pr < 0) {
-            __syncthreads();
-            return false;   // exactly singular base
+            singular = true;   // exactly singular base
+            break;
         }
         const double2 ui = sh.uinv[c];
         if (tid < m && tid != pr) {
@@ -286,28 +314,42 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
         }
         __syncthreads();
     }
-    // det M_0 (wave 0) and the conditioning: ||M_0^-1||_1 from rows piv[c] / u_c
-    if (tid < 64) {
+    // det M_B (wave 0) and the conditioning: ||M_B^-1||_1 from rows piv[c] / u_c
+    if (!singular && tid < 64) {
         double cs = 0.0;
         if (lane < m)
             for (int c = 0; c < m; ++c) cs += sqrt(cabs2(c_mul(W[sh.piv[c] * ld + m + lane], sh.uinv[c])));
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
         if (lane == 0) {
-            if (inversions & 1) det = make_double2(-det.x, -det.y);
-            sh.det = c_mul(sh.det, det);
-            sh.ok = cs * sh.norm <= kLemmaMaxCond ? 1 : 2;
+            const bool good = cs * sh.norm <= kLemmaMaxCond;
+            sh.ok = good ? 1 : 2;
             sh.kappa = cs * sh.norm;
+            if (good) {
+                if (inversions & 1) det = make_double2(-det.x, -det.y);
+                sh.det = c_mul(sh.det, det);
+                sh.shift[blk] = bmask;
+            }
             // Gauss-Jordan (m steps of m - 1 row updates over 2m - c - 1
             // columns), conditioning, X and H
             unsigned long long f = 0;
             for (int c = 0; c < m; ++c) f += 11ull * (m - 1) + 8ull * (m - 1) * (2 * m - c - 1);
-            f += 8ull * m * m * kb + 8ull * kb * m * kb;
+            if (good) f += 8ull * m * m * kb + 8ull * kb * m * kb;
             wk.flops += f;
         }
     }
     __syncthreads();
-    if (sh.ok != 1) return false;
+    if (!singular && sh.ok == 1) break;
+    // next base: the next gate whose flips touch this block (one CPhase layer)
+    if (p.L != 1 || attempt + 1 >= kGenBaseTries) return false;
+    do {
+        ++gate;
+    } while (gate < p.k && gate < 64 &&
+             !(((g.gpos[2 * gate] >> 8) == blk && g.gpos[2 * gate] != kNoPos) ||
+               ((g.gpos[2 * gate + 1] >> 8) == blk && g.gpos[2 * gate + 1] != kNoPos)));
+    if (gate >= p.k || gate >= 64) return false;
+    __syncthreads();
+    }
     // X = M_0^-1 U (m x kb), then H = V X (kb x kb), V = [Phi0[act0, cols]; Q[act1, cols]]
     const double2 *A1 = p.A1, *A2 = p.A2, *Phi0 = p.Phi0, *Q = p.Q;
     auto minv = [&](int i, int k) { return c_mul(W[sh.piv[i] * ld + m + k], sh.uinv[i]); };
@@ -316,7 +358,9 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
     auto vop = [&](int q, int k) { return (q < kb0 ? Phi0 : Q)[(size_t)act[q] * G + col[k]]; };
     auto xop = [&](int k, int q) { return X[k * kb + q]; };
     auto hput = [&](int q, int q2, double2 v) { H[q * hld + q2] = v; };
-    if (MIXED && sh.kappa <= kMixedMaxCond) {
+    // mixed precision: FP32 matrix cores for bases with kappa_1 <= p.mixed_cond
+    // (the FP32 error of H grows with ||M_B^-1||), FP64 for the others
+    if (MIXED && sh.kappa <= p.mixed_cond) {
         cgemm_mfma<true>(m, kb, m, minv, uop, xput);
         __syncthreads();
         cgemm_mfma<true>(kb, kb, m, vop, xop, hput);
@@ -362,8 +406,9 @@ __device__ __forceinline__ void mask_positions(uint64_t mask, int (&pos)[NP]) {
 // CPhase layers.
 template <int NP>
 __device__ __forceinline__ double2 gen_s_entry(bool two_layers, const double2 *H, int hld, const double2 *R1a,
-                                               int kb0, int i, int j, int r0, const int (&pos)[NP]) {
+                                               int kb0, int i, int j, int r0, const int (&pos)[NP], uint64_t neg) {
     double2 h = H[pos[i] * hld + pos[j]];
+    if ((neg >> pos[i]) & 1) h = make_double2(-h.x, -h.y);
     if (two_layers && i >= r0) {
         double2 corr = make_double2(0.0, 0.0);
 #pragma unroll
@@ -424,9 +469,10 @@ __device__ __forceinline__ double2 small_det4(double2 (&a)[4][4], int r) {
 }
 
 // Product over blocks of det S_N for a pattern whose blocks flip at most 4
-// positions each (one lane).
+// positions each (one lane); pm already relative to the blocks' base
+// patterns, neg the positions with sigma = -1.
 __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan &g, const GenLds &T,
-                                                const uint64_t (&pm)[2]) {
+                                                const uint64_t (&pm)[2], const uint64_t (&neg)[2]) {
     double2 det = make_double2(1.0, 0.0);
     for (int blk = 0; blk < g.nblk; ++blk) {
         const int r = __popcll(pm[blk]);
@@ -442,8 +488,9 @@ __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan 
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                a[i][j] = (i < r && j < r) ? gen_s_entry<4>(p.L == 2, H, g.hld[blk], R1a, kb0, i, j, r0, pos)
-                                           : make_double2(i == j ? 1.0 : 0.0, 0.0);
+                a[i][j] = (i < r && j < r)
+                              ? gen_s_entry<4>(p.L == 2, H, g.hld[blk], R1a, kb0, i, j, r0, pos, neg[blk])
+                              : make_double2(i == j ? 1.0 : 0.0, 0.0);
         det = c_mul(det, small_det4(a, r));
     }
     return det;
@@ -453,7 +500,8 @@ __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan 
 // GS positions each); every lane of the group returns the product.
 template <int GS>
 __device__ __forceinline__ double2 gen_det_group(const DevPlan &p, const GenPlan &g, const GenLds &T,
-                                                 const uint64_t (&pm)[2], int lane, double2 *piv) {
+                                                 const uint64_t (&pm)[2], const uint64_t (&neg)[2], int lane,
+                                                 double2 *piv) {
     double2 det = make_double2(1.0, 0.0);
     for (int blk = 0; blk < g.nblk; ++blk) {
         const int r = __popcll(pm[blk]);
@@ -467,11 +515,39 @@ __device__ __forceinline__ double2 gen_det_group(const DevPlan &p, const GenPlan
         double2 a[GS];
 #pragma unroll
         for (int j = 0; j < GS; ++j)
-            a[j] = (lane < r && j < r) ? gen_s_entry<GS>(p.L == 2, H, g.hld[blk], R1a, kb0, lane, j, r0, pos)
+            a[j] = (lane < r && j < r) ? gen_s_entry<GS>(p.L == 2, H, g.hld[blk], R1a, kb0, lane, j, r0, pos, neg[blk])
                                        : make_double2(j == lane ? 1.0 : 0.0, 0.0);
         det = c_mul(det, lu_det<GS>(a, r, lane, piv));
     }
     return det;
+}
+
+// A pattern's flipped positions relative to the blocks' base patterns, and
+// the positions where the base flips and the pattern does not (sigma = -1).
+__device__ __forceinline__ void gen_relative(const uint16_t *kbt, uint64_t key, const uint64_t (&shift)[2],
+                                             uint64_t (&pm)[2], uint64_t (&neg)[2]) {
+    gen_masks(kbt, key, pm);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        neg[b] = shift[b] & ~pm[b];
+        pm[b] ^= shift[b];
+    }
+}
+
+// Algorithmic FLOPs of one pattern: per block the r x r elimination, the
+// two-layer correction of the layer-1 rows (8 r0 per entry), the product of
+// the determinants, and the weight multiply.
+__device__ __forceinline__ unsigned long long gen_pattern_flops(const GenPlan &g, bool two_layers,
+                                                                const uint64_t (&pm)[2]) {
+    unsigned long long f = 8;
+    for (int blk = 0; blk < g.nblk; ++blk) {
+        const int r = __popcll(pm[blk]);
+        if (r == 0) continue;
+        const int kb0 = g.kb0[blk];
+        const int r0 = __popcll(pm[blk] & (kb0 >= 64 ? ~0ull : ((1ull << kb0) - 1)));
+        f += lu_flops(r) + 6 + (two_layers ? 8ull * (r - r0) * r0 * r : 0ull);
+    }
+    return f;
 }
 
 __device__ __forceinline__ int gen_max_rank(const uint64_t (&pm)[2]) {
@@ -487,15 +563,16 @@ __device__ __forceinline__ int rank_bin(int r) { return r <= 4 ? 0 : (r <= 8 ? 1
 // that lanes and lane groups of a pass take like patterns.  Returns false if a
 // block flips more than kGenMaxRank positions.
 __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan &g, const GenLds &T, const RawSmem &s,
-                                                int nl, const double2 *w, double2 detB, Work &wk, uint64_t *sacc) {
+                                                int nl, const double2 *w, double2 detB, const uint64_t (&shift)[2],
+                                                Work &wk, uint64_t *sacc) {
     const int tid = threadIdx.x;
     int *cnt = (int *)s.red;   // [0..4] bins (lane, 8, 16, 32, too large), [8..11] cursors
     uint16_t *order = (uint16_t *)s.piv;
     if (tid < 16) cnt[tid] = 0;
     __syncthreads();
     for (int e = tid; e < nl; e += kThreads) {
-        uint64_t pm[2];
-        gen_masks(T.kbt, s.hkey[e], pm);
+        uint64_t pm[2], neg[2];
+        gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
         atomicAdd(&cnt[rank_bin(gen_max_rank(pm))], 1);
     }
     __syncthreads();
@@ -510,8 +587,8 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
     }
     __syncthreads();
     for (int e = tid; e < nl; e += kThreads) {
-        uint64_t pm[2];
-        gen_masks(T.kbt, s.hkey[e], pm);
+        uint64_t pm[2], neg[2];
+        gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
         order[atomicAdd(&cnt[8 + rank_bin(gen_max_rank(pm))], 1)] = (uint16_t)e;
     }
     __syncthreads();
@@ -529,25 +606,27 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
         s.hkey[e] = (uint64_t)__double_as_longlong(v.x);
         *(double *)&s.hcnt[e] = v.y;
     };
-    unsigned long long rank = 0;
+    unsigned long long rank = 0, flops = 0;
     for (int i = tid; i < n0; i += kThreads) {
         const int e = order[i];
-        uint64_t pm[2];
-        gen_masks(T.kbt, s.hkey[e], pm);
+        uint64_t pm[2], neg[2];
+        gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
         rank += __popcll(pm[0]) + __popcll(pm[1]);
-        store(e, gen_det_lane(p, g, T, pm));
+        flops += gen_pattern_flops(g, p.L == 2, pm);
+        store(e, gen_det_lane(p, g, T, pm, neg));
     }
     {
         const int l8 = tid & 7, g8 = tid >> 3;
         for (int i = n0 + g8; i < n0 + n1; i += kThreads / 8) {
             const int e = order[i];
-            uint64_t pm[2];
-            gen_masks(T.kbt, s.hkey[e], pm);
-            const double2 dS = gen_det_group<8>(p, g, T, pm, l8, T.gpiv + g8 * 8);
+            uint64_t pm[2], neg[2];
+            gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
+            const double2 dS = gen_det_group<8>(p, g, T, pm, neg, l8, T.gpiv + g8 * 8);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (l8 == 0) {
                 rank += __popcll(pm[0]) + __popcll(pm[1]);
+                flops += gen_pattern_flops(g, p.L == 2, pm);
                 store(e, dS);
             }
         }
@@ -556,13 +635,14 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
         const int l16 = tid & 15, g16 = tid >> 4;
         for (int i = n0 + n1 + g16; i < n0 + n1 + n2; i += kThreads / 16) {
             const int e = order[i];
-            uint64_t pm[2];
-            gen_masks(T.kbt, s.hkey[e], pm);
-            const double2 dS = gen_det_group<16>(p, g, T, pm, l16, T.gpiv + g16 * 16);
+            uint64_t pm[2], neg[2];
+            gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
+            const double2 dS = gen_det_group<16>(p, g, T, pm, neg, l16, T.gpiv + g16 * 16);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (l16 == 0) {
                 rank += __popcll(pm[0]) + __popcll(pm[1]);
+                flops += gen_pattern_flops(g, p.L == 2, pm);
                 store(e, dS);
             }
         }
@@ -571,19 +651,21 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
         const int l32 = tid & 31, g32 = tid >> 5;
         for (int i = n0 + n1 + n2 + g32; i < n0 + n1 + n2 + n3; i += kThreads / 32) {
             const int e = order[i];
-            uint64_t pm[2];
-            gen_masks(T.kbt, s.hkey[e], pm);
-            const double2 dS = gen_det_group<32>(p, g, T, pm, l32, T.gpiv + g32 * 32);
+            uint64_t pm[2], neg[2];
+            gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
+            const double2 dS = gen_det_group<32>(p, g, T, pm, neg, l32, T.gpiv + g32 * 32);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (l32 == 0) {
                 rank += __popcll(pm[0]) + __popcll(pm[1]);
+                flops += gen_pattern_flops(g, p.L == 2, pm);
                 store(e, dS);
             }
         }
     }
     __syncthreads();
     wk.rank += rank;
+    wk.flops += flops;
     if (tid == 0) wk.terms += (unsigned)nl;
     // every slot e < nl holds a value: accumulate_slots reads s.list
     for (int e = tid; e < nl; e += kThreads) s.list[e] = (uint16_t)e;
@@ -658,6 +740,7 @@ k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, 
         for (int blk = 0; blk < g.nblk && ok; ++blk)
             ok = gen_setup_block<MIXED>(p, g, T, blk, (unsigned char *)smem, sh, wk);
         const double2 detB = sh.det;
+        const uint64_t shift[2] = {sh.shift[0], sh.shift[1]};
         acc_clear(s_acc);
         __syncthreads();
         const int64_t nent = EXACT ? nkeys : (int64_t)ne;
@@ -672,7 +755,7 @@ k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, 
                 }
             }
             __syncthreads();
-            ok = gen_sum_entries(p, g, T, s, nc, EXACT ? xw + c0 : nullptr, detB, wk, s_acc);
+            ok = gen_sum_entries(p, g, T, s, nc, EXACT ? xw + c0 : nullptr, detB, shift, wk, s_acc);
         }
         if (!ok) {
             if (tid == 0) ecount[i] = kEntryDeferred;

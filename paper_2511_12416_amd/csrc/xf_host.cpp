@@ -156,10 +156,11 @@ struct xf_plan {
     DevBuf dxkeys, dxw, dxdw;         // exact-mode term list (+ angle derivatives of the weights)
     // general determinant-lemma evaluation: blocks of modes and their active lists
     xf::GenPlan gen{};
-    DevBuf dgcol, dgact, dgpos0, dgpos1, dgblk, dgkbt, dflags;
+    DevBuf dgcol, dgact, dgpos0, dgpos1, dgblk, dgkbt, dggpos, dflags;
     int last_gen = 0;                 // the last xf_probabilities call used the general lemma kernel
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
+    double mixed_cond = 100.0;        // XF_MIXED: kappa_1 bound of bases formed in FP32
     int last_lemma = 0;               // the last xf_probabilities call used the determinant lemma
     int last_bwd_lemma = 0;           // the last xf_log_prob_backward call used the determinant lemma
     // determinant-lemma workspace: per-bitstring regions of (pattern, count) entries
@@ -310,17 +311,20 @@ xf_status refresh_gen(xf_plan *P) {
         const int ps = layer == 0 ? pos0[q] : pos1[q];
         return ps < 0 ? 0xFFFF : (uint16_t)((blk[q] << 8) | ps);
     };
+    std::vector<uint16_t> gpos(128, 0xFFFF);
+    for (int j = 0; j < P->k && j < 64; ++j)
+        for (int side = 0; side < 2; ++side) gpos[2 * j + side] = code(P->layer[j], P->pairs[2 * j + side]);
     if (P->keykind == 0) {
         for (int i = 0; i < P->keybits && i < 64; ++i) kbt[2 * i] = code(i < P->off1 ? 0 : 1, P->keymode[i]);
     } else if (P->keykind == 1) {
-        for (int j = 0; j < P->k && j < 64; ++j)
-            for (int side = 0; side < 2; ++side) kbt[2 * j + side] = code(P->layer[j], P->pairs[2 * j + side]);
+        kbt = gpos;
     }
     if (!fits) g.nblk = 0;   // the general evaluation does not apply
     xf_status st;
     if ((st = dev_upload(P->dgcol, col.data(), col.size())) || (st = dev_upload(P->dgact, act.data(), act.size())) ||
         (st = dev_upload(P->dgpos0, pos0.data(), 128)) || (st = dev_upload(P->dgpos1, pos1.data(), 128)) ||
-        (st = dev_upload(P->dgblk, blk.data(), 128)) || (st = dev_upload(P->dgkbt, kbt.data(), 256)))
+        (st = dev_upload(P->dgblk, blk.data(), 128)) || (st = dev_upload(P->dgkbt, kbt.data(), 256)) ||
+        (st = dev_upload(P->dggpos, gpos.data(), 256)))
         return st;
     g.col = (const uint8_t *)P->dgcol.p;
     g.act = (const uint8_t *)P->dgact.p;
@@ -328,6 +332,7 @@ xf_status refresh_gen(xf_plan *P) {
     g.pos1 = (const int8_t *)P->dgpos1.p;
     g.blk = (const int8_t *)P->dgblk.p;
     g.kbt = (const uint16_t *)P->dgkbt.p;
+    g.gpos = (const uint16_t *)P->dggpos.p;
     return XF_OK;
 }
 
@@ -512,6 +517,7 @@ xf::DevPlan snapshot(const xf_plan *P) {
     d.glayer = (const int32_t *)P->dglayer.p;
     d.gneg = (const uint8_t *)P->dgneg.p;
     d.scale = 1.0;
+    d.mixed_cond = P->mixed_cond;
     return d;
 }
 
@@ -520,7 +526,7 @@ void plan_free(xf_plan *P) {
                       &P->fA2, &P->fQ, &P->fR1, &P->dkeymode, &P->dT, &P->dgkey, &P->dgmode,
                       &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
                       &P->dgsum, &P->dekey, &P->decnt, &P->decount, &P->dgcol, &P->dgact, &P->dgpos0,
-                      &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dflags})
+                      &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dggpos, &P->dflags})
         dev_free(*b);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();
@@ -926,6 +932,13 @@ xf_status xf_plan_set_workspace_limit(xf_plan *P, uint64_t bytes) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
     if (bytes == 0) return fail(XF_EINVAL, "workspace limit must be positive");
     P->entry_budget = bytes;
+    return ok();
+}
+
+xf_status xf_plan_set_mixed_condition(xf_plan *P, double kappa_max) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    if (!(kappa_max >= 0.0)) return fail(XF_EINVAL, "kappa_max must be >= 0");
+    P->mixed_cond = kappa_max;
     return ok();
 }
 

@@ -56,6 +56,7 @@ struct DevPlan {
     const int32_t *glayer;    // [k]
     const uint8_t *gneg;      // [k] theta_j < 0
     double scale;             // Raw Estimate: sqrt(xi*) / t
+    double mixed_cond;        // XF_MIXED: largest kappa_1 of a base whose lemma products run in FP32
 };
 
 // Plan data of the general determinant-lemma evaluation (lemma_gen.h): the
@@ -75,6 +76,7 @@ struct GenPlan {
     const int8_t *pos0, *pos1;  // [128]: position of a mode in its block's active list (layer 0 / 1), or -1
     const int8_t *blk;          // [128]: block of each mode
     const uint16_t *kbt;        // [64][2]: (block << 8 | position) of the modes a key bit flips, or 0xFFFF
+    const uint16_t *gpos;       // [64][2]: the same for the two modes of gate j
 };
 
 // One partial gradient (of a workgroup of the lemma backward, or of a lane

@@ -90,18 +90,46 @@ def test_config3_exact_general_vs_oracle(X):
     assert np.array_equal(p, p2)
 
 
+def _config5_golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config5_subset_oracle.json")
+    with open(path) as f:
+        return json.load(f)
+
+
 def test_config5_general_vs_oracle(X):
+    """The full batch in the launch configuration of the benchmark; 1000
+    outputs spread over the batch against the stored FP64 oracle values
+    (tests/golden/make_config5_subset.py), 8 more against the oracle live."""
     w = W.workload(5)
+    gold = _config5_golden()
+    assert gold["workload"] == w.name and gold["t"] == w.t and gold["seed"] == w.seed
+    gidx = np.asarray(gold["index"], dtype=np.int64)
+    gref = np.asarray(gold["prob"])
+    gamp = np.asarray(gold["amp_re"]) + 1j * np.asarray(gold["amp_im"])
     say("config 5 (general lemma, two layers, two blocks): n=100 eta=25a+25b k=40 t=65536 B=1e5")
-    idx = sample_indices(w.B, 16, seed=55)
+    idx = sample_indices(w.B, 8, seed=55)
     ref = oracle.run_workload(w, index=idx)
     for prec, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
         plan = make_plan(w, X, prec)
-        p = gpu_probs(plan, X, w.bits, "approx", w.t, w.seed)
+        bits = X.bits_tensor(w.bits, torch.device("cuda", 0))
+        out = torch.empty(w.B, dtype=torch.float64, device=bits.device)
+        amp = torch.empty((w.B, 2), dtype=torch.float64, device=bits.device)
+        plan.probabilities(bits, "approx", w.t, w.seed, out=out, amp=amp)
+        torch.cuda.synchronize()
+        p = out.cpu().numpy()
+        a = amp.cpu().numpy()
+        a = a[:, 0] + 1j * a[:, 1]
         wk = plan.last_work()
         assert wk["general"] and wk["lemma"]
         say(f"  {prec}: {wk['fp32_bases']} of {2 * w.B} bases in FP32, {wk['determinants']} patterns")
-        _check(p[idx], ref, tol, f"cfg5 {prec}")
+        _check(p[idx], ref, tol, f"cfg5 {prec} live")
+        _check(p[gidx], gref, tol, f"cfg5 {prec} stored")
+        ea = np.abs(a[gidx] - gamp) / np.maximum(np.abs(gamp), 1e-300)
+        say(f"  {prec} amplitudes: max rel err {ea.max():.3e}")
+        assert ea.max() <= tol
+        plan.close()
 
 
 def test_exact_general_defers_ill_conditioned_bases(X):
