@@ -71,10 +71,13 @@ typedef enum {
 typedef enum { XF_EXACT = 0, XF_RAW_ESTIMATE = 1 } xf_mode;
 
 /* XF_FP64: every step in FP64.
- * XF_MIXED: where a trajectory's submatrix is factorised directly (exact mode,
- * and Raw Estimate under XF_EVAL_LU or where the lemma does not apply), its
- * low-rank correction is formed in FP32; the base submatrix, the elimination,
- * the pivot product and the cross-term accumulation stay FP64. */
+ * XF_MIXED: the composition of Sec. IV-B Eq. 16-19 runs in FP32 where it is a
+ * product: under the general determinant-lemma evaluation (see
+ * xf_plan_set_evaluation) the products forming H from a well-conditioned
+ * base run on the FP32 matrix cores (xf_plan_set_mixed_condition); where a
+ * trajectory's submatrix is factorised directly, its low-rank correction is
+ * formed in FP32.  The base inverse or elimination, the pivot products and
+ * the cross-term accumulation stay FP64. */
 typedef enum { XF_FP64 = 0, XF_MIXED = 1 } xf_precision;
 
 /* 128-bit occupation / bitstring: bit p of (w[0] | w[1] << 64) <=> mode p occupied
@@ -82,6 +85,10 @@ typedef enum { XF_FP64 = 0, XF_MIXED = 1 } xf_precision;
  * 128-bit states as in Sec. IV-A). */
 typedef struct { uint64_t w[2]; } xf_bits128;
 
+/* A circuit in the layered form of Sec. IV-B (Eq. 14): passive matchgate
+ * layers, each given by its n x n mode matrix (Sec. II-B Eq. 2-3; a layer
+ * of matchgates G(A, B) multiplies out to one such unitary), with the
+ * controlled-phase gates of Sec. III-B (Eq. 7) between consecutive layers. */
 typedef struct {
     int32_t n;              /* modes = qubits, 1 <= n <= 128                                   */
     int32_t n_rot;          /* rotation layers in time order, 1 <= n_rot <= 3                  */
@@ -95,7 +102,11 @@ typedef struct {
 typedef struct xf_plan xf_plan;
 
 /* Creates a plan on HIP device `device` for circuit `c` and input occupation
- * `input` (eta = popcount <= 64, all bits below n).  Copies what it needs
+ * `input` (eta = popcount <= 64, all bits below n; the input Slater
+ * determinant of Sec. II-B).  Precomputes what every probability call
+ * shares: the layer products and low-rank factors of Sec. IV-B Eq. 14-19,
+ * the extent of Sec. III-A Eq. 5 and the trajectory-sampling table of
+ * Eq. 10-11 (see the sampler definition above).  Copies what it needs
  * from the host arrays; they may be freed afterwards.  Validates unitarity of
  * every layer (max |U^H U - I| <= 1e-10).  The trajectory-sampling table is
  * frozen at the angles given here (see xf_plan_refreeze).
@@ -105,15 +116,18 @@ xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision pre
                          int device, xf_plan **plan);
 
 /* Replaces rotation entries and angles (same shapes as at creation; either
- * pointer may be NULL to keep the current values).  The sampling table stays
+ * pointer may be NULL to keep the current values), recomputing the factors
+ * of Sec. IV-B Eq. 14-19 and the extent of Sec. III-A Eq. 5.  The sampling table stays
  * frozen, so Raw Estimate draws the same trajectories: this is the estimator
  * whose derivative xf_log_prob_backward returns.  Synchronous. */
 xf_status xf_plan_set_params(xf_plan *plan, const double *rot, const double *theta);
 
-/* Rebuilds the sampling table from the current angles.  Synchronous. */
+/* Rebuilds the sampling table (Sec. III-A Eq. 10-11) from the current
+ * angles.  Synchronous. */
 xf_status xf_plan_refreeze(xf_plan *plan);
 
-/* Frees the plan and its device memory (synchronises the plan's device). */
+/* Frees the plan and its device memory (synchronises the plan's device).
+ * NULL is accepted and ignored. */
 xf_status xf_plan_destroy(xf_plan *plan);
 
 /* Extent of the current angles, Sec. III-A Eq. 5:
@@ -181,20 +195,29 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
                                int64_t t, uint64_t seed, const double *d_grad_logp,
                                double *h_grad_rot, double *h_grad_theta, void *hip_stream);
 
-/* How Raw Estimate evaluates the determinant of each distinct flip pattern N
- * of a bitstring (exact mode and backward always use XF_EVAL_LU).
- *   XF_EVAL_LU: LU factorisation of the m x m submatrix
- *     M_N = M_0 - 2 A[R, N] Phi[N, :] (Sec. IV-B Eq. 16-19; m = eta).
- *   XF_EVAL_AUTO (default): for circuits with one CPhase layer (n_rot = 2),
- *     the matrix determinant lemma det M_N = det M_0 det(I_r - 2 H[N, N]) with
- *     H = Phi[act, :] M_0^-1 A[R, act] formed once per bitstring, so that each
- *     pattern costs an r x r determinant (r = |N|; one lane for r <= 4, a
- *     lane group for larger r up to the group size, 4 to 16 lanes by eta).
- *     A bitstring whose base M_0 is singular or has 1-norm condition number
- *     above 1e4, and any larger pattern, is evaluated with the LU of M_N
- *     instead.  The lemma runs in FP64 under both precisions (XF_MIXED then
- *     gives FP64 results).  Other circuits, eta > 16, and sizes whose tables
- *     do not fit in LDS use the LU. */
+/* How the determinant of each distinct flip pattern N of a bitstring is
+ * evaluated (Raw Estimate and exact mode; Sec. IV-B Eq. 16-19).
+ *   XF_EVAL_LU: LU factorisation with partial pivoting of the eta x eta
+ *     submatrix M_N = M_0 - 2 A[R, N] Phi[N, :] (the two-layer form for two
+ *     CPhase layers, the full product for three).
+ *   XF_EVAL_AUTO (default): the matrix determinant lemma
+ *     det M_N = det M_B det(I_r - 2 diag(sigma) H[D, D]),
+ *     H = V M_B^-1 U formed once per bitstring from a base M_B (the empty
+ *     pattern, or for one CPhase layer the flips of one gate when the empty
+ *     pattern's base is singular or ill-conditioned; D = N xor base pattern,
+ *     sigma = -1 where the base flips and N does not), so that each pattern
+ *     costs an r x r determinant (r = |D|; one lane for r <= 4, lane groups
+ *     of 8 to 32 above).  Applies to one or two CPhase layers with
+ *     n_rot = L + 1.  When every rotation layer is block-diagonal over a
+ *     partition of the modes into at most two blocks (spin-restricted layers
+ *     U (+) U), V(x) is block-diagonal for every trajectory and the
+ *     determinant is the product of the blocks' (one base per block, each of
+ *     at most 32 rows and 64 active modes).  A bitstring whose bases are all
+ *     singular or have 1-norm condition number above 1e4, with a pattern
+ *     beyond the largest lane group, or whose patterns overflow its workspace
+ *     region, is evaluated with the LU of every M_N instead.  The gradient
+ *     (xf_log_prob_backward) uses the lemma for one CPhase layer and
+ *     eta <= 16 under Raw Estimate, the LU elsewhere. */
 typedef enum { XF_EVAL_AUTO = 0, XF_EVAL_LU = 1 } xf_evaluation;
 xf_status xf_plan_set_evaluation(xf_plan *plan, xf_evaluation evaluation);
 
@@ -209,9 +232,11 @@ xf_status xf_plan_set_evaluation(xf_plan *plan, xf_evaluation evaluation);
 xf_status xf_plan_set_mixed_condition(xf_plan *plan, double kappa_max);
 
 /* Device memory the determinant-lemma path may use for its workspace
- * (default 4 GiB; bytes > 0).  Each bitstring needs (t + t/511 + 2) * 16 + 4
- * bytes; the batch is processed in chunks of as many bitstrings as fit, at
- * least one.  Results do not depend on the chunking.  Takes effect at the next
+ * (default 16 GiB; bytes > 0).  Each bitstring's region holds
+ * min(t + t/511 + 2, 8192) distinct patterns, 16 bytes each, plus 4 bytes; a
+ * bitstring with more distinct patterns is evaluated by the LU path.  The
+ * batch is processed in chunks of as many bitstrings as fit, at least one.
+ * Results do not depend on the chunking.  Takes effect at the next
  * xf_probabilities call; a workspace already allocated is kept while large
  * enough. */
 xf_status xf_plan_set_workspace_limit(xf_plan *plan, uint64_t bytes);
@@ -248,13 +273,35 @@ typedef struct {
 xf_status xf_plan_last_work(xf_plan *plan, xf_work *work);
 
 /* Host FP64 helpers for rotations parametrised by anti-Hermitian generators
- * (U = exp(K)), n <= 128:
+ * (U = exp(K), the unitary mode matrix of Sec. II-B Eq. 2-3 written through
+ * its generator; used by the differentiation interface), n <= 128:
  *   xf_expm_antihermitian: U = exp(K), K and U host [n][n][2].
  *   xf_expm_adjoint: G_K = L(K^H, G_U), the adjoint of the Frechet derivative
  *     of exp at K applied to G_U; with G_U = dL/dRe U + i dL/dIm U it returns
  *     dL/dRe K + i dL/dIm K. */
 xf_status xf_expm_antihermitian(int32_t n, const double *K, double *U);
 xf_status xf_expm_adjoint(int32_t n, const double *K, const double *G_U, double *G_K);
+
+/* Spin-restricted rotation layers (the same orbital rotation on both spin
+ * sectors, modes 0..d-1 and d..2d-1; the LUCJ orbital rotations of Sec. IV-B), host
+ * FP64, 1 <= d <= 64:
+ *   xf_spin_rotations: rot[l] = exp(K_l) (+) exp(K_l), K host
+ *     [n_layers][d][d][2] anti-Hermitian, rot host [n_layers][2d][2d][2]
+ *     (every entry written).
+ *   xf_spin_rotations_adjoint: G_K[l] = L(K_l^H, G_rot[l][:d, :d] +
+ *     G_rot[l][d:, d:]) (the two blocks' gradients add), G_rot in the layout
+ *     of xf_log_prob_backward's h_grad_rot, G_K [n_layers][d][d][2].
+ * Errors: XF_EINVAL (sizes, NULL, NaN/Inf, K not anti-Hermitian). */
+xf_status xf_spin_rotations(int32_t n_layers, int32_t d, const double *K, double *rot);
+xf_status xf_spin_rotations_adjoint(int32_t n_layers, int32_t d, const double *K, const double *G_rot,
+                                    double *G_K);
+
+/* Gradient with respect to the d^2 real parameters of an anti-Hermitian
+ * generator K -- (Re K_ij) for i < j in row-major order, then (Im K_ij) for
+ * i < j, then Im K_ii -- from G_K = dL/dRe K + i dL/dIm K of the full
+ * matrix (K_ji = -conj(K_ij)).  G_K host [d][d][2], g host [d^2],
+ * 1 <= d <= 128.  Errors: XF_EINVAL. */
+xf_status xf_antihermitian_reals_grad(int32_t d, const double *G_K, double *g);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char *xf_last_error(void);

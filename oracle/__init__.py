@@ -51,7 +51,7 @@ def lib():
         L.xfo_extent.restype = ctypes.c_double
         sig = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P, P,
                ctypes.c_int, ctypes.c_int64, ctypes.c_uint64]
-        L.xfo_probabilities.argtypes = sig + [P, P]
+        L.xfo_probabilities.argtypes = sig + [P, P, P]
         L.xfo_probabilities.restype = ctypes.c_int
         L.xfo_log_prob_grad.argtypes = sig + [P, P, P]
         L.xfo_log_prob_grad.restype = ctypes.c_int
@@ -183,10 +183,11 @@ def _batch_index(batch_index, B):
 
 
 def probabilities(rot, pairs, layer, theta, input_bits, bits, mode="exact", t=0, seed=0,
-                  return_amp=False, theta_sample=None, batch_index=None):
+                  return_amp=False, theta_sample=None, batch_index=None, return_abs_sum=False):
     """Born-rule probabilities p_b (exact, Eq. 8) or Raw Estimate p_hat_b.
     ``theta_sample`` freezes the sampling table at other angles;
-    ``batch_index[b]`` is the index keying bitstring b's samples (default b)."""
+    ``batch_index[b]`` is the index keying bitstring b's samples (default b);
+    ``return_abs_sum`` appends sum_i |w_i det M_i| over the bitstring's terms."""
     rot, n, n_rot, pairs, layer, theta, inp = _circuit_args(rot, pairs, layer, theta, input_bits)
     ts_keep, ts_ptr = _theta_sample(theta_sample)
     bits = _c(bits, np.uint64).reshape(-1, 2)
@@ -194,15 +195,19 @@ def probabilities(rot, pairs, layer, theta, input_bits, bits, mode="exact", t=0,
     bi_keep, bi_ptr = _batch_index(batch_index, B)
     prob = np.zeros(B)
     amp = np.zeros((B, 2))
+    abss = np.zeros(B)
     md = 0 if mode == "exact" else 1
     rc = lib().xfo_probabilities(n, n_rot, _ptr(rot), theta.shape[0], _ptr(pairs), _ptr(layer),
                                  _ptr(theta), ts_ptr, _ptr(inp), B, _ptr(bits), bi_ptr, md, int(t), int(seed),
-                                 _ptr(prob), _ptr(amp))
+                                 _ptr(prob), _ptr(amp), _ptr(abss))
     if rc != 0:
         raise ValueError("oracle: unsupported sizes")
+    out = (prob,)
     if return_amp:
-        return prob, amp[:, 0] + 1j * amp[:, 1]
-    return prob
+        out += (amp[:, 0] + 1j * amp[:, 1],)
+    if return_abs_sum:
+        out += (abss,)
+    return out[0] if len(out) == 1 else out
 
 
 def log_prob_grad(rot, pairs, layer, theta, input_bits, bits, g, mode="exact", t=0, seed=0,
@@ -226,11 +231,12 @@ def log_prob_grad(rot, pairs, layer, theta, input_bits, bits, g, mode="exact", t
     return grot[..., 0] + 1j * grot[..., 1], gth[:theta.shape[0]]
 
 
-def run_workload(w, index=None, mode=None, return_amp=False):
+def run_workload(w, index=None, mode=None, return_amp=False, return_abs_sum=False):
     """Oracle probabilities for a ``workloads.Workload``, optionally for the
     batch positions ``index`` only (their samples keyed by those positions)."""
     rot = w.rot if w.rot is not None else rotations_from_generators(w.gens)
     bits = w.bits if index is None else w.bits[np.asarray(index)]
     return probabilities(rot, w.pairs, w.layer, w.theta, w.input_bits, bits,
                          mode or w.mode, w.t, w.seed, return_amp=return_amp,
-                         batch_index=None if index is None else np.asarray(index))
+                         batch_index=None if index is None else np.asarray(index),
+                         return_abs_sum=return_abs_sum)

@@ -376,13 +376,15 @@ static int build_terms(const circuit *c, int mode, int64_t t, uint64_t seed, uin
  * what a derivative of the estimator with respect to theta differentiates.
  * batch_index (nullable) gives the index that keys bitstring b's samples
  * (default b), so a subset of a larger batch can be recomputed.
- * prob[B], amp[B][2] (nullable).  Returns 0, or -1 on unsupported sizes.
+ * prob[B], amp[B][2] (nullable), abssum[B] (nullable): the sum of the terms'
+ * magnitudes, sum_i |w_i det M_i|, whose ratio to |A_b| measures how much the
+ * terms cancel.  Returns 0, or -1 on unsupported sizes.
  */
 int xfo_probabilities(int n, int n_rot, const double *rot, int k, const int *pairs,
                       const int *layer, const double *theta, const double *theta_sample,
                       const uint64_t *input_bits, int64_t B, const uint64_t *bits,
                       const uint64_t *batch_index, int mode, int64_t t, uint64_t seed,
-                      double *prob, double *amp)
+                      double *prob, double *amp, double *abssum)
 {
     if (n < 1 || n > 128 || n_rot < 1 || k < 0 || (mode == 0 && k > 24) || (mode == 1 && (k > 128 || t < 1)))
         return -1;
@@ -411,6 +413,7 @@ int xfo_probabilities(int n, int n_rot, const double *rot, int k, const int *pai
         int R[128];
         int mb = occupied(bits + 2 * b, n, R);
         cplx A = 0.0;
+        double S = 0.0;
         if (mb == m) {
             term *ts;
             int nt = build_terms(&c, mode, t, seed, batch_index ? batch_index[b] : (uint64_t)b, T, sqrt_xi, &ts);
@@ -426,11 +429,13 @@ int xfo_probabilities(int n, int n_rot, const double *rot, int k, const int *pai
                 int sing;
                 cplx det = (m == 0) ? 1.0 : lu_factor(M, m, perm, &sing);
                 A += ts[i].w * det;
+                S += cabs(ts[i].w * det);
             }
             free(Y); free(M); free(perm); free(ts);
         }
         prob[b] = creal(A) * creal(A) + cimag(A) * cimag(A);
         if (amp) { amp[2 * b] = creal(A); amp[2 * b + 1] = cimag(A); }
+        if (abssum) abssum[b] = S;
     }
     free(Ycache);
     free(T);

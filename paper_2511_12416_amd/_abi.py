@@ -42,7 +42,8 @@ EXPORTS = ["xf_plan_create", "xf_plan_set_params", "xf_plan_refreeze", "xf_plan_
            "xf_extent", "xf_trajectory_bound", "xf_probabilities", "xf_probabilities_noalloc",
            "xf_log_prob_backward",
            "xf_plan_last_term_count", "xf_plan_last_work", "xf_plan_set_evaluation", "xf_plan_set_workspace_limit", "xf_plan_set_mixed_condition",
-           "xf_expm_antihermitian", "xf_expm_adjoint", "xf_last_error"]
+           "xf_expm_antihermitian", "xf_expm_adjoint", "xf_spin_rotations", "xf_spin_rotations_adjoint",
+           "xf_antihermitian_reals_grad", "xf_last_error"]
 
 _lib = None
 
@@ -79,6 +80,9 @@ def lib() -> ctypes.CDLL:
     L.xf_plan_set_mixed_condition.argtypes = [P, D]
     L.xf_expm_antihermitian.argtypes = [I32, P, P]
     L.xf_expm_adjoint.argtypes = [I32, P, P, P]
+    L.xf_spin_rotations.argtypes = [I32, I32, P, P]
+    L.xf_spin_rotations_adjoint.argtypes = [I32, I32, P, P, P]
+    L.xf_antihermitian_reals_grad.argtypes = [I32, P, P]
     L.xf_last_error.argtypes = []
     L.xf_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:

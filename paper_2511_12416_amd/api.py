@@ -219,13 +219,32 @@ def expm_adjoint(K, G_U) -> np.ndarray:
 
 
 def spin_rotations(gens) -> np.ndarray:
-    """Layers exp(K_l) (+) exp(K_l) for anti-Hermitian generators K_l."""
-    out = []
-    for K in gens:
-        U = expm_antihermitian(K)
-        d = U.shape[0]
-        R = np.zeros((2 * d, 2 * d), np.complex128)
-        R[:d, :d] = U
-        R[d:, d:] = U
-        out.append(R)
-    return np.stack(out)
+    """Layers exp(K_l) (+) exp(K_l) for anti-Hermitian generators K_l
+    ([n_layers, d, d] complex), through xf_spin_rotations."""
+    Kh = _complex_host(gens)
+    nl, d = Kh.shape[0], Kh.shape[1]
+    R = np.zeros((nl, 2 * d, 2 * d, 2))
+    check(lib().xf_spin_rotations(nl, d, _ptr(Kh), _ptr(R)))
+    return R[..., 0] + 1j * R[..., 1]
+
+
+def spin_rotations_adjoint(gens, G_rot) -> np.ndarray:
+    """dL/dRe K_l + i dL/dIm K_l of every generator from the gradient of the
+    layers exp(K_l) (+) exp(K_l), through xf_spin_rotations_adjoint."""
+    Kh = _complex_host(gens)
+    Gh = _complex_host(G_rot)
+    nl, d = Kh.shape[0], Kh.shape[1]
+    GK = np.zeros((nl, d, d, 2))
+    check(lib().xf_spin_rotations_adjoint(nl, d, _ptr(Kh), _ptr(Gh), _ptr(GK)))
+    return GK[..., 0] + 1j * GK[..., 1]
+
+
+def antihermitian_reals_grad(G_K) -> np.ndarray:
+    """Gradient with respect to the d^2 real parameters of an anti-Hermitian
+    K ((Re K_ij, Im K_ij) for i < j, then Im K_ii), through
+    xf_antihermitian_reals_grad."""
+    Gh = _complex_host(G_K)
+    d = Gh.shape[0]
+    g = np.zeros(d * d)
+    check(lib().xf_antihermitian_reals_grad(d, _ptr(Gh), _ptr(g)))
+    return g

@@ -2,9 +2,10 @@
 
 ``log_prob`` maps (rotation layers, CPhase angles) to log p_b with its
 backward computed by the library's adjoint kernel; ``spin_rotations`` maps
-anti-Hermitian generators K_l to layers exp(K_l) (+) exp(K_l) with the
-backward of the matrix exponential done by xf_expm_adjoint.  Complex
-gradients follow PyTorch's convention dL/dRe + i dL/dIm.
+anti-Hermitian generators K_l to layers exp(K_l) (+) exp(K_l), forward and
+backward computed by the library (xf_spin_rotations,
+xf_spin_rotations_adjoint).  Complex gradients follow PyTorch's convention
+dL/dRe + i dL/dIm.
 """
 from __future__ import annotations
 
@@ -53,9 +54,7 @@ class _SpinRotations(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g_rot):
-        G = g_rot.detach().cpu().numpy()
-        d = ctx.K.shape[1]
-        out = np.stack([api.expm_adjoint(ctx.K[l], G[l, :d, :d] + G[l, d:, d:]) for l in range(G.shape[0])])
+        out = api.spin_rotations_adjoint(ctx.K, g_rot.detach().cpu().numpy())
         return torch.from_numpy(out).to(dtype=g_rot.dtype, device=g_rot.device)
 
 
@@ -66,10 +65,6 @@ def spin_rotations(gens: torch.Tensor) -> torch.Tensor:
 
 def generator_reals_grad(G_K: np.ndarray) -> np.ndarray:
     """Gradient with respect to the real parameters of an anti-Hermitian K
-    ((Re K_ij, Im K_ij) for i < j, then Im K_ii), from dL/dRe K + i dL/dIm K of
-    the full matrix (K_ji = -conj(K_ij))."""
-    d = G_K.shape[0]
-    iu = np.triu_indices(d, 1)
-    re = G_K[iu].real - G_K.T[iu].real
-    im = G_K[iu].imag + G_K.T[iu].imag
-    return np.concatenate([re, im, np.diagonal(G_K).imag])
+    ((Re K_ij, Im K_ij) for i < j, then Im K_ii) from dL/dRe K + i dL/dIm K of
+    the full matrix (xf_antihermitian_reals_grad)."""
+    return api.antihermitian_reals_grad(G_K)

@@ -163,12 +163,22 @@ __device__ __forceinline__ void cgemm_mfma(int M, int N, int K, FA a_at, FB b_at
     }
 }
 
+// Value of v in lane `src` (wave-uniform) for every lane.
+__device__ __forceinline__ double read_lane_d(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double2 read_lane_c(double2 v, int src) {
+    return make_double2(read_lane_d(v.x, src), read_lane_d(v.y, src));
+}
+
 // Per-bitstring shared state of the general kernels.
 struct GenShared {
     int ok;                        // row counts / base status
     int piv[kGenMaxM];             // pivot row of each column (Gauss-Jordan)
     double2 uinv[kGenMaxM];        // 1 / pivot
-    double2 l[kGenMaxM];           // multipliers of the current step
     double2 det;                   // product of the blocks' det M_0
     double norm;                   // ||M_0||_1 of the current block
     double kappa;                  // kappa_1(M_0) of the current block
@@ -187,7 +197,7 @@ __device__ __forceinline__ void gen_rows(const DevPlan &p, const GenPlan &g, con
         sh.ok = 1;
         for (int r = 0; r < p.m; ++r) {
             const int q = Rb[r];
-            const int blk = g.blk[q];
+            const int blk = (int)((g.bmask[1][q >> 6] >> (q & 63)) & 1);
             if (sh.nrow[blk] < kGenMaxM) sh.rows[blk][sh.nrow[blk]] = (uint8_t)q;
             ++sh.nrow[blk];
         }
@@ -262,55 +272,67 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
         for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
         if (lane == 0) sh.norm = cs;
     }
-    uint64_t used = 0;          // wave 0: rows already used as pivots
-    unsigned inversions = 0;    // wave 0
-    double2 det = make_double2(1.0, 0.0);   // wave 0
+    // Elimination: every wave finds the pivot of column c itself (the same
+    // reduction over the same values gives the same row in all waves), so one
+    // barrier per column suffices; lane j - c - 1 of every wave updates column
+    // j > c in the wave's rows (wave, wave + 4, ...), the multipliers coming
+    // from the lanes that read column c.
+    __syncthreads();   // the norm has been read
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr int NW = kThreads / 64;
+    uint64_t used = 0;          // rows already used as pivots
+    unsigned inversions = 0;
+    double2 det = make_double2(1.0, 0.0);
     bool singular = false;
     for (int c = 0; c < m; ++c) {
-        if (tid < 64) {
-            const bool act_row = lane < m && !((used >> lane) & 1);
-            const double v = act_row ? cabs2(W[lane * ld + c]) : -1.0;
-            double best = v;
-            int idx = lane;
+        const double2 a = lane < m ? W[lane * ld + c] : make_double2(0.0, 0.0);
+        const bool act_row = lane < m && !((used >> lane) & 1);
+        double best = act_row ? cabs2(a) : -1.0;
+        int idx = lane;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double vo = __shfl_xor(best, off, 64);
-                const int io = __shfl_xor(idx, off, 64);
-                if (vo > best || (vo == best && io < idx)) {
-                    best = vo;
-                    idx = io;
-                }
-            }
-            if (best > 0.0) {
-                inversions += __popcll(~used & ((1ull << idx) - 1) & ((1ull << m) - 1));
-                used |= 1ull << idx;
-                const double2 u = W[idx * ld + c];
-                det = c_mul(det, u);
-                if (lane == 0) {
-                    sh.piv[c] = idx;
-                    const double inv = 1.0 / best;
-                    sh.uinv[c] = make_double2(u.x * inv, -u.y * inv);
-                }
-            } else if (lane == 0) {
-                sh.piv[c] = -1;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double vo = __shfl_xor(best, off, 64);
+            const int io = __shfl_xor(idx, off, 64);
+            if (vo > best || (vo == best && io < idx)) {
+                best = vo;
+                idx = io;
             }
         }
-        __syncthreads();
-        const int pr = sh.piv[c];
-        if (pr < 0) {
-            singular = true;   // exactly singular base
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        best = read_lane_d(best, 0);
+        if (!(best > 0.0)) {
+            singular = true;   // exactly singular base (the same decision in every wave)
             break;
         }
-        const double2 ui = sh.uinv[c];
-        if (tid < m && tid != pr) {
-            const double2 a = W[tid * ld + c];
-            sh.l[tid] = make_double2(-(a.x * ui.x - a.y * ui.y), -(a.x * ui.y + a.y * ui.x));
+        inversions += __popcll(~used & ((1ull << idx) - 1) & ((1ull << m) - 1));
+        used |= 1ull << idx;
+        const double2 u = read_lane_c(a, idx);
+        det = c_mul(det, u);
+        const double inv = 1.0 / best;
+        const double2 ui = make_double2(u.x * inv, -u.y * inv);
+        if (tid == 0) {
+            sh.piv[c] = idx;
+            sh.uinv[c] = ui;
         }
-        __syncthreads();
-        const int w = ld - c - 1;
-        for (int e = tid; e < m * w; e += kThreads) {
-            const int i = e / w, j = c + 1 + e % w;
-            if (i != pr) W[i * ld + j] = c_fma(W[i * ld + j], sh.l[i], W[pr * ld + j]);
+        const double2 l = (lane < m && lane != idx)
+                              ? make_double2(-(a.x * ui.x - a.y * ui.y), -(a.x * ui.y + a.y * ui.x))
+                              : make_double2(0.0, 0.0);
+        const int j = c + 1 + lane;
+        const bool jin = j < ld;
+        const double2 pv = jin ? W[idx * ld + j] : make_double2(0.0, 0.0);
+        double2 v[kGenMaxM / NW];
+#pragma unroll
+        for (int q = 0; q < kGenMaxM / NW; ++q) {
+            const int i = wave + NW * q;
+            v[q] = (jin && i < m) ? W[i * ld + j] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < kGenMaxM / NW; ++q) {
+            const int i = wave + NW * q;
+            if (i < m) {
+                const double2 li = read_lane_c(l, i);
+                if (jin && i != idx) W[i * ld + j] = c_fma(v[q], li, pv);
+            }
         }
         __syncthreads();
     }

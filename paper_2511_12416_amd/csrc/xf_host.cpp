@@ -1151,4 +1151,63 @@ xf_status xf_expm_adjoint(int32_t n, const double *K, const double *G_U, double 
     return ok();
 }
 
+xf_status xf_spin_rotations(int32_t n_layers, int32_t d, const double *K, double *rot) {
+    if (n_layers < 1 || d < 1 || d > 64) return fail(XF_EINVAL, "need n_layers >= 1 and 1 <= d <= 64");
+    if (!K || !rot) return fail(XF_EINVAL, "NULL pointer");
+    const int n = 2 * d;
+    std::vector<double> U((size_t)d * d * 2);
+    for (int l = 0; l < n_layers; ++l) {
+        xf_status st = xf_expm_antihermitian(d, K + (size_t)l * d * d * 2, U.data());
+        if (st != XF_OK) return st;
+        double *R = rot + (size_t)l * n * n * 2;
+        std::fill(R, R + (size_t)n * n * 2, 0.0);
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j)
+                for (int h = 0; h < 2; ++h) {
+                    const size_t o = (size_t)(h * d + i) * n + (h * d + j);
+                    R[2 * o] = U[2 * ((size_t)i * d + j)];
+                    R[2 * o + 1] = U[2 * ((size_t)i * d + j) + 1];
+                }
+    }
+    return ok();
+}
+
+xf_status xf_spin_rotations_adjoint(int32_t n_layers, int32_t d, const double *K, const double *G_rot,
+                                    double *G_K) {
+    if (n_layers < 1 || d < 1 || d > 64) return fail(XF_EINVAL, "need n_layers >= 1 and 1 <= d <= 64");
+    if (!K || !G_rot || !G_K) return fail(XF_EINVAL, "NULL pointer");
+    const int n = 2 * d;
+    std::vector<double> G((size_t)d * d * 2);
+    for (int l = 0; l < n_layers; ++l) {
+        // the layer's two diagonal blocks are the same U = exp(K_l): their
+        // gradients add
+        const double *Gr = G_rot + (size_t)l * n * n * 2;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j)
+                for (int c = 0; c < 2; ++c)
+                    G[2 * ((size_t)i * d + j) + c] = Gr[2 * ((size_t)i * n + j) + c] +
+                                                     Gr[2 * ((size_t)(d + i) * n + (d + j)) + c];
+        xf_status st = xf_expm_adjoint(d, K + (size_t)l * d * d * 2, G.data(), G_K + (size_t)l * d * d * 2);
+        if (st != XF_OK) return st;
+    }
+    return ok();
+}
+
+xf_status xf_antihermitian_reals_grad(int32_t d, const double *G_K, double *g) {
+    if (d < 1 || d > 128) return fail(XF_EINVAL, "d must be in [1, 128]");
+    if (!G_K || !g) return fail(XF_EINVAL, "NULL pointer");
+    if (!finite_all(G_K, (size_t)d * d * 2)) return fail(XF_EINVAL, "G_K contains NaN/Inf");
+    // K_ij = a + i b and K_ji = -a + i b for i < j; K_ii = i c
+    const size_t np = (size_t)d * (d - 1) / 2;
+    size_t q = 0;
+    for (int i = 0; i < d; ++i)
+        for (int j = i + 1; j < d; ++j, ++q) {
+            const size_t ij = 2 * ((size_t)i * d + j), ji = 2 * ((size_t)j * d + i);
+            g[q] = G_K[ij] - G_K[ji];
+            g[np + q] = G_K[ij + 1] + G_K[ji + 1];
+        }
+    for (int i = 0; i < d; ++i) g[2 * np + i] = G_K[2 * ((size_t)i * d + i) + 1];
+    return ok();
+}
+
 }  // extern "C"

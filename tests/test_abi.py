@@ -61,6 +61,58 @@ def test_expm_and_adjoint(xf):
         np.testing.assert_allclose(xf.expm_adjoint(K, G), oracle.expm_adjoint(K, G), atol=1e-12)
 
 
+def test_spin_rotations_and_their_adjoint(xf):
+    """exp(K) (+) exp(K) per layer, and its adjoint against central finite
+    differences of L = Re sum conj(G) * R(K) along every anti-Hermitian
+    direction E of every layer (dL = Re sum conj(G_K) * E)."""
+    rng = np.random.default_rng(6)
+    d, nl = 3, 2
+    K = np.stack([W.anti_hermitian(rng, d, 0.4) for _ in range(nl)])
+    R = xf.spin_rotations(K)
+    for l in range(nl):
+        np.testing.assert_allclose(R[l], W.block_diag2(oracle.expm(K[l])), atol=1e-13)
+    G = rng.standard_normal((nl, 2 * d, 2 * d)) + 1j * rng.standard_normal((nl, 2 * d, 2 * d))
+    GK = xf.spin_rotations_adjoint(K, G)
+    loss = lambda KK: float(np.sum((np.conj(G) * xf.spin_rotations(KK)).real))
+    h = 1e-6
+    for l in range(nl):
+        for i in range(d):
+            for j in range(i, d):
+                for unit in ((1.0, 1j) if i < j else (1j,)):
+                    E = np.zeros_like(K)
+                    E[l, i, j] += unit
+                    E[l, j, i] -= np.conj(unit)
+                    fd = (loss(K + h * E) - loss(K - h * E)) / (2 * h)
+                    ref = float(np.sum((np.conj(GK) * E).real))
+                    assert abs(fd - ref) < 1e-7, (l, i, j, unit, fd, ref)
+
+
+def test_antihermitian_reals_grad(xf):
+    """d/d(real parameters) of L = Re sum conj(G) * K(params) by central
+    finite differences, K built from (Re K_ij, Im K_ij) for i < j and Im K_ii."""
+    rng = np.random.default_rng(7)
+    d = 4
+    G = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    iu = np.triu_indices(d, 1)
+    npair = len(iu[0])
+
+    def build(x):
+        K = np.zeros((d, d), np.complex128)
+        K[iu] = x[:npair] + 1j * x[npair:2 * npair]
+        K = K - K.conj().T
+        K[np.diag_indices(d)] = 1j * x[2 * npair:]
+        return K
+
+    x0 = rng.standard_normal(d * d)
+    g = xf.antihermitian_reals_grad(G)
+    loss = lambda x: float(np.sum((np.conj(G) * build(x)).real))
+    for q in range(d * d):
+        e = np.zeros(d * d)
+        e[q] = 1e-6
+        fd = (loss(x0 + e) - loss(x0 - e)) / 2e-6
+        assert abs(fd - g[q]) < 1e-8, (q, fd, g[q])
+
+
 def test_expm_rejects_non_antihermitian(xf):
     with pytest.raises(xf.XfError) as e:
         xf.expm_antihermitian(np.array([[1.0, 0.0], [0.0, 0.0]]))

@@ -101,6 +101,25 @@ def test_no_cphase_is_single_slater_overlap():
     np.testing.assert_allclose(_exact(w), ref, atol=1e-14)
 
 
+def test_term_magnitude_sum():
+    """sum_i |w_i det M_i| (the cancellation measure reported beside the
+    errors): the single term's |det| = sqrt(p) without CPhase gates, |A| when
+    every sampled term is the same (all angles zero), never below |A|."""
+    w = W.random_circuit(21, 9, 4, 0, n_rot=3)
+    p, a, s = oracle.probabilities(w.rot, w.pairs, w.layer, w.theta, w.input_bits, w.bits, "exact",
+                                   return_amp=True, return_abs_sum=True)
+    np.testing.assert_allclose(s, np.sqrt(p), rtol=1e-13, atol=1e-15)
+    w = W.random_circuit(25, 8, 4, 5, n_rot=2, theta_scale=1.0)
+    p, a, s = oracle.probabilities(w.rot, w.pairs, w.layer, np.zeros(5), w.input_bits, w.bits, "approx",
+                                   t=64, seed=3, return_amp=True, return_abs_sum=True)
+    np.testing.assert_allclose(s, np.abs(a), rtol=1e-12, atol=1e-15)
+    for mode, t in (("exact", 0), ("approx", 200)):
+        p, a, s = oracle.probabilities(w.rot, w.pairs, w.layer, w.theta, w.input_bits, w.bits, mode,
+                                       t=t, seed=4, return_amp=True, return_abs_sum=True)
+        assert np.all(s >= np.abs(a) * (1 - 1e-12))
+        assert np.any(s > np.abs(a) * 1.01)
+
+
 def test_zero_angle_gate_is_identity():
     w = W.random_circuit(22, 7, 3, 4, n_rot=2, theta_scale=1.0)
     th = w.theta.copy()
