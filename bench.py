@@ -211,8 +211,9 @@ def run_extras(X, W, args, dev):
     out = torch.empty(w.B, dtype=torch.float64, device=dev)
     lp = torch.empty(w.B, dtype=torch.float64, device=dev)
     d = {"workload": w.name}
+    rot = w.rot if w.rot is not None else X.spin_rotations(w.gens)
     for prec in ("fp64", "mixed"):
-        plan = X.Plan(w.rot, w.pairs, w.layer, w.theta, w.input_bits, prec, device=0)
+        plan = X.Plan(rot, w.pairs, w.layer, w.theta, w.input_bits, prec, device=0)
         steps = max(3, args.steps)
         for _ in range(args.warmup):
             plan.probabilities(bits, "approx", w.t, w.seed, out=out, logp=lp)
@@ -247,6 +248,9 @@ def main() -> int:
                     help="approximate wall time of each oracle baseline sample")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="after the timed region, one device-to-device copy of this many MiB (the "
+                         "reference kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the path shards by "
@@ -281,6 +285,15 @@ def main() -> int:
                                                        "p99": float(np.quantile(kap, 0.99)),
                                                        "max": float(kap.max())}
 
+    if args.calibrate_copy_mb > 0:
+        nbytes = args.calibrate_copy_mb << 20
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del a, b
     extras = {} if args.no_extras else run_extras(X, W, args, dev)
     base = None if args.no_cpu else cpu_baseline(5, args.cpu_seconds)
     m = res["mixed"]

@@ -212,12 +212,14 @@ __device__ __forceinline__ void gen_rows(const DevPlan &p, const GenPlan &g, con
 // base pattern, empty at first) is inverted by Gauss-Jordan (augmented rows
 // [M_B | I] in the setup scratch W, row stride 2m; rows stay in place, row
 // piv[c] ends as u_c e_c | u_c M_B^-1[c, :]) and checked for conditioning;
-// then X = M_B^-1 U and H = V X.  For one CPhase layer a singular or
-// ill-conditioned M_0 is replaced by M_{N*} with N* the flips of one gate
-// (the first few gates touching the block are tried in turn): with
-// Delta = N xor N* and sigma = -1 on N* \ N, +1 on N \ N*,
-//   M_N = M_{N*} - 2 U[:, Delta] diag(sigma) V[Delta, :],
-//   det M_N = det M_{N*} det(I - 2 diag(sigma) H[Delta, Delta]).
+// then X = M_B^-1 U and H = V X.  A singular or ill-conditioned M_0 is
+// replaced by M_{N*} with N* the flips of one gate (of layer 0 for two
+// CPhase layers; the first few gates touching the block are tried in turn):
+// with Delta = N xor N* and sigma = -1 on N* \ N, +1 on N \ N*,
+//   M_N = M_{N*} - 2 U[:, Delta] diag(sigma) V_N[Delta, :],
+//   det M_N = det M_{N*} det(I - 2 diag(sigma) V_N[Delta, :] M_{N*}^-1 U[:, Delta]),
+// where for two layers the layer-1 rows of V_N carry the pattern's own
+// layer-0 flips N0 (N* has none in layer 1, so those rows keep sigma = +1).
 // Returns false if no base was acceptable (kappa_1 > kLemmaMaxCond or
 // singular).  Whole workgroup.
 constexpr int kGenBaseTries = 4;
@@ -362,13 +364,13 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
     }
     __syncthreads();
     if (!singular && sh.ok == 1) break;
-    // next base: the next gate whose flips touch this block (one CPhase layer)
-    if (p.L != 1 || attempt + 1 >= kGenBaseTries) return false;
+    // next base: the next gate whose flips touch this block (of layer 0 for
+    // two CPhase layers)
+    if (attempt + 1 >= kGenBaseTries) return false;
+    auto touches = [&](uint16_t v) { return v != kNoPos && (v >> 8) == blk && (p.L == 1 || (v & 0xFF) < kb0); };
     do {
         ++gate;
-    } while (gate < p.k && gate < 64 &&
-             !(((g.gpos[2 * gate] >> 8) == blk && g.gpos[2 * gate] != kNoPos) ||
-               ((g.gpos[2 * gate + 1] >> 8) == blk && g.gpos[2 * gate + 1] != kNoPos)));
+    } while (gate < p.k && gate < 64 && !(touches(g.gpos[2 * gate]) || touches(g.gpos[2 * gate + 1])));
     if (gate >= p.k || gate >= 64) return false;
     __syncthreads();
     }
@@ -423,19 +425,28 @@ __device__ __forceinline__ void mask_positions(uint64_t mask, int (&pos)[NP]) {
     }
 }
 
-// Entry (i, j) of S_N in a block (i, j < r; positions pos, r0 of them in
-// layer 0): delta_ij - 2 H[p_i, p_j], with the layer-1 correction for two
-// CPhase layers.
+// Entry (i, j) of S in a block (i, j < r; positions pos of the flips
+// relative to the base pattern N*, r0 of them in layer 0):
+// delta_ij - 2 sigma_i H[p_i, p_j], with, for two CPhase layers, the
+// layer-1 rows corrected by the pattern's own layer-0 flips N0, which are
+// the relative positions with sigma = +1 plus `both` (flipped by the pattern
+// and by the base; the base flips layer-0 modes only).
 template <int NP>
 __device__ __forceinline__ double2 gen_s_entry(bool two_layers, const double2 *H, int hld, const double2 *R1a,
-                                               int kb0, int i, int j, int r0, const int (&pos)[NP], uint64_t neg) {
+                                               int kb0, int i, int j, int r0, const int (&pos)[NP], uint64_t neg,
+                                               uint64_t both) {
     double2 h = H[pos[i] * hld + pos[j]];
     if ((neg >> pos[i]) & 1) h = make_double2(-h.x, -h.y);
     if (two_layers && i >= r0) {
         double2 corr = make_double2(0.0, 0.0);
+        const double2 *r1 = R1a + (pos[i] - kb0) * kb0;
 #pragma unroll
         for (int l = 0; l < NP; ++l)
-            if (l < r0) corr = c_fma(corr, R1a[(pos[i] - kb0) * kb0 + pos[l]], H[pos[l] * hld + pos[j]]);
+            if (l < r0 && !((neg >> pos[l]) & 1)) corr = c_fma(corr, r1[pos[l]], H[pos[l] * hld + pos[j]]);
+        for (uint64_t mm = both; mm; mm &= mm - 1) {
+            const int q = __ffsll((long long)mm) - 1;
+            corr = c_fma(corr, r1[q], H[q * hld + pos[j]]);
+        }
         h.x -= 2.0 * corr.x;
         h.y -= 2.0 * corr.y;
     }
@@ -490,15 +501,16 @@ __device__ __forceinline__ double2 small_det4(double2 (&a)[4][4], int r) {
     return neg ? make_double2(-det.x, -det.y) : det;
 }
 
-// Product over blocks of det S_N for a pattern whose blocks flip at most 4
+// Product over blocks of det S for a pattern whose blocks flip at most 4
 // positions each (one lane); pm already relative to the blocks' base
-// patterns, neg the positions with sigma = -1.
+// patterns (shift): sigma = -1 on shift & pm (flipped by the base only).
 __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan &g, const GenLds &T,
-                                                const uint64_t (&pm)[2], const uint64_t (&neg)[2]) {
+                                                const uint64_t (&pm)[2], const uint64_t (&shift)[2]) {
     double2 det = make_double2(1.0, 0.0);
     for (int blk = 0; blk < g.nblk; ++blk) {
         const int r = __popcll(pm[blk]);
         if (r == 0) continue;
+        const uint64_t neg = shift[blk] & pm[blk], both = shift[blk] & ~pm[blk];
         const int kb0 = g.kb0[blk];
         const int r0 = __popcll(pm[blk] & (kb0 >= 64 ? ~0ull : ((1ull << kb0) - 1)));
         int pos[4];
@@ -511,7 +523,7 @@ __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan 
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 a[i][j] = (i < r && j < r)
-                              ? gen_s_entry<4>(p.L == 2, H, g.hld[blk], R1a, kb0, i, j, r0, pos, neg[blk])
+                              ? gen_s_entry<4>(p.L == 2, H, g.hld[blk], R1a, kb0, i, j, r0, pos, neg, both)
                               : make_double2(i == j ? 1.0 : 0.0, 0.0);
         det = c_mul(det, small_det4(a, r));
     }
@@ -522,12 +534,13 @@ __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan 
 // GS positions each); every lane of the group returns the product.
 template <int GS>
 __device__ __forceinline__ double2 gen_det_group(const DevPlan &p, const GenPlan &g, const GenLds &T,
-                                                 const uint64_t (&pm)[2], const uint64_t (&neg)[2], int lane,
+                                                 const uint64_t (&pm)[2], const uint64_t (&shift)[2], int lane,
                                                  double2 *piv) {
     double2 det = make_double2(1.0, 0.0);
     for (int blk = 0; blk < g.nblk; ++blk) {
         const int r = __popcll(pm[blk]);
         if (r == 0) continue;
+        const uint64_t neg = shift[blk] & pm[blk], both = shift[blk] & ~pm[blk];
         const int kb0 = g.kb0[blk];
         const int r0 = __popcll(pm[blk] & (kb0 >= 64 ? ~0ull : ((1ull << kb0) - 1)));
         int pos[GS];
@@ -537,23 +550,21 @@ __device__ __forceinline__ double2 gen_det_group(const DevPlan &p, const GenPlan
         double2 a[GS];
 #pragma unroll
         for (int j = 0; j < GS; ++j)
-            a[j] = (lane < r && j < r) ? gen_s_entry<GS>(p.L == 2, H, g.hld[blk], R1a, kb0, lane, j, r0, pos, neg[blk])
-                                       : make_double2(j == lane ? 1.0 : 0.0, 0.0);
+            a[j] = (lane < r && j < r)
+                       ? gen_s_entry<GS>(p.L == 2, H, g.hld[blk], R1a, kb0, lane, j, r0, pos, neg, both)
+                       : make_double2(j == lane ? 1.0 : 0.0, 0.0);
         det = c_mul(det, lu_det<GS>(a, r, lane, piv));
     }
     return det;
 }
 
-// A pattern's flipped positions relative to the blocks' base patterns, and
-// the positions where the base flips and the pattern does not (sigma = -1).
+// A pattern's flipped positions relative to the blocks' base patterns
+// (the symmetric difference with the base pattern).
 __device__ __forceinline__ void gen_relative(const uint16_t *kbt, uint64_t key, const uint64_t (&shift)[2],
-                                             uint64_t (&pm)[2], uint64_t (&neg)[2]) {
+                                             uint64_t (&pm)[2]) {
     gen_masks(kbt, key, pm);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        neg[b] = shift[b] & ~pm[b];
-        pm[b] ^= shift[b];
-    }
+    for (int b = 0; b < 2; ++b) pm[b] ^= shift[b];
 }
 
 // Algorithmic FLOPs of one pattern: per block the r x r elimination, the
@@ -593,8 +604,8 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
     if (tid < 16) cnt[tid] = 0;
     __syncthreads();
     for (int e = tid; e < nl; e += kThreads) {
-        uint64_t pm[2], neg[2];
-        gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
+        uint64_t pm[2];
+        gen_relative(T.kbt, s.hkey[e], shift, pm);
         atomicAdd(&cnt[rank_bin(gen_max_rank(pm))], 1);
     }
     __syncthreads();
@@ -609,8 +620,8 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
     }
     __syncthreads();
     for (int e = tid; e < nl; e += kThreads) {
-        uint64_t pm[2], neg[2];
-        gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
+        uint64_t pm[2];
+        gen_relative(T.kbt, s.hkey[e], shift, pm);
         order[atomicAdd(&cnt[8 + rank_bin(gen_max_rank(pm))], 1)] = (uint16_t)e;
     }
     __syncthreads();
@@ -631,19 +642,19 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
     unsigned long long rank = 0, flops = 0;
     for (int i = tid; i < n0; i += kThreads) {
         const int e = order[i];
-        uint64_t pm[2], neg[2];
-        gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
+        uint64_t pm[2];
+        gen_relative(T.kbt, s.hkey[e], shift, pm);
         rank += __popcll(pm[0]) + __popcll(pm[1]);
         flops += gen_pattern_flops(g, p.L == 2, pm);
-        store(e, gen_det_lane(p, g, T, pm, neg));
+        store(e, gen_det_lane(p, g, T, pm, shift));
     }
     {
         const int l8 = tid & 7, g8 = tid >> 3;
         for (int i = n0 + g8; i < n0 + n1; i += kThreads / 8) {
             const int e = order[i];
-            uint64_t pm[2], neg[2];
-            gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
-            const double2 dS = gen_det_group<8>(p, g, T, pm, neg, l8, T.gpiv + g8 * 8);
+            uint64_t pm[2];
+            gen_relative(T.kbt, s.hkey[e], shift, pm);
+            const double2 dS = gen_det_group<8>(p, g, T, pm, shift, l8, T.gpiv + g8 * 8);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (l8 == 0) {
@@ -657,9 +668,9 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
         const int l16 = tid & 15, g16 = tid >> 4;
         for (int i = n0 + n1 + g16; i < n0 + n1 + n2; i += kThreads / 16) {
             const int e = order[i];
-            uint64_t pm[2], neg[2];
-            gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
-            const double2 dS = gen_det_group<16>(p, g, T, pm, neg, l16, T.gpiv + g16 * 16);
+            uint64_t pm[2];
+            gen_relative(T.kbt, s.hkey[e], shift, pm);
+            const double2 dS = gen_det_group<16>(p, g, T, pm, shift, l16, T.gpiv + g16 * 16);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (l16 == 0) {
@@ -673,9 +684,9 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
         const int l32 = tid & 31, g32 = tid >> 5;
         for (int i = n0 + n1 + n2 + g32; i < n0 + n1 + n2 + n3; i += kThreads / 32) {
             const int e = order[i];
-            uint64_t pm[2], neg[2];
-            gen_relative(T.kbt, s.hkey[e], shift, pm, neg);
-            const double2 dS = gen_det_group<32>(p, g, T, pm, neg, l32, T.gpiv + g32 * 32);
+            uint64_t pm[2];
+            gen_relative(T.kbt, s.hkey[e], shift, pm);
+            const double2 dS = gen_det_group<32>(p, g, T, pm, shift, l32, T.gpiv + g32 * 32);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (l32 == 0) {

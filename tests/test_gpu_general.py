@@ -161,3 +161,48 @@ def test_exact_general_defers_ill_conditioned_bases(X):
     p = gpu_probs(plan, X, bits, "exact")
     assert plan.last_work()["general"]
     _check(p, ref, TOL_FP64, "deferred exact")
+
+
+def _ill_conditioned_two_layer_circuit(seed):
+    """Two CPhase layers (n_rot = 3) whose last rotation's row 0 is
+    orthogonal to the columns of D_1(0) R_1 D_0(0) R_0[:, C]: every bitstring
+    with mode 0 occupied has a singular M_0 (every D(0) the diagonal of the
+    empty trajectory)."""
+    rng = W.rng_for(seed)
+    n, eta, k = 10, 4, 6
+    R0, R1 = W.haar_unitary(rng, n), W.haar_unitary(rng, n)
+    pairs = W.random_pairs(rng, n, k)
+    layer = np.array([0, 0, 0, 1, 1, 1], dtype=np.int32)
+    theta = rng.uniform(-1.0, 1.0, k)
+    C = list(range(1, eta + 1))
+    d = [np.ones(n, dtype=np.complex128), np.ones(n, dtype=np.complex128)]
+    for (a, b), th, l in zip(pairs, theta, layer):
+        d[l][a] *= np.exp(0.5j * th)
+        d[l][b] *= np.exp(0.5j * th)
+    Y = (d[1][:, None] * (R1 @ (d[0][:, None] * R0)))[:, C]
+    _, _, vh = np.linalg.svd(Y.T)
+    v = vh[eta:].conj().T[:, 0]
+    Z = np.concatenate([v.conj()[:, None], rng.standard_normal((n, n - 1)) + 1j * rng.standard_normal((n, n - 1))],
+                       axis=1)
+    R2 = np.linalg.qr(Z)[0].conj().T
+    return np.stack([R0, R1, R2]), pairs, layer, theta, W.bits_from_modes(C), n, eta
+
+
+@pytest.mark.parametrize("mode", ["exact", "approx"])
+def test_two_layer_bases_shift_past_singular_ones(X, mode):
+    """Two CPhase layers, M_0 exactly singular for every bitstring with mode 0
+    occupied: those bitstrings take a base shifted by a layer-0 gate (the
+    layer-1 rows of S then carry the pattern's own layer-0 flips), and match
+    the oracle like the others."""
+    say(f"two-layer base shift, {mode}")
+    rot, pairs, layer, theta, inp, n, eta = _ill_conditioned_two_layer_circuit(808)
+    bits = W.all_fixed_weight(n, eta)
+    t, smp = (3000, 17) if mode == "approx" else (0, 0)
+    ref = oracle.probabilities(rot, pairs, layer, theta, inp, bits, mode, t=t, seed=smp)
+    plan = X.Plan(rot, pairs, layer, theta, inp)
+    p = gpu_probs(plan, X, bits, mode, t, smp)
+    assert plan.last_work()["general"]
+    zero0 = np.array([(int(b[0]) & 1) == 1 for b in bits])
+    assert zero0.sum() > 10
+    _check(p[zero0], ref[zero0], TOL_FP64, f"{mode} mode-0 occupied")
+    _check(p, ref, TOL_FP64, f"{mode} all")
