@@ -31,12 +31,14 @@
  *   Table T[a][j] (0 <= a <= j < k) = min(floor(2^32 * (1 - S)), 2^32 - 1) with
  *   S = prod_{i=a..j} (1 - p_i) accumulated left to right in IEEE FP64 without
  *   fused multiply-add.  Sample s of the bitstring with batch index i starts at
- *   a = 0; the d-th draw u_d (d = 0, 1, ...) is word (d mod 4) of
- *   Philox4x32-10 (Salmon et al., SC'11) with counter
- *   (s, d div 4, lo32(i), hi32(i)) and key (lo32(seed), hi32(seed)).  While
- *   a < k: draw u; the next gate with x_j = 1 is the smallest j >= a with
- *   u < T[a][j]; if there is none the sample ends, otherwise set x_j = 1 and
- *   continue at a = j + 1.
+ *   a = 0 and draws u_0, u_1, ... from Philox4x32-10 (Salmon et al., SC'11)
+ *   with key (lo32(seed), hi32(seed)): u_0 is word (s mod 4) of the block with
+ *   counter (s div 4, 2^32 - 1, lo32(i), hi32(i)) (so one block gives the
+ *   first draws of four consecutive samples), and u_d for d >= 1 is word
+ *   ((d-1) mod 4) of the block with counter (s, (d-1) div 4, lo32(i),
+ *   hi32(i)).  While a < k: draw the next u; the next gate with x_j = 1 is
+ *   the smallest j >= a with u < T[a][j]; if there is none the sample ends,
+ *   otherwise set x_j = 1 and continue at a = j + 1.
  *
  * Conventions for every call:
  *   - Complex numbers are interleaved (re, im) doubles; matrices row-major.
@@ -182,6 +184,33 @@ xf_status xf_probabilities(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, x
 xf_status xf_probabilities_noalloc(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, xf_mode mode,
                                    int64_t t, uint64_t seed, double *d_prob, double *d_amp,
                                    double *d_logp, void *hip_stream);
+
+/* Estimate (Sec. III-A): Raw Estimate probabilities to additive error eps
+ * with failure probability at most delta per bitstring, without a bound
+ * p_max on the probability.  The paper names the algorithm (start from loose
+ * error and probability bounds, then call Raw Estimate repeatedly, after
+ * Pashayan et al.) without giving its schedule; this library's is:
+ *   p_max_b = 1 for every bitstring; for i = 1, 2, ...:
+ *     eps_i = max(eps, 2^-i), delta_i = delta 2^-i;
+ *     t_b = Eq. 6 at (eps_i, delta_i, p_max_b, xi*) (xf_trajectory_bound),
+ *       rounded up to at most four significant bits (the smallest m 2^e >= t_b
+ *       with m < 16);
+ *     the bitstrings are ordered by t_b (ties by batch index) and each run of
+ *       equal t_b is one Raw Estimate call (xf_probabilities) with t_b
+ *       samples and seed (seed + i - 1) mod 2^64, a bitstring's samples keyed
+ *       by its position in the run;
+ *     if eps_i = eps these estimates are the result; otherwise
+ *       p_max_b = min(p_max_b, 1, p_hat_b + eps_i).
+ *   Each later bound holds when the earlier estimates were within their
+ *   eps_i, and sum_i delta_i < delta.
+ *   d_bits  device [B] xf_bits128;  d_prob  device [B] doubles (p_hat_b)
+ *   h_t     host [B] int64: the last iteration's t_b, or NULL
+ *   h_iterations  host int32: the number of iterations, or NULL
+ * Requires 0 < eps < 1, 0 < delta < 1 (XF_EINVAL); XF_EUNSUPPORTED if some
+ * t_b reaches 2^31 or Raw Estimate is unsupported for the plan.  Allocates
+ * device memory for the grouped batch and synchronises hip_stream. */
+xf_status xf_estimate(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, double eps, double delta,
+                      uint64_t seed, double *d_prob, int64_t *h_t, int32_t *h_iterations, void *hip_stream);
 
 /* Gradient of L = sum_b g_b log p_b, g = d_grad_logp (device [B] doubles),
  * with respect to every rotation entry (h_grad_rot, host [n_rot][n][n][2],

@@ -231,6 +231,45 @@ def log_prob_grad(rot, pairs, layer, theta, input_bits, bits, g, mode="exact", t
     return grot[..., 0] + 1j * grot[..., 1], gth[:theta.shape[0]]
 
 
+def round_to_four_bits(t: int) -> int:
+    """The smallest integer >= t of the form m * 2^e with m < 16."""
+    e = max(0, t.bit_length() - 4)
+    return -(-t // (1 << e)) << e
+
+
+def estimate(rot, pairs, layer, theta, input_bits, bits, eps, delta, seed=0):
+    """Estimate (Sec. III-A): repeated Raw Estimate calls that tighten each
+    bitstring's probability bound.  The paper names the algorithm without a
+    schedule; this one halves the error target each round
+    (eps_i = max(eps, 2^-i)), spends delta_i = delta 2^-i of the failure
+    budget, takes t_b from Eq. 6 at the current bound p_max_b (rounded up to
+    four significant bits), runs Raw Estimate once per distinct t_b over the
+    bitstrings with that t_b (ascending batch index, seed + i - 1, samples
+    keyed by the position in that group), and lowers p_max_b to
+    p_hat_b + eps_i until eps_i = eps.  Returns (p_hat, last t_b, rounds)."""
+    bits = np.ascontiguousarray(np.asarray(bits, dtype=np.uint64).reshape(-1, 2))
+    B = bits.shape[0]
+    xi = extent(theta)
+    p_max = np.ones(B)
+    p_hat = np.zeros(B)
+    t_b = np.zeros(B, dtype=np.int64)
+    i = 0
+    while True:
+        i += 1
+        eps_i = max(eps, 2.0 ** -i)
+        delta_i = delta * 2.0 ** -i
+        t_b = np.array([round_to_four_bits(trajectory_bound(eps_i, delta_i, float(pm), xi)) for pm in p_max],
+                       dtype=np.int64)
+        for tv in sorted(set(t_b.tolist())):
+            members = np.nonzero(t_b == tv)[0]   # ascending batch index
+            p_hat[members] = probabilities(rot, pairs, layer, theta, input_bits, bits[members], "approx",
+                                           t=int(tv), seed=(seed + i - 1) % (1 << 64),
+                                           batch_index=np.arange(len(members)))
+        if eps_i == eps:
+            return p_hat, t_b, i
+        p_max = np.minimum(p_max, np.minimum(1.0, p_hat + eps_i))
+
+
 def run_workload(w, index=None, mode=None, return_amp=False, return_abs_sum=False):
     """Oracle probabilities for a ``workloads.Workload``, optionally for the
     batch positions ``index`` only (their samples keyed by those positions)."""

@@ -71,16 +71,19 @@ void xfo_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* The d-th uniform 32-bit draw of sample s of bitstring index bidx:
- * word (d mod 4) of Philox4x32-10 with counter (s, d div 4, bidx_lo, bidx_hi)
- * and key (seed_lo, seed_hi). */
+/* The d-th uniform 32-bit draw u_d of sample s of bitstring index bidx,
+ * Philox4x32-10 with key (seed_lo, seed_hi): u_0 is word (s mod 4) of the
+ * block with counter (s div 4, 2^32 - 1, bidx_lo, bidx_hi); u_d for d >= 1
+ * is word ((d-1) mod 4) of the block with counter (s, (d-1) div 4, bidx_lo,
+ * bidx_hi). */
 static uint32_t draw_u32(uint64_t seed, uint64_t bidx, uint32_t s, uint32_t d)
 {
-    uint32_t ctr[4] = { s, d >> 2, (uint32_t)bidx, (uint32_t)(bidx >> 32) };
+    uint32_t ctr[4] = { d == 0 ? s >> 2 : s, d == 0 ? 0xFFFFFFFFu : (d - 1) >> 2,
+                        (uint32_t)bidx, (uint32_t)(bidx >> 32) };
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
     uint32_t out[4];
     xfo_philox4x32_10(ctr, key, out);
-    return out[d & 3];
+    return out[d == 0 ? (s & 3) : ((d - 1) & 3)];
 }
 
 /* ------------------------------------------------------------------------ */

@@ -39,7 +39,7 @@ class Circuit(ctypes.Structure):
 
 
 EXPORTS = ["xf_plan_create", "xf_plan_set_params", "xf_plan_refreeze", "xf_plan_destroy",
-           "xf_extent", "xf_trajectory_bound", "xf_probabilities", "xf_probabilities_noalloc",
+           "xf_extent", "xf_trajectory_bound", "xf_probabilities", "xf_probabilities_noalloc", "xf_estimate",
            "xf_log_prob_backward",
            "xf_plan_last_term_count", "xf_plan_last_work", "xf_plan_set_evaluation", "xf_plan_set_workspace_limit", "xf_plan_set_mixed_condition",
            "xf_expm_antihermitian", "xf_expm_adjoint", "xf_spin_rotations", "xf_spin_rotations_adjoint",
@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
     L.xf_trajectory_bound.argtypes = [D, D, D, D, ctypes.POINTER(I64)]
     L.xf_probabilities.argtypes = [P, P, I64, S, I64, U64, P, P, P, P]
     L.xf_probabilities_noalloc.argtypes = [P, P, I64, S, I64, U64, P, P, P, P]
+    L.xf_estimate.argtypes = [P, P, I64, D, D, U64, P, P, P, P]
     L.xf_log_prob_backward.argtypes = [P, P, I64, S, I64, U64, P, P, P, P]
     L.xf_plan_last_term_count.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.xf_plan_last_work.argtypes = [P, ctypes.POINTER(Work)]

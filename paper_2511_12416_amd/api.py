@@ -182,6 +182,25 @@ class Plan:
                                              _stream_handle(self.device)))
         return out
 
+    def estimate(self, bits: torch.Tensor, eps: float, delta: float, seed: int = 0,
+                 out: Optional[torch.Tensor] = None):
+        """Estimate (xf_estimate): p_hat_b within eps of p_b with probability
+        >= 1 - delta each, by Raw Estimate calls that tighten p_max.  Returns
+        (p_hat device tensor, last t per bitstring as a numpy array, number of
+        iterations)."""
+        bits = bits.contiguous()
+        if bits.device != self.device or bits.dtype != torch.int64:
+            raise ValueError("bits must be an int64 tensor on the plan's device")
+        B = bits.shape[0]
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=self.device)
+        tb = np.zeros(max(B, 1), dtype=np.int64)
+        it = ctypes.c_int32()
+        check(lib().xf_estimate(self._h, bits.data_ptr(), B, float(eps), float(delta),
+                                int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(), _ptr(tb), ctypes.byref(it),
+                                _stream_handle(self.device)))
+        return out, tb[:B], it.value
+
     def log_prob_backward(self, bits: torch.Tensor, grad_logp: torch.Tensor, mode: str = "exact",
                           t: int = 0, seed: int = 0):
         """(dL/drot as complex [n_rot, n, n], dL/dtheta [k]) for L = sum_b g_b log p_b."""

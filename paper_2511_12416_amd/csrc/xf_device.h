@@ -674,65 +674,66 @@ __device__ __forceinline__ void clear_table(const RawSmem &s, int *cnt, uint32_t
     st.claimed = 1;
 }
 
-// One trajectory of the product distribution (see the sampler definition in
-// the public header): draws words of Philox blocks (smp, d / 4, b) until no
-// further gate succeeds; r is block 0.  Returns the flip-pattern key, the
-// phase exponent e (i^e, e mod 4) and whether no gate was set.
-__device__ __forceinline__ bool draw_trajectory(const DevPlan &p, const RawSmem &s, uint32_t smp, uint4 r,
-                                                uint32_t blo, uint32_t bhi, uint32_t k0, uint32_t k1,
-                                                uint64_t &key, uint32_t &e) {
-    const int k = p.k;
-    key = 0;
-    e = 0;
-    bool empty = true;
+// The next selected gate from gate a for the uniform draw u (see the
+// sampler definition in the public header): the number of entries <= u of
+// row a of the table (the row is non-decreasing), or -1 when u >= T[a][k-1].
+// The last entry of each 16-wide block, read together with T[a][k-1], picks
+// the block, whose entries are then counted: two dependent LDS round trips
+// instead of a binary search.
+__device__ __forceinline__ int next_gate(const RawSmem &s, int k, int a, uint32_t u) {
     const int kp = s.kpad, nb = kp >> 4;
-    uint32_t blk = 0, d = 0;
-    int a = 0;
-    while (a < k) {
-        if ((d >> 2) != blk) {
-            blk = d >> 2;
-            r = philox10(make_uint4(smp, blk, blo, bhi), k0, k1);
-        }
+    const uint32_t *Ta = s.T + a * kp;
+    const uint32_t tail = Ta[k - 1];
+    int bs = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if (b < nb) bs += Ta[16 * b + 15] <= u ? 1 : 0;
+    if (!(u < tail)) return -1;
+    const uint4 *q = (const uint4 *)(Ta + 16 * bs);
+    const uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+    return 16 * bs + (q0.x <= u) + (q0.y <= u) + (q0.z <= u) + (q0.w <= u) + (q1.x <= u) + (q1.y <= u) +
+           (q1.z <= u) + (q1.w <= u) + (q2.x <= u) + (q2.y <= u) + (q2.z <= u) + (q2.w <= u) + (q3.x <= u) +
+           (q3.y <= u) + (q3.z <= u) + (q3.w <= u);
+}
+
+// The rest of trajectory smp of bitstring (blo, bhi) whose first draw
+// selected gate j0: draws u_1, u_2, ... (word (d - 1) mod 4 of the Philox
+// block with counter (smp, (d - 1) / 4, blo, bhi)) until no further gate is
+// selected.  Returns the flip-pattern key and the phase exponent e (i^e).
+__device__ __forceinline__ void draw_rest(const DevPlan &p, const RawSmem &s, uint32_t smp, int j0, uint32_t blo,
+                                          uint32_t bhi, uint32_t k0, uint32_t k1, uint64_t &key, uint32_t &e) {
+    const int k = p.k;
+    uint64_t g = s.gkey[j0];
+    key = g & ~(1ull << 63);
+    e = 1u + 2u * (uint32_t)(g >> 63);
+    int a = j0 + 1;
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    for (uint32_t d = 0; a < k; ++d) {
+        if ((d & 3) == 0) r = philox10(make_uint4(smp, d >> 2, blo, bhi), k0, k1);
         const uint32_t w = d & 3;
         const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
-        ++d;
-        // The next selected gate is the number of row entries <= u (the row
-        // is non-decreasing); the last entry of each 16-wide block, read
-        // together with T[a][k-1], picks the block, whose entries are then
-        // counted: two dependent LDS round trips instead of a binary search.
-        const uint32_t *Ta = s.T + a * kp;
-        const uint32_t tail = Ta[k - 1];
-        int bs = 0;
-#pragma unroll
-        for (int b = 0; b < 8; ++b)
-            if (b < nb) bs += Ta[16 * b + 15] <= u ? 1 : 0;
-        if (!(u < tail)) break;
-        const uint4 *q = (const uint4 *)(Ta + 16 * bs);
-        const uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
-        const int j = 16 * bs + (q0.x <= u) + (q0.y <= u) + (q0.z <= u) + (q0.w <= u) + (q1.x <= u) +
-                      (q1.y <= u) + (q1.z <= u) + (q1.w <= u) + (q2.x <= u) + (q2.y <= u) + (q2.z <= u) +
-                      (q2.w <= u) + (q3.x <= u) + (q3.y <= u) + (q3.z <= u) + (q3.w <= u);
-        const uint64_t g = s.gkey[j];
+        const int j = next_gate(s, k, a, u);
+        if (j < 0) break;
+        g = s.gkey[j];
         key ^= g & ~(1ull << 63);
         e += 1u + 2u * (uint32_t)(g >> 63);
-        empty = false;
         a = j + 1;
     }
-    return empty;
 }
 
 // Draws trajectories of bitstring b (batch index b) in batches of kBatch
 // samples, reducing each to its flip-pattern key in the LDS hash, until either
 // all t samples are in (returns true) or the next batch could push the table
 // past kFlushAt slots (returns false; that batch is drawn again after the
-// table has been evaluated and cleared).  A batch runs in two phases: every
-// thread takes the first draw of kBatch / NT samples, which decides
-// whether the sample sets any gate at all (u < T[0][k-1]); the indices of the
-// samples that do are queued in LDS, and after the barrier the workgroup
-// draws those trajectories to the end and inserts them, so the long draws
-// are spread over all lanes.  The bound uses the exact count of slots in use
-// plus the batch's non-empty samples, so the stopping points depend only on
-// the samples and every pass over the same bitstring empties the table at the
+// table has been evaluated and cleared).  A batch runs in two phases: the
+// first kBatch / 4 threads each draw the first uniforms of four consecutive
+// samples (one Philox block), which decide whether a sample sets any gate at
+// all (u_0 < T[0][k-1]); those samples are queued in LDS (batch offset), and
+// after the barrier the workgroup draws them to the end (the first draw
+// again, then the rest) and inserts them, so the long draws are spread over
+// all lanes.  The bound uses the exact count of slots in use plus the
+// batch's non-empty samples, so the stopping points depend only on the
+// samples and every pass over the same bitstring empties the table at the
 // same samples.  Counts of the batch's non-empty samples (which are also the
 // queue positions) and of the slots each batch claims live in three rotating
 // LDS counters each (cnt[0..2], cnt[3..5]), read only after the barrier that
@@ -749,19 +750,25 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
     const uint32_t blo = (uint32_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
     const uint32_t any = p.k > 0 ? s.T[p.k - 1] : 0u;   // T[0][k-1]
     int *pend = cnt, *added = cnt + 3;
-    constexpr int SPT = (int)(kBatch / NT);   // samples per thread per batch
-    static_assert(SPT * NT == (int)kBatch, "the batch is a whole number of samples per thread");
+    constexpr int NQ = (int)(kBatch / 4);   // first-draw blocks per batch
+    static_assert(NQ % 64 == 0 && NQ <= NT, "first draws by whole waves");
+    static_assert(kBatch <= 0x10000, "batch offsets fit in 16 bits");
     for (; st.next < t; st.next += kBatch, ++st.j) {
         uint32_t *queue = (st.j & 1) ? (uint32_t *)s.piv : (uint32_t *)s.list;
+        if (tid < NQ) {
+            // u_0 of samples next + 4 tid + w is word w of block (next / 4 + tid, 2^32 - 1)
+            const uint4 r = philox10(make_uint4((st.next >> 2) + (uint32_t)tid, 0xFFFFFFFFu, blo, bhi), k0, k1);
 #pragma unroll
-        for (int q = 0; q < SPT; ++q) {
-            const uint32_t smp = st.next + (uint32_t)(q * NT + tid);
-            const bool hit = smp < t && philox10(make_uint4(smp, 0u, blo, bhi), k0, k1).x < any;
-            const uint64_t ball = __ballot(hit);
-            int at = 0;
-            if (lane == 0 && ball) at = atomicAdd(&pend[st.j % 3], (int)__popcll(ball));
-            at = __shfl(at, 0, 64);
-            if (hit) queue[at + (int)__popcll(ball & ((1ull << lane) - 1))] = smp;
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t off = 4u * (uint32_t)tid + (uint32_t)w;
+                const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
+                const bool hit = st.next + off < t && u < any;
+                const uint64_t ball = __ballot(hit);
+                int at = 0;
+                if (lane == 0 && ball) at = atomicAdd(&pend[st.j % 3], (int)__popcll(ball));
+                at = __shfl(at, 0, 64);
+                if (hit) queue[at + (int)__popcll(ball & ((1ull << lane) - 1))] = off;
+            }
         }
         __syncthreads();
         const int pending = pend[st.j % 3];
@@ -777,10 +784,14 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
         }
         int fresh = 0;
         for (int i = tid; i < pending; i += NT) {
-            const uint32_t smp = queue[i];
+            // the sample's first draw again (the queue keeps its batch offset only)
+            const uint32_t smp = st.next + queue[i];
+            const uint4 r0 = philox10(make_uint4(smp >> 2, 0xFFFFFFFFu, blo, bhi), k0, k1);
+            const uint32_t w0 = smp & 3;
+            const uint32_t u0 = w0 == 0 ? r0.x : (w0 == 1 ? r0.y : (w0 == 2 ? r0.z : r0.w));
             uint64_t key;
             uint32_t e;
-            draw_trajectory(p, s, smp, philox10(make_uint4(smp, 0u, blo, bhi), k0, k1), blo, bhi, k0, k1, key, e);
+            draw_rest(p, s, smp, next_gate(s, p.k, 0, u0), blo, bhi, k0, k1, key, e);
             uint32_t slot = hash_slot(key);
             while (true) {
                 const unsigned long long prev = atomicCAS((unsigned long long *)&s.hkey[slot],

@@ -890,6 +890,100 @@ xf_status xf_probabilities_noalloc(xf_plan *P, const xf_bits128 *d_bits, int64_t
     return probabilities_impl(P, d_bits, B, mode, t, seed, d_prob, d_amp, d_logp, hip_stream, true);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The smallest count >= t with at most four significant bits (m 2^e, m < 16).
+int64_t round_sig4(int64_t t) {
+    if (t < 16) return t;
+    const int e = 63 - __builtin_clzll((uint64_t)t) - 3;
+    const int64_t m = (t + ((int64_t)1 << e) - 1) >> e;
+    return m << e;
+}
+
+struct DevScratch {
+    void *p = nullptr;
+    ~DevScratch() {
+        if (p) hipFree(p);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+xf_status xf_estimate(xf_plan *P, const xf_bits128 *d_bits, int64_t B, double eps, double delta, uint64_t seed,
+                      double *d_prob, int64_t *h_t, int32_t *h_iterations, void *hip_stream) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    if (B < 0) return fail(XF_EINVAL, "B < 0");
+    if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0))
+        return fail(XF_EINVAL, "need 0 < eps < 1 and 0 < delta < 1");
+    if (B > 0 && (!d_bits || !d_prob)) return fail(XF_EINVAL, "d_bits or d_prob is NULL");
+    if (B == 0) {
+        if (h_iterations) *h_iterations = 0;
+        return ok();
+    }
+    DeviceGuard guard(P->device);
+    if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<xf_bits128> hb((size_t)B), gb((size_t)B);
+    if (hipMemcpyAsync(hb.data(), d_bits, (size_t)B * sizeof(xf_bits128), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(XF_EDEVICE, "copy of the bitstrings failed");
+    DevScratch dbits, dprob;
+    if (hipMalloc(&dbits.p, (size_t)B * sizeof(xf_bits128)) != hipSuccess ||
+        hipMalloc(&dprob.p, (size_t)B * sizeof(double)) != hipSuccess)
+        return fail(XF_ENOMEM, "hipMalloc of %lld bitstrings failed", (long long)B);
+    const double xi = extent_of(P->theta);
+    std::vector<double> pmax((size_t)B, 1.0), phat((size_t)B, 0.0), gp((size_t)B);
+    std::vector<int64_t> tb((size_t)B);
+    std::vector<int64_t> order((size_t)B);
+    int it = 0;
+    for (int i = 1;; ++i) {
+        it = i;
+        const double eps_i = std::max(eps, std::ldexp(1.0, -i));
+        const double delta_i = std::ldexp(delta, -i);
+        for (int64_t b = 0; b < B; ++b) {
+            int64_t t;
+            xf_status st = xf_trajectory_bound(eps_i, delta_i, pmax[b], xi, &t);
+            if (st != XF_OK) return st;
+            t = round_sig4(t);
+            if (t >= (int64_t)1 << 31)
+                return fail(XF_EUNSUPPORTED, "Estimate needs t = %lld >= 2^31 trajectories (eps = %g)", (long long)t,
+                            eps_i);
+            tb[b] = t;
+        }
+        for (int64_t b = 0; b < B; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return tb[x] < tb[y]; });
+        for (int64_t j = 0; j < B; ++j) gb[j] = hb[order[j]];
+        if (hipMemcpyAsync(dbits.p, gb.data(), (size_t)B * sizeof(xf_bits128), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            return fail(XF_EDEVICE, "upload of the grouped bitstrings failed");
+        for (int64_t g0 = 0; g0 < B;) {
+            int64_t g1 = g0 + 1;
+            while (g1 < B && tb[order[g1]] == tb[order[g0]]) ++g1;
+            xf_status st = probabilities_impl(P, (const xf_bits128 *)dbits.p + g0, g1 - g0, XF_RAW_ESTIMATE,
+                                              tb[order[g0]], seed + (uint64_t)(i - 1), (double *)dprob.p + g0,
+                                              nullptr, nullptr, hip_stream, false);
+            if (st != XF_OK) return st;
+            g0 = g1;
+        }
+        if (hipMemcpyAsync(gp.data(), dprob.p, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(XF_EDEVICE, "download of the estimates failed");
+        for (int64_t j = 0; j < B; ++j) phat[order[j]] = gp[j];
+        if (eps_i == eps) break;
+        for (int64_t b = 0; b < B; ++b) pmax[b] = std::min(pmax[b], std::min(1.0, phat[b] + eps_i));
+    }
+    if (hipMemcpyAsync(d_prob, phat.data(), (size_t)B * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(XF_EDEVICE, "copy of the results failed");
+    if (h_t) std::copy(tb.begin(), tb.end(), h_t);
+    if (h_iterations) *h_iterations = it;
+    return ok();
+}
+
 xf_status xf_plan_last_term_count(xf_plan *P, int64_t *count, int64_t *rank_sum) {
     if (!count) return fail(XF_EINVAL, "NULL output");
     xf_work w;

@@ -323,6 +323,35 @@ def test_sampler_induced_distribution_is_the_product_distribution():
         assert abs(prob - ref) < 1e-8, (x, prob, ref)
 
 
+def test_sampler_draw_layout():
+    """The counter layout of the uniform draws: u_0 of sample s is word s mod 4
+    of the Philox block (s div 4, 2^32 - 1, i), u_d (d >= 1) word (d-1) mod 4
+    of block (s, (d-1) div 4, i).  Two gates at theta = pi (p = 1/2), walked
+    by hand from the table with draws taken from the rocRAND-pinned Philox."""
+    theta = [math.pi, math.pi]
+    T = oracle.sampler_table(theta).astype(np.int64)
+    seed, bidx, t = 0x1234_5678_9ABC_DEF0, (5 << 32) | 17, 64
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    xs = oracle.sample_trajectories(theta, seed=seed, bidx=bidx, t=t)
+
+    def u(smp, d):
+        if d == 0:
+            return int(oracle.philox4x32_10([smp >> 2, 0xFFFFFFFF, bidx & 0xFFFFFFFF, bidx >> 32], key)[smp & 3])
+        return int(oracle.philox4x32_10([smp, (d - 1) >> 2, bidx & 0xFFFFFFFF, bidx >> 32], key)[(d - 1) & 3])
+
+    for smp in range(t):
+        x, a, d = 0, 0, 0
+        while a < 2:
+            v = u(smp, d)
+            d += 1
+            js = [j for j in range(a, 2) if v < T[a, j]]
+            if not js:
+                break
+            x |= 1 << js[0]
+            a = js[0] + 1
+        assert int(xs[smp, 0]) == x, smp
+
+
 def test_sampler_statistics():
     theta = np.array([0.2, -0.9, 1.5, 3.0, -0.4, 0.05, 2.0, -1.3])
     t = 200_000
