@@ -93,7 +93,8 @@ typedef struct { uint64_t w[2]; } xf_bits128;
  * controlled-phase gates of Sec. III-B (Eq. 7) between consecutive layers. */
 typedef struct {
     int32_t n;              /* modes = qubits, 1 <= n <= 128                                   */
-    int32_t n_rot;          /* rotation layers in time order, 1 <= n_rot <= 3                  */
+    int32_t n_rot;          /* rotation layers in time order, 1 <= n_rot <= 65 (more than 3
+                               needs k <= 63)                                                   */
     const double *rot;      /* host [n_rot][n][n][2]: unitary mode matrices (column convention) */
     int32_t k;              /* CPhase gates (k = 0 requires nothing else)                      */
     const int32_t *pairs;   /* host [k][2]: the two modes of gate j, distinct, in [0, n)        */
@@ -102,6 +103,36 @@ typedef struct {
 } xf_circuit;
 
 typedef struct xf_plan xf_plan;
+
+/* One gate of a circuit given gate by gate (Sec. II-B): a nearest-neighbour
+ * particle-number-conserving matchgate G(A, B) (Eq. 1 with A diagonal, so
+ * that |00> and |11> keep their weight, det A = det B, unitary) on qubits
+ * (q0, q1 = q0 + 1), or a controlled-phase gate diag(1, 1, 1, e^{i theta}) on
+ * two distinct qubits (Sec. III-B). */
+typedef enum { XF_GATE_MATCHGATE = 0, XF_GATE_CPHASE = 1 } xf_gate_kind;
+typedef struct {
+    int32_t kind;       /* xf_gate_kind */
+    int32_t q0, q1;     /* the qubits (= modes) the gate acts on */
+    double theta;       /* CPhase angle, finite, |theta| < 2 pi (ignored for a matchgate) */
+    double g[16][2];    /* matchgate: the 4 x 4 unitary, row-major, basis |x_q0 x_q1> = 00, 01, 10, 11
+                           (ignored for a CPhase gate) */
+} xf_gate;
+
+/* Matchgate ingestion: the layered circuit (xf_circuit) of a gate list in
+ * time order.  Consecutive matchgates multiply into one rotation layer (their
+ * mode matrices, Sec. II-B Eq. 2: the single-particle block of G scaled by
+ * the vacuum phase G[00][00], which is a global phase and dropped; later
+ * gates multiply on the left); consecutive CPhase gates form one CPhase layer
+ * between two rotation layers.  The first and last layers may be the
+ * identity.  With rot == NULL only *n_rot and *k are written (the sizes to
+ * allocate); otherwise rot host [max_rot][n][n][2], pairs [max_k][2],
+ * layer [max_k], theta [max_k] receive the circuit (XF_EINVAL if it needs
+ * more than max_rot layers or max_k gates).  2 <= n <= 128.  Errors:
+ * XF_EINVAL (a gate that is not of the forms above, within 1e-12 on the zero
+ * entries and 1e-10 on unitarity and det A = det B). */
+xf_status xf_circuit_from_gates(int32_t n, int32_t n_gates, const xf_gate *gates, int32_t max_rot, int32_t max_k,
+                                double *rot, int32_t *pairs, int32_t *layer, double *theta, int32_t *n_rot,
+                                int32_t *k);
 
 /* Creates a plan on HIP device `device` for circuit `c` and input occupation
  * `input` (eta = popcount <= 64, all bits below n; the input Slater
@@ -112,8 +143,8 @@ typedef struct xf_plan xf_plan;
  * from the host arrays; they may be freed afterwards.  Validates unitarity of
  * every layer (max |U^H U - I| <= 1e-10).  The trajectory-sampling table is
  * frozen at the angles given here (see xf_plan_refreeze).
- * Errors: XF_EINVAL, XF_EUNSUPPORTED (n > 128, eta > 64, n_rot > 3),
- * XF_ENOMEM, XF_EDEVICE. */
+ * Errors: XF_EINVAL, XF_EUNSUPPORTED (n > 128, eta > 64, n_rot > 65, or
+ * n_rot > 3 with k > 63), XF_ENOMEM, XF_EDEVICE. */
 xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision precision,
                          int device, xf_plan **plan);
 

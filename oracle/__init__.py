@@ -231,6 +231,39 @@ def log_prob_grad(rot, pairs, layer, theta, input_bits, bits, g, mode="exact", t
     return grot[..., 0] + 1j * grot[..., 1], gth[:theta.shape[0]]
 
 
+def circuit_from_gates(n: int, gates):
+    """Layered circuit (rot [n_rot, n, n], pairs, layer, theta) of a gate list
+    in time order (Sec. II-B): a matchgate ("mg", q, G) on qubits (q, q + 1)
+    maps the one-particle state a_c^dag|0> (c in {q, q + 1}; |10> and |01> in
+    the basis |x_q x_{q+1}>) to sum_r U[r, c] a_r^dag|0>, U[r, c] being the
+    matrix element of G between those states divided by the vacuum phase
+    G[00, 00]; the layer's mode matrix is the product of its gates' embedded
+    2 x 2 blocks, later gates on the left.  CPhase gates ("cp", q0, q1, theta)
+    between two runs of matchgates form one CPhase layer."""
+    one = {0: 2, 1: 1}   # basis index of a_q^dag|0> (offset 0) and a_{q+1}^dag|0> (offset 1)
+    layers = [np.eye(n, dtype=np.complex128)]
+    pairs, layer, theta = [], [], []
+    prev_cp = False
+    for g in gates:
+        if g[0] == "cp":
+            if not prev_cp:
+                layers.append(np.eye(n, dtype=np.complex128))
+            pairs.append((g[1], g[2]))
+            layer.append(len(layers) - 2)
+            theta.append(g[3])
+            prev_cp = True
+        else:
+            q, G = g[1], np.asarray(g[2], dtype=np.complex128)
+            E = np.eye(n, dtype=np.complex128)
+            for dr in (0, 1):
+                for dc in (0, 1):
+                    E[q + dr, q + dc] = G[one[dr], one[dc]] / G[0, 0]
+            layers[-1] = E @ layers[-1]
+            prev_cp = False
+    return (np.stack(layers), np.array(pairs, dtype=np.int32).reshape(-1, 2), np.array(layer, dtype=np.int32),
+            np.array(theta, dtype=np.float64))
+
+
 def round_to_four_bits(t: int) -> int:
     """The smallest integer >= t of the form m * 2^e with m < 16."""
     e = max(0, t.bit_length() - 4)

@@ -267,3 +267,35 @@ def antihermitian_reals_grad(G_K) -> np.ndarray:
     g = np.zeros(d * d)
     check(lib().xf_antihermitian_reals_grad(d, _ptr(Gh), _ptr(g)))
     return g
+
+
+def circuit_from_gates(n: int, gates):
+    """Layered circuit (rot [n_rot, n, n] complex, pairs [k, 2], layer [k],
+    theta [k]) of a gate list in time order, through xf_circuit_from_gates.
+    Gates: ("mg", q, G) for a matchgate G(A, B) (4 x 4 complex, basis
+    |x_q x_{q+1}> = 00, 01, 10, 11) on qubits (q, q + 1), ("cp", q0, q1, theta)
+    for a controlled-phase gate."""
+    arr = (_abi.Gate * max(len(gates), 1))()
+    for i, gt in enumerate(gates):
+        if gt[0] == "mg":
+            arr[i].kind, arr[i].q0, arr[i].q1 = _abi.XF_GATE_MATCHGATE, int(gt[1]), int(gt[1]) + 1
+            G = np.asarray(gt[2], dtype=np.complex128).reshape(16)
+            for e in range(16):
+                arr[i].g[e][0], arr[i].g[e][1] = float(G[e].real), float(G[e].imag)
+        elif gt[0] == "cp":
+            arr[i].kind, arr[i].q0, arr[i].q1 = _abi.XF_GATE_CPHASE, int(gt[1]), int(gt[2])
+            arr[i].theta = float(gt[3])
+        else:
+            raise ValueError(f"unknown gate kind {gt[0]!r}")
+    nr, k = ctypes.c_int32(), ctypes.c_int32()
+    L = lib()
+    check(L.xf_circuit_from_gates(int(n), len(gates), arr, 0, 0, None, None, None, None, ctypes.byref(nr),
+                                  ctypes.byref(k)))
+    rot = np.zeros((nr.value, n, n, 2))
+    pairs = np.zeros((max(k.value, 1), 2), dtype=np.int32)
+    layer = np.zeros(max(k.value, 1), dtype=np.int32)
+    theta = np.zeros(max(k.value, 1))
+    check(L.xf_circuit_from_gates(int(n), len(gates), arr, nr.value, k.value, _ptr(rot), _ptr(pairs), _ptr(layer),
+                                  _ptr(theta), ctypes.byref(nr), ctypes.byref(k)))
+    kk = k.value
+    return rot[..., 0] + 1j * rot[..., 1], pairs[:kk], layer[:kk], theta[:kk]

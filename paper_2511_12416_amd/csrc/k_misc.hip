@@ -1,4 +1,4 @@
-// Small utility kernels: zero fill, fixed-order reduction of per-workgroup
+// Small utility kernels: zero and value fills, fixed-order reduction of per-workgroup
 // partial sums, counter reset.
 #include "xf_device.h"
 
@@ -7,6 +7,11 @@ namespace {
 __global__ void k_fill_zero(double *p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
+}
+
+__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 // out[e] = sum over workgroups q = 0, 1, ... of part[q][e], in that order.
@@ -34,6 +39,12 @@ __global__ void k_zero_u64(unsigned long long *p) {
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s) {
     const int grid = (int)std::min<size_t>((count + 255) / 256, 4096);
     hipLaunchKernelGGL(k_fill_zero, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s) {
+    const int grid = (int)std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, p, (size_t)count, v);
     return hipGetLastError();
 }
 

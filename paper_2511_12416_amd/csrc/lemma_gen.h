@@ -84,7 +84,13 @@ __device__ __forceinline__ void load_gen_tables(const DevPlan &p, const GenPlan 
     for (int e = tid; e < 128; e += kThreads) t.kbt[e] = g.kbt[e];
     for (int e = tid; e < 2 * kGenMaxKb; e += kThreads) t.act[e] = g.act[e];
     for (int e = tid; e < 2 * kGenMaxM; e += kThreads) t.col[e] = g.col[e];
-    if (p.L == 2) {
+    if (g.multi) {
+        for (int blk = 0; blk < g.nblk; ++blk) {
+            const int kb = g.kb[blk];
+            for (int e = tid; e < kb * kb; e += kThreads)
+                t.R1a[g.r1off[blk] + e] = g.TT[((size_t)blk * 64 + e / kb) * 64 + e % kb];
+        }
+    } else if (p.L == 2) {
         for (int blk = 0; blk < g.nblk; ++blk) {
             const int kb0 = g.kb0[blk], kb1 = g.kb[blk] - kb0;
             const uint8_t *act = g.act + blk * kGenMaxKb;
@@ -224,7 +230,7 @@ __device__ __forceinline__ void gen_rows(const DevPlan &p, const GenPlan &g, con
 // singular).  Whole workgroup.
 constexpr int kGenBaseTries = 4;
 
-template <bool MIXED>
+template <bool MIXED, bool MULTI>
 __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan &g, const GenLds &T, int blk,
                                                 unsigned char *scratch, GenShared &sh, Work &wk) {
     const int tid = threadIdx.x, lane = tid & 63;
@@ -365,8 +371,8 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
     __syncthreads();
     if (!singular && sh.ok == 1) break;
     // next base: the next gate whose flips touch this block (of layer 0 for
-    // two CPhase layers)
-    if (attempt + 1 >= kGenBaseTries) return false;
+    // two CPhase layers; more layers keep the empty pattern)
+    if (MULTI || attempt + 1 >= kGenBaseTries) return false;
     auto touches = [&](uint16_t v) { return v != kNoPos && (v >> 8) == blk && (p.L == 1 || (v & 0xFF) < kb0); };
     do {
         ++gate;
@@ -384,7 +390,22 @@ __device__ __forceinline__ bool gen_setup_block(const DevPlan &p, const GenPlan 
     auto hput = [&](int q, int q2, double2 v) { H[q * hld + q2] = v; };
     // mixed precision: FP32 matrix cores for bases with kappa_1 <= p.mixed_cond
     // (the FP32 error of H grows with ||M_B^-1||), FP64 for the others
-    if (MIXED && sh.kappa <= p.mixed_cond) {
+    if constexpr (MULTI) {
+        // U = GA[R, positions], V = HC[positions, cols]
+        const double2 *GA = g.GA + (size_t)blk * n * 64, *HC = g.HC + (size_t)blk * 64 * G;
+        auto uopm = [&](int k, int q) { return GA[(size_t)rows[k] * 64 + q]; };
+        auto vopm = [&](int q, int k) { return HC[(size_t)q * G + col[k]]; };
+        if (MIXED && sh.kappa <= p.mixed_cond) {
+            cgemm_mfma<true>(m, kb, m, minv, uopm, xput);
+            __syncthreads();
+            cgemm_mfma<true>(kb, kb, m, vopm, xop, hput);
+            if (tid == 0) ++wk.fp32;
+        } else {
+            cgemm_mfma<false>(m, kb, m, minv, uopm, xput);
+            __syncthreads();
+            cgemm_mfma<false>(kb, kb, m, vopm, xop, hput);
+        }
+    } else if (MIXED && sh.kappa <= p.mixed_cond) {
         cgemm_mfma<true>(m, kb, m, minv, uop, xput);
         __syncthreads();
         cgemm_mfma<true>(kb, kb, m, vop, xop, hput);
@@ -433,13 +454,13 @@ __device__ __forceinline__ void mask_positions(uint64_t mask, int (&pos)[NP]) {
 // and by the base; the base flips layer-0 modes only).
 template <int NP>
 __device__ __forceinline__ double2 gen_s_entry(bool two_layers, const double2 *H, int hld, const double2 *R1a,
-                                               int kb0, int i, int j, int r0, const int (&pos)[NP], uint64_t neg,
-                                               uint64_t both) {
-    double2 h = H[pos[i] * hld + pos[j]];
-    if ((neg >> pos[i]) & 1) h = make_double2(-h.x, -h.y);
+                                               int kb0, int i, int pi, int j, int r0, const int (&pos)[NP],
+                                               uint64_t neg, uint64_t both) {
+    double2 h = H[pi * hld + pos[j]];
+    if ((neg >> pi) & 1) h = make_double2(-h.x, -h.y);
     if (two_layers && i >= r0) {
         double2 corr = make_double2(0.0, 0.0);
-        const double2 *r1 = R1a + (pos[i] - kb0) * kb0;
+        const double2 *r1 = R1a + (pi - kb0) * kb0;
 #pragma unroll
         for (int l = 0; l < NP; ++l)
             if (l < r0 && !((neg >> pos[l]) & 1)) corr = c_fma(corr, r1[pos[l]], H[pos[l] * hld + pos[j]]);
@@ -451,6 +472,58 @@ __device__ __forceinline__ double2 gen_s_entry(bool two_layers, const double2 *H
         h.y -= 2.0 * corr.y;
     }
     return make_double2((i == j ? 1.0 : 0.0) - 2.0 * h.x, -2.0 * h.y);
+}
+
+// Entry (i, j) of S in a block of a circuit with more than two CPhase
+// layers: with K = HC M_0^-1 GA (the block's H) and TT the layer-to-layer
+// transfer blocks, det M_N = det M_0 det(I + 2 TT[N, N] - 2 K[N, N]) (the
+// product of the layers' I - 2 E_l expands into chains whose sum is
+// GA (I + 2 TT)^-1 HC, and I + 2 TT is unit triangular in layer order).
+template <int NP>
+__device__ __forceinline__ double2 gen_s_entry_multi(const double2 *H, int hld, const double2 *TT, int kb, int i,
+                                                     int pi, int j, const int (&pos)[NP]) {
+    const double2 h = H[pi * hld + pos[j]];
+    const double2 tt = TT[pi * kb + pos[j]];
+    return make_double2((i == j ? 1.0 : 0.0) - 2.0 * h.x + 2.0 * tt.x, -2.0 * h.y + 2.0 * tt.y);
+}
+
+// Row `lane` of S (identity row beyond r) for a lane group: the same
+// entries as gen_s_entry / gen_s_entry_multi, with the two-layer correction
+// added position by position (a loop over the correcting positions around an
+// unrolled loop over the row, so that the row stays in registers).
+template <int GS, bool MULTI>
+__device__ __forceinline__ void gen_s_row(bool two_layers, const double2 *H, int hld, const double2 *R1a, int kb0,
+                                          int kb, int lane, int pi, int r, int r0, const int (&pos)[GS],
+                                          uint64_t pmb, uint64_t neg, uint64_t both, double2 (&a)[GS]) {
+    const bool row = lane < r;
+    const double sg = ((neg >> pi) & 1) ? -2.0 : 2.0;
+#pragma unroll
+    for (int j = 0; j < GS; ++j) {
+        double2 v = make_double2(j == lane ? 1.0 : 0.0, 0.0);
+        if (row && j < r) {
+            const double2 h = H[pi * hld + pos[j]];
+            v.x -= sg * h.x;
+            v.y -= sg * h.y;
+            if constexpr (MULTI) {
+                const double2 tt = R1a[pi * kb + pos[j]];
+                v.x += 2.0 * tt.x;
+                v.y += 2.0 * tt.y;
+            }
+        }
+        a[j] = v;
+    }
+    if (!MULTI && two_layers && row && lane >= r0) {
+        const uint64_t l0 = kb0 >= 64 ? ~0ull : ((1ull << kb0) - 1);
+        const double2 *r1 = R1a + (pi - kb0) * kb0;
+        for (uint64_t mm = (pmb & l0 & ~neg) | both; mm; mm &= mm - 1) {
+            const int q = __ffsll((long long)mm) - 1;
+            const double2 w = r1[q];
+            const double2 w4 = make_double2(4.0 * w.x, 4.0 * w.y);
+#pragma unroll
+            for (int j = 0; j < GS; ++j)
+                if (j < r) a[j] = c_fma(a[j], w4, H[q * hld + pos[j]]);
+        }
+    }
 }
 
 // det of a 4 x 4 (top-left r x r of a, identity elsewhere) by LU with
@@ -504,6 +577,7 @@ __device__ __forceinline__ double2 small_det4(double2 (&a)[4][4], int r) {
 // Product over blocks of det S for a pattern whose blocks flip at most 4
 // positions each (one lane); pm already relative to the blocks' base
 // patterns (shift): sigma = -1 on shift & pm (flipped by the base only).
+template <bool MULTI>
 __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan &g, const GenLds &T,
                                                 const uint64_t (&pm)[2], const uint64_t (&shift)[2]) {
     double2 det = make_double2(1.0, 0.0);
@@ -523,7 +597,9 @@ __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan 
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 a[i][j] = (i < r && j < r)
-                              ? gen_s_entry<4>(p.L == 2, H, g.hld[blk], R1a, kb0, i, j, r0, pos, neg, both)
+                              ? (MULTI ? gen_s_entry_multi<4>(H, g.hld[blk], R1a, g.kb[blk], i, pos[i], j, pos)
+                                         : gen_s_entry<4>(p.L == 2, H, g.hld[blk], R1a, kb0, i, pos[i], j, r0, pos,
+                                                          neg, both))
                               : make_double2(i == j ? 1.0 : 0.0, 0.0);
         det = c_mul(det, small_det4(a, r));
     }
@@ -532,7 +608,7 @@ __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan 
 
 // Same by a group of GS lanes (row `lane` of S per lane; blocks flip at most
 // GS positions each); every lane of the group returns the product.
-template <int GS>
+template <int GS, bool MULTI>
 __device__ __forceinline__ double2 gen_det_group(const DevPlan &p, const GenPlan &g, const GenLds &T,
                                                  const uint64_t (&pm)[2], const uint64_t (&shift)[2], int lane,
                                                  double2 *piv) {
@@ -545,14 +621,16 @@ __device__ __forceinline__ double2 gen_det_group(const DevPlan &p, const GenPlan
         const int r0 = __popcll(pm[blk] & (kb0 >= 64 ? ~0ull : ((1ull << kb0) - 1)));
         int pos[GS];
         mask_positions<GS>(pm[blk], pos);
+        // this lane's row position (the lane-th flipped position), without a
+        // dynamically indexed register array
+        uint64_t rest = pm[blk];
+        for (int q = 0; q < lane && rest; ++q) rest &= rest - 1;
+        const int pi = rest ? __ffsll((long long)rest) - 1 : 0;
         const double2 *H = T.H + g.hoff[blk];
         const double2 *R1a = T.R1a + g.r1off[blk];
         double2 a[GS];
-#pragma unroll
-        for (int j = 0; j < GS; ++j)
-            a[j] = (lane < r && j < r)
-                       ? gen_s_entry<GS>(p.L == 2, H, g.hld[blk], R1a, kb0, lane, j, r0, pos, neg, both)
-                       : make_double2(j == lane ? 1.0 : 0.0, 0.0);
+        gen_s_row<GS, MULTI>(p.L == 2, H, g.hld[blk], R1a, kb0, g.kb[blk], lane, pi, r, r0, pos, pm[blk], neg, both,
+                             a);
         det = c_mul(det, lu_det<GS>(a, r, lane, piv));
     }
     return det;
@@ -578,7 +656,7 @@ __device__ __forceinline__ unsigned long long gen_pattern_flops(const GenPlan &g
         if (r == 0) continue;
         const int kb0 = g.kb0[blk];
         const int r0 = __popcll(pm[blk] & (kb0 >= 64 ? ~0ull : ((1ull << kb0) - 1)));
-        f += lu_flops(r) + 6 + (two_layers ? 8ull * (r - r0) * r0 * r : 0ull);
+        f += lu_flops(r) + 6 + (g.multi ? 4ull * r * r : (two_layers ? 8ull * (r - r0) * r0 * r : 0ull));
     }
     return f;
 }
@@ -595,6 +673,7 @@ __device__ __forceinline__ int rank_bin(int r) { return r <= 4 ? 0 : (r <= 8 ? 1
 // are classified by their largest block rank (counting sort into s.piv) so
 // that lanes and lane groups of a pass take like patterns.  Returns false if a
 // block flips more than kGenMaxRank positions.
+template <bool MULTI>
 __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan &g, const GenLds &T, const RawSmem &s,
                                                 int nl, const double2 *w, double2 detB, const uint64_t (&shift)[2],
                                                 Work &wk, uint64_t *sacc) {
@@ -646,7 +725,7 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
         gen_relative(T.kbt, s.hkey[e], shift, pm);
         rank += __popcll(pm[0]) + __popcll(pm[1]);
         flops += gen_pattern_flops(g, p.L == 2, pm);
-        store(e, gen_det_lane(p, g, T, pm, shift));
+        store(e, gen_det_lane<MULTI>(p, g, T, pm, shift));
     }
     {
         const int l8 = tid & 7, g8 = tid >> 3;
@@ -654,7 +733,7 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
             const int e = order[i];
             uint64_t pm[2];
             gen_relative(T.kbt, s.hkey[e], shift, pm);
-            const double2 dS = gen_det_group<8>(p, g, T, pm, shift, l8, T.gpiv + g8 * 8);
+            const double2 dS = gen_det_group<8, MULTI>(p, g, T, pm, shift, l8, T.gpiv + g8 * 8);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (l8 == 0) {
@@ -670,7 +749,7 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
             const int e = order[i];
             uint64_t pm[2];
             gen_relative(T.kbt, s.hkey[e], shift, pm);
-            const double2 dS = gen_det_group<16>(p, g, T, pm, shift, l16, T.gpiv + g16 * 16);
+            const double2 dS = gen_det_group<16, MULTI>(p, g, T, pm, shift, l16, T.gpiv + g16 * 16);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (l16 == 0) {
@@ -686,7 +765,7 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
             const int e = order[i];
             uint64_t pm[2];
             gen_relative(T.kbt, s.hkey[e], shift, pm);
-            const double2 dS = gen_det_group<32>(p, g, T, pm, shift, l32, T.gpiv + g32 * 32);
+            const double2 dS = gen_det_group<32, MULTI>(p, g, T, pm, shift, l32, T.gpiv + g32 * 32);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (l32 == 0) {
@@ -729,7 +808,7 @@ __device__ __forceinline__ void write_result(int64_t b, double2 total, double sc
 // kGenMaxRank in a block, get ecount[i] = kEntryDeferred, as do (from the
 // sampler) those whose patterns overflowed the workspace region; they are
 // left to k_gen_lu.
-template <bool EXACT, bool MIXED>
+template <bool EXACT, bool MIXED, bool MULTI>
 __global__ void __launch_bounds__(kThreads, 1)
 k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
            const uint64_t *__restrict__ ekey, const int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount,
@@ -771,7 +850,7 @@ k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, 
         }
         bool ok = true;
         for (int blk = 0; blk < g.nblk && ok; ++blk)
-            ok = gen_setup_block<MIXED>(p, g, T, blk, (unsigned char *)smem, sh, wk);
+            ok = gen_setup_block<MIXED, MULTI>(p, g, T, blk, (unsigned char *)smem, sh, wk);
         const double2 detB = sh.det;
         const uint64_t shift[2] = {sh.shift[0], sh.shift[1]};
         acc_clear(s_acc);
@@ -788,7 +867,7 @@ k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, 
                 }
             }
             __syncthreads();
-            ok = gen_sum_entries(p, g, T, s, nc, EXACT ? xw + c0 : nullptr, detB, shift, wk, s_acc);
+            ok = gen_sum_entries<MULTI>(p, g, T, s, nc, EXACT ? xw + c0 : nullptr, detB, shift, wk, s_acc);
         }
         if (!ok) {
             if (tid == 0) ecount[i] = kEntryDeferred;
@@ -896,6 +975,91 @@ __device__ __forceinline__ void gen_lu_entries(const DevPlan &p, const GenPlan &
     accumulate_slots(s, nl, sacc);
 }
 
+// Bytes of LDS the fallback adds for circuits with more than two CPhase
+// layers: Y (64 x 32) and one submatrix (32 x 32).
+constexpr size_t kGenMultiLuBytes = (size_t)(64 * 32 + 32 * 32) * 16;
+
+// The same for circuits with more than two CPhase layers: the whole
+// workgroup composes one pattern's submatrix at a time from
+//   M_N = M_0 - 2 GA[R, N] Y,  (I + 2 TT[N, N]) Y = HC[N, cols]
+// (Y by forward substitution in layer order, I + 2 TT being unit lower
+// triangular), then a lane group of 32 factorises it.
+__device__ __forceinline__ void gen_lu_entries_multi(const DevPlan &p, const GenPlan &g, const GenShared &sh,
+                                                     const RawSmem &s, int nl, const double2 *w, Work &wk,
+                                                     uint64_t *sacc, double2 *Y, double2 *M) {
+    const int tid = threadIdx.x, n = p.n, G = p.G;
+    __shared__ double2 s_det;
+    for (int e = 0; e < nl; ++e) {
+        const uint16_t slot = s.list[e];
+        uint64_t pm[2];
+        gen_masks(g.kbt, s.hkey[slot], pm);
+        if (tid == 0) s_det = make_double2(1.0, 0.0);
+        for (int blk = 0; blk < g.nblk; ++blk) {
+            const int m = g.mb[blk], r = __popcll(pm[blk]);
+            const double2 *GA = g.GA + (size_t)blk * n * 64, *HC = g.HC + (size_t)blk * 64 * G;
+            const double2 *TT = g.TT + (size_t)blk * 64 * 64;
+            const uint8_t *col = g.col + blk * kGenMaxM;
+            // Y: lane c of wave 0 solves column c
+            if (tid < m) {
+                int f = 0;
+                for (uint64_t mm = pm[blk]; mm; mm &= mm - 1, ++f) {
+                    const int q = __ffsll((long long)mm) - 1;
+                    double2 y = HC[(size_t)q * G + col[tid]];
+                    int f2 = 0;
+                    for (uint64_t m2 = pm[blk] & ((1ull << q) - 1); m2; m2 &= m2 - 1, ++f2) {
+                        const int q2 = __ffsll((long long)m2) - 1;
+                        const double2 tt = TT[(size_t)q * 64 + q2];
+                        y = c_fma(y, make_double2(-2.0 * tt.x, -2.0 * tt.y), Y[f2 * 32 + tid]);
+                    }
+                    Y[f * 32 + tid] = y;
+                }
+            }
+            __syncthreads();
+            for (int ij = tid; ij < m * m; ij += kThreads) {
+                const int i = ij / m, c = ij % m;
+                const int Ri = sh.rows[blk][i];
+                double2 v = p.P[(size_t)Ri * G + col[c]];
+                int f = 0;
+                for (uint64_t mm = pm[blk]; mm; mm &= mm - 1, ++f) {
+                    const int q = __ffsll((long long)mm) - 1;
+                    const double2 ga = GA[(size_t)Ri * 64 + q];
+                    v = c_fma(v, make_double2(-2.0 * ga.x, -2.0 * ga.y), Y[f * 32 + c]);
+                }
+                M[i * 32 + c] = v;
+            }
+            __syncthreads();
+            if (tid < 32) {
+                double2 a[32];
+#pragma unroll
+                for (int j = 0; j < 32; ++j)
+                    a[j] = (tid < m && j < m) ? M[tid * 32 + j] : make_double2(j == tid ? 1.0 : 0.0, 0.0);
+                const double2 d = lu_det<32>(a, m, tid, s.piv);
+                if (tid == 0) {
+                    s_det = c_mul(s_det, d);
+                    wk.flops += lu_flops(m) + 8ull * m * m * r + 8ull * r * r * m / 2;
+                }
+            }
+            __syncthreads();
+            (void)r;
+        }
+        if (tid == 0) {
+            const double2 det = s_det;
+            double2 v;
+            if (w) {
+                v = c_mul(w[e], det);
+            } else {
+                const int2 c = s.hcnt[slot];
+                v = make_double2((double)c.x * det.x - (double)c.y * det.y, (double)c.x * det.y + (double)c.y * det.x);
+            }
+            s.hkey[slot] = (uint64_t)__double_as_longlong(v.x);
+            *(double *)&s.hcnt[slot] = v.y;
+            wk.terms += 1;
+        }
+        __syncthreads();
+    }
+    accumulate_slots(s, nl, sacc);
+}
+
 template <bool EXACT>
 __global__ void __launch_bounds__(kThreads, 1)
 k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
@@ -908,6 +1072,8 @@ k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, in
     __shared__ GenShared sh;
     __shared__ uint64_t s_acc[kAccWords];
     const RawSmem s = carve_raw(smem, EXACT ? 0 : p.k, p.n, 4, false);
+    double2 *Ym = (double2 *)(smem + raw_lds_bytes(EXACT ? 0 : p.k, p.n, 4, false, false));
+    double2 *Mm = Ym + 64 * 32;
     const int tid = threadIdx.x;
     Work wk;
     bool loaded = false;
@@ -942,7 +1108,10 @@ k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, in
                     s.list[e] = (uint16_t)e;
                 }
                 __syncthreads();
-                gen_lu_entries(p, g, sh, s, nc, xw + c0, wk, s_acc);
+                if (g.multi)
+                    gen_lu_entries_multi(p, g, sh, s, nc, xw + c0, wk, s_acc, Ym, Mm);
+                else
+                    gen_lu_entries(p, g, sh, s, nc, xw + c0, wk, s_acc);
             }
         } else {
             Sampler st;
@@ -950,7 +1119,10 @@ k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, in
             while (true) {
                 const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
                 const int nl = gather_list(s, &s_n);
-                gen_lu_entries(p, g, sh, s, nl, nullptr, wk, s_acc);
+                if (g.multi)
+                    gen_lu_entries_multi(p, g, sh, s, nl, nullptr, wk, s_acc, Ym, Mm);
+                else
+                    gen_lu_entries(p, g, sh, s, nl, nullptr, wk, s_acc);
                 if (done) break;
                 clear_table(s, s_cnt, slot0, st);
             }

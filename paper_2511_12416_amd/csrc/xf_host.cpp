@@ -135,6 +135,9 @@ struct DeviceGuard {
 
 }  // namespace
 
+// Rotation layers of a plan (CPhase layers + 1).
+constexpr int kMaxRot = 65;
+
 struct xf_plan {
     int device = 0;
     int n = 0, n_rot = 0, k = 0, m = 0, L = 0, G = 4;
@@ -157,6 +160,7 @@ struct xf_plan {
     // general determinant-lemma evaluation: blocks of modes and their active lists
     xf::GenPlan gen{};
     DevBuf dgcol, dgact, dgpos0, dgpos1, dgblk, dgkbt, dggpos, dflags;
+    DevBuf dgGA, dgHC, dgTT;          // more than two CPhase layers: the factors of each block's positions
     int last_gen = 0;                 // the last xf_probabilities call used the general lemma kernel
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
@@ -263,6 +267,10 @@ xf_status refresh_gen(xf_plan *P) {
     xf::GenPlan &g = P->gen;
     g = xf::GenPlan{};
     g.nblk = roots.size() == 2 ? 2 : 1;
+    const int L = P->L;
+    const bool multi = L >= 3;
+    g.multi = multi ? 1 : 0;
+    std::vector<std::pair<int, int>> apos[2];   // (layer, mode) of each block's positions
     std::vector<int8_t> blk(128, 0), pos0(128, -1), pos1(128, -1);
     for (int q = 0; q < n; ++q) blk[q] = (int8_t)(g.nblk == 2 && find(q) == roots[1] ? 1 : 0);
     std::vector<uint8_t> col(2 * 32, 0), act(2 * 64, 0);
@@ -279,28 +287,38 @@ xf_status refresh_gen(xf_plan *P) {
                 ++mb;
             }
         g.mb[b] = mb;
-        std::vector<int> a0, a1;
+        // active positions: (CPhase layer, mode) pairs of the block, by layer then mode
+        std::vector<std::vector<int>> al(std::max(L, 1));
         for (int j = 0; j < P->k; ++j)
             for (int side = 0; side < 2; ++side) {
                 const int q = P->pairs[2 * j + side];
-                if (blk[q] != b) continue;
-                (P->layer[j] == 0 ? a0 : a1).push_back(q);
+                if (blk[q] == b) al[P->layer[j]].push_back(q);
             }
-        for (auto *v : {&a0, &a1}) {
-            std::sort(v->begin(), v->end());
-            v->erase(std::unique(v->begin(), v->end()), v->end());
+        int kb = 0;
+        for (auto &v : al) {
+            std::sort(v.begin(), v.end());
+            v.erase(std::unique(v.begin(), v.end()), v.end());
+            kb += (int)v.size();
         }
-        g.kb0[b] = (int)a0.size();
-        g.kb[b] = (int)(a0.size() + a1.size());
-        if (mb > 32 || g.kb[b] > 64) fits = false;
-        for (size_t i = 0; i < a0.size() && i < 64; ++i) act[b * 64 + i] = (uint8_t)a0[i], pos0[a0[i]] = (int8_t)i;
-        for (size_t i = 0; i < a1.size() && a0.size() + i < 64; ++i)
-            act[b * 64 + a0.size() + i] = (uint8_t)a1[i], pos1[a1[i]] = (int8_t)(a0.size() + i);
+        g.kb0[b] = multi ? kb : (int)al[0].size();
+        g.kb[b] = kb;
+        if (mb > 32 || kb > 64) fits = false;
+        int at = 0;
+        for (int l = 0; l < (int)al.size(); ++l)
+            for (int q : al[l]) {
+                if (at < 64) {
+                    act[b * 64 + at] = (uint8_t)q;
+                    if (l == 0) pos0[q] = (int8_t)at;
+                    if (l == 1) pos1[q] = (int8_t)at;
+                    apos[b].push_back({l, q});
+                }
+                ++at;
+            }
         g.hoff[b] = hoff;
         g.hld[b] = g.kb[b] | 1;
         hoff += g.kb[b] * g.hld[b];
         g.r1off[b] = r1;
-        r1 += g.kb0[b] * (g.kb[b] - g.kb0[b]);
+        r1 += multi ? kb * kb : g.kb0[b] * (g.kb[b] - g.kb0[b]);
     }
     g.hsize = hoff;
     g.r1size = r1;
@@ -308,6 +326,12 @@ xf_status refresh_gen(xf_plan *P) {
     // trajectory bit flips the two modes of gate j in its layer
     std::vector<uint16_t> kbt(128, 0xFFFF);
     auto code = [&](int layer, int q) -> uint16_t {
+        if (multi) {
+            const auto &v = apos[blk[q]];
+            for (size_t i = 0; i < v.size(); ++i)
+                if (v[i].first == layer && v[i].second == q) return (uint16_t)((blk[q] << 8) | i);
+            return 0xFFFF;
+        }
         const int ps = layer == 0 ? pos0[q] : pos1[q];
         return ps < 0 ? 0xFFFF : (uint16_t)((blk[q] << 8) | ps);
     };
@@ -321,6 +345,62 @@ xf_status refresh_gen(xf_plan *P) {
     }
     if (!fits) g.nblk = 0;   // the general evaluation does not apply
     xf_status st;
+    if (multi && fits) {
+        // V(x) = R'_L W_{L-1} R'_{L-1} ... W_0 R'_0 with W_l = I - 2 E_l: for the
+        // position q = (l, a) of a block, GA[:, q] = (R'_L ... R'_{l+1})[:, a],
+        // HC[q, :] = (R'_l ... R'_0)[a, C], and for positions q = (l, a),
+        // q' = (l', a') with l > l', TT[q, q'] = (R'_l ... R'_{l'+1})[a, a'].
+        const auto &R = P->Rp;
+        const int G = P->G;
+        auto mv = [&](const std::vector<cd> &A, const std::vector<cd> &v) {
+            std::vector<cd> o(n, 0.0);
+            for (int r = 0; r < n; ++r)
+                for (int c = 0; c < n; ++c) o[r] += A[(size_t)r * n + c] * v[c];
+            return o;
+        };
+        auto vm = [&](const std::vector<cd> &v, const std::vector<cd> &A) {
+            std::vector<cd> o(n, 0.0);
+            for (int r = 0; r < n; ++r)
+                for (int c = 0; c < n; ++c) o[c] += v[r] * A[(size_t)r * n + c];
+            return o;
+        };
+        std::vector<double> GA((size_t)2 * n * 64 * 2, 0.0), HC((size_t)2 * 64 * G * 2, 0.0),
+            TT((size_t)2 * 64 * 64 * 2, 0.0);
+        for (int b = 0; b < g.nblk; ++b)
+            for (size_t q = 0; q < apos[b].size(); ++q) {
+                const int l = apos[b][q].first, a = apos[b][q].second;
+                std::vector<cd> v(n, 0.0);
+                v[a] = 1.0;
+                for (int j = l + 1; j <= L; ++j) {
+                    v = mv(R[j], v);
+                    if (j < L)
+                        for (size_t q2 = 0; q2 < apos[b].size(); ++q2)
+                            if (apos[b][q2].first == j) {
+                                const cd z = v[apos[b][q2].second];
+                                TT[2 * (((size_t)b * 64 + q2) * 64 + q)] = z.real();
+                                TT[2 * (((size_t)b * 64 + q2) * 64 + q) + 1] = z.imag();
+                            }
+                }
+                for (int r = 0; r < n; ++r) {
+                    GA[2 * (((size_t)b * n + r) * 64 + q)] = v[r].real();
+                    GA[2 * (((size_t)b * n + r) * 64 + q) + 1] = v[r].imag();
+                }
+                std::vector<cd> u(n, 0.0);
+                u[a] = 1.0;
+                for (int j = l; j >= 0; --j) u = vm(u, R[j]);
+                for (int c = 0; c < m; ++c) {
+                    HC[2 * (((size_t)b * 64 + q) * G + c)] = u[P->C[c]].real();
+                    HC[2 * (((size_t)b * 64 + q) * G + c) + 1] = u[P->C[c]].imag();
+                }
+            }
+        if ((st = dev_upload(P->dgGA, GA.data(), GA.size() * 8)) ||
+            (st = dev_upload(P->dgHC, HC.data(), HC.size() * 8)) ||
+            (st = dev_upload(P->dgTT, TT.data(), TT.size() * 8)))
+            return st;
+        g.GA = (const double2 *)P->dgGA.p;
+        g.HC = (const double2 *)P->dgHC.p;
+        g.TT = (const double2 *)P->dgTT.p;
+    }
     if ((st = dev_upload(P->dgcol, col.data(), col.size())) || (st = dev_upload(P->dgact, act.data(), act.size())) ||
         (st = dev_upload(P->dgpos0, pos0.data(), 128)) || (st = dev_upload(P->dgpos1, pos1.data(), 128)) ||
         (st = dev_upload(P->dgblk, blk.data(), 128)) || (st = dev_upload(P->dgkbt, kbt.data(), 256)) ||
@@ -368,6 +448,15 @@ xf_status refresh_matrices(xf_plan *P) {
         Qm.assign((size_t)n * m, 0.0);
         matmul(R[1].data(), Phi0.data(), Qm.data(), n, n, m);
         Pm = Qm;
+    }
+    if (L >= 3) {
+        // V(0)[:, C] through every layer (the factors of the positions are
+        // formed with the block tables in refresh_gen)
+        for (int l = 2; l <= L; ++l) {
+            std::vector<cd> X((size_t)n * m, 0.0);
+            matmul(R[l].data(), Pm.data(), X.data(), n, n, m);
+            Pm = X;
+        }
     }
     if (L == 2) {
         Pm.assign((size_t)n * m, 0.0);
@@ -526,7 +615,7 @@ void plan_free(xf_plan *P) {
                       &P->fA2, &P->fQ, &P->fR1, &P->dkeymode, &P->dT, &P->dgkey, &P->dgmode,
                       &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
                       &P->dgsum, &P->dekey, &P->decnt, &P->decount, &P->dgcol, &P->dgact, &P->dgpos0,
-                      &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dggpos, &P->dflags})
+                      &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dggpos, &P->dflags, &P->dgGA, &P->dgHC, &P->dgTT})
         dev_free(*b);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();
@@ -581,7 +670,9 @@ xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision pre
     if (c->n < 1) return fail(XF_EINVAL, "n must be >= 1");
     if (c->n > 128) return fail(XF_EUNSUPPORTED, "n = %d > 128", c->n);
     if (c->n_rot < 1) return fail(XF_EINVAL, "n_rot must be >= 1");
-    if (c->n_rot > 3) return fail(XF_EUNSUPPORTED, "n_rot = %d > 3", c->n_rot);
+    if (c->n_rot > kMaxRot) return fail(XF_EUNSUPPORTED, "n_rot = %d > %d", c->n_rot, kMaxRot);
+    if (c->n_rot > 3 && c->k > 63)
+        return fail(XF_EUNSUPPORTED, "more than two CPhase layers need k <= 63 (k = %d)", c->k);
     if (!c->rot) return fail(XF_EINVAL, "rot is NULL");
     if (c->k < 0) return fail(XF_EINVAL, "k must be >= 0");
     if (c->k > 0 && (!c->pairs || !c->layer || !c->theta)) return fail(XF_EINVAL, "pairs/layer/theta is NULL");
@@ -619,8 +710,9 @@ xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision pre
     for (int q = 0; q < n; ++q)
         if ((input.w[q >> 6] >> (q & 63)) & 1) P->C.push_back(q);
 
-    // Flip-pattern keys: the modes touched by each CPhase layer, packed.
-    std::vector<std::vector<int>> act(2);
+    // Flip-pattern keys: the modes touched by each CPhase layer, packed (one
+    // or two layers), or the trajectory itself.
+    std::vector<std::vector<int>> act(std::max(2, n_rot - 1));
     for (int j = 0; j < k; ++j)
         for (int side = 0; side < 2; ++side) act[P->layer[j]].push_back(P->pairs[2 * j + side]);
     for (auto &v : act) {
@@ -633,11 +725,11 @@ xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision pre
     P->gkey.assign(std::max(k, 1), 0);
     P->gmode.assign(2 * std::max(k, 1), 0);
     std::vector<int32_t> glayer(std::max(k, 1), 0);
-    if (P->keybits <= 63) P->keykind = 0;
+    if (P->keybits <= 63 && n_rot <= 3) P->keykind = 0;
     else if (k <= 63) P->keykind = 1;
     else P->keykind = -1;
-    for (size_t i = 0; i < act[0].size() && P->keybits <= 63; ++i) P->keymode[i] = (uint8_t)act[0][i];
-    for (size_t i = 0; i < act[1].size() && P->keybits <= 63; ++i) P->keymode[P->off1 + i] = (uint8_t)act[1][i];
+    for (size_t i = 0; i < act[0].size() && P->keykind == 0; ++i) P->keymode[i] = (uint8_t)act[0][i];
+    for (size_t i = 0; i < act[1].size() && P->keykind == 0; ++i) P->keymode[P->off1 + i] = (uint8_t)act[1][i];
     for (int j = 0; j < k; ++j) {
         const int l = P->layer[j];
         glayer[j] = l;
@@ -770,8 +862,15 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
     const int alg = P->evaluation == XF_EVAL_LU ? 1 : 0;
     // evaluation: the eta <= 16 one-layer lemma kernels, else the general
     // lemma kernel where its sizes fit, else the LU per pattern
-    const bool fast = mode == XF_RAW_ESTIMATE && xf::raw_estimate_uses_lemma(d, alg);
-    const bool gen = !fast && alg == 0 && xf::gen_applies(d, P->gen);
+    // more than two CPhase layers: the general kernel only (its LU kernel
+    // for every bitstring under XF_EVAL_LU)
+    const bool multi = P->L >= 3;
+    const bool fast = !multi && mode == XF_RAW_ESTIMATE && xf::raw_estimate_uses_lemma(d, alg);
+    const bool gen = !fast && (alg == 0 || multi) && xf::gen_applies(d, P->gen);
+    const bool all_lu = multi && alg == 1;
+    if (multi && !gen)
+        return fail(XF_EUNSUPPORTED, "%d CPhase layers: every spin block needs at most 32 input modes and 64 active "
+                    "(layer, mode) pairs whose tables fit in LDS", P->L);
     const bool lemma = mode == XF_RAW_ESTIMATE && (fast || gen);   // sampler + evaluation kernels
     // lemma workspace: chunks of bitstrings whose entry regions fit
     uint64_t cap = 0;
@@ -845,7 +944,7 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
                     e = xf::launch_lemma_chunk(d, (const uint64_t *)d_bits, b0, nb, t, seed, ekey, ecnt, ecount, cap,
                                                d_prob, d_amp, d_logp, nterm, mid, s);
                 else
-                    e = xf::launch_gen_chunk(d, P->gen, mixed, (const uint64_t *)d_bits, b0, nb, t, seed, ekey, ecnt,
+                    e = xf::launch_gen_chunk(d, P->gen, mixed, all_lu, (const uint64_t *)d_bits, b0, nb, t, seed, ekey, ecnt,
                                              ecount, cap, d_prob, d_amp, d_logp, nterm, mid, s);
                 if (e == hipSuccess && timed) e = hipEventRecord(P->ev[2 + 2 * c], s);
             }
@@ -860,7 +959,7 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
         }
     } else {
         if (gen) {
-            e = xf::launch_gen_exact(d, P->gen, mixed, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p,
+            e = xf::launch_gen_exact(d, P->gen, mixed, all_lu, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p,
                                      P->nxterms, (const uint64_t *)d_bits, B, ecount, d_prob, d_amp, d_logp, nterm,
                                      nullptr, s);
             P->last_gen = 1;
@@ -981,6 +1080,110 @@ xf_status xf_estimate(xf_plan *P, const xf_bits128 *d_bits, int64_t B, double ep
         return fail(XF_EDEVICE, "copy of the results failed");
     if (h_t) std::copy(tb.begin(), tb.end(), h_t);
     if (h_iterations) *h_iterations = it;
+    return ok();
+}
+
+xf_status xf_circuit_from_gates(int32_t n, int32_t n_gates, const xf_gate *gates, int32_t max_rot, int32_t max_k,
+                                double *rot, int32_t *pairs, int32_t *layer, double *theta, int32_t *n_rot,
+                                int32_t *k) {
+    if (n < 2 || n > 128) return fail(XF_EINVAL, "n must be in [2, 128]");
+    if (n_gates < 0 || (n_gates > 0 && !gates)) return fail(XF_EINVAL, "invalid gate list");
+    if (!n_rot || !k) return fail(XF_EINVAL, "NULL count output");
+    // Pass 1: validate and count layers.  Consecutive matchgates multiply into
+    // one rotation layer, consecutive CPhase gates (diagonal, commuting) form
+    // one CPhase layer between two rotation layers.
+    int nr = 1, nk = 0;
+    bool in_cphase = false;
+    for (int gi = 0; gi < n_gates; ++gi) {
+        const xf_gate &g = gates[gi];
+        if (g.kind == XF_GATE_CPHASE) {
+            if (g.q0 < 0 || g.q0 >= n || g.q1 < 0 || g.q1 >= n || g.q0 == g.q1)
+                return fail(XF_EINVAL, "gate %d: invalid CPhase qubits (%d, %d)", gi, g.q0, g.q1);
+            if (!std::isfinite(g.theta) || std::fabs(g.theta) >= 2.0 * M_PI)
+                return fail(XF_EINVAL, "gate %d: angle must be finite with |theta| < 2 pi", gi);
+            if (!in_cphase) ++nr;
+            in_cphase = true;
+            ++nk;
+        } else if (g.kind == XF_GATE_MATCHGATE) {
+            if (g.q0 < 0 || g.q1 != g.q0 + 1 || g.q1 >= n)
+                return fail(XF_EINVAL, "gate %d: a matchgate acts on neighbours (q, q + 1) (got %d, %d)", gi, g.q0,
+                            g.q1);
+            if (!finite_all(&g.g[0][0], 32)) return fail(XF_EINVAL, "gate %d: NaN/Inf entry", gi);
+            cd G[4][4];
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) G[r][c] = cd(g.g[4 * r + c][0], g.g[4 * r + c][1]);
+            // block form of Sec. II-B Eq. 1 with A diagonal (passive: |00>, |11> keep their weight)
+            const int zero[10][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 0}, {1, 3}, {2, 0}, {2, 3}, {3, 0}, {3, 1}, {3, 2}};
+            for (auto &z : zero)
+                if (std::abs(G[z[0]][z[1]]) > 1e-12)
+                    return fail(XF_EINVAL, "gate %d: not a particle-number-conserving matchgate (entry %d,%d)", gi,
+                                z[0], z[1]);
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    cd v = 0.0;
+                    for (int t = 0; t < 4; ++t) v += std::conj(G[t][r]) * G[t][c];
+                    if (std::abs(v - (r == c ? 1.0 : 0.0)) > 1e-10) return fail(XF_EINVAL, "gate %d: not unitary", gi);
+                }
+            const cd detA = G[0][0] * G[3][3], detB = G[1][1] * G[2][2] - G[1][2] * G[2][1];
+            if (std::abs(detA - detB) > 1e-10) return fail(XF_EINVAL, "gate %d: det A != det B", gi);
+            in_cphase = false;
+        } else {
+            return fail(XF_EINVAL, "gate %d: unknown kind %d", gi, g.kind);
+        }
+    }
+    *n_rot = nr;   // one more than the runs of CPhase gates (the last layer may be the identity)
+    *k = nk;
+    if (!rot) return ok();   // sizes only
+    if (nr > max_rot || nk > max_k)
+        return fail(XF_EINVAL, "the circuit needs %d rotation layers and %d CPhase gates (room for %d and %d)", nr,
+                    nk, max_rot, max_k);
+    if (nk > 0 && (!pairs || !layer || !theta)) return fail(XF_EINVAL, "NULL CPhase output");
+    // Pass 2: fill.  Layer l starts as the identity; a matchgate on (q, q + 1)
+    // with vacuum phase a = G[00][00] acts on the modes as the 2 x 2 block
+    //   U[q][q] = G[10][10] / a,  U[q][q+1] = G[10][01] / a,
+    //   U[q+1][q] = G[01][10] / a,  U[q+1][q+1] = G[01][01] / a
+    // (column convention; a_q^dag |0> = |..1_q 0..>, no Jordan-Wigner sign for
+    // neighbours; |11> then gets a det U, which is G[11][11] since det A = det B),
+    // applied after the layer so far: U_layer <- U_gate U_layer.  The phase a
+    // is global and dropped.
+    const size_t nn = (size_t)n * n;
+    std::vector<cd> U(nn);
+    auto reset = [&]() {
+        std::fill(U.begin(), U.end(), cd(0.0));
+        for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+    };
+    int l = 0, j = 0;
+    auto flush = [&]() {
+        for (size_t i = 0; i < nn; ++i) rot[2 * ((size_t)l * nn + i)] = U[i].real(), rot[2 * ((size_t)l * nn + i) + 1] = U[i].imag();
+        ++l;
+        reset();
+    };
+    reset();
+    in_cphase = false;
+    for (int gi = 0; gi < n_gates; ++gi) {
+        const xf_gate &g = gates[gi];
+        if (g.kind == XF_GATE_CPHASE) {
+            if (!in_cphase) flush();
+            in_cphase = true;
+            pairs[2 * j] = g.q0;
+            pairs[2 * j + 1] = g.q1;
+            layer[j] = l - 1;
+            theta[j] = g.theta;
+            ++j;
+        } else {
+            in_cphase = false;
+            const int q = g.q0;
+            auto at = [&](int r, int c) { return cd(g.g[4 * r + c][0], g.g[4 * r + c][1]); };
+            const cd a = at(0, 0);
+            const cd b00 = at(2, 2) / a, b01 = at(2, 1) / a, b10 = at(1, 2) / a, b11 = at(1, 1) / a;
+            for (int c = 0; c < n; ++c) {
+                const cd u0 = U[(size_t)q * n + c], u1 = U[(size_t)(q + 1) * n + c];
+                U[(size_t)q * n + c] = b00 * u0 + b01 * u1;
+                U[(size_t)(q + 1) * n + c] = b10 * u0 + b11 * u1;
+            }
+        }
+    }
+    flush();
     return ok();
 }
 

@@ -77,6 +77,13 @@ struct GenPlan {
     const int8_t *blk;          // [128]: block of each mode
     const uint16_t *kbt;        // [64][2]: (block << 8 | position) of the modes a key bit flips, or 0xFFFF
     const uint16_t *gpos;       // [64][2]: the same for the two modes of gate j
+    // More than two CPhase layers (multi = 1): positions are (layer, mode)
+    // pairs ordered by layer; with V(x) = R'_L W_{L-1} ... W_0 R'_0,
+    // GA[b][r][q] = (R'_L ... R'_{l+1})[r, a], HC[b][q][c] = (R'_l ... R'_0)[a, C[c]]
+    // (row stride G) and TT[b][q][q'] = (R'_l ... R'_{l'+1})[a, a'] for l > l'
+    // (zero otherwise), for q = (l, a), q' = (l', a'); kb0 = kb.
+    int multi;
+    const double2 *GA, *HC, *TT;
 };
 
 // One partial gradient (of a workgroup of the lemma backward, or of a lane
@@ -138,6 +145,7 @@ hipError_t launch_exact_bwd(const DevPlan &p, bool mixed, const uint64_t *keys, 
                             const double *g, double2 *part, int nparts, const GradLayout &lay,
                             hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s);
 hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, double2 *out, hipStream_t s);
 // Raises the dynamic-LDS limit of every kernel instantiated for lane-group
 // size G (k_misc.hip calls the per-file functions).
@@ -171,17 +179,18 @@ hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, c
 // General determinant-lemma evaluation (k_lemma_gen.hip).  gen_applies: the
 // plan's sizes fit its LDS layout.  launch_gen_chunk: Raw Estimate for
 // bitstrings [b0, b0 + nb) (sampler kernel into the workspace, evaluation,
-// then the LU kernel for the bitstrings it deferred).  launch_gen_exact: exact
-// mode over [0, B) with flags[B] marking deferred bitstrings, then the LU kernel
-// for those.
+// then the LU kernel for the bitstrings it deferred; with all_lu, the LU
+// kernel for every bitstring).  launch_gen_exact: exact mode over [0, B) with
+// flags[B] marking deferred bitstrings, then the LU kernel for those (all of
+// them with all_lu).
 bool gen_applies(const DevPlan &p, const GenPlan &g);
-hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, const uint64_t *bits, int64_t b0,
-                            int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount,
-                            uint64_t cap, double *prob, double *amp, double *logp, unsigned long long *nterm,
-                            hipEvent_t ev_mid, hipStream_t s);
-hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, const uint64_t *keys, const double2 *w,
-                            int64_t nkeys, const uint64_t *bits, int64_t B, uint32_t *flags, double *prob,
-                            double *amp, double *logp, unsigned long long *nterm, hipEvent_t ev_mid,
+hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *bits,
+                            int64_t b0, int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt,
+                            uint32_t *ecount, uint64_t cap, double *prob, double *amp, double *logp,
+                            unsigned long long *nterm, hipEvent_t ev_mid, hipStream_t s);
+hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *keys,
+                            const double2 *w, int64_t nkeys, const uint64_t *bits, int64_t B, uint32_t *flags,
+                            double *prob, double *amp, double *logp, unsigned long long *nterm, hipEvent_t ev_mid,
                             hipStream_t s);
 hipError_t prepare_gen();
 // Device address of the no-allocation scratch on `device` (current), looked up

@@ -81,3 +81,27 @@ def statevector_amplitudes(rot, pairs, layer, theta, input_modes, n: int):
 
 def bits_to_int(b) -> int:
     return int(b[0]) | (int(b[1]) << 64)
+
+
+def gate_list_amplitudes(n: int, gates, input_bits: int) -> np.ndarray:
+    """Full 2^n qubit state vector of a gate list applied to the basis state
+    `input_bits` (bit p = qubit p): each gate's 4 x 4 matrix acts on its two
+    qubits as written (basis |x_q0 x_q1> = 00, 01, 10, 11), a CPhase gate as
+    diag(1, 1, 1, e^{i theta}).  No fermionic formalism."""
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[int(input_bits)] = 1.0
+    idx = np.arange(1 << n)
+    for g in gates:
+        if g[0] == "mg":
+            q0, q1, M = g[1], g[1] + 1, np.asarray(g[2], dtype=np.complex128)
+        else:
+            q0, q1 = g[1], g[2]
+            M = np.diag([1.0, 1.0, 1.0, np.exp(1j * g[3])]).astype(np.complex128)
+        sub = 2 * ((idx >> q0) & 1) + ((idx >> q1) & 1)
+        base = idx & ~((1 << q0) | (1 << q1))
+        new = np.zeros_like(psi)
+        for out in range(4):
+            tgt = base | (((out >> 1) & 1) << q0) | ((out & 1) << q1)
+            np.add.at(new, tgt, M[out, sub] * psi)
+        psi = new
+    return psi

@@ -161,12 +161,17 @@ def test_plan_create_validation(xf):
         assert st == status, change
         assert not h.value
         assert len(xf.lib().xf_last_error()) > 0
-    # n > 128 and more than three rotation layers are unsupported, not invalid
+    # n > 128, more than 65 rotation layers, and more than three with k > 63
+    # are unsupported, not invalid
     big = np.stack([np.eye(130, dtype=np.complex128)] * 2)
     st, _ = _create(xf, big, pairs, layer, theta, inp)
     assert st == 2
+    many = np.stack([np.eye(n, dtype=np.complex128)] * 66)
+    st, _ = _create(xf, many, pairs, layer, theta, inp)
+    assert st == 2
+    k64 = 64
     four = np.stack([np.eye(n, dtype=np.complex128)] * 4)
-    st, _ = _create(xf, four, pairs, layer, theta, inp)
+    st, _ = _create(xf, four, np.array([[0, 1]] * k64), np.zeros(k64, np.int32), np.full(k64, 0.1), inp)
     assert st == 2
 
 

@@ -280,3 +280,45 @@ def random_circuit(seed: int, n: int, eta: int, k: int, n_rot: int = 2,
         bits = np.array([bits_from_modes(x) for x in sel], dtype=np.uint64).reshape(-1, 2)
     return Workload(f"random n={n} eta={eta} k={k}", n, bits_from_modes(input_modes),
                     rot, pairs, layer, theta, bits, "exact", n_rot=n_rot)
+
+
+def random_matchgate(rng: np.random.Generator) -> np.ndarray:
+    """A random particle-number-conserving matchgate G(A, B) (4 x 4, basis
+    |x_q x_{q+1}> = 00, 01, 10, 11): A = diag(e^{i a}, e^{i b}) and B a Haar
+    2 x 2 unitary rescaled so that det B = det A."""
+    a, b = rng.uniform(-np.pi, np.pi, size=2)
+    B = haar_unitary(rng, 2)
+    B = B * np.sqrt(np.exp(1j * (a + b)) / np.linalg.det(B))
+    G = np.zeros((4, 4), dtype=np.complex128)
+    G[0, 0], G[3, 3] = np.exp(1j * a), np.exp(1j * b)
+    G[1:3, 1:3] = B
+    return G
+
+
+def random_gate_circuit(seed: int, n: int, eta: int, n_cphase: int, mg_per_layer: Optional[int] = None,
+                        theta_scale: float = 1.0, max_bits: int = 4096):
+    """A random interleaved circuit given gate by gate, shaped like the
+    paper's random extended-matchgate benchmark: layers of nearest-neighbour
+    matchgates (``mg_per_layer``, default n - 1, on random neighbour pairs)
+    each followed by one CPhase gate on a random distinct pair, angles uniform
+    in [-theta_scale, theta_scale], with a closing matchgate layer.  Returns
+    (gates, input_bits, output bitstrings): gates as ("mg", q, G) and
+    ("cp", q0, q1, theta) in time order, the input the first eta modes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    per = n - 1 if mg_per_layer is None else mg_per_layer
+    gates = []
+    for layer in range(n_cphase + 1):
+        for _ in range(per):
+            q = int(rng.integers(0, n - 1))
+            gates.append(("mg", q, random_matchgate(rng)))
+        if layer < n_cphase:
+            q0, q1 = (int(v) for v in rng.choice(n, size=2, replace=False))
+            gates.append(("cp", q0, q1, float(rng.uniform(-theta_scale, theta_scale))))
+    from itertools import combinations
+    from math import comb
+    if comb(n, eta) <= max_bits:
+        bits = np.array([bits_from_modes(c) for c in combinations(range(n), eta)], dtype=np.uint64)
+    else:
+        sel = random_fixed_weight(rng, np.arange(n), eta, max_bits)
+        bits = np.array([bits_from_modes(c) for c in sel], dtype=np.uint64)
+    return gates, bits_from_modes(range(eta)), bits
