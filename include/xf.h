@@ -243,6 +243,29 @@ xf_status xf_probabilities_noalloc(xf_plan *plan, const xf_bits128 *d_bits, int6
 xf_status xf_estimate(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, double eps, double delta,
                       uint64_t seed, double *d_prob, int64_t *h_t, int32_t *h_iterations, void *hip_stream);
 
+/* Weak simulation (Sec. II-A): S output samples of a circuit given gate by
+ * gate, by the gate-by-gate algorithm (Bravyi, Gosset and Liu, 2022), which
+ * needs only probabilities of chosen bitstrings.  Every chain starts at the
+ * input; a CPhase gate (diagonal) leaves the distribution unchanged; at a
+ * matchgate gi on (q, q + 1), a chain whose pair holds one particle (the
+ * other assignments are fixed by particle-number conservation) moves to the
+ * candidate c10 (mode q occupied) or c01 (mode q + 1 occupied), with
+ * probabilities p10, p01 of the circuit of gates 0..gi (xf_probabilities in
+ * `mode` with t samples and seed (seed + gi) mod 2^64, the candidates of the
+ * chains that move ordered by chain, c10 before c01): c10 if
+ * u (p10 + p01) < p10 in FP64, u = w 2^-32 with w word 0 of Philox4x32-10 at
+ * counter (lo32(s), gi, 2^32 - 2, hi32(s)) and key (lo32(seed), hi32(seed)),
+ * s the chain; a chain with p10 + p01 = 0 stays.  With exact probabilities the
+ * samples follow the output distribution exactly; with Raw Estimate,
+ * approximately.  Same gate rules as xf_circuit_from_gates; input as for
+ * xf_plan_create; h_samples host [S].  Creates a plan on `device` per run of
+ * matchgates between CPhase gates, allocates device memory for 2S
+ * candidates, and synchronises hip_stream.  Errors: those of
+ * xf_circuit_from_gates, xf_plan_create and xf_probabilities. */
+xf_status xf_sample_gates(int32_t n, int32_t n_gates, const xf_gate *gates, xf_bits128 input, int64_t S,
+                          xf_mode mode, int64_t t, uint64_t seed, xf_precision precision, int device,
+                          xf_bits128 *h_samples, void *hip_stream);
+
 /* Gradient of L = sum_b g_b log p_b, g = d_grad_logp (device [B] doubles),
  * with respect to every rotation entry (h_grad_rot, host [n_rot][n][n][2],
  * as dL/dRe + i dL/dIm) and every angle (h_grad_theta, host [k]).  Same

@@ -264,6 +264,42 @@ def circuit_from_gates(n: int, gates):
             np.array(theta, dtype=np.float64))
 
 
+def sample_gates(n: int, gates, input_bits, S: int, mode: str = "exact", t: int = 0, seed: int = 0):
+    """Weak simulation by the gate-by-gate algorithm (Bravyi, Gosset and Liu,
+    2022; Sec. II-A names it): S chains start at the input; at matchgate gi
+    on (q, q + 1) every chain with one particle on the pair moves to c10 or
+    c01 with the probabilities of the circuit of gates 0..gi (Exact or Raw
+    Estimate with t samples and seed + gi; candidates of the moving chains in
+    chain order, c10 first), taking c10 when u (p10 + p01) < p10 with
+    u = word 0 of Philox4x32-10 at (lo32(s), gi, 2^32 - 2, hi32(s)) times
+    2^-32; CPhase gates change nothing.  Returns [S, 2] uint64."""
+    inp = np.asarray(input_bits, dtype=np.uint64).reshape(2)
+    x = [(int(inp[0]) | (int(inp[1]) << 64)) for _ in range(S)]
+    key = [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF]
+    for gi, g in enumerate(gates):
+        if g[0] != "mg":
+            continue
+        q = g[1]
+        movers = [s for s in range(S) if ((x[s] >> q) & 1) + ((x[s] >> (q + 1)) & 1) == 1]
+        if not movers:
+            continue
+        cands = []
+        for s in movers:
+            base = x[s] & ~((1 << q) | (1 << (q + 1)))
+            cands += [base | (1 << q), base | (1 << (q + 1))]
+        rot, pairs, layer, theta = circuit_from_gates(n, gates[:gi + 1])
+        cb = np.array([[c & 0xFFFFFFFFFFFFFFFF, c >> 64] for c in cands], dtype=np.uint64)
+        pr = probabilities(rot, pairs, layer, theta, inp, cb, mode, t=t, seed=(seed + gi) % (1 << 64))
+        for a, s in enumerate(movers):
+            p10, p01 = float(pr[2 * a]), float(pr[2 * a + 1])
+            if not p10 + p01 > 0.0:
+                continue
+            w = int(philox4x32_10([s & 0xFFFFFFFF, gi, 0xFFFFFFFE, s >> 32], key)[0])
+            u = w * 2.0 ** -32
+            x[s] = cands[2 * a] if u * (p10 + p01) < p10 else cands[2 * a + 1]
+    return np.array([[v & 0xFFFFFFFFFFFFFFFF, v >> 64] for v in x], dtype=np.uint64).reshape(-1, 2)
+
+
 def round_to_four_bits(t: int) -> int:
     """The smallest integer >= t of the form m * 2^e with m < 16."""
     e = max(0, t.bit_length() - 4)

@@ -50,7 +50,7 @@ EXPORTS = ["xf_plan_create", "xf_plan_set_params", "xf_plan_refreeze", "xf_plan_
            "xf_log_prob_backward",
            "xf_plan_last_term_count", "xf_plan_last_work", "xf_plan_set_evaluation", "xf_plan_set_workspace_limit", "xf_plan_set_mixed_condition",
            "xf_expm_antihermitian", "xf_expm_adjoint", "xf_spin_rotations", "xf_spin_rotations_adjoint",
-           "xf_antihermitian_reals_grad", "xf_circuit_from_gates", "xf_last_error"]
+           "xf_antihermitian_reals_grad", "xf_circuit_from_gates", "xf_sample_gates", "xf_last_error"]
 
 _lib = None
 
@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
     L.xf_spin_rotations.argtypes = [I32, I32, P, P]
     L.xf_spin_rotations_adjoint.argtypes = [I32, I32, P, P, P]
     L.xf_antihermitian_reals_grad.argtypes = [I32, P, P]
+    L.xf_sample_gates.argtypes = [I32, I32, P, Bits128, I64, S, I64, U64, S, ctypes.c_int, P, P]
     L.xf_circuit_from_gates.argtypes = [I32, I32, P, I32, I32, P, P, P, P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     L.xf_last_error.argtypes = []
     L.xf_last_error.restype = ctypes.c_char_p

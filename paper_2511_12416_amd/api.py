@@ -269,12 +269,7 @@ def antihermitian_reals_grad(G_K) -> np.ndarray:
     return g
 
 
-def circuit_from_gates(n: int, gates):
-    """Layered circuit (rot [n_rot, n, n] complex, pairs [k, 2], layer [k],
-    theta [k]) of a gate list in time order, through xf_circuit_from_gates.
-    Gates: ("mg", q, G) for a matchgate G(A, B) (4 x 4 complex, basis
-    |x_q x_{q+1}> = 00, 01, 10, 11) on qubits (q, q + 1), ("cp", q0, q1, theta)
-    for a controlled-phase gate."""
+def _gate_array(gates):
     arr = (_abi.Gate * max(len(gates), 1))()
     for i, gt in enumerate(gates):
         if gt[0] == "mg":
@@ -287,6 +282,31 @@ def circuit_from_gates(n: int, gates):
             arr[i].theta = float(gt[3])
         else:
             raise ValueError(f"unknown gate kind {gt[0]!r}")
+    return arr
+
+
+def sample_gates(n: int, gates, input_bits, S: int, mode: str = "exact", t: int = 0, seed: int = 0,
+                 precision: str = "fp64", device: int = 0) -> np.ndarray:
+    """S output samples ([S, 2] uint64 bit patterns) of a gate list by
+    gate-by-gate sampling (xf_sample_gates)."""
+    arr = _gate_array(gates)
+    ib = np.asarray(input_bits, dtype=np.uint64).reshape(2)
+    b = _abi.Bits128()
+    b.w[0], b.w[1] = int(ib[0]), int(ib[1])
+    out = np.zeros((max(S, 1), 2), dtype=np.uint64)
+    check(lib().xf_sample_gates(int(n), len(gates), arr, b, int(S), _MODES[mode], int(t),
+                                int(seed) & 0xFFFFFFFFFFFFFFFF, _PREC[precision], int(device), _ptr(out),
+                                _stream_handle(torch.device("cuda", int(device)))))
+    return out[:S]
+
+
+def circuit_from_gates(n: int, gates):
+    """Layered circuit (rot [n_rot, n, n] complex, pairs [k, 2], layer [k],
+    theta [k]) of a gate list in time order, through xf_circuit_from_gates.
+    Gates: ("mg", q, G) for a matchgate G(A, B) (4 x 4 complex, basis
+    |x_q x_{q+1}> = 00, 01, 10, 11) on qubits (q, q + 1), ("cp", q0, q1, theta)
+    for a controlled-phase gate."""
+    arr = _gate_array(gates)
     nr, k = ctypes.c_int32(), ctypes.c_int32()
     L = lib()
     check(L.xf_circuit_from_gates(int(n), len(gates), arr, 0, 0, None, None, None, None, ctypes.byref(nr),

@@ -1187,6 +1187,121 @@ xf_status xf_circuit_from_gates(int32_t n, int32_t n_gates, const xf_gate *gates
     return ok();
 }
 
+}  // extern "C"
+
+namespace {
+
+// Philox4x32-10 (Salmon et al., SC'11) on the host, for the sampling
+// decisions of xf_sample_gates.
+void philox_host(const uint32_t ctr_in[4], uint32_t k0, uint32_t k1, uint32_t out[4]) {
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0, out[1] = c1, out[2] = c2, out[3] = c3;
+}
+
+struct PlanHolder {
+    xf_plan *p = nullptr;
+    ~PlanHolder() {
+        if (p) xf_plan_destroy(p);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+xf_status xf_sample_gates(int32_t n, int32_t n_gates, const xf_gate *gates, xf_bits128 input, int64_t S, xf_mode mode,
+                          int64_t t, uint64_t seed, xf_precision precision, int device, xf_bits128 *h_samples,
+                          void *hip_stream) {
+    if (S < 0 || (S > 0 && !h_samples)) return fail(XF_EINVAL, "invalid sample output");
+    if (mode != XF_EXACT && mode != XF_RAW_ESTIMATE) return fail(XF_EINVAL, "unknown mode");
+    int32_t nr_all = 0, k_all = 0;
+    xf_status st = xf_circuit_from_gates(n, n_gates, gates, 0, 0, nullptr, nullptr, nullptr, nullptr, &nr_all,
+                                         &k_all);
+    if (st != XF_OK) return st;
+    for (int64_t s = 0; s < S; ++s) h_samples[s] = input;
+    if (S == 0) return ok();
+    hipStream_t hs = (hipStream_t)hip_stream;
+    DeviceGuard guard(device);
+    if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice(%d) failed", device);
+    DevScratch dbits, dprob;
+    if (hipMalloc(&dbits.p, (size_t)2 * S * sizeof(xf_bits128)) != hipSuccess ||
+        hipMalloc(&dprob.p, (size_t)2 * S * sizeof(double)) != hipSuccess)
+        return fail(XF_ENOMEM, "hipMalloc of %lld candidates failed", (long long)(2 * S));
+    std::vector<double> rot((size_t)nr_all * n * n * 2), th(std::max(k_all, 1));
+    std::vector<int32_t> pairs(2 * std::max(k_all, 1)), layer(std::max(k_all, 1));
+    std::vector<xf_bits128> cand((size_t)2 * S);
+    std::vector<int64_t> chain((size_t)S);
+    std::vector<double> pc((size_t)2 * S);
+    PlanHolder plan;
+    int32_t plan_nr = -1, plan_k = -1;
+    for (int gi = 0; gi < n_gates; ++gi) {
+        const xf_gate &g = gates[gi];
+        if (g.kind != XF_GATE_MATCHGATE) continue;   // diagonal gates leave the distribution as it is
+        // chains whose pair (q, q + 1) holds one particle: two candidates
+        const int q = g.q0;
+        int64_t na = 0;
+        for (int64_t s = 0; s < S; ++s) {
+            const xf_bits128 x = h_samples[s];
+            const int b0 = (int)((x.w[q >> 6] >> (q & 63)) & 1), b1 = (int)((x.w[(q + 1) >> 6] >> ((q + 1) & 63)) & 1);
+            if (b0 + b1 != 1) continue;
+            xf_bits128 c10 = x, c01 = x;
+            c10.w[q >> 6] |= 1ull << (q & 63);
+            c10.w[(q + 1) >> 6] &= ~(1ull << ((q + 1) & 63));
+            c01.w[q >> 6] &= ~(1ull << (q & 63));
+            c01.w[(q + 1) >> 6] |= 1ull << ((q + 1) & 63);
+            cand[2 * na] = c10;
+            cand[2 * na + 1] = c01;
+            chain[na++] = s;
+        }
+        if (na == 0) continue;
+        // the circuit of gates 0..gi
+        int32_t nr = 0, k = 0;
+        if ((st = xf_circuit_from_gates(n, gi + 1, gates, nr_all, k_all, rot.data(), pairs.data(), layer.data(),
+                                        th.data(), &nr, &k)) != XF_OK)
+            return st;
+        if (!plan.p || nr != plan_nr || k != plan_k) {
+            if (plan.p) xf_plan_destroy(plan.p);
+            plan.p = nullptr;
+            const xf_circuit c = {n, nr, rot.data(), k, pairs.data(), layer.data(), th.data()};
+            if ((st = xf_plan_create(&c, input, precision, device, &plan.p)) != XF_OK) return st;
+            plan_nr = nr, plan_k = k;
+        } else if ((st = xf_plan_set_params(plan.p, rot.data(), th.data())) != XF_OK) {
+            return st;
+        }
+        if (hipMemcpyAsync(dbits.p, cand.data(), (size_t)2 * na * sizeof(xf_bits128), hipMemcpyHostToDevice, hs) !=
+            hipSuccess)
+            return fail(XF_EDEVICE, "upload of the candidates failed");
+        if ((st = xf_probabilities(plan.p, (const xf_bits128 *)dbits.p, 2 * na, mode, t, seed + (uint64_t)gi,
+                                   (double *)dprob.p, nullptr, nullptr, hip_stream)) != XF_OK)
+            return st;
+        if (hipMemcpyAsync(pc.data(), dprob.p, (size_t)2 * na * sizeof(double), hipMemcpyDeviceToHost, hs) !=
+                hipSuccess ||
+            hipStreamSynchronize(hs) != hipSuccess)
+            return fail(XF_EDEVICE, "download of the candidate probabilities failed");
+        for (int64_t a = 0; a < na; ++a) {
+            const int64_t s = chain[a];
+            const double p10 = pc[2 * a], p01 = pc[2 * a + 1];
+            if (!(p10 + p01 > 0.0)) continue;
+            const uint32_t ctr[4] = {(uint32_t)s, (uint32_t)gi, 0xFFFFFFFEu, (uint32_t)((uint64_t)s >> 32)};
+            uint32_t r[4];
+            philox_host(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), r);
+            const double u = (double)r[0] * 2.3283064365386963e-10;   // 2^-32
+            h_samples[s] = u * (p10 + p01) < p10 ? cand[2 * a] : cand[2 * a + 1];
+        }
+    }
+    return ok();
+}
+
 xf_status xf_plan_last_term_count(xf_plan *P, int64_t *count, int64_t *rank_sum) {
     if (!count) return fail(XF_EINVAL, "NULL output");
     xf_work w;
