@@ -16,18 +16,29 @@ size_t gen_lu_lds_bytes(const DevPlan &p, const GenPlan &g, bool exact) {
 // rest of the 160 KiB.
 constexpr size_t kGenMaxLds = 150 * 1024;
 
+template <bool EXACT, bool MIXED, bool MULTI>
+void launch_gen_tm(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int64_t b0, int64_t nb,
+                   const uint64_t *ekey, const int2 *ecnt, uint32_t *ecount, uint64_t cap, const uint64_t *xkeys,
+                   const double2 *xw, int64_t nkeys, double2 *hbuf, GenRec *rec, double *prob, double *amp,
+                   double *logp, unsigned long long *nterm, hipStream_t s) {
+    const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
+    hipLaunchKernelGGL((k_gen_setup<EXACT, MIXED, MULTI>), dim3(grid), dim3(kThreads), kGenSetupLds, s, p, g, bits,
+                       b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm);
+    hipLaunchKernelGGL((k_gen_eval<EXACT, MIXED, MULTI>), dim3(grid), dim3(kThreads), gen_lds_bytes(g), s, p, g, b0,
+                       nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, hbuf, rec, prob, amp, logp, nterm);
+}
+
 template <bool EXACT, bool MIXED>
 void launch_gen_t(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int64_t b0, int64_t nb,
                   const uint64_t *ekey, const int2 *ecnt, uint32_t *ecount, uint64_t cap, const uint64_t *xkeys,
-                  const double2 *xw, int64_t nkeys, double *prob, double *amp, double *logp,
-                  unsigned long long *nterm, hipStream_t s) {
-    const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
+                  const double2 *xw, int64_t nkeys, double2 *hbuf, GenRec *rec, double *prob, double *amp,
+                  double *logp, unsigned long long *nterm, hipStream_t s) {
     if (g.multi)
-        hipLaunchKernelGGL((k_gen_eval<EXACT, MIXED, true>), dim3(grid), dim3(kThreads), gen_lds_bytes(g), s, p, g,
-                           bits, b0, nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, prob, amp, logp, nterm);
+        launch_gen_tm<EXACT, MIXED, true>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, hbuf, rec,
+                                          prob, amp, logp, nterm, s);
     else
-        hipLaunchKernelGGL((k_gen_eval<EXACT, MIXED, false>), dim3(grid), dim3(kThreads), gen_lds_bytes(g), s, p, g,
-                           bits, b0, nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, prob, amp, logp, nterm);
+        launch_gen_tm<EXACT, MIXED, false>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, hbuf, rec,
+                                           prob, amp, logp, nterm, s);
 }
 
 }  // namespace
@@ -44,10 +55,14 @@ bool gen_applies(const DevPlan &p, const GenPlan &g) {
     return gen_lds_bytes(g) <= kGenMaxLds && sampler_lds_bytes(p.k) <= kMaxLds;
 }
 
+size_t gen_setup_bytes(const GenPlan &g) { return (size_t)g.hsize * 16 + sizeof(GenRec); }
+
 hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *bits,
                             int64_t b0, int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt,
-                            uint32_t *ecount, uint64_t cap, double *prob, double *amp, double *logp,
+                            uint32_t *ecount, uint64_t cap, void *setup, double *prob, double *amp, double *logp,
                             unsigned long long *nterm, hipEvent_t ev_mid, hipStream_t s) {
+    double2 *hbuf = (double2 *)setup;
+    GenRec *rec = (GenRec *)(hbuf + (size_t)nb * g.hsize);
     const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
     hipError_t e;
     if (all_lu) {
@@ -65,11 +80,11 @@ hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
     if (mixed)
-        launch_gen_t<false, true>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, nullptr, nullptr, 0, prob, amp, logp,
-                                  nterm, s);
+        launch_gen_t<false, true>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, nullptr, nullptr, 0, hbuf, rec, prob,
+                                  amp, logp, nterm, s);
     else
-        launch_gen_t<false, false>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, nullptr, nullptr, 0, prob, amp, logp,
-                                   nterm, s);
+        launch_gen_t<false, false>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, nullptr, nullptr, 0, hbuf, rec, prob,
+                                   amp, logp, nterm, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // then the bitstrings the evaluation deferred, on a smaller grid (its
     // workgroups skip the other bitstrings at once)
@@ -81,17 +96,19 @@ hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool
 
 hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *keys,
                             const double2 *w, int64_t nkeys, const uint64_t *bits, int64_t B, uint32_t *flags,
-                            double *prob, double *amp, double *logp, unsigned long long *nterm, hipEvent_t ev_mid,
-                            hipStream_t s) {
+                            void *setup, double *prob, double *amp, double *logp, unsigned long long *nterm,
+                            hipEvent_t ev_mid, hipStream_t s) {
     hipError_t e;
+    double2 *hbuf = (double2 *)setup;
+    GenRec *rec = (GenRec *)(hbuf + (size_t)B * g.hsize);
     if (all_lu) {
         if ((e = launch_fill_u32(flags, B, kEntryDeferred, s)) != hipSuccess) return e;
     } else if (mixed)
-        launch_gen_t<true, true>(p, g, bits, 0, B, nullptr, nullptr, flags, 0, keys, w, nkeys, prob, amp, logp,
-                                 nterm, s);
+        launch_gen_t<true, true>(p, g, bits, 0, B, nullptr, nullptr, flags, 0, keys, w, nkeys, hbuf, rec, prob, amp,
+                                 logp, nterm, s);
     else
-        launch_gen_t<true, false>(p, g, bits, 0, B, nullptr, nullptr, flags, 0, keys, w, nkeys, prob, amp, logp,
-                                  nterm, s);
+        launch_gen_t<true, false>(p, g, bits, 0, B, nullptr, nullptr, flags, 0, keys, w, nkeys, hbuf, rec, prob, amp,
+                                  logp, nterm, s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
@@ -103,7 +120,11 @@ hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool
 
 hipError_t prepare_gen() {
     hipError_t e;
-    for (const void *f : {(const void *)k_gen_eval<false, false, false>, (const void *)k_gen_eval<false, true, false>,
+    for (const void *f : {(const void *)k_gen_setup<false, false, false>, (const void *)k_gen_setup<false, true, false>,
+                          (const void *)k_gen_setup<true, false, false>, (const void *)k_gen_setup<true, true, false>,
+                          (const void *)k_gen_setup<false, false, true>, (const void *)k_gen_setup<false, true, true>,
+                          (const void *)k_gen_setup<true, false, true>, (const void *)k_gen_setup<true, true, true>,
+                          (const void *)k_gen_eval<false, false, false>, (const void *)k_gen_eval<false, true, false>,
                           (const void *)k_gen_eval<true, false, false>, (const void *)k_gen_eval<true, true, false>,
                           (const void *)k_gen_eval<false, false, true>, (const void *)k_gen_eval<false, true, true>,
                           (const void *)k_gen_eval<true, false, true>, (const void *)k_gen_eval<true, true, true>,

@@ -801,23 +801,102 @@ __device__ __forceinline__ void write_result(int64_t b, double2 total, double sc
     if (logp) logp[b] = log(pb);
 }
 
-// Raw Estimate (EXACT = false; the entries of bitstring i are in the
-// workspace, written by k_sample_entries) or exact mode (EXACT = true; the
-// plan's shared term list, ecount[i] is a flag written here).  Bitstrings
-// whose base is singular or ill-conditioned, or with a pattern beyond
-// kGenMaxRank in a block, get ecount[i] = kEntryDeferred, as do (from the
-// sampler) those whose patterns overflowed the workspace region; they are
-// left to k_gen_lu.
+// The evaluation runs in two kernels per chunk of bitstrings, so that the
+// setup (base inverses and the products forming H, long dependent chains of
+// small steps) runs at the occupancy its small footprint allows, and the
+// pattern evaluation at its own:
+//   k_gen_setup: per bitstring and block, the base M_B, its inverse, X and H
+//     (gen_setup_block); H goes to the bitstring's slot of a workspace (hsize
+//     complex entries, the blocks at hoff with row stride hld), det M_B and
+//     the base patterns to a GenRec.
+//   k_gen_eval: per bitstring, H back into LDS and every distinct pattern's
+//     r x r determinant, summed exactly.
+// Flags in ecount[i] (Raw Estimate: the sampler's entry count; exact mode:
+// written by the setup): kEntryInvalid once p = 0 is written, kEntryDeferred
+// for the bitstrings left to k_gen_lu (singular or ill-conditioned bases, a
+// pattern beyond kGenMaxRank in a block, or, from the sampler, patterns that
+// overflowed the workspace region).
+struct GenRec {
+    double2 det;          // product over blocks of det M_B
+    uint64_t shift[2];    // base pattern of each block (positions)
+};
+
+// LDS bytes of k_gen_setup: the setup scratch and the blocks' input columns
+// and active modes.
+constexpr size_t kGenSetupLds = kGenSetupBytes + 128 + 64;
+
 template <bool EXACT, bool MIXED, bool MULTI>
-__global__ void __launch_bounds__(kThreads, 1)
-k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
-           const uint64_t *__restrict__ ekey, const int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount,
-           uint64_t cap, const uint64_t *__restrict__ xkeys, const double2 *__restrict__ xw, int64_t nkeys,
-           double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
-           unsigned long long *nterm) {
+__global__ void __launch_bounds__(kThreads, 2)
+k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
+            uint32_t *__restrict__ ecount, double2 *__restrict__ hbuf, GenRec *__restrict__ rec,
+            double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
+            unsigned long long *nterm) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok;
     __shared__ GenShared sh;
+    __shared__ uint8_t s_Rb[128];
+    const int tid = threadIdx.x;
+    GenLds T;
+    T.act = smem + kGenSetupBytes;
+    T.col = T.act + 128;
+    T.kbt = nullptr;
+    T.R1a = T.gpiv = nullptr;
+    for (int e = tid; e < 2 * kGenMaxKb; e += kThreads) T.act[e] = g.act[e];
+    for (int e = tid; e < 2 * kGenMaxM; e += kThreads) T.col[e] = g.col[e];
+    __syncthreads();
+    Work wk;
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int64_t b = b0 + i;
+        bool zero = false;
+        if constexpr (!EXACT) {
+            const uint32_t ne = ecount[i];
+            if (ne == kEntryDeferred) continue;   // overflowed its region: k_gen_lu takes it
+            zero = ne == kEntryInvalid;
+        }
+        if (!zero) zero = !load_bitstring(p, bits, b, s_Rb, &s_ok);
+        if (!zero) {
+            gen_rows(p, g, s_Rb, sh);
+            __syncthreads();
+            zero = sh.ok == 0;
+            __syncthreads();
+        }
+        if (zero) {
+            if (tid == 0) {
+                write_zero(b, prob, amp, logp);
+                ecount[i] = kEntryInvalid;
+            }
+            __syncthreads();
+            continue;
+        }
+        T.H = hbuf + (size_t)i * g.hsize;
+        bool ok = true;
+        for (int blk = 0; blk < g.nblk && ok; ++blk)
+            ok = gen_setup_block<MIXED, MULTI>(p, g, T, blk, smem, sh, wk);
+        if (tid == 0) {
+            if (ok) {
+                GenRec r;
+                r.det = sh.det;
+                r.shift[0] = sh.shift[0];
+                r.shift[1] = sh.shift[1];
+                rec[i] = r;
+                if constexpr (EXACT) ecount[i] = 0;
+            } else {
+                ecount[i] = kEntryDeferred;
+            }
+        }
+        __syncthreads();
+    }
+    flush_work(wk, nterm);
+}
+
+template <bool EXACT, bool MIXED, bool MULTI>
+__global__ void __launch_bounds__(kThreads, 1)
+k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restrict__ ekey,
+           const int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount, uint64_t cap,
+           const uint64_t *__restrict__ xkeys, const double2 *__restrict__ xw, int64_t nkeys,
+           const double2 *__restrict__ hbuf, const GenRec *__restrict__ rec, double *__restrict__ prob,
+           double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t s_acc[kAccWords];
     const RawSmem s = carve_raw(smem, 0, p.n, 4, false);
     const GenLds T = carve_gen(smem, g);
@@ -826,36 +905,16 @@ k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, 
     load_gen_tables(p, g, T);
     for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
         const int64_t b = b0 + i;
-        uint32_t ne = 0;
-        bool zero = false;
-        if constexpr (!EXACT) {
-            ne = ecount[i];
-            if (ne == kEntryDeferred) continue;   // overflowed its region: k_gen_lu takes it
-            zero = ne == kEntryInvalid;
-        }
-        if (!zero) zero = !load_bitstring(p, bits, b, s.Rb, &s_ok);
-        if (!zero) {
-            gen_rows(p, g, s.Rb, sh);
-            __syncthreads();
-            zero = sh.ok == 0;
-            __syncthreads();
-        }
-        if (zero) {
-            if (tid == 0) {
-                write_zero(b, prob, amp, logp);
-                if constexpr (EXACT) ecount[i] = 0;
-            }
-            __syncthreads();
-            continue;
-        }
-        bool ok = true;
-        for (int blk = 0; blk < g.nblk && ok; ++blk)
-            ok = gen_setup_block<MIXED, MULTI>(p, g, T, blk, (unsigned char *)smem, sh, wk);
-        const double2 detB = sh.det;
-        const uint64_t shift[2] = {sh.shift[0], sh.shift[1]};
+        const uint32_t flag = ecount[i];
+        if (flag == kEntryDeferred || flag == kEntryInvalid) continue;
+        const double2 detB = rec[i].det;
+        const uint64_t shift[2] = {rec[i].shift[0], rec[i].shift[1]};
+        const double2 *Hg = hbuf + (size_t)i * g.hsize;
+        for (int e = tid; e < g.hsize; e += kThreads) T.H[e] = Hg[e];
         acc_clear(s_acc);
         __syncthreads();
-        const int64_t nent = EXACT ? nkeys : (int64_t)ne;
+        const int64_t nent = EXACT ? nkeys : (int64_t)flag;
+        bool ok = true;
         for (int64_t c0 = 0; ok && c0 < nent; c0 += kHashSlots) {
             const int nc = (int)min((int64_t)kHashSlots, nent - c0);
             for (int e = tid; e < nc; e += kThreads) {
@@ -875,10 +934,7 @@ k_gen_eval(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, 
             continue;
         }
         const double2 total = acc_value(s_acc);
-        if (tid == 0) {
-            write_result(b, total, EXACT ? 1.0 : p.scale, prob, amp, logp);
-            if constexpr (EXACT) ecount[i] = 0;
-        }
+        if (tid == 0) write_result(b, total, EXACT ? 1.0 : p.scale, prob, amp, logp);
         __syncthreads();
     }
     flush_work(wk, nterm);

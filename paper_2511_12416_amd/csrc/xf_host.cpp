@@ -161,6 +161,7 @@ struct xf_plan {
     xf::GenPlan gen{};
     DevBuf dgcol, dgact, dgpos0, dgpos1, dgblk, dgkbt, dggpos, dflags;
     DevBuf dgGA, dgHC, dgTT;          // more than two CPhase layers: the factors of each block's positions
+    DevBuf dgsetup;                   // general lemma: per-bitstring H and base records
     int last_gen = 0;                 // the last xf_probabilities call used the general lemma kernel
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
@@ -615,7 +616,7 @@ void plan_free(xf_plan *P) {
                       &P->fA2, &P->fQ, &P->fR1, &P->dkeymode, &P->dT, &P->dgkey, &P->dgmode,
                       &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
                       &P->dgsum, &P->dekey, &P->decnt, &P->decount, &P->dgcol, &P->dgact, &P->dgpos0,
-                      &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dggpos, &P->dflags, &P->dgGA, &P->dgHC, &P->dgTT})
+                      &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dggpos, &P->dflags, &P->dgGA, &P->dgHC, &P->dgTT, &P->dgsetup})
         dev_free(*b);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();
@@ -878,21 +879,25 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
     uint64_t *ekey = nullptr;
     int2 *ecnt = nullptr;
     uint32_t *ecount = nullptr;
+    void *setup = nullptr;   // general lemma: per-bitstring H and base records
+    const uint64_t setup_bytes = gen ? (uint64_t)xf::gen_setup_bytes(P->gen) : 0;
     if (lemma && B > 0) {
         cap = xf::lemma_entry_cap(t);
-        const uint64_t per_bits = cap * 16 + 4;
+        const uint64_t per_bits = cap * 16 + 4 + setup_bytes;
         if (noalloc) {
-            if (per_bits > xf::kNoAllocScratchBytes)
+            if (per_bits + 256 > xf::kNoAllocScratchBytes)
                 return fail(XF_EUNSUPPORTED, "t = %lld needs %llu bytes of scratch per bitstring; the no-allocation "
                             "scratch holds %llu", (long long)t, (unsigned long long)per_bits,
                             (unsigned long long)xf::kNoAllocScratchBytes);
-            chunk = std::min<int64_t>(B, (int64_t)(xf::kNoAllocScratchBytes / per_bits));
+            chunk = std::min<int64_t>(B, (int64_t)((xf::kNoAllocScratchBytes - 256) / per_bits));
         } else {
             chunk = std::min<int64_t>(B, (int64_t)std::max<uint64_t>(1, P->entry_budget / per_bits));
         }
         nchunks = (B + chunk - 1) / chunk;
     }
-    if (noalloc && mode == XF_EXACT && gen && (uint64_t)B * 4 > xf::kNoAllocScratchBytes)
+    // exact mode: flags, then the setup records, 256-byte aligned
+    const uint64_t xflag_bytes = ((uint64_t)B * 4 + 255) & ~(uint64_t)255;
+    if (noalloc && mode == XF_EXACT && gen && xflag_bytes + (uint64_t)B * setup_bytes > xf::kNoAllocScratchBytes)
         return fail(XF_EUNSUPPORTED, "B = %lld exceeds the no-allocation scratch in exact mode", (long long)B);
     xf_status st;
     if (!noalloc) {
@@ -912,6 +917,14 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
             if ((st = dev_upload(P->dflags, nullptr, (size_t)B * 4))) return st;
         }
         if (mode == XF_EXACT) ecount = (uint32_t *)P->dflags.p;
+        const uint64_t need = (uint64_t)(mode == XF_EXACT ? B : chunk) * setup_bytes;
+        if (gen && B > 0 && need > 0) {
+            if (P->dgsetup.bytes < need) {
+                if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");
+                if ((st = dev_upload(P->dgsetup, nullptr, need))) return st;
+            }
+            setup = P->dgsetup.p;
+        }
     } else if ((lemma || (mode == XF_EXACT && gen)) && B > 0) {
         void *base = nullptr;
         if (xf::noalloc_scratch(P->device, &base) != hipSuccess)
@@ -920,8 +933,10 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
             ekey = (uint64_t *)base;
             ecnt = (int2 *)((unsigned char *)base + (size_t)chunk * cap * 8);
             ecount = (uint32_t *)((unsigned char *)base + (size_t)chunk * cap * 16);
+            setup = (unsigned char *)base + (((size_t)chunk * (cap * 16 + 4) + 255) & ~(size_t)255);
         } else {
             ecount = (uint32_t *)base;
+            setup = (unsigned char *)base + xflag_bytes;
         }
     }
     if (xf::launch_zero_u64((unsigned long long *)P->dnterm.p, s) != hipSuccess)
@@ -944,8 +959,8 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
                     e = xf::launch_lemma_chunk(d, (const uint64_t *)d_bits, b0, nb, t, seed, ekey, ecnt, ecount, cap,
                                                d_prob, d_amp, d_logp, nterm, mid, s);
                 else
-                    e = xf::launch_gen_chunk(d, P->gen, mixed, all_lu, (const uint64_t *)d_bits, b0, nb, t, seed, ekey, ecnt,
-                                             ecount, cap, d_prob, d_amp, d_logp, nterm, mid, s);
+                    e = xf::launch_gen_chunk(d, P->gen, mixed, all_lu, (const uint64_t *)d_bits, b0, nb, t, seed, ekey,
+                                             ecnt, ecount, cap, setup, d_prob, d_amp, d_logp, nterm, mid, s);
                 if (e == hipSuccess && timed) e = hipEventRecord(P->ev[2 + 2 * c], s);
             }
             P->nev = timed ? 1 + 2 * (int)nchunks : 0;
@@ -960,8 +975,8 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
     } else {
         if (gen) {
             e = xf::launch_gen_exact(d, P->gen, mixed, all_lu, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p,
-                                     P->nxterms, (const uint64_t *)d_bits, B, ecount, d_prob, d_amp, d_logp, nterm,
-                                     nullptr, s);
+                                     P->nxterms, (const uint64_t *)d_bits, B, ecount, setup, d_prob, d_amp, d_logp,
+                                     nterm, nullptr, s);
             P->last_gen = 1;
         } else {
             e = xf::launch_exact(d, mixed, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p, P->nxterms,

@@ -184,14 +184,17 @@ hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, c
 // flags[B] marking deferred bitstrings, then the LU kernel for those (all of
 // them with all_lu).
 bool gen_applies(const DevPlan &p, const GenPlan &g);
+// gen_setup_bytes: bytes per bitstring of the setup workspace the launchers
+// take in `setup` (each bitstring's H, then its base determinant and patterns).
+size_t gen_setup_bytes(const GenPlan &g);
 hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *bits,
                             int64_t b0, int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt,
-                            uint32_t *ecount, uint64_t cap, double *prob, double *amp, double *logp,
+                            uint32_t *ecount, uint64_t cap, void *setup, double *prob, double *amp, double *logp,
                             unsigned long long *nterm, hipEvent_t ev_mid, hipStream_t s);
 hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *keys,
                             const double2 *w, int64_t nkeys, const uint64_t *bits, int64_t B, uint32_t *flags,
-                            double *prob, double *amp, double *logp, unsigned long long *nterm, hipEvent_t ev_mid,
-                            hipStream_t s);
+                            void *setup, double *prob, double *amp, double *logp, unsigned long long *nterm,
+                            hipEvent_t ev_mid, hipStream_t s);
 hipError_t prepare_gen();
 // Device address of the no-allocation scratch on `device` (current), looked up
 // once per device (k_noalloc.hip).
