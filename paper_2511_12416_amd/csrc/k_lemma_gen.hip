@@ -4,17 +4,23 @@
 #include "sample_entries.h"
 
 namespace xf {
-namespace {
 
-size_t gen_lds_bytes(const GenPlan &g) { return kGenBaseBytes + gen_tables_bytes(g); }
+hipError_t launch_gen_eval_raw(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t b0, int64_t nb,
+                               const uint64_t *ekey, const int2 *ecnt, uint32_t *ecount, uint64_t cap,
+                               const double2 *hbuf, const GenRec *rec, double *prob, double *amp, double *logp,
+                               unsigned long long *nterm, int grid, hipStream_t s);
+hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t nb,
+                                 const uint64_t *xkeys, const double2 *xw, int64_t nkeys, uint32_t *flags,
+                                 const double2 *hbuf, const GenRec *rec, double *prob, double *amp, double *logp,
+                                 unsigned long long *nterm, int grid, hipStream_t s);
+hipError_t prepare_gen_eval_raw();
+hipError_t prepare_gen_eval_exact();
+
+namespace {
 
 size_t gen_lu_lds_bytes(const DevPlan &p, const GenPlan &g, bool exact) {
     return raw_lds_bytes(exact ? 0 : p.k, p.n, 4, false, false) + (g.multi ? kGenMultiLuBytes : 0);
 }
-
-// Dynamic LDS limit of k_gen_eval: the static per-bitstring state takes the
-// rest of the 160 KiB.
-constexpr size_t kGenMaxLds = 150 * 1024;
 
 template <bool EXACT, bool MIXED, bool MULTI>
 void launch_gen_tm(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int64_t b0, int64_t nb,
@@ -24,8 +30,16 @@ void launch_gen_tm(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int
     const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
     hipLaunchKernelGGL((k_gen_setup<EXACT, MIXED, MULTI>), dim3(grid), dim3(kThreads), kGenSetupLds, s, p, g, bits,
                        b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm);
-    hipLaunchKernelGGL((k_gen_eval<EXACT, MIXED, MULTI>), dim3(grid), dim3(kThreads), gen_lds_bytes(g), s, p, g, b0,
-                       nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, hbuf, rec, prob, amp, logp, nterm);
+    // patterns of more than 16 flipped positions in a block can occur only
+    // where a block has more than 16 active positions
+    bool wide = false;
+    for (int b = 0; b < g.nblk; ++b) wide = wide || g.kb[b] > 16;
+    if constexpr (EXACT)
+        launch_gen_eval_exact(p, g, MULTI, wide, nb, xkeys, xw, nkeys, ecount, hbuf, rec, prob, amp, logp, nterm,
+                              grid, s);
+    else
+        launch_gen_eval_raw(p, g, MULTI, wide, b0, nb, ekey, ecnt, ecount, cap, hbuf, rec, prob, amp, logp, nterm,
+                            grid, s);
 }
 
 template <bool EXACT, bool MIXED>
@@ -52,7 +66,7 @@ bool gen_applies(const DevPlan &p, const GenPlan &g) {
         if (m > kGenMaxM || kb > kGenMaxKb) return false;
         if (align16((size_t)m * 2 * m * 16) + (size_t)m * kb * 16 > kGenSetupBytes) return false;
     }
-    return gen_lds_bytes(g) <= kGenMaxLds && sampler_lds_bytes(p.k) <= kMaxLds;
+    return gen_lds_bytes(g, true) <= kGenMaxLds && sampler_lds_bytes(p.k) <= kMaxLds;
 }
 
 size_t gen_setup_bytes(const GenPlan &g) { return (size_t)g.hsize * 16 + sizeof(GenRec); }
@@ -120,14 +134,11 @@ hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool
 
 hipError_t prepare_gen() {
     hipError_t e;
+    if ((e = prepare_gen_eval_raw()) != hipSuccess || (e = prepare_gen_eval_exact()) != hipSuccess) return e;
     for (const void *f : {(const void *)k_gen_setup<false, false, false>, (const void *)k_gen_setup<false, true, false>,
                           (const void *)k_gen_setup<true, false, false>, (const void *)k_gen_setup<true, true, false>,
                           (const void *)k_gen_setup<false, false, true>, (const void *)k_gen_setup<false, true, true>,
                           (const void *)k_gen_setup<true, false, true>, (const void *)k_gen_setup<true, true, true>,
-                          (const void *)k_gen_eval<false, false, false>, (const void *)k_gen_eval<false, true, false>,
-                          (const void *)k_gen_eval<true, false, false>, (const void *)k_gen_eval<true, true, false>,
-                          (const void *)k_gen_eval<false, false, true>, (const void *)k_gen_eval<false, true, true>,
-                          (const void *)k_gen_eval<true, false, true>, (const void *)k_gen_eval<true, true, true>,
                           (const void *)k_gen_lu<false>, (const void *)k_gen_lu<true>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGenMaxLds)) != hipSuccess)
             return e;

@@ -44,8 +44,14 @@ constexpr int kGenMaxSteps = kGenMaxM / 4;   // 4-wide K slices of a product ove
 // Setup scratch (the augmented base and X) overlays the entry slots, pivot
 // scratch and reduction scratch of the RawSmem layout: 40960 bytes.
 constexpr size_t kGenSetupBytes = (size_t)kHashSlots * 16 + 2 * (size_t)kThreads * 16;
-// Bytes of the RawSmem layout without sampling tables or staged factors.
-constexpr size_t kGenBaseBytes = ((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + 15) & ~(size_t)15;
+// The pattern evaluation takes a bitstring's entries in chunks of SLOTS
+// (lane groups of 32: 2048, else 1024, so that two workgroups fit a CU);
+// bytes of its entry slots (keys, counts, list) and pivot and reduction
+// scratch.
+template <int SLOTS>
+constexpr size_t gen_base_bytes() {
+    return ((size_t)SLOTS * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 15) & ~(size_t)15;
+}
 constexpr uint16_t kNoPos = 0xFFFF;
 
 // Plan tables the general kernels keep in LDS (after the RawSmem layout):
@@ -63,9 +69,10 @@ __host__ __device__ __forceinline__ size_t gen_tables_bytes(const GenPlan &g) {
     return align16((size_t)g.hsize * 16) + (size_t)kThreads * 16 + align16((size_t)g.r1size * 16) + 256 + 128 + 64;
 }
 
+template <int SLOTS>
 __device__ __forceinline__ GenLds carve_gen(unsigned char *smem, const GenPlan &g) {
     GenLds t;
-    unsigned char *q = smem + kGenBaseBytes;
+    unsigned char *q = smem + gen_base_bytes<SLOTS>();
     t.H = (double2 *)q;
     q += align16((size_t)g.hsize * 16);
     t.gpiv = (double2 *)q;
@@ -672,8 +679,9 @@ __device__ __forceinline__ int rank_bin(int r) { return r <= 4 ? 0 : (r <= 8 ? 1
 // adds weight * det M_0 * prod det S_N to the bitstring's exact sum.  Entries
 // are classified by their largest block rank (counting sort into s.piv) so
 // that lanes and lane groups of a pass take like patterns.  Returns false if a
-// block flips more than kGenMaxRank positions.
-template <bool MULTI>
+// block flips more than kGenMaxRank positions, or, without BIG (no lane groups
+// of 32), more than 16.
+template <bool MULTI, bool BIG>
 __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan &g, const GenLds &T, const RawSmem &s,
                                                 int nl, const double2 *w, double2 detB, const uint64_t (&shift)[2],
                                                 Work &wk, uint64_t *sacc) {
@@ -688,7 +696,7 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
         atomicAdd(&cnt[rank_bin(gen_max_rank(pm))], 1);
     }
     __syncthreads();
-    if (cnt[4] > 0) return false;
+    if (cnt[4] > 0 || (!BIG && cnt[3] > 0)) return false;
     const int n0 = cnt[0], n1 = cnt[1], n2 = cnt[2], n3 = cnt[3];
     __syncthreads();
     if (tid == 0) {
@@ -759,7 +767,7 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
             }
         }
     }
-    {
+    if constexpr (BIG) {
         const int l32 = tid & 31, g32 = tid >> 5;
         for (int i = n0 + n1 + n2 + g32; i < n0 + n1 + n2 + n3; i += kThreads / 32) {
             const int e = order[i];
@@ -816,14 +824,32 @@ __device__ __forceinline__ void write_result(int64_t b, double2 total, double sc
 // for the bitstrings left to k_gen_lu (singular or ill-conditioned bases, a
 // pattern beyond kGenMaxRank in a block, or, from the sampler, patterns that
 // overflowed the workspace region).
-struct GenRec {
-    double2 det;          // product over blocks of det M_B
-    uint64_t shift[2];    // base pattern of each block (positions)
-};
+// A bitstring with a pattern of 17..32 flipped positions in a block, left by
+// the evaluation without lane groups of 32 to the one with them.
+constexpr uint32_t kEntryWide = 0xFFFFFFFCu;
 
 // LDS bytes of k_gen_setup: the setup scratch and the blocks' input columns
 // and active modes.
 constexpr size_t kGenSetupLds = kGenSetupBytes + 128 + 64;
+
+// Dynamic LDS of k_gen_eval, and the limit of the general kernels' dynamic
+// LDS (the static per-bitstring state takes the rest of the 160 KiB).
+__host__ __device__ __forceinline__ size_t gen_lds_bytes(const GenPlan &g, bool big) {
+    return (big ? gen_base_bytes<2048>() : gen_base_bytes<1024>()) + gen_tables_bytes(g);
+}
+
+// The entry slots of the pattern evaluation (the RawSmem fields it uses).
+template <int SLOTS>
+__device__ __forceinline__ RawSmem carve_eval(unsigned char *smem) {
+    RawSmem s{};
+    s.hkey = (uint64_t *)smem;
+    s.hcnt = (int2 *)(s.hkey + SLOTS);
+    s.piv = (double2 *)(s.hcnt + SLOTS);
+    s.red = s.piv + kThreads;
+    s.list = (uint16_t *)(s.red + kThreads);
+    return s;
+}
+constexpr size_t kGenMaxLds = 150 * 1024;
 
 template <bool EXACT, bool MIXED, bool MULTI>
 __global__ void __launch_bounds__(kThreads, 2)
@@ -878,6 +904,8 @@ k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0,
                 r.det = sh.det;
                 r.shift[0] = sh.shift[0];
                 r.shift[1] = sh.shift[1];
+                r.count = EXACT ? 0u : ecount[i];
+                r.pad[0] = r.pad[1] = r.pad[2] = 0;
                 rec[i] = r;
                 if constexpr (EXACT) ecount[i] = 0;
             } else {
@@ -889,7 +917,10 @@ k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0,
     flush_work(wk, nterm);
 }
 
-template <bool EXACT, bool MIXED, bool MULTI>
+// BIG: lane groups of 32 for patterns of 17..32 flipped positions in a block;
+// without, such bitstrings get kEntryWide (and keep their entries) for a
+// second pass with.  WIDE_ONLY: that second pass, over the kEntryWide ones.
+template <bool EXACT, bool MULTI, bool BIG, bool WIDE_ONLY>
 __global__ void __launch_bounds__(kThreads, 1)
 k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restrict__ ekey,
            const int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount, uint64_t cap,
@@ -898,25 +929,27 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
            double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t s_acc[kAccWords];
-    const RawSmem s = carve_raw(smem, 0, p.n, 4, false);
-    const GenLds T = carve_gen(smem, g);
+    constexpr int SLOTS = BIG ? 2048 : 1024;
+    const RawSmem s = carve_eval<SLOTS>(smem);
+    const GenLds T = carve_gen<SLOTS>(smem, g);
     const int tid = threadIdx.x;
     Work wk;
     load_gen_tables(p, g, T);
     for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
         const int64_t b = b0 + i;
         const uint32_t flag = ecount[i];
-        if (flag == kEntryDeferred || flag == kEntryInvalid) continue;
+        if (WIDE_ONLY ? flag != kEntryWide : (flag == kEntryDeferred || flag == kEntryInvalid || flag == kEntryWide))
+            continue;
         const double2 detB = rec[i].det;
         const uint64_t shift[2] = {rec[i].shift[0], rec[i].shift[1]};
         const double2 *Hg = hbuf + (size_t)i * g.hsize;
         for (int e = tid; e < g.hsize; e += kThreads) T.H[e] = Hg[e];
         acc_clear(s_acc);
         __syncthreads();
-        const int64_t nent = EXACT ? nkeys : (int64_t)flag;
+        const int64_t nent = EXACT ? nkeys : (int64_t)(WIDE_ONLY ? rec[i].count : flag);
         bool ok = true;
-        for (int64_t c0 = 0; ok && c0 < nent; c0 += kHashSlots) {
-            const int nc = (int)min((int64_t)kHashSlots, nent - c0);
+        for (int64_t c0 = 0; ok && c0 < nent; c0 += SLOTS) {
+            const int nc = (int)min((int64_t)SLOTS, nent - c0);
             for (int e = tid; e < nc; e += kThreads) {
                 if constexpr (EXACT) {
                     s.hkey[e] = xkeys[c0 + e];
@@ -926,10 +959,10 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
                 }
             }
             __syncthreads();
-            ok = gen_sum_entries<MULTI>(p, g, T, s, nc, EXACT ? xw + c0 : nullptr, detB, shift, wk, s_acc);
+            ok = gen_sum_entries<MULTI, BIG>(p, g, T, s, nc, EXACT ? xw + c0 : nullptr, detB, shift, wk, s_acc);
         }
         if (!ok) {
-            if (tid == 0) ecount[i] = kEntryDeferred;
+            if (tid == 0) ecount[i] = BIG ? kEntryDeferred : kEntryWide;
             __syncthreads();
             continue;
         }

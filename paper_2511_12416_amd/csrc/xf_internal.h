@@ -86,6 +86,14 @@ struct GenPlan {
     const double2 *GA, *HC, *TT;
 };
 
+// Per-bitstring record of the general lemma's setup kernel (see lemma_gen.h).
+struct GenRec {
+    double2 det;          // product over blocks of det M_B
+    uint64_t shift[2];    // base pattern of each block (positions)
+    uint32_t count;       // Raw Estimate: the bitstring's entry count
+    uint32_t pad[3];
+};
+
 // One partial gradient (of a workgroup of the lemma backward, or of a lane
 // group of the LU backward; complex entries, offsets in double2):
 //   oP   Gbar_P    n x G (row stride G)

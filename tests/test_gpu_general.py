@@ -206,3 +206,18 @@ def test_two_layer_bases_shift_past_singular_ones(X, mode):
     assert zero0.sum() > 10
     _check(p[zero0], ref[zero0], TOL_FP64, f"{mode} mode-0 occupied")
     _check(p, ref, TOL_FP64, f"{mode} all")
+
+
+def test_wide_patterns_take_the_second_pass(X):
+    """Raw Estimate with large angles on one block of 40 active modes:
+    patterns flip up to 40 positions, those of 17..32 go to the evaluation
+    with lane groups of 32, wider ones to the composition kernel; all match
+    the oracle."""
+    w = W.random_circuit(917, 44, 22, 20, n_rot=2, theta_scale=3.0, max_bits=64)
+    bits = w.bits[:24]
+    say("wide patterns: n=44 eta=22 k=20 theta~U[-3,3], t=600")
+    ref = oracle_probs(w, bits, mode="approx", t=600, seed=3)
+    plan = make_plan(w, X)
+    p = gpu_probs(plan, X, bits, "approx", 600, 3)
+    assert plan.last_work()["general"]
+    _check(p, ref, TOL_FP64, "wide fp64")
