@@ -8,12 +8,14 @@ namespace xf {
 hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t nb,
                                  const uint64_t *xkeys, const double2 *xw, int64_t nkeys, uint32_t *flags,
                                  const double2 *hbuf, const GenRec *rec, double *prob, double *amp, double *logp,
-                                 unsigned long long *nterm, int grid, hipStream_t s) {
+                                 unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s) {
     const size_t lds = gen_lds_bytes(g, true), lds16 = gen_lds_bytes(g, false);
-#define XF_EVAL(MULTI, BIG)                                                                                    \
-    hipLaunchKernelGGL((k_gen_eval<true, MULTI, BIG, false>), dim3(grid), dim3(kThreads), BIG ? lds : lds16, s, p, g, \
-                       (int64_t)0,                                                                              \
-                       nb, nullptr, nullptr, flags, (uint64_t)0, xkeys, xw, nkeys, hbuf, rec, prob, amp, logp, nterm)
+    const int64_t items = nb * nseg;
+    const int grid = (int)(items < kMaxGrid ? items : kMaxGrid);
+#define XF_EVAL(MULTI, BIG)                                                                                     \
+    hipLaunchKernelGGL((k_gen_eval<true, MULTI, BIG, false>), dim3(grid), dim3(kThreads), BIG ? lds : lds16, s, p, \
+                       g, (int64_t)0, nb, nullptr, nullptr, flags, (uint64_t)0, xkeys, xw, nkeys, hbuf, rec, prob,  \
+                       amp, logp, nterm, nseg, part)
     if (multi) {
         if (wide) XF_EVAL(true, true);
         else XF_EVAL(true, false);
@@ -22,6 +24,10 @@ hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi,
         else XF_EVAL(false, false);
     }
 #undef XF_EVAL
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nseg <= 1) return e;
+    hipLaunchKernelGGL(k_gen_reduce_segments, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, nb, nseg, flags, 0u,
+                       (const uint64_t *)part, prob, amp, logp);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ hipError_t launch_gen_eval_raw(const DevPlan &p, const GenPlan &g, bool multi, b
 #define XF_EVAL(MULTI, BIG, WIDE, GRID)                                                                           \
     hipLaunchKernelGGL((k_gen_eval<false, MULTI, BIG, WIDE>), dim3(GRID), dim3(kThreads), BIG ? lds : lds16, s, p, g, \
                        b0, nb, ekey,                                                                            \
-                       ecnt, ecount, cap, nullptr, nullptr, (int64_t)0, hbuf, rec, prob, amp, logp, nterm)
+                       ecnt, ecount, cap, nullptr, nullptr, (int64_t)0, hbuf, rec, prob, amp, logp, nterm, 1, nullptr)
     if (multi) {
         XF_EVAL(true, false, false, grid);
         if (wide) XF_EVAL(true, true, true, grid2);

@@ -12,7 +12,7 @@ hipError_t launch_gen_eval_raw(const DevPlan &p, const GenPlan &g, bool multi, b
 hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t nb,
                                  const uint64_t *xkeys, const double2 *xw, int64_t nkeys, uint32_t *flags,
                                  const double2 *hbuf, const GenRec *rec, double *prob, double *amp, double *logp,
-                                 unsigned long long *nterm, int grid, hipStream_t s);
+                                 unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s);
 hipError_t prepare_gen_eval_raw();
 hipError_t prepare_gen_eval_exact();
 
@@ -26,7 +26,7 @@ template <bool EXACT, bool MIXED, bool MULTI>
 void launch_gen_tm(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int64_t b0, int64_t nb,
                    const uint64_t *ekey, const int2 *ecnt, uint32_t *ecount, uint64_t cap, const uint64_t *xkeys,
                    const double2 *xw, int64_t nkeys, double2 *hbuf, GenRec *rec, double *prob, double *amp,
-                   double *logp, unsigned long long *nterm, hipStream_t s) {
+                   double *logp, unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s) {
     const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
     hipLaunchKernelGGL((k_gen_setup<EXACT, MIXED, MULTI>), dim3(grid), dim3(kThreads), kGenSetupLds, s, p, g, bits,
                        b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm);
@@ -36,7 +36,7 @@ void launch_gen_tm(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int
     for (int b = 0; b < g.nblk; ++b) wide = wide || g.kb[b] > 16;
     if constexpr (EXACT)
         launch_gen_eval_exact(p, g, MULTI, wide, nb, xkeys, xw, nkeys, ecount, hbuf, rec, prob, amp, logp, nterm,
-                              grid, s);
+                              nseg, part, s);
     else
         launch_gen_eval_raw(p, g, MULTI, wide, b0, nb, ekey, ecnt, ecount, cap, hbuf, rec, prob, amp, logp, nterm,
                             grid, s);
@@ -46,13 +46,13 @@ template <bool EXACT, bool MIXED>
 void launch_gen_t(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int64_t b0, int64_t nb,
                   const uint64_t *ekey, const int2 *ecnt, uint32_t *ecount, uint64_t cap, const uint64_t *xkeys,
                   const double2 *xw, int64_t nkeys, double2 *hbuf, GenRec *rec, double *prob, double *amp,
-                  double *logp, unsigned long long *nterm, hipStream_t s) {
+                  double *logp, unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s) {
     if (g.multi)
         launch_gen_tm<EXACT, MIXED, true>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, hbuf, rec,
-                                          prob, amp, logp, nterm, s);
+                                          prob, amp, logp, nterm, nseg, part, s);
     else
         launch_gen_tm<EXACT, MIXED, false>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, hbuf, rec,
-                                           prob, amp, logp, nterm, s);
+                                           prob, amp, logp, nterm, nseg, part, s);
 }
 
 }  // namespace
@@ -71,6 +71,12 @@ bool gen_applies(const DevPlan &p, const GenPlan &g) {
 
 size_t gen_setup_bytes(const GenPlan &g) { return (size_t)g.hsize * 16 + sizeof(GenRec); }
 
+int gen_exact_segments(int64_t B, int64_t nkeys) {
+    if (B <= 0 || B >= 1024) return 1;
+    const int64_t want = (4096 + B - 1) / B, most = (nkeys + 255) / 256;
+    return (int)(want < most ? want : (most > 0 ? most : 1));
+}
+
 hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *bits,
                             int64_t b0, int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt,
                             uint32_t *ecount, uint64_t cap, void *setup, double *prob, double *amp, double *logp,
@@ -85,7 +91,7 @@ hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool
         if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
         hipLaunchKernelGGL((k_gen_lu<false>), dim3(grid < 2048 ? grid : 2048), dim3(kThreads),
                            gen_lu_lds_bytes(p, g, false), s, p, g, bits, b0, nb, (uint32_t)t, seed, ecount, nullptr,
-                           nullptr, (int64_t)0, prob, amp, logp, nterm);
+                           nullptr, (int64_t)0, prob, amp, logp, nterm, 1, nullptr);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_sample_entries<kSamplerThreads>), dim3(grid), dim3(kSamplerThreads),
@@ -95,16 +101,16 @@ hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
     if (mixed)
         launch_gen_t<false, true>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, nullptr, nullptr, 0, hbuf, rec, prob,
-                                  amp, logp, nterm, s);
+                                  amp, logp, nterm, 1, nullptr, s);
     else
         launch_gen_t<false, false>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, nullptr, nullptr, 0, hbuf, rec, prob,
-                                   amp, logp, nterm, s);
+                                   amp, logp, nterm, 1, nullptr, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // then the bitstrings the evaluation deferred, on a smaller grid (its
     // workgroups skip the other bitstrings at once)
     hipLaunchKernelGGL((k_gen_lu<false>), dim3(grid < 2048 ? grid : 2048), dim3(kThreads),
                        gen_lu_lds_bytes(p, g, false), s, p, g, bits, b0, nb, (uint32_t)t, seed, ecount, nullptr,
-                       nullptr, (int64_t)0, prob, amp, logp, nterm);
+                       nullptr, (int64_t)0, prob, amp, logp, nterm, 1, nullptr);
     return hipGetLastError();
 }
 
@@ -115,20 +121,28 @@ hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool
     hipError_t e;
     double2 *hbuf = (double2 *)setup;
     GenRec *rec = (GenRec *)(hbuf + (size_t)B * g.hsize);
+    // few bitstrings: each term list split over segments so that about 4096
+    // workgroups take part; their partial sums follow the records
+    const int nseg = gen_exact_segments(B, nkeys);
+    uint64_t *part = (uint64_t *)(rec + B);
     if (all_lu) {
         if ((e = launch_fill_u32(flags, B, kEntryDeferred, s)) != hipSuccess) return e;
     } else if (mixed)
         launch_gen_t<true, true>(p, g, bits, 0, B, nullptr, nullptr, flags, 0, keys, w, nkeys, hbuf, rec, prob, amp,
-                                 logp, nterm, s);
+                                 logp, nterm, nseg, part, s);
     else
         launch_gen_t<true, false>(p, g, bits, 0, B, nullptr, nullptr, flags, 0, keys, w, nkeys, hbuf, rec, prob, amp,
-                                  logp, nterm, s);
+                                  logp, nterm, nseg, part, s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
-    const int grid = (int)(B < 2048 ? B : 2048);
+    const int64_t items = B * (int64_t)nseg;
+    const int grid = (int)(items < 2048 ? items : 2048);
     hipLaunchKernelGGL((k_gen_lu<true>), dim3(grid), dim3(kThreads), gen_lu_lds_bytes(p, g, true), s, p, g, bits,
-                       (int64_t)0, B, 0u, (uint64_t)0, flags, keys, w, nkeys, prob, amp, logp, nterm);
+                       (int64_t)0, B, 0u, (uint64_t)0, flags, keys, w, nkeys, prob, amp, logp, nterm, nseg, part);
+    if ((e = hipGetLastError()) != hipSuccess || nseg <= 1) return e;
+    hipLaunchKernelGGL(k_gen_reduce_segments, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, B, nseg, flags,
+                       kEntryDeferred, (const uint64_t *)part, prob, amp, logp);
     return hipGetLastError();
 }
 

@@ -926,7 +926,8 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
            const int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount, uint64_t cap,
            const uint64_t *__restrict__ xkeys, const double2 *__restrict__ xw, int64_t nkeys,
            const double2 *__restrict__ hbuf, const GenRec *__restrict__ rec, double *__restrict__ prob,
-           double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
+           double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm, int nseg,
+           uint64_t *__restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t s_acc[kAccWords];
     constexpr int SLOTS = BIG ? 2048 : 1024;
@@ -935,7 +936,12 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
     const int tid = threadIdx.x;
     Work wk;
     load_gen_tables(p, g, T);
-    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+    // exact mode may split each bitstring's term list into nseg segments
+    // (multiples of 256 terms; work items i * nseg + j), whose exact partial
+    // sums k_gen_reduce_segments adds; otherwise one item per bitstring
+    const int64_t seglen = EXACT ? (((nkeys + nseg - 1) / nseg + 255) / 256) * 256 : 0;
+    for (int64_t item = blockIdx.x; item < nb * (int64_t)nseg; item += gridDim.x) {
+        const int64_t i = item / nseg, j = item % nseg;
         const int64_t b = b0 + i;
         const uint32_t flag = ecount[i];
         if (WIDE_ONLY ? flag != kEntryWide : (flag == kEntryDeferred || flag == kEntryInvalid || flag == kEntryWide))
@@ -946,9 +952,10 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
         for (int e = tid; e < g.hsize; e += kThreads) T.H[e] = Hg[e];
         acc_clear(s_acc);
         __syncthreads();
-        const int64_t nent = EXACT ? nkeys : (int64_t)(WIDE_ONLY ? rec[i].count : flag);
+        const int64_t lo = EXACT ? j * seglen : 0;
+        const int64_t nent = EXACT ? min(nkeys, lo + seglen) : (int64_t)(WIDE_ONLY ? rec[i].count : flag);
         bool ok = true;
-        for (int64_t c0 = 0; ok && c0 < nent; c0 += SLOTS) {
+        for (int64_t c0 = lo; ok && c0 < nent; c0 += SLOTS) {
             const int nc = (int)min((int64_t)SLOTS, nent - c0);
             for (int e = tid; e < nc; e += kThreads) {
                 if constexpr (EXACT) {
@@ -966,11 +973,36 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
             __syncthreads();
             continue;
         }
-        const double2 total = acc_value(s_acc);
-        if (tid == 0) write_result(b, total, EXACT ? 1.0 : p.scale, prob, amp, logp);
+        if (nseg > 1) {
+            if (tid < kAccWords) part[(size_t)item * 8 + tid] = s_acc[tid];
+        } else {
+            const double2 total = acc_value(s_acc);
+            if (tid == 0) write_result(b, total, EXACT ? 1.0 : p.scale, prob, amp, logp);
+        }
         __syncthreads();
     }
     flush_work(wk, nterm);
+}
+
+// The sum of a bitstring's segment partials (in segment order; the words are
+// exact integers, so the order does not change the result) for the
+// bitstrings whose flag is `want` (0: evaluated by k_gen_eval; kEntryDeferred:
+// by k_gen_lu).  One thread per bitstring.
+__global__ void k_gen_reduce_segments(int64_t nb, int nseg, const uint32_t *__restrict__ flags, uint32_t want,
+                                      const uint64_t *__restrict__ part, double *__restrict__ prob,
+                                      double *__restrict__ amp, double *__restrict__ logp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb || flags[i] != want) return;
+    Fix192 R, I;
+    uint64_t bad = 0;
+    for (int j = 0; j < nseg; ++j) {
+        const uint64_t *q = part + ((size_t)i * nseg + j) * 8;
+        fix_add(R, q[0], q[1], (int64_t)q[2]);
+        fix_add(I, q[3], q[4], (int64_t)q[5]);
+        bad |= q[6];
+    }
+    uint64_t acc[kAccWords] = {R.w0, R.w1, (uint64_t)R.w2, I.w0, I.w1, (uint64_t)I.w2, bad};
+    write_result(i, acc_value(acc), 1.0, prob, amp, logp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1154,7 +1186,7 @@ __global__ void __launch_bounds__(kThreads, 1)
 k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb, uint32_t t, uint64_t seed,
          const uint32_t *__restrict__ flags, const uint64_t *__restrict__ xkeys, const double2 *__restrict__ xw,
          int64_t nkeys, double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
-         unsigned long long *nterm) {
+         unsigned long long *nterm, int nseg, uint64_t *__restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok, s_n;
     __shared__ int s_cnt[6];
@@ -1168,7 +1200,11 @@ k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, in
     bool loaded = false;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t slot0 = hash_slot(0);
-    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+    // exact mode: segments of the term list as in k_gen_eval (nseg = 1 under
+    // Raw Estimate)
+    const int64_t seglen = EXACT ? (((nkeys + nseg - 1) / nseg + 255) / 256) * 256 : 0;
+    for (int64_t item = blockIdx.x; item < nb * (int64_t)nseg; item += gridDim.x) {
+        const int64_t i = item / nseg, j = item % nseg;
         if (flags[i] != kEntryDeferred) continue;
         const int64_t b = b0 + i;
         if (!EXACT && !loaded) {
@@ -1183,14 +1219,21 @@ k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, in
             __syncthreads();
         }
         if (zero) {
-            if (tid == 0) write_zero(b, prob, amp, logp);
+            if (tid == 0) {
+                if (nseg > 1) {
+                    for (int w = 0; w < 8; ++w) part[(size_t)item * 8 + w] = 0;
+                } else {
+                    write_zero(b, prob, amp, logp);
+                }
+            }
             __syncthreads();
             continue;
         }
         acc_clear(s_acc);
         if constexpr (EXACT) {
-            for (int64_t c0 = 0; c0 < nkeys; c0 += kHashSlots) {
-                const int nc = (int)min((int64_t)kHashSlots, nkeys - c0);
+            const int64_t hi = min(nkeys, j * seglen + seglen);
+            for (int64_t c0 = j * seglen; c0 < hi; c0 += kHashSlots) {
+                const int nc = (int)min((int64_t)kHashSlots, hi - c0);
                 __syncthreads();
                 for (int e = tid; e < nc; e += kThreads) {
                     s.hkey[e] = xkeys[c0 + e];
@@ -1216,8 +1259,12 @@ k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, in
                 clear_table(s, s_cnt, slot0, st);
             }
         }
-        const double2 total = acc_value(s_acc);
-        if (tid == 0) write_result(b, total, EXACT ? 1.0 : p.scale, prob, amp, logp);
+        if (nseg > 1) {
+            if (tid < kAccWords) part[(size_t)item * 8 + tid] = s_acc[tid];
+        } else {
+            const double2 total = acc_value(s_acc);
+            if (tid == 0) write_result(b, total, EXACT ? 1.0 : p.scale, prob, amp, logp);
+        }
         __syncthreads();
     }
     flush_work(wk, nterm);

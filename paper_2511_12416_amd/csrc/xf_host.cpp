@@ -895,9 +895,13 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
         }
         nchunks = (B + chunk - 1) / chunk;
     }
-    // exact mode: flags, then the setup records, 256-byte aligned
+    // exact mode: flags, then the setup records (and the segments' partial
+    // sums), 256-byte aligned
     const uint64_t xflag_bytes = ((uint64_t)B * 4 + 255) & ~(uint64_t)255;
-    if (noalloc && mode == XF_EXACT && gen && xflag_bytes + (uint64_t)B * setup_bytes > xf::kNoAllocScratchBytes)
+    const uint64_t xpart_bytes =
+        (mode == XF_EXACT && gen) ? (uint64_t)B * xf::gen_exact_segments(B, P->nxterms > 0 ? P->nxterms : ((int64_t)1 << P->k)) * 64 : 0;
+    if (noalloc && mode == XF_EXACT && gen &&
+        xflag_bytes + (uint64_t)B * setup_bytes + xpart_bytes > xf::kNoAllocScratchBytes)
         return fail(XF_EUNSUPPORTED, "B = %lld exceeds the no-allocation scratch in exact mode", (long long)B);
     xf_status st;
     if (!noalloc) {
@@ -917,7 +921,7 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
             if ((st = dev_upload(P->dflags, nullptr, (size_t)B * 4))) return st;
         }
         if (mode == XF_EXACT) ecount = (uint32_t *)P->dflags.p;
-        const uint64_t need = (uint64_t)(mode == XF_EXACT ? B : chunk) * setup_bytes;
+        const uint64_t need = (uint64_t)(mode == XF_EXACT ? B : chunk) * setup_bytes + xpart_bytes;
         if (gen && B > 0 && need > 0) {
             if (P->dgsetup.bytes < need) {
                 if (hipStreamSynchronize(s) != hipSuccess) return fail(XF_EDEVICE, "stream synchronisation failed");

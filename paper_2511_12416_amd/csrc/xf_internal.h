@@ -195,6 +195,10 @@ bool gen_applies(const DevPlan &p, const GenPlan &g);
 // gen_setup_bytes: bytes per bitstring of the setup workspace the launchers
 // take in `setup` (each bitstring's H, then its base determinant and patterns).
 size_t gen_setup_bytes(const GenPlan &g);
+// Exact mode: segments of each bitstring's term list (a batch of fewer than
+// 1024 bitstrings is spread over about 4096 workgroups); the setup workspace
+// then also holds B * segments partial sums of 64 bytes after the records.
+int gen_exact_segments(int64_t B, int64_t nkeys);
 hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *bits,
                             int64_t b0, int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt,
                             uint32_t *ecount, uint64_t cap, void *setup, double *prob, double *amp, double *logp,

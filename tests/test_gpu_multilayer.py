@@ -77,7 +77,11 @@ def test_random_benchmark_shape_exact(X):
     CPhase gates (2^16 trajectories), matchgates proportional to the size;
     exact probabilities of a few outcomes."""
     n, eta = 20, 10
-    gates, inp, bits = W.random_gate_circuit(85, n, eta, 16, n - 1, theta_scale=1.0, max_bits=8)
+    gates, inp, far = W.random_gate_circuit(85, n, eta, 16, n - 1, theta_scale=1.0, max_bits=4)
+    # outcomes near the input (where the weight is) and, from the uniform
+    # draw, far ones whose probability vanishes (every base singular: the
+    # composition kernel, split over segments)
+    bits = np.concatenate([W.nearby_outcomes(7, n, range(eta), 6, hops=4), far[:2]])
     rot, pairs, layer, theta = X.circuit_from_gates(n, gates)
     say(f"random benchmark shape: n={n} eta={eta} 16 CPhase layers, {len(bits)} outcomes, exact")
     ref = oracle.probabilities(rot, pairs, layer, theta, inp, bits, "exact")

@@ -322,3 +322,29 @@ def random_gate_circuit(seed: int, n: int, eta: int, n_cphase: int, mg_per_layer
         sel = random_fixed_weight(rng, np.arange(n), eta, max_bits)
         bits = np.array([bits_from_modes(c) for c in sel], dtype=np.uint64)
     return gates, bits_from_modes(range(eta)), bits
+
+
+def nearby_outcomes(seed: int, n: int, input_modes, count: int, hops: int = 3) -> np.ndarray:
+    """``count`` outcomes reached from the input occupation by ``hops``
+    random moves of one particle to a free neighbouring mode: the outcomes a
+    circuit of nearest-neighbour matchgates puts most of its weight on (an
+    outcome far from the input has a negligible probability).  Distinct,
+    seeded."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    start = sorted(int(q) for q in input_modes)
+    seen, out = set(), []
+    for _ in range(count * 200):
+        occ = set(start)
+        for _ in range(hops):
+            q = int(rng.choice(sorted(occ)))
+            d = int(rng.choice([-1, 1]))
+            if 0 <= q + d < n and q + d not in occ:
+                occ.remove(q)
+                occ.add(q + d)
+        key = tuple(sorted(occ))
+        if key not in seen:
+            seen.add(key)
+            out.append(bits_from_modes(key))
+        if len(out) == count:
+            break
+    return np.array(out, dtype=np.uint64)
