@@ -11,15 +11,21 @@ lemma, two CPhase layers, one base per spin block).  Inputs are resident in
 HBM before timing.
 
 Prints one JSON line: value = sampled amplitude terms (bitstring x
-trajectory) per second over the timed steps.  roofline: the dominant kernel
-is the evaluation (k_gen_eval); achieved = the algorithmic FP64 FLOPs it
-executes (per bitstring and block the Gauss-Jordan inverse of the base, the
-products X = M_B^-1 U and H = V X, per distinct flip pattern an r x r
-elimination and the two-layer correction; counted on the device from the
-shapes) over its time from the HIP events the library records on its
-stream; peak = the FP64 vector/matrix rate of the chip.  traffic = HBM bytes
-per launch from the committed rocprofv3 counters (null when the kernel
-source has changed since).  cpu_baseline: the FP64 oracle on a bounded
+trajectory) per second over the timed steps.  The call runs two stages, each
+timed with the HIP events the library records on its stream: the sampler
+(k_sample_entries) and the evaluation (k_gen_setup + k_gen_eval, and the
+fallback kernels, idle here).  roofline: the stage that takes longer.  For
+the sampler, achieved = the 32-bit integer operations of the Philox4x32-10
+blocks the sampling definition draws (100 per block: per round two 32 x 32
+-> 64-bit products, four XORs, two key additions; counted on the device)
+over its time, against the chip's 32-bit integer rate.  For the evaluation,
+achieved = its algorithmic FP64 FLOPs (per bitstring and block the
+Gauss-Jordan inverse of the base and the products X = M_B^-1 U and H = V X,
+per distinct flip pattern an r x r elimination and the two-layer
+correction; counted on the device) over its time, against the FP64 rate; the
+other stage is reported beside it.  traffic = HBM bytes per launch of the
+sampler from the committed rocprofv3 counters (null when its sources have
+changed since).  cpu_baseline: the FP64 oracle on a bounded
 sample of the same bitstrings, on all host threads and on one.  Extra keys:
 the sampler's own rate; the mixed-precision run and both precisions' error
 distributions against the stored oracle values of 1000 bitstrings of this
@@ -46,34 +52,38 @@ METRIC = "amplitude terms/s (bitstring×Gaussian term) at stated rel err; fwd+bw
 # 256 CUs x 2.4 GHz x 128 FP64 FLOP per clock per CU (vector FMA, and the
 # FP64 matrix cores run at the same rate)
 FP64_PEAK_TFLOPS = 78.6
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one 32-bit integer operation per
+# lane and clock
+INT32_PEAK_TOPS = 39.3
+OPS_PER_PHILOX_BLOCK = 100
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_gen_eval_large_batch.json")
-# sources whose change invalidates the committed counters of k_gen_eval
-EVAL_SOURCES = ("lemma_gen.h", "k_lemma_gen.hip", "xf_device.h", "xf_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sample_entries_large_batch.json")
+# sources whose change invalidates the committed counters of the sampler
+SAMPLER_SOURCES = ("sample_entries.h", "xf_device.h", "xf_internal.h", "k_lemma_gen.hip")
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def eval_source_hash() -> str:
+def sampler_source_hash() -> str:
     h = hashlib.sha256()
-    for f in EVAL_SOURCES:
+    for f in SAMPLER_SOURCES:
         with open(os.path.join(ROOT, "paper_2511_12416_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic():
-    """HBM bytes per launch of k_gen_eval from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for a
-    copy of known size), or None if the kernel sources changed since."""
+    """HBM bytes per launch of k_sample_entries from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's
+    reading for a copy of known size), or None if its sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except OSError:
         return None
-    if rec.get("sources_sha256") != eval_source_hash():
+    if rec.get("sources_sha256") != sampler_source_hash():
         return None
     return rec["bytes_per_launch"]
 
@@ -145,10 +155,11 @@ def cpu_baseline(cfg: int, seconds: float) -> dict:
     sized to take about `seconds` (calibrated on a few bitstrings)."""
     threads = host_threads()
     probe = cpu_oracle_rate(cfg, 4, threads)
-    per = probe["seconds"] / probe["count"]
-    n_all = int(max(8, min(2000, seconds / max(per, 1e-6))))
+    # the probe's 4 bitstrings ran side by side: one bitstring on one thread
+    per1 = probe["seconds"] * min(threads, 4) / 4
+    n_all = int(max(threads, min(4000, seconds * threads / max(per1, 1e-6))))
     full = cpu_oracle_rate(cfg, n_all, threads)
-    n_one = int(max(2, min(200, seconds / max(per * threads, 1e-6))))
+    n_one = int(max(2, min(200, seconds / max(per1, 1e-6))))
     one = cpu_oracle_rate(cfg, n_one, 1)
     t = full["t"]
     return {"value": full["count"] * t / full["seconds"], "unit": "terms/s", "cores": threads, "kind": "oracle",
@@ -249,8 +260,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
-                    help="after the timed region, one device-to-device copy of this many MiB (the "
-                         "reference kernel that scales the HBM byte counters)")
+                    help="after the timed region, a fill and a sum over this many MiB (the reference "
+                         "kernels that scale the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the path shards by "
@@ -269,7 +280,23 @@ def main() -> int:
     terms = w.B * w.t
     value = terms * r["steps"] / r["wall"]
     flops = r["work"]["flops"]
-    achieved = flops / (r["eval_ms"] * 1e-3) / 1e12
+    eval_tf = flops / (r["eval_ms"] * 1e-3) / 1e12
+    int_ops = r["work"]["philox_blocks"] * OPS_PER_PHILOX_BLOCK
+    samp_tops = int_ops / (r["sample_ms"] * 1e-3) / 1e12
+    sampler_roof = {"bound": "alu", "achieved": samp_tops, "peak": INT32_PEAK_TOPS, "unit": "TOP/s",
+                    "frac": samp_tops / INT32_PEAK_TOPS, "traffic": measured_traffic(),
+                    "kernel": "k_sample_entries", "kernel_ms": r["sample_ms"], "ops_per_launch": int_ops,
+                    "philox_blocks_per_launch": r["work"]["philox_blocks"],
+                    "ops": "32-bit integer operations of the Philox4x32-10 blocks the sampling definition draws "
+                           "(100 per block), counted on the device"}
+    eval_roof = {"bound": "alu", "achieved": eval_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": eval_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                 "kernel": "k_gen_setup + k_gen_eval (+ fallback kernels, idle here)",
+                 "kernel_ms": r["eval_ms"], "flops_per_launch": flops,
+                 "flops": "algorithmic FP64 FLOPs counted on the device: per bitstring and block Gauss-Jordan of "
+                          "the m x m base, X = M_B^-1 U (8 m^2 kb), H = V X (8 kb^2 m), per distinct pattern and "
+                          "block an r x r LU plus the two-layer correction"}
+    dominant, other = (sampler_roof, eval_roof) if r["sample_ms"] >= r["eval_ms"] else (eval_roof, sampler_roof)
 
     # errors against the stored oracle values of 1000 bitstrings of this batch
     with open(os.path.join(ROOT, "tests", "golden", "config5_subset_oracle.json")) as f:
@@ -286,14 +313,16 @@ def main() -> int:
                                                        "max": float(kap.max())}
 
     if args.calibrate_copy_mb > 0:
+        # reference kernels of known traffic: a fill (writes nbytes) and a sum
+        # (reads nbytes)
         nbytes = args.calibrate_copy_mb << 20
-        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+        a.fill_(1.0)
         torch.cuda.synchronize()
-        b.copy_(a)
+        total = float(a.sum())
         torch.cuda.synchronize()
-        log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
-        del a, b
+        log(f"calibration: fill of {nbytes} bytes, sum over {nbytes} bytes ({total:.0f})")
+        del a
     extras = {} if args.no_extras else run_extras(X, W, args, dev)
     base = None if args.no_cpu else cpu_baseline(5, args.cpu_seconds)
     m = res["mixed"]
@@ -314,13 +343,8 @@ def main() -> int:
                    "B": w.B, "mode": "raw_estimate", "precision": "fp64",
                    "evaluation": "general determinant lemma, spin blocks", "parallelism": "single GPU"},
         "rel_err_vs_oracle": errors,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "k_gen_eval<false,false> (+ k_gen_lu for deferred bitstrings)",
-                     "kernel_ms": r["eval_ms"], "flops_per_launch": flops,
-                     "flops": "algorithmic FP64 FLOPs counted on the device: per bitstring and block "
-                              "Gauss-Jordan of the m x m base, X = M_B^-1 U (8 m^2 kb), H = V X (8 kb^2 m), "
-                              "per distinct pattern and block an r x r LU plus the two-layer correction"},
+        "roofline": dominant,
+        "roofline_other_stage": other,
         "kernels": {"k_sample_entries": {"ms": r["sample_ms"], "trajectories_per_s": terms / (r["sample_ms"] * 1e-3)},
                     "k_gen_eval": {"ms": r["eval_ms"],
                                    "patterns_per_s": r["work"]["determinants"] / (r["eval_ms"] * 1e-3),

@@ -352,6 +352,9 @@ typedef struct {
     int32_t backward_lemma;   /* the last xf_log_prob_backward call used the determinant lemma */
     int32_t general;          /* the call used the general determinant-lemma kernel (see below) */
     int64_t fp32_bases;       /* bases (per block) whose lemma products ran in FP32 (XF_MIXED) */
+    int64_t philox_blocks;    /* Raw Estimate under the lemma: Philox4x32-10 blocks the sampling
+                                 definition draws (one per four samples' first draws, one per four
+                                 further draws of a sample); 100 32-bit integer operations each */
 } xf_work;
 xf_status xf_plan_last_work(xf_plan *plan, xf_work *work);
 

@@ -124,7 +124,7 @@ class Plan:
         return {"determinants": w.determinants, "rank_sum": w.rank_sum, "flops": w.flops,
                 "sample_ms": w.sample_ms, "eval_ms": w.eval_ms, "lemma": bool(w.lemma),
                 "backward_lemma": bool(w.backward_lemma), "general": bool(w.general),
-                "fp32_bases": w.fp32_bases}
+                "fp32_bases": w.fp32_bases, "philox_blocks": w.philox_blocks}
 
     def set_evaluation(self, evaluation: str) -> None:
         """"auto" (determinant lemma where it applies) or "lu" (LU of every

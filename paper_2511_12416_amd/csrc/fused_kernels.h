@@ -50,10 +50,11 @@ k_raw_estimate(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int64_t
         }
         if constexpr (STAGE) stage_rows<MIXED>(p, s);
         Sampler st;
+        unsigned long long blocks = 0;   // not reported here
         acc_clear(s_acc);
         clear_table(s, s_cnt, slot0, st);
         while (true) {
-            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
+            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st, blocks);
             const int nl = gather_list(s, &s_n);
             sum_entries<G, MIXED, STAGE>(p, s, nl, wk, s_acc);
             if (done) break;

@@ -154,10 +154,11 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int
         const double gb = g[b];
         if (gb == 0.0) continue;
         Sampler st;
+        unsigned long long blocks = 0;   // not reported here
         acc_clear(s_acc);
         clear_table(s, s_cnt, slot0, st);
         while (true) {
-            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
+            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st, blocks);
             const int nl = gather_list(s, &s_n);
             Work unused;
             sum_entries<G, MIXED, false>(p, s, nl, unused, s_acc);
@@ -176,7 +177,7 @@ k_raw_estimate_bwd(DevPlan p, const uint64_t *__restrict__ bits, int64_t b0, int
         st = Sampler();
         clear_table(s, s_cnt, slot0, st);
         while (true) {
-            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
+            const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st, blocks);
             const int nl = gather_list(s, &s_n);
             for (int e = grp; e < nl; e += NG) {
                 const uint16_t slot = s.list[e];

@@ -118,7 +118,8 @@ hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0
                               hipEvent_t ev_mid, hipStream_t s) {
     const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
     hipLaunchKernelGGL((k_sample_entries<kSamplerThreads>), dim3(grid), dim3(kSamplerThreads),
-                       sampler_lds_bytes(p.k), s, p, bits, b0, nb, (uint32_t)t, seed, ekey, ecnt, ecount, cap);
+                       sampler_lds_bytes(p.k), s, p, bits, b0, nb, (uint32_t)t, seed, ekey, ecnt, ecount, cap,
+                       nterm ? nterm + 4 : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
@@ -157,7 +158,8 @@ hipError_t launch_lemma_bwd_chunk(const DevPlan &p, const uint64_t *bits, int64_
                                   hipStream_t s) {
     const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
     hipLaunchKernelGGL((k_sample_entries<kSamplerThreads>), dim3(grid), dim3(kSamplerThreads),
-                       sampler_lds_bytes(p.k), s, p, bits, b0, nb, (uint32_t)t, seed, ekey, ecnt, ecount, cap);
+                       sampler_lds_bytes(p.k), s, p, bits, b0, nb, (uint32_t)t, seed, ekey, ecnt, ecount, cap,
+                       nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int bg = nparts < nb ? nparts : (int)nb;

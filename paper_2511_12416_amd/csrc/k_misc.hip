@@ -28,10 +28,7 @@ __global__ void k_reduce_parts(const double2 *__restrict__ part, int nparts, int
 }
 
 __global__ void k_zero_u64(unsigned long long *p) {
-    p[0] = 0ull;
-    p[1] = 0ull;
-    p[2] = 0ull;
-    p[3] = 0ull;
+    if (threadIdx.x < 8) p[threadIdx.x] = 0ull;
 }
 
 }  // namespace
@@ -54,7 +51,7 @@ hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, doub
 }
 
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 

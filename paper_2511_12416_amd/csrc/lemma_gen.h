@@ -1247,9 +1247,10 @@ k_gen_lu(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, in
             }
         } else {
             Sampler st;
+            unsigned long long blocks = 0;   // not reported here
             clear_table(s, s_cnt, slot0, st);
             while (true) {
-                const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st);
+                const bool done = sample_until_flush(p, s, s_cnt, slot0, b, t, k0, k1, st, blocks);
                 const int nl = gather_list(s, &s_n);
                 if (g.multi)
                     gen_lu_entries_multi(p, g, sh, s, nl, nullptr, wk, s_acc, Ym, Mm);

@@ -701,7 +701,8 @@ __device__ __forceinline__ int next_gate(const RawSmem &s, int k, int a, uint32_
 // block with counter (smp, (d - 1) / 4, blo, bhi)) until no further gate is
 // selected.  Returns the flip-pattern key and the phase exponent e (i^e).
 __device__ __forceinline__ void draw_rest(const DevPlan &p, const RawSmem &s, uint32_t smp, int j0, uint32_t blo,
-                                          uint32_t bhi, uint32_t k0, uint32_t k1, uint64_t &key, uint32_t &e) {
+                                          uint32_t bhi, uint32_t k0, uint32_t k1, uint64_t &key, uint32_t &e,
+                                          unsigned long long &blocks) {
     const int k = p.k;
     uint64_t g = s.gkey[j0];
     key = g & ~(1ull << 63);
@@ -709,7 +710,10 @@ __device__ __forceinline__ void draw_rest(const DevPlan &p, const RawSmem &s, ui
     int a = j0 + 1;
     uint4 r = make_uint4(0u, 0u, 0u, 0u);
     for (uint32_t d = 0; a < k; ++d) {
-        if ((d & 3) == 0) r = philox10(make_uint4(smp, d >> 2, blo, bhi), k0, k1);
+        if ((d & 3) == 0) {
+            r = philox10(make_uint4(smp, d >> 2, blo, bhi), k0, k1);
+            ++blocks;
+        }
         const uint32_t w = d & 3;
         const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
         const int j = next_gate(s, k, a, u);
@@ -744,7 +748,7 @@ __device__ __forceinline__ void draw_rest(const DevPlan &p, const RawSmem &s, ui
 template <int NT = kThreads>
 __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSmem &s, int *cnt,
                                                    uint32_t slot0, int64_t b, uint32_t t, uint32_t k0,
-                                                   uint32_t k1, Sampler &st) {
+                                                   uint32_t k1, Sampler &st, unsigned long long &blocks) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const uint32_t blo = (uint32_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
@@ -758,6 +762,7 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
         if (tid < NQ) {
             // u_0 of samples next + 4 tid + w is word w of block (next / 4 + tid, 2^32 - 1)
             const uint4 r = philox10(make_uint4((st.next >> 2) + (uint32_t)tid, 0xFFFFFFFFu, blo, bhi), k0, k1);
+            if (st.next + 4u * (uint32_t)tid < t) ++blocks;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
                 const uint32_t off = 4u * (uint32_t)tid + (uint32_t)w;
@@ -777,7 +782,11 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
             pend[(st.j + 2) % 3] = 0;
             added[(st.j + 1) % 3] = 0;
         }
-        if (st.claimed > 1 && st.claimed + pending > kFlushAt) return false;
+        if (st.claimed > 1 && st.claimed + pending > kFlushAt) {
+            // this batch is drawn again after the flush: count its first draws once
+            if (tid < NQ && st.next + 4u * (uint32_t)tid < t) --blocks;
+            return false;
+        }
         if (tid == 0) {
             const int live = (int)min((uint32_t)kBatch, t - st.next);
             if (live > pending) atomicAdd(&s.hcnt[slot0].x, live - pending);
@@ -791,7 +800,7 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
             const uint32_t u0 = w0 == 0 ? r0.x : (w0 == 1 ? r0.y : (w0 == 2 ? r0.z : r0.w));
             uint64_t key;
             uint32_t e;
-            draw_rest(p, s, smp, next_gate(s, p.k, 0, u0), blo, bhi, k0, k1, key, e);
+            draw_rest(p, s, smp, next_gate(s, p.k, 0, u0), blo, bhi, k0, k1, key, e, blocks);
             uint32_t slot = hash_slot(key);
             while (true) {
                 const unsigned long long prev = atomicCAS((unsigned long long *)&s.hkey[slot],

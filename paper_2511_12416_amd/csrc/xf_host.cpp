@@ -759,13 +759,13 @@ xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision pre
         (st = dev_upload(P->dgkey, P->gkey.data(), P->gkey.size() * 8)) ||
         (st = dev_upload(P->dgmode, P->gmode.data(), P->gmode.size() * 8)) ||
         (st = dev_upload(P->dglayer, glayer.data(), glayer.size() * 4)) ||
-        (st = set_gate_tables(P)) || (st = dev_upload(P->dnterm, nullptr, 32)) ||
+        (st = set_gate_tables(P)) || (st = dev_upload(P->dnterm, nullptr, 64)) ||
         (st = refresh_matrices(P)) || (st = refresh_table(P))) {
         plan_free(P);
         delete P;
         return st;
     }
-    if (hipMemset(P->dnterm.p, 0, 32) != hipSuccess) {
+    if (hipMemset(P->dnterm.p, 0, 64) != hipSuccess) {
         plan_free(P);
         delete P;
         return fail(XF_EDEVICE, "hipMemset failed");
@@ -1335,9 +1335,9 @@ xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
     if (!plan_valid(P) || !work) return fail(XF_EINVAL, "invalid plan or NULL output");
     DeviceGuard guard(P->device);
     if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
-    unsigned long long v[4] = {0, 0, 0, 0};
+    unsigned long long v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(v, P->dnterm.p, 32, hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(v, P->dnterm.p, 64, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(XF_EDEVICE, "could not read the work counters");
     work->determinants = (int64_t)v[0];
     work->rank_sum = (int64_t)v[1];
@@ -1346,6 +1346,7 @@ xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
     work->backward_lemma = P->last_bwd_lemma;
     work->general = P->last_gen;
     work->fp32_bases = (int64_t)v[3];
+    work->philox_blocks = (int64_t)v[4];
     work->sample_ms = 0.0;
     work->eval_ms = 0.0;
     for (int i = 1; i < P->nev; ++i) {

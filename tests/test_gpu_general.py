@@ -221,3 +221,29 @@ def test_wide_patterns_take_the_second_pass(X):
     p = gpu_probs(plan, X, bits, "approx", 600, 3)
     assert plan.last_work()["general"]
     _check(p, ref, TOL_FP64, "wide fp64")
+
+
+def test_sampler_counts_the_philox_blocks_of_the_definition(X):
+    """The sampler's count of Philox4x32-10 blocks equals the number the
+    sampling definition draws, from the oracle's trajectories: one block per
+    four samples' first draws, and per sample one per four further draws (a
+    sample draws once more than it selects gates, unless it selects the last
+    gate)."""
+    w = W.random_circuit(919, 30, 14, 18, n_rot=3, theta_scale=1.5, max_bits=16)
+    bits = w.bits[:12]
+    t = 997
+    plan = make_plan(w, X)
+    gpu_probs(plan, X, bits, "approx", t, 5)
+    wk = plan.last_work()
+    assert wk["lemma"]
+    expect = 0
+    for b in range(len(bits)):
+        xs = oracle.sample_trajectories(w.theta, seed=5, bidx=b, t=t)
+        expect += (t + 3) // 4
+        for x in xs:
+            v = int(x[0]) | (int(x[1]) << 64)
+            sel = bin(v).count("1")
+            draws = sel + (0 if sel and (v >> (w.k - 1)) & 1 else 1)
+            expect += (draws - 1 + 3) // 4
+    say(f"  Philox blocks: {wk['philox_blocks']} (definition {expect})")
+    assert wk["philox_blocks"] == expect
