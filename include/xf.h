@@ -201,8 +201,12 @@ xf_status xf_probabilities(xf_plan *plan, const xf_bits128 *d_bits, int64_t B, x
  * xf_probabilities, except:
  *   - the determinant-lemma workspace is a fixed device array of 256 MiB per
  *     device, held until the process ends; bitstrings are processed in chunks
- *     of floor(2^28 / ((t + t/511 + 2) * 16 + 4)), and XF_EUNSUPPORTED is
- *     returned if one bitstring does not fit (t above about 1.67e7);
+ *     of floor((2^28 - 256) / (16 c + 4 + h)), c = min(t + t/511 + 2, 8192)
+ *     entries and h the general lemma's per-bitstring setup bytes (16 per
+ *     complex entry of H plus a 48-byte record; 0 for the eta <= 16
+ *     one-layer kernels); exact mode under the general lemma holds
+ *     4 B + h (+ the segments' 64-byte partial sums) per bitstring of the
+ *     whole batch and returns XF_EUNSUPPORTED if they do not fit;
  *   - no device memory, pinned host memory or event is allocated and no
  *     kernel time is recorded (xf_plan_last_work reports zero times); the
  *     first call on a device looks up the array's device address;
