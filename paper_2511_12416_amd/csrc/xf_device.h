@@ -730,12 +730,17 @@ __device__ __forceinline__ void draw_rest(const DevPlan &p, const RawSmem &s, ui
 // all t samples are in (returns true) or the next batch could push the table
 // past kFlushAt slots (returns false; that batch is drawn again after the
 // table has been evaluated and cleared).  A batch runs in two phases: the
-// first kBatch / 4 threads each draw the first uniforms of four consecutive
+// last kBatch / 4 threads each draw the first uniforms of four consecutive
 // samples (one Philox block), which decide whether a sample sets any gate at
-// all (u_0 < T[0][k-1]); those samples are queued in LDS (batch offset), and
-// after the barrier the workgroup draws them to the end (the first draw
-// again, then the rest) and inserts them, so the long draws are spread over
-// all lanes.  The bound uses the exact count of slots in use plus the
+// all (u_0 < T[0][k-1]); those samples are queued in LDS, and after the
+// barrier the workgroup, from its first thread on, draws them to the end and
+// inserts them, so the long draws are spread over all lanes, and with more
+// than kBatch / 4 threads the first phase of the next batch runs in other
+// waves than the second phase of this one.  A queue entry holds the sample's
+// batch offset in its low 10 bits and u_0 with those bits cleared in the
+// rest; the first gate follows from that unless a table entry of row 0 falls
+// between the truncated and the full u_0, and only then is u_0 drawn again.
+// The bound uses the exact count of slots in use plus the
 // batch's non-empty samples, so the stopping points depend only on the
 // samples and every pass over the same bitstring empties the table at the
 // same samples.  Counts of the batch's non-empty samples (which are also the
@@ -755,24 +760,35 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
     const uint32_t any = p.k > 0 ? s.T[p.k - 1] : 0u;   // T[0][k-1]
     int *pend = cnt, *added = cnt + 3;
     constexpr int NQ = (int)(kBatch / 4);   // first-draw blocks per batch
+    constexpr uint32_t kOff = kBatch - 1;   // offset bits of a queue entry
     static_assert(NQ % 64 == 0 && NQ <= NT, "first draws by whole waves");
-    static_assert(kBatch <= 0x10000, "batch offsets fit in 16 bits");
+    static_assert((kBatch & kOff) == 0, "batch offsets are the low bits of a queue entry");
+    const int q = tid - (NT - NQ);          // first-draw block of this thread, if >= 0
+    const uint64_t below = (1ull << lane) - 1;
     for (; st.next < t; st.next += kBatch, ++st.j) {
         uint32_t *queue = (st.j & 1) ? (uint32_t *)s.piv : (uint32_t *)s.list;
-        if (tid < NQ) {
-            // u_0 of samples next + 4 tid + w is word w of block (next / 4 + tid, 2^32 - 1)
-            const uint4 r = philox10(make_uint4((st.next >> 2) + (uint32_t)tid, 0xFFFFFFFFu, blo, bhi), k0, k1);
-            if (st.next + 4u * (uint32_t)tid < t) ++blocks;
+        if (q >= 0) {
+            // u_0 of samples next + 4 q + w is word w of block (next / 4 + q, 2^32 - 1)
+            const uint4 r = philox10(make_uint4((st.next >> 2) + (uint32_t)q, 0xFFFFFFFFu, blo, bhi), k0, k1);
+            if (st.next + 4u * (uint32_t)q < t) ++blocks;
+            uint32_t ent[4];
+            uint64_t ball[4];
+            int total = 0;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                const uint32_t off = 4u * (uint32_t)tid + (uint32_t)w;
+                const uint32_t off = 4u * (uint32_t)q + (uint32_t)w;
                 const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
-                const bool hit = st.next + off < t && u < any;
-                const uint64_t ball = __ballot(hit);
-                int at = 0;
-                if (lane == 0 && ball) at = atomicAdd(&pend[st.j % 3], (int)__popcll(ball));
-                at = __shfl(at, 0, 64);
-                if (hit) queue[at + (int)__popcll(ball & ((1ull << lane) - 1))] = off;
+                ent[w] = (u & ~kOff) | off;
+                ball[w] = __ballot(st.next + off < t && u < any);
+                total += (int)__popcll(ball[w]);
+            }
+            int at = 0;
+            if (lane == 0 && total) at = atomicAdd(&pend[st.j % 3], total);
+            at = __shfl(at, 0, 64);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if ((ball[w] >> lane) & 1) queue[at + (int)__popcll(ball[w] & below)] = ent[w];
+                at += (int)__popcll(ball[w]);
             }
         }
         __syncthreads();
@@ -784,7 +800,7 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
         }
         if (st.claimed > 1 && st.claimed + pending > kFlushAt) {
             // this batch is drawn again after the flush: count its first draws once
-            if (tid < NQ && st.next + 4u * (uint32_t)tid < t) --blocks;
+            if (q >= 0 && st.next + 4u * (uint32_t)q < t) --blocks;
             return false;
         }
         if (tid == 0) {
@@ -793,14 +809,19 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
         }
         int fresh = 0;
         for (int i = tid; i < pending; i += NT) {
-            // the sample's first draw again (the queue keeps its batch offset only)
-            const uint32_t smp = st.next + queue[i];
-            const uint4 r0 = philox10(make_uint4(smp >> 2, 0xFFFFFFFFu, blo, bhi), k0, k1);
-            const uint32_t w0 = smp & 3;
-            const uint32_t u0 = w0 == 0 ? r0.x : (w0 == 1 ? r0.y : (w0 == 2 ? r0.z : r0.w));
+            const uint32_t ent = queue[i];
+            const uint32_t smp = st.next + (ent & kOff), hi = ent & ~kOff;
+            // every u in [hi, hi | kOff] selects gate j0 first unless T[0][j0] lies in that range
+            // (hi < T[0][k-1], so 0 <= j0 < k)
+            int j0 = next_gate(s, p.k, 0, hi);
+            if (s.T[j0] <= (hi | kOff)) {
+                const uint4 r0 = philox10(make_uint4(smp >> 2, 0xFFFFFFFFu, blo, bhi), k0, k1);
+                const uint32_t w0 = smp & 3;
+                j0 = next_gate(s, p.k, 0, w0 == 0 ? r0.x : (w0 == 1 ? r0.y : (w0 == 2 ? r0.z : r0.w)));
+            }
             uint64_t key;
             uint32_t e;
-            draw_rest(p, s, smp, next_gate(s, p.k, 0, u0), blo, bhi, k0, k1, key, e, blocks);
+            draw_rest(p, s, smp, j0, blo, bhi, k0, k1, key, e, blocks);
             uint32_t slot = hash_slot(key);
             while (true) {
                 const unsigned long long prev = atomicCAS((unsigned long long *)&s.hkey[slot],
@@ -812,11 +833,8 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
                 if (prev == key) break;
                 slot = (slot + 1) & (kHashSlots - 1);
             }
-            e &= 3;
-            if (e == 0) atomicAdd(&s.hcnt[slot].x, 1);
-            else if (e == 1) atomicAdd(&s.hcnt[slot].y, 1);
-            else if (e == 2) atomicAdd(&s.hcnt[slot].x, -1);
-            else atomicAdd(&s.hcnt[slot].y, -1);
+            // phase i^e: +-1 on the real (e even) or imaginary (e odd) count
+            atomicAdd((e & 1) ? &s.hcnt[slot].y : &s.hcnt[slot].x, (e & 2) ? -1 : 1);
         }
         if (fresh) atomicAdd(&added[st.j % 3], fresh);
     }
