@@ -13,8 +13,8 @@ HBM before timing.
 Prints one JSON line: value = sampled amplitude terms (bitstring x
 trajectory) per second over the timed steps.  The call runs two stages, each
 timed with the HIP events the library records on its stream: the sampler
-(k_sample_entries) and the evaluation (k_gen_setup + k_gen_eval, and the
-fallback kernels, idle here).  roofline: the stage that takes longer.  For
+(k_sample_entries) and the evaluation (k_gen_setup_wave + k_gen_eval, and
+the fallback kernels: k_gen_setup for the bases the first left, k_gen_lu).  roofline: the stage that takes longer.  For
 the sampler, achieved = the 32-bit integer operations of the Philox4x32-10
 blocks the sampling definition draws (100 per block: per round two 32 x 32
 -> 64-bit products, four XORs, two key additions; counted on the device)
@@ -291,10 +291,10 @@ def main() -> int:
                            "(100 per block), counted on the device"}
     eval_roof = {"bound": "alu", "achieved": eval_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": eval_tf / FP64_PEAK_TFLOPS, "traffic": None,
-                 "kernel": "k_gen_setup + k_gen_eval (+ fallback kernels, idle here)",
+                 "kernel": "k_gen_setup_wave + k_gen_eval (+ fallback kernels k_gen_setup, k_gen_lu)",
                  "kernel_ms": r["eval_ms"], "flops_per_launch": flops,
-                 "flops": "algorithmic FP64 FLOPs counted on the device: per bitstring and block Gauss-Jordan of "
-                          "the m x m base, X = M_B^-1 U (8 m^2 kb), H = V X (8 kb^2 m), per distinct pattern and "
+                 "flops": "algorithmic FP64 FLOPs counted on the device: per bitstring and block in-place "
+                          "Gauss-Jordan of the m x m base (8 m^2 (m - 1) and the pivot steps), X = M_B^-1 U (8 m^2 kb), H = V X (8 kb^2 m), per distinct pattern and "
                           "block an r x r LU plus the two-layer correction"}
     dominant, other = (sampler_roof, eval_roof) if r["sample_ms"] >= r["eval_ms"] else (eval_roof, sampler_roof)
 

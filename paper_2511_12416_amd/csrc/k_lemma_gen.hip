@@ -28,8 +28,12 @@ void launch_gen_tm(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int
                    const double2 *xw, int64_t nkeys, double2 *hbuf, GenRec *rec, double *prob, double *amp,
                    double *logp, unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s) {
     const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
-    hipLaunchKernelGGL((k_gen_setup<EXACT, MIXED, MULTI>), dim3(grid), dim3(kThreads), kGenSetupLds, s, p, g, bits,
-                       b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm);
+    // one wave per bitstring, then the workgroup setup over the bases it left
+    // (on a smaller grid: its workgroups pass over the other bitstrings at once)
+    hipLaunchKernelGGL((k_gen_setup_wave<EXACT, MIXED, MULTI>), dim3(grid), dim3(64), gen_setup_wave_lds(g), s, p, g,
+                       bits, b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm);
+    hipLaunchKernelGGL((k_gen_setup<EXACT, MIXED, MULTI>), dim3(grid < 2048 ? grid : 2048), dim3(kThreads),
+                       kGenSetupLds, s, p, g, bits, b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm, 1);
     // patterns of more than 16 flipped positions in a block can occur only
     // where a block has more than 16 active positions
     bool wide = false;
@@ -154,6 +158,14 @@ hipError_t prepare_gen() {
                           (const void *)k_gen_setup<true, false, false>, (const void *)k_gen_setup<true, true, false>,
                           (const void *)k_gen_setup<false, false, true>, (const void *)k_gen_setup<false, true, true>,
                           (const void *)k_gen_setup<true, false, true>, (const void *)k_gen_setup<true, true, true>,
+                          (const void *)k_gen_setup_wave<false, false, false>,
+                          (const void *)k_gen_setup_wave<false, true, false>,
+                          (const void *)k_gen_setup_wave<true, false, false>,
+                          (const void *)k_gen_setup_wave<true, true, false>,
+                          (const void *)k_gen_setup_wave<false, false, true>,
+                          (const void *)k_gen_setup_wave<false, true, true>,
+                          (const void *)k_gen_setup_wave<true, false, true>,
+                          (const void *)k_gen_setup_wave<true, true, true>,
                           (const void *)k_gen_lu<false>, (const void *)k_gen_lu<true>})
         if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGenMaxLds)) != hipSuccess)
             return e;

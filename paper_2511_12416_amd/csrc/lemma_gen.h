@@ -851,12 +851,343 @@ __device__ __forceinline__ RawSmem carve_eval(unsigned char *smem) {
 }
 constexpr size_t kGenMaxLds = 150 * 1024;
 
+// A bitstring whose base the one-wave setup did not accept (singular or
+// kappa_1 above the bound): the workgroup setup (k_gen_setup, retry mode)
+// takes it and tries the shifted bases.  Raw Estimate keeps its entry count
+// in its record meanwhile.
+constexpr uint32_t kEntryRetry = 0xFFFFFFFBu;
+
+// Position of the n-th (from 0) set bit of x, which has more than n set bits.
+__device__ __forceinline__ int nth_bit64(uint64_t x, int n) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int c = __popcll(x & ((1ull << w) - 1));
+        if (n >= c) {
+            n -= c;
+            x >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
+// Maximum over the 32 lanes of a half wave.
+__device__ __forceinline__ double half_max(double v) {
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Dynamic LDS of k_gen_setup_wave: each block's base, m_b x m_b complex.
+__host__ __device__ __forceinline__ size_t gen_setup_wave_lds(const GenPlan &g) {
+    size_t e = (size_t)g.mb[0] * g.mb[0];
+    if (g.nblk > 1) e += (size_t)g.mb[1] * g.mb[1];
+    return align16(e * 16);
+}
+
+// H = V M_B^-1 U of one block on the matrix cores, one wave: for each
+// 16-column tile tn of U, the tiles of X = M_B^-1 U (rows 16 tm ..) are formed
+// and, still in the output registers, serve as the B operand of H += V X: the
+// FP64 instruction leaves X[16 tm + l / 16 + 4 r][16 tn + l % 16] in element r
+// of lane l, which is the B operand of a 4-wide K slice whose lane group
+// l / 16 takes row 16 tm + l / 16 + 4 r (FP32: row 16 tm + 4 (l / 16) + r);
+// the A operand (V) takes the same K index.  minv(i, k), uop(k, q), vop(q, k)
+// return operands, hput(q, q2, v) stores H.
+template <bool F32, class FM, class FU, class FV, class FH>
+__device__ __forceinline__ void gen_wave_products(int m, int kb, FM minv, FU uop, FV vop, FH hput) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int tiles = (kb + 15) / 16, tm_n = (m + 15) / 16, ns = (m + 3) / 4;
+    constexpr int TQ = kGenMaxKb / 16, TM = kGenMaxM / 16;
+    typedef typename std::conditional<F32, f4v, d4v>::type acc_t;
+    for (int tn = 0; tn < tiles; ++tn) {
+        const int col = 16 * tn + li;
+        acc_t hr[TQ], hi[TQ];
+#pragma unroll
+        for (int tq = 0; tq < TQ; ++tq) {
+            hr[tq] = acc_t{0, 0, 0, 0};
+            hi[tq] = acc_t{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+            if (tm >= tm_n) break;
+            const int row = 16 * tm + li;
+            acc_t xr = {0, 0, 0, 0}, xi = {0, 0, 0, 0};
+            // the K slices in two groups, each group's operands loaded before its products
+            constexpr int SG = kGenMaxSteps / 2;
+#pragma unroll
+            for (int st0 = 0; st0 < kGenMaxSteps; st0 += SG) {
+            if (st0 >= ns) break;
+            double2 av[SG], bv[SG];
+#pragma unroll
+            for (int e = 0; e < SG; ++e) {
+                const int st = st0 + e, k = 4 * st + lk;
+                av[e] = (st < ns && row < m && k < m) ? minv(row, k) : make_double2(0.0, 0.0);
+                bv[e] = (st < ns && k < m && col < kb) ? uop(k, col) : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int e = 0; e < SG; ++e) {
+                const int st = st0 + e;
+                if (st < ns) {
+                    if constexpr (F32) {
+                        const float ax = (float)av[e].x, ay = (float)av[e].y;
+                        const float bx = (float)bv[e].x, by = (float)bv[e].y;
+                        xr = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, bx, xr, 0, 0, 0);
+                        xr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ay, by, xr, 0, 0, 0);
+                        xi = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, by, xi, 0, 0, 0);
+                        xi = __builtin_amdgcn_mfma_f32_16x16x4f32(ay, bx, xi, 0, 0, 0);
+                    } else {
+                        const double2 a = av[e], b = bv[e];
+                        xr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, xr, 0, 0, 0);
+                        xr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, xr, 0, 0, 0);
+                        xi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, xi, 0, 0, 0);
+                        xi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, xi, 0, 0, 0);
+                    }
+                }
+            }
+            }
+#pragma unroll
+            for (int tq = 0; tq < TQ; ++tq) {
+                if (tq >= tiles) break;
+                const int q = 16 * tq + li;
+                double2 va[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = F32 ? 16 * tm + 4 * lk + r : 16 * tm + lk + 4 * r;
+                    va[r] = (q < kb && k < m) ? vop(q, k) : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    // FP64: slice r holds rows 16 tm + 4 r .. 16 tm + 4 r + 3 (none left past m)
+                    if (!F32 && 16 * tm + 4 * r >= m) break;
+                    if constexpr (F32) {
+                        const float ax = (float)va[r].x, ay = (float)va[r].y;
+                        hr[tq] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, xr[r], hr[tq], 0, 0, 0);
+                        hr[tq] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ay, xi[r], hr[tq], 0, 0, 0);
+                        hi[tq] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, xi[r], hi[tq], 0, 0, 0);
+                        hi[tq] = __builtin_amdgcn_mfma_f32_16x16x4f32(ay, xr[r], hi[tq], 0, 0, 0);
+                    } else {
+                        hr[tq] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[r].x, xr[r], hr[tq], 0, 0, 0);
+                        hr[tq] = __builtin_amdgcn_mfma_f64_16x16x4f64(-va[r].y, xi[r], hr[tq], 0, 0, 0);
+                        hi[tq] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[r].x, xi[r], hi[tq], 0, 0, 0);
+                        hi[tq] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[r].y, xr[r], hi[tq], 0, 0, 0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int tq = 0; tq < TQ; ++tq) {
+            if (tq >= tiles) break;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int q = 16 * tq + (F32 ? 4 * lk + r : lk + 4 * r);
+                if (q < kb && col < kb) hput(q, col, make_double2((double)hr[tq][r], (double)hi[tq][r]));
+            }
+        }
+    }
+}
+
+// Setup of the general lemma with one wave per bitstring and no barrier
+// between waves: the blocks' bases are inverted at the same time, block b in
+// lanes 32 b .. 32 b + 31, by in-place Gauss-Jordan exchange steps in LDS.
+// Lane j of a half holds column j of its base; at step c, with pivot row p
+// (largest |a_ic|^2 among unused rows, lowest row on ties) and u = a_pc,
+//   a_ij += l_i a_pj (j != c),  a_ic = l_i,  l_i = -a_ic / u  (i != p),
+//   a_pj = a_pj / u (j != c),   a_pc = 1 / u.
+// Rows stay in place; after m steps entry (piv[c], pos[r]) holds M_B^-1[c, r],
+// piv[c] the pivot row of step c and pos[r] the step at which row r was the
+// pivot.  det M_B is the product of the pivots with the sign of that
+// permutation, and the largest column sum of |a| is ||M_B^-1||_1.  A base
+// that is singular or has kappa_1 above the bound is left to the workgroup
+// setup (kEntryRetry), which tries shifted bases; every other bitstring gets
+// H and its record here, as from k_gen_setup.
+template <bool EXACT, bool MIXED, bool MULTI>
+__global__ void __launch_bounds__(64)
+k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
+                 uint32_t *__restrict__ ecount, double2 *__restrict__ hbuf, GenRec *__restrict__ rec,
+                 double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
+                 unsigned long long *nterm) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double2 sL[2][kGenMaxM];                 // multipliers of the current step
+    __shared__ uint8_t sRow[2][kGenMaxM], sPiv[2][kGenMaxM], sPos[2][kGenMaxM];
+    __shared__ uint8_t sCol[2][kGenMaxM], sAct[2][kGenMaxKb];
+    const int lane = threadIdx.x, hb = lane >> 5, hl = lane & 31;
+    for (int e = lane; e < 2 * kGenMaxKb; e += 64) (&sAct[0][0])[e] = g.act[e];
+    for (int e = lane; e < 2 * kGenMaxM; e += 64) (&sCol[0][0])[e] = g.col[e];
+    const int m0 = g.mb[0], m1 = g.nblk > 1 ? g.mb[1] : 0;
+    const int mh = hb ? m1 : m0, mmax = m0 > m1 ? m0 : m1;
+    const uint32_t rowmask = mh >= 32 ? 0xFFFFFFFFu : (1u << mh) - 1;
+    double2 *base = (double2 *)smem;
+    double2 *Ah = base + (hb ? m0 * m0 : 0);
+    const int n = p.n, G = p.G;
+    Work wk;
+    __syncthreads();
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int64_t b = b0 + i;
+        uint32_t cnt = 0;
+        bool ok = true;
+        if constexpr (!EXACT) {
+            cnt = ecount[i];
+            if (cnt == kEntryDeferred) continue;   // overflowed its region: k_gen_lu takes it
+            ok = cnt != kEntryInvalid;
+        }
+        // weight, range and the rows of each block (as load_bitstring, gen_rows)
+        const uint64_t w0 = bits[2 * b], w1 = bits[2 * b + 1];
+        ok = ok && (__popcll(w0) + __popcll(w1)) == p.m;
+        if (p.n < 128) {
+            const uint64_t hi0 = p.n >= 64 ? 0ull : (~0ull << p.n);
+            const uint64_t hi1 = p.n <= 64 ? ~0ull : (~0ull << (p.n - 64));
+            ok = ok && !(w0 & hi0) && !(w1 & hi1);
+        }
+        const uint64_t x0 = hb ? (w0 & g.bmask[1][0]) : (w0 & ~g.bmask[1][0]);
+        const uint64_t x1 = hb ? (w1 & g.bmask[1][1]) : (w1 & ~g.bmask[1][1]);
+        const int c0 = __popcll(x0);
+        // every half (a missing second block has no rows) must hold its block's count
+        ok = ok && c0 + __popcll(x1) == mh;
+        if (__ballot(!ok) != 0) {
+            if (lane == 0) {
+                write_zero(b, prob, amp, logp);
+                ecount[i] = kEntryInvalid;
+            }
+            continue;
+        }
+        if (hl < mh) sRow[hb][hl] = (uint8_t)(hl < c0 ? nth_bit64(x0, hl) : 64 + nth_bit64(x1, hl - c0));
+        __syncthreads();
+        // the base, column hl of this half's block, and ||M_B||_1
+        double csum = 0.0;
+        if (hl < mh) {
+            const double2 *Pc = p.P + sCol[hb][hl];
+            for (int r = 0; r < mh; ++r) {
+                const double2 v = Pc[(size_t)sRow[hb][r] * G];
+                Ah[r * mh + hl] = v;
+                csum += sqrt(cabs2(v));
+            }
+        }
+        const double norm = half_max(csum);
+        __syncthreads();
+        uint32_t used = 0;
+        unsigned inversions = 0;
+        double2 det = make_double2(1.0, 0.0);
+        bool singular = false;
+        for (int c = 0; c < mmax; ++c) {
+            const bool live = c < mh && !singular;
+            const double2 a = (live && hl < mh) ? Ah[hl * mh + c] : make_double2(0.0, 0.0);
+            double best = (live && hl < mh && !((used >> hl) & 1)) ? cabs2(a) : -1.0;
+            int idx = hl;
+#pragma unroll
+            for (int off = 16; off > 0; off >>= 1) {
+                const double vo = __shfl_xor(best, off, 64);
+                const int io = __shfl_xor(idx, off, 64);
+                if (vo > best || (vo == best && io < idx)) {
+                    best = vo;
+                    idx = io;
+                }
+            }
+            if (live && !(best > 0.0)) singular = true;
+            const bool go = live && best > 0.0;
+            double2 ui = make_double2(0.0, 0.0);
+            if (go) {
+                const double2 u = Ah[idx * mh + c];
+                const double inv = 1.0 / best;
+                ui = make_double2(u.x * inv, -u.y * inv);
+                inversions += __popc(~used & ((1u << idx) - 1) & rowmask);
+                used |= 1u << idx;
+                det = c_mul(det, u);
+                if (hl == 0) {
+                    sPiv[hb][c] = (uint8_t)idx;
+                    sPos[hb][idx] = (uint8_t)c;
+                }
+                if (hl < mh)
+                    sL[hb][hl] = hl == idx ? make_double2(0.0, 0.0)
+                                           : make_double2(-(a.x * ui.x - a.y * ui.y), -(a.x * ui.y + a.y * ui.x));
+            }
+            __syncthreads();
+            if (go && hl < mh) {
+                const int j = hl;
+                const bool pc = j == c;
+                const double keep = pc ? 0.0 : 1.0;   // column c becomes the multipliers
+                const double2 pr = pc ? make_double2(1.0, 0.0) : Ah[idx * mh + j];
+                for (int r = 0; r < mh; ++r) {
+                    const double2 l = sL[hb][r];
+                    double2 v = Ah[r * mh + j];
+                    v.x *= keep;
+                    v.y *= keep;
+                    Ah[r * mh + j] = c_fma(v, l, pr);
+                }
+                Ah[idx * mh + j] = c_mul(pr, ui);
+            }
+            __syncthreads();
+        }
+        // kappa_1 from the column sums of |M_B^-1| (a permutation of its columns)
+        double cs = 0.0;
+        if (!singular && hl < mh)
+            for (int r = 0; r < mh; ++r) cs += sqrt(cabs2(Ah[r * mh + hl]));
+        const double kappa = half_max(cs) * norm;
+        const bool good = !singular && kappa <= kLemmaMaxCond;
+        if (__ballot(!good) != 0) {
+            if (lane == 0) {
+                if constexpr (!EXACT) rec[i].count = cnt;
+                ecount[i] = kEntryRetry;
+            }
+            __syncthreads();
+            continue;
+        }
+        if (inversions & 1) det = make_double2(-det.x, -det.y);
+        const double2 d1 = read_lane_c(det, 32);
+        det = c_mul(read_lane_c(det, 0), d1);
+        const double kap[2] = {read_lane_d(kappa, 0), read_lane_d(kappa, 32)};
+        // X and H of each block on the matrix cores, written to the bitstring's slot
+        double2 *Hb = hbuf + (size_t)i * g.hsize;
+        for (int blk = 0; blk < g.nblk; ++blk) {
+            const int m = g.mb[blk], kb = g.kb[blk], kb0 = g.kb0[blk], hld = g.hld[blk];
+            const double2 *Ab = base + (blk ? m0 * m0 : 0);
+            const uint8_t *piv = sPiv[blk], *pos = sPos[blk], *rows = sRow[blk], *col = sCol[blk], *act = sAct[blk];
+            double2 *H = Hb + g.hoff[blk];
+            auto minv = [&](int r, int k) { return Ab[piv[r] * m + pos[k]]; };
+            auto hput = [&](int q, int q2, double2 v) { H[q * hld + q2] = v; };
+            const bool f32 = MIXED && kap[blk] <= p.mixed_cond;
+            if constexpr (MULTI) {
+                const double2 *GA = g.GA + (size_t)blk * n * 64, *HC = g.HC + (size_t)blk * 64 * G;
+                auto uop = [&](int k, int q) { return GA[(size_t)rows[k] * 64 + q]; };
+                auto vop = [&](int q, int k) { return HC[(size_t)q * G + col[k]]; };
+                if (f32) gen_wave_products<true>(m, kb, minv, uop, vop, hput);
+                else gen_wave_products<false>(m, kb, minv, uop, vop, hput);
+            } else {
+                const double2 *A1 = p.A1, *A2 = p.A2, *Phi0 = p.Phi0, *Q = p.Q;
+                auto uop = [&](int k, int q) { return (q < kb0 ? A1 : A2)[(size_t)rows[k] * n + act[q]]; };
+                auto vop = [&](int q, int k) { return (q < kb0 ? Phi0 : Q)[(size_t)act[q] * G + col[k]]; };
+                if (f32) gen_wave_products<true>(m, kb, minv, uop, vop, hput);
+                else gen_wave_products<false>(m, kb, minv, uop, vop, hput);
+            }
+            if (lane == 0) {
+                // m exchange steps of (m - 1) x m complex multiply-adds, the
+                // multipliers, the pivot row and the pivot search; the
+                // conditioning; X and H
+                wk.flops += (unsigned long long)m * (8ull * (m - 1) * m + 6ull * (m - 1) + 6ull * m + 4ull * m) +
+                            4ull * m * m + 8ull * m * m * kb + 8ull * kb * m * kb;
+                if (f32) ++wk.fp32;
+            }
+        }
+        if (lane == 0) {
+            GenRec r;
+            r.det = det;
+            r.shift[0] = r.shift[1] = 0;
+            r.count = EXACT ? 0u : cnt;
+            r.pad[0] = r.pad[1] = r.pad[2] = 0;
+            rec[i] = r;
+            if constexpr (EXACT) ecount[i] = 0;
+        }
+        __syncthreads();
+    }
+    flush_work(wk, nterm);
+}
+
 template <bool EXACT, bool MIXED, bool MULTI>
 __global__ void __launch_bounds__(kThreads, 2)
 k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
             uint32_t *__restrict__ ecount, double2 *__restrict__ hbuf, GenRec *__restrict__ rec,
             double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
-            unsigned long long *nterm) {
+            unsigned long long *nterm, int retry) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_ok;
     __shared__ GenShared sh;
@@ -874,10 +1205,15 @@ k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0,
     for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
         const int64_t b = b0 + i;
         bool zero = false;
-        if constexpr (!EXACT) {
-            const uint32_t ne = ecount[i];
-            if (ne == kEntryDeferred) continue;   // overflowed its region: k_gen_lu takes it
-            zero = ne == kEntryInvalid;
+        uint32_t cnt = 0;   // Raw Estimate: the entry count
+        if (retry) {
+            // only the bitstrings the one-wave setup left (their count is in the record)
+            if (ecount[i] != kEntryRetry) continue;
+            if constexpr (!EXACT) cnt = rec[i].count;
+        } else if constexpr (!EXACT) {
+            cnt = ecount[i];
+            if (cnt == kEntryDeferred) continue;   // overflowed its region: k_gen_lu takes it
+            zero = cnt == kEntryInvalid;
         }
         if (!zero) zero = !load_bitstring(p, bits, b, s_Rb, &s_ok);
         if (!zero) {
@@ -904,10 +1240,10 @@ k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0,
                 r.det = sh.det;
                 r.shift[0] = sh.shift[0];
                 r.shift[1] = sh.shift[1];
-                r.count = EXACT ? 0u : ecount[i];
+                r.count = cnt;
                 r.pad[0] = r.pad[1] = r.pad[2] = 0;
                 rec[i] = r;
-                if constexpr (EXACT) ecount[i] = 0;
+                ecount[i] = cnt;   // exact mode: 0
             } else {
                 ecount[i] = kEntryDeferred;
             }
