@@ -286,8 +286,12 @@ struct RawSmem {
     uint16_t *list;
     uint8_t *Rb;
     uint64_t *gkey;   // [k] key contribution of gate j, bit 63 = theta_j < 0
-    uint32_t *T;      // [k][kpad] sampling table, row a: 0 before a, all-ones from k on
-    int kpad;         // row stride of T, a multiple of 16
+    // Sampling table, k rows of trow words (see load_tables): row a holds
+    // 8 boundaries of its 16-entry blocks, kpad / 4 boundaries of its 4-entry
+    // blocks, then T[a][0 .. kpad) (0 before a, all-ones from k on)
+    uint32_t *T;
+    int kpad;         // entries of a row, a multiple of 16
+    int trow;         // words of a row
     // LDS copies for one-layer circuits (STAGE): P rows of the bitstring
     // (G x G FP64), its A1 rows (G x n) and Phi0 (n x G), FP64 or FP32 (MIXED)
     double2 *sP;
@@ -304,12 +308,18 @@ __host__ __device__ __forceinline__ size_t stage_bytes(int n, int G, bool mixed)
 }
 
 __host__ __device__ __forceinline__ int table_stride(int k) { return (k + 15) & ~15; }
+__host__ __device__ __forceinline__ int table_row_words(int k) { return 8 + table_stride(k) / 4 + table_stride(k); }
+
+// Entry T[a][j] of the LDS sampling table.
+__device__ __forceinline__ uint32_t table_at(const RawSmem &s, int a, int j) {
+    return s.T[a * s.trow + 8 + (s.kpad >> 2) + j];
+}
 
 // Bytes of dynamic LDS the per-bitstring kernels carve (see carve_raw).
 __host__ __device__ __forceinline__ size_t raw_lds_bytes(int kk, int n, int G, bool mixed, bool stage) {
     const size_t k = (size_t)kk;
     const size_t base = align16((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + k * 8) +
-                        k * (size_t)table_stride(kk) * 4;
+                        k * (size_t)table_row_words(kk) * 4;
     return base + (stage ? stage_bytes(n, G, mixed) : 0);
 }
 
@@ -323,9 +333,10 @@ __device__ __forceinline__ RawSmem carve_raw(unsigned char *smem, int k, int n, 
     s.Rb = (uint8_t *)(s.list + kHashSlots);
     s.gkey = (uint64_t *)(s.Rb + 64);
     s.kpad = table_stride(k);
+    s.trow = table_row_words(k);
     const size_t toff = align16((size_t)kHashSlots * (8 + 8 + 2) + 2 * (size_t)kThreads * 16 + 64 + (size_t)k * 8);
     s.T = (uint32_t *)(smem + toff);
-    unsigned char *st = smem + toff + (size_t)k * s.kpad * 4;
+    unsigned char *st = smem + toff + (size_t)k * s.trow * 4;
     s.sP = (double2 *)st;
     s.sA1 = (void *)(st + (size_t)G * G * 16);
     s.sPhi = (void *)(st + (size_t)G * G * 16 + (size_t)n * G * (mixed ? 8 : 16));
@@ -677,23 +688,26 @@ __device__ __forceinline__ void clear_table(const RawSmem &s, int *cnt, uint32_t
 // The next selected gate from gate a for the uniform draw u (see the
 // sampler definition in the public header): the number of entries <= u of
 // row a of the table (the row is non-decreasing), or -1 when u >= T[a][k-1].
-// The last entry of each 16-wide block, read together with T[a][k-1], picks
-// the block, whose entries are then counted: two dependent LDS round trips
-// instead of a binary search.
+// Three levels of four-way comparisons without branches: the boundaries of
+// the 16-entry blocks (eight of them, all-ones past the row), those of the
+// chosen block's 4-entry blocks, then that block's entries.  The last
+// boundary not below u bounds each count (u < T[a][k-1] <= 2^32 - 1 is below
+// every all-ones padding entry).
 __device__ __forceinline__ int next_gate(const RawSmem &s, int k, int a, uint32_t u) {
-    const int kp = s.kpad, nb = kp >> 4;
-    const uint32_t *Ta = s.T + a * kp;
-    const uint32_t tail = Ta[k - 1];
-    int bs = 0;
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-        if (b < nb) bs += Ta[16 * b + 15] <= u ? 1 : 0;
+    const uint32_t *row = s.T + a * s.trow;
+    const uint32_t *ent = row + 8 + (s.kpad >> 2);
+    const uint32_t tail = ent[k - 1];
+    const uint4 b0 = *(const uint4 *)row;
+    int bs = (b0.x <= u) + (b0.y <= u) + (b0.z <= u) + (b0.w <= u);
+    if (s.kpad > 64) {
+        const uint4 b1 = *(const uint4 *)(row + 4);
+        bs += (b1.x <= u) + (b1.y <= u) + (b1.z <= u) + (b1.w <= u);
+    }
     if (!(u < tail)) return -1;
-    const uint4 *q = (const uint4 *)(Ta + 16 * bs);
-    const uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
-    return 16 * bs + (q0.x <= u) + (q0.y <= u) + (q0.z <= u) + (q0.w <= u) + (q1.x <= u) + (q1.y <= u) +
-           (q1.z <= u) + (q1.w <= u) + (q2.x <= u) + (q2.y <= u) + (q2.z <= u) + (q2.w <= u) + (q3.x <= u) +
-           (q3.y <= u) + (q3.z <= u) + (q3.w <= u);
+    const uint4 q = ((const uint4 *)(row + 8))[bs];
+    const int cs = 4 * bs + (q.x <= u) + (q.y <= u) + (q.z <= u) + (q.w <= u);
+    const uint4 e = ((const uint4 *)ent)[cs];
+    return 4 * cs + (e.x <= u) + (e.y <= u) + (e.z <= u) + (e.w <= u);
 }
 
 // The rest of trajectory smp of bitstring (blo, bhi) whose first draw
@@ -757,7 +771,7 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const uint32_t blo = (uint32_t)b, bhi = (uint32_t)((uint64_t)b >> 32);
-    const uint32_t any = p.k > 0 ? s.T[p.k - 1] : 0u;   // T[0][k-1]
+    const uint32_t any = p.k > 0 ? table_at(s, 0, p.k - 1) : 0u;   // T[0][k-1]
     int *pend = cnt, *added = cnt + 3;
     constexpr int NQ = (int)(kBatch / 4);   // first-draw blocks per batch
     constexpr uint32_t kOff = kBatch - 1;   // offset bits of a queue entry
@@ -814,7 +828,7 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
             // every u in [hi, hi | kOff] selects gate j0 first unless T[0][j0] lies in that range
             // (hi < T[0][k-1], so 0 <= j0 < k)
             int j0 = next_gate(s, p.k, 0, hi);
-            if (s.T[j0] <= (hi | kOff)) {
+            if (table_at(s, 0, j0) <= (hi | kOff)) {
                 const uint4 r0 = philox10(make_uint4(smp >> 2, 0xFFFFFFFFu, blo, bhi), k0, k1);
                 const uint32_t w0 = smp & 3;
                 j0 = next_gate(s, p.k, 0, w0 == 0 ? r0.x : (w0 == 1 ? r0.y : (w0 == 2 ? r0.z : r0.w)));
@@ -1413,9 +1427,12 @@ template <int NT = kThreads>
 __device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) {
     const int tid = threadIdx.x;
     const int k = p.k;
-    const int kp = s.kpad;
-    for (int i = tid; i < k * kp; i += NT) {
-        const int a = i / kp, j = i % kp;
+    const int kp = s.kpad, tr = s.trow;
+    // row a: [ T[a][16 b + 15], b < 8 | T[a][4 c + 3], c < kp / 4 | T[a][j], j < kp ],
+    // entries past k all-ones
+    for (int i = tid; i < k * tr; i += NT) {
+        const int a = i / tr, w = i % tr;
+        const int j = w < 8 ? 16 * w + 15 : (w < 8 + kp / 4 ? 4 * (w - 8) + 3 : w - 8 - kp / 4);
         s.T[i] = j < k ? p.T[a * k + j] : 0xFFFFFFFFu;
     }
     for (int i = tid; i < k; i += NT) s.gkey[i] = p.gkey[i] | ((uint64_t)(p.gneg[i] != 0) << 63);
@@ -1429,7 +1446,7 @@ __host__ __device__ __forceinline__ size_t sampler_head_bytes(int k) {
     return align16((size_t)kHashSlots * (8 + 8 + 2) + (size_t)kThreads * 16 + 64 + (size_t)k * 8);
 }
 __host__ __device__ __forceinline__ size_t sampler_lds_bytes(int k) {
-    return sampler_head_bytes(k) + (size_t)k * table_stride(k) * 4;
+    return sampler_head_bytes(k) + (size_t)k * table_row_words(k) * 4;
 }
 
 // Sampler layout: the hash, the two sample queues (pivot scratch and list)
@@ -1444,6 +1461,7 @@ __device__ __forceinline__ RawSmem carve_sampler(unsigned char *smem, int k) {
     s.Rb = (uint8_t *)(s.list + kHashSlots);
     s.gkey = (uint64_t *)(s.Rb + 64);
     s.kpad = table_stride(k);
+    s.trow = table_row_words(k);
     s.T = (uint32_t *)(smem + sampler_head_bytes(k));
     s.sP = nullptr;
     s.sA1 = nullptr;
