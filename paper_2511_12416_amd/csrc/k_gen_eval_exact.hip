@@ -7,7 +7,7 @@ namespace xf {
 
 hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t nb,
                                  const uint64_t *xkeys, const double2 *xw, int64_t nkeys, uint32_t *flags,
-                                 const double2 *hbuf, const GenRec *rec, double *prob, double *amp, double *logp,
+                                 const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
                                  unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s) {
     const size_t lds = gen_lds_bytes(g, true), lds16 = gen_lds_bytes(g, false);
     const int64_t items = nb * nseg;

@@ -8,7 +8,7 @@ namespace xf {
 
 hipError_t launch_gen_eval_raw(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t b0, int64_t nb,
                                const uint64_t *ekey, const int2 *ecnt, uint32_t *ecount, uint64_t cap,
-                               const double2 *hbuf, const GenRec *rec, double *prob, double *amp, double *logp,
+                               const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
                                unsigned long long *nterm, int grid, hipStream_t s) {
     const size_t lds = gen_lds_bytes(g, true), lds16 = gen_lds_bytes(g, false);
     const int grid2 = grid < 2048 ? grid : 2048;

@@ -7,11 +7,11 @@ namespace xf {
 
 hipError_t launch_gen_eval_raw(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t b0, int64_t nb,
                                const uint64_t *ekey, const int2 *ecnt, uint32_t *ecount, uint64_t cap,
-                               const double2 *hbuf, const GenRec *rec, double *prob, double *amp, double *logp,
+                               const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
                                unsigned long long *nterm, int grid, hipStream_t s);
 hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t nb,
                                  const uint64_t *xkeys, const double2 *xw, int64_t nkeys, uint32_t *flags,
-                                 const double2 *hbuf, const GenRec *rec, double *prob, double *amp, double *logp,
+                                 const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
                                  unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s);
 hipError_t prepare_gen_eval_raw();
 hipError_t prepare_gen_eval_exact();
@@ -22,41 +22,39 @@ size_t gen_lu_lds_bytes(const DevPlan &p, const GenPlan &g, bool exact) {
     return raw_lds_bytes(exact ? 0 : p.k, p.n, 4, false, false) + (g.multi ? kGenMultiLuBytes : 0);
 }
 
+// The setup kernels: one wave per bitstring, then the workgroup setup over
+// the bases it left (on a smaller grid: its workgroups pass over the other
+// bitstrings at once, or return at once when there are none).
 template <bool EXACT, bool MIXED, bool MULTI>
-void launch_gen_tm(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int64_t b0, int64_t nb,
-                   const uint64_t *ekey, const int2 *ecnt, uint32_t *ecount, uint64_t cap, const uint64_t *xkeys,
-                   const double2 *xw, int64_t nkeys, double2 *hbuf, GenRec *rec, double *prob, double *amp,
-                   double *logp, unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s) {
+void launch_gen_setup_tm(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int64_t b0, int64_t nb,
+                         uint32_t *ecount, double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
+                         unsigned long long *nterm, hipStream_t s) {
     const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
-    // one wave per bitstring, then the workgroup setup over the bases it left
-    // (on a smaller grid: its workgroups pass over the other bitstrings at once)
     hipLaunchKernelGGL((k_gen_setup_wave<EXACT, MIXED, MULTI>), dim3(grid), dim3(64), gen_setup_wave_lds(g), s, p, g,
                        bits, b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm);
     hipLaunchKernelGGL((k_gen_setup<EXACT, MIXED, MULTI>), dim3(grid < 2048 ? grid : 2048), dim3(kThreads),
                        kGenSetupLds, s, p, g, bits, b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm, 1);
-    // patterns of more than 16 flipped positions in a block can occur only
-    // where a block has more than 16 active positions
-    bool wide = false;
-    for (int b = 0; b < g.nblk; ++b) wide = wide || g.kb[b] > 16;
-    if constexpr (EXACT)
-        launch_gen_eval_exact(p, g, MULTI, wide, nb, xkeys, xw, nkeys, ecount, hbuf, rec, prob, amp, logp, nterm,
-                              nseg, part, s);
-    else
-        launch_gen_eval_raw(p, g, MULTI, wide, b0, nb, ekey, ecnt, ecount, cap, hbuf, rec, prob, amp, logp, nterm,
-                            grid, s);
 }
 
-template <bool EXACT, bool MIXED>
-void launch_gen_t(const DevPlan &p, const GenPlan &g, const uint64_t *bits, int64_t b0, int64_t nb,
-                  const uint64_t *ekey, const int2 *ecnt, uint32_t *ecount, uint64_t cap, const uint64_t *xkeys,
-                  const double2 *xw, int64_t nkeys, double2 *hbuf, GenRec *rec, double *prob, double *amp,
-                  double *logp, unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s) {
-    if (g.multi)
-        launch_gen_tm<EXACT, MIXED, true>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, hbuf, rec,
-                                          prob, amp, logp, nterm, nseg, part, s);
-    else
-        launch_gen_tm<EXACT, MIXED, false>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, xkeys, xw, nkeys, hbuf, rec,
-                                           prob, amp, logp, nterm, nseg, part, s);
+template <bool EXACT>
+void launch_gen_setup_t(const DevPlan &p, const GenPlan &g, bool mixed, const uint64_t *bits, int64_t b0, int64_t nb,
+                        uint32_t *ecount, double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
+                        unsigned long long *nterm, hipStream_t s) {
+    if (g.multi) {
+        if (mixed) launch_gen_setup_tm<EXACT, true, true>(p, g, bits, b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm, s);
+        else launch_gen_setup_tm<EXACT, false, true>(p, g, bits, b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm, s);
+    } else {
+        if (mixed) launch_gen_setup_tm<EXACT, true, false>(p, g, bits, b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm, s);
+        else launch_gen_setup_tm<EXACT, false, false>(p, g, bits, b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm, s);
+    }
+}
+
+// patterns of more than 16 flipped positions in a block can occur only
+// where a block has more than 16 active positions
+bool gen_wide(const GenPlan &g) {
+    bool wide = false;
+    for (int b = 0; b < g.nblk; ++b) wide = wide || g.kb[b] > 16;
+    return wide;
 }
 
 }  // namespace
@@ -104,12 +102,9 @@ hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;
-    if (mixed)
-        launch_gen_t<false, true>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, nullptr, nullptr, 0, hbuf, rec, prob,
-                                  amp, logp, nterm, 1, nullptr, s);
-    else
-        launch_gen_t<false, false>(p, g, bits, b0, nb, ekey, ecnt, ecount, cap, nullptr, nullptr, 0, hbuf, rec, prob,
-                                   amp, logp, nterm, 1, nullptr, s);
+    launch_gen_setup_t<false>(p, g, mixed, bits, b0, nb, ecount, hbuf, rec, prob, amp, logp, nterm, s);
+    launch_gen_eval_raw(p, g, g.multi, gen_wide(g), b0, nb, ekey, ecnt, ecount, cap, hbuf, rec, prob, amp, logp,
+                        nterm, grid, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // then the bitstrings the evaluation deferred, on a smaller grid (its
     // workgroups skip the other bitstrings at once)
@@ -132,12 +127,11 @@ hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool
     uint64_t *part = (uint64_t *)(rec + B);
     if (all_lu) {
         if ((e = launch_fill_u32(flags, B, kEntryDeferred, s)) != hipSuccess) return e;
-    } else if (mixed)
-        launch_gen_t<true, true>(p, g, bits, 0, B, nullptr, nullptr, flags, 0, keys, w, nkeys, hbuf, rec, prob, amp,
-                                 logp, nterm, nseg, part, s);
-    else
-        launch_gen_t<true, false>(p, g, bits, 0, B, nullptr, nullptr, flags, 0, keys, w, nkeys, hbuf, rec, prob, amp,
-                                  logp, nterm, nseg, part, s);
+    } else {
+        launch_gen_setup_t<true>(p, g, mixed, bits, 0, B, flags, hbuf, rec, prob, amp, logp, nterm, s);
+        launch_gen_eval_exact(p, g, g.multi, gen_wide(g), B, keys, w, nkeys, flags, hbuf, rec, prob, amp, logp, nterm,
+                              nseg, part, s);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid && (e = hipEventRecord(ev_mid, s)) != hipSuccess) return e;

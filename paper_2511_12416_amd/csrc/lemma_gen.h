@@ -1024,13 +1024,7 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
     __syncthreads();
     for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
         const int64_t b = b0 + i;
-        uint32_t cnt = 0;
         bool ok = true;
-        if constexpr (!EXACT) {
-            cnt = ecount[i];
-            if (cnt == kEntryDeferred) continue;   // overflowed its region: k_gen_lu takes it
-            ok = cnt != kEntryInvalid;
-        }
         // weight, range and the rows of each block (as load_bitstring, gen_rows)
         const uint64_t w0 = bits[2 * b], w1 = bits[2 * b + 1];
         ok = ok && (__popcll(w0) + __popcll(w1)) == p.m;
@@ -1047,7 +1041,8 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
         if (__ballot(!ok) != 0) {
             if (lane == 0) {
                 write_zero(b, prob, amp, logp);
-                ecount[i] = kEntryInvalid;
+                if constexpr (EXACT) ecount[i] = kEntryInvalid;
+                else rec[i].status = kRecZero;
             }
             continue;
         }
@@ -1126,8 +1121,9 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
         const bool good = !singular && kappa <= kLemmaMaxCond;
         if (__ballot(!good) != 0) {
             if (lane == 0) {
-                if constexpr (!EXACT) rec[i].count = cnt;
-                ecount[i] = kEntryRetry;
+                if constexpr (EXACT) ecount[i] = kEntryRetry;
+                else rec[i].status = kRecRetry;
+                if (nterm) atomicAdd(nterm + 5, 1ull);
             }
             __syncthreads();
             continue;
@@ -1172,8 +1168,9 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
             GenRec r;
             r.det = det;
             r.shift[0] = r.shift[1] = 0;
-            r.count = EXACT ? 0u : cnt;
-            r.pad[0] = r.pad[1] = r.pad[2] = 0;
+            r.count = 0;
+            r.status = kRecOk;
+            r.pad[0] = r.pad[1] = 0;
             rec[i] = r;
             if constexpr (EXACT) ecount[i] = 0;
         }
@@ -1193,6 +1190,7 @@ k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0,
     __shared__ GenShared sh;
     __shared__ uint8_t s_Rb[128];
     const int tid = threadIdx.x;
+    if (retry && nterm && *(volatile unsigned long long *)(nterm + 5) == 0) return;   // none left
     GenLds T;
     T.act = smem + kGenSetupBytes;
     T.col = T.act + 128;
@@ -1205,15 +1203,9 @@ k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0,
     for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
         const int64_t b = b0 + i;
         bool zero = false;
-        uint32_t cnt = 0;   // Raw Estimate: the entry count
         if (retry) {
-            // only the bitstrings the one-wave setup left (their count is in the record)
-            if (ecount[i] != kEntryRetry) continue;
-            if constexpr (!EXACT) cnt = rec[i].count;
-        } else if constexpr (!EXACT) {
-            cnt = ecount[i];
-            if (cnt == kEntryDeferred) continue;   // overflowed its region: k_gen_lu takes it
-            zero = cnt == kEntryInvalid;
+            // only the bitstrings the one-wave setup left
+            if (EXACT ? ecount[i] != kEntryRetry : rec[i].status != kRecRetry) continue;
         }
         if (!zero) zero = !load_bitstring(p, bits, b, s_Rb, &s_ok);
         if (!zero) {
@@ -1225,7 +1217,8 @@ k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0,
         if (zero) {
             if (tid == 0) {
                 write_zero(b, prob, amp, logp);
-                ecount[i] = kEntryInvalid;
+                if constexpr (EXACT) ecount[i] = kEntryInvalid;
+                else rec[i].status = kRecZero;
             }
             __syncthreads();
             continue;
@@ -1240,12 +1233,14 @@ k_gen_setup(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0,
                 r.det = sh.det;
                 r.shift[0] = sh.shift[0];
                 r.shift[1] = sh.shift[1];
-                r.count = cnt;
-                r.pad[0] = r.pad[1] = r.pad[2] = 0;
+                r.count = 0;
+                r.status = kRecOk;
+                r.pad[0] = r.pad[1] = 0;
                 rec[i] = r;
-                ecount[i] = cnt;   // exact mode: 0
+                if constexpr (EXACT) ecount[i] = 0;
             } else {
-                ecount[i] = kEntryDeferred;
+                if constexpr (EXACT) ecount[i] = kEntryDeferred;
+                else rec[i].status = kRecDeferred;
             }
         }
         __syncthreads();
@@ -1261,12 +1256,13 @@ __global__ void __launch_bounds__(kThreads, 1)
 k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restrict__ ekey,
            const int2 *__restrict__ ecnt, uint32_t *__restrict__ ecount, uint64_t cap,
            const uint64_t *__restrict__ xkeys, const double2 *__restrict__ xw, int64_t nkeys,
-           const double2 *__restrict__ hbuf, const GenRec *__restrict__ rec, double *__restrict__ prob,
+           const double2 *__restrict__ hbuf, GenRec *__restrict__ rec, double *__restrict__ prob,
            double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm, int nseg,
            uint64_t *__restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t s_acc[kAccWords];
     constexpr int SLOTS = BIG ? 2048 : 1024;
+    if (WIDE_ONLY && nterm && *(volatile unsigned long long *)(nterm + 6) == 0) return;   // none left
     const RawSmem s = carve_eval<SLOTS>(smem);
     const GenLds T = carve_gen<SLOTS>(smem, g);
     const int tid = threadIdx.x;
@@ -1282,6 +1278,15 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
         const uint32_t flag = ecount[i];
         if (WIDE_ONLY ? flag != kEntryWide : (flag == kEntryDeferred || flag == kEntryInvalid || flag == kEntryWide))
             continue;
+        if (!EXACT && !WIDE_ONLY) {
+            // the setup's outcome: p = 0 already written, or no acceptable base (to k_gen_lu)
+            const uint32_t st = rec[i].status;
+            if (st == kRecZero) continue;
+            if (st == kRecDeferred) {
+                if (tid == 0) ecount[i] = kEntryDeferred;
+                continue;
+            }
+        }
         const double2 detB = rec[i].det;
         const uint64_t shift[2] = {rec[i].shift[0], rec[i].shift[1]};
         const double2 *Hg = hbuf + (size_t)i * g.hsize;
@@ -1305,7 +1310,11 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
             ok = gen_sum_entries<MULTI, BIG>(p, g, T, s, nc, EXACT ? xw + c0 : nullptr, detB, shift, wk, s_acc);
         }
         if (!ok) {
-            if (tid == 0) ecount[i] = BIG ? kEntryDeferred : kEntryWide;
+            if (tid == 0) {
+                if (!BIG && !EXACT) rec[i].count = flag;   // for the pass with lane groups of 32
+                ecount[i] = BIG ? kEntryDeferred : kEntryWide;
+                if (!BIG && nterm) atomicAdd(nterm + 6, 1ull);
+            }
             __syncthreads();
             continue;
         }

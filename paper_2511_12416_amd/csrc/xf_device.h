@@ -858,7 +858,11 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
 // Work done by one thread, kept in registers and added to the plan's device
 // counters once at the end of a kernel: [0] distinct determinants, [1] sum of
 // their correction ranks, [2] FP64-equivalent FLOPs of the evaluation, [3]
-// bases whose lemma products ran on the FP32 matrix cores.
+// bases whose lemma products ran on the FP32 matrix cores.  The other
+// counters of a call: [4] Philox blocks of the sampling definition, [5]
+// bitstrings the one-wave setup left to the workgroup setup, [6] bitstrings
+// left to the pattern pass with lane groups of 32 (the passes that take them
+// return at once when their counter is zero).
 struct Work {
     unsigned long long terms = 0, rank = 0, flops = 0, fp32 = 0;
 };

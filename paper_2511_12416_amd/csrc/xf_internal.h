@@ -90,9 +90,16 @@ struct GenPlan {
 struct GenRec {
     double2 det;          // product over blocks of det M_B
     uint64_t shift[2];    // base pattern of each block (positions)
-    uint32_t count;       // Raw Estimate: the bitstring's entry count
-    uint32_t pad[3];
+    uint32_t count;       // Raw Estimate: the entry count of a bitstring left to the second pattern pass
+    uint32_t status;      // Raw Estimate: kRecOk, kRecZero, kRecRetry or kRecDeferred
+    uint32_t pad[2];
 };
+// Raw Estimate setup outcomes (the setup needs only the bitstrings and
+// leaves the sampler's entry counts alone; the pattern pass reads both): H
+// and det ready; p = 0 written (wrong block counts or an invalid bitstring);
+// base left to the workgroup setup; no acceptable base (the LU kernel takes
+// the bitstring).
+constexpr uint32_t kRecOk = 0, kRecZero = 1, kRecRetry = 2, kRecDeferred = 3;
 
 // One partial gradient (of a workgroup of the lemma backward, or of a lane
 // group of the LU backward; complex entries, offsets in double2):
