@@ -1002,13 +1002,13 @@ __device__ __forceinline__ void gen_wave_products(int m, int kb, FM minv, FU uop
 // setup (kEntryRetry), which tries shifted bases; every other bitstring gets
 // H and its record here, as from k_gen_setup.
 template <bool EXACT, bool MIXED, bool MULTI>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_t b0, int64_t nb,
                  uint32_t *__restrict__ ecount, double2 *__restrict__ hbuf, GenRec *__restrict__ rec,
                  double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
                  unsigned long long *nterm) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double2 sL[2][kGenMaxM];                 // multipliers of the current step
+    __shared__ double2 prow[2][kGenMaxM];               // pivot row of the current step (per block)
     __shared__ uint8_t sRow[2][kGenMaxM], sPiv[2][kGenMaxM], sPos[2][kGenMaxM];
     __shared__ uint8_t sCol[2][kGenMaxM], sAct[2][kGenMaxKb];
     const int lane = threadIdx.x, hb = lane >> 5, hl = lane & 31;
@@ -1060,59 +1060,92 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
         }
         const double norm = half_max(csum);
         __syncthreads();
+        // Gauss-Jordan with each lane's row in registers: a[] holds row hl in
+        // a physical column order that rotates left by 4 after every 4 steps,
+        // so that the pivot column of step 4 q + t is always a[t] (static
+        // register indices); the pivot row goes through LDS (prow).
+        static_assert(kGenMaxM == 32, "the column rotation works modulo 32 in steps of 4");
+        double2 a[kGenMaxM];
+#pragma unroll
+        for (int j = 0; j < kGenMaxM; ++j) a[j] = (hl < mh && j < mh) ? Ah[hl * mh + j] : make_double2(0.0, 0.0);
         uint32_t used = 0;
         unsigned inversions = 0;
         double2 det = make_double2(1.0, 0.0);
         bool singular = false;
-        for (int c = 0; c < mmax; ++c) {
-            const bool live = c < mh && !singular;
-            const double2 a = (live && hl < mh) ? Ah[hl * mh + c] : make_double2(0.0, 0.0);
-            double best = (live && hl < mh && !((used >> hl) & 1)) ? cabs2(a) : -1.0;
-            int idx = hl;
+        const int nchunk = (mmax + 3) / 4;
+        for (int q = 0; q < nchunk; ++q) {
 #pragma unroll
-            for (int off = 16; off > 0; off >>= 1) {
-                const double vo = __shfl_xor(best, off, 64);
-                const int io = __shfl_xor(idx, off, 64);
-                if (vo > best || (vo == best && io < idx)) {
-                    best = vo;
-                    idx = io;
+            for (int t = 0; t < 4; ++t) {
+                const int c = 4 * q + t;   // logical column (physical t)
+                if (c >= mmax) break;
+                const bool live = c < mh && !singular;
+                const double2 ac = a[t];
+                double best = (live && hl < mh && !((used >> hl) & 1)) ? cabs2(ac) : -1.0;
+                int idx = hl;
+#pragma unroll
+                for (int off = 16; off > 0; off >>= 1) {
+                    const double vo = __shfl_xor(best, off, 64);
+                    const int io = __shfl_xor(idx, off, 64);
+                    if (vo > best || (vo == best && io < idx)) {
+                        best = vo;
+                        idx = io;
+                    }
                 }
-            }
-            if (live && !(best > 0.0)) singular = true;
-            const bool go = live && best > 0.0;
-            double2 ui = make_double2(0.0, 0.0);
-            if (go) {
-                const double2 u = Ah[idx * mh + c];
-                const double inv = 1.0 / best;
-                ui = make_double2(u.x * inv, -u.y * inv);
-                inversions += __popc(~used & ((1u << idx) - 1) & rowmask);
-                used |= 1u << idx;
-                det = c_mul(det, u);
-                if (hl == 0) {
-                    sPiv[hb][c] = (uint8_t)idx;
-                    sPos[hb][idx] = (uint8_t)c;
+                if (live && !(best > 0.0)) singular = true;
+                const bool go = live && best > 0.0;
+                const bool piv = go && hl == idx;
+                if (piv) {
+#pragma unroll
+                    for (int j = 0; j < kGenMaxM; ++j) prow[hb][j] = a[j];
                 }
-                if (hl < mh)
-                    sL[hb][hl] = hl == idx ? make_double2(0.0, 0.0)
-                                           : make_double2(-(a.x * ui.x - a.y * ui.y), -(a.x * ui.y + a.y * ui.x));
-            }
-            __syncthreads();
-            if (go && hl < mh) {
-                const int j = hl;
-                const bool pc = j == c;
-                const double keep = pc ? 0.0 : 1.0;   // column c becomes the multipliers
-                const double2 pr = pc ? make_double2(1.0, 0.0) : Ah[idx * mh + j];
-                for (int r = 0; r < mh; ++r) {
-                    const double2 l = sL[hb][r];
-                    double2 v = Ah[r * mh + j];
-                    v.x *= keep;
-                    v.y *= keep;
-                    Ah[r * mh + j] = c_fma(v, l, pr);
+                __syncthreads();
+                if (go) {
+                    const double2 u = prow[hb][t];
+                    const double inv = 1.0 / best;
+                    const double2 ui = make_double2(u.x * inv, -u.y * inv);
+                    inversions += __popc(~used & ((1u << idx) - 1) & rowmask);
+                    used |= 1u << idx;
+                    det = c_mul(det, u);
+                    if (hl == 0) {
+                        sPiv[hb][c] = (uint8_t)idx;
+                        sPos[hb][idx] = (uint8_t)c;
+                    }
+                    // exchange step: a_ij += l_i a_pj with l_i = -a_ic / u; the
+                    // pivot row takes l = 1 / u - 1 (a_pj / u); column c then
+                    // holds l_i, and 1 / u in the pivot row
+                    const double2 l = piv ? make_double2(ui.x - 1.0, ui.y)
+                                          : make_double2(-(ac.x * ui.x - ac.y * ui.y), -(ac.x * ui.y + ac.y * ui.x));
+                    // in groups of 8 columns, so that the pivot-row reads of
+                    // one group are in registers at a time
+#pragma unroll
+                    for (int j0 = 0; j0 < kGenMaxM; j0 += 8) {
+#pragma unroll
+                        for (int j = j0; j < j0 + 8; ++j) a[j] = c_fma(a[j], l, prow[hb][j]);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    a[t] = piv ? ui : l;
                 }
-                Ah[idx * mh + j] = c_mul(pr, ui);
+                __syncthreads();
             }
-            __syncthreads();
+            // rotate: physical column j takes j + 4
+            const double2 r0 = a[0], r1 = a[1], r2 = a[2], r3 = a[3];
+#pragma unroll
+            for (int j = 0; j < kGenMaxM - 4; ++j) a[j] = a[j + 4];
+            a[kGenMaxM - 4] = r0;
+            a[kGenMaxM - 3] = r1;
+            a[kGenMaxM - 2] = r2;
+            a[kGenMaxM - 1] = r3;
         }
+        // back to LDS in logical column order: physical j is logical (j + 4 nchunk) mod 32
+        {
+            const int off = (4 * nchunk) & (kGenMaxM - 1);
+#pragma unroll
+            for (int j = 0; j < kGenMaxM; ++j) {
+                const int lc = (j + off) & (kGenMaxM - 1);
+                if (hl < mh && lc < mh) Ah[hl * mh + lc] = a[j];
+            }
+        }
+        __syncthreads();
         // kappa_1 from the column sums of |M_B^-1| (a permutation of its columns)
         double cs = 0.0;
         if (!singular && hl < mh)
