@@ -690,10 +690,13 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
     uint16_t *order = (uint16_t *)s.piv;
     if (tid < 16) cnt[tid] = 0;
     __syncthreads();
+    // each entry's bin is kept in s.list (free until the accumulation)
     for (int e = tid; e < nl; e += kThreads) {
         uint64_t pm[2];
         gen_relative(T.kbt, s.hkey[e], shift, pm);
-        atomicAdd(&cnt[rank_bin(gen_max_rank(pm))], 1);
+        const int bin = rank_bin(gen_max_rank(pm));
+        s.list[e] = (uint16_t)bin;
+        atomicAdd(&cnt[bin], 1);
     }
     __syncthreads();
     if (cnt[4] > 0 || (!BIG && cnt[3] > 0)) return false;
@@ -706,11 +709,7 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
         cnt[11] = n0 + n1 + n2;
     }
     __syncthreads();
-    for (int e = tid; e < nl; e += kThreads) {
-        uint64_t pm[2];
-        gen_relative(T.kbt, s.hkey[e], shift, pm);
-        order[atomicAdd(&cnt[8 + rank_bin(gen_max_rank(pm))], 1)] = (uint16_t)e;
-    }
+    for (int e = tid; e < nl; e += kThreads) order[atomicAdd(&cnt[8 + s.list[e]], 1)] = (uint16_t)e;
     __syncthreads();
     // value of entry e: weight * detB * prod det S, into its slot (each entry
     // is read and written by the same lane or lane group)

@@ -52,8 +52,13 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
     return c;
 }
 
+// Slot of a key in an LDS hash table: the key folded to 32 bits (high word
+// rotated by 16), then a multiplicative (Fibonacci) hash, top bits.
 __device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
-    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 53) & (kHashSlots - 1);
+    static_assert(kHashSlots == 2048, "11 hash bits");
+    const uint32_t hi = (uint32_t)(key >> 32);
+    const uint32_t x = (uint32_t)key ^ ((hi << 16) | (hi >> 16));
+    return (x * 0x9E3779B1u) >> 21;
 }
 
 // Flip masks (per CPhase layer, 128-bit mode sets) of a trajectory key.
