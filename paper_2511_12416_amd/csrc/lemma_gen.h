@@ -583,9 +583,42 @@ __device__ __forceinline__ double2 small_det4(double2 (&a)[4][4], int r) {
 
 // Product over blocks of det S for a pattern whose blocks flip at most 4
 // positions each (one lane); pm already relative to the blocks' base
-// patterns (shift): sigma = -1 on shift & pm (flipped by the base only).
+// patterns (shift): sigma = -1 on shift & pm (flipped by the base only);
+// code: its lane code (the positions).
+// Compact form of a pattern that one lane evaluates (at most 4 flipped
+// positions per block), kept in its key slot after classification: bit 63
+// set (keys use bits 0..62), block b from bit 27 b: its rank (3 bits), then
+// its positions ascending (6 bits each, 0 past the rank).
+__device__ __forceinline__ uint64_t lane_code(const uint64_t (&pm)[2]) {
+    uint64_t c = 1ull << 63;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        uint64_t mm = pm[b];
+        c |= (uint64_t)__popcll(mm) << (27 * b);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (mm) c |= (uint64_t)(__ffsll((long long)mm) - 1) << (27 * b + 3 + 6 * i);
+            mm &= mm - 1;
+        }
+    }
+    return c;
+}
+
+// The masks of a lane code.
+__device__ __forceinline__ void lane_masks(uint64_t c, uint64_t (&pm)[2]) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int r = (int)((c >> (27 * b)) & 7);
+        uint64_t m = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (i < r) m |= 1ull << ((c >> (27 * b + 3 + 6 * i)) & 63);
+        pm[b] = m;
+    }
+}
+
 template <bool MULTI>
-__device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan &g, const GenLds &T,
+__device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan &g, const GenLds &T, uint64_t code,
                                                 const uint64_t (&pm)[2], const uint64_t (&shift)[2]) {
     double2 det = make_double2(1.0, 0.0);
     for (int blk = 0; blk < g.nblk; ++blk) {
@@ -595,7 +628,8 @@ __device__ __forceinline__ double2 gen_det_lane(const DevPlan &p, const GenPlan 
         const int kb0 = g.kb0[blk];
         const int r0 = __popcll(pm[blk] & (kb0 >= 64 ? ~0ull : ((1ull << kb0) - 1)));
         int pos[4];
-        mask_positions<4>(pm[blk], pos);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pos[i] = (int)((code >> (27 * blk + 3 + 6 * i)) & 63);
         const double2 *H = T.H + g.hoff[blk];
         const double2 *R1a = T.R1a + g.r1off[blk];
         double2 a[4][4];
@@ -690,12 +724,14 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
     uint16_t *order = (uint16_t *)s.piv;
     if (tid < 16) cnt[tid] = 0;
     __syncthreads();
-    // each entry's bin is kept in s.list (free until the accumulation)
+    // each entry's bin is kept in s.list (free until the accumulation), and
+    // the key of an entry for one lane is replaced by its lane code
     for (int e = tid; e < nl; e += kThreads) {
         uint64_t pm[2];
         gen_relative(T.kbt, s.hkey[e], shift, pm);
         const int bin = rank_bin(gen_max_rank(pm));
         s.list[e] = (uint16_t)bin;
+        if (bin == 0) s.hkey[e] = lane_code(pm);
         atomicAdd(&cnt[bin], 1);
     }
     __syncthreads();
@@ -728,11 +764,12 @@ __device__ __forceinline__ bool gen_sum_entries(const DevPlan &p, const GenPlan 
     unsigned long long rank = 0, flops = 0;
     for (int i = tid; i < n0; i += kThreads) {
         const int e = order[i];
+        const uint64_t code = s.hkey[e];
         uint64_t pm[2];
-        gen_relative(T.kbt, s.hkey[e], shift, pm);
+        lane_masks(code, pm);
         rank += __popcll(pm[0]) + __popcll(pm[1]);
         flops += gen_pattern_flops(g, p.L == 2, pm);
-        store(e, gen_det_lane<MULTI>(p, g, T, pm, shift));
+        store(e, gen_det_lane<MULTI>(p, g, T, code, pm, shift));
     }
     {
         const int l8 = tid & 7, g8 = tid >> 3;
