@@ -247,3 +247,39 @@ def test_sampler_counts_the_philox_blocks_of_the_definition(X):
             expect += (draws - 1 + 3) // 4
     say(f"  Philox blocks: {wk['philox_blocks']} (definition {expect})")
     assert wk["philox_blocks"] == expect
+
+
+@pytest.mark.parametrize("mode", ["exact", "approx"])
+def test_blocks_with_wrong_counts_interleaved(X, mode):
+    """Bitstrings whose spin blocks hold the wrong particle counts (p = 0 by
+    the block structure), of the wrong weight or with bits past n, interleaved
+    with valid ones, on the general lemma with two blocks and two CPhase
+    layers: the zero outcomes come out as exact zeros (amplitude 0, log p =
+    -inf) and their neighbours still match the oracle."""
+    n, eta, k = 16, 8, 10
+    inp = list(range(eta // 2)) + list(range(n // 2, n // 2 + eta // 2))
+    w = W.random_circuit(931, n, eta, k, n_rot=3, theta_scale=0.8, spin=True, input_modes=inp, max_bits=64)
+    rng = np.random.default_rng(931)
+    good = W.spin_bitstrings(rng, n // 2, eta // 2, eta // 2, 48)
+    skew = W.spin_bitstrings(rng, n // 2, eta // 2 + 1, eta // 2 - 1, 16)   # right weight, wrong split
+    heavy = np.array([W.bits_from_modes(list(range(eta + 1)))] * 4)           # wrong weight
+    wide = np.array([W.bits_from_modes(list(range(eta - 1)) + [n + 3])] * 4)   # a bit past n
+    bits = np.concatenate([good, skew, heavy, wide])
+    order = rng.permutation(len(bits))
+    bits = bits[order]
+    zero = order >= len(good)
+    t, smp = (2000, 17) if mode == "approx" else (0, 0)
+    ref = oracle_probs(w, bits[~zero], mode=mode, t=t, seed=smp, batch_index=np.nonzero(~zero)[0])
+    for prec, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
+        plan = make_plan(w, X, prec)
+        p, amp = gpu_probs(plan, X, bits, mode, t, smp, return_amp=True)
+        assert plan.last_work()["general"]
+        say(f"wrong block counts ({mode}, {prec}): {int(zero.sum())} zero of {len(bits)}")
+        assert np.all(p[zero] == 0.0) and np.all(amp[zero] == 0.0)
+        _check(p[~zero], ref, tol, f"{prec} valid neighbours")
+        logp = torch.empty(len(bits), dtype=torch.float64, device=plan.device)
+        plan.probabilities(X.bits_tensor(bits, plan.device), mode, t, smp, logp=logp)
+        torch.cuda.synchronize()
+        lp = logp.cpu().numpy()
+        assert np.all(np.isneginf(lp[zero]))
+        assert np.allclose(lp[~zero], np.log(ref), rtol=0, atol=2 * tol)
