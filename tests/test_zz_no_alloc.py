@@ -23,7 +23,8 @@ def X():
     return X
 
 
-def _both(X, plan, bits, t, seed):
+def _both(X, plan, bits, t, seed, mode=None):
+    mode = X._abi.XF_RAW_ESTIMATE if mode is None else mode
     lib = X.lib()
     B = bits.shape[0]
     stream = torch.cuda.current_stream().cuda_stream
@@ -32,7 +33,7 @@ def _both(X, plan, bits, t, seed):
         p = torch.full((B,), -1.0, dtype=torch.float64, device="cuda")
         a = torch.full((B, 2), -1.0, dtype=torch.float64, device="cuda")
         lp = torch.full((B,), -1.0, dtype=torch.float64, device="cuda")
-        X._abi.check(fn(plan._h, bits.data_ptr(), B, X._abi.XF_RAW_ESTIMATE, t, seed, p.data_ptr(),
+        X._abi.check(fn(plan._h, bits.data_ptr(), B, mode, t, seed, p.data_ptr(),
                         a.data_ptr(), lp.data_ptr(), ctypes.c_void_p(stream)))
         torch.cuda.synchronize()
         outs.append((p.cpu().numpy(), a.cpu().numpy(), lp.cpu().numpy()))
@@ -56,6 +57,28 @@ def test_noalloc_matches_allocating_call_twice(X):
     (p2, a2, l2), (q2, b2, m2) = _both(X, plan2, X.bits_tensor(w2.bits), 4096, 77)
     assert np.array_equal(p2, q2) and np.array_equal(a2, b2) and np.array_equal(l2, m2)
     assert np.count_nonzero(p2) == w2.B
+
+
+def test_noalloc_general_lemma_two_calls(X):
+    """The general lemma (two CPhase layers, two spin blocks), whose setup
+    keeps H and the base records in the scratch beside the entry regions:
+    Raw Estimate twice in a row (the second batch smaller, of another
+    circuit), then exact mode, each bitwise equal to the allocating call."""
+    for seed, n, eta, k, B in ((911, 44, 20, 16, 600), (912, 14, 6, 9, 100)):
+        inp = list(range(eta // 2)) + list(range(n // 2, n // 2 + eta // 2))
+        w = W.random_circuit(seed, n, eta, k, n_rot=3, theta_scale=0.6, spin=True, input_modes=inp, max_bits=16)
+        bits = W.spin_bitstrings(np.random.default_rng(seed), n // 2, eta // 2, eta // 2, B)
+        plan = make_plan(w, X)
+        say(f"no-allocation general lemma: n={n} eta={eta} k={k} two layers B={B} t=4096")
+        (p1, a1, l1), (q1, b1, m1) = _both(X, plan, X.bits_tensor(bits), 4096, 31)
+        assert plan.last_work()["general"]
+        assert np.array_equal(p1, q1) and np.array_equal(a1, b1) and np.array_equal(l1, m1)
+        assert np.count_nonzero(p1) == B
+    # exact mode on the last plan (its term list built by the allocating call)
+    say(f"no-allocation general lemma, exact mode: B={B}")
+    (p2, a2, l2), (q2, b2, m2) = _both(X, plan, X.bits_tensor(bits), 0, 0, X._abi.XF_EXACT)
+    assert plan.last_work()["general"]
+    assert np.array_equal(p2, q2) and np.array_equal(a2, b2) and np.array_equal(l2, m2)
 
 
 def test_noalloc_overflowing_regions_match(X):
