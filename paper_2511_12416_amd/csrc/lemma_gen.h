@@ -20,14 +20,15 @@
 // (zero unless R and C have the same number of modes in every block), and
 // each block has its own base, H and S_N.
 //
-// Per bitstring (one workgroup): for each block, the base M_0 is inverted by
-// Gauss-Jordan in LDS with partial pivoting (the whole workgroup updates, one
-// wave searches the pivot), checked for conditioning (kappa_1 <= 1e4, else
-// the bitstring is left to the LU kernels), and X = M_0^-1 U, H = V X are
-// formed on the matrix cores (v_mfma_f64_16x16x4f64; with MIXED,
-// v_mfma_f32_16x16x4f32 on FP32-rounded operands).  Then every distinct
-// pattern takes an r x r determinant per block: one lane for r <= 4, lane
-// groups of 8, 16 or 32 above; the weighted determinants are summed exactly.
+// Per bitstring: the blocks' bases M_0 are inverted by Gauss-Jordan with
+// partial pivoting (one wave, a block per half-wave: k_gen_setup_wave; the
+// workgroup form gen_setup_block for the shifted bases of k_gen_setup),
+// checked for conditioning (kappa_1 <= 1e4, else a shifted base, else the
+// LU kernels), and X = M_0^-1 U, H = V X are formed on the matrix cores
+// (v_mfma_f64_16x16x4f64; with MIXED, v_mfma_f32_16x16x4f32 on FP32-rounded
+// operands).  Then every distinct pattern takes an r x r determinant per
+// block: one lane for r <= 4, lane groups of 8, 16 or 32 above; the weighted
+// determinants are summed exactly.
 #pragma once
 #include "xf_device.h"
 
@@ -845,21 +846,24 @@ __device__ __forceinline__ void write_result(int64_t b, double2 total, double sc
     if (logp) logp[b] = log(pb);
 }
 
-// The evaluation runs in two kernels per chunk of bitstrings, so that the
-// setup (base inverses and the products forming H, long dependent chains of
-// small steps) runs at the occupancy its small footprint allows, and the
+// The evaluation runs in separate kernels per chunk of bitstrings, so that
+// the setup (base inverses and the products forming H, long dependent chains
+// of small steps) runs at the occupancy its small footprint allows, and the
 // pattern evaluation at its own:
-//   k_gen_setup: per bitstring and block, the base M_B, its inverse, X and H
-//     (gen_setup_block); H goes to the bitstring's slot of a workspace (hsize
-//     complex entries, the blocks at hoff with row stride hld), det M_B and
-//     the base patterns to a GenRec.
+//   k_gen_setup_wave: per bitstring (one wave) the blocks' bases M_B, their
+//     inverses, X and H; H goes to the bitstring's slot of a workspace
+//     (hsize complex entries, the blocks at hoff with row stride hld), det
+//     M_B, the base patterns and (Raw Estimate) the outcome to a GenRec.
+//   k_gen_setup (retry): the workgroup setup with shifted bases (gen_setup_block)
+//     for the bitstrings the first rejected.
 //   k_gen_eval: per bitstring, H back into LDS and every distinct pattern's
 //     r x r determinant, summed exactly.
-// Flags in ecount[i] (Raw Estimate: the sampler's entry count; exact mode:
-// written by the setup): kEntryInvalid once p = 0 is written, kEntryDeferred
-// for the bitstrings left to k_gen_lu (singular or ill-conditioned bases, a
-// pattern beyond kGenMaxRank in a block, or, from the sampler, patterns that
-// overflowed the workspace region).
+// Flags in ecount[i] (Raw Estimate: the sampler's entry count, with the
+// setup's outcome in the record until the pattern pass merges it; exact
+// mode: written by the setup): kEntryInvalid once p = 0 is written,
+// kEntryDeferred for the bitstrings left to k_gen_lu (singular or
+// ill-conditioned bases, a pattern beyond kGenMaxRank in a block, or, from
+// the sampler, patterns that overflowed the workspace region).
 // A bitstring with a pattern of 17..32 flipped positions in a block, left by
 // the evaluation without lane groups of 32 to the one with them.
 constexpr uint32_t kEntryWide = 0xFFFFFFFCu;
