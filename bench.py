@@ -30,8 +30,10 @@ sample of the same bitstrings, on all host threads and on one.  Extra keys:
 the sampler's own rate; the mixed-precision run and both precisions' error
 distributions against the stored oracle values of 1000 bitstrings of this
 batch (with the terms' cancellation sum|w det| / |A|); the LUCJ workload
-(n = 32), the exact-mode stress workload (n = 52, all 4096 terms), and the
-forward and forward+adjoint time of the differentiation workload.
+(n = 32), the exact-mode stress workload (n = 52, all 4096 terms; along the
+term list's prefix tree, and again with every pattern's determinant on its
+own), and the forward and forward+adjoint time of the differentiation
+workload.
 """
 from __future__ import annotations
 
@@ -210,10 +212,18 @@ def run_extras(X, W, args, dev):
         wall = timed_steps(plan, bits, w.mode, w.t, w.seed, out, steps, args.warmup)
         terms = w.B * (w.t if w.mode == "approx" else (1 << w.k))
         wk = plan.last_work()
+        ev = "general lemma" if wk["general"] else ("lemma" if wk["lemma"] else "LU")
+        if wk["tree_bitstrings"]:
+            ev += f", prefix tree ({wk['tree_bitstrings']} of {w.B} bitstrings)"
         extra[key] = {"workload": w.name, "ms_per_step": wall * 1e3 / steps, "value": terms * steps / wall,
-                      "unit": "terms/s", "dtype": "f64", "evaluation": "general lemma" if wk["general"]
-                      else ("lemma" if wk["lemma"] else "LU")}
-        log(f"{key}: {wall * 1e3 / steps:.3f} ms/step, {terms * steps / wall:.3e} terms/s")
+                      "unit": "terms/s", "dtype": "f64", "evaluation": ev}
+        log(f"{key}: {wall * 1e3 / steps:.3f} ms/step, {terms * steps / wall:.3e} terms/s ({ev})")
+        if wk["tree_bitstrings"]:
+            # the same call with every pattern's determinant on its own
+            plan.set_evaluation("patterns")
+            wall2 = timed_steps(plan, bits, w.mode, w.t, w.seed, out, steps, args.warmup)
+            extra[key]["per_pattern_ms_per_step"] = wall2 * 1e3 / steps
+            log(f"{key} per pattern: {wall2 * 1e3 / steps:.3f} ms/step")
         plan.close()
     # differentiation workload: forward (log p) and forward + adjoint
     w = W.workload(4)

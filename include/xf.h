@@ -304,8 +304,22 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
  *     beyond the largest lane group, or whose patterns overflow its workspace
  *     region, is evaluated with the LU of every M_N instead.  The gradient
  *     (xf_log_prob_backward) uses the lemma for one CPhase layer and
- *     eta <= 16 under Raw Estimate, the LU elsewhere. */
-typedef enum { XF_EVAL_AUTO = 0, XF_EVAL_LU = 1 } xf_evaluation;
+ *     eta <= 16 under Raw Estimate, the LU elsewhere.
+ * Exact mode under XF_EVAL_AUTO, for one CPhase layer or more than two: the
+ * patterns' determinants det S are principal minors of one matrix per
+ * bitstring (I - 2H, or I + 2TT - 2K for many layers), so terms whose flipped
+ * positions share a prefix share its elimination.  The plan arranges the
+ * term list as a prefix tree over those positions (at most 32 in all; anchors
+ * every four positions, each a Schur complement of its parent's), and one
+ * wave per bitstring walks it: each term then costs a determinant of at most
+ * 4 x 4 (all principal minors by the recursion of Griffin and Tsatsomeros,
+ * Linear Algebra Appl. 419 (2006)).  Bitstrings with a shifted base, an
+ * exactly singular pivot block, or entries grown beyond 10^4 times G's
+ * largest, and batches small enough to split the term list into segments,
+ * take the per-pattern evaluation instead.
+ *   XF_EVAL_PATTERNS: XF_EVAL_AUTO without the prefix tree (every pattern's
+ *     r x r determinant on its own). */
+typedef enum { XF_EVAL_AUTO = 0, XF_EVAL_LU = 1, XF_EVAL_PATTERNS = 2 } xf_evaluation;
 xf_status xf_plan_set_evaluation(xf_plan *plan, xf_evaluation evaluation);
 
 /* XF_MIXED under the general determinant-lemma evaluation (see
@@ -359,6 +373,8 @@ typedef struct {
     int64_t philox_blocks;    /* Raw Estimate under the lemma: Philox4x32-10 blocks the sampling
                                  definition draws (one per four samples' first draws, one per four
                                  further draws of a sample); 100 32-bit integer operations each */
+    int64_t tree_bitstrings;  /* exact mode: bitstrings evaluated along the prefix tree (see
+                                 xf_plan_set_evaluation) */
 } xf_work;
 xf_status xf_plan_last_work(xf_plan *plan, xf_work *work);
 

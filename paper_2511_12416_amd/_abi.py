@@ -29,7 +29,8 @@ class Work(ctypes.Structure):
     _fields_ = [("determinants", ctypes.c_int64), ("rank_sum", ctypes.c_int64), ("flops", ctypes.c_double),
                 ("sample_ms", ctypes.c_double), ("eval_ms", ctypes.c_double), ("lemma", ctypes.c_int32),
                 ("backward_lemma", ctypes.c_int32), ("general", ctypes.c_int32),
-                ("fp32_bases", ctypes.c_int64), ("philox_blocks", ctypes.c_int64)]
+                ("fp32_bases", ctypes.c_int64), ("philox_blocks", ctypes.c_int64),
+                ("tree_bitstrings", ctypes.c_int64)]
 
 
 class Circuit(ctypes.Structure):

@@ -18,7 +18,7 @@ from ._abi import check, lib
 
 _MODES = {"exact": _abi.XF_EXACT, "approx": _abi.XF_RAW_ESTIMATE, "raw_estimate": _abi.XF_RAW_ESTIMATE}
 _PREC = {"fp64": _abi.XF_FP64, "mixed": _abi.XF_MIXED}
-_EVAL = {"auto": 0, "lu": 1}
+_EVAL = {"auto": 0, "lu": 1, "patterns": 2}
 
 
 def _f64(a) -> np.ndarray:
@@ -124,11 +124,14 @@ class Plan:
         return {"determinants": w.determinants, "rank_sum": w.rank_sum, "flops": w.flops,
                 "sample_ms": w.sample_ms, "eval_ms": w.eval_ms, "lemma": bool(w.lemma),
                 "backward_lemma": bool(w.backward_lemma), "general": bool(w.general),
-                "fp32_bases": w.fp32_bases, "philox_blocks": w.philox_blocks}
+                "fp32_bases": w.fp32_bases, "philox_blocks": w.philox_blocks,
+                "tree_bitstrings": w.tree_bitstrings}
 
     def set_evaluation(self, evaluation: str) -> None:
-        """"auto" (determinant lemma where it applies) or "lu" (LU of every
-        distinct submatrix) for Raw Estimate."""
+        """"auto" (determinant lemma where it applies; exact mode along the
+        term list's prefix tree where it applies), "patterns" (the lemma, each
+        pattern's determinant on its own) or "lu" (LU of every distinct
+        submatrix)."""
         if evaluation not in _EVAL:
             raise ValueError(f"evaluation must be one of {sorted(_EVAL)}")
         check(lib().xf_plan_set_evaluation(self._h, _EVAL[evaluation]))

@@ -13,8 +13,12 @@ hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi,
                                  const uint64_t *xkeys, const double2 *xw, int64_t nkeys, uint32_t *flags,
                                  const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
                                  unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s);
+hipError_t launch_gen_tree(const DevPlan &p, const GenPlan &g, const DevTree &tr, int64_t nb, uint32_t *flags,
+                           const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
+                           unsigned long long *nterm, hipStream_t s);
 hipError_t prepare_gen_eval_raw();
 hipError_t prepare_gen_eval_exact();
+hipError_t prepare_gen_tree();
 
 namespace {
 
@@ -79,6 +83,18 @@ int gen_exact_segments(int64_t B, int64_t nkeys) {
     return (int)(want < most ? want : (most > 0 ? most : 1));
 }
 
+int gen_tree_left_segments(int64_t nkeys) {
+    const int64_t most = (nkeys + 255) / 256;
+    return (int)(most < 16 ? (most > 0 ? most : 1) : 16);
+}
+
+int gen_exact_part_segments(int64_t B, int64_t nkeys, bool tree) {
+    const int a = gen_exact_segments(B, nkeys);
+    if (!tree || a > 1) return a;
+    const int b = gen_tree_left_segments(nkeys);
+    return a > b ? a : b;
+}
+
 hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *bits,
                             int64_t b0, int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt,
                             uint32_t *ecount, uint64_t cap, void *setup, double *prob, double *amp, double *logp,
@@ -117,18 +133,21 @@ hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool
 hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *keys,
                             const double2 *w, int64_t nkeys, const uint64_t *bits, int64_t B, uint32_t *flags,
                             void *setup, double *prob, double *amp, double *logp, unsigned long long *nterm,
-                            hipEvent_t ev_mid, hipStream_t s) {
+                            hipEvent_t ev_mid, hipStream_t s, const DevTree *tree) {
     hipError_t e;
     double2 *hbuf = (double2 *)setup;
     GenRec *rec = (GenRec *)(hbuf + (size_t)B * g.hsize);
     // few bitstrings: each term list split over segments so that about 4096
     // workgroups take part; their partial sums follow the records
-    const int nseg = gen_exact_segments(B, nkeys);
+    int nseg = gen_exact_segments(B, nkeys);
+    const bool use_tree = tree && nseg <= 1 && !all_lu;
+    if (use_tree) nseg = gen_tree_left_segments(nkeys);
     uint64_t *part = (uint64_t *)(rec + B);
     if (all_lu) {
         if ((e = launch_fill_u32(flags, B, kEntryDeferred, s)) != hipSuccess) return e;
     } else {
         launch_gen_setup_t<true>(p, g, mixed, bits, 0, B, flags, hbuf, rec, prob, amp, logp, nterm, s);
+        if (use_tree) launch_gen_tree(p, g, *tree, B, flags, hbuf, rec, prob, amp, logp, nterm, s);
         launch_gen_eval_exact(p, g, g.multi, gen_wide(g), B, keys, w, nkeys, flags, hbuf, rec, prob, amp, logp, nterm,
                               nseg, part, s);
     }
@@ -147,7 +166,9 @@ hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool
 
 hipError_t prepare_gen() {
     hipError_t e;
-    if ((e = prepare_gen_eval_raw()) != hipSuccess || (e = prepare_gen_eval_exact()) != hipSuccess) return e;
+    if ((e = prepare_gen_eval_raw()) != hipSuccess || (e = prepare_gen_eval_exact()) != hipSuccess ||
+        (e = prepare_gen_tree()) != hipSuccess)
+        return e;
     for (const void *f : {(const void *)k_gen_setup<false, false, false>, (const void *)k_gen_setup<false, true, false>,
                           (const void *)k_gen_setup<true, false, false>, (const void *)k_gen_setup<true, true, false>,
                           (const void *)k_gen_setup<false, false, true>, (const void *)k_gen_setup<false, true, true>,

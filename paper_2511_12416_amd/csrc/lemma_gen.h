@@ -896,6 +896,9 @@ constexpr size_t kGenMaxLds = 150 * 1024;
 // takes it and tries the shifted bases.  Raw Estimate keeps its entry count
 // in its record meanwhile.
 constexpr uint32_t kEntryRetry = 0xFFFFFFFBu;
+// Exact mode: a bitstring that the prefix-tree kernel (lemma_tree.h) has
+// evaluated; the pattern pass skips it.
+constexpr uint32_t kEntryTree = 0xFFFFFFFAu;
 
 // Position of the n-th (from 0) set bit of x, which has more than n set bits.
 __device__ __forceinline__ int nth_bit64(uint64_t x, int n) {
@@ -1349,7 +1352,8 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
         const int64_t i = item / nseg, j = item % nseg;
         const int64_t b = b0 + i;
         const uint32_t flag = ecount[i];
-        if (WIDE_ONLY ? flag != kEntryWide : (flag == kEntryDeferred || flag == kEntryInvalid || flag == kEntryWide))
+        if (WIDE_ONLY ? flag != kEntryWide
+                      : (flag == kEntryDeferred || flag == kEntryInvalid || flag == kEntryWide || flag == kEntryTree))
             continue;
         if (!EXACT && !WIDE_ONLY) {
             // the setup's outcome: p = 0 already written, or no acceptable base (to k_gen_lu)

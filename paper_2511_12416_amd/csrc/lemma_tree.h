@@ -1,0 +1,380 @@
+// Exact mode by a prefix tree over the term list.
+//
+// Under the determinant lemma with an unshifted base, a term with flip
+// pattern N contributes w(N) det M_B det G[N, N] (Sec. IV-B Eq. 16-19 moved
+// onto the base), where G is fixed per bitstring: G = I - 2H for one CPhase
+// layer, G = I + 2TT - 2K for more than two (lemma_gen.h), block-diagonal
+// over the spin blocks.  Every det G[N, N] is a principal minor of the same
+// matrix, so the terms share work: ordering the flipped positions, a term's
+// minor is the product of the pivots of Gaussian elimination in that order,
+// and terms with a common prefix share its elimination (the recursion of
+// Griffin and Tsatsomeros for all principal minors of a matrix, Linear
+// Algebra Appl. 419 (2006), taken here four positions at a time).
+//
+// The tree (built once per plan on the host, shared by every bitstring): an
+// anchor is a set of 4 l positions that is the prefix of some pattern; its
+// matrix is the Schur complement G / G[anchor, anchor] on the positions its
+// descendants still need, computed from its parent's by eliminating four
+// positions (a 4 x 4 block with partial pivoting, then a rank-4 update); its
+// prefix determinant is the parent's times det of that block.  A pattern
+// hangs from its deepest anchor with at most four positions left, and costs a
+// det of at most 4 x 4 of its anchor's matrix.
+//
+// Elimination in a fixed order can lose accuracy where a pivot block is
+// nearly singular; the kernel tracks the growth of the entries (largest
+// |entry|^2 of any anchor matrix over the largest of G) and leaves every
+// bitstring whose growth exceeds the plan's limit, or whose pivot block is
+// exactly singular, to the pattern pass (which factorises each pattern's
+// r x r matrix on its own with partial pivoting).
+#pragma once
+#include "lemma_gen.h"
+
+namespace xf {
+namespace {
+
+// Solves a x = b (b replaced by x) for a 4 x 4 complex a by LU with partial
+// pivoting (largest |a|^2, lowest row on ties; row swaps through static-index
+// selects) and returns det a; 0 (and b unspecified) for an exactly singular a.
+__device__ __forceinline__ double2 solve4(double2 (&a)[4][4], double2 (&b)[4]) {
+    bool neg = false;
+    double2 det = make_double2(1.0, 0.0);
+    double2 inv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        double best = cabs2(a[c][c]);
+#pragma unroll
+        for (int i = c + 1; i < 4; ++i) {
+            const double v = cabs2(a[i][c]);
+            if (v > best) {
+                best = v;
+                piv = i;
+            }
+        }
+        if (!(best > 0.0)) return make_double2(0.0, 0.0);
+        neg ^= piv != c;
+#pragma unroll
+        for (int i = c + 1; i < 4; ++i) {
+            if (piv == i) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double2 t = a[c][j];
+                    a[c][j] = a[i][j];
+                    a[i][j] = t;
+                }
+                const double2 t = b[c];
+                b[c] = b[i];
+                b[i] = t;
+            }
+        }
+        det = c_mul(det, a[c][c]);
+        const double rb = 1.0 / best;
+        inv[c] = make_double2(a[c][c].x * rb, -a[c][c].y * rb);
+        const double2 ui = make_double2(-inv[c].x, -inv[c].y);
+#pragma unroll
+        for (int i = c + 1; i < 4; ++i) {
+            const double2 l = c_mul(a[i][c], ui);
+#pragma unroll
+            for (int j = c + 1; j < 4; ++j) a[i][j] = c_fma(a[i][j], l, a[c][j]);
+            b[i] = c_fma(b[i], l, b[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 3; c >= 0; --c) {
+        double2 v = b[c];
+#pragma unroll
+        for (int j = c + 1; j < 4; ++j) v = c_fma(v, make_double2(-a[c][j].x, -a[c][j].y), b[j]);
+        b[c] = c_mul(v, inv[c]);
+    }
+    return neg ? make_double2(-det.x, -det.y) : det;
+}
+
+// A pattern in registers: its weight, then r and idx[0..2] in m0 and idx[3]
+// in m1 (the byte layout of TreePat).
+struct PatRegs {
+    double2 w;
+    uint32_t m0, m1;
+};
+__device__ __forceinline__ PatRegs load_pat(const DevTree &tr, uint32_t q) {
+    const TreePat *t = tr.pat + q;
+    PatRegs r;
+    r.w = t->w;
+    const uint2 m = *(const uint2 *)((const unsigned char *)t + 16);
+    r.m0 = m.x;
+    r.m1 = m.y;
+    return r;
+}
+
+// One pattern: det of its r x r block of its anchor's matrix Q (row stride
+// ld), times its anchor's prefix determinant, the base determinant and its
+// weight, added exactly to acc.  Returns r.
+__device__ __forceinline__ int tree_pattern(const PatRegs &tp, const double2 *Q, int ld, double2 dpre, double2 detB,
+                                            FixAcc &acc) {
+    const int r = (int)(tp.m0 & 0xFF);
+    int idx[4];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) idx[u] = (int)((tp.m0 >> (8 * (u + 1))) & 0xFF);
+    idx[3] = (int)(tp.m1 & 0xFF);
+    double2 a[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            a[u][v] = (u < r && v < r) ? Q[idx[u] * ld + idx[v]] : make_double2(u == v ? 1.0 : 0.0, 0.0);
+    const double2 d = small_det4(a, r);
+    const double2 val = c_mul(tp.w, c_mul(detB, c_mul(dpre, d)));
+    fix_add_double(acc.re, acc.bad, val.x);
+    fix_add_double(acc.im, acc.bad, val.y);
+    return r;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// LDS ordering between the phases of one wave (the workgroup is one wave,
+// whose LDS accesses complete in issue order): a compiler fence, with no
+// wait on the global loads prefetched for the next anchor.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Evaluates the n staged patterns (a lane each): det of the 4 x 4 block
+// (LU with partial pivoting) times the factor, added exactly to acc.
+__device__ __forceinline__ void tree_flush(const double2 *St, const double2 *Fs, int n, FixAcc &acc) {
+    const int lane = threadIdx.x;
+    if (lane < n) {
+        double2 a[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[u][v] = St[lane * 16 + 4 * u + v];
+        const double2 val = c_mul(Fs[lane], small_det4(a, 4));
+        fix_add_double(acc.re, acc.bad, val.x);
+        fix_add_double(acc.im, acc.bad, val.y);
+    }
+    wave_sync();
+}
+
+// 64 anchor records, one per lane (five words each), and the fields of one
+// of them read back into every lane.
+struct AncLanes {
+    uint32_t w[5];
+};
+struct AncAt {
+    uint32_t pat0, npat, roff;
+    int level, nr, pnr;
+    int j[4];
+};
+__device__ __forceinline__ void load_anchor_lanes(const DevTree &tr, int base, AncLanes &a) {
+    // unconditional loads (clamped index), so that no branch holds back the
+    // compiler's wait counts
+    const int idx = base + (int)threadIdx.x;
+    const uint32_t *q = (const uint32_t *)tr.anc + 5 * (size_t)(idx < tr.nanc ? idx : 0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a.w[k] = q[k];
+}
+__device__ __forceinline__ AncAt anchor_at(const AncLanes &a, int lane) {
+    uint32_t w[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) w[k] = (uint32_t)__builtin_amdgcn_readlane((int)a.w[k], lane);
+    AncAt r;
+    r.pat0 = w[0];
+    r.npat = w[1];
+    r.roff = w[2];
+    r.level = (int)(w[3] & 0xFF);
+    r.nr = (int)((w[3] >> 8) & 0xFF);
+    r.pnr = (int)((w[3] >> 16) & 0xFF);
+    r.j[0] = (int)(w[3] >> 24);
+    r.j[1] = (int)(w[4] & 0xFF);
+    r.j[2] = (int)((w[4] >> 8) & 0xFF);
+    r.j[3] = (int)((w[4] >> 16) & 0xFF);
+    return r;
+}
+
+// One wave per bitstring (grid-stride).  Takes the bitstrings whose setup
+// succeeded with unshifted bases (flag 0, shift 0); on success writes p, A
+// and log p and sets the flag to kEntryTree, so that the pattern pass skips
+// them; otherwise leaves the flag for the pattern pass.  LDS: tr.lds bytes
+// (the levels' matrices, T, the prefix determinants and the staged
+// patterns).  The anchor records come 64 at a time into the lanes' registers
+// (the next 64 loaded while these are used); each anchor's R indices and
+// first four patterns are loaded one anchor ahead.  An anchor's patterns are
+// copied, as identity-padded 4 x 4 blocks with their factors, into a stage
+// that is evaluated kTreeStage at a time (a lane each), so that the
+// determinants run on full waves although an anchor has few patterns.
+template <bool MULTI>
+__global__ void __launch_bounds__(64)
+k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ flags,
+           const double2 *__restrict__ hbuf, const GenRec *__restrict__ rec, double *__restrict__ prob,
+           double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
+    static_assert(sizeof(TreeAnchor) == 20, "anchor records are five words");
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int sR[kTreeMaxM];
+    double2 *S = (double2 *)smem;
+    double2 *Tb = S + tr.toff;
+    double2 *Dl = S + tr.doff;
+    double2 *St = S + tr.soff;                      // staged blocks, 16 entries each
+    double2 *Fs = St + 16 * kTreeStage;             // their factors
+    const int lane = threadIdx.x;
+    const int M = tr.M;
+    Work wk;
+    unsigned long long done = 0;
+    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        if (flags[i] != 0) continue;
+        const uint64_t sh0 = rec[i].shift[0], sh1 = rec[i].shift[1];
+        if (sh0 | sh1) continue;
+        const double2 detB = rec[i].det;
+        const double2 *Hg = hbuf + (size_t)i * g.hsize;
+        AncLanes cur, nxt;
+        load_anchor_lanes(tr, 0, cur);
+        load_anchor_lanes(tr, 64, nxt);
+        // G on the tree's positions (zero across blocks)
+        double gmax = 0.0;
+        for (int e = lane; e < M * M; e += 64) {
+            const int a = e / M, b = e - a * M;
+            const int ca = tr.rpos[a], cb = tr.rpos[b];
+            const int blk = ca >> 8;
+            double2 v = make_double2(0.0, 0.0);
+            if (blk == (cb >> 8)) {
+                const int pa = ca & 0xFF, pb = cb & 0xFF;
+                const double2 h = Hg[g.hoff[blk] + pa * g.hld[blk] + pb];
+                v = make_double2((a == b ? 1.0 : 0.0) - 2.0 * h.x, -2.0 * h.y);
+                if constexpr (MULTI) {
+                    const double2 t = g.TT[((size_t)blk * 64 + pa) * 64 + pb];
+                    v.x += 2.0 * t.x;
+                    v.y += 2.0 * t.y;
+                }
+            }
+            S[e] = v;
+            gmax = fmax(gmax, cabs2(v));
+        }
+        if (lane == 0) Dl[0] = make_double2(1.0, 0.0);
+        wave_sync();
+        FixAcc acc;
+        double grow = 0.0;
+        bool bad = false;
+        unsigned long long rank = 0, flops = 0;
+        int nst = 0;   // patterns staged
+        for (int q = lane; q < tr.nroot; q += 64) {
+            const int r = tree_pattern(load_pat(tr, q), S, M, Dl[0], detB, acc);
+            rank += r;
+            flops += lu_flops(r) + 18;
+        }
+        // (the R index and pattern loads are unconditional, on clamped
+        // indices: both arrays hold at least one element)
+        AncAt A = anchor_at(cur, 0);
+        int rr = tr.ridx[A.roff + min(lane, max(A.nr - 1, 0))];
+        PatRegs pp = load_pat(tr, A.pat0 + (uint32_t)min(lane >> 4, max((int)A.npat - 1, 0)));
+        for (int an = 0; an < tr.nanc; ++an) {
+            // the next anchor's record, R indices and first patterns
+            const int n1 = an + 1;
+            if ((n1 & 63) == 0) {
+                cur = nxt;
+                load_anchor_lanes(tr, n1 + 64, nxt);
+            }
+            const bool more = n1 < tr.nanc;
+            const AncAt B = anchor_at(cur, n1 & 63);
+            const int rrB = tr.ridx[more ? B.roff + min(lane, max(B.nr - 1, 0)) : 0];
+            const PatRegs ppB = load_pat(tr, more ? B.pat0 + (uint32_t)min(lane >> 4, max((int)B.npat - 1, 0)) : 0u);
+
+            const int lv = A.level, nr = A.nr, pnr = A.pnr;
+            const double2 *P = S + tr.slot[lv - 1];
+            double2 *Q = S + tr.slot[lv];
+            // T = P[J, J]^-1 P[J, R] (a column per lane; every lane factorises
+            // the same block) and the prefix determinant
+            if (lane < max(nr, 1)) {
+                double2 m4[4][4], x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) m4[u][v] = P[A.j[u] * pnr + A.j[v]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = lane < nr ? P[A.j[u] * pnr + rr] : make_double2(0.0, 0.0);
+                const double2 dJ = solve4(m4, x);
+                bad |= dJ.x == 0.0 && dJ.y == 0.0;
+                if (lane < nr) {
+                    sR[lane] = rr;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) Tb[u * tr.maxr + lane] = x[u];
+                }
+                if (lane == 0) Dl[lv] = c_mul(Dl[lv - 1], dJ);
+            }
+            wave_sync();
+            // Q = P[R, R] - P[R, J] T; e / nr by a multiply (exact for
+            // e < nr^2 <= 1024, nr <= 32)
+            const uint32_t mg = ((1u << 20) + (uint32_t)nr - 1) / (uint32_t)max(nr, 1);
+            for (int e = lane; e < nr * nr; e += 64) {
+                const int ii = (int)(((uint32_t)e * mg) >> 20), jj = e - ii * nr;
+                const int ri = sR[ii], rj = sR[jj];
+                double2 s = P[ri * pnr + rj];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double2 c = P[ri * pnr + A.j[u]];
+                    s = c_fma(s, make_double2(-c.x, -c.y), Tb[u * tr.maxr + jj]);
+                }
+                Q[e] = s;
+                grow = fmax(grow, cabs2(s));
+            }
+            wave_sync();
+            // stage the anchor's patterns, four per pass (16 lanes each: one
+            // entry of the 4 x 4 block, identity past r) with their factors
+            // w det M_B dpre; evaluate the stage when it is full
+            const double2 dpre = Dl[lv];
+            for (int q0 = 0; q0 < (int)A.npat; q0 += 4) {
+                const int cnt = min(4, (int)A.npat - q0);
+                if (nst + cnt > kTreeStage) {
+                    wave_sync();
+                    tree_flush(St, Fs, nst, acc);
+                    nst = 0;
+                }
+                const int ql = lane >> 4, e = lane & 15, u = e >> 2, v = e & 3;
+                if (ql < cnt) {
+                    const PatRegs t = q0 == 0 ? pp : load_pat(tr, A.pat0 + q0 + ql);
+                    const int r = (int)(t.m0 & 0xFF);
+                    const uint64_t mm = (uint64_t)t.m0 | ((uint64_t)t.m1 << 32);
+                    const int iu = (int)((mm >> (8 * (u + 1))) & 0xFF), iv = (int)((mm >> (8 * (v + 1))) & 0xFF);
+                    St[(nst + ql) * 16 + e] =
+                        (u < r && v < r) ? Q[iu * nr + iv] : make_double2(u == v ? 1.0 : 0.0, 0.0);
+                    if (e == 0) {
+                        Fs[nst + ql] = c_mul(t.w, c_mul(detB, dpre));
+                        rank += 4 * lv + r;
+                        flops += lu_flops(r) + 18;
+                    }
+                }
+                nst += cnt;
+            }
+            if (lane == 0) flops += lu_flops(4) + 128ull * nr + 32ull * nr * nr + 6;
+            wave_sync();
+            A = B;
+            rr = rrB;
+            pp = ppB;
+        }
+        wave_sync();
+        tree_flush(St, Fs, nst, acc);
+        const double gm = wave_max(gmax), gr = wave_max(grow);
+        const bool fail = __ballot(bad) != 0 || !(gr <= tr.growth2 * gm);
+        if (fail) continue;   // the pattern pass takes it
+        fix_wave_sum(acc.re);
+        fix_wave_sum(acc.im);
+        const bool accbad = __ballot(acc.bad) != 0;
+        wk.rank += rank;
+        wk.flops += flops;
+        if (lane == 0) {
+            const uint64_t words[kAccWords] = {acc.re.w0, acc.re.w1, (uint64_t)acc.re.w2, acc.im.w0,
+                                               acc.im.w1, (uint64_t)acc.im.w2, accbad ? 1ull : 0ull};
+            write_result(i, acc_value(words), 1.0, prob, amp, logp);
+            flags[i] = kEntryTree;
+            wk.terms += (unsigned)tr.npat;
+            ++done;
+        }
+    }
+    flush_work(wk, nterm);
+    if (nterm && lane == 0 && done) atomicAdd(nterm + 7, done);
+}
+
+}  // namespace
+}  // namespace xf

@@ -162,6 +162,11 @@ struct xf_plan {
     DevBuf dgcol, dgact, dgpos0, dgpos1, dgblk, dgkbt, dggpos, dflags;
     DevBuf dgGA, dgHC, dgTT;          // more than two CPhase layers: the factors of each block's positions
     DevBuf dgsetup;                   // general lemma: per-bitstring H and base records
+    std::vector<uint16_t> hkbt;       // host copy of the key-bit table of the general lemma
+    // exact mode: the term list's prefix tree (lemma_tree.h), built with it
+    DevBuf dtanc, dtridx, dtpat, dtrpos;
+    xf::DevTree tree{};
+    bool has_tree = false;
     int last_gen = 0;                 // the last xf_probabilities call used the general lemma kernel
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
@@ -402,6 +407,7 @@ xf_status refresh_gen(xf_plan *P) {
         g.HC = (const double2 *)P->dgHC.p;
         g.TT = (const double2 *)P->dgTT.p;
     }
+    P->hkbt = kbt;
     if ((st = dev_upload(P->dgcol, col.data(), col.size())) || (st = dev_upload(P->dgact, act.data(), act.size())) ||
         (st = dev_upload(P->dgpos0, pos0.data(), 128)) || (st = dev_upload(P->dgpos1, pos1.data(), 128)) ||
         (st = dev_upload(P->dgblk, blk.data(), 128)) || (st = dev_upload(P->dgkbt, kbt.data(), 256)) ||
@@ -516,6 +522,221 @@ xf_status refresh_table(xf_plan *P) {
 // sums to exactly zero are dropped.  With derivatives (for the backward
 // pass), dw[key][j] = sum over its x of dw(x)/dtheta_j is stored as well and
 // keys are kept while any of weight or derivatives is non-zero.
+// Exact mode: the prefix tree of the term list over its flipped positions
+// (lemma_tree.h), for one CPhase layer or more than two under the general
+// lemma.  Tree positions are the (block, position) pairs some term flips, in
+// order; a pattern's anchor chain is the prefixes of 4, 8, ... of its
+// positions that leave it 1 to 4 more; each anchor keeps the positions beyond
+// its own that its descendants use.  No tree (has_tree = false) where more
+// than kTreeMaxM positions are flipped in all.
+xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::vector<double> &w) {
+    P->has_tree = false;
+    const xf::GenPlan &g = P->gen;
+    if (g.nblk == 0 || !(P->L == 1 || g.multi) || keys.empty() || P->hkbt.size() < 128) return XF_OK;
+    // the keys' flipped positions per block (a key bit flips one or two positions)
+    std::vector<uint32_t> code_of(2 * 256, 0xFFFFFFFFu);
+    std::vector<uint16_t> codes;
+    std::vector<std::vector<uint16_t>> kpos(keys.size());
+    for (size_t i = 0; i < keys.size(); ++i) {
+        uint64_t pm[2] = {0, 0};
+        for (uint64_t key = keys[i]; key; key &= key - 1) {
+            const int j = __builtin_ctzll(key);
+            for (int e = 0; e < 2; ++e) {
+                const uint16_t v = P->hkbt[2 * j + e];
+                if (v != 0xFFFF) pm[v >> 8] ^= 1ull << (v & 0xFF);
+            }
+        }
+        for (int b = 0; b < 2; ++b)
+            for (uint64_t mm = pm[b]; mm; mm &= mm - 1) {
+                const uint16_t c = (uint16_t)((b << 8) | __builtin_ctzll(mm));
+                kpos[i].push_back(c);
+                codes.push_back(c);
+            }
+    }
+    std::sort(codes.begin(), codes.end());
+    codes.erase(std::unique(codes.begin(), codes.end()), codes.end());
+    const int M = (int)codes.size();
+    if (M == 0 || M > xf::kTreeMaxM) return XF_OK;
+    for (int t = 0; t < M; ++t) code_of[codes[t]] = (uint32_t)t;
+    // distinct tree masks with summed weights
+    std::vector<std::pair<uint32_t, cd>> pats;
+    {
+        std::vector<std::pair<uint32_t, cd>> all(keys.size());
+        for (size_t i = 0; i < keys.size(); ++i) {
+            uint32_t m = 0;
+            for (uint16_t c : kpos[i]) m |= 1u << code_of[c];
+            all[i] = {m, cd(w[2 * i], w[2 * i + 1])};
+        }
+        std::sort(all.begin(), all.end(), [](const std::pair<uint32_t, cd> &a, const std::pair<uint32_t, cd> &b) {
+            return a.first < b.first;
+        });
+        for (size_t i = 0; i < all.size();) {
+            size_t e = i;
+            cd acc = 0.0;
+            while (e < all.size() && all[e].first == all[i].first) acc += all[e++].second;
+            if (acc != 0.0) pats.emplace_back(all[i].first, acc);
+            i = e;
+        }
+    }
+    struct Anc {
+        int level = 0, parent = -1;
+        int j[4] = {0, 0, 0, 0};
+        uint32_t need = 0;   // positions beyond its own that its descendants use
+        std::vector<int> kids, pats;
+    };
+    std::vector<Anc> an(1);
+    std::vector<std::pair<uint32_t, int>> ids;   // prefix mask -> anchor, sorted on insertion
+    auto find_anchor = [&](uint32_t m) -> int {
+        auto it = std::lower_bound(ids.begin(), ids.end(), std::make_pair(m, -1));
+        return (it != ids.end() && it->first == m) ? it->second : -1;
+    };
+    for (size_t pi = 0; pi < pats.size(); ++pi) {
+        int bits[32];
+        int r = 0;
+        for (uint32_t m = pats[pi].first; m; m &= m - 1) bits[r++] = __builtin_ctz(m);
+        const int q = r > 0 ? (r - 1) / 4 : 0;
+        int chain[9] = {0};
+        uint32_t pre = 0;
+        for (int lv = 1; lv <= q; ++lv) {
+            for (int u = 4 * lv - 4; u < 4 * lv; ++u) pre |= 1u << bits[u];
+            int id = find_anchor(pre);
+            if (id < 0) {
+                id = (int)an.size();
+                Anc a;
+                a.level = lv;
+                a.parent = chain[lv - 1];
+                for (int u = 0; u < 4; ++u) a.j[u] = bits[4 * lv - 4 + u];
+                an.push_back(a);
+                an[chain[lv - 1]].kids.push_back(id);
+                ids.insert(std::lower_bound(ids.begin(), ids.end(), std::make_pair(pre, -1)), std::make_pair(pre, id));
+            }
+            chain[lv] = id;
+        }
+        for (int lv = 0; lv <= q; ++lv) {
+            const int last = lv == 0 ? -1 : an[chain[lv]].j[3];
+            for (int u = 0; u < r; ++u)
+                if (bits[u] > last) an[chain[lv]].need |= 1u << bits[u];
+        }
+        an[chain[q]].pats.push_back((int)pi);
+    }
+    // the positions each anchor keeps: the root all M, others their need
+    auto rlist = [&](int a) {
+        std::vector<int> v;
+        if (a == 0) {
+            for (int t = 0; t < M; ++t) v.push_back(t);
+        } else {
+            for (uint32_t m = an[a].need; m; m &= m - 1) v.push_back(__builtin_ctz(m));
+        }
+        return v;
+    };
+    auto index_in = [](const std::vector<int> &v, int x) {
+        return (int)(std::lower_bound(v.begin(), v.end(), x) - v.begin());
+    };
+    std::vector<xf::TreeAnchor> tanc;
+    std::vector<uint8_t> tridx;
+    std::vector<xf::TreePat> tpat;
+    int maxnr[xf::kTreeLevels] = {M, 0, 0, 0, 0, 0, 0, 0};
+    int maxr = 1;
+    auto emit_pats = [&](int a, const std::vector<int> &R) {
+        const int last = a == 0 ? -1 : an[a].j[3];
+        for (int pi : an[a].pats) {
+            xf::TreePat tp{};
+            tp.w.x = pats[pi].second.real();
+            tp.w.y = pats[pi].second.imag();
+            tp.level = (uint8_t)an[a].level;
+            int r = 0;
+            for (uint32_t m = pats[pi].first; m; m &= m - 1) {
+                const int b = __builtin_ctz(m);
+                if (b > last) tp.idx[r++] = (uint8_t)index_in(R, b);
+            }
+            tp.r = (uint8_t)r;
+            tpat.push_back(tp);
+        }
+    };
+    emit_pats(0, rlist(0));
+    const int nroot = (int)tpat.size();
+    // depth-first over the anchors (iterative; children in creation order)
+    std::vector<std::pair<int, size_t>> stack;
+    stack.emplace_back(0, 0);
+    while (!stack.empty()) {
+        const int a = stack.back().first;
+        const size_t k = stack.back().second;
+        if (k >= an[a].kids.size()) {
+            stack.pop_back();
+            continue;
+        }
+        ++stack.back().second;
+        const int c = an[a].kids[k];
+        const std::vector<int> RP = rlist(a), RC = rlist(c);
+        xf::TreeAnchor ta{};
+        ta.level = (uint8_t)an[c].level;
+        ta.nr = (uint8_t)RC.size();
+        ta.pnr = (uint8_t)RP.size();
+        for (int u = 0; u < 4; ++u) ta.j[u] = (uint8_t)index_in(RP, an[c].j[u]);
+        ta.roff = (uint32_t)tridx.size();
+        for (int x : RC) tridx.push_back((uint8_t)index_in(RP, x));
+        ta.pat0 = (uint32_t)tpat.size();
+        emit_pats(c, RC);
+        ta.npat = (uint32_t)(tpat.size() - ta.pat0);
+        tanc.push_back(ta);
+        maxnr[ta.level] = std::max(maxnr[ta.level], (int)ta.nr);
+        maxr = std::max(maxr, (int)ta.nr);
+        stack.emplace_back(c, 0);
+    }
+    xf::DevTree &t = P->tree;
+    t = xf::DevTree{};
+    t.nanc = (int)tanc.size();
+    t.nroot = nroot;
+    t.npat = (int)tpat.size();
+    t.M = M;
+    int off = 0;
+    for (int l = 0; l < xf::kTreeLevels; ++l) {
+        t.slot[l] = off;
+        off += maxnr[l] * maxnr[l];
+    }
+    t.maxr = maxr;
+    t.toff = off;
+    t.doff = off + 4 * maxr;
+    t.soff = t.doff + xf::kTreeLevels;
+    t.lds = 16 * (t.soff + 17 * xf::kTreeStage);
+    t.growth2 = 1e8;
+    if (t.lds > 64 * 1024) return XF_OK;
+    // every index the kernel follows stays inside its matrix
+    for (const xf::TreeAnchor &a : tanc) {
+        if (a.level < 1 || a.level >= xf::kTreeLevels || a.pnr > maxnr[a.level - 1] || a.nr > maxnr[a.level])
+            return fail(XF_EDEVICE, "internal error: prefix tree anchor size");
+        for (int u = 0; u < 4; ++u)
+            if (a.j[u] >= a.pnr) return fail(XF_EDEVICE, "internal error: prefix tree anchor index");
+        for (int x = 0; x < a.nr; ++x)
+            if (tridx[a.roff + x] >= a.pnr) return fail(XF_EDEVICE, "internal error: prefix tree row index");
+        for (uint32_t q = a.pat0; q < a.pat0 + a.npat; ++q)
+            for (int u = 0; u < tpat[q].r; ++u)
+                if (tpat[q].r > 4 || tpat[q].idx[u] >= a.nr)
+                    return fail(XF_EDEVICE, "internal error: prefix tree pattern index");
+    }
+    for (int q = 0; q < nroot; ++q)
+        for (int u = 0; u < tpat[q].r; ++u)
+            if (tpat[q].r > 4 || tpat[q].idx[u] >= M) return fail(XF_EDEVICE, "internal error: prefix tree root index");
+    xf_status st;
+    // the kernel's prefetches read, unconditionally, one element past an
+    // anchor's R indices or patterns when it has none, and element 0 of the
+    // anchors: one element of padding each
+    tridx.push_back(0);
+    tpat.push_back(xf::TreePat{});
+    if (tanc.empty()) tanc.push_back(xf::TreeAnchor{});
+    if ((st = dev_upload(P->dtanc, tanc.data(), tanc.size() * sizeof(xf::TreeAnchor))) ||
+        (st = dev_upload(P->dtridx, tridx.data(), tridx.size())) ||
+        (st = dev_upload(P->dtpat, tpat.data(), tpat.size() * sizeof(xf::TreePat))) ||
+        (st = dev_upload(P->dtrpos, codes.data(), codes.size() * sizeof(uint16_t))))
+        return st;
+    t.anc = (const xf::TreeAnchor *)P->dtanc.p;
+    t.ridx = (const uint8_t *)P->dtridx.p;
+    t.pat = (const xf::TreePat *)P->dtpat.p;
+    t.rpos = (const uint16_t *)P->dtrpos.p;
+    P->has_tree = true;
+    return XF_OK;
+}
+
 xf_status build_exact_terms(xf_plan *P, bool with_dw) {
     const int k = P->k;
     const uint64_t nx = 1ull << k;
@@ -582,7 +803,7 @@ xf_status build_exact_terms(xf_plan *P, bool with_dw) {
     if (with_dw && (st = dev_upload(P->dxdw, dw.data(), dw.size() * 8))) return st;
     P->nxterms = (int64_t)keys.size();
     P->xterms_have_dw = with_dw;
-    return XF_OK;
+    return build_tree(P, keys, w);
 }
 
 xf::DevPlan snapshot(const xf_plan *P) {
@@ -616,7 +837,8 @@ void plan_free(xf_plan *P) {
                       &P->fA2, &P->fQ, &P->fR1, &P->dkeymode, &P->dT, &P->dgkey, &P->dgmode,
                       &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
                       &P->dgsum, &P->dekey, &P->decnt, &P->decount, &P->dgcol, &P->dgact, &P->dgpos0,
-                      &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dggpos, &P->dflags, &P->dgGA, &P->dgHC, &P->dgTT, &P->dgsetup})
+                      &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dggpos, &P->dflags, &P->dgGA, &P->dgHC, &P->dgTT, &P->dgsetup,
+                      &P->dtanc, &P->dtridx, &P->dtpat, &P->dtrpos})
         dev_free(*b);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();
@@ -899,7 +1121,9 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
     // sums), 256-byte aligned
     const uint64_t xflag_bytes = ((uint64_t)B * 4 + 255) & ~(uint64_t)255;
     const uint64_t xpart_bytes =
-        (mode == XF_EXACT && gen) ? (uint64_t)B * xf::gen_exact_segments(B, P->nxterms > 0 ? P->nxterms : ((int64_t)1 << P->k)) * 64 : 0;
+        (mode == XF_EXACT && gen)
+            ? (uint64_t)B * xf::gen_exact_part_segments(B, P->nxterms > 0 ? P->nxterms : ((int64_t)1 << P->k), true) * 64
+            : 0;
     if (noalloc && mode == XF_EXACT && gen &&
         xflag_bytes + (uint64_t)B * setup_bytes + xpart_bytes > xf::kNoAllocScratchBytes)
         return fail(XF_EUNSUPPORTED, "B = %lld exceeds the no-allocation scratch in exact mode", (long long)B);
@@ -980,7 +1204,8 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
         if (gen) {
             e = xf::launch_gen_exact(d, P->gen, mixed, all_lu, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p,
                                      P->nxterms, (const uint64_t *)d_bits, B, ecount, setup, d_prob, d_amp, d_logp,
-                                     nterm, nullptr, s);
+                                     nterm, nullptr, s,
+                                     (P->has_tree && P->evaluation == XF_EVAL_AUTO) ? &P->tree : nullptr);
             P->last_gen = 1;
         } else {
             e = xf::launch_exact(d, mixed, (const uint64_t *)P->dxkeys.p, (const double2 *)P->dxw.p, P->nxterms,
@@ -1347,6 +1572,7 @@ xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
     work->general = P->last_gen;
     work->fp32_bases = (int64_t)v[3];
     work->philox_blocks = (int64_t)v[4];
+    work->tree_bitstrings = (int64_t)v[7];
     work->sample_ms = 0.0;
     work->eval_ms = 0.0;
     for (int i = 1; i < P->nev; ++i) {
@@ -1376,7 +1602,8 @@ xf_status xf_plan_set_mixed_condition(xf_plan *P, double kappa_max) {
 
 xf_status xf_plan_set_evaluation(xf_plan *P, xf_evaluation evaluation) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
-    if (evaluation != XF_EVAL_AUTO && evaluation != XF_EVAL_LU) return fail(XF_EINVAL, "unknown evaluation");
+    if (evaluation != XF_EVAL_AUTO && evaluation != XF_EVAL_LU && evaluation != XF_EVAL_PATTERNS)
+        return fail(XF_EINVAL, "unknown evaluation");
     P->evaluation = evaluation;
     return ok();
 }

@@ -86,6 +86,42 @@ struct GenPlan {
     const double2 *GA, *HC, *TT;
 };
 
+// Exact mode: the term list as a prefix tree over the flipped positions,
+// shared by every bitstring (lemma_tree.h).  An anchor is a prefix of four
+// more positions than its parent's; its matrix is the Schur complement that
+// eliminating them leaves on the positions its descendants still need (R).
+// Anchors are stored in depth-first order, each with its own patterns.
+struct TreeAnchor {
+    uint32_t pat0, npat;   // its patterns: pat[pat0 .. pat0 + npat)
+    uint32_t roff;         // R as indices into the parent's R: ridx[roff .. roff + nr)
+    uint8_t level;         // 4 level positions eliminated (1, 2, ...)
+    uint8_t nr, pnr;       // |R| and the parent's |R|
+    uint8_t j[4];          // the four positions, as indices into the parent's R
+    uint8_t pad;
+};
+struct TreePat {
+    double2 w;             // summed weight of the terms with this flip pattern
+    uint8_t r;             // positions beyond its anchor (0..4)
+    uint8_t idx[4];        // their indices into the anchor's R
+    uint8_t level;         // its anchor's level (0: the root)
+    uint8_t pad[10];
+};
+constexpr int kTreeMaxM = 32;     // positions of the tree (all blocks)
+constexpr int kTreeLevels = 8;    // anchor levels 0 (the root, all positions) .. 7
+constexpr int kTreeStage = 32;    // patterns staged for one batched evaluation
+struct DevTree {
+    const TreeAnchor *anc;
+    const uint8_t *ridx;
+    const TreePat *pat;
+    const uint16_t *rpos;  // [M]: (block << 8 | position) of each tree position
+    int nanc, nroot, npat, M;
+    int slot[kTreeLevels];  // LDS offset (complex entries) of each level's matrix; slot[0]: M x M
+    int toff, doff, maxr;   // LDS offsets of T (4 x maxr) and of the levels' prefix determinants
+    int soff;               // LDS offset of the staged patterns (kTreeStage 4 x 4 blocks, then their factors)
+    int lds;                // bytes
+    double growth2;         // largest |entry|^2 / max |G|^2 accepted
+};
+
 // Per-bitstring record of the general lemma's setup kernel (see lemma_gen.h).
 struct GenRec {
     double2 det;          // product over blocks of det M_B
@@ -197,7 +233,9 @@ hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, c
 // then the LU kernel for the bitstrings it deferred; with all_lu, the LU
 // kernel for every bitstring).  launch_gen_exact: exact mode over [0, B) with
 // flags[B] marking deferred bitstrings, then the LU kernel for those (all of
-// them with all_lu).
+// them with all_lu); with a prefix tree (tree != nullptr, one or more than two
+// CPhase layers), its kernel takes the bitstrings whose bases need no shift
+// before the pattern pass takes the rest.
 bool gen_applies(const DevPlan &p, const GenPlan &g);
 // gen_setup_bytes: bytes per bitstring of the setup workspace the launchers
 // take in `setup` (each bitstring's H, then its base determinant and patterns).
@@ -206,6 +244,12 @@ size_t gen_setup_bytes(const GenPlan &g);
 // 1024 bitstrings is spread over about 4096 workgroups); the setup workspace
 // then also holds B * segments partial sums of 64 bytes after the records.
 int gen_exact_segments(int64_t B, int64_t nkeys);
+// Segments of the pattern pass (and of the LU kernel) after the prefix-tree
+// kernel, which leaves few bitstrings: each of their term lists is split so
+// that no single workgroup walks a long list.  gen_exact_part_segments: the
+// segments the setup workspace holds partial sums for (the larger of both).
+int gen_tree_left_segments(int64_t nkeys);
+int gen_exact_part_segments(int64_t B, int64_t nkeys, bool tree);
 hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *bits,
                             int64_t b0, int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt,
                             uint32_t *ecount, uint64_t cap, void *setup, double *prob, double *amp, double *logp,
@@ -213,7 +257,7 @@ hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool
 hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *keys,
                             const double2 *w, int64_t nkeys, const uint64_t *bits, int64_t B, uint32_t *flags,
                             void *setup, double *prob, double *amp, double *logp, unsigned long long *nterm,
-                            hipEvent_t ev_mid, hipStream_t s);
+                            hipEvent_t ev_mid, hipStream_t s, const DevTree *tree);
 hipError_t prepare_gen();
 // Device address of the no-allocation scratch on `device` (current), looked up
 // once per device (k_noalloc.hip).
