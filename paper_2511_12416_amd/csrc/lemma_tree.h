@@ -15,68 +15,57 @@
 // anchor is a set of 4 l positions that is the prefix of some pattern; its
 // matrix is the Schur complement G / G[anchor, anchor] on the positions its
 // descendants still need, computed from its parent's by eliminating four
-// positions (a 4 x 4 block with partial pivoting, then a rank-4 update); its
+// positions (Gaussian elimination of a 4 x 4 block, then a rank-4 update); its
 // prefix determinant is the parent's times det of that block.  A pattern
 // hangs from its deepest anchor with at most four positions left, and costs a
 // det of at most 4 x 4 of its anchor's matrix.
 //
-// Elimination in a fixed order can lose accuracy where a pivot block is
-// nearly singular; the kernel tracks the growth of the entries (largest
-// |entry|^2 of any anchor matrix over the largest of G) and leaves every
-// bitstring whose growth exceeds the plan's limit, or whose pivot block is
-// exactly singular, to the pattern pass (which factorises each pattern's
-// r x r matrix on its own with partial pivoting).
+// Elimination in a fixed order can lose accuracy where a pivot is small; the
+// kernel tracks the growth it allows (the largest |multiplier|^2 of the
+// blocks' eliminations, and the largest |entry|^2 of any anchor matrix over
+// the largest of G) and leaves every bitstring whose growth exceeds the
+// plan's limit, or that meets a zero pivot, to the pattern pass (which
+// factorises each pattern's r x r matrix on its own with partial pivoting).
+// The patterns' own determinants (at most 4 x 4) use partial pivoting.
 #pragma once
 #include "lemma_gen.h"
 
 namespace xf {
 namespace {
 
-// Solves a x = b (b replaced by x) for a 4 x 4 complex a by LU with partial
-// pivoting (largest |a|^2, lowest row on ties; row swaps through static-index
-// selects) and returns det a; 0 (and b unspecified) for an exactly singular a.
-__device__ __forceinline__ double2 solve4(double2 (&a)[4][4], double2 (&b)[4]) {
-    bool neg = false;
+// 1 / x for a normal, finite x > 0: the hardware reciprocal estimate
+// refined by two Newton steps (each at least doubles the correct bits).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Solves a x = b (b replaced by x) for a 4 x 4 complex a by Gaussian
+// elimination in the given order (the tree's order: no row exchanges) and
+// returns det a; 0 (and b unspecified) for a zero or non-finite pivot.  gl
+// takes the largest |multiplier|^2, the growth the elimination allows.
+__device__ __forceinline__ double2 solve4(double2 (&a)[4][4], double2 (&b)[4], double &gl) {
     double2 det = make_double2(1.0, 0.0);
     double2 inv[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        int piv = c;
-        double best = cabs2(a[c][c]);
+        const double2 pv = a[c][c];
+        const double n2 = cabs2(pv);
+        if (!(n2 > 0.0 && n2 < 1e300)) return make_double2(0.0, 0.0);
+        det = c_mul(det, pv);
+        const double rb = recip(n2);
+        inv[c] = make_double2(pv.x * rb, -pv.y * rb);
 #pragma unroll
         for (int i = c + 1; i < 4; ++i) {
-            const double v = cabs2(a[i][c]);
-            if (v > best) {
-                best = v;
-                piv = i;
-            }
-        }
-        if (!(best > 0.0)) return make_double2(0.0, 0.0);
-        neg ^= piv != c;
+            const double2 l = c_mul(a[i][c], inv[c]);
+            gl = fmax(gl, cabs2(l));
+            const double2 nl = make_double2(-l.x, -l.y);
 #pragma unroll
-        for (int i = c + 1; i < 4; ++i) {
-            if (piv == i) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const double2 t = a[c][j];
-                    a[c][j] = a[i][j];
-                    a[i][j] = t;
-                }
-                const double2 t = b[c];
-                b[c] = b[i];
-                b[i] = t;
-            }
-        }
-        det = c_mul(det, a[c][c]);
-        const double rb = 1.0 / best;
-        inv[c] = make_double2(a[c][c].x * rb, -a[c][c].y * rb);
-        const double2 ui = make_double2(-inv[c].x, -inv[c].y);
-#pragma unroll
-        for (int i = c + 1; i < 4; ++i) {
-            const double2 l = c_mul(a[i][c], ui);
-#pragma unroll
-            for (int j = c + 1; j < 4; ++j) a[i][j] = c_fma(a[i][j], l, a[c][j]);
-            b[i] = c_fma(b[i], l, b[c]);
+            for (int j = c + 1; j < 4; ++j) a[i][j] = c_fma(a[i][j], nl, a[c][j]);
+            b[i] = c_fma(b[i], nl, b[c]);
         }
     }
 #pragma unroll
@@ -86,7 +75,7 @@ __device__ __forceinline__ double2 solve4(double2 (&a)[4][4], double2 (&b)[4]) {
         for (int j = c + 1; j < 4; ++j) v = c_fma(v, make_double2(-a[c][j].x, -a[c][j].y), b[j]);
         b[c] = c_mul(v, inv[c]);
     }
-    return neg ? make_double2(-det.x, -det.y) : det;
+    return det;
 }
 
 // A pattern in registers: its weight, then r and idx[0..2] in m0 and idx[3]
@@ -255,7 +244,7 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
         if (lane == 0) Dl[0] = make_double2(1.0, 0.0);
         wave_sync();
         FixAcc acc;
-        double grow = 0.0;
+        double grow = 0.0, gl = 0.0;
         bool bad = false;
         unsigned long long rank = 0, flops = 0;
         int nst = 0;   // patterns staged
@@ -294,7 +283,7 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
                     for (int v = 0; v < 4; ++v) m4[u][v] = P[A.j[u] * pnr + A.j[v]];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) x[u] = lane < nr ? P[A.j[u] * pnr + rr] : make_double2(0.0, 0.0);
-                const double2 dJ = solve4(m4, x);
+                const double2 dJ = solve4(m4, x, gl);
                 bad |= dJ.x == 0.0 && dJ.y == 0.0;
                 if (lane < nr) {
                     sR[lane] = rr;
@@ -355,8 +344,8 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
         }
         wave_sync();
         tree_flush(St, Fs, nst, acc);
-        const double gm = wave_max(gmax), gr = wave_max(grow);
-        const bool fail = __ballot(bad) != 0 || !(gr <= tr.growth2 * gm);
+        const double gm = wave_max(gmax), gr = wave_max(grow), ml = wave_max(gl);
+        const bool fail = __ballot(bad) != 0 || !(gr <= tr.growth2 * gm) || !(ml <= tr.growth2);
         if (fail) continue;   // the pattern pass takes it
         fix_wave_sum(acc.re);
         fix_wave_sum(acc.im);
