@@ -8,10 +8,11 @@ namespace xf {
 hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t nb,
                                  const uint64_t *xkeys, const double2 *xw, int64_t nkeys, uint32_t *flags,
                                  const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
-                                 unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s) {
+                                 unsigned long long *nterm, int nseg, uint64_t *part, int grid_cap, hipStream_t s) {
     const size_t lds = gen_lds_bytes(g, true), lds16 = gen_lds_bytes(g, false);
     const int64_t items = nb * nseg;
-    const int grid = (int)(items < kMaxGrid ? items : kMaxGrid);
+    const int64_t cap = grid_cap > 0 ? grid_cap : kMaxGrid;
+    const int grid = (int)(items < cap ? items : cap);
 #define XF_EVAL(MULTI, BIG)                                                                                     \
     hipLaunchKernelGGL((k_gen_eval<true, MULTI, BIG, false>), dim3(grid), dim3(kThreads), BIG ? lds : lds16, s, p, \
                        g, (int64_t)0, nb, nullptr, nullptr, flags, (uint64_t)0, xkeys, xw, nkeys, hbuf, rec, prob,  \

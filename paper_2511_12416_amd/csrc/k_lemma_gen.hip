@@ -12,7 +12,7 @@ hipError_t launch_gen_eval_raw(const DevPlan &p, const GenPlan &g, bool multi, b
 hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi, bool wide, int64_t nb,
                                  const uint64_t *xkeys, const double2 *xw, int64_t nkeys, uint32_t *flags,
                                  const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
-                                 unsigned long long *nterm, int nseg, uint64_t *part, hipStream_t s);
+                                 unsigned long long *nterm, int nseg, uint64_t *part, int grid_cap, hipStream_t s);
 hipError_t launch_gen_tree(const DevPlan &p, const GenPlan &g, const DevTree &tr, int64_t nb, uint32_t *flags,
                            const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
                            unsigned long long *nterm, hipStream_t s);
@@ -149,7 +149,7 @@ hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool
         launch_gen_setup_t<true>(p, g, mixed, bits, 0, B, flags, hbuf, rec, prob, amp, logp, nterm, s);
         if (use_tree) launch_gen_tree(p, g, *tree, B, flags, hbuf, rec, prob, amp, logp, nterm, s);
         launch_gen_eval_exact(p, g, g.multi, gen_wide(g), B, keys, w, nkeys, flags, hbuf, rec, prob, amp, logp, nterm,
-                              nseg, part, s);
+                              nseg, part, use_tree ? 2048 : 0, s);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
