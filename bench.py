@@ -199,6 +199,25 @@ def run_headline(X, W, args, dev):
     return w, res
 
 
+def run_exact_stress(X, W, args, dev) -> int:
+    """The exact stress workload alone (the command its kernel profile is
+    taken with): ms per call, terms/s, the evaluation kernels' time."""
+    import torch
+    w = W.workload(3)
+    bits = X.bits_tensor(w.bits, dev)
+    out = torch.empty(w.B, dtype=torch.float64, device=dev)
+    plan = X.Plan(w.rot, w.pairs, w.layer, w.theta, w.input_bits, "fp64", device=0)
+    wall = timed_steps(plan, bits, w.mode, w.t, w.seed, out, args.steps, args.warmup)
+    wk = plan.last_work()
+    terms = w.B * (1 << w.k)
+    print(json.dumps({"workload": w.name, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": wall * 1e3 / args.steps, "value": terms * args.steps / wall,
+                      "unit": "terms/s", "dtype": "f64", "eval_ms_last_call": wk["eval_ms"],
+                      "tree_bitstrings": wk["tree_bitstrings"], "flops_per_call": wk["flops"]}), flush=True)
+    plan.close()
+    return 0
+
+
 def run_extras(X, W, args, dev):
     """Configs other than the headline: ms per call and terms/s."""
     import torch
@@ -272,6 +291,9 @@ def main() -> int:
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="after the timed region, a fill and a sum over this many MiB (the reference "
                          "kernels that scale the HBM byte counters)")
+    ap.add_argument("--exact-stress", action="store_true",
+                    help="only the exact-mode stress workload (n = 52, eta = 26, all 4096 terms of 4096 "
+                         "bitstrings, along the term list's prefix tree): one JSON line of its own")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the path shards by "
@@ -285,6 +307,8 @@ def main() -> int:
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.exact_stress:
+        return run_exact_stress(X, W, args, dev)
     w, res = run_headline(X, W, args, dev)
     r = res["fp64"]
     terms = w.B * w.t
