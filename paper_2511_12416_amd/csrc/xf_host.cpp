@@ -578,6 +578,99 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
             i = e;
         }
     }
+    // The order of the positions decides how many prefixes the patterns
+    // share (how many anchors the tree has): the natural order, the gates'
+    // order and seeded random orders of the gates and of the positions are
+    // tried, and the one with the fewest anchors is kept (deterministic for
+    // a given plan).
+    {
+        std::vector<std::vector<int>> gate_pos;
+        for (int j = 0; j < P->k && j < 64; ++j) {
+            std::vector<int> v;
+            for (uint64_t gk = P->gkey[j]; gk; gk &= gk - 1) {
+                const int b = __builtin_ctzll(gk);
+                for (int e = 0; e < 2 && b < 64; ++e) {
+                    const uint16_t c = P->hkbt[2 * b + e];
+                    if (c != 0xFFFF && code_of[c] != 0xFFFFFFFFu) v.push_back((int)code_of[c]);
+                }
+            }
+            gate_pos.push_back(v);
+        }
+        auto from_gates = [&](const std::vector<int> &gorder) {
+            std::vector<int> ord;
+            std::vector<char> in(M, 0);
+            for (int j : gorder)
+                for (int t : gate_pos[j])
+                    if (!in[t]) in[t] = 1, ord.push_back(t);
+            for (int t = 0; t < M; ++t)
+                if (!in[t]) ord.push_back(t);
+            return ord;
+        };
+        // anchors of an order (ord[r] = the position taking rank r)
+        std::vector<uint32_t> seen;
+        auto anchors_of = [&](const std::vector<int> &ord) {
+            int rank[xf::kTreeMaxM];
+            for (int r = 0; r < M; ++r) rank[ord[r]] = r;
+            seen.clear();
+            for (const auto &pw : pats) {
+                uint32_t rm = 0;
+                for (uint32_t m = pw.first; m; m &= m - 1) rm |= 1u << rank[__builtin_ctz(m)];
+                // the prefixes of 4, 8, ... positions (ascending rank) short of the whole pattern
+                const int r = __builtin_popcount(rm);
+                uint32_t pre = 0;
+                int cnt = 0;
+                for (uint32_t m = rm; m; m &= m - 1) {
+                    pre |= m & (~m + 1);
+                    if (++cnt % 4 == 0) {
+                        if (cnt >= r) break;
+                        seen.push_back(pre);
+                    }
+                }
+            }
+            std::sort(seen.begin(), seen.end());
+            return (size_t)(std::unique(seen.begin(), seen.end()) - seen.begin());
+        };
+        std::vector<int> best(M);
+        for (int t = 0; t < M; ++t) best[t] = t;
+        size_t best_n = anchors_of(best);
+        std::vector<int> gorder(gate_pos.size());
+        for (size_t j = 0; j < gorder.size(); ++j) gorder[j] = (int)j;
+        auto consider = [&](const std::vector<int> &ord) {
+            const size_t n = anchors_of(ord);
+            if (n < best_n) best_n = n, best = ord;
+        };
+        consider(from_gates(gorder));
+        uint64_t z = 0x9E3779B97F4A7C15ull;   // splitmix64, fixed seed
+        auto next = [&]() {
+            uint64_t x = (z += 0x9E3779B97F4A7C15ull);
+            x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+            x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+            return x ^ (x >> 31);
+        };
+        const size_t work = pats.size() * (size_t)M;
+        const int tries = work > (8u << 20) ? 4 : (work > (1u << 20) ? 16 : 48);
+        for (int it = 0; it < tries; ++it) {
+            std::vector<int> g = gorder, o(M);
+            for (int i = (int)g.size() - 1; i > 0; --i) std::swap(g[i], g[next() % (uint64_t)(i + 1)]);
+            consider(from_gates(g));
+            for (int t = 0; t < M; ++t) o[t] = t;
+            for (int i = M - 1; i > 0; --i) std::swap(o[i], o[next() % (uint64_t)(i + 1)]);
+            consider(o);
+        }
+        int rank[xf::kTreeMaxM];
+        for (int r = 0; r < M; ++r) rank[best[r]] = r;
+        std::vector<uint16_t> c2(M);
+        for (int r = 0; r < M; ++r) c2[r] = codes[best[r]];
+        codes = c2;
+        for (auto &pw : pats) {
+            uint32_t rm = 0;
+            for (uint32_t m = pw.first; m; m &= m - 1) rm |= 1u << rank[__builtin_ctz(m)];
+            pw.first = rm;
+        }
+        std::sort(pats.begin(), pats.end(), [](const std::pair<uint32_t, cd> &a, const std::pair<uint32_t, cd> &b) {
+            return a.first < b.first;
+        });
+    }
     struct Anc {
         int level = 0, parent = -1;
         int j[4] = {0, 0, 0, 0};
