@@ -167,6 +167,10 @@ struct xf_plan {
     DevBuf dtanc, dtridx, dtpat, dtrpos;
     xf::DevTree tree{};
     bool has_tree = false;
+    // the tree's position order, kept while the set of flip patterns (not
+    // their weights) stays the same
+    std::vector<uint16_t> tree_codes;
+    uint64_t tree_key = 0;
     int last_gen = 0;                 // the last xf_probabilities call used the general lemma kernel
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
@@ -581,9 +585,26 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
     // The order of the positions decides how many prefixes the patterns
     // share (how many anchors the tree has): the natural order, the gates'
     // order and seeded random orders of the gates and of the positions are
-    // tried, and the one with the fewest anchors is kept (deterministic for
-    // a given plan).
-    {
+    // tried, the best is improved by swapping pairs of positions while that
+    // does not add anchors, and the order with the fewest anchors is kept
+    // (deterministic for a given plan; reused while the set of patterns is
+    // unchanged).
+    uint64_t pkey = 1469598103934665603ull ^ (uint64_t)M;
+    for (const auto &pw : pats) pkey = (pkey ^ pw.first) * 1099511628211ull;
+    for (uint16_t c : codes) pkey = (pkey ^ c) * 1099511628211ull;
+    if (pkey == P->tree_key && P->tree_codes.size() == (size_t)M) {
+        std::vector<int> rank_of(M);
+        for (int r = 0; r < M; ++r) rank_of[code_of[P->tree_codes[r]]] = r;
+        for (auto &pw : pats) {
+            uint32_t rm = 0;
+            for (uint32_t m = pw.first; m; m &= m - 1) rm |= 1u << rank_of[__builtin_ctz(m)];
+            pw.first = rm;
+        }
+        codes = P->tree_codes;
+        std::sort(pats.begin(), pats.end(), [](const std::pair<uint32_t, cd> &a, const std::pair<uint32_t, cd> &b) {
+            return a.first < b.first;
+        });
+    } else {
         std::vector<std::vector<int>> gate_pos;
         for (int j = 0; j < P->k && j < 64; ++j) {
             std::vector<int> v;
@@ -657,6 +678,17 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
             for (int i = M - 1; i > 0; --i) std::swap(o[i], o[next() % (uint64_t)(i + 1)]);
             consider(o);
         }
+        // pairwise swaps, kept unless they add anchors (about 6e7 position
+        // visits in all)
+        const int swaps = (int)std::min<size_t>(600, (60u << 20) / std::max<size_t>(work, 1));
+        for (int it = 0; it < swaps && M > 1; ++it) {
+            std::vector<int> o = best;
+            const int a = (int)(next() % (uint64_t)M), b = (int)(next() % (uint64_t)M);
+            if (a == b) continue;
+            std::swap(o[a], o[b]);
+            const size_t n = anchors_of(o);
+            if (n <= best_n) best_n = n, best = o;
+        }
         int rank[xf::kTreeMaxM];
         for (int r = 0; r < M; ++r) rank[best[r]] = r;
         std::vector<uint16_t> c2(M);
@@ -670,6 +702,8 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
         std::sort(pats.begin(), pats.end(), [](const std::pair<uint32_t, cd> &a, const std::pair<uint32_t, cd> &b) {
             return a.first < b.first;
         });
+        P->tree_key = pkey;
+        P->tree_codes = codes;
     }
     struct Anc {
         int level = 0, parent = -1;
