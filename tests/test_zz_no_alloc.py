@@ -81,6 +81,24 @@ def test_noalloc_general_lemma_two_calls(X):
     assert np.array_equal(p2, q2) and np.array_equal(a2, b2) and np.array_equal(l2, m2)
 
 
+def test_noalloc_exact_prefix_tree_two_calls(X):
+    """Exact mode along the term list's prefix tree (batches of at least 1024
+    bitstrings), the setup records and segment partials in the scratch: the
+    exact stress workload, then a smaller batch of another circuit, each
+    bitwise equal to the allocating call."""
+    w = W.workload(3)
+    w2 = W.random_circuit(951, 14, 7, 10, n_rot=2, max_bits=4096)
+    for ww, bits in ((w, w.bits), (w2, w2.bits[:1024])):
+        plan = make_plan(ww, X)
+        say(f"no-allocation prefix tree: {ww.name} B={len(bits)}")
+        (p1, a1, l1), (q1, b1, m1) = _both(X, plan, X.bits_tensor(bits), 0, 0, X._abi.XF_EXACT)
+        wk = plan.last_work()
+        assert wk["general"] and wk["tree_bitstrings"] > 0, wk
+        assert np.array_equal(p1, q1) and np.array_equal(a1, b1) and np.array_equal(l1, m1)
+        assert np.count_nonzero(p1) == len(bits)
+        plan.close()
+
+
 def test_noalloc_overflowing_regions_match(X):
     """Large angles: every sample is a distinct pattern, more than a
     workspace region holds, so the bitstrings are left to the LU kernel; the
