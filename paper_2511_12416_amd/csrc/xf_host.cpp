@@ -529,10 +529,11 @@ xf_status refresh_table(xf_plan *P) {
 // Exact mode: the prefix tree of the term list over its flipped positions
 // (lemma_tree.h), for one CPhase layer or more than two under the general
 // lemma.  Tree positions are the (block, position) pairs some term flips, in
-// order; a pattern's anchor chain is the prefixes of 4, 8, ... of its
-// positions that leave it 1 to 4 more; each anchor keeps the positions beyond
-// its own that its descendants use.  No tree (has_tree = false) where more
-// than kTreeMaxM positions are flipped in all.
+// an order chosen to minimise the anchors; a pattern's anchor chain is the
+// prefixes of 4, 8, ... of its positions (in that order) that leave it 1 to 4
+// more; each anchor keeps the positions beyond its own that its descendants
+// use.  No tree (has_tree = false) where more than kTreeMaxM positions are
+// flipped in all.
 xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::vector<double> &w) {
     P->has_tree = false;
     const xf::GenPlan &g = P->gen;
