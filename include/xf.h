@@ -305,9 +305,10 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
  *     region, is evaluated with the LU of every M_N instead.  The gradient
  *     (xf_log_prob_backward) uses the lemma for one CPhase layer and
  *     eta <= 16 under Raw Estimate, the LU elsewhere.
- * Exact mode under XF_EVAL_AUTO, for one CPhase layer or more than two: the
- * patterns' determinants det S are principal minors of one matrix per
- * bitstring (I - 2H, or I + 2TT - 2K for many layers), so terms whose flipped
+ * Exact mode under XF_EVAL_AUTO: the patterns' determinants det S are
+ * principal minors of one matrix per bitstring (I - 2H for one CPhase layer,
+ * I + 2T - 2H with T = R'_1 between the layers' positions for two, I + 2TT -
+ * 2K for more), so terms whose flipped
  * positions share a prefix share its elimination.  The plan arranges the
  * term list as a prefix tree over those positions (at most 32 in all; anchors
  * every four positions, each a Schur complement of its parent's), and one

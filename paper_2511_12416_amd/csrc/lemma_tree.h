@@ -2,9 +2,12 @@
 //
 // Under the determinant lemma with an unshifted base, a term with flip
 // pattern N contributes w(N) det M_B det G[N, N] (Sec. IV-B Eq. 16-19 moved
-// onto the base), where G is fixed per bitstring: G = I - 2H for one CPhase
-// layer, G = I + 2TT - 2K for more than two (lemma_gen.h), block-diagonal
-// over the spin blocks.  Every det G[N, N] is a principal minor of the same
+// onto the base), where G is fixed per bitstring and block-diagonal over the
+// spin blocks: G = I - 2H for one CPhase layer; G = I + 2T - 2H for two,
+// with T = R'_1 from layer-0 to layer-1 positions (zero elsewhere: T^2 = 0,
+// so det(I + 2T - 2H)[N, N] = det(I - 2(I - 2T)H)[N, N], the two-layer form
+// that corrects the layer-1 rows by the pattern's layer-0 flips); G = I +
+// 2TT - 2K for more than two (lemma_gen.h).  Every det G[N, N] is a principal minor of the same
 // matrix, so the terms share work: ordering the flipped positions, a term's
 // minor is the product of the pivots of Gaussian elimination in that order,
 // and terms with a common prefix share its elimination (the recursion of
@@ -234,6 +237,12 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
                 v = make_double2((a == b ? 1.0 : 0.0) - 2.0 * h.x, -2.0 * h.y);
                 if constexpr (MULTI) {
                     const double2 t = g.TT[((size_t)blk * 64 + pa) * 64 + pb];
+                    v.x += 2.0 * t.x;
+                    v.y += 2.0 * t.y;
+                } else if (p.L == 2 && pa >= g.kb0[blk] && pb < g.kb0[blk]) {
+                    // two layers: T = R'_1 from layer-0 to layer-1 positions
+                    const uint8_t *act = g.act + blk * kGenMaxKb;
+                    const double2 t = p.R1[(size_t)act[pa] * p.n + act[pb]];
                     v.x += 2.0 * t.x;
                     v.y += 2.0 * t.y;
                 }

@@ -527,8 +527,7 @@ xf_status refresh_table(xf_plan *P) {
 // pass), dw[key][j] = sum over its x of dw(x)/dtheta_j is stored as well and
 // keys are kept while any of weight or derivatives is non-zero.
 // Exact mode: the prefix tree of the term list over its flipped positions
-// (lemma_tree.h), for one CPhase layer or more than two under the general
-// lemma.  Tree positions are the (block, position) pairs some term flips, in
+// (lemma_tree.h), for one or more CPhase layers under the general lemma.  Tree positions are the (block, position) pairs some term flips, in
 // an order chosen to minimise the anchors; a pattern's anchor chain is the
 // prefixes of 4, 8, ... of its positions (in that order) that leave it 1 to 4
 // more; each anchor keeps the positions beyond its own that its descendants
@@ -537,7 +536,7 @@ xf_status refresh_table(xf_plan *P) {
 xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::vector<double> &w) {
     P->has_tree = false;
     const xf::GenPlan &g = P->gen;
-    if (g.nblk == 0 || !(P->L == 1 || g.multi) || keys.empty() || P->hkbt.size() < 128) return XF_OK;
+    if (g.nblk == 0 || P->L < 1 || keys.empty() || P->hkbt.size() < 128) return XF_OK;
     // the keys' flipped positions per block (a key bit flips one or two positions)
     std::vector<uint32_t> code_of(2 * 256, 0xFFFFFFFFu);
     std::vector<uint16_t> codes;

@@ -233,8 +233,8 @@ hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, c
 // then the LU kernel for the bitstrings it deferred; with all_lu, the LU
 // kernel for every bitstring).  launch_gen_exact: exact mode over [0, B) with
 // flags[B] marking deferred bitstrings, then the LU kernel for those (all of
-// them with all_lu); with a prefix tree (tree != nullptr, one or more than two
-// CPhase layers), its kernel takes the bitstrings whose bases need no shift
+// them with all_lu); with a prefix tree (tree != nullptr), its kernel takes
+// the bitstrings whose bases need no shift
 // before the pattern pass takes the rest.
 bool gen_applies(const DevPlan &p, const GenPlan &g);
 // gen_setup_bytes: bytes per bitstring of the setup workspace the launchers

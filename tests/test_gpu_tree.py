@@ -94,6 +94,36 @@ def test_tree_one_layer(X, case):
         plan.close()
 
 
+TWO_LAYER_CASES = [
+    # seed, n, eta, k, spin
+    (961, 12, 6, 10, False),   # one block, both layers' positions
+    (962, 16, 8, 12, True),    # two spin blocks
+]
+
+
+@pytest.mark.parametrize("case", TWO_LAYER_CASES, ids=[f"n{c[1]}_eta{c[2]}_k{c[3]}{'_spin' if c[4] else ''}"
+                                                        for c in TWO_LAYER_CASES])
+def test_tree_two_layers(X, case):
+    """Two CPhase layers: G = I + 2T - 2H with T = R'_1 from layer-0 to
+    layer-1 positions (the two-layer form of the per-pattern evaluation)."""
+    seed, n, eta, k, spin = case
+    inp = None
+    if spin:
+        inp = list(range(eta // 2)) + list(range(n // 2, n // 2 + eta - eta // 2))
+    w = W.random_circuit(seed, n, eta, k, n_rot=3, theta_scale=0.8, spin=spin, input_modes=inp, max_bits=4096)
+    if spin:
+        bits = W.spin_bitstrings(np.random.default_rng(seed), n // 2, eta // 2, eta - eta // 2, 1024)
+    else:
+        bits = _tile(w.bits[:1024])
+    idx = sample_indices(len(bits), 48, seed=seed)
+    say(f"prefix tree, two layers {case}: B={len(bits)}")
+    ref = oracle_probs(w, bits[idx], mode="exact")
+    for prec, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
+        plan = make_plan(w, X, prec)
+        _tree_vs_patterns(X, plan, bits, idx, ref, tol, f"{prec} two layers", expect_tree=0.5)
+        plan.close()
+
+
 def test_tree_many_layers(X):
     """Eight CPhase layers (keys are trajectories; positions are (layer,
     mode) pairs, at most 16): G = I + 2TT - 2K."""
