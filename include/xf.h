@@ -333,6 +333,13 @@ xf_status xf_plan_set_evaluation(xf_plan *plan, xf_evaluation evaluation);
  * 100; 0 gives FP64 results).  kappa_max >= 0, else XF_EINVAL. */
 xf_status xf_plan_set_mixed_condition(xf_plan *plan, double kappa_max);
 
+/* Exact mode along the prefix tree (see xf_plan_set_evaluation): the largest
+ * growth accepted, as max |entry| of the Schur complements over max |G| and
+ * as the largest |multiplier| of the 4 x 4 block eliminations (default 1e4;
+ * growth > 0, else XF_EINVAL).  A bitstring beyond it takes the per-pattern
+ * evaluation.  Takes effect at the next xf_probabilities call. */
+xf_status xf_plan_set_tree_growth(xf_plan *plan, double growth);
+
 /* Device memory the determinant-lemma path may use for its workspace
  * (default 16 GiB; bytes > 0).  Each bitstring's region holds
  * min(t + t/511 + 2, 8192) distinct patterns, 16 bytes each, plus 4 bytes; a

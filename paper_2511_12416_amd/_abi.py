@@ -50,6 +50,7 @@ EXPORTS = ["xf_plan_create", "xf_plan_set_params", "xf_plan_refreeze", "xf_plan_
            "xf_extent", "xf_trajectory_bound", "xf_probabilities", "xf_probabilities_noalloc", "xf_estimate",
            "xf_log_prob_backward",
            "xf_plan_last_term_count", "xf_plan_last_work", "xf_plan_set_evaluation", "xf_plan_set_workspace_limit", "xf_plan_set_mixed_condition",
+           "xf_plan_set_tree_growth",
            "xf_expm_antihermitian", "xf_expm_adjoint", "xf_spin_rotations", "xf_spin_rotations_adjoint",
            "xf_antihermitian_reals_grad", "xf_circuit_from_gates", "xf_sample_gates", "xf_last_error"]
 
@@ -87,6 +88,7 @@ def lib() -> ctypes.CDLL:
     L.xf_plan_set_evaluation.argtypes = [P, S]
     L.xf_plan_set_workspace_limit.argtypes = [P, U64]
     L.xf_plan_set_mixed_condition.argtypes = [P, D]
+    L.xf_plan_set_tree_growth.argtypes = [P, D]
     L.xf_expm_antihermitian.argtypes = [I32, P, P]
     L.xf_expm_adjoint.argtypes = [I32, P, P, P]
     L.xf_spin_rotations.argtypes = [I32, I32, P, P]

@@ -141,6 +141,11 @@ class Plan:
         matrix cores, others in FP64."""
         check(lib().xf_plan_set_mixed_condition(self._h, float(kappa_max)))
 
+    def set_tree_growth(self, growth: float) -> None:
+        """Exact mode along the prefix tree: the largest entry growth accepted
+        before a bitstring takes the per-pattern evaluation."""
+        check(lib().xf_plan_set_tree_growth(self._h, float(growth)))
+
     def set_workspace_limit(self, nbytes: int) -> None:
         """Device memory the determinant-lemma workspace may use (bitstrings
         are processed in chunks that fit, at least one at a time)."""

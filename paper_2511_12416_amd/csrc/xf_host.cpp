@@ -171,6 +171,7 @@ struct xf_plan {
     // their weights) stays the same
     std::vector<uint16_t> tree_codes;
     uint64_t tree_key = 0;
+    double tree_growth = 1e4;         // growth accepted along the tree
     int last_gen = 0;                 // the last xf_probabilities call used the general lemma kernel
     int64_t nxterms = -1;             // -1: not built for the current parameters
     xf_evaluation evaluation = XF_EVAL_AUTO;
@@ -826,7 +827,7 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
     t.doff = off + 4 * maxr;
     t.soff = t.doff + xf::kTreeLevels;
     t.lds = 16 * (t.soff + 17 * xf::kTreeStage);
-    t.growth2 = 1e8;
+    t.growth2 = P->tree_growth * P->tree_growth;
     if (t.lds > 64 * 1024) return XF_OK;
     // every index the kernel follows stays inside its matrix
     for (const xf::TreeAnchor &a : tanc) {
@@ -1717,6 +1718,14 @@ xf_status xf_plan_set_workspace_limit(xf_plan *P, uint64_t bytes) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
     if (bytes == 0) return fail(XF_EINVAL, "workspace limit must be positive");
     P->entry_budget = bytes;
+    return ok();
+}
+
+xf_status xf_plan_set_tree_growth(xf_plan *P, double growth) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    if (!(growth > 0.0)) return fail(XF_EINVAL, "growth must be > 0");
+    P->tree_growth = growth;
+    P->tree.growth2 = growth * growth;
     return ok();
 }
 

@@ -151,6 +151,29 @@ def test_tree_config3(X):
     plan.close()
 
 
+def test_tree_growth_limit_hands_bitstrings_to_the_pattern_pass(X):
+    """With a growth limit below any bitstring's growth, every bitstring is
+    left to the per-pattern pass: the results are bitwise those of the
+    per-pattern evaluation; restoring the limit takes the tree again."""
+    w = W.random_circuit(951, 14, 7, 10, n_rot=2, max_bits=4096)
+    bits = _tile(w.bits[:1024])
+    plan = make_plan(w, X)
+    plan.set_evaluation("patterns")
+    q = gpu_probs(plan, X, bits, "exact")
+    plan.set_evaluation("auto")
+    plan.set_tree_growth(1e-6)
+    p = gpu_probs(plan, X, bits, "exact")
+    assert plan.last_work()["tree_bitstrings"] == 0
+    assert np.array_equal(p, q)
+    plan.set_tree_growth(1e4)
+    p2 = gpu_probs(plan, X, bits, "exact")
+    assert plan.last_work()["tree_bitstrings"] == len(bits)
+    _check(p2, q, TOL_FP64, "tree vs per-pattern after restoring the limit")
+    with pytest.raises(X.XfError):
+        plan.set_tree_growth(0.0)
+    plan.close()
+
+
 def test_tree_off_beyond_32_positions(X):
     """17 disjoint gates flip 34 positions: no tree; every bitstring takes the
     pattern pass or, past 32 positions in a pattern, the LU kernel."""
