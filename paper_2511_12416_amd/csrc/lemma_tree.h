@@ -160,7 +160,13 @@ struct AncAt {
     uint32_t pat0, npat, roff;
     int level, nr, pnr;
     int j[4];
+    int flags;   // kTreeLeaf, kTreePairFirst
 };
+// An anchor without children: its patterns are staged straight from its
+// parent's matrix (no matrix of its own).  The first of two sibling leaves
+// that one step takes together, a half-wave each (the next record is the
+// other).
+constexpr int kTreeLeaf = 1, kTreePairFirst = 2;
 __device__ __forceinline__ void load_anchor_lanes(const DevTree &tr, int base, AncLanes &a) {
     // unconditional loads (clamped index), so that no branch holds back the
     // compiler's wait counts
@@ -184,17 +190,52 @@ __device__ __forceinline__ AncAt anchor_at(const AncLanes &a, int lane) {
     r.j[1] = (int)(w[4] & 0xFF);
     r.j[2] = (int)((w[4] >> 8) & 0xFF);
     r.j[3] = (int)((w[4] >> 16) & 0xFF);
+    r.flags = (int)(w[4] >> 24);
     return r;
+}
+
+// Record idx of the two chunks held in the lanes (cur: base .. base + 63,
+// nxt: the 64 after).
+__device__ __forceinline__ AncAt anchor_of(const AncLanes &cur, const AncLanes &nxt, int base, int idx) {
+    return idx < base + 64 ? anchor_at(cur, idx - base) : anchor_at(nxt, idx - base - 64);
+}
+
+// A step's global loads, issued one step ahead: the R index of this lane's
+// column (lanes 0..63 of one anchor, or 0..31 and 32..63 of a pair) and the
+// pattern of its staging slot (lane / 16 in the step's pattern list).
+// Unconditional loads on clamped indices (each array has one element of
+// padding).
+struct StepLoads {
+    int rr;
+    PatRegs pp;
+};
+__device__ __forceinline__ StepLoads step_loads(const DevTree &tr, const AncAt &a, const AncAt &b, bool two,
+                                                bool valid) {
+    const int lane = threadIdx.x;
+    const bool hb = two && lane >= 32;
+    const int l = two ? (lane & 31) : lane;
+    const uint32_t roff = hb ? b.roff : a.roff;
+    const int nr = hb ? b.nr : a.nr;
+    const uint32_t ri = valid ? roff + (uint32_t)min(l, max(nr - 1, 0)) : 0u;
+    const int q = lane >> 4, na = (int)a.npat, nb = (int)b.npat;
+    uint32_t pi = a.pat0 + (uint32_t)min(q, max(na - 1, 0));
+    if (two && q >= na) pi = b.pat0 + (uint32_t)min(q - na, max(nb - 1, 0));
+    StepLoads s;
+    s.rr = tr.ridx[ri];
+    s.pp = load_pat(tr, valid ? pi : 0u);
+    return s;
 }
 
 // One wave per bitstring (grid-stride).  Takes the bitstrings whose setup
 // succeeded with unshifted bases (flag 0, shift 0); on success writes p, A
 // and log p and sets the flag to kEntryTree, so that the pattern pass skips
 // them; otherwise leaves the flag for the pattern pass.  LDS: tr.lds bytes
-// (the levels' matrices, T, the prefix determinants and the staged
-// patterns).  The anchor records come 64 at a time into the lanes' registers
-// (the next 64 loaded while these are used); each anchor's R indices and
-// first four patterns are loaded one anchor ahead.  An anchor's patterns are
+// (the levels' matrices, two T buffers, the prefix determinants and the
+// staged patterns).  The anchor records come 64 at a time into the lanes'
+// registers (the next 64 loaded while these are used); each step's R indices
+// and first four patterns are loaded one step ahead.  A step is one anchor,
+// or two sibling leaves (a half-wave each), whose patterns' blocks are formed
+// from the parent's matrix without a matrix of their own.  An anchor's patterns are
 // copied, as identity-padded 4 x 4 blocks with their factors, into a stage
 // that is evaluated kTreeStage at a time (a lane each), so that the
 // determinants run on full waves although an anchor has few patterns.
@@ -205,7 +246,7 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
            double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
     static_assert(sizeof(TreeAnchor) == 20, "anchor records are five words");
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int sR[kTreeMaxM];
+    __shared__ int sR[2][kTreeMaxM];
     double2 *S = (double2 *)smem;
     double2 *Tb = S + tr.toff;
     double2 *Dl = S + tr.doff;
@@ -264,92 +305,170 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
         }
         // (the R index and pattern loads are unconditional, on clamped
         // indices: both arrays hold at least one element)
-        AncAt A = anchor_at(cur, 0);
-        int rr = tr.ridx[A.roff + min(lane, max(A.nr - 1, 0))];
-        PatRegs pp = load_pat(tr, A.pat0 + (uint32_t)min(lane >> 4, max((int)A.npat - 1, 0)));
-        for (int an = 0; an < tr.nanc; ++an) {
-            // the next anchor's record, R indices and first patterns
-            const int n1 = an + 1;
-            if ((n1 & 63) == 0) {
+        int base = 0;
+        AncAt A0 = anchor_of(cur, nxt, base, 0);
+        AncAt A1 = anchor_of(cur, nxt, base, tr.nanc > 1 ? 1 : 0);
+        bool two = tr.nanc > 1 && (A0.flags & kTreePairFirst);
+        StepLoads ld = step_loads(tr, A0, A1, two, tr.nanc > 0);
+        for (int st = 0; st < tr.nanc;) {
+            // the next step's records (the chunks move on when it starts past
+            // the first; st < base + 64 holds at every step) and loads
+            const int ns = st + (two ? 2 : 1);
+            if (ns >= base + 64) {
                 cur = nxt;
-                load_anchor_lanes(tr, n1 + 64, nxt);
+                base += 64;
+                load_anchor_lanes(tr, base + 64, nxt);
             }
-            const bool more = n1 < tr.nanc;
-            const AncAt B = anchor_at(cur, n1 & 63);
-            const int rrB = tr.ridx[more ? B.roff + min(lane, max(B.nr - 1, 0)) : 0];
-            const PatRegs ppB = load_pat(tr, more ? B.pat0 + (uint32_t)min(lane >> 4, max((int)B.npat - 1, 0)) : 0u);
+            const bool more = ns < tr.nanc;
+            const AncAt B0 = anchor_of(cur, nxt, base, more ? ns : base);
+            const AncAt B1 = anchor_of(cur, nxt, base, ns + 1 < tr.nanc ? ns + 1 : (more ? ns : base));
+            const bool twoB = ns + 1 < tr.nanc && (B0.flags & kTreePairFirst);
+            const StepLoads ldB = step_loads(tr, B0, B1, twoB, more);
 
-            const int lv = A.level, nr = A.nr, pnr = A.pnr;
+            const int lv = A0.level, pnr = A0.pnr;
             const double2 *P = S + tr.slot[lv - 1];
-            double2 *Q = S + tr.slot[lv];
-            // T = P[J, J]^-1 P[J, R] (a column per lane; every lane factorises
-            // the same block) and the prefix determinant
-            if (lane < max(nr, 1)) {
-                double2 m4[4][4], x[4];
+            if (A0.flags & kTreeLeaf) {
+                // one leaf, or two sibling leaves (a half-wave each): T for
+                // each, then its patterns' blocks of P[R, R] - P[R, J] T
+                // staged directly
+                const int hb = (two && lane >= 32) ? 1 : 0;
+                const int l = two ? (lane & 31) : lane;
+                const int nr = hb ? A1.nr : A0.nr;
+                int J[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 4; ++u) J[u] = hb ? A1.j[u] : A0.j[u];
+                if ((hb == 0 || two) && l < max(nr, 1)) {
+                    double2 m4[4][4], x[4];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) m4[u][v] = P[A.j[u] * pnr + A.j[v]];
+                    for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int u = 0; u < 4; ++u) x[u] = lane < nr ? P[A.j[u] * pnr + rr] : make_double2(0.0, 0.0);
-                const double2 dJ = solve4(m4, x, gl);
-                bad |= dJ.x == 0.0 && dJ.y == 0.0;
-                if (lane < nr) {
-                    sR[lane] = rr;
+                        for (int v = 0; v < 4; ++v) m4[u][v] = P[J[u] * pnr + J[v]];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) Tb[u * tr.maxr + lane] = x[u];
-                }
-                if (lane == 0) Dl[lv] = c_mul(Dl[lv - 1], dJ);
-            }
-            wave_sync();
-            // Q = P[R, R] - P[R, J] T; e / nr by a multiply (exact for
-            // e < nr^2 <= 1024, nr <= 32)
-            const uint32_t mg = ((1u << 20) + (uint32_t)nr - 1) / (uint32_t)max(nr, 1);
-            for (int e = lane; e < nr * nr; e += 64) {
-                const int ii = (int)(((uint32_t)e * mg) >> 20), jj = e - ii * nr;
-                const int ri = sR[ii], rj = sR[jj];
-                double2 s = P[ri * pnr + rj];
+                    for (int u = 0; u < 4; ++u) x[u] = l < nr ? P[J[u] * pnr + ld.rr] : make_double2(0.0, 0.0);
+                    const double2 dJ = solve4(m4, x, gl);
+                    bad |= dJ.x == 0.0 && dJ.y == 0.0;
+                    if (l < nr) {
+                        sR[hb][l] = ld.rr;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const double2 c = P[ri * pnr + A.j[u]];
-                    s = c_fma(s, make_double2(-c.x, -c.y), Tb[u * tr.maxr + jj]);
-                }
-                Q[e] = s;
-                grow = fmax(grow, cabs2(s));
-            }
-            wave_sync();
-            // stage the anchor's patterns, four per pass (16 lanes each: one
-            // entry of the 4 x 4 block, identity past r) with their factors
-            // w det M_B dpre; evaluate the stage when it is full
-            const double2 dpre = Dl[lv];
-            for (int q0 = 0; q0 < (int)A.npat; q0 += 4) {
-                const int cnt = min(4, (int)A.npat - q0);
-                if (nst + cnt > kTreeStage) {
-                    wave_sync();
-                    tree_flush(St, Fs, nst, acc);
-                    nst = 0;
-                }
-                const int ql = lane >> 4, e = lane & 15, u = e >> 2, v = e & 3;
-                if (ql < cnt) {
-                    const PatRegs t = q0 == 0 ? pp : load_pat(tr, A.pat0 + q0 + ql);
-                    const int r = (int)(t.m0 & 0xFF);
-                    const uint64_t mm = (uint64_t)t.m0 | ((uint64_t)t.m1 << 32);
-                    const int iu = (int)((mm >> (8 * (u + 1))) & 0xFF), iv = (int)((mm >> (8 * (v + 1))) & 0xFF);
-                    St[(nst + ql) * 16 + e] =
-                        (u < r && v < r) ? Q[iu * nr + iv] : make_double2(u == v ? 1.0 : 0.0, 0.0);
-                    if (e == 0) {
-                        Fs[nst + ql] = c_mul(t.w, c_mul(detB, dpre));
-                        rank += 4 * lv + r;
-                        flops += lu_flops(r) + 18;
+                        for (int u = 0; u < 4; ++u) Tb[(hb * 4 + u) * tr.maxr + l] = x[u];
                     }
+                    if (l == 0) Dl[kTreeLevels + hb] = c_mul(Dl[lv - 1], dJ);
                 }
-                nst += cnt;
+                wave_sync();
+                const int na = (int)A0.npat, total = na + (two ? (int)A1.npat : 0);
+                for (int q0 = 0; q0 < total; q0 += 4) {
+                    const int cnt = min(4, total - q0);
+                    if (nst + cnt > kTreeStage) {
+                        wave_sync();
+                        tree_flush(St, Fs, nst, acc);
+                        nst = 0;
+                    }
+                    const int ql = lane >> 4, e = lane & 15, u = e >> 2, v = e & 3;
+                    if (ql < cnt) {
+                        const int q = q0 + ql;
+                        const int qb = q >= na ? 1 : 0;
+                        const PatRegs t =
+                            q0 == 0 ? ld.pp : load_pat(tr, qb ? A1.pat0 + (uint32_t)(q - na) : A0.pat0 + (uint32_t)q);
+                        const int r = (int)(t.m0 & 0xFF);
+                        const uint64_t mm = (uint64_t)t.m0 | ((uint64_t)t.m1 << 32);
+                        const int iu = (int)((mm >> (8 * (u + 1))) & 0xFF), iv = (int)((mm >> (8 * (v + 1))) & 0xFF);
+                        double2 val = make_double2(u == v ? 1.0 : 0.0, 0.0);
+                        if (u < r && v < r) {
+                            const int ri = sR[qb][iu], rj = sR[qb][iv];
+                            val = P[ri * pnr + rj];
+#pragma unroll
+                            for (int w = 0; w < 4; ++w) {
+                                const double2 c = P[ri * pnr + (qb ? A1.j[w] : A0.j[w])];
+                                val = c_fma(val, make_double2(-c.x, -c.y), Tb[(qb * 4 + w) * tr.maxr + iv]);
+                            }
+                            grow = fmax(grow, cabs2(val));
+                        }
+                        St[(nst + ql) * 16 + e] = val;
+                        if (e == 0) {
+                            Fs[nst + ql] = c_mul(t.w, c_mul(detB, Dl[kTreeLevels + qb]));
+                            rank += 4 * lv + r;
+                            flops += lu_flops(r) + 18 + 32ull * r * r;
+                        }
+                    }
+                    nst += cnt;
+                }
+                if (lane == 0)
+                    flops += lu_flops(4) + 128ull * A0.nr + 6 + (two ? lu_flops(4) + 128ull * A1.nr + 6 : 0ull);
+            } else {
+                const int nr = A0.nr;
+                double2 *Q = S + tr.slot[lv];
+                // T = P[J, J]^-1 P[J, R] (a column per lane; every lane
+                // factorises the same block) and the prefix determinant
+                if (lane < max(nr, 1)) {
+                    double2 m4[4][4], x[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) m4[u][v] = P[A0.j[u] * pnr + A0.j[v]];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        x[u] = lane < nr ? P[A0.j[u] * pnr + ld.rr] : make_double2(0.0, 0.0);
+                    const double2 dJ = solve4(m4, x, gl);
+                    bad |= dJ.x == 0.0 && dJ.y == 0.0;
+                    if (lane < nr) {
+                        sR[0][lane] = ld.rr;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) Tb[u * tr.maxr + lane] = x[u];
+                    }
+                    if (lane == 0) Dl[lv] = c_mul(Dl[lv - 1], dJ);
+                }
+                wave_sync();
+                // Q = P[R, R] - P[R, J] T; e / nr by a multiply (exact for
+                // e < nr^2 <= 1024, nr <= 32)
+                const uint32_t mg = ((1u << 20) + (uint32_t)nr - 1) / (uint32_t)max(nr, 1);
+                for (int e = lane; e < nr * nr; e += 64) {
+                    const int ii = (int)(((uint32_t)e * mg) >> 20), jj = e - ii * nr;
+                    const int ri = sR[0][ii], rj = sR[0][jj];
+                    double2 sv = P[ri * pnr + rj];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double2 c = P[ri * pnr + A0.j[u]];
+                        sv = c_fma(sv, make_double2(-c.x, -c.y), Tb[u * tr.maxr + jj]);
+                    }
+                    Q[e] = sv;
+                    grow = fmax(grow, cabs2(sv));
+                }
+                wave_sync();
+                // stage the anchor's patterns, four per pass (16 lanes each:
+                // one entry of the 4 x 4 block, identity past r) with their
+                // factors w det M_B dpre; evaluate the stage when it is full
+                const double2 dpre = Dl[lv];
+                for (int q0 = 0; q0 < (int)A0.npat; q0 += 4) {
+                    const int cnt = min(4, (int)A0.npat - q0);
+                    if (nst + cnt > kTreeStage) {
+                        wave_sync();
+                        tree_flush(St, Fs, nst, acc);
+                        nst = 0;
+                    }
+                    const int ql = lane >> 4, e = lane & 15, u = e >> 2, v = e & 3;
+                    if (ql < cnt) {
+                        const PatRegs t = q0 == 0 ? ld.pp : load_pat(tr, A0.pat0 + q0 + ql);
+                        const int r = (int)(t.m0 & 0xFF);
+                        const uint64_t mm = (uint64_t)t.m0 | ((uint64_t)t.m1 << 32);
+                        const int iu = (int)((mm >> (8 * (u + 1))) & 0xFF), iv = (int)((mm >> (8 * (v + 1))) & 0xFF);
+                        St[(nst + ql) * 16 + e] =
+                            (u < r && v < r) ? Q[iu * nr + iv] : make_double2(u == v ? 1.0 : 0.0, 0.0);
+                        if (e == 0) {
+                            Fs[nst + ql] = c_mul(t.w, c_mul(detB, dpre));
+                            rank += 4 * lv + r;
+                            flops += lu_flops(r) + 18;
+                        }
+                    }
+                    nst += cnt;
+                }
+                if (lane == 0) flops += lu_flops(4) + 128ull * nr + 32ull * nr * nr + 6;
             }
-            if (lane == 0) flops += lu_flops(4) + 128ull * nr + 32ull * nr * nr + 6;
             wave_sync();
-            A = B;
-            rr = rrB;
-            pp = ppB;
+            A0 = B0;
+            A1 = B1;
+            two = twoB;
+            ld = ldB;
+            st = ns;
         }
         wave_sync();
         tree_flush(St, Fs, nst, acc);

@@ -711,6 +711,7 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
         int j[4] = {0, 0, 0, 0};
         uint32_t need = 0;   // positions beyond its own that its descendants use
         std::vector<int> kids, pats;
+        bool pair_first = false;   // a leaf taken together with the next sibling leaf
     };
     std::vector<Anc> an(1);
     std::vector<std::pair<uint32_t, int>> ids;   // prefix mask -> anchor, sorted on insertion
@@ -783,7 +784,15 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
     };
     emit_pats(0, rlist(0));
     const int nroot = (int)tpat.size();
-    // depth-first over the anchors (iterative; children in creation order)
+    // leaves (anchors without children) first among their siblings, in
+    // pairs where two follow each other
+    for (Anc &a : an) {
+        std::stable_partition(a.kids.begin(), a.kids.end(), [&](int c) { return an[c].kids.empty(); });
+        size_t nl = 0;
+        while (nl < a.kids.size() && an[a.kids[nl]].kids.empty()) ++nl;
+        for (size_t k = 0; k + 1 < nl; k += 2) an[a.kids[k]].pair_first = true;
+    }
+    // depth-first over the anchors (iterative; children in that order)
     std::vector<std::pair<int, size_t>> stack;
     stack.emplace_back(0, 0);
     while (!stack.empty()) {
@@ -806,8 +815,11 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
         ta.pat0 = (uint32_t)tpat.size();
         emit_pats(c, RC);
         ta.npat = (uint32_t)(tpat.size() - ta.pat0);
+        const bool leaf = an[c].kids.empty();
+        ta.pad = (uint8_t)((leaf ? 1 : 0) | (an[c].pair_first ? 2 : 0));
         tanc.push_back(ta);
-        maxnr[ta.level] = std::max(maxnr[ta.level], (int)ta.nr);
+        // a leaf keeps no matrix of its own: the levels' slots hold the others
+        if (!leaf) maxnr[ta.level] = std::max(maxnr[ta.level], (int)ta.nr);
         maxr = std::max(maxr, (int)ta.nr);
         stack.emplace_back(c, 0);
     }
@@ -824,14 +836,16 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
     }
     t.maxr = maxr;
     t.toff = off;
-    t.doff = off + 4 * maxr;
-    t.soff = t.doff + xf::kTreeLevels;
+    t.doff = off + 8 * maxr;                  // two T buffers (a pair of leaves)
+    t.soff = t.doff + xf::kTreeLevels + 2;    // the levels' prefix dets, then the pair's
     t.lds = 16 * (t.soff + 17 * xf::kTreeStage);
     t.growth2 = P->tree_growth * P->tree_growth;
     if (t.lds > 64 * 1024) return XF_OK;
     // every index the kernel follows stays inside its matrix
     for (const xf::TreeAnchor &a : tanc) {
-        if (a.level < 1 || a.level >= xf::kTreeLevels || a.pnr > maxnr[a.level - 1] || a.nr > maxnr[a.level])
+        if (a.level < 1 || a.level >= xf::kTreeLevels || a.pnr > maxnr[a.level - 1] || a.nr > maxr ||
+            (!(a.pad & 1) && a.nr > maxnr[a.level]) || ((a.pad & 2) && (&a == &tanc.back() || !((&a)[1].pad & 1) ||
+                                                                        (&a)[1].level != a.level || (&a)[1].pnr != a.pnr)))
             return fail(XF_EDEVICE, "internal error: prefix tree anchor size");
         for (int u = 0; u < 4; ++u)
             if (a.j[u] >= a.pnr) return fail(XF_EDEVICE, "internal error: prefix tree anchor index");
