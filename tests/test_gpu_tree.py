@@ -174,6 +174,34 @@ def test_tree_growth_limit_hands_bitstrings_to_the_pattern_pass(X):
     plan.close()
 
 
+def test_tree_at_32_positions(X):
+    """16 disjoint gates flip 32 positions (the largest tree: seven anchor
+    levels, the largest LDS layout), 65536 terms: the tree against the
+    oracle."""
+    n, eta, k = 34, 6, 16
+    rng = W.rng_for(956)
+    u = W.haar_unitary(rng, n)
+    v = W.haar_unitary(rng, n)
+    pairs = np.array([(2 * j, 2 * j + 1) for j in range(k)], dtype=np.int32)
+    theta = rng.uniform(-0.6, 0.6, k)
+    modes = W.random_fixed_weight(rng, np.arange(n), eta, 1024)
+    bits = np.array([W.bits_from_modes(s) for s in modes], dtype=np.uint64)
+    w = W.Workload("disjoint gates n=34 eta=6 k=16", n, W.bits_from_modes(range(eta)), np.stack([u, v]), pairs,
+                   np.zeros(k, np.int32), theta, bits, "exact")
+    idx = sample_indices(len(bits), 4, seed=956)
+    say("32 flipped positions: B=1024, 2^16 terms")
+    ref = oracle_probs(w, bits[idx], mode="exact")
+    plan = make_plan(w, X)
+    p = gpu_probs(plan, X, bits, "exact")
+    wk = plan.last_work()
+    say(f"  {wk['tree_bitstrings']} of {len(bits)} along the tree, eval {wk['eval_ms']:.2f} ms")
+    assert wk["tree_bitstrings"] >= 0.9 * len(bits), wk
+    _check(p[idx], ref, TOL_FP64, "fp64 tree at 32 positions")
+    p2 = gpu_probs(plan, X, bits, "exact")
+    assert np.array_equal(p, p2)
+    plan.close()
+
+
 def test_tree_off_beyond_32_positions(X):
     """17 disjoint gates flip 34 positions: no tree; every bitstring takes the
     pattern pass or, past 32 positions in a pattern, the LU kernel."""
