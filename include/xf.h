@@ -314,10 +314,11 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
  * every four positions, each a Schur complement of its parent's), and one
  * wave per bitstring walks it: each term then costs a determinant of at most
  * 4 x 4 (all principal minors by the recursion of Griffin and Tsatsomeros,
- * Linear Algebra Appl. 419 (2006)).  Bitstrings with a shifted base, an
- * exactly singular pivot block, or entries grown beyond 10^4 times G's
- * largest, and batches small enough to split the term list into segments,
- * take the per-pattern evaluation instead.
+ * Linear Algebra Appl. 419 (2006)); batches of fewer than 1024 bitstrings
+ * split each walk into parts (whole subtrees) on separate waves.
+ * Bitstrings with a shifted base, an exactly singular pivot block, or
+ * entries grown beyond 10^4 times G's largest, and batches of fewer than 128
+ * bitstrings, take the per-pattern evaluation instead.
  *   XF_EVAL_PATTERNS: XF_EVAL_AUTO without the prefix tree (every pattern's
  *     r x r determinant on its own). */
 typedef enum { XF_EVAL_AUTO = 0, XF_EVAL_LU = 1, XF_EVAL_PATTERNS = 2 } xf_evaluation;

@@ -13,9 +13,9 @@ hipError_t launch_gen_eval_exact(const DevPlan &p, const GenPlan &g, bool multi,
                                  const uint64_t *xkeys, const double2 *xw, int64_t nkeys, uint32_t *flags,
                                  const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
                                  unsigned long long *nterm, int nseg, uint64_t *part, int grid_cap, hipStream_t s);
-hipError_t launch_gen_tree(const DevPlan &p, const GenPlan &g, const DevTree &tr, int64_t nb, uint32_t *flags,
-                           const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
-                           unsigned long long *nterm, hipStream_t s);
+hipError_t launch_gen_tree(const DevPlan &p, const GenPlan &g, const DevTree &tr, int64_t nb, int parts,
+                           uint32_t *flags, const double2 *hbuf, GenRec *rec, double *prob, double *amp, double *logp,
+                           unsigned long long *nterm, uint64_t *part, hipStream_t s);
 hipError_t prepare_gen_eval_raw();
 hipError_t prepare_gen_eval_exact();
 hipError_t prepare_gen_tree();
@@ -139,15 +139,22 @@ hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool
     GenRec *rec = (GenRec *)(hbuf + (size_t)B * g.hsize);
     // few bitstrings: each term list split over segments so that about 4096
     // workgroups take part; their partial sums follow the records
+    // the tree: one item per bitstring for large batches; for smaller ones
+    // each bitstring's walk split into as many parts as its term list has
+    // segments (at most the plan's), whose partial sums are added after.
+    // Below 128 bitstrings the segmented pattern pass is as fast or faster
+    // (the parts are whole subtrees of the root's children, too coarse to
+    // spread a few bitstrings over the chip).
     int nseg = gen_exact_segments(B, nkeys);
-    const bool use_tree = tree && nseg <= 1 && !all_lu;
-    if (use_tree) nseg = gen_tree_left_segments(nkeys);
+    const bool use_tree = tree && !all_lu && B >= 128;
+    const int tparts = !use_tree ? 0 : (nseg > 1 ? (nseg < tree->nparts ? nseg : tree->nparts) : 1);
+    if (use_tree && nseg <= 1) nseg = gen_tree_left_segments(nkeys);
     uint64_t *part = (uint64_t *)(rec + B);
     if (all_lu) {
         if ((e = launch_fill_u32(flags, B, kEntryDeferred, s)) != hipSuccess) return e;
     } else {
         launch_gen_setup_t<true>(p, g, mixed, bits, 0, B, flags, hbuf, rec, prob, amp, logp, nterm, s);
-        if (use_tree) launch_gen_tree(p, g, *tree, B, flags, hbuf, rec, prob, amp, logp, nterm, s);
+        if (use_tree) launch_gen_tree(p, g, *tree, B, tparts, flags, hbuf, rec, prob, amp, logp, nterm, part, s);
         launch_gen_eval_exact(p, g, g.multi, gen_wide(g), B, keys, w, nkeys, flags, hbuf, rec, prob, amp, logp, nterm,
                               nseg, part, use_tree ? 2048 : 0, s);
     }

@@ -241,9 +241,10 @@ __device__ __forceinline__ StepLoads step_loads(const DevTree &tr, const AncAt &
 // determinants run on full waves although an anchor has few patterns.
 template <bool MULTI>
 __global__ void __launch_bounds__(64)
-k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ flags,
+k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, int parts, uint32_t *__restrict__ flags,
            const double2 *__restrict__ hbuf, const GenRec *__restrict__ rec, double *__restrict__ prob,
-           double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm) {
+           double *__restrict__ amp, double *__restrict__ logp, unsigned long long *nterm,
+           uint64_t *__restrict__ part) {
     static_assert(sizeof(TreeAnchor) == 20, "anchor records are five words");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sR[2][kTreeMaxM];
@@ -256,15 +257,19 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
     const int M = tr.M;
     Work wk;
     unsigned long long done = 0;
-    for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+    for (int64_t item = blockIdx.x; item < nb * (int64_t)parts; item += gridDim.x) {
+        const int64_t i = item / parts;
+        const int pi = (int)(item - i * parts);
         if (flags[i] != 0) continue;
         const uint64_t sh0 = rec[i].shift[0], sh1 = rec[i].shift[1];
         if (sh0 | sh1) continue;
         const double2 detB = rec[i].det;
         const double2 *Hg = hbuf + (size_t)i * g.hsize;
+        // this item's anchors: whole subtrees of the root's children
+        const int lo = (int)tr.pstart[(pi * tr.nparts) / parts], hi = (int)tr.pstart[((pi + 1) * tr.nparts) / parts];
         AncLanes cur, nxt;
-        load_anchor_lanes(tr, 0, cur);
-        load_anchor_lanes(tr, 64, nxt);
+        load_anchor_lanes(tr, lo, cur);
+        load_anchor_lanes(tr, lo + 64, nxt);
         // G on the tree's positions (zero across blocks)
         double gmax = 0.0;
         for (int e = lane; e < M * M; e += 64) {
@@ -298,19 +303,19 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
         bool bad = false;
         unsigned long long rank = 0, flops = 0;
         int nst = 0;   // patterns staged
-        for (int q = lane; q < tr.nroot; q += 64) {
+        for (int q = lane; q < (pi == 0 ? tr.nroot : 0); q += 64) {
             const int r = tree_pattern(load_pat(tr, q), S, M, Dl[0], detB, acc);
             rank += r;
             flops += lu_flops(r) + 18;
         }
         // (the R index and pattern loads are unconditional, on clamped
         // indices: both arrays hold at least one element)
-        int base = 0;
-        AncAt A0 = anchor_of(cur, nxt, base, 0);
-        AncAt A1 = anchor_of(cur, nxt, base, tr.nanc > 1 ? 1 : 0);
-        bool two = tr.nanc > 1 && (A0.flags & kTreePairFirst);
-        StepLoads ld = step_loads(tr, A0, A1, two, tr.nanc > 0);
-        for (int st = 0; st < tr.nanc;) {
+        int base = lo;
+        AncAt A0 = anchor_of(cur, nxt, base, lo);
+        AncAt A1 = anchor_of(cur, nxt, base, hi - lo > 1 ? lo + 1 : lo);
+        bool two = hi - lo > 1 && (A0.flags & kTreePairFirst);
+        StepLoads ld = step_loads(tr, A0, A1, two, hi > lo);
+        for (int st = lo; st < hi;) {
             // the next step's records (the chunks move on when it starts past
             // the first; st < base + 64 holds at every step) and loads
             const int ns = st + (two ? 2 : 1);
@@ -319,10 +324,10 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
                 base += 64;
                 load_anchor_lanes(tr, base + 64, nxt);
             }
-            const bool more = ns < tr.nanc;
+            const bool more = ns < hi;
             const AncAt B0 = anchor_of(cur, nxt, base, more ? ns : base);
-            const AncAt B1 = anchor_of(cur, nxt, base, ns + 1 < tr.nanc ? ns + 1 : (more ? ns : base));
-            const bool twoB = ns + 1 < tr.nanc && (B0.flags & kTreePairFirst);
+            const AncAt B1 = anchor_of(cur, nxt, base, ns + 1 < hi ? ns + 1 : (more ? ns : base));
+            const bool twoB = ns + 1 < hi && (B0.flags & kTreePairFirst);
             const StepLoads ldB = step_loads(tr, B0, B1, twoB, more);
 
             const int lv = A0.level, pnr = A0.pnr;
@@ -474,23 +479,61 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, uint32_t *__restrict__ 
         tree_flush(St, Fs, nst, acc);
         const double gm = wave_max(gmax), gr = wave_max(grow), ml = wave_max(gl);
         const bool fail = __ballot(bad) != 0 || !(gr <= tr.growth2 * gm) || !(ml <= tr.growth2);
-        if (fail) continue;   // the pattern pass takes it
+        if (fail && parts == 1) continue;   // the pattern pass takes it
         fix_wave_sum(acc.re);
         fix_wave_sum(acc.im);
         const bool accbad = __ballot(acc.bad) != 0;
-        wk.rank += rank;
-        wk.flops += flops;
+        if (!fail) {
+            wk.rank += rank;
+            wk.flops += flops;
+        }
         if (lane == 0) {
             const uint64_t words[kAccWords] = {acc.re.w0, acc.re.w1, (uint64_t)acc.re.w2, acc.im.w0,
-                                               acc.im.w1, (uint64_t)acc.im.w2, accbad ? 1ull : 0ull};
-            write_result(i, acc_value(words), 1.0, prob, amp, logp);
-            flags[i] = kEntryTree;
-            wk.terms += (unsigned)tr.npat;
-            ++done;
+                                               acc.im.w1, (uint64_t)acc.im.w2,
+                                               (accbad ? 1ull : 0ull) | (fail ? 2ull : 0ull)};
+            if (parts == 1) {
+                write_result(i, acc_value(words), 1.0, prob, amp, logp);
+                flags[i] = kEntryTree;
+                wk.terms += (unsigned)tr.npat;
+                ++done;
+            } else {
+                // a part's exact partial sum; bit 1 of the last word: this
+                // part's growth or pivots fail (k_gen_tree_reduce)
+#pragma unroll
+                for (int w = 0; w < kAccWords; ++w) part[(size_t)item * 8 + w] = words[w];
+            }
         }
     }
     flush_work(wk, nterm);
     if (nterm && lane == 0 && done) atomicAdd(nterm + 7, done);
+}
+
+// The sum of the parts of each bitstring the tree kernel took in `parts`
+// parts (in part order; the words are exact integers), one thread per
+// bitstring: p, A and log p written and the flag set to kEntryTree, unless
+// a part failed (then the pattern pass takes the bitstring).
+__global__ void k_gen_tree_reduce(int64_t nb, int parts, int npat, uint32_t *__restrict__ flags,
+                                  const GenRec *__restrict__ rec, const uint64_t *__restrict__ part,
+                                  double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
+                                  unsigned long long *nterm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb || flags[i] != 0 || (rec[i].shift[0] | rec[i].shift[1])) return;
+    Fix192 R, I;
+    uint64_t bad = 0;
+    for (int j = 0; j < parts; ++j) {
+        const uint64_t *q = part + ((size_t)i * parts + j) * 8;
+        fix_add(R, q[0], q[1], (int64_t)q[2]);
+        fix_add(I, q[3], q[4], (int64_t)q[5]);
+        bad |= q[6];
+    }
+    if (bad & 2) return;
+    const uint64_t acc[kAccWords] = {R.w0, R.w1, (uint64_t)R.w2, I.w0, I.w1, (uint64_t)I.w2, bad & 1};
+    write_result(i, acc_value(acc), 1.0, prob, amp, logp);
+    flags[i] = kEntryTree;
+    if (nterm) {
+        atomicAdd(nterm, (unsigned long long)npat);
+        atomicAdd(nterm + 7, 1ull);
+    }
 }
 
 }  // namespace

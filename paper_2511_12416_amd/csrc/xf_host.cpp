@@ -164,7 +164,7 @@ struct xf_plan {
     DevBuf dgsetup;                   // general lemma: per-bitstring H and base records
     std::vector<uint16_t> hkbt;       // host copy of the key-bit table of the general lemma
     // exact mode: the term list's prefix tree (lemma_tree.h), built with it
-    DevBuf dtanc, dtridx, dtpat, dtrpos;
+    DevBuf dtanc, dtridx, dtpat, dtrpos, dtpart;
     xf::DevTree tree{};
     bool has_tree = false;
     // the tree's position order, kept while the set of flip patterns (not
@@ -823,8 +823,33 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
         maxr = std::max(maxr, (int)ta.nr);
         stack.emplace_back(c, 0);
     }
+    // parts of the walk for small batches: up to 256 runs of whole subtrees
+    // of the root's children (never between the two leaves of a pair), cut
+    // where the estimated work (per anchor a block elimination, its matrix
+    // and its patterns' passes) reaches equal shares
+    std::vector<uint32_t> pstart(1, 0);
+    {
+        std::vector<double> pre(tanc.size() + 1, 0.0);
+        for (size_t x = 0; x < tanc.size(); ++x) {
+            const double nr = tanc[x].nr;
+            pre[x + 1] = pre[x] + 4.0 + std::ceil(nr * nr / 64.0) + std::ceil(tanc[x].npat / 4.0);
+        }
+        std::vector<size_t> cuts;
+        for (size_t x = 1; x < tanc.size(); ++x)
+            if (tanc[x].level == 1 && !(tanc[x - 1].pad & 2)) cuts.push_back(x);
+        const int want = (int)std::min<size_t>(256, cuts.size() + 1);
+        size_t c = 0;
+        for (int kq = 1; kq < want; ++kq) {
+            const double target = pre.back() * kq / want;
+            while (c < cuts.size() && (pre[cuts[c]] < target || cuts[c] <= pstart.back())) ++c;
+            if (c >= cuts.size()) break;
+            pstart.push_back((uint32_t)cuts[c]);
+        }
+        pstart.push_back((uint32_t)tanc.size());
+    }
     xf::DevTree &t = P->tree;
     t = xf::DevTree{};
+    t.nparts = (int)pstart.size() - 1;
     t.nanc = (int)tanc.size();
     t.nroot = nroot;
     t.npat = (int)tpat.size();
@@ -869,12 +894,14 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
     if ((st = dev_upload(P->dtanc, tanc.data(), tanc.size() * sizeof(xf::TreeAnchor))) ||
         (st = dev_upload(P->dtridx, tridx.data(), tridx.size())) ||
         (st = dev_upload(P->dtpat, tpat.data(), tpat.size() * sizeof(xf::TreePat))) ||
-        (st = dev_upload(P->dtrpos, codes.data(), codes.size() * sizeof(uint16_t))))
+        (st = dev_upload(P->dtrpos, codes.data(), codes.size() * sizeof(uint16_t))) ||
+        (st = dev_upload(P->dtpart, pstart.data(), pstart.size() * sizeof(uint32_t))))
         return st;
     t.anc = (const xf::TreeAnchor *)P->dtanc.p;
     t.ridx = (const uint8_t *)P->dtridx.p;
     t.pat = (const xf::TreePat *)P->dtpat.p;
     t.rpos = (const uint16_t *)P->dtrpos.p;
+    t.pstart = (const uint32_t *)P->dtpart.p;
     P->has_tree = true;
     return XF_OK;
 }
@@ -980,7 +1007,7 @@ void plan_free(xf_plan *P) {
                       &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
                       &P->dgsum, &P->dekey, &P->decnt, &P->decount, &P->dgcol, &P->dgact, &P->dgpos0,
                       &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dggpos, &P->dflags, &P->dgGA, &P->dgHC, &P->dgTT, &P->dgsetup,
-                      &P->dtanc, &P->dtridx, &P->dtpat, &P->dtrpos})
+                      &P->dtanc, &P->dtridx, &P->dtpat, &P->dtrpos, &P->dtpart})
         dev_free(*b);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();

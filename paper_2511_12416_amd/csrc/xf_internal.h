@@ -114,7 +114,8 @@ struct DevTree {
     const uint8_t *ridx;
     const TreePat *pat;
     const uint16_t *rpos;  // [M]: (block << 8 | position) of each tree position
-    int nanc, nroot, npat, M;
+    const uint32_t *pstart;  // [nparts + 1]: first anchor of each part (whole subtrees of the root's children)
+    int nanc, nroot, npat, M, nparts;
     int slot[kTreeLevels];  // LDS offset (complex entries) of each level's matrix; slot[0]: M x M
     int toff, doff, maxr;   // LDS offsets of T (4 x maxr) and of the levels' prefix determinants
     int soff;               // LDS offset of the staged patterns (kTreeStage 4 x 4 blocks, then their factors)
@@ -234,7 +235,8 @@ hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, c
 // kernel for every bitstring).  launch_gen_exact: exact mode over [0, B) with
 // flags[B] marking deferred bitstrings, then the LU kernel for those (all of
 // them with all_lu); with a prefix tree (tree != nullptr), its kernel takes
-// the bitstrings whose bases need no shift
+// (split into parts for small batches) the bitstrings whose bases need no
+// shift
 // before the pattern pass takes the rest.
 bool gen_applies(const DevPlan &p, const GenPlan &g);
 // gen_setup_bytes: bytes per bitstring of the setup workspace the launchers

@@ -4,7 +4,8 @@ four positions as Schur complements of their parents) against the FP64
 oracle, which builds each trajectory's mode matrix and factorises its
 submatrix directly, and against the library's per-pattern evaluation of the
 same bitstrings (XF_EVAL_PATTERNS).  The tree is taken for batches of at
-least 1024 bitstrings (smaller ones split the term list into segments)."""
+least 128 bitstrings; below 1024 each bitstring's walk is split into parts
+(whole subtrees) whose exact partial sums are added afterwards."""
 import numpy as np
 import pytest
 
@@ -148,6 +149,32 @@ def test_tree_config3(X):
     ref = oracle.run_workload(w, index=idx)
     plan = make_plan(w, X)
     _tree_vs_patterns(X, plan, w.bits, idx, ref, TOL_FP64, "cfg3 fp64")
+    plan.close()
+
+
+@pytest.mark.parametrize("B", [300, 1000])
+def test_tree_split_into_parts(X, B):
+    """Batches under 1024 bitstrings: each walk split into parts, their
+    partial sums added by a reduction; against the oracle and the
+    per-pattern evaluation, bitwise repeatable."""
+    w = W.workload(3)
+    bits = w.bits[:B]
+    idx = sample_indices(B, 12, seed=B)
+    say(f"prefix tree split into parts: config 3, B={B}")
+    ref = oracle.run_workload(w, index=idx)
+    plan = make_plan(w, X)
+    _tree_vs_patterns(X, plan, bits, idx, ref, TOL_FP64, f"cfg3 B={B}")
+    plan.close()
+
+
+def test_tree_not_below_128_bitstrings(X):
+    """Below 128 bitstrings the segmented per-pattern pass is taken."""
+    w = W.workload(3)
+    plan = make_plan(w, X)
+    p = gpu_probs(plan, X, w.bits[:100], "exact")
+    assert plan.last_work()["tree_bitstrings"] == 0
+    idx = sample_indices(100, 4, seed=100)
+    _check(p[idx], oracle.run_workload(w, index=idx), TOL_FP64, "cfg3 B=100 per pattern")
     plan.close()
 
 
