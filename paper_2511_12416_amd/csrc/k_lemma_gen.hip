@@ -88,11 +88,17 @@ int gen_tree_left_segments(int64_t nkeys) {
     return (int)(most < 16 ? (most > 0 ? most : 1) : 16);
 }
 
+int gen_tree_parts(int64_t B, int64_t nkeys) {
+    const int64_t want = (kTreeWaves + B - 1) / (B > 0 ? B : 1), most = (nkeys + 255) / 256;
+    const int64_t p = want < most ? want : most;
+    return (int)(p < 1 ? 1 : p);
+}
+
 int gen_exact_part_segments(int64_t B, int64_t nkeys, bool tree) {
     const int a = gen_exact_segments(B, nkeys);
-    if (!tree || a > 1) return a;
-    const int b = gen_tree_left_segments(nkeys);
-    return a > b ? a : b;
+    if (!tree) return a;
+    const int b = a > 1 ? a : gen_tree_left_segments(nkeys), c = gen_tree_parts(B, nkeys);
+    return b > c ? b : c;
 }
 
 hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *bits,
@@ -139,15 +145,13 @@ hipError_t launch_gen_exact(const DevPlan &p, const GenPlan &g, bool mixed, bool
     GenRec *rec = (GenRec *)(hbuf + (size_t)B * g.hsize);
     // few bitstrings: each term list split over segments so that about 4096
     // workgroups take part; their partial sums follow the records
-    // the tree: one item per bitstring for large batches; for smaller ones
-    // each bitstring's walk split into as many parts as its term list has
-    // segments (at most the plan's), whose partial sums are added after.
-    // Below 128 bitstrings the segmented pattern pass is as fast or faster
-    // (the parts are whole subtrees of the root's children, too coarse to
-    // spread a few bitstrings over the chip).
+    // the tree: each bitstring's walk split into parts (at most the plan's)
+    // so that about kTreeWaves waves share the call, each with at least
+    // about 256 terms' work; their partial sums are added after
     int nseg = gen_exact_segments(B, nkeys);
-    const bool use_tree = tree && !all_lu && B >= 128;
-    const int tparts = !use_tree ? 0 : (nseg > 1 ? (nseg < tree->nparts ? nseg : tree->nparts) : 1);
+    const bool use_tree = tree && !all_lu;
+    const int tp = gen_tree_parts(B, nkeys);
+    const int tparts = !use_tree ? 0 : (tp < tree->nparts ? tp : tree->nparts);
     if (use_tree && nseg <= 1) nseg = gen_tree_left_segments(nkeys);
     uint64_t *part = (uint64_t *)(rec + B);
     if (all_lu) {

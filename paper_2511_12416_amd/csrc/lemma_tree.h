@@ -226,6 +226,74 @@ __device__ __forceinline__ StepLoads step_loads(const DevTree &tr, const AncAt &
     return s;
 }
 
+// The matrix of an anchor A with children, from its parent's (level
+// A.level - 1): T = P[J, J]^-1 P[J, R] (a column per lane; every lane
+// factorises the same block) into Tb, its R indices into sR[0], the prefix
+// determinant into Dl[A.level], then Q = P[R, R] - P[R, J] T (an entry per
+// lane; e / nr by a multiply, exact for e < nr^2 <= 1024, nr <= 32) into the
+// level's slot.  rr: this lane's R index (lanes < A.nr).
+__device__ __forceinline__ void tree_anchor_matrix(const DevTree &tr, double2 *S, double2 *Tb, double2 *Dl,
+                                                   int (*sR)[kTreeMaxM], const AncAt &A, int rr, double &gl,
+                                                   double &grow, bool &bad) {
+    const int lane = threadIdx.x;
+    const int lv = A.level, nr = A.nr, pnr = A.pnr;
+    const double2 *P = S + tr.slot[lv - 1];
+    double2 *Q = S + tr.slot[lv];
+    if (lane < max(nr, 1)) {
+        double2 m4[4][4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) m4[u][v] = P[A.j[u] * pnr + A.j[v]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = lane < nr ? P[A.j[u] * pnr + rr] : make_double2(0.0, 0.0);
+        const double2 dJ = solve4(m4, x, gl);
+        bad |= dJ.x == 0.0 && dJ.y == 0.0;
+        if (lane < nr) {
+            sR[0][lane] = rr;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) Tb[u * tr.maxr + lane] = x[u];
+        }
+        if (lane == 0) Dl[lv] = c_mul(Dl[lv - 1], dJ);
+    }
+    wave_sync();
+    const uint32_t mg = ((1u << 20) + (uint32_t)nr - 1) / (uint32_t)max(nr, 1);
+    for (int e = lane; e < nr * nr; e += 64) {
+        const int ii = (int)(((uint32_t)e * mg) >> 20), jj = e - ii * nr;
+        const int ri = sR[0][ii], rj = sR[0][jj];
+        double2 sv = P[ri * pnr + rj];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double2 c = P[ri * pnr + A.j[u]];
+            sv = c_fma(sv, make_double2(-c.x, -c.y), Tb[u * tr.maxr + jj]);
+        }
+        Q[e] = sv;
+        grow = fmax(grow, cabs2(sv));
+    }
+    wave_sync();
+}
+
+// One anchor record read directly (uniform index).
+__device__ __forceinline__ AncAt anchor_direct(const DevTree &tr, uint32_t x) {
+    const uint32_t *q = (const uint32_t *)tr.anc + 5 * (size_t)x;
+    uint32_t w[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) w[k] = q[k];
+    AncAt r;
+    r.pat0 = w[0];
+    r.npat = w[1];
+    r.roff = w[2];
+    r.level = (int)(w[3] & 0xFF);
+    r.nr = (int)((w[3] >> 8) & 0xFF);
+    r.pnr = (int)((w[3] >> 16) & 0xFF);
+    r.j[0] = (int)(w[3] >> 24);
+    r.j[1] = (int)(w[4] & 0xFF);
+    r.j[2] = (int)((w[4] >> 8) & 0xFF);
+    r.j[3] = (int)((w[4] >> 16) & 0xFF);
+    r.flags = (int)(w[4] >> 24);
+    return r;
+}
+
 // One wave per bitstring (grid-stride).  Takes the bitstrings whose setup
 // succeeded with unshifted bases (flag 0, shift 0); on success writes p, A
 // and log p and sets the flag to kEntryTree, so that the pattern pass skips
@@ -265,8 +333,10 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, int parts, uint32_t *__
         if (sh0 | sh1) continue;
         const double2 detB = rec[i].det;
         const double2 *Hg = hbuf + (size_t)i * g.hsize;
-        // this item's anchors: whole subtrees of the root's children
-        const int lo = (int)tr.pstart[(pi * tr.nparts) / parts], hi = (int)tr.pstart[((pi + 1) * tr.nparts) / parts];
+        // this item's anchors: a run of the depth-first order (the plan's
+        // parts pa .. pb - 1), after its first anchor's ancestors
+        const int pa = (pi * tr.nparts) / parts, pb = ((pi + 1) * tr.nparts) / parts;
+        const int lo = (int)tr.pstart[pa], hi = (int)tr.pstart[pb];
         AncLanes cur, nxt;
         load_anchor_lanes(tr, lo, cur);
         load_anchor_lanes(tr, lo + 64, nxt);
@@ -303,7 +373,7 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, int parts, uint32_t *__
         bool bad = false;
         unsigned long long rank = 0, flops = 0;
         int nst = 0;   // patterns staged
-        for (int q = lane; q < (pi == 0 ? tr.nroot : 0); q += 64) {
+        for (int q = lane; q < (pa == 0 ? tr.nroot : 0); q += 64) {
             const int r = tree_pattern(load_pat(tr, q), S, M, Dl[0], detB, acc);
             rank += r;
             flops += lu_flops(r) + 18;
@@ -315,6 +385,12 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, int parts, uint32_t *__
         AncAt A1 = anchor_of(cur, nxt, base, hi - lo > 1 ? lo + 1 : lo);
         bool two = hi - lo > 1 && (A0.flags & kTreePairFirst);
         StepLoads ld = step_loads(tr, A0, A1, two, hi > lo);
+        // the ancestors' matrices (their patterns belong to earlier parts)
+        for (int l = 1; l < (hi > lo ? A0.level : 0); ++l) {
+            const AncAt C = anchor_direct(tr, tr.pchain[(size_t)pa * 8 + l]);
+            const int rc = tr.ridx[C.roff + min(lane, max(C.nr - 1, 0))];
+            tree_anchor_matrix(tr, S, Tb, Dl, sR, C, rc, gl, grow, bad);
+        }
         for (int st = lo; st < hi;) {
             // the next step's records (the chunks move on when it starts past
             // the first; st < base + 64 holds at every step) and loads
@@ -402,43 +478,7 @@ k_gen_tree(DevPlan p, GenPlan g, DevTree tr, int64_t nb, int parts, uint32_t *__
             } else {
                 const int nr = A0.nr;
                 double2 *Q = S + tr.slot[lv];
-                // T = P[J, J]^-1 P[J, R] (a column per lane; every lane
-                // factorises the same block) and the prefix determinant
-                if (lane < max(nr, 1)) {
-                    double2 m4[4][4], x[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) m4[u][v] = P[A0.j[u] * pnr + A0.j[v]];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        x[u] = lane < nr ? P[A0.j[u] * pnr + ld.rr] : make_double2(0.0, 0.0);
-                    const double2 dJ = solve4(m4, x, gl);
-                    bad |= dJ.x == 0.0 && dJ.y == 0.0;
-                    if (lane < nr) {
-                        sR[0][lane] = ld.rr;
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) Tb[u * tr.maxr + lane] = x[u];
-                    }
-                    if (lane == 0) Dl[lv] = c_mul(Dl[lv - 1], dJ);
-                }
-                wave_sync();
-                // Q = P[R, R] - P[R, J] T; e / nr by a multiply (exact for
-                // e < nr^2 <= 1024, nr <= 32)
-                const uint32_t mg = ((1u << 20) + (uint32_t)nr - 1) / (uint32_t)max(nr, 1);
-                for (int e = lane; e < nr * nr; e += 64) {
-                    const int ii = (int)(((uint32_t)e * mg) >> 20), jj = e - ii * nr;
-                    const int ri = sR[0][ii], rj = sR[0][jj];
-                    double2 sv = P[ri * pnr + rj];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const double2 c = P[ri * pnr + A0.j[u]];
-                        sv = c_fma(sv, make_double2(-c.x, -c.y), Tb[u * tr.maxr + jj]);
-                    }
-                    Q[e] = sv;
-                    grow = fmax(grow, cabs2(sv));
-                }
-                wave_sync();
+                tree_anchor_matrix(tr, S, Tb, Dl, sR, A0, ld.rr, gl, grow, bad);
                 // stage the anchor's patterns, four per pass (16 lanes each:
                 // one entry of the 4 x 4 block, identity past r) with their
                 // factors w det M_B dpre; evaluate the stage when it is full

@@ -164,7 +164,7 @@ struct xf_plan {
     DevBuf dgsetup;                   // general lemma: per-bitstring H and base records
     std::vector<uint16_t> hkbt;       // host copy of the key-bit table of the general lemma
     // exact mode: the term list's prefix tree (lemma_tree.h), built with it
-    DevBuf dtanc, dtridx, dtpat, dtrpos, dtpart;
+    DevBuf dtanc, dtridx, dtpat, dtrpos, dtpart, dtchain;
     xf::DevTree tree{};
     bool has_tree = false;
     // the tree's position order, kept while the set of flip patterns (not
@@ -792,7 +792,9 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
         while (nl < a.kids.size() && an[a.kids[nl]].kids.empty()) ++nl;
         for (size_t k = 0; k + 1 < nl; k += 2) an[a.kids[k]].pair_first = true;
     }
-    // depth-first over the anchors (iterative; children in that order)
+    // depth-first over the anchors (iterative; children in that order);
+    // each emitted anchor's parent (emitted index, -1 for the root)
+    std::vector<int> emit_of(an.size(), -1), parent_of;
     std::vector<std::pair<int, size_t>> stack;
     stack.emplace_back(0, 0);
     while (!stack.empty()) {
@@ -817,16 +819,21 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
         ta.npat = (uint32_t)(tpat.size() - ta.pat0);
         const bool leaf = an[c].kids.empty();
         ta.pad = (uint8_t)((leaf ? 1 : 0) | (an[c].pair_first ? 2 : 0));
+        emit_of[c] = (int)tanc.size();
+        parent_of.push_back(a == 0 ? -1 : emit_of[a]);
         tanc.push_back(ta);
         // a leaf keeps no matrix of its own: the levels' slots hold the others
         if (!leaf) maxnr[ta.level] = std::max(maxnr[ta.level], (int)ta.nr);
         maxr = std::max(maxr, (int)ta.nr);
         stack.emplace_back(c, 0);
     }
-    // parts of the walk for small batches: up to 256 runs of whole subtrees
-    // of the root's children (never between the two leaves of a pair), cut
-    // where the estimated work (per anchor a block elimination, its matrix
-    // and its patterns' passes) reaches equal shares
+    // parts of the walk for small batches: up to 1024 runs of the
+    // depth-first order (never between the two leaves of a pair), cut where
+    // the estimated work (per anchor a block elimination, its matrix and its
+    // patterns' passes) reaches equal shares; a part starts by recomputing
+    // the matrices of its first anchor's ancestors (any run is then
+    // self-contained: an anchor's parent precedes it, in the run or among
+    // those ancestors)
     std::vector<uint32_t> pstart(1, 0);
     {
         std::vector<double> pre(tanc.size() + 1, 0.0);
@@ -836,8 +843,8 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
         }
         std::vector<size_t> cuts;
         for (size_t x = 1; x < tanc.size(); ++x)
-            if (tanc[x].level == 1 && !(tanc[x - 1].pad & 2)) cuts.push_back(x);
-        const int want = (int)std::min<size_t>(256, cuts.size() + 1);
+            if (!(tanc[x - 1].pad & 2)) cuts.push_back(x);
+        const int want = (int)std::min<size_t>(1024, cuts.size() + 1);
         size_t c = 0;
         for (int kq = 1; kq < want; ++kq) {
             const double target = pre.back() * kq / want;
@@ -846,6 +853,11 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
             pstart.push_back((uint32_t)cuts[c]);
         }
         pstart.push_back((uint32_t)tanc.size());
+    }
+    std::vector<uint32_t> pchain((pstart.size() - 1) * 8, 0xFFFFFFFFu);
+    for (size_t q = 0; q + 1 < pstart.size(); ++q) {
+        if (pstart[q] >= tanc.size()) continue;
+        for (int y = parent_of[pstart[q]]; y >= 0; y = parent_of[y]) pchain[q * 8 + tanc[y].level] = (uint32_t)y;
     }
     xf::DevTree &t = P->tree;
     t = xf::DevTree{};
@@ -881,6 +893,12 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
                 if (tpat[q].r > 4 || tpat[q].idx[u] >= a.nr)
                     return fail(XF_EDEVICE, "internal error: prefix tree pattern index");
     }
+    for (size_t q = 0; q + 1 < pstart.size(); ++q) {
+        if (pstart[q] >= tanc.size()) continue;
+        for (int l = 1; l < tanc[pstart[q]].level; ++l)
+            if (pchain[q * 8 + l] >= tanc.size() || tanc[pchain[q * 8 + l]].level != l || (tanc[pchain[q * 8 + l]].pad & 1))
+                return fail(XF_EDEVICE, "internal error: prefix tree part ancestors");
+    }
     for (int q = 0; q < nroot; ++q)
         for (int u = 0; u < tpat[q].r; ++u)
             if (tpat[q].r > 4 || tpat[q].idx[u] >= M) return fail(XF_EDEVICE, "internal error: prefix tree root index");
@@ -895,13 +913,15 @@ xf_status build_tree(xf_plan *P, const std::vector<uint64_t> &keys, const std::v
         (st = dev_upload(P->dtridx, tridx.data(), tridx.size())) ||
         (st = dev_upload(P->dtpat, tpat.data(), tpat.size() * sizeof(xf::TreePat))) ||
         (st = dev_upload(P->dtrpos, codes.data(), codes.size() * sizeof(uint16_t))) ||
-        (st = dev_upload(P->dtpart, pstart.data(), pstart.size() * sizeof(uint32_t))))
+        (st = dev_upload(P->dtpart, pstart.data(), pstart.size() * sizeof(uint32_t))) ||
+        (st = dev_upload(P->dtchain, pchain.data(), pchain.size() * sizeof(uint32_t))))
         return st;
     t.anc = (const xf::TreeAnchor *)P->dtanc.p;
     t.ridx = (const uint8_t *)P->dtridx.p;
     t.pat = (const xf::TreePat *)P->dtpat.p;
     t.rpos = (const uint16_t *)P->dtrpos.p;
     t.pstart = (const uint32_t *)P->dtpart.p;
+    t.pchain = (const uint32_t *)P->dtchain.p;
     P->has_tree = true;
     return XF_OK;
 }
@@ -1007,7 +1027,7 @@ void plan_free(xf_plan *P) {
                       &P->dglayer, &P->dgneg, &P->dnterm, &P->dxkeys, &P->dxw, &P->dxdw, &P->dpart,
                       &P->dgsum, &P->dekey, &P->decnt, &P->decount, &P->dgcol, &P->dgact, &P->dgpos0,
                       &P->dgpos1, &P->dgblk, &P->dgkbt, &P->dggpos, &P->dflags, &P->dgGA, &P->dgHC, &P->dgTT, &P->dgsetup,
-                      &P->dtanc, &P->dtridx, &P->dtpat, &P->dtrpos, &P->dtpart})
+                      &P->dtanc, &P->dtridx, &P->dtpat, &P->dtrpos, &P->dtpart, &P->dtchain})
         dev_free(*b);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();

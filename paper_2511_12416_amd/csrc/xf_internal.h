@@ -114,7 +114,8 @@ struct DevTree {
     const uint8_t *ridx;
     const TreePat *pat;
     const uint16_t *rpos;  // [M]: (block << 8 | position) of each tree position
-    const uint32_t *pstart;  // [nparts + 1]: first anchor of each part (whole subtrees of the root's children)
+    const uint32_t *pstart;  // [nparts + 1]: first anchor of each part (runs of the depth-first order)
+    const uint32_t *pchain;  // [nparts][8]: the ancestors of each part's first anchor, by level (1 ..)
     int nanc, nroot, npat, M, nparts;
     int slot[kTreeLevels];  // LDS offset (complex entries) of each level's matrix; slot[0]: M x M
     int toff, doff, maxr;   // LDS offsets of T (4 x maxr) and of the levels' prefix determinants
@@ -235,8 +236,7 @@ hipError_t fused_exact_g64(const DevPlan &p, bool mixed, const uint64_t *keys, c
 // kernel for every bitstring).  launch_gen_exact: exact mode over [0, B) with
 // flags[B] marking deferred bitstrings, then the LU kernel for those (all of
 // them with all_lu); with a prefix tree (tree != nullptr), its kernel takes
-// (split into parts for small batches) the bitstrings whose bases need no
-// shift
+// (each walk split into parts) the bitstrings whose bases need no shift
 // before the pattern pass takes the rest.
 bool gen_applies(const DevPlan &p, const GenPlan &g);
 // gen_setup_bytes: bytes per bitstring of the setup workspace the launchers
@@ -249,8 +249,12 @@ int gen_exact_segments(int64_t B, int64_t nkeys);
 // Segments of the pattern pass (and of the LU kernel) after the prefix-tree
 // kernel, which leaves few bitstrings: each of their term lists is split so
 // that no single workgroup walks a long list.  gen_exact_part_segments: the
-// segments the setup workspace holds partial sums for (the larger of both).
+// segments or parts the setup workspace holds partial sums for (the largest).
 int gen_tree_left_segments(int64_t nkeys);
+// Parts of each bitstring's walk along the prefix tree: about kTreeWaves
+// waves per call, at most one per 256 terms (and at most the plan's parts).
+constexpr int kTreeWaves = 16384;
+int gen_tree_parts(int64_t B, int64_t nkeys);
 int gen_exact_part_segments(int64_t B, int64_t nkeys, bool tree);
 hipError_t launch_gen_chunk(const DevPlan &p, const GenPlan &g, bool mixed, bool all_lu, const uint64_t *bits,
                             int64_t b0, int64_t nb, int64_t t, uint64_t seed, uint64_t *ekey, int2 *ecnt,

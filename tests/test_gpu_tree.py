@@ -3,9 +3,10 @@ pattern's det S a principal minor of one matrix per bitstring, anchors every
 four positions as Schur complements of their parents) against the FP64
 oracle, which builds each trajectory's mode matrix and factorises its
 submatrix directly, and against the library's per-pattern evaluation of the
-same bitstrings (XF_EVAL_PATTERNS).  The tree is taken for batches of at
-least 128 bitstrings; below 1024 each bitstring's walk is split into parts
-(whole subtrees) whose exact partial sums are added afterwards."""
+same bitstrings (XF_EVAL_PATTERNS).  Below 1024 bitstrings each
+bitstring's walk is split into parts (runs of the depth-first order, each
+after its first anchor's ancestors) whose exact partial sums are added
+afterwards."""
 import numpy as np
 import pytest
 
@@ -167,14 +168,20 @@ def test_tree_split_into_parts(X, B):
     plan.close()
 
 
-def test_tree_not_below_128_bitstrings(X):
-    """Below 128 bitstrings the segmented per-pattern pass is taken."""
+@pytest.mark.parametrize("B", [1, 7, 100])
+def test_tree_few_bitstrings(X, B):
+    """A few bitstrings: each walk split into up to 16 parts (runs of the
+    depth-first order after their first anchor's ancestors)."""
     w = W.workload(3)
     plan = make_plan(w, X)
-    p = gpu_probs(plan, X, w.bits[:100], "exact")
-    assert plan.last_work()["tree_bitstrings"] == 0
-    idx = sample_indices(100, 4, seed=100)
-    _check(p[idx], oracle.run_workload(w, index=idx), TOL_FP64, "cfg3 B=100 per pattern")
+    bits = w.bits[:B]
+    p = gpu_probs(plan, X, bits, "exact")
+    assert plan.last_work()["tree_bitstrings"] == B
+    idx = sample_indices(B, 4, seed=B)
+    _check(p[idx], oracle.run_workload(w, index=idx), TOL_FP64, f"cfg3 B={B} tree")
+    plan.set_evaluation("patterns")
+    q = gpu_probs(plan, X, bits, "exact")
+    _check(p, q, TOL_FP64, f"cfg3 B={B} tree vs per-pattern")
     plan.close()
 
 
