@@ -311,14 +311,14 @@ xf_status xf_log_prob_backward(xf_plan *plan, const xf_bits128 *d_bits, int64_t 
  * 2K for more), so terms whose flipped
  * positions share a prefix share its elimination.  The plan arranges the
  * term list as a prefix tree over those positions (at most 32 in all; anchors
- * every four positions, each a Schur complement of its parent's), and one
- * wave per bitstring walks it: each term then costs a determinant of at most
+ * every four positions, each a Schur complement of its parent's), and waves
+ * walk it, each bitstring's walk split into parts (runs of the depth-first
+ * order, about 16K waves per call, at most one per 256 terms) whose exact
+ * partial sums are added: each term then costs a determinant of at most
  * 4 x 4 (all principal minors by the recursion of Griffin and Tsatsomeros,
- * Linear Algebra Appl. 419 (2006)); batches of fewer than 1024 bitstrings
- * split each walk into parts (whole subtrees) on separate waves.
- * Bitstrings with a shifted base, an exactly singular pivot block, or
- * entries grown beyond 10^4 times G's largest, and batches of fewer than 128
- * bitstrings, take the per-pattern evaluation instead.
+ * Linear Algebra Appl. 419 (2006)).  Bitstrings with a shifted base, an
+ * exactly singular pivot block, or entries grown beyond 10^4 times G's
+ * largest take the per-pattern evaluation instead.
  *   XF_EVAL_PATTERNS: XF_EVAL_AUTO without the prefix tree (every pattern's
  *     r x r determinant on its own). */
 typedef enum { XF_EVAL_AUTO = 0, XF_EVAL_LU = 1, XF_EVAL_PATTERNS = 2 } xf_evaluation;
