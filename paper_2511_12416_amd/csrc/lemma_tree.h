@@ -7,8 +7,8 @@
 // with T = R'_1 from layer-0 to layer-1 positions (zero elsewhere: T^2 = 0,
 // so det(I + 2T - 2H)[N, N] = det(I - 2(I - 2T)H)[N, N], the two-layer form
 // that corrects the layer-1 rows by the pattern's layer-0 flips); G = I +
-// 2TT - 2K for more than two (lemma_gen.h).  Every det G[N, N] is a principal minor of the same
-// matrix, so the terms share work: ordering the flipped positions, a term's
+// 2TT - 2K for more than two (lemma_gen.h).  Every det G[N, N] is a
+// principal minor of the same matrix, so the terms share work: ordering the flipped positions, a term's
 // minor is the product of the pivots of Gaussian elimination in that order,
 // and terms with a common prefix share its elimination (the recursion of
 // Griffin and Tsatsomeros for all principal minors of a matrix, Linear
@@ -294,16 +294,21 @@ __device__ __forceinline__ AncAt anchor_direct(const DevTree &tr, uint32_t x) {
     return r;
 }
 
-// One wave per bitstring (grid-stride).  Takes the bitstrings whose setup
-// succeeded with unshifted bases (flag 0, shift 0); on success writes p, A
-// and log p and sets the flag to kEntryTree, so that the pattern pass skips
-// them; otherwise leaves the flag for the pattern pass.  LDS: tr.lds bytes
-// (the levels' matrices, two T buffers, the prefix determinants and the
-// staged patterns).  The anchor records come 64 at a time into the lanes'
-// registers (the next 64 loaded while these are used); each step's R indices
-// and first four patterns are loaded one step ahead.  A step is one anchor,
-// or two sibling leaves (a half-wave each), whose patterns' blocks are formed
-// from the parent's matrix without a matrix of their own.  An anchor's patterns are
+// One wave per (bitstring, part) item (grid-stride): part pi of `parts`
+// covers the plan's parts pa .. pb - 1, a run of the depth-first anchor
+// order, which it walks after recomputing its first anchor's ancestors (the
+// root's patterns go with the first part).  Takes the bitstrings whose setup
+// succeeded with unshifted bases (flag 0, shift 0).  With one part: on
+// success writes p, A and log p and sets the flag to kEntryTree, so that the
+// pattern pass skips them; otherwise leaves the flag for the pattern pass.
+// With several: writes each part's exact partial sum and its failure bit to
+// part[item], for k_gen_tree_reduce.  LDS: tr.lds bytes (the levels'
+// matrices, two T buffers, the prefix determinants and the staged patterns).
+// The anchor records come 64 at a time into the lanes' registers (the next
+// 64 loaded while these are used); each step's R indices and first four
+// patterns are loaded one step ahead.  A step is one anchor, or two sibling
+// leaves (a half-wave each), whose patterns' blocks are formed from the
+// parent's matrix without a matrix of their own.  An anchor's patterns are
 // copied, as identity-padded 4 x 4 blocks with their factors, into a stage
 // that is evaluated kTreeStage at a time (a lane each), so that the
 // determinants run on full waves although an anchor has few patterns.
