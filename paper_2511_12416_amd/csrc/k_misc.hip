@@ -1,5 +1,5 @@
 // Small utility kernels: zero and value fills, fixed-order reduction of per-workgroup
-// partial sums, counter reset.
+// partial sums (overwrites the partials), counter reset.
 #include "xf_device.h"
 
 namespace xf {
@@ -14,12 +14,30 @@ __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
         p[i] = v;
 }
 
-// out[e] = sum over workgroups q = 0, 1, ... of part[q][e], in that order.
-__global__ void k_reduce_parts(const double2 *__restrict__ part, int nparts, int stride, double2 *out) {
+// Fixed-order sum of the partials part[q][e], q < nparts, in two levels:
+// k_reduce_chunks adds each chunk of `len` consecutive partials in order and
+// stores the sum in the chunk's first row (blockIdx.y = chunk);
+// k_reduce_parts then adds the chunks' sums in chunk order into out[e].
+// The association does not depend on the launch, so results repeat bitwise.
+__global__ void k_reduce_chunks(double2 *__restrict__ part, int nparts, int stride, int len) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q0 = blockIdx.y * len;
+    if (e >= stride || q0 >= nparts) return;
+    const int q1 = min(nparts, q0 + len);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int q = q0; q < q1; ++q) {
+        const double2 v = part[(size_t)q * stride + e];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    part[(size_t)q0 * stride + e] = acc;
+}
+
+__global__ void k_reduce_parts(const double2 *__restrict__ part, int nparts, int stride, int len, double2 *out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= stride) return;
     double2 acc = make_double2(0.0, 0.0);
-    for (int q = 0; q < nparts; ++q) {
+    for (int q = 0; q < nparts; q += len) {
         const double2 v = part[(size_t)q * stride + e];
         acc.x += v.x;
         acc.y += v.y;
@@ -45,8 +63,18 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, double2 *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_parts, dim3((stride + 255) / 256), dim3(256), 0, s, part, nparts, stride, out);
+hipError_t launch_reduce_parts(double2 *part, int nparts, int stride, double2 *out, hipStream_t s) {
+    // chunks of 32 partials: enough workgroups to read the partials at the
+    // memory's rate, few enough chunk sums for the second level
+    const int len = 32, chunks = (nparts + len - 1) / len;
+    const unsigned gx = (unsigned)((stride + 255) / 256);
+    if (chunks > 1) {
+        hipLaunchKernelGGL(k_reduce_chunks, dim3(gx, (unsigned)chunks), dim3(256), 0, s, part, nparts, stride, len);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_reduce_parts, dim3(gx), dim3(256), 0, s, (const double2 *)part, nparts, stride,
+                       chunks > 1 ? len : 1, out);
     return hipGetLastError();
 }
 

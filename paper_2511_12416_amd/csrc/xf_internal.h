@@ -199,7 +199,7 @@ hipError_t launch_exact_bwd(const DevPlan &p, bool mixed, const uint64_t *keys, 
                             hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s);
-hipError_t launch_reduce_parts(const double2 *part, int nparts, int stride, double2 *out, hipStream_t s);
+hipError_t launch_reduce_parts(double2 *part, int nparts, int stride, double2 *out, hipStream_t s);   // overwrites part
 // Raises the dynamic-LDS limit of every kernel instantiated for lane-group
 // size G (k_misc.hip calls the per-file functions).
 hipError_t prepare_kernels(int G);
