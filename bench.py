@@ -32,8 +32,10 @@ distributions against the stored oracle values of 1000 bitstrings of this
 batch (with the terms' cancellation sum|w det| / |A|); the LUCJ workload
 (n = 32), the exact-mode stress workload (n = 52, all 4096 terms; along the
 term list's prefix tree, and again with every pattern's determinant on its
-own), and the forward and forward+adjoint time of the differentiation
-workload.
+own), the forward and forward+adjoint time of the differentiation
+workload, and the latency of one exact outcome of random extended-matchgate
+circuits with 16 CPhase layers (the paper's random benchmark shape) for n =
+8 to 36.
 """
 from __future__ import annotations
 
@@ -276,6 +278,32 @@ def run_extras(X, W, args, dev):
         log(f"differentiation {prec}: forward {fwd * 1e3:.3f} ms, forward+adjoint {fb * 1e3:.3f} ms")
         plan.close()
     extra["differentiation_n32"] = d
+    # the paper's random-circuit benchmark shape (Sec. V-A): extended
+    # matchgate circuits of n qubits, 16 CPhase gates and n - 1 matchgates
+    # per layer; exact probability of one outcome near the input, per call
+    lat = {}
+    for n in (8, 16, 24, 32, 36):
+        eta = n // 2
+        gates, inp, _ = W.random_gate_circuit(85 + n, n, eta, 16, n - 1, theta_scale=1.0, max_bits=4)
+        rot, pairs, layer, theta = X.circuit_from_gates(n, gates)
+        one = X.bits_tensor(W.nearby_outcomes(7 + n, n, range(eta), 1, hops=4), dev)
+        o1 = torch.empty(1, dtype=torch.float64, device=dev)
+        plan = X.Plan(rot, pairs, layer, theta, inp, "fp64", device=0)
+        for _ in range(3):
+            plan.probabilities(one, "exact", out=o1)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(20):
+            t0 = time.perf_counter()
+            plan.probabilities(one, "exact", out=o1)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        lat[f"n{n}"] = float(np.median(ts)) * 1e3
+        plan.close()
+    extra["random_circuits_one_outcome_ms"] = {
+        "workload": "random extended-matchgate circuits, 16 CPhase layers, n-1 matchgates per layer, "
+                    "eta = n/2, exact probability of one outcome (median of 20 calls)", **lat}
+    log("one outcome, 16 CPhase layers: " + ", ".join(f"{k} {v:.3f} ms" for k, v in lat.items()))
     return extra
 
 
