@@ -785,14 +785,16 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
     static_assert(NQ % 64 == 0 && NQ <= NT, "first draws by whole waves");
     static_assert((kBatch & kOff) == 0, "batch offsets are the low bits of a queue entry");
     const int q = tid - (NT - NQ);          // first-draw block of this thread, if >= 0
-    const uint64_t below = (1ull << lane) - 1;
     for (; st.next < t; st.next += kBatch, ++st.j) {
         uint32_t *queue = (st.j & 1) ? (uint32_t *)s.piv : (uint32_t *)s.list;
         if (q >= 0) {
             // u_0 of samples next + 4 q + w is word w of block (next / 4 + q, 2^32 - 1)
             const uint4 r = philox10(make_uint4((st.next >> 2) + (uint32_t)q, 0xFFFFFFFFu, blo, bhi), k0, k1);
             if (st.next + 4u * (uint32_t)q < t) ++blocks;
+            // live samples of the batch (offsets below lim)
+            const uint32_t lim = min(kBatch, t - st.next);
             uint32_t ent[4];
+            bool sel[4];
             uint64_t ball[4];
             int total = 0;
 #pragma unroll
@@ -800,7 +802,8 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
                 const uint32_t off = 4u * (uint32_t)q + (uint32_t)w;
                 const uint32_t u = w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
                 ent[w] = (u & ~kOff) | off;
-                ball[w] = __ballot(st.next + off < t && u < any);
+                sel[w] = (u < any) & (off < lim);
+                ball[w] = __ballot(sel[w]);
                 total += (int)__popcll(ball[w]);
             }
             int at = 0;
@@ -808,7 +811,10 @@ __device__ __forceinline__ bool sample_until_flush(const DevPlan &p, const RawSm
             at = __shfl(at, 0, 64);
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                if ((ball[w] >> lane) & 1) queue[at + (int)__popcll(ball[w] & below)] = ent[w];
+                // queue position: the selected samples of lower lanes (mbcnt of the ballot)
+                const uint32_t below_sel = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(ball[w] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball[w], 0u));
+                if (sel[w]) queue[at + (int)below_sel] = ent[w];
                 at += (int)__popcll(ball[w]);
             }
         }
