@@ -35,9 +35,10 @@ batch (with the terms' cancellation sum|w det| / |A|); the LUCJ workload
 (n = 32), the exact-mode stress workload (n = 52, all 4096 terms; along the
 term list's prefix tree, and again with every pattern's determinant on its
 own), the forward and forward+adjoint time of the differentiation
-workload, and the latency of one exact outcome of random extended-matchgate
-circuits with 16 CPhase layers (the paper's random benchmark shape) for n =
-8 to 36.
+workload (the backward taking the forward call's sampled patterns, and
+drawing them again), and the latency of one exact outcome of random
+extended-matchgate circuits with 16 CPhase layers (the paper's random
+benchmark shape) for n = 8 to 36.
 """
 from __future__ import annotations
 
@@ -268,16 +269,23 @@ def run_extras(X, W, args, dev):
             plan.probabilities(bits, "approx", w.t, w.seed, out=out, logp=lp)
         torch.cuda.synchronize()
         fwd = (time.perf_counter() - t0) / steps
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            plan.probabilities(bits, "approx", w.t, w.seed, out=out, logp=lp)
-            plan.log_prob_backward(bits, g, "approx", w.t, w.seed)
-        torch.cuda.synchronize()
-        fb = (time.perf_counter() - t0) / steps
-        d[prec] = {"fwd_ms": fwd * 1e3, "fwd_bwd_ms": fb * 1e3,
-                   "fwd_bwd_terms_per_s": w.B * w.t / fb,
+        fb = {}
+        # the backward draws the samples again, then takes the forward call's
+        for reuse in (False, True):
+            plan.set_reuse_samples(reuse)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.probabilities(bits, "approx", w.t, w.seed, out=out, logp=lp)
+                plan.log_prob_backward(bits, g, "approx", w.t, w.seed)
+            torch.cuda.synchronize()
+            fb[reuse] = (time.perf_counter() - t0) / steps
+            assert plan.last_work()["backward_reused"] == reuse
+        d[prec] = {"fwd_ms": fwd * 1e3, "fwd_bwd_ms": fb[True] * 1e3,
+                   "fwd_bwd_terms_per_s": w.B * w.t / fb[True],
+                   "fwd_bwd_ms_backward_resampling": fb[False] * 1e3,
                    "backward_lemma": bool(plan.last_work()["backward_lemma"])}
-        log(f"differentiation {prec}: forward {fwd * 1e3:.3f} ms, forward+adjoint {fb * 1e3:.3f} ms")
+        log(f"differentiation {prec}: forward {fwd * 1e3:.3f} ms, forward+adjoint {fb[True] * 1e3:.3f} ms "
+            f"({fb[False] * 1e3:.3f} ms with the backward drawing the samples again)")
         plan.close()
     extra["differentiation_n32"] = d
     # the paper's random-circuit benchmark shape (Sec. V-A): extended

@@ -351,6 +351,22 @@ xf_status xf_plan_set_tree_growth(xf_plan *plan, double growth);
  * enough. */
 xf_status xf_plan_set_workspace_limit(xf_plan *plan, uint64_t bytes);
 
+/* Backward without resampling (default off).  When on, an
+ * xf_log_prob_backward call in Raw Estimate mode whose d_bits, B, t and seed
+ * equal those of the plan's last xf_probabilities call takes that call's
+ * distinct flip patterns and counts (the determinant table of Sec. IV-B,
+ * drawn per Sec. III-B Eq. 10-12) from the plan's workspace instead of
+ * drawing them again; the gradient is the same.  This applies only when both
+ * calls use the one-layer determinant-lemma kernels (eta <= 16) and the
+ * forward call processed the batch in one chunk (see
+ * xf_plan_set_workspace_limit); otherwise the backward draws the samples
+ * itself.  Any other xf_probabilities or xf_estimate call on the plan, and
+ * any parameter or setting change, ends the reuse until the next forward
+ * call.  The caller guarantees that the bitstrings at d_bits are unchanged
+ * between the two calls and that the backward is ordered after the forward
+ * (the same stream, or an event).  on is 0 or 1, else XF_EINVAL. */
+xf_status xf_plan_set_reuse_samples(xf_plan *plan, int32_t on);
+
 /* Work done by the last xf_probabilities call on this plan (synchronises the
  * device): *count = distinct (bitstring, flip-pattern) determinants
  * evaluated; *rank_sum (nullable) = the sum over them of the number of
@@ -378,6 +394,8 @@ typedef struct {
     int32_t lemma;
     int32_t backward_lemma;   /* the last xf_log_prob_backward call used the determinant lemma */
     int32_t general;          /* the call used the general determinant-lemma kernel (see below) */
+    int32_t backward_reused;  /* the last xf_log_prob_backward call took the forward call's sampled
+                                 patterns (see xf_plan_set_reuse_samples) */
     int64_t fp32_bases;       /* bases (per block) whose lemma products ran in FP32 (XF_MIXED) */
     int64_t philox_blocks;    /* Raw Estimate under the lemma: Philox4x32-10 blocks the sampling
                                  definition draws (one per four samples' first draws, one per four

@@ -28,7 +28,7 @@ class Bits128(ctypes.Structure):
 class Work(ctypes.Structure):
     _fields_ = [("determinants", ctypes.c_int64), ("rank_sum", ctypes.c_int64), ("flops", ctypes.c_double),
                 ("sample_ms", ctypes.c_double), ("eval_ms", ctypes.c_double), ("lemma", ctypes.c_int32),
-                ("backward_lemma", ctypes.c_int32), ("general", ctypes.c_int32),
+                ("backward_lemma", ctypes.c_int32), ("general", ctypes.c_int32), ("backward_reused", ctypes.c_int32),
                 ("fp32_bases", ctypes.c_int64), ("philox_blocks", ctypes.c_int64),
                 ("tree_bitstrings", ctypes.c_int64)]
 
@@ -50,7 +50,7 @@ EXPORTS = ["xf_plan_create", "xf_plan_set_params", "xf_plan_refreeze", "xf_plan_
            "xf_extent", "xf_trajectory_bound", "xf_probabilities", "xf_probabilities_noalloc", "xf_estimate",
            "xf_log_prob_backward",
            "xf_plan_last_term_count", "xf_plan_last_work", "xf_plan_set_evaluation", "xf_plan_set_workspace_limit", "xf_plan_set_mixed_condition",
-           "xf_plan_set_tree_growth",
+           "xf_plan_set_tree_growth", "xf_plan_set_reuse_samples",
            "xf_expm_antihermitian", "xf_expm_adjoint", "xf_spin_rotations", "xf_spin_rotations_adjoint",
            "xf_antihermitian_reals_grad", "xf_circuit_from_gates", "xf_sample_gates", "xf_last_error"]
 
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
     L.xf_plan_set_workspace_limit.argtypes = [P, U64]
     L.xf_plan_set_mixed_condition.argtypes = [P, D]
     L.xf_plan_set_tree_growth.argtypes = [P, D]
+    L.xf_plan_set_reuse_samples.argtypes = [P, I32]
     L.xf_expm_antihermitian.argtypes = [I32, P, P]
     L.xf_expm_adjoint.argtypes = [I32, P, P, P]
     L.xf_spin_rotations.argtypes = [I32, I32, P, P]

@@ -124,6 +124,7 @@ class Plan:
         return {"determinants": w.determinants, "rank_sum": w.rank_sum, "flops": w.flops,
                 "sample_ms": w.sample_ms, "eval_ms": w.eval_ms, "lemma": bool(w.lemma),
                 "backward_lemma": bool(w.backward_lemma), "general": bool(w.general),
+                "backward_reused": bool(w.backward_reused),
                 "fp32_bases": w.fp32_bases, "philox_blocks": w.philox_blocks,
                 "tree_bitstrings": w.tree_bitstrings}
 
@@ -145,6 +146,12 @@ class Plan:
         """Exact mode along the prefix tree: the largest entry growth accepted
         before a bitstring takes the per-pattern evaluation."""
         check(lib().xf_plan_set_tree_growth(self._h, float(growth)))
+
+    def set_reuse_samples(self, on: bool) -> None:
+        """Raw Estimate backward calls on the same bitstring tensor, t and seed
+        as the last forward call take its sampled patterns instead of drawing
+        them again (the bitstrings must not change in between)."""
+        check(lib().xf_plan_set_reuse_samples(self._h, 1 if on else 0))
 
     def set_workspace_limit(self, nbytes: int) -> None:
         """Device memory the determinant-lemma workspace may use (bitstrings

@@ -155,13 +155,15 @@ bool backward_uses_lemma(const DevPlan &p, int algorithm) {
 hipError_t launch_lemma_bwd_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
                                   uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,
                                   const double *g, double2 *part, int nparts, const GradLayout &lay,
-                                  hipStream_t s) {
+                                  bool resample, hipStream_t s) {
     const int grid = (int)(nb < kMaxGrid ? nb : kMaxGrid);
-    hipLaunchKernelGGL((k_sample_entries<kSamplerThreads>), dim3(grid), dim3(kSamplerThreads),
-                       sampler_lds_bytes(p.k), s, p, bits, b0, nb, (uint32_t)t, seed, ekey, ecnt, ecount, cap,
-                       nullptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (resample) {
+        hipLaunchKernelGGL((k_sample_entries<kSamplerThreads>), dim3(grid), dim3(kSamplerThreads),
+                           sampler_lds_bytes(p.k), s, p, bits, b0, nb, (uint32_t)t, seed, ekey, ecnt, ecount, cap,
+                           nullptr);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const int bg = nparts < nb ? nparts : (int)nb;
     const size_t lds = bwd_lemma_lds(p);
     switch (p.G) {

@@ -178,9 +178,17 @@ struct xf_plan {
     double mixed_cond = 100.0;        // XF_MIXED: kappa_1 bound of bases formed in FP32
     int last_lemma = 0;               // the last xf_probabilities call used the determinant lemma
     int last_bwd_lemma = 0;           // the last xf_log_prob_backward call used the determinant lemma
+    int last_bwd_reused = 0;          // ... and took the forward call's patterns from the workspace
     // determinant-lemma workspace: per-bitstring regions of (pattern, count) entries
     DevBuf dekey, decnt, decount;
     uint64_t entry_budget = 16ull << 30;  // bytes of workspace the chunking aims at
+    // the last Raw Estimate forward call whose patterns the workspace still
+    // holds (one-layer lemma kernels, one chunk), for xf_plan_set_reuse_samples
+    bool reuse_samples = false;
+    bool fwd_valid = false;
+    const void *fwd_bits = nullptr;
+    int64_t fwd_B = 0, fwd_t = 0;
+    uint64_t fwd_seed = 0;
     // timing of the last call: ev[0] start, then per chunk (mid, end) of the
     // two lemma kernels, or one end event for a fused kernel
     std::vector<hipEvent_t> ev;
@@ -1187,6 +1195,7 @@ xf_status xf_plan_create(const xf_circuit *c, xf_bits128 input, xf_precision pre
 
 xf_status xf_plan_set_params(xf_plan *P, const double *rot, const double *theta) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    P->fwd_valid = false;
     const double *r = rot ? rot : P->rot.data();
     const double *th = theta ? theta : P->theta.data();
     xf_status st = check_params(P->n, P->n_rot, r, P->k, th);
@@ -1202,6 +1211,7 @@ xf_status xf_plan_set_params(xf_plan *P, const double *rot, const double *theta)
 
 xf_status xf_plan_refreeze(xf_plan *P) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    P->fwd_valid = false;
     DeviceGuard guard(P->device);
     if (!guard.okay) return fail(XF_EDEVICE, "hipSetDevice failed");
     if (hipDeviceSynchronize() != hipSuccess) return fail(XF_EDEVICE, "device synchronisation failed");
@@ -1252,6 +1262,7 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
                              uint64_t seed, double *d_prob, double *d_amp, double *d_logp, void *hip_stream,
                              bool noalloc) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    P->fwd_valid = false;   // the workspace may be refilled or reallocated below
     if (B < 0) return fail(XF_EINVAL, "B < 0");
     if (mode != XF_EXACT && mode != XF_RAW_ESTIMATE) return fail(XF_EINVAL, "unknown mode");
     if (mode == XF_RAW_ESTIMATE) {
@@ -1383,6 +1394,13 @@ xf_status probabilities_impl(xf_plan *P, const xf_bits128 *d_bits, int64_t B, xf
             P->nev = timed ? 1 + 2 * (int)nchunks : 0;
             P->last_lemma = 1;
             P->last_gen = gen ? 1 : 0;
+            if (e == hipSuccess && fast && !noalloc && nchunks == 1) {
+                P->fwd_valid = true;
+                P->fwd_bits = d_bits;
+                P->fwd_B = B;
+                P->fwd_t = t;
+                P->fwd_seed = seed;
+            }
         } else {
             e = xf::launch_raw_estimate(d, mixed, (const uint64_t *)d_bits, 0, B, t, seed, d_prob, d_amp, d_logp,
                                         nterm, nullptr, 0, s);
@@ -1758,6 +1776,7 @@ xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
     work->flops = (double)v[2];
     work->lemma = P->last_lemma;
     work->backward_lemma = P->last_bwd_lemma;
+    work->backward_reused = P->last_bwd_reused;
     work->general = P->last_gen;
     work->fp32_bases = (int64_t)v[3];
     work->philox_blocks = (int64_t)v[4];
@@ -1778,7 +1797,16 @@ xf_status xf_plan_last_work(xf_plan *P, xf_work *work) {
 xf_status xf_plan_set_workspace_limit(xf_plan *P, uint64_t bytes) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
     if (bytes == 0) return fail(XF_EINVAL, "workspace limit must be positive");
+    P->fwd_valid = false;
     P->entry_budget = bytes;
+    return ok();
+}
+
+xf_status xf_plan_set_reuse_samples(xf_plan *P, int32_t on) {
+    if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
+    if (on != 0 && on != 1) return fail(XF_EINVAL, "on must be 0 or 1");
+    P->reuse_samples = on == 1;
+    P->fwd_valid = false;
     return ok();
 }
 
@@ -1801,6 +1829,7 @@ xf_status xf_plan_set_evaluation(xf_plan *P, xf_evaluation evaluation) {
     if (!plan_valid(P)) return fail(XF_EINVAL, "invalid plan");
     if (evaluation != XF_EVAL_AUTO && evaluation != XF_EVAL_LU && evaluation != XF_EVAL_PATTERNS)
         return fail(XF_EINVAL, "unknown evaluation");
+    P->fwd_valid = false;
     P->evaluation = evaluation;
     return ok();
 }
@@ -1852,11 +1881,16 @@ xf_status xf_log_prob_backward(xf_plan *P, const xf_bits128 *d_bits, int64_t B, 
         int64_t chunk = B, nchunks = 1;
         uint64_t cap = 0;
         int n_lemma = 0, n_lu = 0;
+        bool reuse = false;   // the forward call's patterns are still in the workspace
         if (lemma) {
             cap = xf::lemma_entry_cap(t);
             const int64_t per = (int64_t)std::max<uint64_t>(1, P->entry_budget / (cap * 16 + 4));
             chunk = std::min<int64_t>(B, per);
             nchunks = (B + chunk - 1) / chunk;
+            reuse = P->reuse_samples && P->fwd_valid && nchunks == 1 && P->fwd_bits == (const void *)d_bits &&
+                    P->fwd_B == B && P->fwd_t == t && P->fwd_seed == seed;
+            // otherwise this call's own samples replace the forward call's
+            if (!reuse) P->fwd_valid = false;
             n_lemma = (int)std::min<int64_t>(chunk, 1024);
             n_lu = 64;   // deferred bitstrings only (rare)
             if ((st = ensure_lemma_workspace(P, chunk, cap, s))) return st;
@@ -1876,7 +1910,8 @@ xf_status xf_log_prob_backward(xf_plan *P, const xf_bits128 *d_bits, int64_t B, 
                     const int64_t b0 = c * chunk, nb = std::min(chunk, B - b0);
                     e = xf::launch_lemma_bwd_chunk(d, (const uint64_t *)d_bits, b0, nb, t, seed,
                                                    (uint64_t *)P->dekey.p, (int2 *)P->decnt.p,
-                                                   (uint32_t *)P->decount.p, cap, d_grad_logp, part, n_lemma, lay, s);
+                                                   (uint32_t *)P->decount.p, cap, d_grad_logp, part, n_lemma, lay,
+                                                   !reuse, s);
                     if (e == hipSuccess)
                         e = xf::launch_raw_estimate_bwd(d, mixed, (const uint64_t *)d_bits, b0, nb, t, seed,
                                                         d_grad_logp, part_lu, n_lu, lay,
@@ -1898,6 +1933,7 @@ xf_status xf_log_prob_backward(xf_plan *P, const xf_bits128 *d_bits, int64_t B, 
             hipStreamSynchronize(s) != hipSuccess)
             return fail(XF_EDEVICE, "could not read back the gradient sums");
         P->last_bwd_lemma = lemma ? 1 : 0;
+        P->last_bwd_reused = reuse ? 1 : 0;
     }
     // Host FP64 chain rule from the factors back to rotations and angles.
     // All Gbar below are holomorphic adjoints: dL = 2 Re sum Gbar .* dZ.

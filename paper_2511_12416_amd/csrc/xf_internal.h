@@ -172,7 +172,9 @@ hipError_t launch_lemma_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0
                               double *prob, double *amp, double *logp, unsigned long long *nterm,
                               hipEvent_t ev_mid, hipStream_t s);
 // Determinant-lemma backward for bitstrings [b0, b0 + nb): the sampler kernel
-// refills the workspace, then k_bwd_entries adds each bitstring's adjoint into
+// refills the workspace (with resample false the workspace already holds the
+// forward call's patterns of these bitstrings), then k_bwd_entries adds each
+// bitstring's adjoint into
 // workgroup partial i of part (nparts of them, stride lay.stride); bitstrings
 // it cannot take get ecount = kEntryDeferred (see launch_raw_estimate_bwd).
 bool backward_uses_lemma(const DevPlan &p, int algorithm);
@@ -180,7 +182,7 @@ size_t bwd_lemma_lds(const DevPlan &p);
 hipError_t launch_lemma_bwd_chunk(const DevPlan &p, const uint64_t *bits, int64_t b0, int64_t nb, int64_t t,
                                   uint64_t seed, uint64_t *ekey, int2 *ecnt, uint32_t *ecount, uint64_t cap,
                                   const double *g, double2 *part, int nparts, const GradLayout &lay,
-                                  hipStream_t s);
+                                  bool resample, hipStream_t s);
 // Exact mode with the LU per term over bitstrings [0, B) (only: those with
 // only[b] == kEntryDeferred); grid <= 0: one workgroup per bitstring.
 hipError_t launch_exact(const DevPlan &p, bool mixed, const uint64_t *keys, const double2 *w, int64_t nkeys,

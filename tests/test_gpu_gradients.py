@@ -111,6 +111,50 @@ def test_config4_backward_is_bitwise_reproducible(X):
     assert np.all(np.isfinite(r1[0])) and np.all(np.isfinite(r1[1]))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_config4_backward_reusing_forward_samples(X, prec):
+    """With reuse on, a backward call after a forward call on the same bitstring
+    tensor, t and seed takes the forward call's patterns and gives bitwise the
+    gradients of a backward that draws them again; a forward call with another
+    seed, a parameter change or a setting change in between ends the reuse."""
+    w = W.workload(4)
+    say(f"config 4 backward reusing the forward call's samples ({prec})")
+    rot = X.spin_rotations(w.gens)
+    bits = X.bits_tensor(w.bits)
+    g = torch.full((w.B,), 1.0 / w.B, dtype=torch.float64, device="cuda")
+    logp = torch.empty(w.B, dtype=torch.float64, device="cuda")
+    ref_plan = X.Plan(rot, w.pairs, w.layer, w.theta, w.input_bits, prec)
+    ref = ref_plan.log_prob_backward(bits, g, "approx", w.t, w.seed)
+    assert not ref_plan.last_work()["backward_reused"]
+    ref_plan.close()
+    plan = X.Plan(rot, w.pairs, w.layer, w.theta, w.input_bits, prec)
+    plan.set_reuse_samples(True)
+
+    def check(expect_reuse):
+        r = plan.log_prob_backward(bits, g, "approx", w.t, w.seed)
+        assert plan.last_work()["backward_reused"] == expect_reuse
+        assert np.array_equal(r[0], ref[0]) and np.array_equal(r[1], ref[1])
+
+    plan.probabilities(bits, "approx", w.t, w.seed, logp=logp)
+    check(True)
+    check(True)            # the workspace still holds the forward call's patterns
+    plan.probabilities(bits, "approx", w.t, w.seed + 1, logp=logp)
+    check(False)           # another seed: drawn again
+    check(False)           # ... and the workspace now holds the backward's own draws
+    plan.probabilities(bits, "approx", w.t, w.seed, logp=logp)
+    plan.set_params(rot, w.theta)
+    check(False)
+    plan.probabilities(bits, "approx", w.t, w.seed, logp=logp)
+    plan.set_workspace_limit(1 << 34)
+    check(False)
+    plan.probabilities(bits[: w.B // 2], "approx", w.t, w.seed, logp=logp[: w.B // 2])
+    check(False)           # another batch
+    plan.set_reuse_samples(False)
+    plan.probabilities(bits, "approx", w.t, w.seed, logp=logp)
+    check(False)
+    plan.close()
+
+
 def test_config4_gradient_vs_finite_differences(X):
     """Mean log-probability over all 4096 bitstrings (t = 2^14, samples frozen):
     analytic gradients for every generator real and every angle vs central
