@@ -294,8 +294,9 @@ struct RawSmem {
     uint8_t *Rb;
     uint64_t *gkey;   // [k] key contribution of gate j, bit 63 = theta_j < 0
     // Sampling table, k rows of trow words (see load_tables): row a holds
-    // 8 boundaries of its 16-entry blocks, kpad / 4 boundaries of its 4-entry
-    // blocks, then T[a][0 .. kpad) (0 before a, all-ones from k on)
+    // 32 guide bytes (bucket i: the number of entries <= i << bucket_shift),
+    // kpad / 4 boundaries of its 4-entry blocks, then T[a][0 .. kpad) (0
+    // before a, all-ones from k on)
     uint32_t *T;
     int kpad;         // entries of a row, a multiple of 16
     int trow;         // words of a row
@@ -692,27 +693,38 @@ __device__ __forceinline__ void clear_table(const RawSmem &s, int *cnt, uint32_t
     st.claimed = 1;
 }
 
+// Bucket shift of a table row with last entry `tail`: u < tail falls in
+// bucket u >> shift, one of 32 (the row's range cut into equal parts).
+__device__ __forceinline__ int bucket_shift(uint32_t tail) {
+    const int sh = 27 - (int)__clz(tail);
+    return sh > 0 ? sh : 0;
+}
+
 // The next selected gate from gate a for the uniform draw u (see the
 // sampler definition in the public header): the number of entries <= u of
 // row a of the table (the row is non-decreasing), or -1 when u >= T[a][k-1].
-// Three levels of four-way comparisons without branches: the boundaries of
-// the 16-entry blocks (eight of them, all-ones past the row), those of the
-// chosen block's 4-entry blocks, then that block's entries.  The last
-// boundary not below u bounds each count (u < T[a][k-1] <= 2^32 - 1 is below
-// every all-ones padding entry).
+// The row's guide byte of u's bucket counts the entries <= the bucket's
+// start, so the count is that many, rounded down to a multiple of four
+// (at most kpad - 8), plus the entries <= u among the next eight, unless all
+// eight are (a crowded bucket): then the boundaries of the 4-entry blocks,
+// then that block's entries.  Entries past k are all-ones, above every
+// u < T[a][k-1] <= 2^32 - 1.
 __device__ __forceinline__ int next_gate(const RawSmem &s, int k, int a, uint32_t u) {
     const uint32_t *row = s.T + a * s.trow;
     const uint32_t *ent = row + 8 + (s.kpad >> 2);
     const uint32_t tail = ent[k - 1];
-    const uint4 b0 = *(const uint4 *)row;
-    int bs = (b0.x <= u) + (b0.y <= u) + (b0.z <= u) + (b0.w <= u);
-    if (s.kpad > 64) {
-        const uint4 b1 = *(const uint4 *)(row + 4);
-        bs += (b1.x <= u) + (b1.y <= u) + (b1.z <= u) + (b1.w <= u);
-    }
     if (!(u < tail)) return -1;
-    const uint4 q = ((const uint4 *)(row + 8))[bs];
-    const int cs = 4 * bs + (q.x <= u) + (q.y <= u) + (q.z <= u) + (q.w <= u);
+    const int g = ((const uint8_t *)row)[u >> bucket_shift(tail)];
+    const int b4 = min(g & ~3, s.kpad - 8);
+    const uint4 e0 = *(const uint4 *)(ent + b4), e1 = *(const uint4 *)(ent + b4 + 4);
+    const int c = (e0.x <= u) + (e0.y <= u) + (e0.z <= u) + (e0.w <= u) + (e1.x <= u) + (e1.y <= u) +
+                  (e1.z <= u) + (e1.w <= u);
+    if (c < 8) return b4 + c;
+    int cs = 0;
+    for (int i = 0; i < (s.kpad >> 2); i += 4) {
+        const uint4 q = *(const uint4 *)(row + 8 + i);
+        cs += (q.x <= u) + (q.y <= u) + (q.z <= u) + (q.w <= u);
+    }
     const uint4 e = ((const uint4 *)ent)[cs];
     return 4 * cs + (e.x <= u) + (e.y <= u) + (e.z <= u) + (e.w <= u);
 }
@@ -1445,12 +1457,27 @@ __device__ __forceinline__ void load_tables(const DevPlan &p, const RawSmem &s) 
     const int tid = threadIdx.x;
     const int k = p.k;
     const int kp = s.kpad, tr = s.trow;
-    // row a: [ T[a][16 b + 15], b < 8 | T[a][4 c + 3], c < kp / 4 | T[a][j], j < kp ],
-    // entries past k all-ones
+    // row a: [ 32 guide bytes | T[a][4 c + 3], c < kp / 4 | T[a][j], j < kp ],
+    // entries past k all-ones; the guide bytes from the entries in LDS
     for (int i = tid; i < k * tr; i += NT) {
         const int a = i / tr, w = i % tr;
-        const int j = w < 8 ? 16 * w + 15 : (w < 8 + kp / 4 ? 4 * (w - 8) + 3 : w - 8 - kp / 4);
+        if (w < 8) continue;
+        const int j = w < 8 + kp / 4 ? 4 * (w - 8) + 3 : w - 8 - kp / 4;
         s.T[i] = j < k ? p.T[a * k + j] : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    for (int i = tid; i < k * 8; i += NT) {
+        const int a = i >> 3, w = i & 7;
+        const uint32_t *ent = s.T + a * tr + 8 + kp / 4;
+        const int sh = bucket_shift(ent[k - 1]);
+        uint32_t word = 0;
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t start = (uint32_t)(4 * w + b) << sh;
+            int c = 0;
+            for (int j = 0; j < k; ++j) c += ent[j] <= start;
+            word |= (uint32_t)c << (8 * b);
+        }
+        s.T[a * tr + w] = word;
     }
     for (int i = tid; i < k; i += NT) s.gkey[i] = p.gkey[i] | ((uint64_t)(p.gneg[i] != 0) << 63);
 }
