@@ -922,10 +922,15 @@ __device__ __forceinline__ double half_max(double v) {
     return v;
 }
 
-// Dynamic LDS of k_gen_setup_wave: each block's base, m_b x m_b complex.
+// Dynamic LDS of k_gen_setup_wave: each block's base, m_b x m_b complex
+// (at least kGenMaxM entries: during the elimination, while the rows are in
+// registers, the region's first kGenMaxM entries hold the pivot row).
+__host__ __device__ __forceinline__ int gen_setup_wave_region(int mb) {
+    return mb * mb > kGenMaxM ? mb * mb : kGenMaxM;
+}
 __host__ __device__ __forceinline__ size_t gen_setup_wave_lds(const GenPlan &g) {
-    size_t e = (size_t)g.mb[0] * g.mb[0];
-    if (g.nblk > 1) e += (size_t)g.mb[1] * g.mb[1];
+    size_t e = (size_t)gen_setup_wave_region(g.mb[0]);
+    if (g.nblk > 1) e += (size_t)gen_setup_wave_region(g.mb[1]);
     return align16(e * 16);
 }
 
@@ -1051,7 +1056,6 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
                  double *__restrict__ prob, double *__restrict__ amp, double *__restrict__ logp,
                  unsigned long long *nterm) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double2 prow[2][kGenMaxM];               // pivot row of the current step (per block)
     __shared__ uint8_t sRow[2][kGenMaxM], sPiv[2][kGenMaxM], sPos[2][kGenMaxM];
     __shared__ uint8_t sCol[2][kGenMaxM], sAct[2][kGenMaxKb];
     const int lane = threadIdx.x, hb = lane >> 5, hl = lane & 31;
@@ -1061,7 +1065,10 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
     const int mh = hb ? m1 : m0, mmax = m0 > m1 ? m0 : m1;
     const uint32_t rowmask = mh >= 32 ? 0xFFFFFFFFu : (1u << mh) - 1;
     double2 *base = (double2 *)smem;
-    double2 *Ah = base + (hb ? m0 * m0 : 0);
+    double2 *Ah = base + (hb ? gen_setup_wave_region(m0) : 0);
+    // the pivot row of the current step (this half's block), over the base
+    // while the rows are in registers
+    double2 *prow = Ah;
     const int n = p.n, G = p.G;
     Work wk;
     __syncthreads();
@@ -1139,11 +1146,11 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
                 const bool piv = go && hl == idx;
                 if (piv) {
 #pragma unroll
-                    for (int j = 0; j < kGenMaxM; ++j) prow[hb][j] = a[j];
+                    for (int j = 0; j < kGenMaxM; ++j) prow[j] = a[j];
                 }
                 __syncthreads();
                 if (go) {
-                    const double2 u = prow[hb][t];
+                    const double2 u = prow[t];
                     const double inv = 1.0 / best;
                     const double2 ui = make_double2(u.x * inv, -u.y * inv);
                     inversions += __popc(~used & ((1u << idx) - 1) & rowmask);
@@ -1163,7 +1170,7 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
 #pragma unroll
                     for (int j0 = 0; j0 < kGenMaxM; j0 += 8) {
 #pragma unroll
-                        for (int j = j0; j < j0 + 8; ++j) a[j] = c_fma(a[j], l, prow[hb][j]);
+                        for (int j = j0; j < j0 + 8; ++j) a[j] = c_fma(a[j], l, prow[j]);
                         __builtin_amdgcn_sched_barrier(0);
                     }
                     a[t] = piv ? ui : l;
@@ -1212,7 +1219,7 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
         double2 *Hb = hbuf + (size_t)i * g.hsize;
         for (int blk = 0; blk < g.nblk; ++blk) {
             const int m = g.mb[blk], kb = g.kb[blk], kb0 = g.kb0[blk], hld = g.hld[blk];
-            const double2 *Ab = base + (blk ? m0 * m0 : 0);
+            const double2 *Ab = base + (blk ? gen_setup_wave_region(m0) : 0);
             const uint8_t *piv = sPiv[blk], *pos = sPos[blk], *rows = sRow[blk], *col = sCol[blk], *act = sAct[blk];
             double2 *H = Hb + g.hoff[blk];
             auto minv = [&](int r, int k) { return Ab[piv[r] * m + pos[k]]; };
