@@ -1101,8 +1101,20 @@ k_gen_setup_wave(DevPlan p, GenPlan g, const uint64_t *__restrict__ bits, int64_
         // the base, column hl of this half's block, and ||M_B||_1
         double csum = 0.0;
         if (hl < mh) {
+            // eight loads in flight before their stores
             const double2 *Pc = p.P + sCol[hb][hl];
-            for (int r = 0; r < mh; ++r) {
+            int r = 0;
+            for (; r + 8 <= mh; r += 8) {
+                double2 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = Pc[(size_t)sRow[hb][r + u] * G];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    Ah[(r + u) * mh + hl] = v[u];
+                    csum += sqrt(cabs2(v[u]));
+                }
+            }
+            for (; r < mh; ++r) {
                 const double2 v = Pc[(size_t)sRow[hb][r] * G];
                 Ah[r * mh + hl] = v;
                 csum += sqrt(cabs2(v));
@@ -1374,7 +1386,18 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
         const double2 detB = rec[i].det;
         const uint64_t shift[2] = {rec[i].shift[0], rec[i].shift[1]};
         const double2 *Hg = hbuf + (size_t)i * g.hsize;
-        for (int e = tid; e < g.hsize; e += kThreads) T.H[e] = Hg[e];
+        {
+            // eight loads in flight before their stores
+            int e = tid;
+            for (; e + 7 * kThreads < g.hsize; e += 8 * kThreads) {
+                double2 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = Hg[e + u * kThreads];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) T.H[e + u * kThreads] = v[u];
+            }
+            for (; e < g.hsize; e += kThreads) T.H[e] = Hg[e];
+        }
         acc_clear(s_acc);
         __syncthreads();
         const int64_t lo = EXACT ? j * seglen : 0;
@@ -1382,7 +1405,27 @@ k_gen_eval(DevPlan p, GenPlan g, int64_t b0, int64_t nb, const uint64_t *__restr
         bool ok = true;
         for (int64_t c0 = lo; ok && c0 < nent; c0 += SLOTS) {
             const int nc = (int)min((int64_t)SLOTS, nent - c0);
-            for (int e = tid; e < nc; e += kThreads) {
+            int e = tid;
+            if constexpr (!EXACT) {
+                // four entries in flight before their stores
+                const uint64_t *kin = ekey + (size_t)i * cap + c0;
+                const int2 *cin = ecnt + (size_t)i * cap + c0;
+                for (; e + 3 * kThreads < nc; e += 4 * kThreads) {
+                    uint64_t kv[4];
+                    int2 cv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        kv[u] = kin[e + u * kThreads];
+                        cv[u] = cin[e + u * kThreads];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        s.hkey[e + u * kThreads] = kv[u];
+                        s.hcnt[e + u * kThreads] = cv[u];
+                    }
+                }
+            }
+            for (; e < nc; e += kThreads) {
                 if constexpr (EXACT) {
                     s.hkey[e] = xkeys[c0 + e];
                 } else {
